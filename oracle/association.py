@@ -1,0 +1,97 @@
+"""Projective data association and validity masks, FP32 mirror (mask layer).
+
+The ICP term pairs each current point with "a corresponding point in the
+global model" (Section IV-B, eq. (4)) without stating the rule; the
+photometric term samples the reference image at the warped pixel (eq. (3)).
+Readings taken here:
+
+* ICP: transform the current vertex into the model-view camera,
+  q = R_a p + t_a, project it with the pinhole model, round to the nearest
+  pixel (half-even), and accept the pair when the pixel is in the image, both
+  depths and both normals are valid, |q - v0|^2 <= 0.1^2 m^2 and the rotated
+  current normal makes at most 20 degrees with the model normal;
+* RGB: transform into the reference camera, q' = R_b p + t_b, project without
+  rounding, and accept when q'.z > 0 and 1 <= u' < W-2, 1 <= v' < H-2, so
+  that every bilinear tap has a central-difference gradient.
+
+Inputs are the float32 transforms (row-major 3x3 and 3-vector) the caller
+supplies.  Every operation is a single float32 operation with no contraction:
+a matrix-vector product is ((R00 x + R01 y) + R02 z) + t0, the projection is
+inv = 1/z; u = ((fx x) inv) + cx.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+F = np.float32
+DIST2_THRESHOLD = F(0.01)          # (0.10 m)^2
+COS_THRESHOLD = F(0.93969262)      # cos(20 deg) rounded to float32
+
+
+def _xform(R, t, x, y, z):
+    R = np.asarray(R, dtype=np.float32).reshape(3, 3)
+    t = np.asarray(t, dtype=np.float32).reshape(3)
+    out = []
+    for r in range(3):
+        v = ((R[r, 0] * x + R[r, 1] * y) + R[r, 2] * z)
+        if t is not None:
+            v = v + t[r]
+        out.append(v.astype(np.float32))
+    return out
+
+
+def _rotate(R, x, y, z):
+    R = np.asarray(R, dtype=np.float32).reshape(3, 3)
+    return [((R[r, 0] * x + R[r, 1] * y) + R[r, 2] * z).astype(np.float32) for r in range(3)]
+
+
+def _project(qx, qy, qz, K):
+    fx, fy, cx, cy = (F(k) for k in K)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = (F(1) / qz).astype(np.float32)
+        u = ((fx * qx) * inv + cx).astype(np.float32)
+        v = ((fy * qy) * inv + cy).astype(np.float32)
+    return u, v
+
+
+def icp_association(cur: dict, ref: dict, Ra, ta):
+    """Returns (valid mask, ui, vi) over the current level's pixels."""
+    V1, N1, D1 = cur["V"], cur["N"], cur["D"]
+    V0, N0, D0 = ref["V"], ref["N"], ref["D"]
+    H0, W0 = D0.shape
+    x, y, z = V1[..., 0], V1[..., 1], V1[..., 2]
+    qx, qy, qz = _xform(Ra, ta, x, y, z)
+    u, v = _project(qx, qy, qz, ref["K"])
+    ui = np.rint(u).astype(np.float32)
+    vi = np.rint(v).astype(np.float32)
+    with np.errstate(invalid="ignore"):
+        inb = (ui >= F(0)) & (ui <= F(W0 - 1)) & (vi >= F(0)) & (vi <= F(H0 - 1))
+    ok = (D1 > F(0)) & (qz > F(0)) & inb
+    iu = np.where(ok, ui, 0).astype(np.int64)
+    iv = np.where(ok, vi, 0).astype(np.int64)
+    d0 = D0[iv, iu]
+    v0 = V0[iv, iu]
+    n0 = N0[iv, iu]
+    n1_ok = (N1[..., 0] != 0) | (N1[..., 1] != 0) | (N1[..., 2] != 0)
+    n0_ok = (n0[..., 0] != 0) | (n0[..., 1] != 0) | (n0[..., 2] != 0)
+    ex = (qx - v0[..., 0]).astype(np.float32)
+    ey = (qy - v0[..., 1]).astype(np.float32)
+    ez = (qz - v0[..., 2]).astype(np.float32)
+    dist2 = ((ex * ex + ey * ey) + ez * ez).astype(np.float32)
+    nx, ny, nz = _rotate(Ra, N1[..., 0], N1[..., 1], N1[..., 2])
+    cosang = ((nx * n0[..., 0] + ny * n0[..., 1]) + nz * n0[..., 2]).astype(np.float32)
+    ok = ok & (d0 > F(0)) & n0_ok & n1_ok & (dist2 <= DIST2_THRESHOLD) & (cosang >= COS_THRESHOLD)
+    return ok, iu, iv
+
+
+def rgb_validity(cur: dict, ref: dict, Rb, tb):
+    """Returns (valid mask, u', v') with u', v' the float32 warped coordinates."""
+    V1, D1 = cur["V"], cur["D"]
+    H0, W0 = ref["D"].shape
+    x, y, z = V1[..., 0], V1[..., 1], V1[..., 2]
+    qx, qy, qz = _xform(Rb, tb, x, y, z)
+    u, v = _project(qx, qy, qz, ref["K"])
+    with np.errstate(invalid="ignore"):
+        inside = (u >= F(1)) & (u < F(W0 - 2)) & (v >= F(1)) & (v < F(H0 - 2))
+    ok = (D1 > F(0)) & (qz > F(0)) & inside
+    return ok, u, v

@@ -1,0 +1,132 @@
+"""The per-frame tracking step (Sections IV-B to IV-E), oracle form.
+
+At the arrival of frame 1 the step estimates x1 while refining x0 (Section
+IV-A) by Gauss-Newton on the joint cost of eq. (6), coarse to fine over the
+pyramid (Section IV-D), updating both states with box-plus after each
+iteration, and finally marginalising x0 into the prior for the next frame
+(Section IV-E).
+
+Readings taken where the paper is silent:
+
+* x1 starts at the IMU prediction from x0 (RGB-D-inertial mode) or at x0's
+  pose with x0 held fixed (RGB-D-only mode, the paper's baseline system);
+* the IMU and prior terms are added at every iteration of every level;
+* a fixed number of iterations per level, no damping, no early exit;
+* the float32 transforms that drive association are the float64 compositions
+  T_WM^-1 T_WC1 (ICP) and T_WC0^-1 T_WC1 (photometric) rounded once to float32.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import imu as imu_mod
+from . import pyramid as pyr
+from . import residuals as res
+from . import solve as slv
+from .lie import copy_state, quat_to_rot, state_boxplus
+
+
+def default_params(levels=3, iters=(10, 5, 4), mode="rgbdi"):
+    return {
+        "levels": levels, "iters": list(iters), "mode": mode,
+        "depth_k": 1e-3, "sigma_I": 4.0, "huber_k": 1.345,
+        "sigma_g": 1.7e-4, "sigma_a": 2.0e-3, "sigma_bg_rw": 4.0e-6, "sigma_ba_rw": 2.0e-5,
+        "gravity": 9.81, "R_CS": np.eye(3), "t_CS": np.zeros(3),
+    }
+
+
+def fp32_transforms(T_WM, x0, x1):
+    """(R_a, t_a) = T_WM^-1 T_WC1 and (R_b, t_b) = T_WC0^-1 T_WC1, rounded to float32."""
+    R_WM, t_WM = T_WM[:3, :3], T_WM[:3, 3]
+    R0, R1 = quat_to_rot(x0["q"]), quat_to_rot(x1["q"])
+    Ra = R_WM.T @ R1
+    ta = R_WM.T @ (x1["r"] - t_WM)
+    Rb = R0.T @ R1
+    tb = R0.T @ (x1["r"] - x0["r"])
+    f = np.float32
+    return Ra.astype(f), ta.astype(f), Rb.astype(f), tb.astype(f)
+
+
+def linearise_visual(cur, ref, T_WM, x0, x1, Ra, ta, Rb, tb, params):
+    """Visual normal equations over [pose0 (6), pose1 (6)], per term."""
+    icp = res.icp_terms(cur, ref, T_WM, x1, Ra, ta, params)
+    rgb = res.rgb_terms(cur, ref, x0, x1, Rb, tb, params)
+    Hi, bi, ci, ni = res.normal_equations(icp, np.r_[6:12], 12)
+    Hr, br, cr, nr = res.normal_equations(rgb, np.r_[0:12], 12)
+    return {"H_icp": Hi, "b_icp": bi, "cost_icp": ci, "n_icp": ni, "mask_icp": icp["mask"],
+            "H_rgb": Hr, "b_rgb": br, "cost_rgb": cr, "n_rgb": nr, "mask_rgb": rgb["mask"],
+            "icp": icp, "rgb": rgb}
+
+
+def build_pyramids(depth, intensity, model_depth, model_intensity, camera, levels):
+    fx, fy, cx, cy = camera.fx, camera.fy, camera.cx, camera.cy
+    cur = pyr.build(depth, intensity, fx, fy, cx, cy, levels)
+    ref = pyr.build(model_depth, model_intensity, fx, fy, cx, cy, levels, with_gradient=True)
+    return cur, ref
+
+
+def track_frame(depth, intensity, model_depth, model_intensity, T_WM, camera, imu, t0, t1, x0, q_IW, prior,
+                params, *, x1_init=None, record=False):
+    """One tracking step.  Returns a dict with x0, x1, q_IW, prior (new), status and per-iteration logs."""
+    levels = params["levels"]
+    cur, ref = build_pyramids(depth, intensity, model_depth, model_intensity, camera, levels)
+    mode = params["mode"]
+    x0 = copy_state(x0)
+    q_IW = np.array(q_IW, dtype=np.float64)
+    pre = None
+    if mode != "rgbd":
+        pre = imu_mod.preintegrate(imu["t"], imu["gyro"], imu["acc"], t0, t1, x0["bg"], x0["ba"],
+                                   params["sigma_g"], params["sigma_a"])
+    if x1_init is not None:
+        x1 = copy_state(x1_init)
+    elif mode == "rgbd":
+        x1 = copy_state(x0)
+    else:
+        x1 = imu_mod.predict_state(x0, q_IW, pre, params)
+    log = []
+    H = b = dz = None
+    status = "ok"
+    for lvl in reversed(range(levels)):
+        for it in range(params["iters"][lvl]):
+            Ra, ta, Rb, tb = fp32_transforms(T_WM, x0, x1)
+            vis = linearise_visual(cur[lvl], ref[lvl], T_WM, x0, x1, Ra, ta, Rb, tb, params)
+            if mode == "rgbd":
+                Hv = vis["H_icp"] + vis["H_rgb"]
+                bv = vis["b_icp"] + vis["b_rgb"]
+                H6, b6 = Hv[6:12, 6:12], bv[6:12]
+                if not slv.is_spd(H6):
+                    status = "singular"
+                    break
+                d6 = np.linalg.solve(H6, b6)
+                x1 = state_boxplus(x1, np.concatenate([d6, np.zeros(9)]))
+                H = b = None
+                dz = d6
+            else:
+                H = np.zeros((33, 33))
+                b = np.zeros(33)
+                idx = np.r_[0:6, 15:21]
+                H[np.ix_(idx, idx)] += vis["H_icp"] + vis["H_rgb"]
+                b[idx] += vis["b_icp"] + vis["b_rgb"]
+                e, J, W = imu_mod.factor(x0, x1, q_IW, pre, params)
+                H += J.T @ W @ J
+                b += -(J.T @ W @ e)
+                Hp, bp = slv.prior_terms(x0, q_IW, prior)
+                H += Hp
+                b += bp
+                if not slv.is_spd(H):
+                    status = "singular"
+                    break
+                dz = slv.gn_step(H, b)
+                x0, x1, q_IW = slv.apply_update(x0, x1, q_IW, dz)
+            if record:
+                log.append({"level": lvl, "iter": it, "Ra": Ra, "ta": ta, "Rb": Rb, "tb": tb,
+                            "n_icp": vis["n_icp"], "n_rgb": vis["n_rgb"], "cost_icp": vis["cost_icp"],
+                            "cost_rgb": vis["cost_rgb"], "H_icp": vis["H_icp"], "b_icp": vis["b_icp"],
+                            "H_rgb": vis["H_rgb"], "b_rgb": vis["b_rgb"], "dz": dz.copy(),
+                            "mask_icp": vis["mask_icp"], "mask_rgb": vis["mask_rgb"]})
+        if status != "ok":
+            break
+    new_prior = None
+    if status == "ok" and mode != "rgbd":
+        new_prior = slv.marginalise(H, b, dz, x1, q_IW)
+    return {"x0": x0, "x1": x1, "q_IW": q_IW, "prior": new_prior, "status": status, "preint": pre, "log": log}
