@@ -1,0 +1,183 @@
+"""Benchmark: dense RGB-D-inertial tracking of a 640x480 sequence on one MI355X.
+
+One step = one tracked frame through the whole hot path: the model-view and
+current-frame pyramids, IMU preintegration and prediction, 3 pyramid levels
+of Gauss-Newton (10/5/4 iterations of the residual pass + float64 solve) and
+the marginalisation.  Inputs (300 synthetic frames rendered from the
+procedural scene along a seeded spline trajectory, IMU at 200 Hz) are
+resident in HBM before timing starts.
+
+Prints one JSON line (see the "roofline" and "cpu_baseline" objects for the
+dominant kernel's achieved bandwidth and the CPU oracle's rate).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tracked frames/s + residual-pass GB/s at 640x480; p50/p99 track latency"
+HBM_PEAK_GBS = 8000.0
+REF_BYTES_PER_PIXEL = 64  # V1 12 + N1 12 + I1 4 + V0 12 + N0 12 + I0 4 + G0 8 per pixel-iteration
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_sequence(n_frames, W, H, device):
+    import synth
+    t = time.time()
+    seq = synth.configs.sequence(seed=2001, n_frames=n_frames, width=W, height=H, device=device)
+    log(f"[bench] generated {n_frames} frames {W}x{H} in {time.time() - t:.1f}s")
+    return seq
+
+
+def frame_inputs(seq, j):
+    """(model depth, model intensity, T_WM, depth, intensity, imu window, t0, t1) for tracking frame j."""
+    import synth
+    md, mi, T = synth.configs.model_view(seq, j)
+    t0, t1 = seq["times"][j - 1], seq["times"][j]
+    a, b = synth.configs.imu_window(seq["imu"]["t"], t0, t1)
+    imu = {k: v[a:b] for k, v in seq["imu"].items()}
+    return md, mi, T, seq["depth"][j], seq["intensity"][j], imu, t0, t1
+
+
+def run_gpu(args):
+    import torch
+
+    import paper_2207_10940_amd as P
+    W, H = 640, 480
+    n_frames = args.warmup + args.steps + 1
+    seq = make_sequence(n_frames, W, H, "cuda")
+    frames = [frame_inputs(seq, j) for j in range(1, n_frames)]
+    frames = [(md.contiguous(), mi.contiguous(), T, d.contiguous(), i.contiguous(), imu, t0, t1)
+              for (md, mi, T, d, i, imu, t0, t1) in frames]
+    torch.cuda.synchronize()
+    ctx = P.Context(0)
+    tp = P.track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32")
+    sess = P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], seq["prior"])
+    x_init = sess.get_state()
+    stream = torch.cuda.current_stream()
+
+    def track(k):
+        md, mi, T, d, i, imu, t0, t1 = frames[k]
+        sess.set_model(md, mi, T, stream)
+        sess.track_frame(d, i, imu, t0, t1, stream)
+
+    for k in range(args.warmup):
+        track(k)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} frames done")
+    t_start = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        track(k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    res = sess.result()
+    log(f"[bench] timed {args.steps} frames in {elapsed * 1e3:.1f} ms; last status {res['status']}")
+    gt = seq["gt"][args.warmup + args.steps]
+    pos_err = float(np.linalg.norm(res["x1"]["r"] - gt["r"]))
+
+    # latency: each frame submitted and waited for on its own
+    sess.set_state(*x_init)
+    lat = []
+    n_lat = min(args.latency_frames, n_frames - 1)
+    for k in range(n_lat):
+        t = time.perf_counter()
+        track(k)
+        sess.result()
+        lat.append((time.perf_counter() - t) * 1e3)
+    lat = np.array(lat[5:] if len(lat) > 10 else lat)
+    log(f"[bench] latency over {len(lat)} frames: p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
+
+    # dominant kernel: the level-0 residual pass, timed back to back with events on the same stream
+    reps = args.kernel_reps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sess.profile_residual(0, 20, stream)
+    e0.record(stream)
+    sess.profile_residual(0, reps, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / reps
+    px = W * H
+    achieved = REF_BYTES_PER_PIXEL * px / (k_ms * 1e-3) / 1e9
+    log(f"[bench] level-0 residual pass: {k_ms * 1e3:.2f} us/launch, {achieved:.1f} GB/s (64 B/px algorithmic)")
+    sess.close()
+    ctx.close()
+    return {
+        "value": args.steps / elapsed, "ms_per_step": elapsed * 1e3 / args.steps,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "frames": int(len(lat)), "kind": "host submit to result, one frame at a time"},
+        "pose_err_final_m": pos_err,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "residual_kernel<2> (level 0, 640x480)", "kernel_us": k_ms * 1e3,
+                     "bytes_per_launch": REF_BYTES_PER_PIXEL * px},
+        "seq": seq,
+    }
+
+
+def cpu_baseline(seq, n_frames):
+    """The oracle as it stands, single-threaded, on the first frames of the same sequence."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import track
+    params = track.default_params(levels=3, iters=(10, 5, 4), mode="rgbdi")
+    x0, q, prior = seq["x0"], seq["q_IW"], seq["prior"]
+    t_total = 0.0
+    with threadpool_limits(limits=1):
+        for j in range(1, n_frames + 1):
+            md, mi, T, d, i, imu, t0, t1 = frame_inputs(seq, j)
+            args = [d.cpu().numpy(), i.cpu().numpy(), md.cpu().numpy(), mi.cpu().numpy()]
+            t = time.perf_counter()
+            o = track.track_frame(*args, T, seq["camera"], imu, t0, t1, x0, q, prior, params)
+            t_total += time.perf_counter() - t
+            x0, q, prior = o["x1"], o["q_IW"], o["prior"]
+    return {"value": n_frames / t_total, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_frames} tracked frames of the 640x480 sequence, 3 levels 10/5/4 iterations, "
+                      f"numpy float64 value layer + float32 mask layer, BLAS limited to 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=279)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--latency-frames", type=int, default=100)
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the tracking step shards by session, one process per GPU, and this "
+              "build runs and reports a single MI355X only", file=sys.stderr)
+        sys.exit(2)
+    g = run_gpu(args)
+    cpu = None
+    if not args.no_cpu_baseline and args.cpu_frames > 0:
+        t = time.time()
+        cpu = cpu_baseline(g["seq"], args.cpu_frames)
+        log(f"[bench] cpu baseline {cpu['value']:.3f} frames/s in {time.time() - t:.1f}s")
+    out = {
+        "metric": METRIC, "value": g["value"], "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": g["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "single-session 640x480 RGB-D-inertial sequence, 3 levels 10/5/4 GN iterations, "
+                               "IMU 200 Hz, procedural 3-plane/4-sphere scene", "width": 640, "height": 480,
+                   "levels": 3, "iters": [10, 5, 4], "jac_format": "fp32", "frames": args.steps},
+        "latency_ms": g["latency_ms"], "pose_err_final_m": g["pose_err_final_m"],
+        "roofline": g["roofline"], "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

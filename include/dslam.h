@@ -1,0 +1,274 @@
+/*
+ * dslam.h -- C ABI of the MI355X dense RGB-D-inertial tracking library.
+ *
+ * The library implements the per-frame tracking step of Laidlow, Bloesch, Li
+ * and Leutenegger, "Dense RGB-D-Inertial SLAM with Map Deformations"
+ * (Section IV): projective association against a predicted model view,
+ * photometric (eq. (3)) and point-to-plane ICP (eq. (4)) residuals with
+ * inverse-covariance and Huber weights, reduction into Gauss-Newton normal
+ * equations per pyramid level, the IMU preintegration factor (Section IV-C,
+ * eq. (5)), the joint solve over pose, velocity, IMU biases and gravity
+ * direction (eqs. (6)-(7)) and the Schur-complement marginalisation into a
+ * prior with its first-order correction (eqs. (8)-(9)).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns a dslam_status; DSLAM_OK (0) on success.  Outputs are
+ *   written only on success.  No C++ exception and no abort crosses the ABI.
+ * - "device pointer" means memory allocated on the session's GPU (for example
+ *   a torch CUDA tensor's data_ptr()); "host pointer" means ordinary CPU memory.
+ * - Streams are hipStream_t passed as void*; NULL means the default stream.
+ *   All calls on one session must be issued on one stream (or be externally
+ *   ordered): the session's device state is updated in stream order.
+ * - Images are row-major with a pitch given in elements.  Depth is float32
+ *   metres, 0 (or non-finite, or negative) meaning invalid.  Intensity is uint8.
+ * - Quaternions are Hamilton unit quaternions stored (w, x, y, z) (Section II).
+ *   Orientation perturbations are on the left: q [+] da = exp(da) (x) q
+ *   (Section IV-A).
+ * - Per-frame tangent order is [dr, dalpha, dv, dbg, dba] (15); the gravity
+ *   orientation q_IW has its own 3-vector dg.  The paper keeps q_IW in every
+ *   state (eq. (1)); this library keeps one q_IW shared by the previous and
+ *   the current state, so the joint system is 33-d and the prior 18-d.
+ * - Matrices are row-major doubles unless stated otherwise.
+ */
+#ifndef DSLAM_H
+#define DSLAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DSLAM_OK = 0,
+  DSLAM_ERR_INVALID = 1,     /* bad argument: size, null pointer, non-unit quaternion, unsorted IMU ... */
+  DSLAM_ERR_NO_CAPACITY = 2, /* the context's HBM budget cannot hold the session */
+  DSLAM_ERR_SINGULAR = 3,    /* the normal equations were not positive definite; state left unchanged */
+  DSLAM_ERR_DEVICE = 4,      /* a HIP runtime error */
+  DSLAM_ERR_BUSY = 5,        /* the session has work in flight that the call would race with */
+  DSLAM_ERR_NOT_READY = 6    /* a required input (for example the model view) has not been supplied */
+} dslam_status;
+
+enum { DSLAM_MAX_LEVELS = 4, DSLAM_MAX_IMU_SAMPLES = 32 };
+
+/* tracking modes: RGB-D-inertial (the paper's system), RGB-D only (its baseline), gyro only */
+enum { DSLAM_MODE_RGBDI = 0, DSLAM_MODE_RGBD = 1, DSLAM_MODE_GYRO = 2 };
+
+/* how the residual pass stores Jacobian rows and contracts J^T J (see DESIGN notes in the source) */
+enum {
+  DSLAM_JAC_FP32 = 0,      /* FP32 rows, wavefront-shuffle + LDS block reduction on the vector ALUs */
+  DSLAM_JAC_FP32_MFMA = 1, /* FP32 rows contracted on matrix cores (v_mfma_f32_16x16x4_f32) */
+  DSLAM_JAC_FP16 = 2,      /* FP16 rows (power-of-two column scales) on v_mfma_f32_16x16x32_f16 */
+  DSLAM_JAC_BF16 = 3       /* BF16 rows on v_mfma_f32_16x16x32_bf16 */
+};
+
+enum { DSLAM_PYR_CURRENT = 0, DSLAM_PYR_MODEL = 1 };
+
+/* pyramid channels for dslam_copy_pyramid */
+enum {
+  DSLAM_CH_VX = 0, DSLAM_CH_VY, DSLAM_CH_VZ, DSLAM_CH_NX, DSLAM_CH_NY, DSLAM_CH_NZ,
+  DSLAM_CH_I, DSLAM_CH_GX, DSLAM_CH_GY
+};
+
+/* State of one camera frame (eq. (1) without q_IW): camera position r_WC,
+ * orientation q_WC, IMU velocity v_IS expressed in I, gyro and accelerometer biases. */
+typedef struct {
+  double r[3];
+  double q[4];
+  double v[3];
+  double bg[3];
+  double ba[3];
+} dslam_frame_state;
+
+/* Pinhole camera at pyramid level 0; pixel centres sit at integer coordinates. */
+typedef struct {
+  int32_t width, height;
+  double fx, fy, cx, cy;
+} dslam_camera;
+
+/* IMU noise model and extrinsics (Table I).  Noise densities: white noise of
+ * density sigma gives the held value of a sub-interval of length dt the
+ * variance sigma^2/dt; bias random walks add sigma_rw^2 * Dt per frame. */
+typedef struct {
+  double sigma_g;      /* gyro noise density, rad/s/sqrt(Hz) */
+  double sigma_a;      /* accelerometer noise density, m/s^2/sqrt(Hz) */
+  double sigma_bg_rw;  /* gyro drift density, rad/s^2/sqrt(Hz) */
+  double sigma_ba_rw;  /* accelerometer drift density, m/s^3/sqrt(Hz) */
+  double gravity;      /* |g|, m/s^2; g_I = (0, 0, -gravity) */
+  double R_CS[9];      /* rotation S -> C */
+  double t_CS[3];      /* origin of S expressed in C */
+} dslam_imu_params;
+
+/* Tracking parameters.  levels in [1, 4]; iters[l] Gauss-Newton iterations at
+ * level l (level 0 = full resolution), run coarse to fine (Section IV-D). */
+typedef struct {
+  int32_t levels;
+  int32_t iters[DSLAM_MAX_LEVELS];
+  double icp_dist;   /* association distance gate, metres (0.10) */
+  double icp_cos;    /* optional normal-compatibility gate as a cosine; < -1 disables it (default) */
+  double sigma_I;    /* photometric noise; W_RGB = 1/sigma_I^2 */
+  double depth_k;    /* depth noise sigma_z = depth_k * z^2; W_ICP = 1/sigma_z^2 */
+  double huber_k;    /* Huber threshold on the whitened residual; 0 = no robust weight */
+  int32_t jac_format;
+  int32_t mode;
+} dslam_track_params;
+
+typedef struct {
+  double t;        /* seconds; the sample is held over [t, next t) */
+  double gyro[3];  /* rad/s in S */
+  double acc[3];   /* m/s^2 in S (specific force) */
+} dslam_imu_sample;
+
+/* Preintegrated IMU measurement between two frames (Section IV-C). */
+typedef struct {
+  double dR[9], dv[3], dp[3];
+  double dt;
+  double bg[3], ba[3];  /* linearisation biases */
+  double J[54];         /* 9x6: d(dphi, dv, dp)/d(bg, ba); dR(b) ~ dR Exp(J[0:3] db) */
+  double Sigma[81];     /* 9x9 noise covariance of (dphi, dv, dp), dR <- dR Exp(dphi) */
+} dslam_preint;
+
+/* Marginal prior on (x0, q_IW) (eqs. (6), (8)): cost (d - H^-1 b)^T H (d - H^-1 b)
+ * with d = [x0 [-] xbar ; q_IW [-] q_IW_bar]. */
+typedef struct {
+  double H[324];
+  double b[18];
+  dslam_frame_state xbar;
+  double q_IW_bar[4];
+} dslam_prior;
+
+/* Result of one tracked frame. */
+typedef struct {
+  int32_t status;       /* dslam_status of the frame */
+  int32_t frame_index;  /* frames tracked by the session so far */
+  dslam_frame_state x0; /* refined previous state */
+  dslam_frame_state x1; /* current state */
+  double q_IW[4];
+  double cost_icp, cost_rgb, cost_imu, cost_prior; /* weighted costs at the last linearisation */
+  int64_t n_icp[DSLAM_MAX_LEVELS]; /* ICP inliers at the last iteration of each level */
+  int64_t n_rgb[DSLAM_MAX_LEVELS]; /* photometric inliers at the last iteration of each level */
+  double last_step_norm;           /* |dz| of the last iteration */
+  dslam_prior prior;               /* prior handed to the next frame */
+} dslam_track_result;
+
+/* Visual normal equations of one residual pass, lifted to the world frame
+ * over [dr0, da0, dr1, da1] (12) and split per term, b = -sum w J^T e.
+ * raw[] holds the pass's own sums before lifting: per term (ICP then RGB)
+ * the 21 upper-triangular entries of sum w j j^T (row-major upper triangle of
+ * 6x6), the 6 entries of sum w j e, sum w e^2 and the inlier count (29). */
+typedef struct {
+  double H_icp[144], b_icp[12], cost_icp;
+  int64_t n_icp;
+  double H_rgb[144], b_rgb[12], cost_rgb;
+  int64_t n_rgb;
+  double raw[58];
+} dslam_linear_system;
+
+typedef struct dslam_context dslam_context;
+typedef struct dslam_session dslam_session;
+
+/* Human-readable name of a status code (static string). */
+const char* dslam_status_string(dslam_status s);
+
+/* Library build tag: target, compiler and options (static string). */
+const char* dslam_build_info(void);
+
+/* Create a context on GPU `device` that admits sessions while their summed
+ * device footprint (dslam_session_bytes) stays within hbm_budget_bytes
+ * (0 = no limit).  *out is owned by the caller; release with dslam_context_destroy. */
+dslam_status dslam_context_create(int32_t device, uint64_t hbm_budget_bytes, dslam_context** out);
+dslam_status dslam_context_destroy(dslam_context* ctx);
+/* Bytes currently admitted on the context. */
+uint64_t dslam_context_used_bytes(const dslam_context* ctx);
+
+/* Device bytes a session of this camera and pyramid depth holds for its lifetime. */
+uint64_t dslam_session_bytes(const dslam_camera* cam, int32_t levels);
+
+/* Open a tracking session.  All device memory is allocated here; nothing is
+ * allocated per frame.  x0/q_IW/prior give the initial state and its prior
+ * (prior may be NULL in DSLAM_MODE_RGBD).  Errors: INVALID (levels outside
+ * [1,4], width or height not divisible by 2^(levels-1), non-unit quaternion,
+ * unknown mode or format), NO_CAPACITY (budget), DEVICE. */
+dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, const dslam_track_params* tp,
+                                const dslam_imu_params* ip, const dslam_frame_state* x0, const double q_IW[4],
+                                const dslam_prior* prior, dslam_session** out);
+/* Wait for the session's work, free its memory and return its bytes to the context. */
+dslam_status dslam_session_close(dslam_session* s);
+
+/* Build the session's CURRENT or MODEL pyramid (Section IV-D) from device
+ * images: depth_dev (float32, metres) and intensity_dev (uint8), both
+ * height x width with row pitch `pitch_elems`.  For MODEL, T_W_ref (4x4,
+ * host) is the pose at which the model view was predicted.  Enqueued on
+ * `stream`; the caller keeps the inputs alive until the stream passes it. */
+dslam_status dslam_build_pyramid(dslam_session* s, int32_t which, const float* depth_dev,
+                                 const uint8_t* intensity_dev, int32_t pitch_elems, const double T_W_ref[16],
+                                 void* stream);
+
+/* Host float64 IMU preintegration (Section IV-C) over [t0, t1) at the
+ * linearisation biases bg, ba.  Samples (host) must be sorted by time, the
+ * first stamped at or before t0, and hold the zero-order-hold values.  Noise
+ * covariance and bias Jacobians are propagated analytically. */
+dslam_status dslam_preintegrate_imu(const dslam_imu_sample* samples, int32_t n, double t0, double t1,
+                                    const double bg[3], const double ba[3], const dslam_imu_params* p,
+                                    dslam_preint* out);
+
+/* Host float64 Gauss-Newton step (eqs. (6)-(9)) from the raw sums of one
+ * residual pass (`raw`, the layout of dslam_linear_system.raw) taken at the
+ * states x0, x1 with the model-view pose T_WM (4x4): lift the visual terms,
+ * add the IMU factor and the prior (DSLAM_MODE_RGBDI), solve, and update
+ * x0, x1 and q_IW in place.  dz_out (33, nullable) receives the increment; if
+ * marg_out is not NULL the Schur-complement prior of x0 is written there.
+ * SINGULAR leaves the states untouched.  Same arithmetic as the device solve. */
+dslam_status dslam_solve_step(const double raw[58], const double T_WM[16], const dslam_preint* pre,
+                              const dslam_imu_params* ip, const dslam_track_params* tp, const dslam_prior* prior,
+                              dslam_frame_state* x0, dslam_frame_state* x1, double q_IW[4], double dz_out[33],
+                              dslam_prior* marg_out);
+
+/* Track one frame (Section IV): builds the CURRENT pyramid from the device
+ * images, preintegrates the host IMU samples (n in [1, 32]) over [t0, t1) on
+ * the device at the session's current bias estimates, runs the coarse-to-fine
+ * Gauss-Newton iterations entirely on the device, marginalises x0 and shifts
+ * the state for the next frame.  Asynchronous: returns after enqueueing on
+ * `stream`; read the result with dslam_session_result.  Requires a MODEL
+ * pyramid (NOT_READY otherwise). */
+dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const uint8_t* intensity_dev,
+                               int32_t pitch_elems, const dslam_imu_sample* imu, int32_t n_imu, double t0,
+                               double t1, void* stream);
+
+/* Wait for the session's last tracked frame and copy its result to host memory. */
+dslam_status dslam_session_result(dslam_session* s, dslam_track_result* out);
+
+/* One residual pass at `level` with caller-chosen float32 transforms:
+ * Ra, ta map current-camera points into the model-view camera (ICP
+ * association) and Rb, tb into the reference camera of x0 (photometric warp);
+ * x0, x1 (host) give the float64 poses used to lift the sums to the world
+ * frame.  If mask_dev (device, width_l x height_l bytes) is not NULL, each
+ * pixel gets bit 0 = ICP inlier, bit 1 = photometric inlier.  Synchronous. */
+dslam_status dslam_linearize(dslam_session* s, int32_t level, const float Ra[9], const float ta[3],
+                             const float Rb[9], const float tb[3], const dslam_frame_state* x0,
+                             const dslam_frame_state* x1, uint8_t* mask_dev, dslam_linear_system* out,
+                             void* stream);
+
+/* Launch the residual pass of `level` `reps` times back to back on `stream`
+ * with the session's current transforms, writing only its scratch partials
+ * (the estimator state is untouched).  For timing the pass with events on
+ * the caller's stream.  Asynchronous.  NOT_READY without both pyramids. */
+dslam_status dslam_profile_residual(dslam_session* s, int32_t level, int32_t reps, void* stream);
+
+/* Copy one channel of one pyramid level to host memory (width_l*height_l floats). Synchronous. */
+dslam_status dslam_copy_pyramid(dslam_session* s, int32_t which, int32_t level, int32_t channel, float* host_out);
+
+/* Checkpoint / restore the session's estimator state (x0, q_IW, prior and
+ * frame counter) through host memory; the pyramids are not part of it. */
+dslam_status dslam_session_get_state(dslam_session* s, dslam_frame_state* x0, double q_IW[4], dslam_prior* prior,
+                                     int32_t* frame_index);
+dslam_status dslam_session_set_state(dslam_session* s, const dslam_frame_state* x0, const double q_IW[4],
+                                     const dslam_prior* prior, int32_t frame_index);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSLAM_H */

@@ -7,9 +7,14 @@ Readings taken here:
 
 * ICP: transform the current vertex into the model-view camera,
   q = R_a p + t_a, project it with the pinhole model, round to the nearest
-  pixel (half-even), and accept the pair when the pixel is in the image, both
-  depths and both normals are valid, |q - v0|^2 <= 0.1^2 m^2 and the rotated
-  current normal makes at most 20 degrees with the model normal;
+  pixel (half-even), and accept the pair when the pixel is in the image, the
+  current depth, the model depth and the model normal are valid and
+  |q - v0|^2 <= d_max^2 (d_max = 0.10 m).  Eq. (4) involves only the model
+  normal; an optional compatibility gate (rotated current normal within an
+  angle of the model normal, given as a cosine) is off by default: with the
+  configured depth noise at full resolution the forward-difference normals of
+  the raw current depth are dominated by noise, and such a gate discards most
+  correct pairs;
 * RGB: transform into the reference camera, q' = R_b p + t_b, project without
   rounding, and accept when q'.z > 0 and 1 <= u' < W-2, 1 <= v' < H-2, so
   that every bilinear tap has a central-difference gradient.
@@ -24,8 +29,7 @@ from __future__ import annotations
 import numpy as np
 
 F = np.float32
-DIST2_THRESHOLD = F(0.01)          # (0.10 m)^2
-COS_THRESHOLD = F(0.93969262)      # cos(20 deg) rounded to float32
+DIST_THRESHOLD = 0.10              # metres
 
 
 def _xform(R, t, x, y, z):
@@ -54,8 +58,11 @@ def _project(qx, qy, qz, K):
     return u, v
 
 
-def icp_association(cur: dict, ref: dict, Ra, ta):
-    """Returns (valid mask, ui, vi) over the current level's pixels."""
+def icp_association(cur: dict, ref: dict, Ra, ta, dist=DIST_THRESHOLD, cos_min=None):
+    """Returns (valid mask, ui, vi) over the current level's pixels.
+
+    dist: association distance gate (m); the squared gate is dist^2 rounded to
+    float32.  cos_min: optional normal-compatibility gate (None: off)."""
     V1, N1, D1 = cur["V"], cur["N"], cur["D"]
     V0, N0, D0 = ref["V"], ref["N"], ref["D"]
     H0, W0 = D0.shape
@@ -72,15 +79,17 @@ def icp_association(cur: dict, ref: dict, Ra, ta):
     d0 = D0[iv, iu]
     v0 = V0[iv, iu]
     n0 = N0[iv, iu]
-    n1_ok = (N1[..., 0] != 0) | (N1[..., 1] != 0) | (N1[..., 2] != 0)
     n0_ok = (n0[..., 0] != 0) | (n0[..., 1] != 0) | (n0[..., 2] != 0)
     ex = (qx - v0[..., 0]).astype(np.float32)
     ey = (qy - v0[..., 1]).astype(np.float32)
     ez = (qz - v0[..., 2]).astype(np.float32)
     dist2 = ((ex * ex + ey * ey) + ez * ez).astype(np.float32)
-    nx, ny, nz = _rotate(Ra, N1[..., 0], N1[..., 1], N1[..., 2])
-    cosang = ((nx * n0[..., 0] + ny * n0[..., 1]) + nz * n0[..., 2]).astype(np.float32)
-    ok = ok & (d0 > F(0)) & n0_ok & n1_ok & (dist2 <= DIST2_THRESHOLD) & (cosang >= COS_THRESHOLD)
+    ok = ok & (d0 > F(0)) & n0_ok & (dist2 <= F(dist * dist))
+    if cos_min is not None:
+        n1_ok = (N1[..., 0] != 0) | (N1[..., 1] != 0) | (N1[..., 2] != 0)
+        nx, ny, nz = _rotate(Ra, N1[..., 0], N1[..., 1], N1[..., 2])
+        cosang = ((nx * n0[..., 0] + ny * n0[..., 1]) + nz * n0[..., 2]).astype(np.float32)
+        ok = ok & n1_ok & (cosang >= F(cos_min))
     return ok, iu, iv
 
 

@@ -55,7 +55,7 @@ def icp_terms(cur, ref, T_WM, x1, Ra, ta, params):
 
     Returns a dict with mask (H, W), e (n,), J (n, 6), w (n,) for the valid pixels.
     """
-    mask, iu, iv = icp_association(cur, ref, Ra, ta)
+    mask, iu, iv = icp_association(cur, ref, Ra, ta, params.get("icp_dist", 0.10), params.get("icp_cos"))
     p = cur["V"][mask].astype(np.float64)
     v0 = ref["V"][iv[mask], iu[mask]].astype(np.float64)
     n0 = ref["N"][iv[mask], iu[mask]].astype(np.float64)

@@ -29,7 +29,7 @@ from .lie import copy_state, quat_to_rot, state_boxplus
 def default_params(levels=3, iters=(10, 5, 4), mode="rgbdi"):
     return {
         "levels": levels, "iters": list(iters), "mode": mode,
-        "depth_k": 1e-3, "sigma_I": 4.0, "huber_k": 1.345,
+        "depth_k": 1e-3, "sigma_I": 4.0, "huber_k": 1.345, "icp_dist": 0.10, "icp_cos": None,
         "sigma_g": 1.7e-4, "sigma_a": 2.0e-3, "sigma_bg_rw": 4.0e-6, "sigma_ba_rw": 2.0e-5,
         "gravity": 9.81, "R_CS": np.eye(3), "t_CS": np.zeros(3),
     }

@@ -1,0 +1,284 @@
+"""MI355X (gfx950) dense RGB-D-inertial tracking: Python binding of libdslam.so.
+
+Every step of the tracking path runs in the HIP library behind the C ABI of
+include/dslam.h; this module only marshals arguments (torch CUDA tensors for
+device images, numpy arrays and dicts for host-side states).  There is no
+fallback: if the library is missing every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import (CH_GX, CH_GY, CH_I, CH_NX, CH_NY, CH_NZ, CH_VX, CH_VY, CH_VZ, JAC_BF16, JAC_FP16, JAC_FP32,
+                   JAC_FP32_MFMA, MODE_GYRO, MODE_RGBD, MODE_RGBDI, PYR_CURRENT, PYR_MODEL)
+
+__all__ = ["DslamError", "Context", "Session", "preintegrate_imu", "solve_step", "track_params", "imu_params",
+           "camera", "state_struct", "state_dict", "prior_struct", "prior_dict", "lib"]
+
+MODES = {"rgbdi": MODE_RGBDI, "rgbd": MODE_RGBD, "gyro": MODE_GYRO}
+JAC = {"fp32": JAC_FP32, "fp32_mfma": JAC_FP32_MFMA, "fp16": JAC_FP16, "bf16": JAC_BF16}
+
+
+class DslamError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {lib().dslam_status_string(code).decode()} ({code})")
+
+
+def lib():
+    return _abi.load()
+
+
+def _check(code, where):
+    if code != _abi.OK:
+        raise DslamError(code, where)
+
+
+# --- struct conversion --------------------------------------------------------
+
+def state_struct(x: dict) -> _abi.FrameState:
+    s = _abi.FrameState()
+    for k in ("r", "q", "v", "bg", "ba"):
+        getattr(s, k)[:] = [float(v) for v in np.asarray(x[k], dtype=np.float64)]
+    return s
+
+
+def state_dict(s: _abi.FrameState) -> dict:
+    return {k: np.array(getattr(s, k)[:], dtype=np.float64) for k in ("r", "q", "v", "bg", "ba")}
+
+
+def prior_struct(p: dict) -> _abi.Prior:
+    s = _abi.Prior()
+    s.H[:] = [float(v) for v in np.asarray(p["H"], dtype=np.float64).ravel()]
+    s.b[:] = [float(v) for v in np.asarray(p["b"], dtype=np.float64)]
+    s.xbar = state_struct(p["xbar"])
+    s.q_IW_bar[:] = [float(v) for v in p["qIW_bar"]]
+    return s
+
+
+def prior_dict(s: _abi.Prior) -> dict:
+    return {"H": np.array(s.H[:]).reshape(18, 18), "b": np.array(s.b[:]), "xbar": state_dict(s.xbar),
+            "qIW_bar": np.array(s.q_IW_bar[:])}
+
+
+def camera(cam) -> _abi.Camera:
+    return _abi.Camera(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy))
+
+
+def track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32", icp_dist=0.10, icp_cos=None,
+                 sigma_I=4.0, depth_k=1e-3, huber_k=1.345) -> _abi.TrackParams:
+    p = _abi.TrackParams()
+    p.levels = levels
+    its = list(iters) + [0] * (_abi.MAX_LEVELS - len(iters))
+    p.iters[:] = its[:_abi.MAX_LEVELS]
+    p.icp_dist = icp_dist
+    p.icp_cos = -2.0 if icp_cos is None else float(icp_cos)  # None: no normal-compatibility gate
+    p.sigma_I = sigma_I
+    p.depth_k = depth_k
+    p.huber_k = huber_k
+    p.jac_format = JAC[jac] if isinstance(jac, str) else int(jac)
+    p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    return p
+
+
+def imu_params(sigma_g=1.7e-4, sigma_a=2.0e-3, sigma_bg_rw=4.0e-6, sigma_ba_rw=2.0e-5, gravity=9.81,
+               R_CS=np.eye(3), t_CS=np.zeros(3)) -> _abi.ImuParams:
+    p = _abi.ImuParams()
+    p.sigma_g, p.sigma_a, p.sigma_bg_rw, p.sigma_ba_rw, p.gravity = sigma_g, sigma_a, sigma_bg_rw, sigma_ba_rw, gravity
+    p.R_CS[:] = [float(v) for v in np.asarray(R_CS, dtype=np.float64).ravel()]
+    p.t_CS[:] = [float(v) for v in np.asarray(t_CS, dtype=np.float64)]
+    return p
+
+
+def imu_samples(stamps, gyro, acc):
+    n = len(stamps)
+    arr = (_abi.ImuSample * max(n, 1))()
+    for k in range(n):
+        arr[k].t = float(stamps[k])
+        arr[k].gyro[:] = [float(v) for v in gyro[k]]
+        arr[k].acc[:] = [float(v) for v in acc[k]]
+    return arr, n
+
+
+def _dptr(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+# --- host entry points ----------------------------------------------------------
+
+def preintegrate_imu(stamps, gyro, acc, t0, t1, bg, ba, ip: _abi.ImuParams) -> dict:
+    arr, n = imu_samples(stamps, gyro, acc)
+    _, bgp = _dptr(bg)
+    _, bap = _dptr(ba)
+    out = _abi.Preint()
+    _check(lib().dslam_preintegrate_imu(arr, n, float(t0), float(t1), bgp, bap, C.byref(ip), C.byref(out)),
+           "dslam_preintegrate_imu")
+    return {"dR": np.array(out.dR[:]).reshape(3, 3), "dv": np.array(out.dv[:]), "dp": np.array(out.dp[:]),
+            "dt": out.dt, "bg": np.array(out.bg[:]), "ba": np.array(out.ba[:]),
+            "J": np.array(out.J[:]).reshape(9, 6), "Sigma": np.array(out.Sigma[:]).reshape(9, 9), "_struct": out}
+
+
+def preint_struct(pre: dict) -> _abi.Preint:
+    if "_struct" in pre:
+        return pre["_struct"]
+    s = _abi.Preint()
+    s.dR[:] = list(np.asarray(pre["dR"]).ravel())
+    s.dv[:] = list(pre["dv"])
+    s.dp[:] = list(pre["dp"])
+    s.dt = float(pre["dt"])
+    s.bg[:] = list(pre["bg"])
+    s.ba[:] = list(pre["ba"])
+    s.J[:] = list(np.asarray(pre["J"]).ravel())
+    s.Sigma[:] = list(np.asarray(pre["Sigma"]).ravel())
+    return s
+
+
+def solve_step(raw, T_WM, pre, ip, tp, prior, x0, x1, q_IW, marginalise=False):
+    """Host float64 Gauss-Newton step; returns (x0, x1, q_IW, dz, new_prior or None)."""
+    _, rawp = _dptr(raw)
+    _, Tp = _dptr(np.asarray(T_WM).ravel())
+    a, b = state_struct(x0), state_struct(x1)
+    q = np.ascontiguousarray(q_IW, dtype=np.float64).copy()
+    dz = np.zeros(33)
+    m = _abi.Prior() if marginalise else None
+    pre_s = preint_struct(pre) if pre is not None else None
+    prior_s = prior_struct(prior) if prior is not None else None
+    code = lib().dslam_solve_step(rawp, Tp, C.byref(pre_s) if pre_s else None, C.byref(ip), C.byref(tp),
+                                  C.byref(prior_s) if prior_s else None, C.byref(a), C.byref(b),
+                                  q.ctypes.data_as(C.POINTER(C.c_double)), dz.ctypes.data_as(C.POINTER(C.c_double)),
+                                  C.byref(m) if m is not None else None)
+    _check(code, "dslam_solve_step")
+    return state_dict(a), state_dict(b), q, dz, (prior_dict(m) if m is not None else None)
+
+
+# --- device objects ----------------------------------------------------------------
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = C.c_void_p()
+        _check(lib().dslam_context_create(int(device), int(hbm_budget_bytes), C.byref(h)), "dslam_context_create")
+        self.handle = h
+        self.device = device
+
+    def used_bytes(self) -> int:
+        return int(lib().dslam_context_used_bytes(self.handle))
+
+    def close(self):
+        if self.handle:
+            _check(lib().dslam_context_destroy(self.handle), "dslam_context_destroy")
+            self.handle = None
+
+
+def session_bytes(cam, levels) -> int:
+    c = camera(cam) if not isinstance(cam, _abi.Camera) else cam
+    return int(lib().dslam_session_bytes(C.byref(c), int(levels)))
+
+
+class Session:
+    """One tracking session (device-resident pyramids and estimator state)."""
+
+    def __init__(self, ctx: Context, cam, tp: _abi.TrackParams, ip: _abi.ImuParams, x0: dict, q_IW, prior=None):
+        self.cam = camera(cam) if not isinstance(cam, _abi.Camera) else cam
+        self.tp, self.ip = tp, ip
+        h = C.c_void_p()
+        xs = state_struct(x0)
+        q, qp = _dptr(q_IW)
+        ps = prior_struct(prior) if prior is not None else None
+        _check(lib().dslam_session_open(ctx.handle, C.byref(self.cam), C.byref(tp), C.byref(ip), C.byref(xs), qp,
+                                        C.byref(ps) if ps is not None else None, C.byref(h)), "dslam_session_open")
+        self.handle = h
+        self.ctx = ctx
+
+    def close(self):
+        if self.handle:
+            _check(lib().dslam_session_close(self.handle), "dslam_session_close")
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_pyramid(self, which, depth, intensity, T_W_ref=None, stream=None):
+        assert depth.is_cuda and intensity.is_cuda and depth.is_contiguous() and intensity.is_contiguous()
+        T = None
+        if T_W_ref is not None:
+            T, Tp = _dptr(np.asarray(T_W_ref).ravel())
+        _check(lib().dslam_build_pyramid(self.handle, int(which), C.c_void_p(depth.data_ptr()),
+                                         C.c_void_p(intensity.data_ptr()), int(depth.shape[1]),
+                                         Tp if T is not None else None, _stream_ptr(stream)), "dslam_build_pyramid")
+
+    def set_model(self, depth, intensity, T_WM, stream=None):
+        self.build_pyramid(PYR_MODEL, depth, intensity, T_WM, stream)
+
+    def track_frame(self, depth, intensity, imu=None, t0=0.0, t1=0.0, stream=None):
+        """Enqueue one tracking step; imu = dict(t, gyro, acc) of the samples covering [t0, t1)."""
+        assert depth.is_cuda and intensity.is_cuda and depth.is_contiguous() and intensity.is_contiguous()
+        if imu is not None:
+            arr, n = imu_samples(imu["t"], imu["gyro"], imu["acc"])
+        else:
+            arr, n = None, 0
+        _check(lib().dslam_track_frame(self.handle, C.c_void_p(depth.data_ptr()), C.c_void_p(intensity.data_ptr()),
+                                       int(depth.shape[1]), arr, n, float(t0), float(t1), _stream_ptr(stream)),
+               "dslam_track_frame")
+
+    def result(self) -> dict:
+        r = _abi.TrackResult()
+        _check(lib().dslam_session_result(self.handle, C.byref(r)), "dslam_session_result")
+        return {"status": r.status, "frame_index": r.frame_index, "x0": state_dict(r.x0), "x1": state_dict(r.x1),
+                "q_IW": np.array(r.q_IW[:]), "cost_icp": r.cost_icp, "cost_rgb": r.cost_rgb, "cost_imu": r.cost_imu,
+                "n_icp": list(r.n_icp), "n_rgb": list(r.n_rgb), "last_step_norm": r.last_step_norm,
+                "prior": prior_dict(r.prior)}
+
+    def linearize(self, level, Ra, ta, Rb, tb, x0, x1, mask=None, stream=None) -> dict:
+        f = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float32).ravel())  # noqa: E731
+        arrs = [f(Ra), f(ta), f(Rb), f(tb)]
+        ptrs = [a.ctypes.data_as(C.POINTER(C.c_float)) for a in arrs]
+        out = _abi.LinearSystem()
+        a, b = state_struct(x0), state_struct(x1)
+        mptr = C.c_void_p(mask.data_ptr()) if mask is not None else None
+        _check(lib().dslam_linearize(self.handle, int(level), *ptrs, C.byref(a), C.byref(b), mptr, C.byref(out),
+                                     _stream_ptr(stream)), "dslam_linearize")
+        return {"H_icp": np.array(out.H_icp[:]).reshape(12, 12), "b_icp": np.array(out.b_icp[:]),
+                "cost_icp": out.cost_icp, "n_icp": out.n_icp, "H_rgb": np.array(out.H_rgb[:]).reshape(12, 12),
+                "b_rgb": np.array(out.b_rgb[:]), "cost_rgb": out.cost_rgb, "n_rgb": out.n_rgb,
+                "raw": np.array(out.raw[:])}
+
+    def profile_residual(self, level, reps, stream=None):
+        _check(lib().dslam_profile_residual(self.handle, int(level), int(reps), _stream_ptr(stream)),
+               "dslam_profile_residual")
+
+    def copy_pyramid(self, which, level, channel) -> np.ndarray:
+        W, H = self.cam.width >> level, self.cam.height >> level
+        out = np.empty((H, W), dtype=np.float32)
+        _check(lib().dslam_copy_pyramid(self.handle, int(which), int(level), int(channel),
+                                        out.ctypes.data_as(C.POINTER(C.c_float))), "dslam_copy_pyramid")
+        return out
+
+    def get_state(self):
+        x = _abi.FrameState()
+        q = np.zeros(4)
+        p = _abi.Prior()
+        fi = C.c_int32()
+        _check(lib().dslam_session_get_state(self.handle, C.byref(x), q.ctypes.data_as(C.POINTER(C.c_double)),
+                                             C.byref(p), C.byref(fi)), "dslam_session_get_state")
+        return state_dict(x), q, prior_dict(p), fi.value
+
+    def set_state(self, x0, q_IW, prior, frame_index=0):
+        xs = state_struct(x0)
+        q, qp = _dptr(q_IW)
+        ps = prior_struct(prior) if prior is not None else None
+        _check(lib().dslam_session_set_state(self.handle, C.byref(xs), qp, C.byref(ps) if ps is not None else None,
+                                             int(frame_index)), "dslam_session_set_state")

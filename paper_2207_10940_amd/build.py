@@ -1,0 +1,67 @@
+"""Build libdslam.so (HIP, gfx950) in-tree with hipcc.
+
+Usage: python -m paper_2207_10940_amd.build   (or build() from Python)
+"""
+from __future__ import annotations
+
+import os
+import shlex
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libdslam.so")
+ARCH = "gfx950"
+
+COMMON = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # no packed-FP32 instructions anywhere in the device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+]
+# The pyramid and residual kernels decide pyramid values, validity bits and
+# associations in float32: one rounding per operation, no contraction,
+# correctly rounded division and square root.
+EXACT_FP32 = ["-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt"]
+
+SOURCES = {
+    "kernels.hip": EXACT_FP32,
+    "solve.hip": [],
+    "dslam.hip": [],
+}
+
+
+def _hipcc():
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
+        if c and os.path.exists(c):
+            return c
+    return "hipcc"
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source and link the shared library; returns its path."""
+    hipcc = _hipcc()
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    tag = f'-DDSLAM_BUILD_TAG="{ARCH} {" ".join(COMMON[:2])}"'
+    objs = []
+    for src, extra in SOURCES.items():
+        obj = os.path.join(objdir, src + ".o")
+        cmd = [hipcc, "-c", os.path.join(CSRC, src), "-o", obj, tag] + COMMON + extra
+        if verbose:
+            print(" ".join(shlex.quote(c) for c in cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    if verbose:
+        print(" ".join(shlex.quote(c) for c in cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
+    print(LIB)

@@ -1,0 +1,552 @@
+// Host side of the C ABI declared in include/dslam.h: contexts, sessions,
+// argument checking, launch sequencing of the tracking step and the host
+// float64 entry points (preintegration and Gauss-Newton step).
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "device.h"
+#include "solve_core.h"
+
+namespace dslam {
+// kernels.hip
+hipError_t launch_pyramid_level0(const float* depth, const uint8_t* inten, int pitch, const LevelPtrs& L,
+                                 int with_grad, hipStream_t st);
+hipError_t launch_pyramid_down(const LevelPtrs& parent, const LevelPtrs& L, int with_grad, hipStream_t st);
+int residual_blocks(int npix, int ppt);
+hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st);
+// solve.hip
+struct ImuBatch {
+  int32_t n;
+  double t0, t1;
+  dslam_imu_sample s[DSLAM_MAX_IMU_SAMPLES];
+};
+struct FrameArgs {
+  ImuParamsD imu;
+  double sigma_g, sigma_a;
+  double R_WM[9], t_WM[3];
+  int32_t mode;
+};
+struct SolveArgs {
+  SolveParams sp;
+  int32_t level;
+  int32_t last;
+  int32_t nblocks;
+};
+hipError_t launch_frame_init(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, hipStream_t st);
+hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& a, hipStream_t st);
+hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st);
+}  // namespace dslam
+
+using namespace dslam;
+
+struct dslam_context {
+  int device;
+  uint64_t budget;
+  std::atomic<uint64_t> used{0};
+};
+
+struct dslam_session {
+  dslam_context* ctx;
+  dslam_camera cam;
+  dslam_track_params tp;
+  dslam_imu_params ip;
+  int levels;
+  uint64_t bytes;
+  void* arena;
+  LevelPtrs cur[DSLAM_MAX_LEVELS], model[DSLAM_MAX_LEVELS];
+  SessionDev* sd;
+  float* partials;
+  int max_blocks;
+  double* red_out;   // device, 64 doubles
+  float* xf_scratch; // device, 24 floats (dslam_linearize)
+  hipEvent_t done;
+  bool have_model;
+  double T_WM[16];
+  int ppt[DSLAM_MAX_LEVELS];
+  std::mutex mu;
+};
+
+namespace {
+
+const char* kStatus[] = {"ok", "invalid argument", "no capacity", "singular system", "device error", "busy",
+                         "not ready"};
+
+#define HIP_OK(expr)                           \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return DSLAM_ERR_DEVICE; \
+  } while (0)
+
+bool quat_ok(const double* q) {
+  double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  return std::isfinite(n) && std::fabs(n - 1.0) <= 1e-6;
+}
+
+bool state_ok(const dslam_frame_state* x) {
+  if (!x || !quat_ok(x->q)) return false;
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(x->r[i]) || !std::isfinite(x->v[i]) || !std::isfinite(x->bg[i]) || !std::isfinite(x->ba[i]))
+      return false;
+  return true;
+}
+
+bool params_ok(const dslam_camera* cam, const dslam_track_params* tp) {
+  if (!cam || !tp) return false;
+  if (tp->levels < 1 || tp->levels > DSLAM_MAX_LEVELS) return false;
+  int div = 1 << (tp->levels - 1);
+  if (cam->width < 8 || cam->height < 8 || cam->width % div || cam->height % div) return false;
+  if ((cam->width >> (tp->levels - 1)) < 4 || (cam->height >> (tp->levels - 1)) < 4) return false;
+  if ((int64_t)cam->width * cam->height > (1 << 26)) return false;
+  if (!(cam->fx > 0) || !(cam->fy > 0) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy)) return false;
+  for (int l = 0; l < tp->levels; ++l)
+    if (tp->iters[l] < 0 || tp->iters[l] > 1000) return false;
+  if (tp->mode != DSLAM_MODE_RGBDI && tp->mode != DSLAM_MODE_RGBD) return false;
+  if (tp->jac_format != DSLAM_JAC_FP32) return false;
+  if (!(tp->icp_dist > 0) || !(tp->icp_cos <= 1) || !(tp->sigma_I > 0) ||
+      !(tp->depth_k > 0) || !(tp->huber_k >= 0))
+    return false;
+  return true;
+}
+
+void level_intrinsics(const dslam_camera& c, int l, LevelPtrs* L) {
+  double s = std::ldexp(1.0, -l);
+  L->W = c.width >> l;
+  L->H = c.height >> l;
+  L->fx = (float)(c.fx * s);
+  L->fy = (float)(c.fy * s);
+  L->cx = (float)((c.cx + 0.5) * s - 0.5);
+  L->cy = (float)((c.cy + 0.5) * s - 0.5);
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t planes, partial_floats, total;
+  int max_blocks;
+};
+
+Layout layout_for(const dslam_camera& c, int levels) {
+  Layout lo{0, 0, 0, 0};
+  size_t planes = 0;
+  for (int l = 0; l < levels; ++l) {
+    size_t n = (size_t)(c.width >> l) * (c.height >> l);
+    planes += 16 * align256(n * sizeof(float));  // 7 current + 9 model planes
+  }
+  int nb = residual_blocks(c.width * c.height, 1);
+  lo.planes = planes;
+  lo.max_blocks = nb;
+  lo.partial_floats = (size_t)nb * PARTIAL_STRIDE;
+  lo.total = planes + align256(lo.partial_floats * sizeof(float)) + align256(sizeof(SessionDev)) +
+             align256(64 * sizeof(double)) + align256(24 * sizeof(float));
+  return lo;
+}
+
+ImuParamsD imu_params_d(const dslam_imu_params& ip) {
+  ImuParamsD d;
+  d.gravity = ip.gravity;
+  d.sigma_bg_rw = ip.sigma_bg_rw;
+  d.sigma_ba_rw = ip.sigma_ba_rw;
+  for (int i = 0; i < 9; ++i) d.R_CS[i] = ip.R_CS[i];
+  for (int i = 0; i < 3; ++i) d.t_CS[i] = ip.t_CS[i];
+  return d;
+}
+
+int default_ppt(int npix) { return npix >= 600000 ? 4 : (npix >= 150000 ? 2 : 1); }
+
+ResidualArgs residual_args(dslam_session* s, int l, const float* xf, float* partials, uint8_t* mask) {
+  const LevelPtrs& c = s->cur[l];
+  const LevelPtrs& m = s->model[l];
+  ResidualArgs a;
+  a.cV0 = c.V[0]; a.cV1 = c.V[1]; a.cV2 = c.V[2];
+  a.cN0 = c.N[0]; a.cN1 = c.N[1]; a.cN2 = c.N[2];
+  a.cI = c.I;
+  a.mV0 = m.V[0]; a.mV1 = m.V[1]; a.mV2 = m.V[2];
+  a.mN0 = m.N[0]; a.mN1 = m.N[1]; a.mN2 = m.N[2];
+  a.mI = m.I; a.mG0 = m.G[0]; a.mG1 = m.G[1];
+  a.W = c.W; a.H = c.H; a.npix = c.W * c.H;
+  a.fx = c.fx; a.fy = c.fy; a.cx = c.cx; a.cy = c.cy;
+  a.dist2 = (float)(s->tp.icp_dist * s->tp.icp_dist);
+  a.cosmin = (float)s->tp.icp_cos;
+  a.depth_k = (float)s->tp.depth_k;
+  a.sigma_I = (float)s->tp.sigma_I;
+  a.huber_k = (float)s->tp.huber_k;
+  a.xf = xf;
+  a.partials = partials;
+  a.mask = mask;
+  return a;
+}
+
+SolveParams solve_params(dslam_session* s) {
+  SolveParams sp;
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) sp.R_WM[3 * r + c] = s->T_WM[4 * r + c];
+    sp.t_WM[r] = s->T_WM[4 * r + 3];
+  }
+  sp.imu = imu_params_d(s->ip);
+  sp.mode = s->tp.mode;
+  sp.marginalise = 0;
+  return sp;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dslam_status_string(dslam_status s) {
+  int i = (int)s;
+  return (i >= 0 && i < (int)(sizeof(kStatus) / sizeof(kStatus[0]))) ? kStatus[i] : "unknown status";
+}
+
+const char* dslam_build_info(void) {
+  return "dslam gfx950 HIP " DSLAM_BUILD_TAG;
+}
+
+dslam_status dslam_context_create(int32_t device, uint64_t hbm_budget_bytes, dslam_context** out) {
+  if (!out) return DSLAM_ERR_INVALID;
+  int n = 0;
+  HIP_OK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return DSLAM_ERR_INVALID;
+  dslam_context* c = new (std::nothrow) dslam_context;
+  if (!c) return DSLAM_ERR_NO_CAPACITY;
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_context_destroy(dslam_context* ctx) {
+  if (!ctx) return DSLAM_ERR_INVALID;
+  if (ctx->used.load() != 0) return DSLAM_ERR_BUSY;
+  delete ctx;
+  return DSLAM_OK;
+}
+
+uint64_t dslam_context_used_bytes(const dslam_context* ctx) { return ctx ? ctx->used.load() : 0; }
+
+uint64_t dslam_session_bytes(const dslam_camera* cam, int32_t levels) {
+  if (!cam || levels < 1 || levels > DSLAM_MAX_LEVELS || cam->width <= 0 || cam->height <= 0) return 0;
+  return layout_for(*cam, levels).total;
+}
+
+dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, const dslam_track_params* tp,
+                                const dslam_imu_params* ip, const dslam_frame_state* x0, const double q_IW[4],
+                                const dslam_prior* prior, dslam_session** out) {
+  if (!ctx || !out || !params_ok(cam, tp) || !ip || !state_ok(x0) || !q_IW || !quat_ok(q_IW)) return DSLAM_ERR_INVALID;
+  if (tp->mode != DSLAM_MODE_RGBD && !prior) return DSLAM_ERR_INVALID;
+  Layout lo = layout_for(*cam, tp->levels);
+  uint64_t prev = ctx->used.fetch_add(lo.total);
+  if (ctx->budget && prev + lo.total > ctx->budget) {
+    ctx->used.fetch_sub(lo.total);
+    return DSLAM_ERR_NO_CAPACITY;
+  }
+  dslam_session* s = new (std::nothrow) dslam_session;
+  if (!s) {
+    ctx->used.fetch_sub(lo.total);
+    return DSLAM_ERR_NO_CAPACITY;
+  }
+  s->ctx = ctx;
+  s->cam = *cam;
+  s->tp = *tp;
+  s->ip = *ip;
+  s->levels = tp->levels;
+  s->bytes = lo.total;
+  s->have_model = false;
+  s->max_blocks = lo.max_blocks;
+  for (int i = 0; i < 16; ++i) s->T_WM[i] = (i % 5 == 0) ? 1.0 : 0.0;
+  auto fail = [&](dslam_status st) {
+    if (s->arena) hipFree(s->arena);
+    ctx->used.fetch_sub(lo.total);
+    delete s;
+    return st;
+  };
+  s->arena = nullptr;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
+  if (hipMalloc(&s->arena, lo.total) != hipSuccess) {
+    s->arena = nullptr;
+    return fail(DSLAM_ERR_NO_CAPACITY);
+  }
+  char* p = (char*)s->arena;
+  for (int l = 0; l < s->levels; ++l) {
+    size_t bytes = align256((size_t)(cam->width >> l) * (cam->height >> l) * sizeof(float));
+    LevelPtrs* C = &s->cur[l];
+    LevelPtrs* M = &s->model[l];
+    level_intrinsics(*cam, l, C);
+    level_intrinsics(*cam, l, M);
+    for (int k = 0; k < 3; ++k) { C->V[k] = (float*)p; p += bytes; }
+    for (int k = 0; k < 3; ++k) { C->N[k] = (float*)p; p += bytes; }
+    C->I = (float*)p; p += bytes;
+    C->G[0] = C->G[1] = nullptr;
+    for (int k = 0; k < 3; ++k) { M->V[k] = (float*)p; p += bytes; }
+    for (int k = 0; k < 3; ++k) { M->N[k] = (float*)p; p += bytes; }
+    M->I = (float*)p; p += bytes;
+    for (int k = 0; k < 2; ++k) { M->G[k] = (float*)p; p += bytes; }
+    s->ppt[l] = default_ppt(C->W * C->H);
+  }
+  s->partials = (float*)p; p += align256(lo.partial_floats * sizeof(float));
+  s->sd = (SessionDev*)p; p += align256(sizeof(SessionDev));
+  s->red_out = (double*)p; p += align256(64 * sizeof(double));
+  s->xf_scratch = (float*)p;
+  SessionDev init;
+  std::memset(&init, 0, sizeof(init));
+  init.x0 = *x0;
+  init.x1 = *x0;
+  for (int i = 0; i < 4; ++i) init.qIW[i] = q_IW[i];
+  if (prior) init.prior = *prior;
+  if (hipMemset(s->arena, 0, lo.planes) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
+  if (hipMemcpy(s->sd, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
+  if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
+  *out = s;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_session_close(dslam_session* s) {
+  if (!s) return DSLAM_ERR_INVALID;
+  hipSetDevice(s->ctx->device);
+  hipDeviceSynchronize();
+  hipEventDestroy(s->done);
+  hipFree(s->arena);
+  s->ctx->used.fetch_sub(s->bytes);
+  delete s;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_build_pyramid(dslam_session* s, int32_t which, const float* depth_dev,
+                                 const uint8_t* intensity_dev, int32_t pitch_elems, const double T_W_ref[16],
+                                 void* stream) {
+  if (!s || !depth_dev || !intensity_dev || pitch_elems < s->cam.width) return DSLAM_ERR_INVALID;
+  if (which != DSLAM_PYR_CURRENT && which != DSLAM_PYR_MODEL) return DSLAM_ERR_INVALID;
+  if (which == DSLAM_PYR_MODEL) {
+    if (!T_W_ref) return DSLAM_ERR_INVALID;
+    for (int i = 0; i < 16; ++i)
+      if (!std::isfinite(T_W_ref[i])) return DSLAM_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> g(s->mu);
+  HIP_OK(hipSetDevice(s->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  LevelPtrs* P = which == DSLAM_PYR_MODEL ? s->model : s->cur;
+  int grad = which == DSLAM_PYR_MODEL;
+  HIP_OK(launch_pyramid_level0(depth_dev, intensity_dev, pitch_elems, P[0], grad, st));
+  for (int l = 1; l < s->levels; ++l) HIP_OK(launch_pyramid_down(P[l - 1], P[l], grad, st));
+  if (which == DSLAM_PYR_MODEL) {
+    std::memcpy(s->T_WM, T_W_ref, sizeof(s->T_WM));
+    s->have_model = true;
+  }
+  return DSLAM_OK;
+}
+
+dslam_status dslam_preintegrate_imu(const dslam_imu_sample* samples, int32_t n, double t0, double t1,
+                                    const double bg[3], const double ba[3], const dslam_imu_params* p,
+                                    dslam_preint* out) {
+  if (!samples || !bg || !ba || !p || !out) return DSLAM_ERR_INVALID;
+  PreintWork* w = new (std::nothrow) PreintWork;
+  if (!w) return DSLAM_ERR_NO_CAPACITY;
+  dslam_preint r;
+  int st = preintegrate(Par{0, 1}, samples, n, t0, t1, bg, ba, p->sigma_g, p->sigma_a, w, &r);
+  delete w;
+  if (st != DSLAM_OK) return (dslam_status)st;
+  *out = r;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_solve_step(const double raw[58], const double T_WM[16], const dslam_preint* pre,
+                              const dslam_imu_params* ip, const dslam_track_params* tp, const dslam_prior* prior,
+                              dslam_frame_state* x0, dslam_frame_state* x1, double q_IW[4], double dz_out[33],
+                              dslam_prior* marg_out) {
+  if (!raw || !T_WM || !ip || !tp || !x0 || !x1 || !q_IW) return DSLAM_ERR_INVALID;
+  if (tp->mode != DSLAM_MODE_RGBD && tp->mode != DSLAM_MODE_RGBDI) return DSLAM_ERR_INVALID;
+  if (tp->mode == DSLAM_MODE_RGBDI && (!pre || !prior)) return DSLAM_ERR_INVALID;
+  if (!state_ok(x0) || !state_ok(x1) || !quat_ok(q_IW)) return DSLAM_ERR_INVALID;
+  SolveWork* w = new (std::nothrow) SolveWork;
+  if (!w) return DSLAM_ERR_NO_CAPACITY;
+  SolveParams sp;
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) sp.R_WM[3 * r + c] = T_WM[4 * r + c];
+    sp.t_WM[r] = T_WM[4 * r + 3];
+  }
+  sp.imu = imu_params_d(*ip);
+  sp.mode = tp->mode;
+  sp.marginalise = marg_out != nullptr;
+  dslam_frame_state a = *x0, b = *x1;
+  double q[4] = {q_IW[0], q_IW[1], q_IW[2], q_IW[3]};
+  dslam_prior m;
+  dslam_preint dummy_pre;
+  dslam_prior dummy_prior;
+  if (!pre) { std::memset(&dummy_pre, 0, sizeof(dummy_pre)); pre = &dummy_pre; }
+  if (!prior) { std::memset(&dummy_prior, 0, sizeof(dummy_prior)); prior = &dummy_prior; }
+  int st = solve_step(Par{0, 1}, w, raw, sp, pre, prior, &a, &b, q, &m);
+  if (st == DSLAM_OK) {
+    *x0 = a;
+    *x1 = b;
+    for (int i = 0; i < 4; ++i) q_IW[i] = q[i];
+    if (dz_out) {
+      int n = tp->mode == DSLAM_MODE_RGBD ? 6 : NZ;
+      for (int i = 0; i < NZ; ++i) dz_out[i] = i < n ? w->dz[i] : 0.0;
+    }
+    if (marg_out && tp->mode != DSLAM_MODE_RGBD) *marg_out = m;
+  }
+  delete w;
+  return (dslam_status)st;
+}
+
+dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const uint8_t* intensity_dev,
+                               int32_t pitch_elems, const dslam_imu_sample* imu, int32_t n_imu, double t0,
+                               double t1, void* stream) {
+  if (!s || !depth_dev || !intensity_dev || pitch_elems < s->cam.width) return DSLAM_ERR_INVALID;
+  const bool inertial = s->tp.mode != DSLAM_MODE_RGBD;
+  ImuBatch batch;
+  std::memset(&batch, 0, sizeof(batch));
+  if (inertial) {
+    if (!imu || n_imu < 1 || n_imu > DSLAM_MAX_IMU_SAMPLES || !(t1 > t0)) return DSLAM_ERR_INVALID;
+    if (!(imu[0].t <= t0)) return DSLAM_ERR_INVALID;
+    for (int k = 1; k < n_imu; ++k)
+      if (!(imu[k].t > imu[k - 1].t)) return DSLAM_ERR_INVALID;
+    batch.n = n_imu;
+    batch.t0 = t0;
+    batch.t1 = t1;
+    for (int k = 0; k < n_imu; ++k) batch.s[k] = imu[k];
+  }
+  if (!s->have_model) return DSLAM_ERR_NOT_READY;
+  dslam_status st0 = dslam_build_pyramid(s, DSLAM_PYR_CURRENT, depth_dev, intensity_dev, pitch_elems, nullptr, stream);
+  if (st0 != DSLAM_OK) return st0;
+  std::lock_guard<std::mutex> g(s->mu);
+  hipStream_t st = (hipStream_t)stream;
+  FrameArgs fa;
+  fa.imu = imu_params_d(s->ip);
+  fa.sigma_g = s->ip.sigma_g;
+  fa.sigma_a = s->ip.sigma_a;
+  SolveArgs sa;
+  sa.sp = solve_params(s);
+  for (int i = 0; i < 9; ++i) fa.R_WM[i] = sa.sp.R_WM[i];
+  for (int i = 0; i < 3; ++i) fa.t_WM[i] = sa.sp.t_WM[i];
+  fa.mode = s->tp.mode;
+  HIP_OK(launch_frame_init(s->sd, batch, fa, st));
+  int last_level = -1;
+  for (int l = s->levels - 1; l >= 0; --l)
+    if (s->tp.iters[l] > 0) last_level = l;
+  for (int l = s->levels - 1; l >= 0; --l) {
+    ResidualArgs ra = residual_args(s, l, s->sd->xf, s->partials, nullptr);
+    int nb = residual_blocks(ra.npix, s->ppt[l]);
+    for (int it = 0; it < s->tp.iters[l]; ++it) {
+      HIP_OK(launch_residual(ra, s->ppt[l], st));
+      sa.level = l;
+      sa.nblocks = nb;
+      sa.last = (l == last_level && it == s->tp.iters[l] - 1) ? 1 : 0;
+      HIP_OK(launch_solve(s->sd, s->partials, sa, st));
+    }
+  }
+  if (last_level < 0) return DSLAM_ERR_INVALID;
+  HIP_OK(hipEventRecord(s->done, st));
+  return DSLAM_OK;
+}
+
+dslam_status dslam_session_result(dslam_session* s, dslam_track_result* out) {
+  if (!s || !out) return DSLAM_ERR_INVALID;
+  HIP_OK(hipSetDevice(s->ctx->device));
+  HIP_OK(hipEventSynchronize(s->done));
+  HIP_OK(hipMemcpy(out, &s->sd->result, sizeof(dslam_track_result), hipMemcpyDeviceToHost));
+  return DSLAM_OK;
+}
+
+dslam_status dslam_linearize(dslam_session* s, int32_t level, const float Ra[9], const float ta[3],
+                             const float Rb[9], const float tb[3], const dslam_frame_state* x0,
+                             const dslam_frame_state* x1, uint8_t* mask_dev, dslam_linear_system* out,
+                             void* stream) {
+  if (!s || !Ra || !ta || !Rb || !tb || !state_ok(x0) || !state_ok(x1) || !out) return DSLAM_ERR_INVALID;
+  if (level < 0 || level >= s->levels) return DSLAM_ERR_INVALID;
+  if (!s->have_model) return DSLAM_ERR_NOT_READY;
+  std::lock_guard<std::mutex> g(s->mu);
+  HIP_OK(hipSetDevice(s->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  float xf[24];
+  for (int i = 0; i < 9; ++i) { xf[i] = Ra[i]; xf[12 + i] = Rb[i]; }
+  for (int i = 0; i < 3; ++i) { xf[9 + i] = ta[i]; xf[21 + i] = tb[i]; }
+  HIP_OK(hipMemcpyAsync(s->xf_scratch, xf, sizeof(xf), hipMemcpyHostToDevice, st));
+  ResidualArgs ra = residual_args(s, level, s->xf_scratch, s->partials, mask_dev);
+  int nb = residual_blocks(ra.npix, s->ppt[level]);
+  HIP_OK(launch_residual(ra, s->ppt[level], st));
+  HIP_OK(launch_reduce(s->partials, nb, s->red_out, st));
+  double raw[64];
+  HIP_OK(hipMemcpyAsync(raw, s->red_out, 58 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  SolveParams sp = solve_params(s);
+  dslam_linear_system r;
+  lift_visual(raw, sp.R_WM, *x0, *x1, r.H_icp, r.b_icp, r.H_rgb, r.b_rgb);
+  r.cost_icp = raw[27];
+  r.cost_rgb = raw[29 + 27];
+  r.n_icp = (int64_t)raw[28];
+  r.n_rgb = (int64_t)raw[57];
+  for (int i = 0; i < 58; ++i) r.raw[i] = raw[i];
+  *out = r;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_profile_residual(dslam_session* s, int32_t level, int32_t reps, void* stream) {
+  if (!s || level < 0 || level >= s->levels || reps < 1 || reps > 100000) return DSLAM_ERR_INVALID;
+  if (!s->have_model) return DSLAM_ERR_NOT_READY;
+  std::lock_guard<std::mutex> g(s->mu);
+  HIP_OK(hipSetDevice(s->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  ResidualArgs ra = residual_args(s, level, s->sd->xf, s->partials, nullptr);
+  for (int r = 0; r < reps; ++r) HIP_OK(launch_residual(ra, s->ppt[level], st));
+  return DSLAM_OK;
+}
+
+dslam_status dslam_copy_pyramid(dslam_session* s, int32_t which, int32_t level, int32_t channel, float* host_out) {
+  if (!s || !host_out || level < 0 || level >= s->levels) return DSLAM_ERR_INVALID;
+  if (which != DSLAM_PYR_CURRENT && which != DSLAM_PYR_MODEL) return DSLAM_ERR_INVALID;
+  const LevelPtrs& L = which == DSLAM_PYR_MODEL ? s->model[level] : s->cur[level];
+  const float* src = nullptr;
+  if (channel >= DSLAM_CH_VX && channel <= DSLAM_CH_VZ) src = L.V[channel - DSLAM_CH_VX];
+  else if (channel >= DSLAM_CH_NX && channel <= DSLAM_CH_NZ) src = L.N[channel - DSLAM_CH_NX];
+  else if (channel == DSLAM_CH_I) src = L.I;
+  else if ((channel == DSLAM_CH_GX || channel == DSLAM_CH_GY) && which == DSLAM_PYR_MODEL) src = L.G[channel - DSLAM_CH_GX];
+  if (!src) return DSLAM_ERR_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  HIP_OK(hipSetDevice(s->ctx->device));
+  HIP_OK(hipDeviceSynchronize());
+  HIP_OK(hipMemcpy(host_out, src, (size_t)L.W * L.H * sizeof(float), hipMemcpyDeviceToHost));
+  return DSLAM_OK;
+}
+
+dslam_status dslam_session_get_state(dslam_session* s, dslam_frame_state* x0, double q_IW[4], dslam_prior* prior,
+                                     int32_t* frame_index) {
+  if (!s) return DSLAM_ERR_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  HIP_OK(hipSetDevice(s->ctx->device));
+  HIP_OK(hipDeviceSynchronize());
+  SessionDev d;
+  HIP_OK(hipMemcpy(&d, s->sd, sizeof(d), hipMemcpyDeviceToHost));
+  if (x0) *x0 = d.x0;
+  if (q_IW) for (int i = 0; i < 4; ++i) q_IW[i] = d.qIW[i];
+  if (prior) *prior = d.prior;
+  if (frame_index) *frame_index = d.frame_index;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_session_set_state(dslam_session* s, const dslam_frame_state* x0, const double q_IW[4],
+                                     const dslam_prior* prior, int32_t frame_index) {
+  if (!s || !state_ok(x0) || !q_IW || !quat_ok(q_IW)) return DSLAM_ERR_INVALID;
+  if (s->tp.mode != DSLAM_MODE_RGBD && !prior) return DSLAM_ERR_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  HIP_OK(hipSetDevice(s->ctx->device));
+  HIP_OK(hipDeviceSynchronize());
+  SessionDev d;
+  HIP_OK(hipMemcpy(&d, s->sd, sizeof(d), hipMemcpyDeviceToHost));
+  d.x0 = *x0;
+  d.x1 = *x0;
+  for (int i = 0; i < 4; ++i) d.qIW[i] = q_IW[i];
+  if (prior) d.prior = *prior;
+  d.frame_index = frame_index;
+  d.status = DSLAM_OK;
+  HIP_OK(hipMemcpy(s->sd, &d, sizeof(d), hipMemcpyHostToDevice));
+  return DSLAM_OK;
+}
+
+}  // extern "C"

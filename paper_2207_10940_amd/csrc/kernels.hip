@@ -1,0 +1,282 @@
+// Pyramid construction and the dense residual pass (gfx950).
+//
+// This translation unit is compiled with -ffp-contract=off and correctly
+// rounded float32 division and square root: every operation that decides a
+// pyramid value, a validity bit or an association is one IEEE float32
+// operation in the order written.  Where fused multiply-adds are wanted (the
+// value layer: bilinear weights, Jacobian products, accumulation) they are
+// written explicitly with fmaf().
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "device.h"
+
+namespace dslam {
+
+// ---------------------------------------------------------------------------
+// Pyramid (Section IV-D: three-level coarse-to-fine scheme).
+//   level 0: depth cleaned (finite and > 0, else 0), intensity = float(uint8);
+//   level l+1: depth = mean of the valid depths of the 2x2 block summed in the
+//   order (2x,2y), (2x+1,2y), (2x,2y+1), (2x+1,2y+1); intensity =
+//   ((a + b) + (c + d)) * 0.25;
+//   vertex = rho(u, d) = (((i - cx) d) / fx, ((j - cy) d) / fy, d);
+//   normal = (a x b) / |a x b| with a = V(i+1,j) - V(i,j), b = V(i,j+1) - V(i,j);
+//   gradient (model view) = central differences * 0.5, zero on the border.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float clean_depth(float d) { return (__builtin_isfinite(d) && d > 0.0f) ? d : 0.0f; }
+
+struct Src0 {  // level 0 from the caller's images
+  const float* depth;
+  const uint8_t* inten;
+  int pitch;
+  __device__ __forceinline__ float D(int i, int j) const { return clean_depth(depth[(size_t)j * pitch + i]); }
+  __device__ __forceinline__ float I(int i, int j) const { return (float)inten[(size_t)j * pitch + i]; }
+};
+
+struct SrcDown {  // level l+1 from level l's depth (V[2]) and intensity planes
+  const float* pd;
+  const float* pi;
+  int pw;
+  __device__ __forceinline__ float D(int i, int j) const {
+    const float* r0 = pd + (size_t)(2 * j) * pw + 2 * i;
+    const float* r1 = r0 + pw;
+    float t[4] = {r0[0], r0[1], r1[0], r1[1]};
+    float s = 0.0f, n = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (t[k] > 0.0f) {
+        s = s + t[k];
+        n = n + 1.0f;
+      }
+    return n > 0.0f ? s / n : 0.0f;
+  }
+  __device__ __forceinline__ float I(int i, int j) const {
+    const float* r0 = pi + (size_t)(2 * j) * pw + 2 * i;
+    const float* r1 = r0 + pw;
+    return ((r0[0] + r0[1]) + (r1[0] + r1[1])) * 0.25f;
+  }
+};
+
+template <class Src>
+__global__ __launch_bounds__(256) void pyramid_level_kernel(Src src, LevelPtrs L, int with_grad) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= L.W || j >= L.H) return;
+  const size_t p = (size_t)j * L.W + i;
+  float d = src.D(i, j);
+  float inten = src.I(i, j);
+  float fi = (float)i, fj = (float)j;
+  float vx = ((fi - L.cx) * d) / L.fx;
+  float vy = ((fj - L.cy) * d) / L.fy;
+  L.V[0][p] = vx;
+  L.V[1][p] = vy;
+  L.V[2][p] = d;
+  L.I[p] = inten;
+  float nx = 0.0f, ny = 0.0f, nz = 0.0f;
+  if (i < L.W - 1 && j < L.H - 1) {
+    float dr = src.D(i + 1, j), dd = src.D(i, j + 1);
+    float ax = (((fi + 1.0f) - L.cx) * dr) / L.fx - vx;
+    float ay = ((fj - L.cy) * dr) / L.fy - vy;
+    float az = dr - d;
+    float bx = ((fi - L.cx) * dd) / L.fx - vx;
+    float by = (((fj + 1.0f) - L.cy) * dd) / L.fy - vy;
+    float bz = dd - d;
+    float cx = ay * bz - az * by;
+    float cy = az * bx - ax * bz;
+    float cz = ax * by - ay * bx;
+    float len = __builtin_sqrtf((cx * cx + cy * cy) + cz * cz);
+    if (d > 0.0f && dr > 0.0f && dd > 0.0f && len > 0.0f) {
+      nx = cx / len;
+      ny = cy / len;
+      nz = cz / len;
+    }
+  }
+  L.N[0][p] = nx;
+  L.N[1][p] = ny;
+  L.N[2][p] = nz;
+  if (with_grad) {
+    float gx = 0.0f, gy = 0.0f;
+    if (i > 0 && i < L.W - 1 && j > 0 && j < L.H - 1) {
+      gx = (src.I(i + 1, j) - src.I(i - 1, j)) * 0.5f;
+      gy = (src.I(i, j + 1) - src.I(i, j - 1)) * 0.5f;
+    }
+    L.G[0][p] = gx;
+    L.G[1][p] = gy;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual pass: association, residuals, Jacobians, weights and the block
+// reduction of the per-term normal equations (Section IV-B/D).
+// ---------------------------------------------------------------------------
+
+// j = [k, a x k]; accumulates w j j^T (upper triangle, 21), w j e (6), w e^2, count.
+__device__ __forceinline__ void accumulate(float* acc, const float* jv, float e, float w) {
+  float wj[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) wj[a] = w * jv[a];
+  int k = 0;
+#pragma unroll
+  for (int a = 0; a < 6; ++a)
+#pragma unroll
+    for (int b = a; b < 6; ++b) {
+      acc[k] = fmaf(wj[a], jv[b], acc[k]);
+      ++k;
+    }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) acc[21 + a] = fmaf(wj[a], e, acc[21 + a]);
+  acc[27] = fmaf(w * e, e, acc[27]);
+  acc[28] = acc[28] + 1.0f;
+}
+
+__device__ __forceinline__ float huber(float s, float k) { return (k > 0.0f && s > k) ? k / s : 1.0f; }
+
+__device__ __forceinline__ void pixel(const ResidualArgs& a, const float* T, int p, float* acc) {
+  const float x = a.cV0[p], y = a.cV1[p], z = a.cV2[p];
+  uint8_t bits = 0;
+  if (z > 0.0f) {
+    // ---- ICP: projective association in the model-view camera (mask layer)
+    float qx = ((T[0] * x + T[1] * y) + T[2] * z) + T[9];
+    float qy = ((T[3] * x + T[4] * y) + T[5] * z) + T[10];
+    float qz = ((T[6] * x + T[7] * y) + T[8] * z) + T[11];
+    if (qz > 0.0f) {
+      float inv = 1.0f / qz;
+      float u = ((a.fx * qx) * inv) + a.cx;
+      float v = ((a.fy * qy) * inv) + a.cy;
+      float ui = __builtin_rintf(u), vi = __builtin_rintf(v);
+      if (ui >= 0.0f && ui <= (float)(a.W - 1) && vi >= 0.0f && vi <= (float)(a.H - 1)) {
+        int m = (int)vi * a.W + (int)ui;
+        float v0x = a.mV0[m], v0y = a.mV1[m], v0z = a.mV2[m];
+        float n0x = a.mN0[m], n0y = a.mN1[m], n0z = a.mN2[m];
+        bool n0ok = (n0x != 0.0f) | (n0y != 0.0f) | (n0z != 0.0f);
+        float ex = qx - v0x, ey = qy - v0y, ez = qz - v0z;
+        float dist2 = (ex * ex + ey * ey) + ez * ez;
+        bool ok = v0z > 0.0f && n0ok && dist2 <= a.dist2;
+        if (a.cosmin >= -1.0f) {  // optional normal-compatibility gate
+          float n1x = a.cN0[p], n1y = a.cN1[p], n1z = a.cN2[p];
+          bool n1ok = (n1x != 0.0f) | (n1y != 0.0f) | (n1z != 0.0f);
+          float nrx = (T[0] * n1x + T[1] * n1y) + T[2] * n1z;
+          float nry = (T[3] * n1x + T[4] * n1y) + T[5] * n1z;
+          float nrz = (T[6] * n1x + T[7] * n1y) + T[8] * n1z;
+          float cosang = (nrx * n0x + nry * n0y) + nrz * n0z;
+          ok = ok && n1ok && cosang >= a.cosmin;
+        }
+        if (ok) {
+          // ---- value layer (eq. (4)): e = n0 . (q - v0), j = [n0, a' x n0]
+          float e = fmaf(n0x, ex, fmaf(n0y, ey, n0z * ez));
+          float px = qx - T[9], py = qy - T[10], pz = qz - T[11];
+          float jv[6] = {n0x, n0y, n0z, fmaf(py, n0z, -pz * n0y), fmaf(pz, n0x, -px * n0z), fmaf(px, n0y, -py * n0x)};
+          float isg = 1.0f / (a.depth_k * z * z);
+          float s = fabsf(e) * isg;
+          float w = isg * isg * huber(s, a.huber_k);
+          accumulate(acc, jv, e, w);
+          bits |= 1;
+        }
+      }
+    }
+    // ---- photometric: warp into the reference camera (mask layer)
+    float rx = ((T[12] * x + T[13] * y) + T[14] * z) + T[21];
+    float ry = ((T[15] * x + T[16] * y) + T[17] * z) + T[22];
+    float rz = ((T[18] * x + T[19] * y) + T[20] * z) + T[23];
+    if (rz > 0.0f) {
+      float inv = 1.0f / rz;
+      float u = ((a.fx * rx) * inv) + a.cx;
+      float v = ((a.fy * ry) * inv) + a.cy;
+      if (u >= 1.0f && u < (float)(a.W - 2) && v >= 1.0f && v < (float)(a.H - 2)) {
+        // ---- value layer (eq. (3)): bilinear I0 and gradient at (u, v)
+        float fu = floorf(u), fv = floorf(v);
+        int x0 = (int)fu, y0 = (int)fv;
+        float au = u - fu, av = v - fv;
+        int m = y0 * a.W + x0;
+        float w00 = (1.0f - au) * (1.0f - av), w10 = au * (1.0f - av), w01 = (1.0f - au) * av, w11 = au * av;
+        float I0 = fmaf(w00, a.mI[m], fmaf(w10, a.mI[m + 1], fmaf(w01, a.mI[m + a.W], w11 * a.mI[m + a.W + 1])));
+        float gx = fmaf(w00, a.mG0[m], fmaf(w10, a.mG0[m + 1], fmaf(w01, a.mG0[m + a.W], w11 * a.mG0[m + a.W + 1])));
+        float gy = fmaf(w00, a.mG1[m], fmaf(w10, a.mG1[m + 1], fmaf(w01, a.mG1[m + a.W], w11 * a.mG1[m + a.W + 1])));
+        float e = I0 - a.cI[p];
+        float gfx = gx * a.fx * inv, gfy = gy * a.fy * inv;
+        float g2 = -fmaf(gfx, rx, gfy * ry) * inv;
+        float px = rx - T[21], py = ry - T[22], pz = rz - T[23];
+        float jv[6] = {gfx, gfy, g2, fmaf(py, g2, -pz * gfy), fmaf(pz, gfx, -px * g2), fmaf(px, gfy, -py * gfx)};
+        float s = fabsf(e) / a.sigma_I;
+        float w = huber(s, a.huber_k) / (a.sigma_I * a.sigma_I);
+        accumulate(acc + 29, jv, e, w);
+        bits |= 2;
+      }
+    }
+  }
+  if (a.mask) a.mask[p] = bits;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int PPT>
+__global__ __launch_bounds__(RES_THREADS) void residual_kernel(ResidualArgs a) {
+  __shared__ float red[RES_THREADS / 64][58];
+  float T[24];
+#pragma unroll
+  for (int k = 0; k < 24; ++k) T[k] = a.xf[k];
+  float acc[58];
+#pragma unroll
+  for (int k = 0; k < 58; ++k) acc[k] = 0.0f;
+  const int base = blockIdx.x * RES_THREADS * PPT + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    int p = base + k * RES_THREADS;
+    if (p < a.npix) pixel(a, T, p, acc);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 58; ++k) {
+    float s = wave_sum(acc[k]);
+    if (lane == 0) red[wave][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 58) {
+    float s = red[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < RES_THREADS / 64; ++w) s += red[w][threadIdx.x];
+    a.partials[(size_t)blockIdx.x * PARTIAL_STRIDE + threadIdx.x] = s;
+  }
+}
+
+}  // namespace dslam
+
+// ---------------------------------------------------------------------------
+// launch wrappers (host)
+// ---------------------------------------------------------------------------
+namespace dslam {
+
+hipError_t launch_pyramid_level0(const float* depth, const uint8_t* inten, int pitch, const LevelPtrs& L,
+                                 int with_grad, hipStream_t st) {
+  dim3 blk(64, 4), grd((L.W + 63) / 64, (L.H + 3) / 4);
+  Src0 s{depth, inten, pitch};
+  hipLaunchKernelGGL(pyramid_level_kernel<Src0>, grd, blk, 0, st, s, L, with_grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_pyramid_down(const LevelPtrs& parent, const LevelPtrs& L, int with_grad, hipStream_t st) {
+  dim3 blk(64, 4), grd((L.W + 63) / 64, (L.H + 3) / 4);
+  SrcDown s{parent.V[2], parent.I, parent.W};
+  hipLaunchKernelGGL(pyramid_level_kernel<SrcDown>, grd, blk, 0, st, s, L, with_grad);
+  return hipGetLastError();
+}
+
+int residual_blocks(int npix, int ppt) { return (npix + RES_THREADS * ppt - 1) / (RES_THREADS * ppt); }
+
+hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st) {
+  int nb = residual_blocks(a.npix, ppt);
+  switch (ppt) {
+    case 1: hipLaunchKernelGGL(residual_kernel<1>, dim3(nb), dim3(RES_THREADS), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(residual_kernel<2>, dim3(nb), dim3(RES_THREADS), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(residual_kernel<4>, dim3(nb), dim3(RES_THREADS), 0, st, a); break;
+    case 8: hipLaunchKernelGGL(residual_kernel<8>, dim3(nb), dim3(RES_THREADS), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dslam

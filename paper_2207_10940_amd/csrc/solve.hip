@@ -1,0 +1,171 @@
+// Device-side frame initialisation (IMU preintegration and prediction), the
+// cross-block float64 reduction and the float64 Gauss-Newton solve, so that
+// the whole coarse-to-fine iteration stays on the GPU (Section IV-C/D/E).
+// One workgroup of one wavefront runs each of these small kernels.
+#include <hip/hip_runtime.h>
+#include "device.h"
+#include "solve_core.h"
+
+namespace dslam {
+
+struct ImuBatch {
+  int32_t n;
+  double t0, t1;
+  dslam_imu_sample s[DSLAM_MAX_IMU_SAMPLES];
+};
+
+struct FrameArgs {
+  ImuParamsD imu;
+  double sigma_g, sigma_a;
+  double R_WM[9], t_WM[3];
+  int32_t mode;
+};
+
+struct SolveArgs {
+  SolveParams sp;
+  int32_t level;
+  int32_t last;      // 1 on the last iteration of the frame: marginalise and publish
+  int32_t nblocks;
+};
+
+enum { SOLVE_THREADS = 64 };
+
+// Fixed-order float64 sum of the block partials (cross-block reduction).
+__device__ void reduce_partials(const float* partials, int nblocks, double* out) {
+  int l = threadIdx.x;
+  if (l < 58) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = 0;
+    for (; b + 4 <= nblocks; b += 4) {
+      s0 += (double)partials[(size_t)(b + 0) * PARTIAL_STRIDE + l];
+      s1 += (double)partials[(size_t)(b + 1) * PARTIAL_STRIDE + l];
+      s2 += (double)partials[(size_t)(b + 2) * PARTIAL_STRIDE + l];
+      s3 += (double)partials[(size_t)(b + 3) * PARTIAL_STRIDE + l];
+    }
+    for (; b < nblocks; ++b) s0 += (double)partials[(size_t)b * PARTIAL_STRIDE + l];
+    out[l] = (s0 + s1) + (s2 + s3);
+  }
+}
+
+__global__ __launch_bounds__(SOLVE_THREADS) void reduce_kernel(const float* partials, int nblocks, double* out) {
+  reduce_partials(partials, nblocks, out);
+}
+
+__global__ __launch_bounds__(SOLVE_THREADS) void frame_init_kernel(SessionDev* sd, ImuBatch batch, FrameArgs fa) {
+  __shared__ PreintWork pw;
+  __shared__ dslam_preint pre;
+  __shared__ dslam_frame_state x0;
+  __shared__ double qIW[4];
+  Par par{(int)threadIdx.x, SOLVE_THREADS};
+  SERIAL {
+    x0 = sd->x0;
+    for (int i = 0; i < 4; ++i) qIW[i] = sd->qIW[i];
+    sd->status = DSLAM_OK;
+  }
+  DSLAM_SYNC();
+  int st = DSLAM_OK;
+  if (fa.mode != DSLAM_MODE_RGBD)
+    st = preintegrate(par, batch.s, batch.n, batch.t0, batch.t1, x0.bg, x0.ba, fa.sigma_g, fa.sigma_a, &pw, &pre);
+  SERIAL {
+    if (st != DSLAM_OK) sd->status = st;
+    dslam_frame_state x1 = x0;
+    if (fa.mode != DSLAM_MODE_RGBD && st == DSLAM_OK) {
+      sd->pre = pre;
+      imu_predict(x0, qIW, pre, fa.imu, &x1);
+    }
+    sd->x1 = x1;
+    next_transforms(x0, x1, fa.R_WM, fa.t_WM, sd->xf);
+    for (int l = 0; l < DSLAM_MAX_LEVELS; ++l) {
+      sd->result.n_icp[l] = 0;
+      sd->result.n_rgb[l] = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, const float* partials, SolveArgs a) {
+  __shared__ SolveWork w;
+  __shared__ double raw[58];
+  __shared__ dslam_frame_state x0, x1;
+  __shared__ double qIW[4];
+  __shared__ dslam_prior marg;
+  __shared__ int skip;
+  Par par{(int)threadIdx.x, SOLVE_THREADS};
+  reduce_partials(partials, a.nblocks, raw);
+  SERIAL {
+    skip = sd->status != DSLAM_OK;
+    x0 = sd->x0;
+    x1 = sd->x1;
+    for (int i = 0; i < 4; ++i) qIW[i] = sd->qIW[i];
+  }
+  DSLAM_SYNC();
+  if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
+  if (skip) {
+    if (a.last) {
+      SERIAL {
+        sd->result.status = sd->status;
+        sd->result.frame_index = sd->frame_index;
+      }
+    }
+    return;
+  }
+  SolveParams sp = a.sp;
+  sp.marginalise = a.last;
+  int st = solve_step(par, &w, raw, sp, &sd->pre, &sd->prior, &x0, &x1, qIW, &marg);
+  SERIAL {
+    if (st != DSLAM_OK) {
+      sd->status = st;
+    } else {
+      sd->x0 = x0;
+      sd->x1 = x1;
+      for (int i = 0; i < 4; ++i) sd->qIW[i] = qIW[i];
+      next_transforms(x0, x1, sp.R_WM, sp.t_WM, sd->xf);
+    }
+    sd->result.n_icp[a.level] = (int64_t)raw[28];
+    sd->result.n_rgb[a.level] = (int64_t)raw[57];
+    sd->result.cost_icp = w.cost[0];
+    sd->result.cost_rgb = w.cost[1];
+    sd->result.cost_imu = w.cost[2];
+    double nrm = 0.0;
+    int n = sp.mode != DSLAM_MODE_RGBD ? NZ : 6;
+    for (int i = 0; i < n; ++i) nrm += w.dz[i] * w.dz[i];
+    sd->result.last_step_norm = sqrt(nrm);
+  }
+  if (a.last) {
+    DSLAM_SYNC();
+    SERIAL {
+      dslam_track_result& r = sd->result;
+      r.status = sd->status;
+      r.x0 = x0;
+      r.x1 = x1;
+      for (int i = 0; i < 4; ++i) r.q_IW[i] = qIW[i];
+      if (sd->status == DSLAM_OK) {
+        if (sp.mode != DSLAM_MODE_RGBD) {
+          sd->prior = marg;
+          r.prior = marg;
+        }
+        // the current state becomes the previous one of the next frame
+        sd->x0 = x1;
+        sd->frame_index += 1;
+      }
+      r.frame_index = sd->frame_index;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_frame_init(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, hipStream_t st) {
+  hipLaunchKernelGGL(frame_init_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, sd, b, fa);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, sd, partials, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, partials, nblocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace dslam

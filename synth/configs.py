@@ -21,6 +21,7 @@ from .trajectory import ConstantTwistTrajectory, base_orientation, make_spline_t
 # Table I (synthetic column) and the configs' sensor noise
 BIAS_PRIOR_G = 0.03
 BIAS_PRIOR_A = 0.1
+SEQUENCE_SECONDS = 301 / 30.0
 
 
 @dataclass
@@ -143,7 +144,9 @@ def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: in
     track frame j is the noise-free render at frame j-1's ground-truth pose."""
     rng = np.random.default_rng(seed)
     scene = make_scene(rng, seed)
-    duration = (n_frames + 1) / fps
+    # the trajectory and the IMU stream always span the full 10 s sequence, so a
+    # shorter sequence is a prefix of the long one
+    duration = max((n_frames + 1) / fps, SEQUENCE_SECONDS)
     traj = make_spline_trajectory(rng, duration)
     cam = camera_for(width, height)
     gen = torch.Generator(device="cpu").manual_seed(seed)
@@ -153,7 +156,7 @@ def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: in
     noise = ImuNoise()
     bg0 = rng.normal(0.0, 2e-3, 3)
     ba0 = rng.normal(0.0, 2e-2, 3)
-    stamps, gyro, acc, tbg, tba = synth_imu(traj, 0.0, times[-1] + 1.0 / fps, imu_rate, rng, noise, bg0, ba0)
+    stamps, gyro, acc, tbg, tba = synth_imu(traj, 0.0, duration - 1.0 / fps, imu_rate, rng, noise, bg0, ba0)
     for j, t in enumerate(times):
         R_IC, p_IC = traj.pose(t)
         z, inten = render(scene, R_IC, p_IC, cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy,

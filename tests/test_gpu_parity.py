@@ -1,0 +1,173 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: pyramid values, association masks and inlier counts bit-exact; visual
+J^T J within 1e-5 relative Frobenius and J^T r within 1e-5 of its normwise
+scale | |J|^T |w e| |; final pose within 1e-6 rad / 1e-6 m."""
+import numpy as np
+import pytest
+
+import paper_2207_10940_amd as P
+import synth
+from oracle import lie, track
+from tests.gpu_common import cuda, jtr_scale, pose_err, rel_fro, session
+
+pytestmark = pytest.mark.gpu
+
+CHANNELS = {"V": (P.CH_VX, P.CH_VY, P.CH_VZ), "N": (P.CH_NX, P.CH_NY, P.CH_NZ), "I": (P.CH_I,),
+            "G": (P.CH_GX, P.CH_GY)}
+
+
+def _bits(a):
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+@pytest.mark.parametrize("W,H,levels", [(160, 120, 2), (200, 152, 3), (640, 480, 3)])
+def test_pyramid_bit_exact(W, H, levels):
+    d = synth.configs.frame_pair(width=W, height=H)
+    depth = d["depth"].numpy().copy()
+    depth[3, 5], depth[7, 11], depth[10, 2] = np.nan, np.inf, -1.0
+    depth[20:26, 30:41] = 0.0  # a hole
+    inten = d["intensity"].numpy()
+    print(f"pyramid {W}x{H} L{levels}", flush=True)
+    with session(W, H, levels, [1] * levels, mode="rgbd") as s:
+        s.build_pyramid(P.PYR_CURRENT, cuda(depth), cuda(inten))
+        s.build_pyramid(P.PYR_MODEL, cuda(depth), cuda(inten), np.eye(4))
+        cam = d["camera"]
+        from oracle import pyramid as pyr
+        ref = pyr.build(depth, inten, cam.fx, cam.fy, cam.cx, cam.cy, levels, with_gradient=True)
+        for l in range(levels):
+            for which in (P.PYR_CURRENT, P.PYR_MODEL):
+                for key, chans in CHANNELS.items():
+                    if key == "G" and which == P.PYR_CURRENT:
+                        continue
+                    for k, ch in enumerate(chans):
+                        got = s.copy_pyramid(which, l, ch)
+                        want = ref[l][key][..., k] if ref[l][key].ndim == 3 else ref[l][key]
+                        assert np.array_equal(_bits(got), _bits(want)), (l, which, key, k)
+
+
+def _linearize_case(W, H, seed):
+    d = synth.configs.frame_pair(seed=seed, width=W, height=H)
+    rng = np.random.default_rng(seed)
+    x0 = lie.state_boxplus(d["x0"], np.r_[rng.normal(size=6) * 1e-3, np.zeros(9)])
+    x1 = lie.state_boxplus(d["gt1"], np.r_[rng.normal(size=6) * 2e-3, np.zeros(9)])
+    T_WM = np.eye(4)
+    T_WM[:3, :3] = lie.exp_so3(rng.normal(size=3) * 1e-3)
+    T_WM[:3, 3] = rng.normal(size=3) * 1e-3
+    return d, x0, x1, T_WM
+
+
+COS20 = float(np.cos(np.deg2rad(20.0)))
+
+
+@pytest.mark.parametrize("W,H,levels,seed,icp_cos", [(160, 120, 2, 1001, None), (160, 120, 2, 1001, COS20),
+                                                     (200, 152, 3, 7, None), (640, 480, 3, 1002, None),
+                                                     (640, 480, 3, 1002, COS20)])
+def test_linearize_masks_and_systems(W, H, levels, seed, icp_cos):
+    import torch
+    d, x0, x1, T_WM = _linearize_case(W, H, seed)
+    cam = d["camera"]
+    params = track.default_params(levels=levels, iters=[1] * levels, mode="rgbdi")
+    params["icp_cos"] = icp_cos
+    cur, ref = track.build_pyramids(d["depth"].numpy(), d["intensity"].numpy(), d["model_depth"].numpy(),
+                                    d["model_intensity"].numpy(), cam, levels)
+    Ra, ta, Rb, tb = track.fp32_transforms(T_WM, x0, x1)
+    print(f"linearize {W}x{H} seed {seed} cos {icp_cos}", flush=True)
+    with session(W, H, levels, [1] * levels, icp_cos=icp_cos) as s:
+        s.set_model(cuda(d["model_depth"].numpy()), cuda(d["model_intensity"].numpy()), T_WM)
+        s.build_pyramid(P.PYR_CURRENT, cuda(d["depth"].numpy()), cuda(d["intensity"].numpy()))
+        for l in range(levels):
+            vis = track.linearise_visual(cur[l], ref[l], T_WM, x0, x1, Ra, ta, Rb, tb, params)
+            mask = torch.zeros((H >> l, W >> l), dtype=torch.uint8, device="cuda")
+            g = s.linearize(l, Ra, ta, Rb, tb, x0, x1, mask=mask)
+            m = mask.cpu().numpy()
+            assert np.array_equal((m & 1) != 0, vis["mask_icp"]), l
+            assert np.array_equal((m & 2) != 0, vis["mask_rgb"]), l
+            assert g["n_icp"] == vis["n_icp"] and g["n_rgb"] == vis["n_rgb"]
+            assert vis["n_icp"] > (0.05 if icp_cos else 0.2) * m.size and vis["n_rgb"] > 0.5 * m.size
+            for term, cols in (("icp", np.r_[6:12]), ("rgb", np.r_[0:12])):
+                assert rel_fro(g["H_" + term], vis["H_" + term]) < 1e-5, (l, term)
+                scale = jtr_scale(vis[term], cols, 12)
+                assert np.linalg.norm(g["b_" + term] - vis["b_" + term]) < 1e-5 * scale, (l, term)
+                assert abs(g["cost_" + term] - vis["cost_" + term]) < 1e-5 * vis["cost_" + term]
+
+
+def _track_pair(mode, seed=1001, W=160, H=120, levels=2, iters=(4, 4)):
+    d = synth.configs.frame_pair(seed=seed, width=W, height=H)
+    params = track.default_params(levels=levels, iters=iters, mode=mode)
+    o = track.track_frame(d["depth"].numpy(), d["intensity"].numpy(), d["model_depth"].numpy(),
+                          d["model_intensity"].numpy(), d["T_WM"], d["camera"], d["imu"], d["t0"], d["t1"], d["x0"],
+                          d["q_IW"], d["prior"], params, record=True)
+    prior = d["prior"] if mode != "rgbd" else None
+    with session(W, H, levels, list(iters), mode=mode, x0=d["x0"], q_IW=d["q_IW"], prior=prior) as s:
+        s.set_model(cuda(d["model_depth"].numpy()), cuda(d["model_intensity"].numpy()), d["T_WM"])
+        s.track_frame(cuda(d["depth"].numpy()), cuda(d["intensity"].numpy()), d["imu"], d["t0"], d["t1"])
+        g = s.result()
+    return d, o, g
+
+
+@pytest.mark.parametrize("mode", ["rgbdi", "rgbd"])
+def test_track_frame_pair_matches_oracle(mode):
+    print(f"track pair {mode}", flush=True)
+    d, o, g = _track_pair(mode)
+    assert g["status"] == 0 and o["status"] == "ok"
+    dr, da = pose_err(g["x1"], o["x1"])
+    assert dr < 1e-6 and da < 1e-6, (dr, da)
+    last = o["log"][-1]
+    assert g["n_icp"][0] == last["n_icp"] and g["n_rgb"][0] == last["n_rgb"]
+    if mode == "rgbdi":
+        dr0, da0 = pose_err(g["x0"], o["x0"])
+        assert dr0 < 1e-6 and da0 < 1e-6
+        assert np.linalg.norm(lie.quat_boxminus(g["q_IW"], o["q_IW"])) < 1e-6
+        assert np.abs(g["x1"]["v"] - o["x1"]["v"]).max() < 1e-5
+        assert np.abs(g["x1"]["bg"] - o["x1"]["bg"]).max() < 1e-5
+        assert np.abs(g["x1"]["ba"] - o["x1"]["ba"]).max() < 1e-4
+        Hg, Ho = g["prior"]["H"], o["prior"]["H"]
+        assert rel_fro(Hg, Ho) < 1e-4
+
+
+def test_track_frame_full_resolution_pair():
+    """640x480, three levels (10/5/4 iterations): final pose against the oracle."""
+    print("track pair 640x480", flush=True)
+    d, o, g = _track_pair("rgbdi", seed=1002, W=640, H=480, levels=3, iters=(10, 5, 4))
+    assert g["status"] == 0
+    dr, da = pose_err(g["x1"], o["x1"])
+    assert dr < 1e-6 and da < 1e-6, (dr, da)
+
+
+def test_result_is_deterministic_and_checkpoint_restores():
+    d = synth.configs.frame_pair()
+    with session(160, 120, 2, [4, 4], x0=d["x0"], q_IW=d["q_IW"], prior=d["prior"]) as s:
+        s.set_model(cuda(d["model_depth"].numpy()), cuda(d["model_intensity"].numpy()), d["T_WM"])
+        x0, q, pr, fi = s.get_state()
+        runs = []
+        for _ in range(2):
+            s.set_state(x0, q, pr, fi)
+            s.track_frame(cuda(d["depth"].numpy()), cuda(d["intensity"].numpy()), d["imu"], d["t0"], d["t1"])
+            runs.append(s.result())
+        for k in ("r", "q", "v", "bg", "ba"):
+            assert np.array_equal(runs[0]["x1"][k], runs[1]["x1"][k])
+        assert np.array_equal(runs[0]["prior"]["H"], runs[1]["prior"]["H"])
+        assert runs[1]["frame_index"] == fi + 1
+
+
+def test_error_paths():
+    d = synth.configs.frame_pair()
+    with session(160, 120, 2, [2, 2], x0=d["x0"], q_IW=d["q_IW"], prior=d["prior"]) as s:
+        with pytest.raises(P.DslamError) as ei:  # no model view yet
+            s.track_frame(cuda(d["depth"].numpy()), cuda(d["intensity"].numpy()), d["imu"], d["t0"], d["t1"])
+        assert ei.value.code == P._abi.ERR_NOT_READY
+        s.set_model(cuda(d["model_depth"].numpy()), cuda(d["model_intensity"].numpy()), d["T_WM"])
+        bad = dict(d["imu"])
+        bad["t"] = d["imu"]["t"][::-1].copy()
+        with pytest.raises(P.DslamError) as ei:
+            s.track_frame(cuda(d["depth"].numpy()), cuda(d["intensity"].numpy()), bad, d["t0"], d["t1"])
+        assert ei.value.code == P._abi.ERR_INVALID
+    with session(160, 120, 2, [2, 2], mode="rgbd") as s:
+        s.set_model(cuda(d["model_depth"].numpy()), cuda(d["model_intensity"].numpy()), d["T_WM"])
+        z = np.zeros((120, 160), np.float32)
+        s.track_frame(cuda(z), cuda(d["intensity"].numpy()))
+        assert s.result()["status"] == P._abi.ERR_SINGULAR
+    with pytest.raises(P.DslamError):  # width not divisible by 2^(levels-1)
+        with session(162, 120, 3, [1, 1, 1], mode="rgbd"):
+            pass
