@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "tracked frames/s + residual-pass GB/s at 640x480; p50/p99 track latency"
 HBM_PEAK_GBS = 8000.0
-REF_BYTES_PER_PIXEL = 64  # V1 12 + N1 12 + I1 4 + V0 12 + N0 12 + I0 4 + G0 8 per pixel-iteration
+REF_BYTES_PER_PIXEL = 52  # V1 12 + I1 4 + V0 12 + N0 12 + I0 4 + G0 8 per pixel-iteration (N1 unread: no normal gate)
 
 
 def log(msg):
@@ -109,7 +109,7 @@ def run_gpu(args):
     k_ms = e0.elapsed_time(e1) / reps
     px = W * H
     achieved = REF_BYTES_PER_PIXEL * px / (k_ms * 1e-3) / 1e9
-    log(f"[bench] level-0 residual pass: {k_ms * 1e3:.2f} us/launch, {achieved:.1f} GB/s (64 B/px algorithmic)")
+    log(f"[bench] level-0 residual pass: {k_ms * 1e3:.2f} us/launch, {achieved:.1f} GB/s ({REF_BYTES_PER_PIXEL} B/px algorithmic)")
     sess.close()
     ctx.close()
     return {

@@ -241,8 +241,10 @@ dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const u
 dslam_status dslam_session_result(dslam_session* s, dslam_track_result* out);
 
 /* One residual pass at `level` with caller-chosen float32 transforms:
- * Ra, ta map current-camera points into the model-view camera (ICP
- * association) and Rb, tb into the reference camera of x0 (photometric warp);
+ * (Ra, ta) map current-camera points into the model-view camera (ICP
+ * association) and (Rb, tb) into the reference camera of x0 (photometric
+ * warp), each rotation given as its offset from the identity, R - I,
+ * rounded to float32 from float64 (a point maps as p + ((R - I) p + t));
  * x0, x1 (host) give the float64 poses used to lift the sums to the world
  * frame.  If mask_dev (device, width_l x height_l bytes) is not NULL, each
  * pixel gets bit 0 = ICP inlier, bit 1 = photometric inlier.  Synchronous. */

@@ -19,9 +19,13 @@ Readings taken here:
   rounding, and accept when q'.z > 0 and 1 <= u' < W-2, 1 <= v' < H-2, so
   that every bilinear tap has a central-difference gradient.
 
-Inputs are the float32 transforms (row-major 3x3 and 3-vector) the caller
-supplies.  Every operation is a single float32 operation with no contraction:
-a matrix-vector product is ((R00 x + R01 y) + R02 z) + t0, the projection is
+Inputs are float32 transforms given as D = R - I (row-major 3x3, the
+rotation's offset from the identity, rounded once to float32 from its float64
+value) and t.  Keeping the offset instead of R makes the rounding of the
+transform about as small as the rotation angle times one ulp, which matters
+because every pixel sees the same rounding.  Every operation is a single
+float32 operation with no contraction: a point maps as
+q_x = x + (((D00 x + D01 y) + D02 z) + t0) (likewise y, z), the projection is
 inv = 1/z; u = ((fx x) inv) + cx.
 """
 from __future__ import annotations
@@ -32,21 +36,19 @@ F = np.float32
 DIST_THRESHOLD = 0.10              # metres
 
 
-def _xform(R, t, x, y, z):
-    R = np.asarray(R, dtype=np.float32).reshape(3, 3)
+def _xform(D, t, x, y, z):
+    """q = p + (D p + t), D = R - I, all float32."""
+    D = np.asarray(D, dtype=np.float32).reshape(3, 3)
     t = np.asarray(t, dtype=np.float32).reshape(3)
-    out = []
-    for r in range(3):
-        v = ((R[r, 0] * x + R[r, 1] * y) + R[r, 2] * z)
-        if t is not None:
-            v = v + t[r]
-        out.append(v.astype(np.float32))
-    return out
+    p = (x, y, z)
+    return [(p[r] + (((D[r, 0] * x + D[r, 1] * y) + D[r, 2] * z) + t[r])).astype(np.float32) for r in range(3)]
 
 
-def _rotate(R, x, y, z):
-    R = np.asarray(R, dtype=np.float32).reshape(3, 3)
-    return [((R[r, 0] * x + R[r, 1] * y) + R[r, 2] * z).astype(np.float32) for r in range(3)]
+def _rotate(D, x, y, z):
+    """n' = n + D n."""
+    D = np.asarray(D, dtype=np.float32).reshape(3, 3)
+    p = (x, y, z)
+    return [(p[r] + ((D[r, 0] * x + D[r, 1] * y) + D[r, 2] * z)).astype(np.float32) for r in range(3)]
 
 
 def _project(qx, qy, qz, K):
@@ -58,7 +60,7 @@ def _project(qx, qy, qz, K):
     return u, v
 
 
-def icp_association(cur: dict, ref: dict, Ra, ta, dist=DIST_THRESHOLD, cos_min=None):
+def icp_association(cur: dict, ref: dict, Da, ta, dist=DIST_THRESHOLD, cos_min=None):
     """Returns (valid mask, ui, vi) over the current level's pixels.
 
     dist: association distance gate (m); the squared gate is dist^2 rounded to
@@ -67,7 +69,7 @@ def icp_association(cur: dict, ref: dict, Ra, ta, dist=DIST_THRESHOLD, cos_min=N
     V0, N0, D0 = ref["V"], ref["N"], ref["D"]
     H0, W0 = D0.shape
     x, y, z = V1[..., 0], V1[..., 1], V1[..., 2]
-    qx, qy, qz = _xform(Ra, ta, x, y, z)
+    qx, qy, qz = _xform(Da, ta, x, y, z)
     u, v = _project(qx, qy, qz, ref["K"])
     ui = np.rint(u).astype(np.float32)
     vi = np.rint(v).astype(np.float32)
@@ -87,18 +89,18 @@ def icp_association(cur: dict, ref: dict, Ra, ta, dist=DIST_THRESHOLD, cos_min=N
     ok = ok & (d0 > F(0)) & n0_ok & (dist2 <= F(dist * dist))
     if cos_min is not None:
         n1_ok = (N1[..., 0] != 0) | (N1[..., 1] != 0) | (N1[..., 2] != 0)
-        nx, ny, nz = _rotate(Ra, N1[..., 0], N1[..., 1], N1[..., 2])
+        nx, ny, nz = _rotate(Da, N1[..., 0], N1[..., 1], N1[..., 2])
         cosang = ((nx * n0[..., 0] + ny * n0[..., 1]) + nz * n0[..., 2]).astype(np.float32)
         ok = ok & n1_ok & (cosang >= F(cos_min))
     return ok, iu, iv
 
 
-def rgb_validity(cur: dict, ref: dict, Rb, tb):
+def rgb_validity(cur: dict, ref: dict, Db, tb):
     """Returns (valid mask, u', v') with u', v' the float32 warped coordinates."""
     V1, D1 = cur["V"], cur["D"]
     H0, W0 = ref["D"].shape
     x, y, z = V1[..., 0], V1[..., 1], V1[..., 2]
-    qx, qy, qz = _xform(Rb, tb, x, y, z)
+    qx, qy, qz = _xform(Db, tb, x, y, z)
     u, v = _project(qx, qy, qz, ref["K"])
     with np.errstate(invalid="ignore"):
         inside = (u >= F(1)) & (u < F(W0 - 2)) & (v >= F(1)) & (v < F(H0 - 2))

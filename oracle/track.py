@@ -13,7 +13,8 @@ Readings taken where the paper is silent:
 * the IMU and prior terms are added at every iteration of every level;
 * a fixed number of iterations per level, no damping, no early exit;
 * the float32 transforms that drive association are the float64 compositions
-  T_WM^-1 T_WC1 (ICP) and T_WC0^-1 T_WC1 (photometric) rounded once to float32.
+  T_WM^-1 T_WC1 (ICP) and T_WC0^-1 T_WC1 (photometric), their rotations kept
+  as R - I, rounded once to float32.
 """
 from __future__ import annotations
 
@@ -36,7 +37,8 @@ def default_params(levels=3, iters=(10, 5, 4), mode="rgbdi"):
 
 
 def fp32_transforms(T_WM, x0, x1):
-    """(R_a, t_a) = T_WM^-1 T_WC1 and (R_b, t_b) = T_WC0^-1 T_WC1, rounded to float32."""
+    """(R_a - I, t_a) of T_WM^-1 T_WC1 and (R_b - I, t_b) of T_WC0^-1 T_WC1,
+    formed in float64 and rounded once to float32."""
     R_WM, t_WM = T_WM[:3, :3], T_WM[:3, 3]
     R0, R1 = quat_to_rot(x0["q"]), quat_to_rot(x1["q"])
     Ra = R_WM.T @ R1
@@ -44,7 +46,7 @@ def fp32_transforms(T_WM, x0, x1):
     Rb = R0.T @ R1
     tb = R0.T @ (x1["r"] - x0["r"])
     f = np.float32
-    return Ra.astype(f), ta.astype(f), Rb.astype(f), tb.astype(f)
+    return (Ra - np.eye(3)).astype(f), ta.astype(f), (Rb - np.eye(3)).astype(f), tb.astype(f)
 
 
 def linearise_visual(cur, ref, T_WM, x0, x1, Ra, ta, Rb, tb, params):

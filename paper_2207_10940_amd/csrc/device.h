@@ -24,7 +24,7 @@ struct SessionDev {
   double qIW[4];
   dslam_prior prior;
   dslam_preint pre;
-  float xf[24];        // Ra(9) ta(3) Rb(9) tb(3) for the next residual pass
+  float xf[24];        // Ra-I (9) ta (3) Rb-I (9) tb (3) for the next residual pass
   double sys[58];      // reduced sums of the last residual pass
   dslam_track_result result;
   int32_t status;      // first error of the current frame
@@ -39,7 +39,7 @@ struct ResidualArgs {
   int W, H, npix;
   float fx, fy, cx, cy;
   float dist2, cosmin, depth_k, sigma_I, huber_k;
-  const float* xf;   // device, 24 floats
+  const float* xf;   // device, 24 floats: Ra-I, ta, Rb-I, tb
   float* partials;   // device, [gridDim.x][64]
   uint8_t* mask;     // device, optional
 };

@@ -136,9 +136,10 @@ __device__ __forceinline__ void pixel(const ResidualArgs& a, const float* T, int
   uint8_t bits = 0;
   if (z > 0.0f) {
     // ---- ICP: projective association in the model-view camera (mask layer)
-    float qx = ((T[0] * x + T[1] * y) + T[2] * z) + T[9];
-    float qy = ((T[3] * x + T[4] * y) + T[5] * z) + T[10];
-    float qz = ((T[6] * x + T[7] * y) + T[8] * z) + T[11];
+    // transforms arrive as D = R - I: q = p + (D p + t)
+    float qx = x + (((T[0] * x + T[1] * y) + T[2] * z) + T[9]);
+    float qy = y + (((T[3] * x + T[4] * y) + T[5] * z) + T[10]);
+    float qz = z + (((T[6] * x + T[7] * y) + T[8] * z) + T[11]);
     if (qz > 0.0f) {
       float inv = 1.0f / qz;
       float u = ((a.fx * qx) * inv) + a.cx;
@@ -155,9 +156,9 @@ __device__ __forceinline__ void pixel(const ResidualArgs& a, const float* T, int
         if (a.cosmin >= -1.0f) {  // optional normal-compatibility gate
           float n1x = a.cN0[p], n1y = a.cN1[p], n1z = a.cN2[p];
           bool n1ok = (n1x != 0.0f) | (n1y != 0.0f) | (n1z != 0.0f);
-          float nrx = (T[0] * n1x + T[1] * n1y) + T[2] * n1z;
-          float nry = (T[3] * n1x + T[4] * n1y) + T[5] * n1z;
-          float nrz = (T[6] * n1x + T[7] * n1y) + T[8] * n1z;
+          float nrx = n1x + ((T[0] * n1x + T[1] * n1y) + T[2] * n1z);
+          float nry = n1y + ((T[3] * n1x + T[4] * n1y) + T[5] * n1z);
+          float nrz = n1z + ((T[6] * n1x + T[7] * n1y) + T[8] * n1z);
           float cosang = (nrx * n0x + nry * n0y) + nrz * n0z;
           ok = ok && n1ok && cosang >= a.cosmin;
         }
@@ -175,9 +176,9 @@ __device__ __forceinline__ void pixel(const ResidualArgs& a, const float* T, int
       }
     }
     // ---- photometric: warp into the reference camera (mask layer)
-    float rx = ((T[12] * x + T[13] * y) + T[14] * z) + T[21];
-    float ry = ((T[15] * x + T[16] * y) + T[17] * z) + T[22];
-    float rz = ((T[18] * x + T[19] * y) + T[20] * z) + T[23];
+    float rx = x + (((T[12] * x + T[13] * y) + T[14] * z) + T[21]);
+    float ry = y + (((T[15] * x + T[16] * y) + T[17] * z) + T[22]);
+    float rz = z + (((T[18] * x + T[19] * y) + T[20] * z) + T[23]);
     if (rz > 0.0f) {
       float inv = 1.0f / rz;
       float u = ((a.fx * rx) * inv) + a.cx;

@@ -108,7 +108,8 @@ DX void chol_solve_cols(Par par, const double* Lm, int n, int ld, double* X, int
 }
 
 // Float32 transforms for the next residual pass: (R_a, t_a) = T_WM^-1 T_WC1
-// and (R_b, t_b) = T_WC0^-1 T_WC1, each entry rounded once to float32.
+// and (R_b, t_b) = T_WC0^-1 T_WC1, rotations stored as R - I, each entry
+// formed in float64 and rounded once to float32.
 DX void next_transforms(const dslam_frame_state& x0, const dslam_frame_state& x1, const double* R_WM,
                         const double* t_WM, float* xf) {
   M3 RWM = load33(R_WM);
@@ -118,8 +119,9 @@ DX void next_transforms(const dslam_frame_state& x0, const dslam_frame_state& x1
   M3 Rb = tr(R0) * R1;
   V3 tb = tr(R0) * (load3(x1.r) - load3(x0.r));
   for (int i = 0; i < 9; ++i) {
-    xf[i] = (float)Ra.m[i];
-    xf[12 + i] = (float)Rb.m[i];
+    double id = (i % 4 == 0) ? 1.0 : 0.0;
+    xf[i] = (float)(Ra.m[i] - id);
+    xf[12 + i] = (float)(Rb.m[i] - id);
   }
   for (int i = 0; i < 3; ++i) {
     xf[9 + i] = (float)ta[i];

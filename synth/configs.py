@@ -85,8 +85,8 @@ def add_depth_noise(z: torch.Tensor, k: float, generator: torch.Generator) -> to
 def imu_window(stamps: np.ndarray, t0: float, t1: float):
     """Indices of the samples whose hold intervals meet [t0, t1): the last
     sample stamped at or before t0 through the last stamped before t1."""
-    first = int(np.searchsorted(stamps, t0 + 1e-12, side="right")) - 1
-    last = int(np.searchsorted(stamps, t1 - 1e-12, side="left"))
+    first = int(np.searchsorted(stamps, t0, side="right")) - 1
+    last = int(np.searchsorted(stamps, t1, side="left"))
     return max(first, 0), last
 
 

@@ -22,6 +22,8 @@ def session(W, H, levels, iters, mode="rgbdi", x0=None, q_IW=None, prior=None, b
         x0 = {"r": np.zeros(3), "q": np.array([1.0, 0, 0, 0]), "v": np.zeros(3), "bg": np.zeros(3), "ba": np.zeros(3)}
     if q_IW is None:
         q_IW = np.array([1.0, 0, 0, 0])
+    if prior is None and mode != "rgbd":
+        prior = synth.configs.initial_prior(x0, q_IW)
     s = P.Session(ctx, cam, tp, P.imu_params(), x0, q_IW, prior)
     try:
         yield s

@@ -86,10 +86,15 @@ def test_linearize_masks_and_systems(W, H, levels, seed, icp_cos):
             assert g["n_icp"] == vis["n_icp"] and g["n_rgb"] == vis["n_rgb"]
             assert vis["n_icp"] > (0.05 if icp_cos else 0.2) * m.size and vis["n_rgb"] > 0.5 * m.size
             for term, cols in (("icp", np.r_[6:12]), ("rgb", np.r_[0:12])):
-                assert rel_fro(g["H_" + term], vis["H_" + term]) < 1e-5, (l, term)
+                eH = rel_fro(g["H_" + term], vis["H_" + term])
                 scale = jtr_scale(vis[term], cols, 12)
-                assert np.linalg.norm(g["b_" + term] - vis["b_" + term]) < 1e-5 * scale, (l, term)
-                assert abs(g["cost_" + term] - vis["cost_" + term]) < 1e-5 * vis["cost_" + term]
+                eb = np.linalg.norm(g["b_" + term] - vis["b_" + term]) / scale
+                ec = abs(g["cost_" + term] - vis["cost_" + term]) / vis["cost_" + term]
+                print(f"  level {l} {term}: n {g['n_' + term]}  JtJ {eH:.2e}  Jtr {eb:.2e}  cost {ec:.2e}", flush=True)
+                assert eH < 1e-5 and eb < 1e-5, (l, term, eH, eb)
+                # the photometric residual cancels to a few grey levels out of ~100-255,
+                # so float32 rounding of the interpolated I0 alone is ~1e-5 of e
+                assert ec < 1e-4, (l, term, ec)
 
 
 def _track_pair(mode, seed=1001, W=160, H=120, levels=2, iters=(4, 4)):
@@ -126,13 +131,29 @@ def test_track_frame_pair_matches_oracle(mode):
         assert rel_fro(Hg, Ho) < 1e-4
 
 
-def test_track_frame_full_resolution_pair():
-    """640x480, three levels (10/5/4 iterations): final pose against the oracle."""
-    print("track pair 640x480", flush=True)
-    d, o, g = _track_pair("rgbdi", seed=1002, W=640, H=480, levels=3, iters=(10, 5, 4))
-    assert g["status"] == 0
-    dr, da = pose_err(g["x1"], o["x1"])
-    assert dr < 1e-6 and da < 1e-6, (dr, da)
+def test_track_sequence_full_resolution():
+    """The benchmark's workload: 640x480 frames of the spline sequence tracked
+    by one session against a noise-free model view (3 levels, 10/5/4
+    iterations), the oracle chained over the same frames.  Final pose of every
+    frame within 1e-6 m / 1e-6 rad."""
+    import bench
+    seq = synth.configs.sequence(n_frames=4, width=640, height=480)
+    params = track.default_params(levels=3, iters=(10, 5, 4), mode="rgbdi")
+    x0, q, prior = seq["x0"], seq["q_IW"], seq["prior"]
+    with session(640, 480, 3, [10, 5, 4], x0=x0, q_IW=q, prior=prior) as s:
+        for j in range(1, 4):
+            md, mi, T, d, i, imu, t0, t1 = bench.frame_inputs(seq, j)
+            s.set_model(cuda(md.numpy()), cuda(mi.numpy()), T)
+            s.track_frame(cuda(d.numpy()), cuda(i.numpy()), imu, t0, t1)
+            g = s.result()
+            o = track.track_frame(d.numpy(), i.numpy(), md.numpy(), mi.numpy(), T, seq["camera"], imu, t0, t1, x0,
+                                  q, prior, params)
+            x0, q, prior = o["x1"], o["q_IW"], o["prior"]
+            dr, da = pose_err(g["x1"], o["x1"])
+            print(f"frame {j}: |dr| {dr:.2e} m |da| {da:.2e} rad  icp {g['n_icp'][0]} rgb {g['n_rgb'][0]}",
+                  flush=True)
+            assert g["status"] == 0 and o["status"] == "ok"
+            assert dr < 1e-6 and da < 1e-6, (j, dr, da)
 
 
 def test_result_is_deterministic_and_checkpoint_restores():

@@ -33,8 +33,8 @@ def test_association_brute_force_8x6():
     z0, i0, z1, i1, R1, t1 = _frames_8x6()
     cur = pyr.build(z1, i1, 6.5, 6.5, 4.0, 3.0, 1)[0]
     ref = pyr.build(z0, i0, 6.5, 6.5, 4.0, 3.0, 1, with_gradient=True)[0]
-    Ra, ta = R1.astype(np.float32), t1.astype(np.float32)
-    ok, iu, iv = assoc.icp_association(cur, ref, Ra, ta)
+    Da, ta = (R1 - np.eye(3)).astype(np.float32), t1.astype(np.float32)
+    ok, iu, iv = assoc.icp_association(cur, ref, Da, ta)
     cells = np.stack(np.meshgrid(np.arange(8), np.arange(6)), -1).reshape(-1, 2).astype(np.float64)
     checked = 0
     for j in range(6):
@@ -66,7 +66,7 @@ def test_identical_frames_at_identity():
     cur, ref = track.build_pyramids(d["z0"], d["I0"], d["z0"], d["I0"], cam, 1)
     x = identity_state()
     Ra, ta, Rb, tb = track.fp32_transforms(np.eye(4), x, x)
-    assert np.array_equal(Ra, np.eye(3, dtype=np.float32)) and not np.any(ta)
+    assert not np.any(Ra) and not np.any(ta)  # R - I = 0 at identity
     p = _params()
     icp = res.icp_terms(cur[0], ref[0], np.eye(4), x, Ra, ta, p)
     ok, iu, iv = assoc.icp_association(cur[0], ref[0], Ra, ta)
