@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--latency-frames", type=int, default=100)
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--cpu-frames", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

@@ -40,10 +40,10 @@ struct ResidualArgs {
   float fx, fy, cx, cy;
   float dist2, cosmin, depth_k, sigma_I, huber_k;
   const float* xf;   // device, 24 floats: Ra-I, ta, Rb-I, tb
-  float* partials;   // device, [gridDim.x][64]
+  float* partials;   // device, [gridDim.x][64] block sums
   uint8_t* mask;     // device, optional
 };
 
-enum { RES_THREADS = 256, PARTIAL_STRIDE = 64 };
+enum { RES_THREADS = 256, PARTIAL_STRIDE = 64, SOLVE_THREADS = 256 };
 
 }  // namespace dslam

@@ -160,7 +160,7 @@ ImuParamsD imu_params_d(const dslam_imu_params& ip) {
 
 int default_ppt(int npix) { return npix >= 600000 ? 4 : (npix >= 150000 ? 2 : 1); }
 
-ResidualArgs residual_args(dslam_session* s, int l, const float* xf, float* partials, uint8_t* mask) {
+ResidualArgs residual_args(dslam_session* s, int l, const float* xf, uint8_t* mask) {
   const LevelPtrs& c = s->cur[l];
   const LevelPtrs& m = s->model[l];
   ResidualArgs a;
@@ -178,7 +178,7 @@ ResidualArgs residual_args(dslam_session* s, int l, const float* xf, float* part
   a.sigma_I = (float)s->tp.sigma_I;
   a.huber_k = (float)s->tp.huber_k;
   a.xf = xf;
-  a.partials = partials;
+  a.partials = s->partials;
   a.mask = mask;
   return a;
 }
@@ -299,7 +299,7 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   init.x1 = *x0;
   for (int i = 0; i < 4; ++i) init.qIW[i] = q_IW[i];
   if (prior) init.prior = *prior;
-  if (hipMemset(s->arena, 0, lo.planes) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
+  if (hipMemset(s->arena, 0, lo.total) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
   if (hipMemcpy(s->sd, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
   if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
   *out = s;
@@ -431,7 +431,7 @@ dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const u
   for (int l = s->levels - 1; l >= 0; --l)
     if (s->tp.iters[l] > 0) last_level = l;
   for (int l = s->levels - 1; l >= 0; --l) {
-    ResidualArgs ra = residual_args(s, l, s->sd->xf, s->partials, nullptr);
+    ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
     int nb = residual_blocks(ra.npix, s->ppt[l]);
     for (int it = 0; it < s->tp.iters[l]; ++it) {
       HIP_OK(launch_residual(ra, s->ppt[l], st));
@@ -468,10 +468,9 @@ dslam_status dslam_linearize(dslam_session* s, int32_t level, const float Ra[9],
   for (int i = 0; i < 9; ++i) { xf[i] = Ra[i]; xf[12 + i] = Rb[i]; }
   for (int i = 0; i < 3; ++i) { xf[9 + i] = ta[i]; xf[21 + i] = tb[i]; }
   HIP_OK(hipMemcpyAsync(s->xf_scratch, xf, sizeof(xf), hipMemcpyHostToDevice, st));
-  ResidualArgs ra = residual_args(s, level, s->xf_scratch, s->partials, mask_dev);
-  int nb = residual_blocks(ra.npix, s->ppt[level]);
+  ResidualArgs ra = residual_args(s, level, s->xf_scratch, mask_dev);
   HIP_OK(launch_residual(ra, s->ppt[level], st));
-  HIP_OK(launch_reduce(s->partials, nb, s->red_out, st));
+  HIP_OK(launch_reduce(s->partials, residual_blocks(ra.npix, s->ppt[level]), s->red_out, st));
   double raw[64];
   HIP_OK(hipMemcpyAsync(raw, s->red_out, 58 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
@@ -493,7 +492,7 @@ dslam_status dslam_profile_residual(dslam_session* s, int32_t level, int32_t rep
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  ResidualArgs ra = residual_args(s, level, s->sd->xf, s->partials, nullptr);
+  ResidualArgs ra = residual_args(s, level, s->sd->xf, nullptr);
   for (int r = 0; r < reps; ++r) HIP_OK(launch_residual(ra, s->ppt[level], st));
   return DSLAM_OK;
 }

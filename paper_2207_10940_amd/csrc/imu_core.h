@@ -75,8 +75,17 @@ DX void gamma_apply(V3 phi, V3 a, double k0, double ca, double cb, double da, do
 }
 
 // Working storage for the preintegration (LDS on the device).
+struct PreintStep {
+  M3 E, Jr, G1, G2, D1, D2;  // Exp(phi), right Jacobian, G1, G2 and d(Gk a)/dphi
+  V3 g1a, g2a;               // G1 a, G2 a
+  M3 dR;                     // dR at the start of the step
+  double dt;
+};
 struct PreintWork {
-  double A[81], B[54], T[81], TB[54];
+  PreintStep st[DSLAM_MAX_IMU_SAMPLES];
+  double A[DSLAM_MAX_IMU_SAMPLES][81];
+  double B[DSLAM_MAX_IMU_SAMPLES][54];
+  double T[81], TB[54];
   double dR[9], dv[3], dp[3];
   int nsub;
   int ksub[DSLAM_MAX_IMU_SAMPLES];
@@ -103,103 +112,119 @@ DX int imu_subintervals(const dslam_imu_sample* s, int n, double t0, double t1, 
   return m > 0 ? DSLAM_OK : DSLAM_ERR_INVALID;
 }
 
-// Preintegration over [t0, t1) at biases (bg, ba).  Runs on the lanes of `par`;
-// `out` and `w` are visible to all lanes.  Returns DSLAM_OK / DSLAM_ERR_INVALID.
+// Preintegration over [t0, t1) at biases (bg, ba).  Runs on the lanes of `par`
+// (one lane per sub-interval for the step quantities, then the covariance and
+// bias-Jacobian recursions split over matrix entries); `out` and `w` are
+// visible to all lanes.  Returns DSLAM_OK / DSLAM_ERR_INVALID.
 DX int preintegrate(Par par, const dslam_imu_sample* s, int n, double t0, double t1, const double* bg,
                     const double* ba, double sigma_g, double sigma_a, PreintWork* w, dslam_preint* out) {
   SERIAL {
-    w->nsub = -1;
     int st = imu_subintervals(s, n, t0, t1, w);
     if (st != DSLAM_OK) w->nsub = -1;
-    for (int i = 0; i < 9; ++i) w->dR[i] = (i % 4 == 0) ? 1.0 : 0.0;
-    for (int i = 0; i < 3; ++i) { w->dv[i] = 0.0; w->dp[i] = 0.0; }
   }
   PFOR(i, 81) out->Sigma[i] = 0.0;
   PFOR(i, 54) out->J[i] = 0.0;
   DSLAM_SYNC();
-  int nsub = w->nsub;
+  const int nsub = w->nsub;
   if (nsub < 0) return DSLAM_ERR_INVALID;
-  for (int m = 0; m < nsub; ++m) {
+  // per-step quantities, independent across steps
+  PFOR(m, nsub) {
     const dslam_imu_sample& smp = s[w->ksub[m]];
     double dt = w->dtsub[m];
-    SERIAL {
-      V3 wv = v3(smp.gyro[0] - bg[0], smp.gyro[1] - bg[1], smp.gyro[2] - bg[2]);
-      V3 av = v3(smp.acc[0] - ba[0], smp.acc[1] - ba[1], smp.acc[2] - ba[2]);
-      V3 phi = dt * wv;
-      double c[3], d[3];
-      gamma_coeffs(norm(phi), c, d);
-      V3 g1a, g2a;
-      M3 D1, D2;
-      gamma_apply(phi, av, 1.0, c[0], c[1], d[0], d[1], &g1a, &D1);
-      gamma_apply(phi, av, 0.5, c[1], c[2], d[1], d[2], &g2a, &D2);
-      M3 K = hat(phi);
-      M3 G1 = eye3() + c[0] * K + c[1] * (K * K);
-      M3 G2 = 0.5 * eye3() + c[1] * K + c[2] * (K * K);
-      M3 dR = load33(w->dR);
-      M3 E = Exp(phi);
-      // step Jacobian w.r.t. the incoming error state [dphi, dv, dp]
-      for (int i = 0; i < 81; ++i) w->A[i] = (i % 10 == 0) ? 1.0 : 0.0;
-      M3 Et = tr(E);
-      M3 Av_phi = (-dt) * (dR * hat(g1a));
-      M3 Ap_phi = (-dt * dt) * (dR * hat(g2a));
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          w->A[9 * i + j] = Et(i, j);
-          w->A[9 * (3 + i) + j] = Av_phi(i, j);
-          w->A[9 * (6 + i) + j] = Ap_phi(i, j);
-        }
-      for (int i = 0; i < 3; ++i) w->A[9 * (6 + i) + 3 + i] = dt;
-      // step Jacobian w.r.t. the biases [bg, ba] (the noise enters with the opposite sign)
-      M3 Bphi_g = (-dt) * Jr(phi);
-      M3 Bv_g = (-dt * dt) * (dR * D1);
-      M3 Bp_g = (-dt * dt * dt) * (dR * D2);
-      M3 Bv_a = (-dt) * (dR * G1);
-      M3 Bp_a = (-dt * dt) * (dR * G2);
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          w->B[6 * i + j] = Bphi_g(i, j);
-          w->B[6 * i + 3 + j] = 0.0;
-          w->B[6 * (3 + i) + j] = Bv_g(i, j);
-          w->B[6 * (3 + i) + 3 + j] = Bv_a(i, j);
-          w->B[6 * (6 + i) + j] = Bp_g(i, j);
-          w->B[6 * (6 + i) + 3 + j] = Bp_a(i, j);
-        }
-      // state update (uses the old dR, dv)
-      V3 dRg2a = dR * g2a, dRg1a = dR * g1a;
-      for (int i = 0; i < 3; ++i) {
-        w->dp[i] = w->dp[i] + w->dv[i] * dt + dRg2a[i] * dt * dt;
-        w->dv[i] = w->dv[i] + dRg1a[i] * dt;
-      }
-      M3 dRn = dR * E;
-      for (int i = 0; i < 9; ++i) w->dR[i] = dRn.m[i];
+    V3 wv = v3(smp.gyro[0] - bg[0], smp.gyro[1] - bg[1], smp.gyro[2] - bg[2]);
+    V3 av = v3(smp.acc[0] - ba[0], smp.acc[1] - ba[1], smp.acc[2] - ba[2]);
+    V3 phi = dt * wv;
+    double c[3], d[3];
+    gamma_coeffs(norm(phi), c, d);
+    PreintStep& P = w->st[m];
+    gamma_apply(phi, av, 1.0, c[0], c[1], d[0], d[1], &P.g1a, &P.D1);
+    gamma_apply(phi, av, 0.5, c[1], c[2], d[1], d[2], &P.g2a, &P.D2);
+    M3 K = hat(phi);
+    P.G1 = eye3() + c[0] * K + c[1] * (K * K);
+    P.G2 = 0.5 * eye3() + c[1] * K + c[2] * (K * K);
+    P.E = Exp(phi);
+    P.Jr = Jr(phi);
+    P.dt = dt;
+  }
+  DSLAM_SYNC();
+  // the rotation chain and the integrated velocity and position (cheap, serial)
+  SERIAL {
+    M3 dR = eye3();
+    V3 dv = v3(0, 0, 0), dp = v3(0, 0, 0);
+    for (int m = 0; m < nsub; ++m) {
+      PreintStep& P = w->st[m];
+      double dt = P.dt;
+      P.dR = dR;
+      dp = dp + dt * dv + (dt * dt) * (dR * P.g2a);
+      dv = dv + dt * (dR * P.g1a);
+      dR = dR * P.E;
     }
-    DSLAM_SYNC();
-    // T = A Sigma, TB = A J
+    for (int i = 0; i < 9; ++i) w->dR[i] = dR.m[i];
+    store3(w->dv, dv);
+    store3(w->dp, dp);
+  }
+  DSLAM_SYNC();
+  // step Jacobians A (error state [dphi, dv, dp]) and B (biases [bg, ba])
+  PFOR(m, nsub) {
+    const PreintStep& P = w->st[m];
+    double dt = P.dt;
+    double* A = w->A[m];
+    double* B = w->B[m];
+    for (int i = 0; i < 81; ++i) A[i] = (i % 10 == 0) ? 1.0 : 0.0;
+    M3 Et = tr(P.E);
+    M3 Av_phi = (-dt) * (P.dR * hat(P.g1a));
+    M3 Ap_phi = (-dt * dt) * (P.dR * hat(P.g2a));
+    M3 Bphi_g = (-dt) * P.Jr;
+    M3 Bv_g = (-dt * dt) * (P.dR * P.D1);
+    M3 Bp_g = (-dt * dt * dt) * (P.dR * P.D2);
+    M3 Bv_a = (-dt) * (P.dR * P.G1);
+    M3 Bp_a = (-dt * dt) * (P.dR * P.G2);
+    for (int i = 0; i < 3; ++i) {
+      A[9 * (6 + i) + 3 + i] = dt;
+      for (int j = 0; j < 3; ++j) {
+        A[9 * i + j] = Et(i, j);
+        A[9 * (3 + i) + j] = Av_phi(i, j);
+        A[9 * (6 + i) + j] = Ap_phi(i, j);
+        B[6 * i + j] = Bphi_g(i, j);
+        B[6 * i + 3 + j] = 0.0;
+        B[6 * (3 + i) + j] = Bv_g(i, j);
+        B[6 * (3 + i) + 3 + j] = Bv_a(i, j);
+        B[6 * (6 + i) + j] = Bp_g(i, j);
+        B[6 * (6 + i) + 3 + j] = Bp_a(i, j);
+      }
+    }
+  }
+  DSLAM_SYNC();
+  // Sigma <- A Sigma A^T + B diag(sigma^2/dt) B^T,  J <- A J + B
+  for (int m = 0; m < nsub; ++m) {
+    const double* A = w->A[m];
+    const double* B = w->B[m];
     PFOR(idx, 81) {
       int i = idx / 9, j = idx % 9;
       double acc = 0.0;
-      for (int k = 0; k < 9; ++k) acc += w->A[9 * i + k] * out->Sigma[9 * k + j];
+      for (int k = 0; k < 9; ++k) acc += A[9 * i + k] * out->Sigma[9 * k + j];
       w->T[idx] = acc;
     }
     PFOR(idx, 54) {
       int i = idx / 6, j = idx % 6;
       double acc = 0.0;
-      for (int k = 0; k < 9; ++k) acc += w->A[9 * i + k] * out->J[6 * k + j];
+      for (int k = 0; k < 9; ++k) acc += A[9 * i + k] * out->J[6 * k + j];
       w->TB[idx] = acc;
     }
     DSLAM_SYNC();
+    double dt = w->st[m].dt;
     double vg = sigma_g * sigma_g / dt, va = sigma_a * sigma_a / dt;
     PFOR(idx, 81) {
       int i = idx / 9, j = idx % 9;
       double acc = 0.0;
-      for (int k = 0; k < 9; ++k) acc += w->T[9 * i + k] * w->A[9 * j + k];
+      for (int k = 0; k < 9; ++k) acc += w->T[9 * i + k] * A[9 * j + k];
       double q = 0.0;
-      for (int k = 0; k < 3; ++k) q += w->B[6 * i + k] * w->B[6 * j + k];
+      for (int k = 0; k < 3; ++k) q += B[6 * i + k] * B[6 * j + k];
       double r = 0.0;
-      for (int k = 3; k < 6; ++k) r += w->B[6 * i + k] * w->B[6 * j + k];
+      for (int k = 3; k < 6; ++k) r += B[6 * i + k] * B[6 * j + k];
       out->Sigma[idx] = acc + vg * q + va * r;
     }
-    PFOR(idx, 54) out->J[idx] = w->TB[idx] + w->B[idx];
+    PFOR(idx, 54) out->J[idx] = w->TB[idx] + B[idx];
     DSLAM_SYNC();
   }
   SERIAL {
@@ -211,7 +236,6 @@ DX int preintegrate(Par par, const dslam_imu_sample* s, int n, double t0, double
       out->ba[i] = ba[i];
     }
     out->dt = t1 - t0;
-    // symmetrise
     for (int i = 0; i < 9; ++i)
       for (int j = i + 1; j < 9; ++j) {
         double a = 0.5 * (out->Sigma[9 * i + j] + out->Sigma[9 * j + i]);
@@ -228,13 +252,24 @@ struct ImuParamsD {
   double R_CS[9], t_CS[3];
 };
 
-// IMU error e = x1_hat(x0) [-] x1 (eq. (5)), ordered [r, alpha, v, bg, ba], with
-// the Jacobian rows of its first nine entries (9x33 over [x0, x1, dg]) and the
-// map A9 (9x9) from the preintegration noise (dphi, dv, dp) to those entries
-// (J9 == nullptr: residual only).  The bias rows are [I at x0's bias, -I at
-// x1's bias].  Serial.
-DX void imu_factor(const dslam_frame_state& x0, const dslam_frame_state& x1, const double* qIW,
-                   const dslam_preint& pre, const ImuParamsD& ip, double* e, double* J9, double* A9) {
+// Quantities shared by the IMU error and its Jacobian blocks.
+struct ImuCommon {
+  M3 R0, Q, Qt, S, QS, SdRt, Jli, Jri, Krot, Kal, RbT, JRg, JRa, Jpg, Jpa, Jvg, Jva;
+  V3 yr, yg, wt, Sdv, QSdv;
+  double T;
+};
+
+enum { IMU_BLOCKS = 16 };
+
+// IMU error e = x1_hat(x0) [-] x1 (eq. (5)), ordered [r, alpha, v, bg, ba],
+// and the quantities its Jacobian blocks need (c may be nullptr: residual
+// only).  The derivation uses the left perturbations of Section IV-A; with
+// S = R0 R_CS, dR~ = dR Exp(J_R db) and y_r = t_CS + R_CS dp~ - R_CS dR~ R_CS^T t_CS:
+//   r_hat = r0 + R0 y_r + R_IW^T (v0 T + g T^2/2),
+//   R_hat = S dR~ R_CS^T,  v_hat = v0 + g T + R_IW S dv~.
+// Serial.
+DX void imu_common(const dslam_frame_state& x0, const dslam_frame_state& x1, const double* qIW,
+                   const dslam_preint& pre, const ImuParamsD& ip, double* e, ImuCommon* c) {
   M3 R0 = q2R(x0.q), R1 = q2R(x1.q), Q = q2R(qIW);
   M3 Rcs = load33(ip.R_CS);
   V3 tcs = load3(ip.t_CS);
@@ -269,7 +304,8 @@ DX void imu_factor(const dslam_frame_state& x0, const dslam_frame_state& x1, con
   V3 v0 = load3(x0.v), r0 = load3(x0.r);
   M3 Qt = tr(Q);
   V3 yg = T * v0 + (0.5 * T * T) * g;
-  V3 rh = r0 + R0 * tcs + Qt * yg + S * dpv - Rh1 * tcs;
+  V3 yr = tcs + Rcs * dpv - Rcs * (dRt * wt);
+  V3 rh = r0 + R0 * yr + Qt * yg;
   V3 Sdv = S * dvv;
   V3 QSdv = Q * Sdv;
   V3 vh = v0 + T * g + QSdv;
@@ -283,79 +319,76 @@ DX void imu_factor(const dslam_frame_state& x0, const dslam_frame_state& x1, con
     e[9 + i] = x0.bg[i] - x1.bg[i];
     e[12 + i] = x0.ba[i] - x1.ba[i];
   }
-  if (J9 == nullptr) return;
-  for (int i = 0; i < 9 * 33; ++i) J9[i] = 0.0;
-  for (int i = 0; i < 81; ++i) A9[i] = 0.0;
-  M3 Jli = JlInv(ea);
-  M3 Jri = tr(Jli);
+  if (c == nullptr) return;
+  c->R0 = R0; c->Q = Q; c->Qt = Qt; c->S = S; c->QS = Q * S; c->SdRt = SdRt;
+  c->Jli = JlInv(ea);
+  c->Jri = tr(c->Jli);
   M3 Jrb = Jr(phib);
-  M3 JRg, JRa, Jpg, Jpa, Jvg, Jva;
+  c->Krot = SdRt * hat(wt) * Jrb;
+  c->Kal = c->Jli * SdRt * Jrb;
+  c->RbT = tr(Rb);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
-      JRg(i, j) = pre.J[6 * i + j];
-      JRa(i, j) = pre.J[6 * i + 3 + j];
-      Jvg(i, j) = pre.J[6 * (3 + i) + j];
-      Jva(i, j) = pre.J[6 * (3 + i) + 3 + j];
-      Jpg(i, j) = pre.J[6 * (6 + i) + j];
-      Jpa(i, j) = pre.J[6 * (6 + i) + 3 + j];
+      c->JRg(i, j) = pre.J[6 * i + j];
+      c->JRa(i, j) = pre.J[6 * i + 3 + j];
+      c->Jvg(i, j) = pre.J[6 * (3 + i) + j];
+      c->Jva(i, j) = pre.J[6 * (3 + i) + 3 + j];
+      c->Jpg(i, j) = pre.J[6 * (6 + i) + j];
+      c->Jpa(i, j) = pre.J[6 * (6 + i) + 3 + j];
     }
-  // e_r rows
-  V3 yr = tcs + Rcs * dpv - Rcs * (dRt * wt);
-  M3 Er_a0 = (-1.0) * hat(R0 * yr);
-  M3 Er_v0 = T * Qt;
-  M3 Krot = SdRt * hat(wt) * Jrb;
-  M3 Er_bg = S * Jpg + Krot * JRg;
-  M3 Er_ba = S * Jpa + Krot * JRa;
-  M3 Er_g = Qt * hat(yg);
-  // e_alpha rows
-  M3 Kal = Jli * SdRt * Jrb;
-  M3 Ea_bg = Kal * JRg;
-  M3 Ea_ba = Kal * JRa;
-  // e_v rows
-  M3 Ev_a0 = (-1.0) * (Q * hat(Sdv));
-  M3 Ev_bg = Q * S * Jvg;
-  M3 Ev_ba = Q * S * Jva;
-  M3 Ev_g = (-1.0) * hat(QSdv);
-  // noise map
-  M3 RbT = tr(Rb);
-  M3 Nr_phi = SdRt * hat(wt) * RbT;
-  M3 Na_phi = Jli * SdRt * RbT;
-  M3 Nv_v = Q * S;
+  c->yr = yr; c->yg = yg; c->wt = wt; c->Sdv = Sdv; c->QSdv = QSdv;
+  c->T = T;
+}
+
+DX void put_block(double* M, int ld, int r0, int c0, const M3& B) {
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      double d = (i == j) ? 1.0 : 0.0;
-      double* rr = J9 + 33 * i;
-      double* ra = J9 + 33 * (3 + i);
-      double* rv = J9 + 33 * (6 + i);
-      rr[0 + j] = d;
-      rr[3 + j] = Er_a0(i, j);
-      rr[6 + j] = Er_v0(i, j);
-      rr[9 + j] = Er_bg(i, j);
-      rr[12 + j] = Er_ba(i, j);
-      rr[15 + j] = -d;
-      rr[30 + j] = Er_g(i, j);
-      ra[3 + j] = Jli(i, j);
-      ra[9 + j] = Ea_bg(i, j);
-      ra[12 + j] = Ea_ba(i, j);
-      ra[18 + j] = -Jri(i, j);
-      rv[3 + j] = Ev_a0(i, j);
-      rv[6 + j] = d;
-      rv[9 + j] = Ev_bg(i, j);
-      rv[12 + j] = Ev_ba(i, j);
-      rv[21 + j] = -d;
-      rv[30 + j] = Ev_g(i, j);
-      A9[9 * i + j] = Nr_phi(i, j);
-      A9[9 * i + 6 + j] = S(i, j);
-      A9[9 * (3 + i) + j] = Na_phi(i, j);
-      A9[9 * (6 + i) + 3 + j] = Nv_v(i, j);
-    }
+    for (int j = 0; j < 3; ++j) M[(r0 + i) * ld + c0 + j] = B(i, j);
+}
+
+// Block b (0 <= b < IMU_BLOCKS) of the Jacobian rows J9 (9x33 over
+// [x0 (15), x1 (15), dg (3)]) of the first nine IMU error entries and of the
+// map A9 (9x9) from the preintegration noise (dphi, dv, dp) to them.  J9 and
+// A9 must be zero-filled first; blocks write disjoint entries.
+DX void imu_block(const ImuCommon& c, int b, double* J9, double* A9) {
+  const int L = 33;
+  M3 I3 = eye3();
+  switch (b) {
+    case 0:  // e_r: dr0 = I, dr1 = -I, da0 = -[R0 y_r]x
+      put_block(J9, L, 0, 0, I3);
+      put_block(J9, L, 0, 15, (-1.0) * I3);
+      put_block(J9, L, 0, 3, (-1.0) * hat(c.R0 * c.yr));
+      break;
+    case 1: put_block(J9, L, 0, 6, c.T * c.Qt); break;                               // e_r / dv0
+    case 2: put_block(J9, L, 0, 9, c.S * c.Jpg + c.Krot * c.JRg); break;             // e_r / dbg0
+    case 3: put_block(J9, L, 0, 12, c.S * c.Jpa + c.Krot * c.JRa); break;            // e_r / dba0
+    case 4: put_block(J9, L, 0, 30, c.Qt * hat(c.yg)); break;                        // e_r / dg
+    case 5: put_block(J9, L, 3, 3, c.Jli); break;                                    // e_a / da0
+    case 6: put_block(J9, L, 3, 9, c.Kal * c.JRg); break;                            // e_a / dbg0
+    case 7: put_block(J9, L, 3, 12, c.Kal * c.JRa); break;                           // e_a / dba0
+    case 8: put_block(J9, L, 3, 18, (-1.0) * c.Jri); break;                          // e_a / da1
+    case 9:  // e_v: dv0 = I, dv1 = -I, da0 = -R_IW [S dv~]x
+      put_block(J9, L, 6, 6, I3);
+      put_block(J9, L, 6, 21, (-1.0) * I3);
+      put_block(J9, L, 6, 3, (-1.0) * (c.Q * hat(c.Sdv)));
+      break;
+    case 10: put_block(J9, L, 6, 9, c.QS * c.Jvg); break;                            // e_v / dbg0
+    case 11: put_block(J9, L, 6, 12, c.QS * c.Jva); break;                           // e_v / dba0
+    case 12: put_block(J9, L, 6, 30, (-1.0) * hat(c.QSdv)); break;                   // e_v / dg
+    case 13: put_block(A9, 9, 0, 0, c.SdRt * hat(c.wt) * c.RbT); break;              // e_r / dphi
+    case 14: put_block(A9, 9, 3, 0, c.Jli * c.SdRt * c.RbT); break;                  // e_a / dphi
+    case 15:
+      put_block(A9, 9, 0, 6, c.S);                                                   // e_r / d(dp)
+      put_block(A9, 9, 6, 3, c.QS);                                                  // e_v / d(dv)
+      break;
+    default: break;
+  }
 }
 
 // IMU prediction of the current state from x0 (x1 <- x1_hat(x0)).  Serial.
 DX void imu_predict(const dslam_frame_state& x0, const double* qIW, const dslam_preint& pre, const ImuParamsD& ip,
                     dslam_frame_state* x1) {
   double e[15];
-  imu_factor(x0, x0, qIW, pre, ip, e, nullptr, nullptr);
+  imu_common(x0, x0, qIW, pre, ip, e, nullptr);
   // e = x1_hat [-] x0 with x1 := x0; recover x1_hat
   *x1 = x0;
   for (int i = 0; i < 3; ++i) {

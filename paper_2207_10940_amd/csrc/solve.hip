@@ -1,10 +1,11 @@
 // Device-side frame initialisation (IMU preintegration and prediction), the
-// cross-block float64 reduction and the float64 Gauss-Newton solve, so that
-// the whole coarse-to-fine iteration stays on the GPU (Section IV-C/D/E).
-// One workgroup of one wavefront runs each of these small kernels.
+// fixed-order float64 cross-block reduction and the float64 Gauss-Newton
+// solve, so that the whole coarse-to-fine iteration stays on the GPU
+// (Section IV-C/D/E).  One workgroup runs each of these small kernels.
 #include <hip/hip_runtime.h>
 #include "device.h"
 #include "solve_core.h"
+#include "solve_wave.h"
 
 namespace dslam {
 
@@ -28,28 +29,52 @@ struct SolveArgs {
   int32_t nblocks;
 };
 
-enum { SOLVE_THREADS = 64 };
-
-// Fixed-order float64 sum of the block partials (cross-block reduction).
-__device__ void reduce_partials(const float* partials, int nblocks, double* out) {
-  int l = threadIdx.x;
-  if (l < 58) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int b = 0;
-    for (; b + 4 <= nblocks; b += 4) {
-      s0 += (double)partials[(size_t)(b + 0) * PARTIAL_STRIDE + l];
-      s1 += (double)partials[(size_t)(b + 1) * PARTIAL_STRIDE + l];
-      s2 += (double)partials[(size_t)(b + 2) * PARTIAL_STRIDE + l];
-      s3 += (double)partials[(size_t)(b + 3) * PARTIAL_STRIDE + l];
+// Fixed-order float64 sum of the block partials ([nblocks][64] floats, 58
+// used): thread t sums the float4 column group t % 16 over blocks t/16,
+// t/16 + 16, ...; the 16 partial sums of each column are then added in row
+// order.  Same order whatever the launch.  Needs SOLVE_THREADS == 256.
+__device__ void reduce_partials(const float* partials, int nblocks, double* red /*shared 16x64*/, double* out) {
+  const int g = threadIdx.x & 15, r = threadIdx.x >> 4;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const float* base = partials + 4 * g;
+  int b = r;
+  for (; b + 16 * 7 < nblocks; b += 16 * 8) {  // eight independent loads in flight
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const float4*>(base + (size_t)(b + 16 * u) * PARTIAL_STRIDE);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s0 += (double)v[u].x;
+      s1 += (double)v[u].y;
+      s2 += (double)v[u].z;
+      s3 += (double)v[u].w;
     }
-    for (; b < nblocks; ++b) s0 += (double)partials[(size_t)b * PARTIAL_STRIDE + l];
-    out[l] = (s0 + s1) + (s2 + s3);
   }
+  for (; b < nblocks; b += 16) {
+    const float4 v = *reinterpret_cast<const float4*>(base + (size_t)b * PARTIAL_STRIDE);
+    s0 += (double)v.x;
+    s1 += (double)v.y;
+    s2 += (double)v.z;
+    s3 += (double)v.w;
+  }
+  red[r * 64 + 4 * g + 0] = s0;
+  red[r * 64 + 4 * g + 1] = s1;
+  red[r * 64 + 4 * g + 2] = s2;
+  red[r * 64 + 4 * g + 3] = s3;
+  __syncthreads();
+  if (threadIdx.x < 58) {
+    double acc = 0.0;
+    for (int k = 0; k < 16; ++k) acc += red[k * 64 + threadIdx.x];
+    out[threadIdx.x] = acc;
+  }
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(SOLVE_THREADS) void reduce_kernel(const float* partials, int nblocks, double* out) {
-  reduce_partials(partials, nblocks, out);
+  __shared__ double red[16 * 64];
+  reduce_partials(partials, nblocks, red, out);
 }
+
 
 __global__ __launch_bounds__(SOLVE_THREADS) void frame_init_kernel(SessionDev* sd, ImuBatch batch, FrameArgs fa) {
   __shared__ PreintWork pw;
@@ -90,7 +115,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, co
   __shared__ dslam_prior marg;
   __shared__ int skip;
   Par par{(int)threadIdx.x, SOLVE_THREADS};
-  reduce_partials(partials, a.nblocks, raw);
+  reduce_partials(partials, a.nblocks, w.L, raw);
+  if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
   SERIAL {
     skip = sd->status != DSLAM_OK;
     x0 = sd->x0;
@@ -98,7 +124,6 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, co
     for (int i = 0; i < 4; ++i) qIW[i] = sd->qIW[i];
   }
   DSLAM_SYNC();
-  if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
   if (skip) {
     if (a.last) {
       SERIAL {

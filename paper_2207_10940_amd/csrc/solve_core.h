@@ -35,16 +35,17 @@ struct SolveParams {
 
 struct SolveWork {
   double H[NZ * NZ];   // assembled system (full symmetric)
-  double L[NZ * NZ];   // Cholesky factor (lower), also Schur workspace
+  double L[(NZ + 1) * NZ];  // Cholesky factor (lower) with the right-hand side as row NZ; Schur workspace
   double b[NZ], y[NZ], dz[NZ];
   double J9[9 * NZ];   // IMU Jacobian rows (then whitened)
   double A9[81], S9[81];
   double e[15];
   double Hm[2][36], gm[2][6];
   double Lr[12 * 6], LH[12 * 6], Li[12 * 6], LHi[12 * 6];
-  double Y[15 * 19];   // H00^-1 [H0k, b'0] during marginalisation
+  double Y[18 * 19 > 9 * NZ ? 18 * 19 : 9 * NZ];  // scratch: A9 Sigma, W9 J9, H00^-1 [H0k, b0], Schur complement
   double prior_d[18];
   double cost[4];
+  ImuCommon ic;
   int status;
 };
 
@@ -60,33 +61,44 @@ DX void unpack_term(const double* raw, double* Hm, double* gm) {
   for (int i = 0; i < 6; ++i) gm[i] = raw[21 + i];
 }
 
-// In-place Cholesky of the n x n SPD matrix A (leading dim ld) into its lower
-// triangle, on the lanes of `par`.  Returns 0, or 1 if a pivot was not positive.
-DX int cholesky(Par par, double* A, int n, int ld, int* flag) {
+// In-place Cholesky factorisation A = L L^T of the leading n x n block of A
+// (leading dimension ld) into its lower triangle.  Rows n .. n+nrhs-1 hold
+// right-hand sides b^T: they are carried through the elimination, so on
+// return they hold (L^-1 b)^T (forward substitution for free).  Each row is
+// owned by one lane; two phase barriers per column.  Returns 1 if a pivot
+// was not positive and finite (the factor is then meaningless), else 0.
+DX int cholesky(Par par, double* A, int n, int ld, int nrhs, int* flag) {
   SERIAL *flag = 0;
   DSLAM_SYNC();
+  const int rows = n + nrhs;
   for (int k = 0; k < n; ++k) {
-    SERIAL {
-      double p = A[k * ld + k];
-      if (!(p > 0.0) || !(p < 1e300)) {
-        *flag = 1;
-        A[k * ld + k] = 1.0;
-      } else {
-        A[k * ld + k] = sqrt(p);
-      }
-    }
+    double p = A[k * ld + k];
+    bool good = (p > 0.0) && (p < 1e300);
+    double d = good ? sqrt(p) : 1.0;
+    PFOR(i, rows - k - 1) A[(k + 1 + i) * ld + k] /= d;
+    SERIAL if (!good) *flag = 1;
     DSLAM_SYNC();
-    double d = A[k * ld + k];
-    PFOR(i, n - k - 1) A[(k + 1 + i) * ld + k] /= d;
-    DSLAM_SYNC();
-    int m = n - k - 1;
-    PFOR(idx, m * m) {
-      int i = idx / m, j = idx % m;
-      if (j <= i) A[(k + 1 + i) * ld + (k + 1 + j)] -= A[(k + 1 + i) * ld + k] * A[(k + 1 + j) * ld + k];
+    SERIAL A[k * ld + k] = d;  // nobody reads the pivot in this phase
+    PFOR(i, rows - k - 1) {
+      int r = k + 1 + i;
+      double lrk = A[r * ld + k];
+      int jend = r < n ? r : n - 1;
+      for (int j = k + 1; j <= jend; ++j) A[r * ld + j] -= lrk * A[j * ld + k];
     }
     DSLAM_SYNC();
   }
   return *flag;
+}
+
+// Back substitution L^T x = y for one right-hand side, y in y[] (overwritten),
+// x written to x[]; one barrier per row.
+DX void chol_back(Par par, const double* Lm, int n, int ld, double* y, double* x) {
+  for (int k = n - 1; k >= 0; --k) {
+    double xk = y[k] / Lm[k * ld + k];
+    PFOR(i, k) y[i] -= Lm[k * ld + i] * xk;
+    SERIAL x[k] = xk;
+    DSLAM_SYNC();
+  }
 }
 
 // Solve L L^T x = rhs for `nr` right-hand sides stored as columns of X (ld ldx),
@@ -196,15 +208,85 @@ DX void lift_visual(const double* raw, const double* R_WM, const dslam_frame_sta
   }
 }
 
+// ---------------------------------------------------------------------------
+// Dense SPD back ends.  Host: textbook Cholesky on one thread.  Device: a
+// register-resident Gauss-Jordan elimination on one wavefront (solve_wave.h),
+// declared here and defined by the device translation unit.
+// ---------------------------------------------------------------------------
+#ifdef __HIP_DEVICE_COMPILE__
+__device__ int spd_inverse9_dev(const double* S9, double* W9);
+__device__ int spd_solve_dev(const double* H, const double* b, int n, double* dz, double* schur);
+#endif
+
+// W9 = S9^-1 for a 9x9 SPD matrix.  Returns 0, or 1 if S9 is not SPD.
+DX int spd_inverse9(Par par, SolveWork* w, const double* S9, double* W9) {
+#ifdef __HIP_DEVICE_COMPILE__
+  (void)par;
+  (void)w;
+  return spd_inverse9_dev(S9, W9);
+#else
+  double L[81], X[81];
+  for (int i = 0; i < 81; ++i) {
+    L[i] = S9[i];
+    X[i] = (i % 10 == 0) ? 1.0 : 0.0;
+  }
+  if (cholesky(par, L, 9, 9, 0, &w->status)) return 1;
+  chol_solve_cols(par, L, 9, 9, X, 9, 9);
+  for (int i = 0; i < 81; ++i) W9[i] = X[i];
+  return 0;
+#endif
+}
+
+// dz = H^-1 b for the leading n x n block of H (leading dimension NZ).  If
+// schur != nullptr (n == NZ), also the Schur complement of the leading 15x15
+// block of [H | b]: schur (18 x 19, row-major) = [H_kk - H_k0 H_00^-1 H_0k |
+// b_k - H_k0 H_00^-1 b_0].  Returns 0, or 1 if H is not SPD.
+DX int spd_solve(Par par, SolveWork* w, const double* H, const double* b, int n, double* dz, double* schur) {
+#ifdef __HIP_DEVICE_COMPILE__
+  (void)par;
+  (void)w;
+  return spd_solve_dev(H, b, n, dz, schur);
+#else
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) w->L[i * NZ + j] = H[i * NZ + j];
+    w->L[n * NZ + i] = b[i];
+  }
+  if (cholesky(par, w->L, n, NZ, 1, &w->status)) return 1;
+  chol_back(par, w->L, n, NZ, w->L + n * NZ, dz);
+  if (schur) {
+    for (int i = 0; i < 15; ++i)
+      for (int j = 0; j < 15; ++j) w->L[i * NZ + j] = H[i * NZ + j];
+    if (cholesky(par, w->L, 15, NZ, 0, &w->status)) return 1;
+    double Z[15 * 19];  // H00^-1 [H0k, b0]
+    for (int i = 0; i < 15; ++i)
+      for (int c = 0; c < 19; ++c) Z[i * 19 + c] = c < 18 ? H[i * NZ + 15 + c] : b[i];
+    chol_solve_cols(par, w->L, 15, NZ, Z, 19, 19);
+    for (int i = 0; i < 18; ++i)
+      for (int c = 0; c < 19; ++c) {
+        double a = c < 18 ? H[(15 + i) * NZ + 15 + c] : b[15 + i];
+        for (int k = 0; k < 15; ++k) a -= H[(15 + i) * NZ + k] * Z[k * 19 + c];
+        schur[i * 19 + c] = a;
+      }
+  }
+  return 0;
+#endif
+}
+
+// Independent serial tasks run on the first lane of different wavefronts
+// (concurrently on the device, one after the other on the host).
+#define TASK(t) if (par.lane == (((t) * 64 < par.nl) ? (t) * 64 : 0))
+
 // One Gauss-Newton step.  raw: the 58 sums of the residual pass (ICP then RGB),
-// taken at (x0, x1).  Updates x0, x1, qIW in place on success (lane 0 writes),
-// writes the marginal prior if sp.marginalise.  Returns a dslam_status.
+// taken at (x0, x1).  Updates x0, x1, qIW in place on success, writes the
+// marginal prior if sp.marginalise.  Returns a dslam_status.
 DX int solve_step(Par par, SolveWork* w, const double* raw, const SolveParams& sp, const dslam_preint* pre,
                   const dslam_prior* prior, dslam_frame_state* x0, dslam_frame_state* x1, double* qIW,
                   dslam_prior* marg_out) {
   const bool full = sp.mode != DSLAM_MODE_RGBD;
   const int n = full ? NZ : 6;
-  SERIAL {
+  const bool marg = full && sp.marginalise && marg_out != nullptr;
+  // ---- independent serial set-up
+  TASK(0) {
     unpack_term(raw, w->Hm[0], w->gm[0]);
     unpack_term(raw + 29, w->Hm[1], w->gm[1]);
     w->cost[0] = raw[27];
@@ -213,208 +295,197 @@ DX int solve_step(Par par, SolveWork* w, const double* raw, const SolveParams& s
     w->cost[3] = 0.0;
     build_lift(sp.R_WM, *x0, *x1, w->Li, w->Lr);
   }
+  if (full) {
+    TASK(1) imu_common(*x0, *x1, qIW, *pre, sp.imu, w->e, &w->ic);
+    TASK(2) {
+      state_boxminus(*x0, prior->xbar, w->prior_d);
+      V3 dg = qboxminus(qIW, prior->q_IW_bar);
+      w->prior_d[15] = dg.x;
+      w->prior_d[16] = dg.y;
+      w->prior_d[17] = dg.z;
+    }
+  }
   PFOR(i, NZ * NZ) w->H[i] = 0.0;
   PFOR(i, NZ) w->b[i] = 0.0;
+  PFOR(i, 9 * NZ) w->J9[i] = 0.0;
+  PFOR(i, 81) w->A9[i] = 0.0;
   DSLAM_SYNC();
-  // LH = L Hm (12x6)
-  PFOR(idx, 72) {
-    int i = idx / 6, j = idx % 6;
-    double a = 0.0, c = 0.0;
-    for (int k = 0; k < 6; ++k) {
-      a += w->Lr[6 * i + k] * w->Hm[1][6 * k + j];
-      c += w->Li[6 * i + k] * w->Hm[0][6 * k + j];
-    }
-    w->LH[idx] = a;
-    w->LHi[idx] = c;
-  }
-  DSLAM_SYNC();
-  // visual 12x12 block into z indices {0..5, 15..20}; in RGBD mode only the x1 pose block
-  PFOR(idx, 144) {
-    int i = idx / 12, j = idx % 12;
-    double a = 0.0;
-    for (int k = 0; k < 6; ++k) a += w->LH[6 * i + k] * w->Lr[6 * j + k] + w->LHi[6 * i + k] * w->Li[6 * j + k];
-    if (full) {
-      int zi = i < 6 ? i : 9 + i, zj = j < 6 ? j : 9 + j;
-      w->H[zi * NZ + zj] = a;
-    } else if (i >= 6 && j >= 6) {
-      w->H[(i - 6) * NZ + (j - 6)] = a;
+  // ---- LH = L Hm (12x6) per term; IMU Jacobian blocks
+  PFOR(idx, 72 + IMU_BLOCKS) {
+    if (idx < 72) {
+      int i = idx / 6, j = idx % 6;
+      double a = 0.0, c = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        a += w->Lr[6 * i + k] * w->Hm[1][6 * k + j];
+        c += w->Li[6 * i + k] * w->Hm[0][6 * k + j];
+      }
+      w->LH[idx] = a;
+      w->LHi[idx] = c;
+    } else if (full) {
+      imu_block(w->ic, idx - 72, w->J9, w->A9);
     }
   }
-  PFOR(i, 12) {
-    double a = 0.0;
-    for (int k = 0; k < 6; ++k) a -= w->Lr[6 * i + k] * w->gm[1][k] + w->Li[6 * i + k] * w->gm[0][k];
-    if (full) w->b[i < 6 ? i : 9 + i] = a;
-    else if (i >= 6) w->b[i - 6] = a;
+  DSLAM_SYNC();
+  // ---- visual 12x12 block into z indices {0..5, 15..20} (RGBD mode: only the
+  // x1 pose block); Y = A9 Sigma for the IMU covariance
+  PFOR(idx, 144 + 12 + 81) {
+    if (idx < 144) {
+      int i = idx / 12, j = idx % 12;
+      double a = 0.0;
+      for (int k = 0; k < 6; ++k) a += w->LH[6 * i + k] * w->Lr[6 * j + k] + w->LHi[6 * i + k] * w->Li[6 * j + k];
+      if (full) w->H[(i < 6 ? i : 9 + i) * NZ + (j < 6 ? j : 9 + j)] = a;
+      else if (i >= 6 && j >= 6) w->H[(i - 6) * NZ + (j - 6)] = a;
+    } else if (idx < 156) {
+      int i = idx - 144;
+      double a = 0.0;
+      for (int k = 0; k < 6; ++k) a -= w->Lr[6 * i + k] * w->gm[1][k] + w->Li[6 * i + k] * w->gm[0][k];
+      if (full) w->b[i < 6 ? i : 9 + i] = a;
+      else if (i >= 6) w->b[i - 6] = a;
+    } else if (full) {
+      int q = idx - 156, i = q / 9, j = q % 9;
+      double a = 0.0;
+      for (int k = 0; k < 9; ++k) a += w->A9[9 * i + k] * pre->Sigma[9 * k + j];
+      w->Y[q] = a;
+    }
   }
   DSLAM_SYNC();
   if (full) {
-    // IMU factor: residual, Jacobian rows and noise map (serial), covariance (parallel)
-    SERIAL imu_factor(*x0, *x1, qIW, *pre, sp.imu, w->e, w->J9, w->A9);
-    DSLAM_SYNC();
-    PFOR(idx, 81) {  // Y = A9 Sigma (in L as scratch)
-      int i = idx / 9, j = idx % 9;
-      double a = 0.0;
-      for (int k = 0; k < 9; ++k) a += w->A9[9 * i + k] * pre->Sigma[9 * k + j];
-      w->L[idx] = a;
-    }
-    DSLAM_SYNC();
+    // ---- IMU term: Sigma_e = A9 Sigma A9^T (+ random-walk rows), W = Sigma_e^-1
     PFOR(idx, 81) {
       int i = idx / 9, j = idx % 9;
       double a = 0.0;
-      for (int k = 0; k < 9; ++k) a += w->L[9 * i + k] * w->A9[9 * j + k];
+      for (int k = 0; k < 9; ++k) a += w->Y[9 * i + k] * w->A9[9 * j + k];
       w->S9[idx] = a;
     }
     DSLAM_SYNC();
-    int bad = cholesky(par, w->S9, 9, 9, &w->status);
-    if (bad) {
+    if (spd_inverse9(par, w, w->S9, w->A9)) {  // W9 overwrites A9
       SERIAL w->status = DSLAM_ERR_SINGULAR;
       DSLAM_SYNC();
       return DSLAM_ERR_SINGULAR;
     }
-    // whiten: J9 <- S^-1 J9, e9 <- S^-1 e9 (forward substitution per column)
-    PFOR(c, NZ + 1) {
-      for (int i = 0; i < 9; ++i) {
-        double s = c < NZ ? w->J9[i * NZ + c] : w->e[i];
-        for (int k = 0; k < i; ++k) s -= w->S9[9 * i + k] * (c < NZ ? w->J9[k * NZ + c] : w->e[k]);
-        s /= w->S9[9 * i + i];
-        if (c < NZ) w->J9[i * NZ + c] = s;
-        else w->e[i] = s;
+    DSLAM_SYNC();
+    // T = W9 J9 (9 x 33), we = W9 e9
+    PFOR(idx, 9 * NZ + 9) {
+      int i = idx / NZ, c = idx % NZ;
+      if (idx < 9 * NZ) {
+        double a = 0.0;
+        for (int k = 0; k < 9; ++k) a += w->A9[9 * i + k] * w->J9[k * NZ + c];
+        w->Y[idx] = a;
+      } else {
+        int r = idx - 9 * NZ;
+        double a = 0.0;
+        for (int k = 0; k < 9; ++k) a += w->A9[9 * r + k] * w->e[k];
+        w->y[r] = a;
       }
     }
     DSLAM_SYNC();
-    double T = pre->dt;
-    double wbg = 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T);
-    double wba = 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T);
-    PFOR(idx, NZ * NZ) {
-      int i = idx / NZ, j = idx % NZ;
-      double a = 0.0;
-      for (int k = 0; k < 9; ++k) a += w->J9[k * NZ + i] * w->J9[k * NZ + j];
-      w->H[idx] += a;
-    }
-    PFOR(i, NZ) {
-      double a = 0.0;
-      for (int k = 0; k < 9; ++k) a += w->J9[k * NZ + i] * w->e[k];
-      w->b[i] -= a;
+    // H += J9^T T, b -= J9^T we
+    PFOR(idx, NZ * NZ + NZ) {
+      if (idx < NZ * NZ) {
+        int i = idx / NZ, j = idx % NZ;
+        double a = 0.0;
+        for (int k = 0; k < 9; ++k) a += w->J9[k * NZ + i] * w->Y[k * NZ + j];
+        w->H[idx] += a;
+      } else {
+        int i = idx - NZ * NZ;
+        double a = 0.0;
+        for (int k = 0; k < 9; ++k) a += w->J9[k * NZ + i] * w->y[k];
+        w->b[i] -= a;
+      }
     }
     DSLAM_SYNC();
-    // bias random-walk rows: e = b0 - b1 with J = [I at x0, -I at x1]
+    // bias random-walk rows (e = b0 - b1, J = [I at x0, -I at x1]) and the prior
     SERIAL {
+      double T = pre->dt;
+      double wbg = 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T);
+      double wba = 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T);
       double c = 0.0;
-      for (int k = 0; k < 9; ++k) c += w->e[k] * w->e[k];
+      for (int k = 0; k < 9; ++k) c += w->e[k] * w->y[k];
       for (int i = 0; i < 3; ++i) {
         double eg = w->e[9 + i], ea = w->e[12 + i];
         int g0 = 9 + i, g1 = 24 + i, a0 = 12 + i, a1 = 27 + i;
-        w->H[g0 * NZ + g0] += wbg; w->H[g1 * NZ + g1] += wbg;
-        w->H[g0 * NZ + g1] -= wbg; w->H[g1 * NZ + g0] -= wbg;
-        w->H[a0 * NZ + a0] += wba; w->H[a1 * NZ + a1] += wba;
-        w->H[a0 * NZ + a1] -= wba; w->H[a1 * NZ + a0] -= wba;
-        w->b[g0] -= wbg * eg; w->b[g1] += wbg * eg;
-        w->b[a0] -= wba * ea; w->b[a1] += wba * ea;
+        w->H[g0 * NZ + g1] -= wbg;
+        w->H[g1 * NZ + g0] -= wbg;
+        w->H[g1 * NZ + g1] += wbg;
+        w->H[a0 * NZ + a1] -= wba;
+        w->H[a1 * NZ + a0] -= wba;
+        w->H[a1 * NZ + a1] += wba;
+        w->b[g1] += wbg * eg;
+        w->b[a1] += wba * ea;
         c += wbg * eg * eg + wba * ea * ea;
       }
       w->cost[2] = c;
-      // prior: d = (x0, q_IW) [-] xbar
-      state_boxminus(*x0, prior->xbar, w->prior_d);
-      V3 dg = qboxminus(qIW, prior->q_IW_bar);
-      w->prior_d[15] = dg.x; w->prior_d[16] = dg.y; w->prior_d[17] = dg.z;
     }
-    DSLAM_SYNC();
-    PFOR(idx, 18 * 18) {
-      int i = idx / 18, j = idx % 18;
-      int zi = i < 15 ? i : 15 + i, zj = j < 15 ? j : 15 + j;
-      w->H[zi * NZ + zj] += prior->H[idx];
-    }
-    PFOR(i, 18) {
-      double a = prior->b[i];
-      for (int k = 0; k < 18; ++k) a -= prior->H[18 * i + k] * w->prior_d[k];
-      w->b[i < 15 ? i : 15 + i] += a;
+    // prior on (x0, q_IW): H += H*, b += b* - H* d; the x0-bias diagonal of the
+    // random-walk rows is added here too (disjoint from the SERIAL block's entries)
+    PFOR(idx, 18 * 18 + 18) {
+      if (idx < 324) {
+        int i = idx / 18, j = idx % 18;
+        int zi = i < 15 ? i : 15 + i, zj = j < 15 ? j : 15 + j;
+        double a = prior->H[idx];
+        if (i == j && i >= 9 && i < 15) {
+          double T = pre->dt;
+          double sr = i < 12 ? sp.imu.sigma_bg_rw : sp.imu.sigma_ba_rw;
+          a += 1.0 / (sr * sr * T);
+        }
+        w->H[zi * NZ + zj] += a;
+      } else {
+        int i = idx - 324;
+        double a = prior->b[i];
+        for (int k = 0; k < 18; ++k) a -= prior->H[18 * i + k] * w->prior_d[k];
+        if (i >= 9 && i < 15) {
+          double T = pre->dt;
+          double sr = i < 12 ? sp.imu.sigma_bg_rw : sp.imu.sigma_ba_rw;
+          a -= w->e[i] / (sr * sr * T);
+        }
+        w->b[i < 15 ? i : 15 + i] += a;
+      }
     }
     DSLAM_SYNC();
   }
-  // Cholesky solve of H dz = b
-  PFOR(idx, n * n) {
-    int i = idx / n, j = idx % n;
-    w->L[i * NZ + j] = w->H[i * NZ + j];
-  }
-  PFOR(i, n) w->dz[i] = w->b[i];
-  DSLAM_SYNC();
-  int bad = cholesky(par, w->L, n, NZ, &w->status);
-  if (bad) {
+  // ---- solve H dz = b (and, on the last iteration, the Schur complement of x0)
+  if (spd_solve(par, w, w->H, w->b, n, w->dz, marg ? w->Y : nullptr)) {
     SERIAL w->status = DSLAM_ERR_SINGULAR;
     DSLAM_SYNC();
     return DSLAM_ERR_SINGULAR;
   }
+  DSLAM_SYNC();
   SERIAL {
-    for (int i = 0; i < n; ++i) {
-      double s = w->dz[i];
-      for (int k = 0; k < i; ++k) s -= w->L[i * NZ + k] * w->dz[k];
-      w->dz[i] = s / w->L[i * NZ + i];
-    }
-    for (int i = n - 1; i >= 0; --i) {
-      double s = w->dz[i];
-      for (int k = i + 1; k < n; ++k) s -= w->L[k * NZ + i] * w->dz[k];
-      w->dz[i] = s / w->L[i * NZ + i];
-    }
     bool finite = true;
     for (int i = 0; i < n; ++i) finite = finite && (w->dz[i] == w->dz[i]) && fabs(w->dz[i]) < 1e30;
     w->status = finite ? DSLAM_OK : DSLAM_ERR_SINGULAR;
-    if (finite) {
-      if (full) {
-        state_boxplus(x0, w->dz);
-        state_boxplus(x1, w->dz + 15);
-        qboxplus(qIW, v3(w->dz[30], w->dz[31], w->dz[32]));
+  }
+  DSLAM_SYNC();
+  if (w->status != DSLAM_OK) return w->status;
+  // ---- box-plus updates (Section IV-D)
+  if (full) {
+    TASK(0) state_boxplus(x0, w->dz);
+    TASK(1) state_boxplus(x1, w->dz + 15);
+    TASK(2) qboxplus(qIW, v3(w->dz[30], w->dz[31], w->dz[32]));
+  } else {
+    SERIAL {
+      double d15[15] = {w->dz[0], w->dz[1], w->dz[2], w->dz[3], w->dz[4], w->dz[5], 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      state_boxplus(x1, d15);
+    }
+  }
+  // ---- marginalisation (eq. (8)) at the updated point: with b' = b - H dz,
+  // S(b') = S(b) - H* dz_k, so b* = S(b) - H* dz_k
+  if (marg) {
+    PFOR(idx, 18 * 18 + 18) {
+      if (idx < 324) {
+        int i = idx / 18, j = idx % 18;
+        marg_out->H[idx] = 0.5 * (w->Y[i * 19 + j] + w->Y[j * 19 + i]);
       } else {
-        double d15[15] = {w->dz[0], w->dz[1], w->dz[2], w->dz[3], w->dz[4], w->dz[5], 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        state_boxplus(x1, d15);
+        int i = idx - 324;
+        double a = w->Y[i * 19 + 18];
+        for (int k = 0; k < 18; ++k) a -= w->Y[i * 19 + k] * w->dz[15 + k];
+        marg_out->b[i] = a;
       }
     }
   }
   DSLAM_SYNC();
-  if (w->status != DSLAM_OK) return w->status;
-  if (full && sp.marginalise && marg_out != nullptr) {
-    // b' = b - H dz (re-expressed at the updated point)
-    PFOR(i, NZ) {
-      double a = w->b[i];
-      for (int k = 0; k < NZ; ++k) a -= w->H[i * NZ + k] * w->dz[k];
-      w->y[i] = a;
-    }
-    // Cholesky of H00 (15x15) in L
-    PFOR(idx, 15 * 15) {
-      int i = idx / 15, j = idx % 15;
-      w->L[i * NZ + j] = w->H[i * NZ + j];
-    }
-    DSLAM_SYNC();
-    if (cholesky(par, w->L, 15, NZ, &w->status)) {
-      SERIAL w->status = DSLAM_ERR_SINGULAR;
-      DSLAM_SYNC();
-      return DSLAM_ERR_SINGULAR;
-    }
-    // Y = H00^-1 [H0k (15x18), b'0]
-    PFOR(idx, 15 * 19) {
-      int i = idx / 19, c = idx % 19;
-      w->Y[idx] = c < 18 ? w->H[i * NZ + 15 + c] : w->y[i];
-    }
-    DSLAM_SYNC();
-    chol_solve_cols(par, w->L, 15, NZ, w->Y, 19, 19);
-    PFOR(idx, 18 * 18) {
-      int i = idx / 18, j = idx % 18;
-      double a = w->H[(15 + i) * NZ + 15 + j];
-      for (int k = 0; k < 15; ++k) a -= w->H[(15 + i) * NZ + k] * w->Y[k * 19 + j];
-      marg_out->H[idx] = a;
-    }
-    PFOR(i, 18) {
-      double a = w->y[15 + i];
-      for (int k = 0; k < 15; ++k) a -= w->H[(15 + i) * NZ + k] * w->Y[k * 19 + 18];
-      marg_out->b[i] = a;
-    }
-    DSLAM_SYNC();
+  if (marg) {
     SERIAL {
-      for (int i = 0; i < 18; ++i)
-        for (int j = i + 1; j < 18; ++j) {
-          double a = 0.5 * (marg_out->H[18 * i + j] + marg_out->H[18 * j + i]);
-          marg_out->H[18 * i + j] = a;
-          marg_out->H[18 * j + i] = a;
-        }
       marg_out->xbar = *x1;
       for (int i = 0; i < 4; ++i) marg_out->q_IW_bar[i] = qIW[i];
     }

@@ -1,0 +1,108 @@
+// Device back ends of the dense SPD solves of the Gauss-Newton step: one
+// wavefront holds the augmented system one row per lane, in registers, and
+// runs Gauss-Jordan elimination without pivoting (positive pivots exist for
+// every SPD matrix; a non-positive pivot reports the system as singular).
+// The pivot row of each step is broadcast with v_readlane, so a step costs
+// two lane reads and one FMA per remaining column and no LDS round trip.
+//
+// Eliminating the first 15 pivot columns of [H | b] leaves, in rows 15..32,
+// exactly the Schur complement [H* | S(b)] of the previous state's block
+// (Section IV-E, eq. (8)); the solve captures it on the way.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dslam {
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
+  unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Gauss-Jordan on the rows held by the lanes of one wavefront: lane i < NSTEP
+// holds R[0..NC) = row i of [A | B].  After the loop every pivot column k <
+// NSTEP is zero in every row but row k, whose entries are left unscaled.  If
+// cap != nullptr, rows CAP..NSTEP-1, columns CAP..NC-1 are stored there just
+// before step CAP (row-major, NC - CAP per row).
+template <int NC, int NSTEP, int CAP>
+__device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* cap) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < NSTEP; ++k) {
+    if (k == CAP && cap != nullptr && lane >= CAP && lane < NSTEP) {
+#pragma unroll
+      for (int j = CAP; j < NC; ++j) cap[(lane - CAP) * (NC - CAP) + (j - CAP)] = R[j];
+    }
+    const double p = readlane_d(R[k], k);
+    ok = ok && (p > 0.0) && (p < 1e300);
+    const double inv = 1.0 / p;
+    const double m = (lane == k) ? 0.0 : R[k] * inv;
+#pragma unroll
+    for (int j = k + 1; j < NC; ++j) R[j] = fma(-m, readlane_d(R[j], k), R[j]);
+    if (lane != k) R[k] = 0.0;
+  }
+  return ok;
+}
+
+template <int NC>
+__device__ __forceinline__ double own_diag(const double (&R)[NC], int lane) {
+  double d = 1.0;
+#pragma unroll
+  for (int i = 0; i < NC; ++i) d = (lane == i) ? R[i] : d;
+  return d;
+}
+
+// W9 = S9^-1 (9x9 row-major, shared memory).  Called by every thread of the
+// block; wave 0 computes.  Returns 0, or 1 if S9 is not SPD.
+__device__ int spd_inverse9_dev(const double* S9, double* W9) {
+  __shared__ int bad;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    double R[18];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      R[j] = lane < 9 ? S9[9 * lane + j] : (lane == j ? 1.0 : 0.0);
+      R[9 + j] = (lane == j) ? 1.0 : 0.0;
+    }
+    bool ok = gauss_jordan<18, 9, -1>(R, lane, nullptr);
+    const double d = own_diag(R, lane);
+    if (lane < 9) {
+#pragma unroll
+      for (int j = 0; j < 9; ++j) W9[9 * lane + j] = R[9 + j] / d;
+    }
+    if (lane == 0) bad = ok ? 0 : 1;
+  }
+  __syncthreads();
+  return bad;
+}
+
+template <int N, int CAP>
+__device__ __forceinline__ bool solve_rows(const double* H, const double* b, int lane, double* dz, double* cap) {
+  double R[N + 1];
+#pragma unroll
+  for (int j = 0; j < N; ++j) R[j] = lane < N ? H[lane * 33 + j] : (lane == j ? 1.0 : 0.0);
+  R[N] = lane < N ? b[lane] : 0.0;
+  bool ok = gauss_jordan<N + 1, N, CAP>(R, lane, cap);
+  const double d = own_diag(R, lane);
+  if (lane < N) dz[lane] = R[N] / d;
+  return ok;
+}
+
+// dz = H^-1 b (H leading dimension 33, shared memory); n is 33 or 6.  With
+// schur != nullptr (n == 33) also writes the 18 x 19 Schur complement of the
+// leading 15x15 block of [H | b].  Called by every thread; wave 0 computes.
+__device__ int spd_solve_dev(const double* H, const double* b, int n, double* dz, double* schur) {
+  __shared__ int bad;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    bool ok = false;
+    if (n == 33) ok = solve_rows<33, 15>(H, b, lane, dz, schur);
+    else if (n == 6) ok = solve_rows<6, -1>(H, b, lane, dz, nullptr);
+    if (lane == 0) bad = ok ? 0 : 1;
+  }
+  __syncthreads();
+  return bad;
+}
+
+}  // namespace dslam
