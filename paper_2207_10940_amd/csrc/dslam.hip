@@ -261,7 +261,7 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   s->max_blocks = lo.max_blocks;
   for (int i = 0; i < 16; ++i) s->T_WM[i] = (i % 5 == 0) ? 1.0 : 0.0;
   auto fail = [&](dslam_status st) {
-    if (s->arena) hipFree(s->arena);
+    if (s->arena) (void)hipFree(s->arena);
     ctx->used.fetch_sub(lo.total);
     delete s;
     return st;
@@ -308,10 +308,10 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
 
 dslam_status dslam_session_close(dslam_session* s) {
   if (!s) return DSLAM_ERR_INVALID;
-  hipSetDevice(s->ctx->device);
-  hipDeviceSynchronize();
-  hipEventDestroy(s->done);
-  hipFree(s->arena);
+  (void)hipSetDevice(s->ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipEventDestroy(s->done);
+  (void)hipFree(s->arena);
   s->ctx->used.fetch_sub(s->bytes);
   delete s;
   return DSLAM_OK;

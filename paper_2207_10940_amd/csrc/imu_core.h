@@ -254,12 +254,18 @@ struct ImuParamsD {
 
 // Quantities shared by the IMU error and its Jacobian blocks.
 struct ImuCommon {
-  M3 R0, Q, Qt, S, QS, SdRt, Jli, Jri, Krot, Kal, RbT, JRg, JRa, Jpg, Jpa, Jvg, Jva;
-  V3 yr, yg, wt, Sdv, QSdv;
+  // operands of the Jacobian blocks (see imu_block); mats[0] is the identity
+  M3 mats[24];
   double T;
 };
 
-enum { IMU_BLOCKS = 16 };
+// indices into ImuCommon::mats
+enum {
+  IC_I = 0, IC_NEG_I, IC_HAT_R0YR, IC_QT, IC_S, IC_JPG, IC_KROT, IC_JRG, IC_JPA, IC_JRA, IC_HAT_YG, IC_JLI, IC_KAL,
+  IC_JRI, IC_Q, IC_HAT_SDV, IC_QS, IC_JVG, IC_JVA, IC_HAT_QSDV, IC_KROT_NOISE, IC_JLI_SDRT, IC_RBT, IC_COUNT
+};
+
+enum { IMU_BLOCKS = 20 };
 
 // IMU error e = x1_hat(x0) [-] x1 (eq. (5)), ordered [r, alpha, v, bg, ba],
 // and the quantities its Jacobian blocks need (c may be nullptr: residual
@@ -320,24 +326,166 @@ DX void imu_common(const dslam_frame_state& x0, const dslam_frame_state& x1, con
     e[12 + i] = x0.ba[i] - x1.ba[i];
   }
   if (c == nullptr) return;
-  c->R0 = R0; c->Q = Q; c->Qt = Qt; c->S = S; c->QS = Q * S; c->SdRt = SdRt;
-  c->Jli = JlInv(ea);
-  c->Jri = tr(c->Jli);
+  M3* m = c->mats;
+  M3 Jli = JlInv(ea);
   M3 Jrb = Jr(phib);
-  c->Krot = SdRt * hat(wt) * Jrb;
-  c->Kal = c->Jli * SdRt * Jrb;
-  c->RbT = tr(Rb);
+  M3 hwt = hat(wt);
+  m[IC_I] = eye3();
+  m[IC_NEG_I] = (-1.0) * eye3();
+  m[IC_HAT_R0YR] = (-1.0) * hat(R0 * yr);
+  m[IC_QT] = T * Qt;
+  m[IC_S] = S;
+  m[IC_KROT] = SdRt * hwt * Jrb;
+  m[IC_HAT_YG] = Qt * hat(yg);
+  m[IC_JLI] = Jli;
+  m[IC_KAL] = Jli * SdRt * Jrb;
+  m[IC_JRI] = (-1.0) * tr(Jli);
+  m[IC_Q] = (-1.0) * Q;
+  m[IC_HAT_SDV] = hat(Sdv);
+  m[IC_QS] = Q * S;
+  m[IC_HAT_QSDV] = (-1.0) * hat(QSdv);
+  m[IC_KROT_NOISE] = SdRt * hwt;
+  m[IC_JLI_SDRT] = Jli * SdRt;
+  m[IC_RBT] = tr(Rb);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
-      c->JRg(i, j) = pre.J[6 * i + j];
-      c->JRa(i, j) = pre.J[6 * i + 3 + j];
-      c->Jvg(i, j) = pre.J[6 * (3 + i) + j];
-      c->Jva(i, j) = pre.J[6 * (3 + i) + 3 + j];
-      c->Jpg(i, j) = pre.J[6 * (6 + i) + j];
-      c->Jpa(i, j) = pre.J[6 * (6 + i) + 3 + j];
+      m[IC_JRG](i, j) = pre.J[6 * i + j];
+      m[IC_JRA](i, j) = pre.J[6 * i + 3 + j];
+      m[IC_JVG](i, j) = pre.J[6 * (3 + i) + j];
+      m[IC_JVA](i, j) = pre.J[6 * (3 + i) + 3 + j];
+      m[IC_JPG](i, j) = pre.J[6 * (6 + i) + j];
+      m[IC_JPA](i, j) = pre.J[6 * (6 + i) + 3 + j];
     }
-  c->yr = yr; c->yg = yg; c->wt = wt; c->Sdv = Sdv; c->QSdv = QSdv;
   c->T = T;
+}
+
+// Intermediates of imu_common_par shared between its lanes.
+struct ImuStage {
+  M3 R0, R1, Q, Rb, Jrb, SdRt, Jli;
+  V3 phib, dvt, dpt, ea, yr, yg, Sdv, QSdv;
+};
+
+#ifndef TASK
+// Independent serial tasks run on the first lane of different wavefronts
+// (concurrently on the device, one after the other on the host).
+#define TASK(t) if (par.lane == (((t) * 64 < par.nl) ? (t) * 64 : 0))
+#endif
+
+// imu_common split over the first lanes of three wavefronts: the three
+// rotations and the bias-corrected preintegration first, then the residual,
+// then the Jacobian operands.  Same arithmetic as imu_common.  `side` runs on
+// a fourth wavefront during the last stage.
+template <class Side>
+DX void imu_common_par(Par par, const dslam_frame_state& x0, const dslam_frame_state& x1, const double* qIW,
+                       const dslam_preint& pre, const ImuParamsD& ip, double* e, ImuCommon* c, ImuStage* t,
+                       Side side) {
+  TASK(0) t->R0 = q2R(x0.q);
+  TASK(1) {
+    t->R1 = q2R(x1.q);
+    t->Q = q2R(qIW);
+  }
+  TASK(2) {
+    double db[6];
+    for (int i = 0; i < 3; ++i) {
+      db[i] = x0.bg[i] - pre.bg[i];
+      db[3 + i] = x0.ba[i] - pre.ba[i];
+    }
+    double pb[3], dvt[3], dpt[3];
+    for (int i = 0; i < 3; ++i) {
+      double a = 0.0, bv = 0.0, bp = 0.0;
+      for (int k = 0; k < 6; ++k) {
+        a += pre.J[6 * i + k] * db[k];
+        bv += pre.J[6 * (3 + i) + k] * db[k];
+        bp += pre.J[6 * (6 + i) + k] * db[k];
+      }
+      pb[i] = a;
+      dvt[i] = pre.dv[i] + bv;
+      dpt[i] = pre.dp[i] + bp;
+    }
+    t->phib = load3(pb);
+    t->dvt = load3(dvt);
+    t->dpt = load3(dpt);
+    t->Rb = Exp(t->phib);
+    t->Jrb = Jr(t->phib);
+  }
+  DSLAM_SYNC();
+  TASK(0) {
+    M3 R0 = t->R0, Q = t->Q;
+    M3 Rcs = load33(ip.R_CS);
+    V3 tcs = load3(ip.t_CS);
+    V3 g = v3(0.0, 0.0, -ip.gravity);
+    double T = pre.dt;
+    M3 dRt = load33(pre.dR) * t->Rb;
+    M3 S = R0 * Rcs;
+    M3 SdRt = S * dRt;
+    M3 Rh1 = SdRt * tr(Rcs);
+    V3 wt = tr(Rcs) * tcs;
+    V3 v0 = load3(x0.v), r0 = load3(x0.r);
+    V3 yg = T * v0 + (0.5 * T * T) * g;
+    V3 yr = tcs + Rcs * t->dpt - Rcs * (dRt * wt);
+    V3 rh = r0 + R0 * yr + tr(Q) * yg;
+    V3 Sdv = S * t->dvt;
+    V3 QSdv = Q * Sdv;
+    V3 vh = v0 + T * g + QSdv;
+    V3 ea = Log(Rh1 * tr(t->R1));
+    V3 er = rh - load3(x1.r);
+    V3 ev = vh - load3(x1.v);
+    for (int i = 0; i < 3; ++i) {
+      e[i] = er[i];
+      e[3 + i] = ea[i];
+      e[6 + i] = ev[i];
+      e[9 + i] = x0.bg[i] - x1.bg[i];
+      e[12 + i] = x0.ba[i] - x1.ba[i];
+    }
+    t->SdRt = SdRt;
+    t->ea = ea;
+    t->yr = yr;
+    t->yg = yg;
+    t->Sdv = Sdv;
+    t->QSdv = QSdv;
+  }
+  DSLAM_SYNC();
+  M3* m = c->mats;
+  TASK(0) {
+    M3 Jli = JlInv(t->ea);
+    m[IC_JLI] = Jli;
+    m[IC_KAL] = Jli * t->SdRt * t->Jrb;
+    m[IC_JRI] = (-1.0) * tr(Jli);
+    m[IC_JLI_SDRT] = Jli * t->SdRt;
+  }
+  TASK(1) {
+    M3 Rcs = load33(ip.R_CS);
+    V3 wt = tr(Rcs) * load3(ip.t_CS);
+    M3 hwt = hat(wt);
+    M3 Qt = tr(t->Q);
+    m[IC_HAT_R0YR] = (-1.0) * hat(t->R0 * t->yr);
+    m[IC_QT] = pre.dt * Qt;
+    m[IC_S] = t->R0 * Rcs;
+    m[IC_KROT] = t->SdRt * hwt * t->Jrb;
+    m[IC_HAT_YG] = Qt * hat(t->yg);
+    m[IC_Q] = (-1.0) * t->Q;
+    m[IC_HAT_SDV] = hat(t->Sdv);
+    m[IC_QS] = t->Q * m[IC_S];
+    m[IC_HAT_QSDV] = (-1.0) * hat(t->QSdv);
+    m[IC_KROT_NOISE] = t->SdRt * hwt;
+    m[IC_RBT] = tr(t->Rb);
+  }
+  TASK(2) {
+    m[IC_I] = eye3();
+    m[IC_NEG_I] = (-1.0) * eye3();
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        m[IC_JRG](i, j) = pre.J[6 * i + j];
+        m[IC_JRA](i, j) = pre.J[6 * i + 3 + j];
+        m[IC_JVG](i, j) = pre.J[6 * (3 + i) + j];
+        m[IC_JVA](i, j) = pre.J[6 * (3 + i) + 3 + j];
+        m[IC_JPG](i, j) = pre.J[6 * (6 + i) + j];
+        m[IC_JPA](i, j) = pre.J[6 * (6 + i) + 3 + j];
+      }
+    c->T = pre.dt;
+  }
+  TASK(3) side();
+  DSLAM_SYNC();
 }
 
 DX void put_block(double* M, int ld, int r0, int c0, const M3& B) {
@@ -345,43 +493,50 @@ DX void put_block(double* M, int ld, int r0, int c0, const M3& B) {
     for (int j = 0; j < 3; ++j) M[(r0 + i) * ld + c0 + j] = B(i, j);
 }
 
+// Jacobian block table: block b is out[row, col] = A1 A2 + A3 A4 with the
+// operands taken from ImuCommon::mats (the identity pads unused factors, and
+// A3 A4 = 0 when A3 is IC_COUNT).  dst 0: J9 (9x33), dst 1: A9 (9x9).
+struct ImuBlockSpec {
+  signed char dst, row, col, a1, a2, a3, a4;
+};
+
 // Block b (0 <= b < IMU_BLOCKS) of the Jacobian rows J9 (9x33 over
 // [x0 (15), x1 (15), dg (3)]) of the first nine IMU error entries and of the
 // map A9 (9x9) from the preintegration noise (dphi, dv, dp) to them.  J9 and
-// A9 must be zero-filled first; blocks write disjoint entries.
-DX void imu_block(const ImuCommon& c, int b, double* J9, double* A9) {
-  const int L = 33;
-  M3 I3 = eye3();
+// A9 must be zero-filled first; blocks write disjoint entries.  Every block
+// runs the same instructions on different operands, so lanes do not diverge.
+DX ImuBlockSpec imu_block_spec(int b) {
   switch (b) {
-    case 0:  // e_r: dr0 = I, dr1 = -I, da0 = -[R0 y_r]x
-      put_block(J9, L, 0, 0, I3);
-      put_block(J9, L, 0, 15, (-1.0) * I3);
-      put_block(J9, L, 0, 3, (-1.0) * hat(c.R0 * c.yr));
-      break;
-    case 1: put_block(J9, L, 0, 6, c.T * c.Qt); break;                               // e_r / dv0
-    case 2: put_block(J9, L, 0, 9, c.S * c.Jpg + c.Krot * c.JRg); break;             // e_r / dbg0
-    case 3: put_block(J9, L, 0, 12, c.S * c.Jpa + c.Krot * c.JRa); break;            // e_r / dba0
-    case 4: put_block(J9, L, 0, 30, c.Qt * hat(c.yg)); break;                        // e_r / dg
-    case 5: put_block(J9, L, 3, 3, c.Jli); break;                                    // e_a / da0
-    case 6: put_block(J9, L, 3, 9, c.Kal * c.JRg); break;                            // e_a / dbg0
-    case 7: put_block(J9, L, 3, 12, c.Kal * c.JRa); break;                           // e_a / dba0
-    case 8: put_block(J9, L, 3, 18, (-1.0) * c.Jri); break;                          // e_a / da1
-    case 9:  // e_v: dv0 = I, dv1 = -I, da0 = -R_IW [S dv~]x
-      put_block(J9, L, 6, 6, I3);
-      put_block(J9, L, 6, 21, (-1.0) * I3);
-      put_block(J9, L, 6, 3, (-1.0) * (c.Q * hat(c.Sdv)));
-      break;
-    case 10: put_block(J9, L, 6, 9, c.QS * c.Jvg); break;                            // e_v / dbg0
-    case 11: put_block(J9, L, 6, 12, c.QS * c.Jva); break;                           // e_v / dba0
-    case 12: put_block(J9, L, 6, 30, (-1.0) * hat(c.QSdv)); break;                   // e_v / dg
-    case 13: put_block(A9, 9, 0, 0, c.SdRt * hat(c.wt) * c.RbT); break;              // e_r / dphi
-    case 14: put_block(A9, 9, 3, 0, c.Jli * c.SdRt * c.RbT); break;                  // e_a / dphi
-    case 15:
-      put_block(A9, 9, 0, 6, c.S);                                                   // e_r / d(dp)
-      put_block(A9, 9, 6, 3, c.QS);                                                  // e_v / d(dv)
-      break;
-    default: break;
+    case 0: return {0, 0, 0, IC_I, IC_I, IC_COUNT, 0};               // e_r / dr0 = I
+    case 1: return {0, 0, 15, IC_NEG_I, IC_I, IC_COUNT, 0};          // e_r / dr1 = -I
+    case 2: return {0, 0, 3, IC_HAT_R0YR, IC_I, IC_COUNT, 0};        // e_r / da0 = -[R0 y_r]x
+    case 3: return {0, 0, 6, IC_QT, IC_I, IC_COUNT, 0};              // e_r / dv0 = T R_IW^T
+    case 4: return {0, 0, 9, IC_S, IC_JPG, IC_KROT, IC_JRG};         // e_r / dbg0
+    case 5: return {0, 0, 12, IC_S, IC_JPA, IC_KROT, IC_JRA};        // e_r / dba0
+    case 6: return {0, 0, 30, IC_HAT_YG, IC_I, IC_COUNT, 0};         // e_r / dg = R_IW^T [y_g]x
+    case 7: return {0, 3, 3, IC_JLI, IC_I, IC_COUNT, 0};             // e_a / da0 = Jl^-1
+    case 8: return {0, 3, 9, IC_KAL, IC_JRG, IC_COUNT, 0};           // e_a / dbg0
+    case 9: return {0, 3, 12, IC_KAL, IC_JRA, IC_COUNT, 0};          // e_a / dba0
+    case 10: return {0, 3, 18, IC_JRI, IC_I, IC_COUNT, 0};           // e_a / da1 = -Jr^-1
+    case 11: return {0, 6, 6, IC_I, IC_I, IC_COUNT, 0};              // e_v / dv0 = I
+    case 12: return {0, 6, 21, IC_NEG_I, IC_I, IC_COUNT, 0};         // e_v / dv1 = -I
+    case 13: return {0, 6, 3, IC_Q, IC_HAT_SDV, IC_COUNT, 0};        // e_v / da0 = -R_IW [S dv~]x
+    case 14: return {0, 6, 9, IC_QS, IC_JVG, IC_COUNT, 0};           // e_v / dbg0
+    case 15: return {0, 6, 12, IC_QS, IC_JVA, IC_COUNT, 0};          // e_v / dba0
+    case 16: return {0, 6, 30, IC_HAT_QSDV, IC_I, IC_COUNT, 0};      // e_v / dg = -[R_IW S dv~]x
+    case 17: return {1, 0, 0, IC_KROT_NOISE, IC_RBT, IC_COUNT, 0};   // e_r / dphi
+    case 18: return {1, 3, 0, IC_JLI_SDRT, IC_RBT, IC_COUNT, 0};     // e_a / dphi
+    default: return {1, 0, 6, IC_S, IC_I, IC_COUNT, 0};              // e_r / d(dp) (e_v / d(dv) below)
   }
+}
+
+DX void imu_block(const ImuCommon& c, int b, double* J9, double* A9) {
+  const ImuBlockSpec t = imu_block_spec(b);
+  M3 r = c.mats[t.a1] * c.mats[t.a2];
+  if (t.a3 != IC_COUNT) r = r + c.mats[t.a3] * c.mats[t.a4];
+  if (t.dst == 0) put_block(J9, 33, t.row, t.col, r);
+  else put_block(A9, 9, t.row, t.col, r);
+  if (b == IMU_BLOCKS - 1) put_block(A9, 9, 6, 3, c.mats[IC_QS]);  // e_v / d(dv) = R_IW S
 }
 
 // IMU prediction of the current state from x0 (x1 <- x1_hat(x0)).  Serial.

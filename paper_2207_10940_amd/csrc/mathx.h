@@ -50,13 +50,15 @@ DX M3 operator-(const M3& a, const M3& b) { M3 r; for (int i = 0; i < 9; ++i) r.
 DX M3 operator*(double s, const M3& a) { M3 r; for (int i = 0; i < 9; ++i) r.m[i] = s * a.m[i]; return r; }
 DX M3 tr(const M3& a) { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r(i, j) = a(j, i); return r; }
 
-// Rodrigues' formula with a Taylor form near zero.
+// Rodrigues' formula; below 0.1 rad its coefficients come from their Taylor
+// series (exact to double precision there), which avoids sin/cos for the small
+// rotations of a Gauss-Newton step or an IMU sample.
 DX M3 Exp(V3 phi) {
   double t2 = dot(phi, phi), th = sqrt(t2);
   double a, b;
-  if (th < 1e-4) {
-    a = 1.0 - t2 / 6.0 + t2 * t2 / 120.0;
-    b = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
+  if (th < 0.1) {
+    a = 1.0 + t2 * (-1.0 / 6.0 + t2 * (1.0 / 120.0 + t2 * (-1.0 / 5040.0 + t2 * (1.0 / 362880.0))));
+    b = 0.5 + t2 * (-1.0 / 24.0 + t2 * (1.0 / 720.0 + t2 * (-1.0 / 40320.0 + t2 * (1.0 / 3628800.0))));
   } else {
     a = sin(th) / th;
     b = (1.0 - cos(th)) / t2;
@@ -65,12 +67,19 @@ DX M3 Exp(V3 phi) {
   return eye3() + a * K + b * (K * K);
 }
 
-// Inverse of Exp for angles in [0, pi).
+// Inverse of Exp for angles in [0, pi).  With w the skew part (|w| = 2 sin th),
+// Log = (th / (2 sin th)) w; for small angles th / sin th is the series of
+// asin(s)/s in s = |w|/2 (no inverse trigonometry).
 DX V3 Log(const M3& R) {
   double c = 0.5 * (R(0, 0) + R(1, 1) + R(2, 2) - 1.0);
+  V3 w = v3(R(2, 1) - R(1,2), R(0, 2) - R(2, 0), R(1, 0) - R(0, 1));
+  double s2 = 0.25 * dot(w, w);
+  if (c > 0.0 && s2 < 0.0025) {  // th < ~0.05 rad
+    double f = 1.0 + s2 * (1.0 / 6.0 + s2 * (3.0 / 40.0 + s2 * (5.0 / 112.0 + s2 * (35.0 / 1152.0))));
+    return (0.5 * f) * w;
+  }
   c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
   double th = acos(c);
-  V3 w = v3(R(2, 1) - R(1, 2), R(0, 2) - R(2, 0), R(1, 0) - R(0, 1));
   if (th < 1e-5) return (0.5 * (1.0 + th * th / 6.0)) * w;
   if (M_PI - th < 1e-6) {
     int k = 0;
@@ -90,9 +99,9 @@ DX V3 Log(const M3& R) {
 DX M3 Jr(V3 phi) {
   double t2 = dot(phi, phi), th = sqrt(t2);
   double a, b;
-  if (th < 0.05) {
-    a = 0.5 - t2 / 24.0 + t2 * t2 / 720.0;
-    b = 1.0 / 6.0 - t2 / 120.0 + t2 * t2 / 5040.0;
+  if (th < 0.1) {
+    a = 0.5 + t2 * (-1.0 / 24.0 + t2 * (1.0 / 720.0 + t2 * (-1.0 / 40320.0 + t2 * (1.0 / 3628800.0))));
+    b = 1.0 / 6.0 + t2 * (-1.0 / 120.0 + t2 * (1.0 / 5040.0 + t2 * (-1.0 / 362880.0 + t2 * (1.0 / 39916800.0))));
   } else {
     a = (1.0 - cos(th)) / t2;
     b = (th - sin(th)) / (t2 * th);
@@ -105,7 +114,7 @@ DX M3 Jr(V3 phi) {
 DX M3 JlInv(V3 phi) {
   double t2 = dot(phi, phi), th = sqrt(t2);
   double c;
-  if (th < 0.05) c = 1.0 / 12.0 + t2 / 720.0 + t2 * t2 / 30240.0;
+  if (th < 0.1) c = 1.0 / 12.0 + t2 * (1.0 / 720.0 + t2 * (1.0 / 30240.0 + t2 * (1.0 / 1209600.0)));
   else c = 1.0 / t2 - (1.0 + cos(th)) / (2.0 * th * sin(th));
   M3 K = hat(phi);
   return eye3() - 0.5 * K + c * (K * K);
@@ -120,20 +129,23 @@ DX void qmul(const double* p, const double* q, double* r) {
   r[0] = w; r[1] = x; r[2] = y; r[3] = z;
 }
 DX M3 q2R(const double* qin) {
-  double n = sqrt(qin[0] * qin[0] + qin[1] * qin[1] + qin[2] * qin[2] + qin[3] * qin[3]);
-  double w = qin[0] / n, x = qin[1] / n, y = qin[2] / n, z = qin[3] / n;
+  double inv = 1.0 / sqrt(qin[0] * qin[0] + qin[1] * qin[1] + qin[2] * qin[2] + qin[3] * qin[3]);
+  double w = qin[0] * inv, x = qin[1] * inv, y = qin[2] * inv, z = qin[3] * inv;
   M3 R = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
            2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
            2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
   return R;
 }
 DX void qexp(V3 phi, double* q) {
-  double th = norm(phi);
-  if (th < 1e-12) {
-    double s = 1.0 / sqrt(1.0 + 0.25 * th * th);
-    q[0] = s; q[1] = 0.5 * phi.x * s; q[2] = 0.5 * phi.y * s; q[3] = 0.5 * phi.z * s;
+  double t2 = dot(phi, phi);
+  if (t2 < 0.01) {  // th < 0.1: Taylor series of cos(th/2) and sin(th/2)/th
+    double h2 = 0.25 * t2;
+    double co = 1.0 + h2 * (-0.5 + h2 * (1.0 / 24.0 + h2 * (-1.0 / 720.0 + h2 * (1.0 / 40320.0))));
+    double s = 0.5 * (1.0 + h2 * (-1.0 / 6.0 + h2 * (1.0 / 120.0 + h2 * (-1.0 / 5040.0 + h2 * (1.0 / 362880.0)))));
+    q[0] = co; q[1] = s * phi.x; q[2] = s * phi.y; q[3] = s * phi.z;
     return;
   }
+  double th = sqrt(t2);
   double s = sin(0.5 * th) / th;
   q[0] = cos(0.5 * th); q[1] = s * phi.x; q[2] = s * phi.y; q[3] = s * phi.z;
 }

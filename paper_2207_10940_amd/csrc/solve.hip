@@ -38,12 +38,12 @@ __device__ void reduce_partials(const float* partials, int nblocks, double* red 
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   const float* base = partials + 4 * g;
   int b = r;
-  for (; b + 16 * 7 < nblocks; b += 16 * 8) {  // eight independent loads in flight
-    float4 v[8];
+  for (; b + 16 * 15 < nblocks; b += 16 * 16) {  // sixteen independent loads in flight
+    float4 v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const float4*>(base + (size_t)(b + 16 * u) * PARTIAL_STRIDE);
+    for (int u = 0; u < 16; ++u) v[u] = *reinterpret_cast<const float4*>(base + (size_t)(b + 16 * u) * PARTIAL_STRIDE);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       s0 += (double)v[u].x;
       s1 += (double)v[u].y;
       s2 += (double)v[u].z;
@@ -113,8 +113,20 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, co
   __shared__ dslam_frame_state x0, x1;
   __shared__ double qIW[4];
   __shared__ dslam_prior marg;
+  __shared__ dslam_prior prior;
+  __shared__ dslam_preint pre;
   __shared__ int skip;
   Par par{(int)threadIdx.x, SOLVE_THREADS};
+  // stage the prior and the preintegrated measurement in shared memory (one
+  // coalesced pass) so the serial parts of the step never wait on global loads
+  {
+    const double* src = reinterpret_cast<const double*>(&sd->prior);
+    double* dst = reinterpret_cast<double*>(&prior);
+    for (int i = threadIdx.x; i < (int)(sizeof(dslam_prior) / 8); i += SOLVE_THREADS) dst[i] = src[i];
+    src = reinterpret_cast<const double*>(&sd->pre);
+    dst = reinterpret_cast<double*>(&pre);
+    for (int i = threadIdx.x; i < (int)(sizeof(dslam_preint) / 8); i += SOLVE_THREADS) dst[i] = src[i];
+  }
   reduce_partials(partials, a.nblocks, w.L, raw);
   if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
   SERIAL {
@@ -135,7 +147,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, co
   }
   SolveParams sp = a.sp;
   sp.marginalise = a.last;
-  int st = solve_step(par, &w, raw, sp, &sd->pre, &sd->prior, &x0, &x1, qIW, &marg);
+  int st = solve_step(par, &w, raw, sp, &pre, &prior, &x0, &x1, qIW, &marg);
   SERIAL {
     if (st != DSLAM_OK) {
       sd->status = st;
@@ -157,17 +169,23 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, co
   }
   if (a.last) {
     DSLAM_SYNC();
+    const bool ok = st == DSLAM_OK;
+    if (ok && sp.mode != DSLAM_MODE_RGBD) {  // publish the marginal prior (parallel copy)
+      const double* src = reinterpret_cast<const double*>(&marg);
+      double* d1 = reinterpret_cast<double*>(&sd->prior);
+      double* d2 = reinterpret_cast<double*>(&sd->result.prior);
+      for (int i = threadIdx.x; i < (int)(sizeof(dslam_prior) / 8); i += SOLVE_THREADS) {
+        d1[i] = src[i];
+        d2[i] = src[i];
+      }
+    }
     SERIAL {
       dslam_track_result& r = sd->result;
       r.status = sd->status;
       r.x0 = x0;
       r.x1 = x1;
       for (int i = 0; i < 4; ++i) r.q_IW[i] = qIW[i];
-      if (sd->status == DSLAM_OK) {
-        if (sp.mode != DSLAM_MODE_RGBD) {
-          sd->prior = marg;
-          r.prior = marg;
-        }
+      if (ok) {
         // the current state becomes the previous one of the next frame
         sd->x0 = x1;
         sd->frame_index += 1;

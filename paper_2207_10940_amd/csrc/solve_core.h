@@ -46,6 +46,7 @@ struct SolveWork {
   double prior_d[18];
   double cost[4];
   ImuCommon ic;
+  ImuStage is;
   int status;
 };
 
@@ -253,6 +254,8 @@ DX int spd_solve(Par par, SolveWork* w, const double* H, const double* b, int n,
   }
   if (cholesky(par, w->L, n, NZ, 1, &w->status)) return 1;
   chol_back(par, w->L, n, NZ, w->L + n * NZ, dz);
+  for (int i = 0; i < n; ++i)
+    if (!(dz[i] == dz[i]) || !(fabs(dz[i]) < 1e30)) return 1;
   if (schur) {
     for (int i = 0; i < 15; ++i)
       for (int j = 0; j < 15; ++j) w->L[i * NZ + j] = H[i * NZ + j];
@@ -272,10 +275,6 @@ DX int spd_solve(Par par, SolveWork* w, const double* H, const double* b, int n,
 #endif
 }
 
-// Independent serial tasks run on the first lane of different wavefronts
-// (concurrently on the device, one after the other on the host).
-#define TASK(t) if (par.lane == (((t) * 64 < par.nl) ? (t) * 64 : 0))
-
 // One Gauss-Newton step.  raw: the 58 sums of the residual pass (ICP then RGB),
 // taken at (x0, x1).  Updates x0, x1, qIW in place on success, writes the
 // marginal prior if sp.marginalise.  Returns a dslam_status.
@@ -285,8 +284,8 @@ DX int solve_step(Par par, SolveWork* w, const double* raw, const SolveParams& s
   const bool full = sp.mode != DSLAM_MODE_RGBD;
   const int n = full ? NZ : 6;
   const bool marg = full && sp.marginalise && marg_out != nullptr;
-  // ---- independent serial set-up
-  TASK(0) {
+  // ---- independent serial set-up, spread over the first lanes of the wavefronts
+  TASK(3) {
     unpack_term(raw, w->Hm[0], w->gm[0]);
     unpack_term(raw + 29, w->Hm[1], w->gm[1]);
     w->cost[0] = raw[27];
@@ -296,14 +295,13 @@ DX int solve_step(Par par, SolveWork* w, const double* raw, const SolveParams& s
     build_lift(sp.R_WM, *x0, *x1, w->Li, w->Lr);
   }
   if (full) {
-    TASK(1) imu_common(*x0, *x1, qIW, *pre, sp.imu, w->e, &w->ic);
-    TASK(2) {
+    imu_common_par(par, *x0, *x1, qIW, *pre, sp.imu, w->e, &w->ic, &w->is, [&]() {
       state_boxminus(*x0, prior->xbar, w->prior_d);
       V3 dg = qboxminus(qIW, prior->q_IW_bar);
       w->prior_d[15] = dg.x;
       w->prior_d[16] = dg.y;
       w->prior_d[17] = dg.z;
-    }
+    });
   }
   PFOR(i, NZ * NZ) w->H[i] = 0.0;
   PFOR(i, NZ) w->b[i] = 0.0;
@@ -449,14 +447,6 @@ DX int solve_step(Par par, SolveWork* w, const double* raw, const SolveParams& s
     DSLAM_SYNC();
     return DSLAM_ERR_SINGULAR;
   }
-  DSLAM_SYNC();
-  SERIAL {
-    bool finite = true;
-    for (int i = 0; i < n; ++i) finite = finite && (w->dz[i] == w->dz[i]) && fabs(w->dz[i]) < 1e30;
-    w->status = finite ? DSLAM_OK : DSLAM_ERR_SINGULAR;
-  }
-  DSLAM_SYNC();
-  if (w->status != DSLAM_OK) return w->status;
   // ---- box-plus updates (Section IV-D)
   if (full) {
     TASK(0) state_boxplus(x0, w->dz);

@@ -2,8 +2,9 @@
 // wavefront holds the augmented system one row per lane, in registers, and
 // runs Gauss-Jordan elimination without pivoting (positive pivots exist for
 // every SPD matrix; a non-positive pivot reports the system as singular).
-// The pivot row of each step is broadcast with v_readlane, so a step costs
-// two lane reads and one FMA per remaining column and no LDS round trip.
+// Symmetry lets one shared-memory store per lane publish each pivot row (see
+// gauss_jordan), so a step costs one store, a few wide broadcast loads and one
+// FMA per remaining column.
 //
 // Eliminating the first 15 pivot columns of [H | b] leaves, in rows 15..32,
 // exactly the Schur complement [H* | S(b)] of the previous state's block
@@ -21,12 +22,20 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 }
 
 // Gauss-Jordan on the rows held by the lanes of one wavefront: lane i < NSTEP
-// holds R[0..NC) = row i of [A | B].  After the loop every pivot column k <
-// NSTEP is zero in every row but row k, whose entries are left unscaled.  If
-// cap != nullptr, rows CAP..NSTEP-1, columns CAP..NC-1 are stored there just
-// before step CAP (row-major, NC - CAP per row).
+// holds R[0..NC) = row i of [A | B] with A (NSTEP x NSTEP) symmetric positive
+// definite.  After the loop every pivot column k < NSTEP is zero in every row
+// but row k, whose entries are left unscaled.  If cap != nullptr, rows
+// CAP..NSTEP-1, columns CAP..NC-1 are stored there just before step CAP
+// (row-major, NC - CAP per row).
+//
+// The trailing block of a symmetric matrix stays symmetric under elimination,
+// so the pivot row's entries A[k][j], j > k, equal column k's entries A[j][k],
+// which lane j holds: one shared-memory store per lane publishes the whole
+// pivot row, and every lane reads it back with wide broadcast loads.  The
+// pivot row's right-hand-side entries are published by lane k.
 template <int NC, int NSTEP, int CAP>
-__device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* cap) {
+__device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* col, double* cap) {
+  constexpr int NR = NC - NSTEP;  // right-hand-side columns
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < NSTEP; ++k) {
@@ -34,13 +43,26 @@ __device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* 
 #pragma unroll
       for (int j = CAP; j < NC; ++j) cap[(lane - CAP) * (NC - CAP) + (j - CAP)] = R[j];
     }
+    // two column buffers alternate, so publishing step k+1's column never
+    // waits for step k's readers; the loop body has no branch, which lets the
+    // compiler start step k+1's pivot while step k's updates are in flight
+    double* c = col + (k & 1) * 64;
+    c[lane] = R[k];
     const double p = readlane_d(R[k], k);
-    ok = ok && (p > 0.0) && (p < 1e300);
-    const double inv = 1.0 / p;
-    const double m = (lane == k) ? 0.0 : R[k] * inv;
+    double rhs[NR > 0 ? NR : 1];
 #pragma unroll
-    for (int j = k + 1; j < NC; ++j) R[j] = fma(-m, readlane_d(R[j], k), R[j]);
-    if (lane != k) R[k] = 0.0;
+    for (int j = 0; j < NR; ++j) rhs[j] = readlane_d(R[NSTEP + j], k);
+    ok = ok && (p > 0.0) && (p < 1e300);
+    // reciprocal: hardware estimate refined by two Newton steps (full precision)
+    double inv = __builtin_amdgcn_rcp(p);
+    inv = fma(inv, fma(-p, inv, 1.0), inv);
+    inv = fma(inv, fma(-p, inv, 1.0), inv);
+    const double m = (lane == k) ? 0.0 : R[k] * inv;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int j = k + 1; j < NSTEP; ++j) R[j] = fma(-m, c[j], R[j]);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) R[NSTEP + j] = fma(-m, rhs[j], R[NSTEP + j]);
   }
   return ok;
 }
@@ -57,6 +79,7 @@ __device__ __forceinline__ double own_diag(const double (&R)[NC], int lane) {
 // block; wave 0 computes.  Returns 0, or 1 if S9 is not SPD.
 __device__ int spd_inverse9_dev(const double* S9, double* W9) {
   __shared__ int bad;
+  __shared__ double col[128];
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     double R[18];
@@ -65,7 +88,7 @@ __device__ int spd_inverse9_dev(const double* S9, double* W9) {
       R[j] = lane < 9 ? S9[9 * lane + j] : (lane == j ? 1.0 : 0.0);
       R[9 + j] = (lane == j) ? 1.0 : 0.0;
     }
-    bool ok = gauss_jordan<18, 9, -1>(R, lane, nullptr);
+    bool ok = gauss_jordan<18, 9, -1>(R, lane, col, nullptr);
     const double d = own_diag(R, lane);
     if (lane < 9) {
 #pragma unroll
@@ -78,15 +101,18 @@ __device__ int spd_inverse9_dev(const double* S9, double* W9) {
 }
 
 template <int N, int CAP>
-__device__ __forceinline__ bool solve_rows(const double* H, const double* b, int lane, double* dz, double* cap) {
+__device__ __forceinline__ bool solve_rows(const double* H, const double* b, int lane, double* dz, double* col,
+                                           double* cap) {
   double R[N + 1];
 #pragma unroll
   for (int j = 0; j < N; ++j) R[j] = lane < N ? H[lane * 33 + j] : (lane == j ? 1.0 : 0.0);
   R[N] = lane < N ? b[lane] : 0.0;
-  bool ok = gauss_jordan<N + 1, N, CAP>(R, lane, cap);
+  bool ok = gauss_jordan<N + 1, N, CAP>(R, lane, col, cap);
   const double d = own_diag(R, lane);
-  if (lane < N) dz[lane] = R[N] / d;
-  return ok;
+  const double x = R[N] / d;
+  const bool finite = lane >= N || (x == x && fabs(x) < 1e30);
+  if (lane < N) dz[lane] = x;
+  return ok && !__any(!finite);
 }
 
 // dz = H^-1 b (H leading dimension 33, shared memory); n is 33 or 6.  With
@@ -94,11 +120,12 @@ __device__ __forceinline__ bool solve_rows(const double* H, const double* b, int
 // leading 15x15 block of [H | b].  Called by every thread; wave 0 computes.
 __device__ int spd_solve_dev(const double* H, const double* b, int n, double* dz, double* schur) {
   __shared__ int bad;
+  __shared__ double col[128];
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     bool ok = false;
-    if (n == 33) ok = solve_rows<33, 15>(H, b, lane, dz, schur);
-    else if (n == 6) ok = solve_rows<6, -1>(H, b, lane, dz, nullptr);
+    if (n == 33) ok = solve_rows<33, 15>(H, b, lane, dz, col, schur);
+    else if (n == 6) ok = solve_rows<6, -1>(H, b, lane, dz, col, nullptr);
     if (lane == 0) bad = ok ? 0 : 1;
   }
   __syncthreads();
