@@ -208,10 +208,57 @@ __device__ __forceinline__ void pixel(const ResidualArgs& a, const float* T, int
   if (a.mask) a.mask[p] = bits;
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
+// ---- wavefront reduction ---------------------------------------------------
+// Sums N <= 64 per-lane values over the 64 lanes of a wavefront and returns
+// them transposed: lane l receives the total of value l (0 for l >= N).  Six
+// exchange stages each pair up the live values and halve their number:
+//   stage 1: lanes l, l^32 through v_permlane32_swap (value i, i+32 -> one register)
+//   stage 2: lanes l, l^16 through v_permlane16_swap
+//   stages 3-6: DPP row_mirror, row_half_mirror, quad_perm [3,2,1,0] and
+//   [1,0,3,2]; each partner differs from the lane in bit 3, 2, 1, 0 (and
+//   lower bits), and the lane keeps the value that its own bit selects.
+// After stage k a register holds, in lane l, the value whose index agrees with
+// l in the bits already exchanged; the pairing masks {32, 16, 15, 7, 3, 1}
+// span all 64 lanes, so every total covers each lane once.  About 140 VALU
+// instructions with no LDS round trip; the summation order is fixed.
+__device__ __forceinline__ float f_of(unsigned u) { return __builtin_bit_cast(float, u); }
+__device__ __forceinline__ unsigned u_of(float f) { return __builtin_bit_cast(unsigned, f); }
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+
+template <int H, int CTRL>
+__device__ __forceinline__ void in_row_stage(const float* in, float* out, bool hi) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  for (int i = 0; i < H; ++i) {
+    const float keep = hi ? in[i + H] : in[i];
+    const float send = hi ? in[i] : in[i + H];
+    out[i] = keep + dpp<CTRL>(send);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ float wave_transpose_sum(const float (&v)[N], int lane) {
+  static_assert(N > 32 && N <= 64, "needs 33..64 values");
+  float s[32], t[16], u[8], w[4], x[2], y[1];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const float b = (i + 32 < N) ? v[i + 32] : 0.0f;
+    const auto r = __builtin_amdgcn_permlane32_swap(u_of(v[i]), u_of(b), false, false);
+    s[i] = f_of(r[0]) + f_of(r[1]);  // lanes 0-31: value i, lanes 32-63: value i+32
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(u_of(s[i]), u_of(s[i + 16]), false, false);
+    t[i] = f_of(r[0]) + f_of(r[1]);  // value i + 16 * (lane / 16)
+  }
+  in_row_stage<8, 0x140>(t, u, lane & 8);  // row_mirror
+  in_row_stage<4, 0x141>(u, w, lane & 4);  // row_half_mirror
+  in_row_stage<2, 0x1B>(w, x, lane & 2);   // quad_perm [3,2,1,0]
+  in_row_stage<1, 0xB1>(x, y, lane & 1);   // quad_perm [1,0,3,2]
+  return y[0];
 }
 
 template <int PPT>
@@ -230,11 +277,8 @@ __global__ __launch_bounds__(RES_THREADS) void residual_kernel(ResidualArgs a) {
     if (p < a.npix) pixel(a, T, p, acc);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < 58; ++k) {
-    float s = wave_sum(acc[k]);
-    if (lane == 0) red[wave][k] = s;
-  }
+  const float tot = wave_transpose_sum(acc, lane);
+  if (lane < 58) red[wave][lane] = tot;
   __syncthreads();
   if (threadIdx.x < 58) {
     float s = red[0][threadIdx.x];
