@@ -25,6 +25,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "tracked frames/s + residual-pass GB/s at 640x480; p50/p99 track latency"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20  # calibration copy for the HBM byte counters
+# HBM bytes per level-0 residual launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by the
+# reading of a 256 MiB copy (fetch x1.99987, write x1.0); valid for the kernel source with this hash.
+TRAFFIC_BYTES_LEVEL0 = (8607.8 * 262144 / 131087.7 + 150.0) * 1024
+TRAFFIC_SOURCE_SHA256 = "66d802343b8670f1"
 REF_BYTES_PER_PIXEL = 52  # V1 12 + I1 4 + V0 12 + N0 12 + I0 4 + G0 8 per pixel-iteration (N1 unread: no normal gate)
 
 
@@ -48,6 +53,14 @@ def frame_inputs(seq, j):
     a, b = synth.configs.imu_window(seq["imu"]["t"], t0, t1)
     imu = {k: v[a:b] for k, v in seq["imu"].items()}
     return md, mi, T, seq["depth"][j], seq["intensity"][j], imu, t0, t1
+
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2207_10940_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()
+    return TRAFFIC_BYTES_LEVEL0 if h.startswith(TRAFFIC_SOURCE_SHA256) else None
 
 
 def run_gpu(args):
@@ -118,11 +131,43 @@ def run_gpu(args):
                        "frames": int(len(lat)), "kind": "host submit to result, one frame at a time"},
         "pose_err_final_m": pos_err,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "residual_kernel<2> (level 0, 640x480)", "kernel_us": k_ms * 1e3,
                      "bytes_per_launch": REF_BYTES_PER_PIXEL * px},
         "seq": seq,
     }
+
+
+def run_counters(args):
+    """Hardware-counter run: the level-0 residual pass on a tracked sequence frame, then a plain
+    device copy of known size whose FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes.
+    Meant to be run under rocprofv3 --pmc; prints one JSON line describing what ran."""
+    import torch
+
+    import paper_2207_10940_amd as P
+    W, H = 640, 480
+    seq = make_sequence(4, W, H, "cuda")
+    ctx = P.Context(0)
+    tp = P.track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32")
+    sess = P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], seq["prior"])
+    stream = torch.cuda.current_stream()
+    for j in range(1, 4):
+        md, mi, T, d, i, imu, t0, t1 = frame_inputs(seq, j)
+        sess.set_model(md.contiguous(), mi.contiguous(), T, stream)
+        sess.track_frame(d.contiguous(), i.contiguous(), imu, t0, t1, stream)
+    torch.cuda.synchronize()
+    sess.profile_residual(0, args.kernel_reps, stream)
+    torch.cuda.synchronize()
+    n = COPY_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    sess.close()
+    ctx.close()
+    print(json.dumps({"counters_run": True, "residual_reps": args.kernel_reps, "residual_pixels": W * H,
+                      "copy_bytes_each_way": COPY_BYTES, "copy_reps": 3}), flush=True)
 
 
 def cpu_baseline(seq, n_frames):
@@ -155,11 +200,16 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-frames", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="only run the level-0 residual pass and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the tracking step shards by session, one process per GPU, and this "
               "build runs and reports a single MI355X only", file=sys.stderr)
         sys.exit(2)
+    if args.counters:
+        run_counters(args)
+        return
     g = run_gpu(args)
     cpu = None
     if not args.no_cpu_baseline and args.cpu_frames > 0:
