@@ -168,6 +168,28 @@ typedef struct {
 
 typedef struct dslam_context dslam_context;
 typedef struct dslam_session dslam_session;
+typedef struct dslam_batch dslam_batch;
+
+/* Maximum sessions in one batched step and distinct resolutions within it. */
+#define DSLAM_MAX_BATCH 256
+#define DSLAM_MAX_BATCH_RESOLUTIONS 16
+
+/* One session's inputs for a batched step: the new frame and the model view
+ * predicted for it (device images, height x width, row pitch in elements),
+ * the model-view pose T_WM (4x4 row-major, host) and the frame's IMU samples
+ * (host, same rules as dslam_track_frame; ignored in DSLAM_MODE_RGBD). */
+typedef struct {
+  const float* depth;
+  const uint8_t* intensity;
+  int32_t pitch;
+  const float* model_depth;
+  const uint8_t* model_intensity;
+  int32_t model_pitch;
+  double T_WM[16];
+  const dslam_imu_sample* imu;
+  int32_t n_imu;
+  double t0, t1;
+} dslam_frame_input;
 
 /* Human-readable name of a status code (static string). */
 const char* dslam_status_string(dslam_status s);
@@ -261,6 +283,31 @@ dslam_status dslam_profile_residual(dslam_session* s, int32_t level, int32_t rep
 
 /* Copy one channel of one pyramid level to host memory (width_l*height_l floats). Synchronous. */
 dslam_status dslam_copy_pyramid(dslam_session* s, int32_t which, int32_t level, int32_t channel, float* host_out);
+
+/* Batched tracking (serving form): one step tracks one frame of each of n
+ * sessions with shared launches, so that many sessions fill the GPU.  Every
+ * session's arithmetic is the same as in dslam_track_frame (same pixel
+ * partition, order of sums and solve), so its result does not depend on the
+ * other sessions of the batch.
+ *
+ * dslam_batch_create allocates the staging memory for up to max_sessions
+ * (<= DSLAM_MAX_BATCH) sessions (device and pinned host; counted against the
+ * context's budget, NO_CAPACITY otherwise). */
+dslam_status dslam_batch_create(dslam_context* ctx, int32_t max_sessions, dslam_batch** out);
+/* Wait for the batch's work and free it. */
+dslam_status dslam_batch_destroy(dslam_batch* b);
+/* Enqueue one tracking step for sessions[0..n) with frames[0..n) on `stream`
+ * (Section IV, as dslam_track_frame, plus both pyramids of each session built
+ * from frames[i]).  The sessions must belong to the batch's context, be
+ * distinct, share the pyramid depth and iteration counts, and use at most
+ * DSLAM_MAX_BATCH_RESOLUTIONS distinct resolutions.  Waits first for the
+ * batch's previous step (its staging memory is reused).  The caller keeps the
+ * device images alive until the step completes.  Asynchronous; errors:
+ * INVALID (arguments), DEVICE. */
+dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* sessions,
+                               const dslam_frame_input* frames, void* stream);
+/* Wait for the batch's last step and copy its n results, in call order. */
+dslam_status dslam_batch_results(dslam_batch* b, dslam_track_result* out);
 
 /* Checkpoint / restore the session's estimator state (x0, q_IW, prior and
  * frame counter) through host memory; the pyramids are not part of it. */

@@ -162,6 +162,13 @@ def solve_step(raw, T_WM, pre, ip, tp, prior, x0, x1, q_IW, marginalise=False):
     return state_dict(a), state_dict(b), q, dz, (prior_dict(m) if m is not None else None)
 
 
+def result_dict(r: _abi.TrackResult) -> dict:
+    return {"status": r.status, "frame_index": r.frame_index, "x0": state_dict(r.x0), "x1": state_dict(r.x1),
+            "q_IW": np.array(r.q_IW[:]), "cost_icp": r.cost_icp, "cost_rgb": r.cost_rgb, "cost_imu": r.cost_imu,
+            "n_icp": list(r.n_icp), "n_rgb": list(r.n_rgb), "last_step_norm": r.last_step_norm,
+            "prior": prior_dict(r.prior)}
+
+
 # --- device objects ----------------------------------------------------------------
 
 class Context:
@@ -237,10 +244,7 @@ class Session:
     def result(self) -> dict:
         r = _abi.TrackResult()
         _check(lib().dslam_session_result(self.handle, C.byref(r)), "dslam_session_result")
-        return {"status": r.status, "frame_index": r.frame_index, "x0": state_dict(r.x0), "x1": state_dict(r.x1),
-                "q_IW": np.array(r.q_IW[:]), "cost_icp": r.cost_icp, "cost_rgb": r.cost_rgb, "cost_imu": r.cost_imu,
-                "n_icp": list(r.n_icp), "n_rgb": list(r.n_rgb), "last_step_norm": r.last_step_norm,
-                "prior": prior_dict(r.prior)}
+        return result_dict(r)
 
     def linearize(self, level, Ra, ta, Rb, tb, x0, x1, mask=None, stream=None) -> dict:
         f = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float32).ravel())  # noqa: E731
@@ -282,3 +286,55 @@ class Session:
         ps = prior_struct(prior) if prior is not None else None
         _check(lib().dslam_session_set_state(self.handle, C.byref(xs), qp, C.byref(ps) if ps is not None else None,
                                              int(frame_index)), "dslam_session_set_state")
+
+
+class Batch:
+    """Staging for batched tracking steps over many sessions (dslam_batch_*)."""
+
+    def __init__(self, ctx: Context, max_sessions: int):
+        h = C.c_void_p()
+        _check(lib().dslam_batch_create(ctx.handle, int(max_sessions), C.byref(h)), "dslam_batch_create")
+        self.handle = h
+        self.max_sessions = int(max_sessions)
+        self._keep = None
+        self._n = 0
+
+    def close(self):
+        if self.handle:
+            _check(lib().dslam_batch_destroy(self.handle), "dslam_batch_destroy")
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def track(self, sessions, frames, stream=None):
+        """Enqueue one step.  frames[i] = dict(depth, intensity, model_depth, model_intensity, T_WM,
+        imu (dict t/gyro/acc or None), t0, t1) for sessions[i]; device images contiguous."""
+        n = len(sessions)
+        handles = (C.c_void_p * n)(*[s.handle for s in sessions])
+        inputs = (_abi.FrameInput * n)()
+        keep = []
+        for i, f in enumerate(frames):
+            d, im, md, mi = f["depth"], f["intensity"], f["model_depth"], f["model_intensity"]
+            for t in (d, im, md, mi):
+                assert t.is_cuda and t.is_contiguous()
+            fi = inputs[i]
+            fi.depth, fi.intensity, fi.pitch = d.data_ptr(), im.data_ptr(), int(d.shape[1])
+            fi.model_depth, fi.model_intensity, fi.model_pitch = md.data_ptr(), mi.data_ptr(), int(md.shape[1])
+            fi.T_WM[:] = [float(v) for v in np.asarray(f["T_WM"], dtype=np.float64).ravel()]
+            if f.get("imu") is not None:
+                arr, cnt = imu_samples(f["imu"]["t"], f["imu"]["gyro"], f["imu"]["acc"])
+                keep.append(arr)
+                fi.imu, fi.n_imu = arr, cnt
+            fi.t0, fi.t1 = float(f.get("t0", 0.0)), float(f.get("t1", 0.0))
+        _check(lib().dslam_batch_track(self.handle, n, handles, inputs, _stream_ptr(stream)), "dslam_batch_track")
+        self._keep = (keep, frames)
+        self._n = n
+
+    def results(self) -> list:
+        out = (_abi.TrackResult * self._n)()
+        _check(lib().dslam_batch_results(self.handle, out), "dslam_batch_results")
+        return [result_dict(out[i]) for i in range(self._n)]

@@ -62,6 +62,16 @@ class LinearSystem(C.Structure):
                 ("cost_rgb", C.c_double), ("n_rgb", C.c_int64), ("raw", C.c_double * 58)]
 
 
+class FrameInput(C.Structure):
+    _fields_ = [("depth", C.c_void_p), ("intensity", C.c_void_p), ("pitch", C.c_int32),
+                ("model_depth", C.c_void_p), ("model_intensity", C.c_void_p), ("model_pitch", C.c_int32),
+                ("T_WM", C.c_double * 16), ("imu", C.POINTER(ImuSample)), ("n_imu", C.c_int32),
+                ("t0", C.c_double), ("t1", C.c_double)]
+
+
+MAX_BATCH = 256
+MAX_BATCH_RESOLUTIONS = 16
+
 P = C.POINTER
 vp = C.c_void_p
 dp = P(C.c_double)
@@ -90,6 +100,10 @@ SIGNATURES = {
     "dslam_profile_residual": (C.c_int, [vp, C.c_int32, C.c_int32, vp]),
     "dslam_session_get_state": (C.c_int, [vp, P(FrameState), dp, P(Prior), P(C.c_int32)]),
     "dslam_session_set_state": (C.c_int, [vp, P(FrameState), dp, P(Prior), C.c_int32]),
+    "dslam_batch_create": (C.c_int, [vp, C.c_int32, P(vp)]),
+    "dslam_batch_destroy": (C.c_int, [vp]),
+    "dslam_batch_track": (C.c_int, [vp, C.c_int32, P(vp), P(FrameInput), vp]),
+    "dslam_batch_results": (C.c_int, [vp, P(TrackResult)]),
 }
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdslam.so")

@@ -25,10 +25,16 @@ COMMON = [
 # correctly rounded division and square root.
 EXACT_FP32 = ["-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt"]
 
+# The float64 solve and IMU code contracts nothing implicitly either: every
+# fused multiply-add it uses is written out, so the same source gives the same
+# bits in every kernel that inlines it (single-session and batched launches)
+# and on the host.
+EXACT_FP64 = ["-ffp-contract=off"]
+
 SOURCES = {
     "kernels.hip": EXACT_FP32,
-    "solve.hip": [],
-    "dslam.hip": [],
+    "solve.hip": EXACT_FP64,
+    "dslam.hip": EXACT_FP64,
 }
 
 

@@ -46,4 +46,40 @@ struct ResidualArgs {
 
 enum { RES_THREADS = 256, PARTIAL_STRIDE = 64, SOLVE_THREADS = 256 };
 
+// ---- batched steps: several sessions share every launch ---------------------
+enum { MAX_BATCH = 256, MAX_CLASSES = 16, PYR_TILE_W = 64, PYR_TILE_H = 4 };
+
+// One session's visual inputs for a batched step (device copy of host staging).
+struct SlotVis {
+  ResidualArgs res[DSLAM_MAX_LEVELS];  // xf = the session's transforms, partials = its buffer
+  LevelPtrs cur[DSLAM_MAX_LEVELS], model[DSLAM_MAX_LEVELS];
+  const float* depth;                  // current frame, device
+  const uint8_t* inten;
+  const float* mdepth;                 // model view, device
+  const uint8_t* minten;
+  int32_t pitch, mpitch;
+  int32_t ppt[DSLAM_MAX_LEVELS];       // pixels per thread of each level's residual pass
+};
+
+// Work split of one batched launch.  The slots are ordered so that slots with
+// the same number of workgroups are contiguous; class c covers workgroups
+// [first_block[c], first_block[c+1]) and slots first_slot[c] onwards, each
+// slot taking blocks_per_slot[c] consecutive workgroups.
+struct BatchGrid {
+  int32_t nclass;
+  int32_t first_block[MAX_CLASSES + 1];
+  int32_t blocks_per_slot[MAX_CLASSES];
+  int32_t first_slot[MAX_CLASSES];
+};
+
+// Workgroup -> (slot, workgroup within the slot); uniform across the workgroup.
+__device__ __forceinline__ void batch_locate(const BatchGrid& g, int blk, int* slot, int* b) {
+  int c = 0;
+  for (int k = 1; k < g.nclass; ++k) c = blk >= g.first_block[k] ? k : c;
+  const int off = blk - g.first_block[c];
+  const int q = off / g.blocks_per_slot[c];
+  *slot = g.first_slot[c] + q;
+  *b = off - q * g.blocks_per_slot[c];
+}
+
 }  // namespace dslam

@@ -3,6 +3,7 @@
 // float64 entry points (preintegration and Gauss-Newton step).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -11,38 +12,8 @@
 #include <new>
 #include <vector>
 
-#include "device.h"
-#include "solve_core.h"
+#include "step.h"
 
-namespace dslam {
-// kernels.hip
-hipError_t launch_pyramid_level0(const float* depth, const uint8_t* inten, int pitch, const LevelPtrs& L,
-                                 int with_grad, hipStream_t st);
-hipError_t launch_pyramid_down(const LevelPtrs& parent, const LevelPtrs& L, int with_grad, hipStream_t st);
-int residual_blocks(int npix, int ppt);
-hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st);
-// solve.hip
-struct ImuBatch {
-  int32_t n;
-  double t0, t1;
-  dslam_imu_sample s[DSLAM_MAX_IMU_SAMPLES];
-};
-struct FrameArgs {
-  ImuParamsD imu;
-  double sigma_g, sigma_a;
-  double R_WM[9], t_WM[3];
-  int32_t mode;
-};
-struct SolveArgs {
-  SolveParams sp;
-  int32_t level;
-  int32_t last;
-  int32_t nblocks;
-};
-hipError_t launch_frame_init(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, hipStream_t st);
-hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& a, hipStream_t st);
-hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st);
-}  // namespace dslam
 
 using namespace dslam;
 
@@ -195,7 +166,65 @@ SolveParams solve_params(dslam_session* s) {
   return sp;
 }
 
+// Validates the frame's IMU samples and packs them for the device.
+dslam_status pack_imu(const dslam_session* s, const dslam_imu_sample* imu, int32_t n_imu, double t0, double t1,
+                      ImuBatch* batch) {
+  std::memset(batch, 0, sizeof(*batch));
+  if (s->tp.mode == DSLAM_MODE_RGBD) return DSLAM_OK;
+  if (!imu || n_imu < 1 || n_imu > DSLAM_MAX_IMU_SAMPLES || !(t1 > t0)) return DSLAM_ERR_INVALID;
+  if (!(imu[0].t <= t0)) return DSLAM_ERR_INVALID;
+  for (int k = 1; k < n_imu; ++k)
+    if (!(imu[k].t > imu[k - 1].t)) return DSLAM_ERR_INVALID;
+  batch->n = n_imu;
+  batch->t0 = t0;
+  batch->t1 = t1;
+  for (int k = 0; k < n_imu; ++k) batch->s[k] = imu[k];
+  return DSLAM_OK;
+}
+
+FrameArgs frame_args(dslam_session* s, const SolveParams& sp) {
+  FrameArgs fa;
+  fa.imu = imu_params_d(s->ip);
+  fa.sigma_g = s->ip.sigma_g;
+  fa.sigma_a = s->ip.sigma_a;
+  for (int i = 0; i < 9; ++i) fa.R_WM[i] = sp.R_WM[i];
+  for (int i = 0; i < 3; ++i) fa.t_WM[i] = sp.t_WM[i];
+  fa.mode = s->tp.mode;
+  return fa;
+}
+
+int last_level_of(const dslam_track_params& tp) {
+  int last = -1;
+  for (int l = tp.levels - 1; l >= 0; --l)
+    if (tp.iters[l] > 0) last = l;
+  return last;
+}
+
+bool finite16(const double* T) {
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(T[i])) return false;
+  return true;
+}
+
 }  // namespace
+
+struct dslam_batch {
+  dslam_context* ctx;
+  int max_n;
+  uint64_t bytes;
+  void* dev;                   // SlotVis[max_n] | SlotSolve[max_n] | dslam_track_result[max_n]
+  SlotVis* d_vis;
+  SlotSolve* d_solve;
+  dslam_track_result* d_res;
+  void* host;                  // pinned mirror of the same layout
+  SlotVis* h_vis;
+  SlotSolve* h_solve;
+  dslam_track_result* h_res;
+  hipEvent_t done;
+  bool pending;
+  int n;
+  int order[MAX_BATCH];        // slot -> caller index
+};
 
 extern "C" {
 
@@ -399,37 +428,20 @@ dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const u
                                int32_t pitch_elems, const dslam_imu_sample* imu, int32_t n_imu, double t0,
                                double t1, void* stream) {
   if (!s || !depth_dev || !intensity_dev || pitch_elems < s->cam.width) return DSLAM_ERR_INVALID;
-  const bool inertial = s->tp.mode != DSLAM_MODE_RGBD;
   ImuBatch batch;
-  std::memset(&batch, 0, sizeof(batch));
-  if (inertial) {
-    if (!imu || n_imu < 1 || n_imu > DSLAM_MAX_IMU_SAMPLES || !(t1 > t0)) return DSLAM_ERR_INVALID;
-    if (!(imu[0].t <= t0)) return DSLAM_ERR_INVALID;
-    for (int k = 1; k < n_imu; ++k)
-      if (!(imu[k].t > imu[k - 1].t)) return DSLAM_ERR_INVALID;
-    batch.n = n_imu;
-    batch.t0 = t0;
-    batch.t1 = t1;
-    for (int k = 0; k < n_imu; ++k) batch.s[k] = imu[k];
-  }
+  dslam_status sti = pack_imu(s, imu, n_imu, t0, t1, &batch);
+  if (sti != DSLAM_OK) return sti;
+  if (last_level_of(s->tp) < 0) return DSLAM_ERR_INVALID;
   if (!s->have_model) return DSLAM_ERR_NOT_READY;
   dslam_status st0 = dslam_build_pyramid(s, DSLAM_PYR_CURRENT, depth_dev, intensity_dev, pitch_elems, nullptr, stream);
   if (st0 != DSLAM_OK) return st0;
   std::lock_guard<std::mutex> g(s->mu);
   hipStream_t st = (hipStream_t)stream;
-  FrameArgs fa;
-  fa.imu = imu_params_d(s->ip);
-  fa.sigma_g = s->ip.sigma_g;
-  fa.sigma_a = s->ip.sigma_a;
   SolveArgs sa;
   sa.sp = solve_params(s);
-  for (int i = 0; i < 9; ++i) fa.R_WM[i] = sa.sp.R_WM[i];
-  for (int i = 0; i < 3; ++i) fa.t_WM[i] = sa.sp.t_WM[i];
-  fa.mode = s->tp.mode;
+  FrameArgs fa = frame_args(s, sa.sp);
   HIP_OK(launch_frame_init(s->sd, batch, fa, st));
-  int last_level = -1;
-  for (int l = s->levels - 1; l >= 0; --l)
-    if (s->tp.iters[l] > 0) last_level = l;
+  const int last_level = last_level_of(s->tp);
   for (int l = s->levels - 1; l >= 0; --l) {
     ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
     int nb = residual_blocks(ra.npix, s->ppt[l]);
@@ -441,8 +453,199 @@ dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const u
       HIP_OK(launch_solve(s->sd, s->partials, sa, st));
     }
   }
-  if (last_level < 0) return DSLAM_ERR_INVALID;
   HIP_OK(hipEventRecord(s->done, st));
+  return DSLAM_OK;
+}
+
+dslam_status dslam_batch_create(dslam_context* ctx, int32_t max_sessions, dslam_batch** out) {
+  if (!ctx || !out || max_sessions < 1 || max_sessions > MAX_BATCH) return DSLAM_ERR_INVALID;
+  const size_t vis = align256(sizeof(SlotVis) * max_sessions);
+  const size_t sol = align256(sizeof(SlotSolve) * max_sessions);
+  const size_t res = align256(sizeof(dslam_track_result) * max_sessions);
+  const uint64_t bytes = vis + sol + res;
+  uint64_t prev = ctx->used.fetch_add(bytes);
+  if (ctx->budget && prev + bytes > ctx->budget) {
+    ctx->used.fetch_sub(bytes);
+    return DSLAM_ERR_NO_CAPACITY;
+  }
+  dslam_batch* b = new (std::nothrow) dslam_batch;
+  if (!b) {
+    ctx->used.fetch_sub(bytes);
+    return DSLAM_ERR_NO_CAPACITY;
+  }
+  b->ctx = ctx;
+  b->max_n = max_sessions;
+  b->bytes = bytes;
+  b->dev = nullptr;
+  b->host = nullptr;
+  b->pending = false;
+  b->n = 0;
+  auto fail = [&](dslam_status st) {
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->host) (void)hipHostFree(b->host);
+    ctx->used.fetch_sub(bytes);
+    delete b;
+    return st;
+  };
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
+  if (hipMalloc(&b->dev, bytes) != hipSuccess) {
+    b->dev = nullptr;
+    return fail(DSLAM_ERR_NO_CAPACITY);
+  }
+  if (hipHostMalloc(&b->host, bytes, hipHostMallocDefault) != hipSuccess) {
+    b->host = nullptr;
+    return fail(DSLAM_ERR_NO_CAPACITY);
+  }
+  char* d = (char*)b->dev;
+  char* h = (char*)b->host;
+  b->d_vis = (SlotVis*)d;
+  b->d_solve = (SlotSolve*)(d + vis);
+  b->d_res = (dslam_track_result*)(d + vis + sol);
+  b->h_vis = (SlotVis*)h;
+  b->h_solve = (SlotSolve*)(h + vis);
+  b->h_res = (dslam_track_result*)(h + vis + sol);
+  if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
+  *out = b;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_batch_destroy(dslam_batch* b) {
+  if (!b) return DSLAM_ERR_INVALID;
+  (void)hipSetDevice(b->ctx->device);
+  if (b->pending) (void)hipEventSynchronize(b->done);
+  (void)hipEventDestroy(b->done);
+  (void)hipFree(b->dev);
+  (void)hipHostFree(b->host);
+  b->ctx->used.fetch_sub(b->bytes);
+  delete b;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* sessions,
+                               const dslam_frame_input* frames, void* stream) {
+  if (!b || !sessions || !frames || n < 1 || n > b->max_n) return DSLAM_ERR_INVALID;
+  const dslam_session* s0 = sessions[0];
+  if (!s0) return DSLAM_ERR_INVALID;
+  // ---- validate everything before touching any state
+  for (int i = 0; i < n; ++i) {
+    const dslam_session* s = sessions[i];
+    const dslam_frame_input& f = frames[i];
+    if (!s || s->ctx != b->ctx || s->levels != s0->levels) return DSLAM_ERR_INVALID;
+    for (int l = 0; l < s->levels; ++l)
+      if (s->tp.iters[l] != s0->tp.iters[l]) return DSLAM_ERR_INVALID;
+    for (int j = 0; j < i; ++j)
+      if (sessions[j] == s) return DSLAM_ERR_INVALID;
+    if (!f.depth || !f.intensity || f.pitch < s->cam.width) return DSLAM_ERR_INVALID;
+    if (!f.model_depth || !f.model_intensity || f.model_pitch < s->cam.width) return DSLAM_ERR_INVALID;
+    if (!finite16(f.T_WM)) return DSLAM_ERR_INVALID;
+  }
+  const int last_level = last_level_of(s0->tp);
+  if (last_level < 0) return DSLAM_ERR_INVALID;
+  // ---- slot order: sessions grouped by resolution, larger images first
+  int order[MAX_BATCH];
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order, order + n, [&](int a, int c) {
+    const dslam_camera& A = sessions[a]->cam;
+    const dslam_camera& C = sessions[c]->cam;
+    if (A.width * A.height != C.width * C.height) return A.width * A.height > C.width * C.height;
+    return A.width != C.width ? A.width > C.width : false;
+  });
+  int nclass = 0, cls_first[MAX_BATCH + 1];
+  for (int k = 0; k < n; ++k) {
+    const dslam_camera& A = sessions[order[k]]->cam;
+    if (k == 0 || A.width != sessions[order[k - 1]]->cam.width || A.height != sessions[order[k - 1]]->cam.height)
+      cls_first[nclass++] = k;
+  }
+  if (nclass > MAX_CLASSES) return DSLAM_ERR_INVALID;
+  cls_first[nclass] = n;
+  HIP_OK(hipSetDevice(b->ctx->device));
+  if (b->pending) HIP_OK(hipEventSynchronize(b->done));  // staging memory is reused
+  b->pending = false;
+  // ---- stage the slots
+  ImuBatch imu;
+  for (int k = 0; k < n; ++k) {
+    dslam_session* s = sessions[order[k]];
+    const dslam_frame_input& f = frames[order[k]];
+    dslam_status sti = pack_imu(s, f.imu, f.n_imu, f.t0, f.t1, &imu);
+    if (sti != DSLAM_OK) return sti;
+    std::memcpy(s->T_WM, f.T_WM, sizeof(s->T_WM));
+    SlotVis& v = b->h_vis[k];
+    SlotSolve& o = b->h_solve[k];
+    for (int l = 0; l < s->levels; ++l) {
+      v.res[l] = residual_args(s, l, s->sd->xf, nullptr);
+      v.cur[l] = s->cur[l];
+      v.model[l] = s->model[l];
+      v.ppt[l] = s->ppt[l];
+      o.nblocks[l] = residual_blocks(v.res[l].npix, s->ppt[l]);
+    }
+    v.depth = f.depth;
+    v.inten = f.intensity;
+    v.pitch = f.pitch;
+    v.mdepth = f.model_depth;
+    v.minten = f.model_intensity;
+    v.mpitch = f.model_pitch;
+    o.sd = s->sd;
+    o.partials = s->partials;
+    o.imu = imu;
+    o.sp = solve_params(s);
+    o.fa = frame_args(s, o.sp);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIP_OK(hipMemcpyAsync(b->d_vis, b->h_vis, sizeof(SlotVis) * n, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(b->d_solve, b->h_solve, sizeof(SlotSolve) * n, hipMemcpyHostToDevice, st));
+  // ---- work split of each launch: one class per resolution
+  auto grid = [&](auto blocks_of) {
+    BatchGrid g;
+    g.nclass = nclass;
+    int blk = 0;
+    for (int c = 0; c < nclass; ++c) {
+      const int per = blocks_of(sessions[order[cls_first[c]]]);
+      g.first_block[c] = blk;
+      g.blocks_per_slot[c] = per;
+      g.first_slot[c] = cls_first[c];
+      blk += per * (cls_first[c + 1] - cls_first[c]);
+    }
+    g.first_block[nclass] = blk;
+    return g;
+  };
+  for (int which = 0; which < 2; ++which)
+    for (int l = 0; l < s0->levels; ++l) {
+      BatchGrid g = grid([&](const dslam_session* s) {
+        const LevelPtrs& L = s->cur[l];
+        return ((L.W + PYR_TILE_W - 1) / PYR_TILE_W) * ((L.H + PYR_TILE_H - 1) / PYR_TILE_H);
+      });
+      HIP_OK(launch_pyramid_batch(b->d_vis, g, l, which, st));
+    }
+  HIP_OK(launch_frame_init_batch(b->d_solve, n, st));
+  for (int l = s0->levels - 1; l >= 0; --l) {
+    int max_ppt = 1;
+    for (int k = 0; k < n; ++k) max_ppt = std::max(max_ppt, sessions[k]->ppt[l]);
+    BatchGrid g = grid([&](const dslam_session* s) { return residual_blocks(s->cur[l].W * s->cur[l].H, s->ppt[l]); });
+    for (int it = 0; it < s0->tp.iters[l]; ++it) {
+      HIP_OK(launch_residual_batch(b->d_vis, g, l, max_ppt, st));
+      const int last = (l == last_level && it == s0->tp.iters[l] - 1) ? 1 : 0;
+      HIP_OK(launch_solve_batch(b->d_solve, n, l, last, st));
+    }
+  }
+  HIP_OK(launch_gather_results(b->d_solve, n, b->d_res, st));
+  HIP_OK(hipMemcpyAsync(b->h_res, b->d_res, sizeof(dslam_track_result) * n, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipEventRecord(b->done, st));
+  for (int k = 0; k < n; ++k) {
+    dslam_session* s = sessions[order[k]];
+    s->have_model = true;
+    HIP_OK(hipEventRecord(s->done, st));
+    b->order[k] = order[k];
+  }
+  b->n = n;
+  b->pending = true;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_batch_results(dslam_batch* b, dslam_track_result* out) {
+  if (!b || !out || !b->pending) return DSLAM_ERR_INVALID;
+  HIP_OK(hipSetDevice(b->ctx->device));
+  HIP_OK(hipEventSynchronize(b->done));
+  for (int k = 0; k < b->n; ++k) out[b->order[k]] = b->h_res[k];
   return DSLAM_OK;
 }
 

@@ -8,7 +8,7 @@
 // written explicitly with fmaf().
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-#include "device.h"
+#include "step.h"
 
 namespace dslam {
 
@@ -58,9 +58,7 @@ struct SrcDown {  // level l+1 from level l's depth (V[2]) and intensity planes
 };
 
 template <class Src>
-__global__ __launch_bounds__(256) void pyramid_level_kernel(Src src, LevelPtrs L, int with_grad) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
+__device__ __forceinline__ void pyramid_pixel(const Src& src, const LevelPtrs& L, int with_grad, int i, int j) {
   if (i >= L.W || j >= L.H) return;
   const size_t p = (size_t)j * L.W + i;
   float d = src.D(i, j);
@@ -102,6 +100,32 @@ __global__ __launch_bounds__(256) void pyramid_level_kernel(Src src, LevelPtrs L
     }
     L.G[0][p] = gx;
     L.G[1][p] = gy;
+  }
+}
+
+template <class Src>
+__global__ __launch_bounds__(256) void pyramid_level_kernel(Src src, LevelPtrs L, int with_grad) {
+  pyramid_pixel(src, L, with_grad, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y * blockDim.y + threadIdx.y);
+}
+
+// Batched: one launch builds one level of the current (which = 0) or model-view
+// (which = 1) pyramid of every session of the batch; each workgroup covers one
+// PYR_TILE_W x PYR_TILE_H tile of one session.
+__global__ __launch_bounds__(256) void pyramid_batch_kernel(const SlotVis* slots, BatchGrid g, int level, int which) {
+  int slot, b;
+  batch_locate(g, blockIdx.x, &slot, &b);
+  const SlotVis* sv = slots + slot;
+  const LevelPtrs& L = which ? sv->model[level] : sv->cur[level];
+  const int tiles_x = (L.W + PYR_TILE_W - 1) / PYR_TILE_W;
+  const int ty = b / tiles_x, tx = b - ty * tiles_x;
+  const int i = tx * PYR_TILE_W + (threadIdx.x % PYR_TILE_W), j = ty * PYR_TILE_H + (threadIdx.x / PYR_TILE_W);
+  if (level == 0) {
+    Src0 src{which ? sv->mdepth : sv->depth, which ? sv->minten : sv->inten, which ? sv->mpitch : sv->pitch};
+    pyramid_pixel(src, L, which, i, j);
+  } else {
+    const LevelPtrs& P = which ? sv->model[level - 1] : sv->cur[level - 1];
+    SrcDown src{P.V[2], P.I, P.W};
+    pyramid_pixel(src, L, which, i, j);
   }
 }
 
@@ -261,8 +285,11 @@ __device__ __forceinline__ float wave_transpose_sum(const float (&v)[N], int lan
   return y[0];
 }
 
-template <int PPT>
-__global__ __launch_bounds__(RES_THREADS) void residual_kernel(ResidualArgs a) {
+// Workgroup blk of a residual pass with ppt pixels per thread: thread t visits
+// pixels blk*256*ppt + t + 256 k, k = 0..ppt-1, in that order, so the sums of a
+// session do not depend on whether it runs alone or in a batch.
+template <int PMAX>
+__device__ __forceinline__ void residual_block(const ResidualArgs& a, int blk, int ppt) {
   __shared__ float red[RES_THREADS / 64][58];
   float T[24];
 #pragma unroll
@@ -270,11 +297,11 @@ __global__ __launch_bounds__(RES_THREADS) void residual_kernel(ResidualArgs a) {
   float acc[58];
 #pragma unroll
   for (int k = 0; k < 58; ++k) acc[k] = 0.0f;
-  const int base = blockIdx.x * RES_THREADS * PPT + threadIdx.x;
+  const int base = blk * RES_THREADS * ppt + threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < PPT; ++k) {
+  for (int k = 0; k < PMAX; ++k) {
     int p = base + k * RES_THREADS;
-    if (p < a.npix) pixel(a, T, p, acc);
+    if (k < ppt && p < a.npix) pixel(a, T, p, acc);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float tot = wave_transpose_sum(acc, lane);
@@ -284,8 +311,23 @@ __global__ __launch_bounds__(RES_THREADS) void residual_kernel(ResidualArgs a) {
     float s = red[0][threadIdx.x];
 #pragma unroll
     for (int w = 1; w < RES_THREADS / 64; ++w) s += red[w][threadIdx.x];
-    a.partials[(size_t)blockIdx.x * PARTIAL_STRIDE + threadIdx.x] = s;
+    a.partials[(size_t)blk * PARTIAL_STRIDE + threadIdx.x] = s;
   }
+}
+
+template <int PPT>
+__global__ __launch_bounds__(RES_THREADS) void residual_kernel(ResidualArgs a) {
+  residual_block<PPT>(a, blockIdx.x, PPT);
+}
+
+// Batched: one launch runs one residual pass of every session of the batch.
+template <int PMAX>
+__global__ __launch_bounds__(RES_THREADS) void residual_batch_kernel(const SlotVis* slots, BatchGrid g, int level) {
+  int slot, b;
+  batch_locate(g, blockIdx.x, &slot, &b);
+  const SlotVis* sv = slots + slot;
+  const ResidualArgs a = sv->res[level];
+  residual_block<PMAX>(a, b, sv->ppt[level]);
 }
 
 }  // namespace dslam
@@ -307,6 +349,22 @@ hipError_t launch_pyramid_down(const LevelPtrs& parent, const LevelPtrs& L, int 
   dim3 blk(64, 4), grd((L.W + 63) / 64, (L.H + 3) / 4);
   SrcDown s{parent.V[2], parent.I, parent.W};
   hipLaunchKernelGGL(pyramid_level_kernel<SrcDown>, grd, blk, 0, st, s, L, with_grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_pyramid_batch(const SlotVis* slots, const BatchGrid& g, int level, int which, hipStream_t st) {
+  hipLaunchKernelGGL(pyramid_batch_kernel, dim3(g.first_block[g.nclass]), dim3(256), 0, st, slots, g, level, which);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, hipStream_t st) {
+  const dim3 grid(g.first_block[g.nclass]);
+  switch (max_ppt) {
+    case 1: hipLaunchKernelGGL(residual_batch_kernel<1>, grid, dim3(RES_THREADS), 0, st, slots, g, level); break;
+    case 2: hipLaunchKernelGGL(residual_batch_kernel<2>, grid, dim3(RES_THREADS), 0, st, slots, g, level); break;
+    case 4: hipLaunchKernelGGL(residual_batch_kernel<4>, grid, dim3(RES_THREADS), 0, st, slots, g, level); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -3,31 +3,10 @@
 // solve, so that the whole coarse-to-fine iteration stays on the GPU
 // (Section IV-C/D/E).  One workgroup runs each of these small kernels.
 #include <hip/hip_runtime.h>
-#include "device.h"
-#include "solve_core.h"
+#include "step.h"
 #include "solve_wave.h"
 
 namespace dslam {
-
-struct ImuBatch {
-  int32_t n;
-  double t0, t1;
-  dslam_imu_sample s[DSLAM_MAX_IMU_SAMPLES];
-};
-
-struct FrameArgs {
-  ImuParamsD imu;
-  double sigma_g, sigma_a;
-  double R_WM[9], t_WM[3];
-  int32_t mode;
-};
-
-struct SolveArgs {
-  SolveParams sp;
-  int32_t level;
-  int32_t last;      // 1 on the last iteration of the frame: marginalise and publish
-  int32_t nblocks;
-};
 
 // Fixed-order float64 sum of the block partials ([nblocks][64] floats, 58
 // used): thread t sums the float4 column group t % 16 over blocks t/16,
@@ -76,7 +55,9 @@ __global__ __launch_bounds__(SOLVE_THREADS) void reduce_kernel(const float* part
 }
 
 
-__global__ __launch_bounds__(SOLVE_THREADS) void frame_init_kernel(SessionDev* sd, ImuBatch batch, FrameArgs fa) {
+// Preintegrates the frame's IMU samples at x0's bias estimate and predicts x1
+// (Section IV-C); resets the frame's status and inlier counts.
+__device__ void frame_init_body(SessionDev* sd, const ImuBatch& batch, const FrameArgs& fa) {
   __shared__ PreintWork pw;
   __shared__ dslam_preint pre;
   __shared__ dslam_frame_state x0;
@@ -107,7 +88,19 @@ __global__ __launch_bounds__(SOLVE_THREADS) void frame_init_kernel(SessionDev* s
   }
 }
 
-__global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, const float* partials, SolveArgs a) {
+__global__ __launch_bounds__(SOLVE_THREADS) void frame_init_kernel(SessionDev* sd, ImuBatch batch, FrameArgs fa) {
+  frame_init_body(sd, batch, fa);
+}
+
+// one workgroup per session of the batch
+__global__ __launch_bounds__(SOLVE_THREADS) void frame_init_batch_kernel(const SlotSolve* slots) {
+  const SlotSolve* s = slots + blockIdx.x;
+  frame_init_body(s->sd, s->imu, s->fa);
+}
+
+// One Gauss-Newton step of one session: reduce the block partials, solve,
+// update the states (and on the frame's last step marginalise and publish).
+__device__ void solve_body(SessionDev* sd, const float* partials, const SolveArgs& a) {
   __shared__ SolveWork w;
   __shared__ double raw[58];
   __shared__ dslam_frame_state x0, x1;
@@ -195,6 +188,28 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, co
   }
 }
 
+__global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, const float* partials, SolveArgs a) {
+  solve_body(sd, partials, a);
+}
+
+__global__ __launch_bounds__(SOLVE_THREADS) void solve_batch_kernel(const SlotSolve* slots, int level, int last) {
+  const SlotSolve* s = slots + blockIdx.x;
+  SolveArgs a;
+  a.sp = s->sp;
+  a.level = level;
+  a.last = last;
+  a.nblocks = s->nblocks[level];
+  solve_body(s->sd, s->partials, a);
+}
+
+// Copies each session's result record into the batch's contiguous result array.
+__global__ __launch_bounds__(SOLVE_THREADS) void gather_results_kernel(const SlotSolve* slots,
+                                                                         dslam_track_result* out) {
+  const double* src = reinterpret_cast<const double*>(&slots[blockIdx.x].sd->result);
+  double* dst = reinterpret_cast<double*>(out + blockIdx.x);
+  for (int i = threadIdx.x; i < (int)(sizeof(dslam_track_result) / 8); i += SOLVE_THREADS) dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------------------
 hipError_t launch_frame_init(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, hipStream_t st) {
   hipLaunchKernelGGL(frame_init_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, sd, b, fa);
@@ -208,6 +223,21 @@ hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& 
 
 hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, partials, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_frame_init_batch(const SlotSolve* slots, int n, hipStream_t st) {
+  hipLaunchKernelGGL(frame_init_batch_kernel, dim3(n), dim3(SOLVE_THREADS), 0, st, slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_batch(const SlotSolve* slots, int n, int level, int last, hipStream_t st) {
+  hipLaunchKernelGGL(solve_batch_kernel, dim3(n), dim3(SOLVE_THREADS), 0, st, slots, level, last);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_results(const SlotSolve* slots, int n, dslam_track_result* out, hipStream_t st) {
+  hipLaunchKernelGGL(gather_results_kernel, dim3(n), dim3(SOLVE_THREADS), 0, st, slots, out);
   return hipGetLastError();
 }
 

@@ -1,0 +1,61 @@
+// Arguments of the per-frame device kernels (frame initialisation, solve) and
+// the launch wrappers of every kernel, shared by the kernel sources and the
+// host library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "device.h"
+#include "solve_core.h"
+
+namespace dslam {
+
+// The frame's IMU samples, by value (they reach the device inside kernel
+// arguments or a batch's staging copy).
+struct ImuBatch {
+  int32_t n;
+  double t0, t1;
+  dslam_imu_sample s[DSLAM_MAX_IMU_SAMPLES];
+};
+
+struct FrameArgs {
+  ImuParamsD imu;
+  double sigma_g, sigma_a;
+  double R_WM[9], t_WM[3];
+  int32_t mode;
+};
+
+struct SolveArgs {
+  SolveParams sp;
+  int32_t level;
+  int32_t last;      // 1 on the last iteration of the frame: marginalise and publish
+  int32_t nblocks;
+};
+
+// One session's share of a batched step, frame-initialisation and solve part.
+struct SlotSolve {
+  SessionDev* sd;
+  const float* partials;
+  ImuBatch imu;
+  FrameArgs fa;
+  SolveParams sp;
+  int32_t nblocks[DSLAM_MAX_LEVELS];
+};
+
+// kernels.hip
+hipError_t launch_pyramid_level0(const float* depth, const uint8_t* inten, int pitch, const LevelPtrs& L,
+                                 int with_grad, hipStream_t st);
+hipError_t launch_pyramid_down(const LevelPtrs& parent, const LevelPtrs& L, int with_grad, hipStream_t st);
+int residual_blocks(int npix, int ppt);
+hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st);
+// which: 0 current frame, 1 model view
+hipError_t launch_pyramid_batch(const SlotVis* slots, const BatchGrid& g, int level, int which, hipStream_t st);
+hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, hipStream_t st);
+
+// solve.hip
+hipError_t launch_frame_init(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, hipStream_t st);
+hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& a, hipStream_t st);
+hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st);
+hipError_t launch_frame_init_batch(const SlotSolve* slots, int n, hipStream_t st);
+hipError_t launch_solve_batch(const SlotSolve* slots, int n, int level, int last, hipStream_t st);
+hipError_t launch_gather_results(const SlotSolve* slots, int n, dslam_track_result* out, hipStream_t st);
+
+}  // namespace dslam

@@ -1,0 +1,114 @@
+"""Batched tracking (serving form) through the C ABI: every session's result
+in a batch must equal, bit for bit, the result of tracking it alone, whatever
+the other sessions of the batch and the batch composition of each step."""
+import numpy as np
+import pytest
+
+import paper_2207_10940_amd as P
+import synth
+
+pytestmark = pytest.mark.gpu
+
+# (seed, width, height, mode): mixed resolutions, a ragged one (200x152: tiles
+# and blocks do not divide the image) and one RGB-D-only session
+SESSIONS = [(3101, 160, 120, "rgbdi"), (3102, 320, 240, "rgbdi"), (3103, 160, 120, "rgbdi"),
+            (3104, 200, 152, "rgbdi"), (3105, 160, 120, "rgbd")]
+# batch composition per step: indices of the sessions that get their next frame
+STEPS = [[0, 1, 2, 3, 4], [1, 3], [0, 2, 3, 4], [4, 0, 1], [2, 1, 0, 3, 4]]
+
+
+def _frame(seq, j):
+    md, mi, T = synth.configs.model_view(seq, j)
+    t0, t1 = seq["times"][j - 1], seq["times"][j]
+    a, b = synth.configs.imu_window(seq["imu"]["t"], t0, t1)
+    imu = {k: v[a:b] for k, v in seq["imu"].items()}
+    return {"depth": seq["depth"][j].contiguous(), "intensity": seq["intensity"][j].contiguous(),
+            "model_depth": md.contiguous(), "model_intensity": mi.contiguous(), "T_WM": T,
+            "imu": imu, "t0": t0, "t1": t1}
+
+
+def _open(ctx, seq, mode):
+    tp = P.track_params(levels=3, iters=(4, 3, 2), mode=mode)
+    prior = seq["prior"] if mode != "rgbd" else None
+    return P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], prior)
+
+
+def _same(a, b, what):
+    assert a["status"] == b["status"] == 0, what
+    for k in ("x0", "x1"):
+        for f in ("r", "q", "v", "bg", "ba"):
+            assert np.array_equal(a[k][f], b[k][f]), (what, k, f, a[k][f] - b[k][f])
+    assert np.array_equal(a["q_IW"], b["q_IW"]), what
+    assert a["n_icp"] == b["n_icp"] and a["n_rgb"] == b["n_rgb"], what
+    for f in ("cost_icp", "cost_rgb", "cost_imu", "last_step_norm"):
+        assert a[f] == b[f], (what, f)
+    assert np.array_equal(a["prior"]["H"], b["prior"]["H"]) and np.array_equal(a["prior"]["b"], b["prior"]["b"]), what
+
+
+def test_batched_results_equal_alone_results():
+    import torch
+    seqs = [synth.configs.sequence(seed=s, n_frames=8, width=w, height=h, device="cuda") for s, w, h, _ in SESSIONS]
+    stream = torch.cuda.current_stream()
+    # alone: each session tracks its frames 1, 2, ... one at a time
+    ctx = P.Context(0)
+    alone = []
+    for idx, (seq, (_, _, _, mode)) in enumerate(zip(seqs, SESSIONS)):
+        s = _open(ctx, seq, mode)
+        res = []
+        count = sum(1 for st in STEPS if idx in st)
+        for j in range(1, count + 1):
+            f = _frame(seq, j)
+            s.set_model(f["model_depth"], f["model_intensity"], f["T_WM"], stream)
+            s.track_frame(f["depth"], f["intensity"], f["imu"] if mode != "rgbd" else None, f["t0"], f["t1"], stream)
+            res.append(s.result())
+        alone.append(res)
+        s.close()
+    # batched: the composition changes from step to step
+    sess = [_open(ctx, seq, mode) for seq, (_, _, _, mode) in zip(seqs, SESSIONS)]
+    batch = P.Batch(ctx, len(SESSIONS))
+    nxt = [1] * len(SESSIONS)
+    for step, members in enumerate(STEPS):
+        frames = [_frame(seqs[i], nxt[i]) for i in members]
+        for i, f in zip(members, frames):
+            if SESSIONS[i][3] == "rgbd":
+                f["imu"] = None
+        batch.track([sess[i] for i in members], frames, stream)
+        out = batch.results()
+        for i, r in zip(members, out):
+            _same(r, alone[i][nxt[i] - 1], f"step {step} session {i} frame {nxt[i]}")
+            # the session's own result call sees the same record
+            _same(sess[i].result(), r, f"session result {i}")
+            nxt[i] += 1
+        print(f"step {step}: sessions {members} equal to alone", flush=True)
+    batch.close()
+    for s in sess:
+        s.close()
+    ctx.close()
+
+
+def test_batch_rejects_inconsistent_sessions():
+    import torch
+    seq = synth.configs.sequence(seed=3201, n_frames=3, width=160, height=120, device="cuda")
+    ctx = P.Context(0)
+    a = _open(ctx, seq, "rgbdi")
+    tp = P.track_params(levels=2, iters=(4, 3), mode="rgbdi")
+    b = P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], seq["prior"])
+    batch = P.Batch(ctx, 4)
+    f = _frame(seq, 1)
+    stream = torch.cuda.current_stream()
+    with pytest.raises(P.DslamError):   # different pyramid depth
+        batch.track([a, b], [f, f], stream)
+    with pytest.raises(P.DslamError):   # the same session twice
+        batch.track([a, a], [f, f], stream)
+    bad = dict(f)
+    bad["imu"] = {k: v[::-1].copy() for k, v in f["imu"].items()}
+    with pytest.raises(P.DslamError):   # unsorted IMU samples
+        batch.track([a], [bad], stream)
+    batch.track([a], [f], stream)
+    assert batch.results()[0]["status"] == 0
+    with pytest.raises(P.DslamError):   # more sessions than the batch holds
+        P.Batch(ctx, 0)
+    batch.close()
+    a.close()
+    b.close()
+    ctx.close()
