@@ -309,6 +309,57 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
 /* Wait for the batch's last step and copy its n results, in call order. */
 dslam_status dslam_batch_results(dslam_batch* b, dslam_track_result* out);
 
+/* Serving loop with continuous batching.  Frames of many sessions are
+ * submitted as requests; each poll retires finished batched steps and
+ * launches new ones from the pending requests: every session with a pending
+ * frame and no frame in flight joins the next step (oldest request first, up
+ * to max_batch sessions with the same pyramid schedule), and up to
+ * pipeline_depth steps run at once on the server's own streams, so requests
+ * that arrive while others are on the GPU are admitted as soon as a step slot
+ * frees up.  Sessions are admitted by the context's HBM budget at
+ * dslam_session_open (NO_CAPACITY when it is exhausted).  A session's frames
+ * are tracked in submission order.  Not thread-safe: one thread drives a
+ * server. */
+typedef struct dslam_server dslam_server;
+
+typedef struct {
+  int32_t max_batch;       /* sessions per batched step, 1..DSLAM_MAX_BATCH */
+  int32_t pipeline_depth;  /* batched steps in flight at once, 1..8 */
+} dslam_server_params;
+
+/* A finished request.  submit_s / done_s are host steady-clock seconds (the
+ * same clock as dslam_server_clock) at submission and at the poll that
+ * retired it; device_ms is the GPU time of the batched step that ran it. */
+typedef struct {
+  uint64_t request_id;
+  dslam_session* session;
+  double submit_s, launch_s, done_s;
+  float device_ms;
+  int32_t batch_size;
+  dslam_track_result result;
+} dslam_request_done;
+
+dslam_status dslam_server_create(dslam_context* ctx, const dslam_server_params* p, dslam_server** out);
+/* Wait for in-flight steps and free the server (pending requests are dropped). */
+dslam_status dslam_server_destroy(dslam_server* sv);
+/* Queue one frame of `session` (opened on the server's context).  The frame
+ * input is copied, IMU samples included; its device images must stay valid
+ * until the request is returned by dslam_server_poll.  *request_id receives a
+ * server-unique id.  Errors: INVALID (arguments, IMU samples). */
+dslam_status dslam_server_submit(dslam_server* sv, dslam_session* session, const dslam_frame_input* frame,
+                                 uint64_t* request_id);
+/* Retire finished steps, launch new ones, and copy up to max_out finished
+ * requests to out (*n_out of them).  With wait != 0 and nothing finished yet,
+ * blocks until the oldest in-flight step completes.  Returns the first error
+ * met while launching or retiring a step; the requests of that step are
+ * returned with the error in result.status. */
+dslam_status dslam_server_poll(dslam_server* sv, int32_t wait, dslam_request_done* out, int32_t max_out,
+                               int32_t* n_out);
+/* Requests queued but not launched, and launched but not yet returned. */
+dslam_status dslam_server_counts(const dslam_server* sv, int32_t* pending, int32_t* in_flight);
+/* The server's clock (steady clock, seconds). */
+double dslam_server_clock(void);
+
 /* Checkpoint / restore the session's estimator state (x0, q_IW, prior and
  * frame counter) through host memory; the pyramids are not part of it. */
 dslam_status dslam_session_get_state(dslam_session* s, dslam_frame_state* x0, double q_IW[4], dslam_prior* prior,

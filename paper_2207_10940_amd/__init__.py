@@ -15,7 +15,7 @@ from . import _abi
 from ._abi import (CH_GX, CH_GY, CH_I, CH_NX, CH_NY, CH_NZ, CH_VX, CH_VY, CH_VZ, JAC_BF16, JAC_FP16, JAC_FP32,
                    JAC_FP32_MFMA, MODE_GYRO, MODE_RGBD, MODE_RGBDI, PYR_CURRENT, PYR_MODEL)
 
-__all__ = ["DslamError", "Context", "Session", "preintegrate_imu", "solve_step", "track_params", "imu_params",
+__all__ = ["DslamError", "Context", "Session", "Batch", "Server", "frame_input", "preintegrate_imu", "solve_step", "track_params", "imu_params",
            "camera", "state_struct", "state_dict", "prior_struct", "prior_dict", "lib"]
 
 MODES = {"rgbdi": MODE_RGBDI, "rgbd": MODE_RGBD, "gyro": MODE_GYRO}
@@ -288,6 +288,24 @@ class Session:
                                              int(frame_index)), "dslam_session_set_state")
 
 
+def frame_input(f: dict):
+    """FrameInput for dict(depth, intensity, model_depth, model_intensity, T_WM, imu, t0, t1) (device images
+    contiguous); returns (struct, keep-alive) -- the IMU array must outlive the struct's use."""
+    d, im, md, mi = f["depth"], f["intensity"], f["model_depth"], f["model_intensity"]
+    for t in (d, im, md, mi):
+        assert t.is_cuda and t.is_contiguous()
+    fi = _abi.FrameInput()
+    fi.depth, fi.intensity, fi.pitch = d.data_ptr(), im.data_ptr(), int(d.shape[1])
+    fi.model_depth, fi.model_intensity, fi.model_pitch = md.data_ptr(), mi.data_ptr(), int(md.shape[1])
+    fi.T_WM[:] = [float(v) for v in np.asarray(f["T_WM"], dtype=np.float64).ravel()]
+    arr = None
+    if f.get("imu") is not None:
+        arr, cnt = imu_samples(f["imu"]["t"], f["imu"]["gyro"], f["imu"]["acc"])
+        fi.imu, fi.n_imu = arr, cnt
+    fi.t0, fi.t1 = float(f.get("t0", 0.0)), float(f.get("t1", 0.0))
+    return fi, (arr, f)
+
+
 class Batch:
     """Staging for batched tracking steps over many sessions (dslam_batch_*)."""
 
@@ -318,18 +336,8 @@ class Batch:
         inputs = (_abi.FrameInput * n)()
         keep = []
         for i, f in enumerate(frames):
-            d, im, md, mi = f["depth"], f["intensity"], f["model_depth"], f["model_intensity"]
-            for t in (d, im, md, mi):
-                assert t.is_cuda and t.is_contiguous()
-            fi = inputs[i]
-            fi.depth, fi.intensity, fi.pitch = d.data_ptr(), im.data_ptr(), int(d.shape[1])
-            fi.model_depth, fi.model_intensity, fi.model_pitch = md.data_ptr(), mi.data_ptr(), int(md.shape[1])
-            fi.T_WM[:] = [float(v) for v in np.asarray(f["T_WM"], dtype=np.float64).ravel()]
-            if f.get("imu") is not None:
-                arr, cnt = imu_samples(f["imu"]["t"], f["imu"]["gyro"], f["imu"]["acc"])
-                keep.append(arr)
-                fi.imu, fi.n_imu = arr, cnt
-            fi.t0, fi.t1 = float(f.get("t0", 0.0)), float(f.get("t1", 0.0))
+            inputs[i], k = frame_input(f)
+            keep.append(k)
         _check(lib().dslam_batch_track(self.handle, n, handles, inputs, _stream_ptr(stream)), "dslam_batch_track")
         self._keep = (keep, frames)
         self._n = n
@@ -338,3 +346,54 @@ class Batch:
         out = (_abi.TrackResult * self._n)()
         _check(lib().dslam_batch_results(self.handle, out), "dslam_batch_results")
         return [result_dict(out[i]) for i in range(self._n)]
+
+
+class Server:
+    """Serving loop with continuous batching (dslam_server_*).  One thread drives it."""
+
+    def __init__(self, ctx: Context, max_batch: int, pipeline_depth: int = 2):
+        p = _abi.ServerParams(int(max_batch), int(pipeline_depth))
+        h = C.c_void_p()
+        _check(lib().dslam_server_create(ctx.handle, C.byref(p), C.byref(h)), "dslam_server_create")
+        self.handle = h
+        self._buf = (_abi.RequestDone * 256)()
+
+    def close(self):
+        if self.handle:
+            _check(lib().dslam_server_destroy(self.handle), "dslam_server_destroy")
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def clock() -> float:
+        return float(lib().dslam_server_clock())
+
+    def submit(self, session: Session, fi: _abi.FrameInput) -> int:
+        rid = C.c_uint64()
+        _check(lib().dslam_server_submit(self.handle, session.handle, C.byref(fi), C.byref(rid)),
+               "dslam_server_submit")
+        return rid.value
+
+    def poll(self, wait: bool = False) -> list:
+        """Finished requests as (request_id, session handle value, submit_s, launch_s, done_s, device_ms,
+        batch_size, result struct copy)."""
+        n = C.c_int32()
+        code = lib().dslam_server_poll(self.handle, int(bool(wait)), self._buf, len(self._buf), C.byref(n))
+        out = []
+        for i in range(n.value):
+            r = self._buf[i]
+            res = _abi.TrackResult()
+            C.pointer(res)[0] = r.result
+            out.append((r.request_id, r.session, r.submit_s, r.launch_s, r.done_s, r.device_ms, r.batch_size, res))
+        _check(code, "dslam_server_poll")
+        return out
+
+    def counts(self):
+        p, f = C.c_int32(), C.c_int32()
+        _check(lib().dslam_server_counts(self.handle, C.byref(p), C.byref(f)), "dslam_server_counts")
+        return p.value, f.value

@@ -69,6 +69,16 @@ class FrameInput(C.Structure):
                 ("t0", C.c_double), ("t1", C.c_double)]
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("max_batch", C.c_int32), ("pipeline_depth", C.c_int32)]
+
+
+class RequestDone(C.Structure):
+    _fields_ = [("request_id", C.c_uint64), ("session", C.c_void_p), ("submit_s", C.c_double),
+                ("launch_s", C.c_double), ("done_s", C.c_double), ("device_ms", C.c_float),
+                ("batch_size", C.c_int32), ("result", TrackResult)]
+
+
 MAX_BATCH = 256
 MAX_BATCH_RESOLUTIONS = 16
 
@@ -104,6 +114,12 @@ SIGNATURES = {
     "dslam_batch_destroy": (C.c_int, [vp]),
     "dslam_batch_track": (C.c_int, [vp, C.c_int32, P(vp), P(FrameInput), vp]),
     "dslam_batch_results": (C.c_int, [vp, P(TrackResult)]),
+    "dslam_server_create": (C.c_int, [vp, P(ServerParams), P(vp)]),
+    "dslam_server_destroy": (C.c_int, [vp]),
+    "dslam_server_submit": (C.c_int, [vp, vp, P(FrameInput), P(C.c_uint64)]),
+    "dslam_server_poll": (C.c_int, [vp, C.c_int32, P(RequestDone), C.c_int32, P(C.c_int32)]),
+    "dslam_server_counts": (C.c_int, [vp, P(C.c_int32), P(C.c_int32)]),
+    "dslam_server_clock": (C.c_double, []),
 }
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdslam.so")

@@ -35,6 +35,7 @@ SOURCES = {
     "kernels.hip": EXACT_FP32,
     "solve.hip": EXACT_FP64,
     "dslam.hip": EXACT_FP64,
+    "server.hip": EXACT_FP64,
 }
 
 

@@ -1,0 +1,58 @@
+// Host-side objects behind the opaque handles of the C ABI (contexts,
+// sessions, batches), shared by the library's host sources.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <mutex>
+
+#include "step.h"
+
+struct dslam_context {
+  int device;
+  uint64_t budget;
+  std::atomic<uint64_t> used{0};
+};
+
+using dslam::LevelPtrs;
+using dslam::SessionDev;
+
+struct dslam_session {
+  dslam_context* ctx;
+  dslam_camera cam;
+  dslam_track_params tp;
+  dslam_imu_params ip;
+  int levels;
+  uint64_t bytes;
+  void* arena;
+  LevelPtrs cur[DSLAM_MAX_LEVELS], model[DSLAM_MAX_LEVELS];
+  SessionDev* sd;
+  float* partials;
+  int max_blocks;
+  double* red_out;   // device, 64 doubles
+  float* xf_scratch; // device, 24 floats (dslam_linearize)
+  hipEvent_t done;
+  bool have_model;
+  double T_WM[16];
+  int ppt[DSLAM_MAX_LEVELS];
+  std::mutex mu;
+};
+
+struct dslam_batch {
+  dslam_context* ctx;
+  int max_n;
+  uint64_t bytes;
+  void* dev;                   // SlotVis[max_n] | SlotSolve[max_n] | dslam_track_result[max_n]
+  dslam::SlotVis* d_vis;
+  dslam::SlotSolve* d_solve;
+  dslam_track_result* d_res;
+  void* host;                  // pinned mirror of the same layout
+  dslam::SlotVis* h_vis;
+  dslam::SlotSolve* h_solve;
+  dslam_track_result* h_res;
+  hipEvent_t done;
+  bool pending;
+  int n;
+  int order[dslam::MAX_BATCH];        // slot -> caller index
+};
+

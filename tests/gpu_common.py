@@ -46,3 +46,33 @@ def jtr_scale(terms, cols, dim):
 
 def pose_err(xa, xb):
     return np.linalg.norm(xa["r"] - xb["r"]), np.linalg.norm(lie.quat_boxminus(xa["q"], xb["q"]))
+
+
+def seq_frame(seq, j):
+    """Inputs of tracking frame j of a synthetic sequence (frame dict of the batch and server APIs)."""
+    md, mi, T = synth.configs.model_view(seq, j)
+    t0, t1 = seq["times"][j - 1], seq["times"][j]
+    a, b = synth.configs.imu_window(seq["imu"]["t"], t0, t1)
+    imu = {k: v[a:b] for k, v in seq["imu"].items()}
+    return {"depth": seq["depth"][j].contiguous(), "intensity": seq["intensity"][j].contiguous(),
+            "model_depth": md.contiguous(), "model_intensity": mi.contiguous(), "T_WM": T,
+            "imu": imu, "t0": t0, "t1": t1}
+
+
+def open_seq_session(ctx, seq, mode, iters=(4, 3, 2)):
+    tp = P.track_params(levels=len(iters), iters=iters, mode=mode)
+    prior = seq["prior"] if mode != "rgbd" else None
+    return P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], prior)
+
+
+def same_result(a, b, what):
+    """Bit-for-bit equality of two result dicts."""
+    assert a["status"] == b["status"] == 0, what
+    for k in ("x0", "x1"):
+        for f in ("r", "q", "v", "bg", "ba"):
+            assert np.array_equal(a[k][f], b[k][f]), (what, k, f, a[k][f] - b[k][f])
+    assert np.array_equal(a["q_IW"], b["q_IW"]), what
+    assert a["n_icp"] == b["n_icp"] and a["n_rgb"] == b["n_rgb"], what
+    for f in ("cost_icp", "cost_rgb", "cost_imu", "last_step_norm"):
+        assert a[f] == b[f], (what, f)
+    assert np.array_equal(a["prior"]["H"], b["prior"]["H"]) and np.array_equal(a["prior"]["b"], b["prior"]["b"]), what

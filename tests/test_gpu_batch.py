@@ -6,6 +6,7 @@ import pytest
 
 import paper_2207_10940_amd as P
 import synth
+from gpu_common import open_seq_session as _open, same_result as _same, seq_frame as _frame
 
 pytestmark = pytest.mark.gpu
 
@@ -15,34 +16,6 @@ SESSIONS = [(3101, 160, 120, "rgbdi"), (3102, 320, 240, "rgbdi"), (3103, 160, 12
             (3104, 200, 152, "rgbdi"), (3105, 160, 120, "rgbd")]
 # batch composition per step: indices of the sessions that get their next frame
 STEPS = [[0, 1, 2, 3, 4], [1, 3], [0, 2, 3, 4], [4, 0, 1], [2, 1, 0, 3, 4]]
-
-
-def _frame(seq, j):
-    md, mi, T = synth.configs.model_view(seq, j)
-    t0, t1 = seq["times"][j - 1], seq["times"][j]
-    a, b = synth.configs.imu_window(seq["imu"]["t"], t0, t1)
-    imu = {k: v[a:b] for k, v in seq["imu"].items()}
-    return {"depth": seq["depth"][j].contiguous(), "intensity": seq["intensity"][j].contiguous(),
-            "model_depth": md.contiguous(), "model_intensity": mi.contiguous(), "T_WM": T,
-            "imu": imu, "t0": t0, "t1": t1}
-
-
-def _open(ctx, seq, mode):
-    tp = P.track_params(levels=3, iters=(4, 3, 2), mode=mode)
-    prior = seq["prior"] if mode != "rgbd" else None
-    return P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], prior)
-
-
-def _same(a, b, what):
-    assert a["status"] == b["status"] == 0, what
-    for k in ("x0", "x1"):
-        for f in ("r", "q", "v", "bg", "ba"):
-            assert np.array_equal(a[k][f], b[k][f]), (what, k, f, a[k][f] - b[k][f])
-    assert np.array_equal(a["q_IW"], b["q_IW"]), what
-    assert a["n_icp"] == b["n_icp"] and a["n_rgb"] == b["n_rgb"], what
-    for f in ("cost_icp", "cost_rgb", "cost_imu", "last_step_norm"):
-        assert a[f] == b[f], (what, f)
-    assert np.array_equal(a["prior"]["H"], b["prior"]["H"]) and np.array_equal(a["prior"]["b"], b["prior"]["b"]), what
 
 
 def test_batched_results_equal_alone_results():
