@@ -170,6 +170,165 @@ def run_counters(args):
                       "copy_bytes_each_way": COPY_BYTES, "copy_reps": 3}), flush=True)
 
 
+SERVING_MIX = ((1280, 720, 8), (640, 480, 32), (320, 240, 24))  # (width, height, sessions)
+
+
+def serving_frame(seq, j):
+    md, mi, T = synth_mod().configs.model_view(seq, j)
+    t0, t1 = seq["times"][j - 1], seq["times"][j]
+    a, b = synth_mod().configs.imu_window(seq["imu"]["t"], t0, t1)
+    return {"depth": seq["depth"][j].contiguous(), "intensity": seq["intensity"][j].contiguous(),
+            "model_depth": md.contiguous(), "model_intensity": mi.contiguous(), "T_WM": T,
+            "imu": {k: v[a:b] for k, v in seq["imu"].items()}, "t0": t0, "t1": t1}
+
+
+def synth_mod():
+    import synth
+    return synth
+
+
+def run_serving(args):
+    """Serving form: 64 concurrent sessions (8 at 1280x720, 32 at 640x480, 24 at 320x240) through the
+    continuous-batching server.  Saturation throughput (every frame queued at once), latency under Poisson
+    arrivals at 30 Hz per session, the plain path (one session, one frame at a time, synchronous) on the
+    same mix, and the batched level-0 residual pass against the HBM roofline."""
+    import torch
+
+    import paper_2207_10940_amd as P
+    synth = synth_mod()
+    nf = args.serving_frames
+    t = time.time()
+    seqs, specs = {}, []
+    for ci, (w, h, count) in enumerate(SERVING_MIX):
+        nseq = min(count, args.serving_sequences)
+        seqs[(w, h)] = [synth.configs.sequence(seed=4000 + 100 * ci + k, n_frames=nf + 1, width=w, height=h,
+                                               device="cuda", duration=(nf + 3) / 30.0) for k in range(nseq)]
+        specs += [(w, h, k % nseq) for k in range(count)]
+    frames = {key: [[serving_frame(sq, j) for j in range(1, nf + 1)] for sq in lst] for key, lst in seqs.items()}
+    fins = {key: [[P.frame_input(f)[0] for f in fl] for fl in lst] for key, lst in frames.items()}
+    torch.cuda.synchronize()
+    log(f"[serving] generated {sum(len(v) for v in seqs.values())} sequences x {nf} frames in {time.time() - t:.1f}s")
+    ctx = P.Context(0)
+    tp = P.track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32")
+    sess = []
+    for w, h, k in specs:
+        sq = seqs[(w, h)][k]
+        sess.append(P.Session(ctx, sq["camera"], tp, P.imu_params(), sq["x0"], sq["q_IW"], sq["prior"]))
+
+    def reset():
+        for (w, h, k), s in zip(specs, sess):
+            sq = seqs[(w, h)][k]
+            s.set_state(sq["x0"], sq["q_IW"], sq["prior"])
+
+    server = P.Server(ctx, max_batch=len(sess), pipeline_depth=2)
+    total = len(sess) * nf
+    # ---- saturation: every frame queued at once (each session's frames in order)
+    reset()
+    torch.cuda.synchronize()
+    t0 = P.Server.clock()
+    for j in range(nf):
+        for (w, h, k), s in zip(specs, sess):
+            server.submit(s, fins[(w, h)][k][j])
+    done, bad, dev_ms, sizes = 0, 0, [], []
+    while done < total:
+        for rec in server.poll(wait=True):
+            done += 1
+            bad += rec[7].status != 0
+            dev_ms.append(rec[5])
+            sizes.append(rec[6])
+    t_sat = P.Server.clock() - t0
+    sat_fps = total / t_sat
+    log(f"[serving] saturation: {total} frames in {t_sat * 1e3:.1f} ms = {sat_fps:.0f} frames/s, "
+        f"mean batch {np.mean(sizes):.1f}, failed {bad}")
+    # ---- nominal load: Poisson arrivals at 30 Hz per session
+    reset()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    arrivals = []
+    for i in range(len(sess)):
+        ts = np.cumsum(rng.exponential(1.0 / 30.0, size=nf))
+        arrivals += [(float(ta), i, j) for j, ta in enumerate(ts)]
+    arrivals.sort()
+    start = P.Server.clock() + 0.01
+    owner, lat, dev_nom, sizes_nom = {}, [], [], []
+    nxt, done = 0, 0
+    while done < total:
+        now = P.Server.clock() - start
+        while nxt < total and arrivals[nxt][0] <= now:
+            ta, i, j = arrivals[nxt]
+            w, h, k = specs[i]
+            owner[server.submit(sess[i], fins[(w, h)][k][j])] = ta
+            nxt += 1
+        for rec in server.poll(wait=False):
+            done += 1
+            ta = owner[rec[0]]
+            if ta >= args.serving_warmup:
+                lat.append((rec[4] - start - ta) * 1e3)
+                dev_nom.append(rec[5])
+            sizes_nom.append(rec[6])
+    span = P.Server.clock() - start
+    log(f"[serving] nominal 30 Hz x {len(sess)}: p50 {np.percentile(lat, 50):.2f} ms p99 "
+        f"{np.percentile(lat, 99):.2f} ms over {len(lat)} frames, mean batch {np.mean(sizes_nom):.1f}")
+    server.close()
+    # ---- plain path on the same mix: one session, one frame at a time, synchronous
+    stream = torch.cuda.current_stream()
+    per_class = {}
+    for w, h, count in SERVING_MIX:
+        i = next(n for n, sp in enumerate(specs) if sp[:2] == (w, h))
+        sq = seqs[(w, h)][specs[i][2]]
+        s = sess[i]
+        s.set_state(sq["x0"], sq["q_IW"], sq["prior"])
+        tl = []
+        for j in range(min(nf, 12)):
+            f = frames[(w, h)][specs[i][2]][j]
+            ts = time.perf_counter()
+            s.set_model(f["model_depth"], f["model_intensity"], f["T_WM"], stream)
+            s.track_frame(f["depth"], f["intensity"], f["imu"], f["t0"], f["t1"], stream)
+            s.result()
+            tl.append(time.perf_counter() - ts)
+        per_class[f"{w}x{h}"] = float(np.median(tl[2:]))
+    plain_s = sum(per_class[f"{w}x{h}"] * c for w, h, c in SERVING_MIX)  # one frame of every session
+    plain_fps = len(sess) / plain_s
+    log(f"[serving] plain path on the mix: {plain_fps:.0f} frames/s ({per_class})")
+    # ---- batched level-0 residual pass over all 64 sessions
+    reset()
+    batch = P.Batch(ctx, len(sess))
+    batch.track(sess, [frames[(w, h)][k][0] for w, h, k in specs], stream)
+    batch.results()
+    batch.profile_residual(0, 5, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(stream)
+    px = batch.profile_residual(0, reps, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / reps
+    gbs = REF_BYTES_PER_PIXEL * px / (k_ms * 1e-3) / 1e9
+    log(f"[serving] batched level-0 residual pass: {px} px in {k_ms * 1e3:.1f} us = {gbs:.0f} GB/s")
+    batch.close()
+    for s in sess:
+        s.close()
+    ctx.close()
+    return {
+        "workload": "64 sessions: 8 at 1280x720, 32 at 640x480, 24 at 320x240; 3 levels 10/5/4 iterations, "
+                    "RGB-D-inertial, float32 Jacobians; continuous batching, 2 steps in flight",
+        "frames": total, "distinct_sequences_per_resolution": args.serving_sequences,
+        "saturation_fps": sat_fps, "saturation_mean_batch": float(np.mean(sizes)),
+        "saturation_device_ms_per_step_p50": float(np.percentile(dev_ms, 50)),
+        "nominal": {"offered_fps": 30.0 * len(sess), "achieved_fps": total / span,
+                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                    "device_p50_ms": float(np.percentile(dev_nom, 50)), "frames": len(lat),
+                    "mean_batch": float(np.mean(sizes_nom)),
+                    "kind": "arrival (Poisson, 30 Hz per session) to result on the host"},
+        "plain_fps_same_mix": plain_fps, "plain_ms_per_frame": {k: v * 1e3 for k, v in per_class.items()},
+        "speedup_vs_plain": sat_fps / plain_fps,
+        "failed": int(bad),
+        "batched_residual_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": gbs / HBM_PEAK_GBS, "kernel_us": k_ms * 1e3, "pixels": px,
+                                      "bytes_per_launch": REF_BYTES_PER_PIXEL * px},
+    }
+
+
 def cpu_baseline(seq, n_frames):
     """The oracle as it stands, single-threaded, on the first frames of the same sequence."""
     from threadpoolctl import threadpool_limits
@@ -200,6 +359,11 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-frames", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-frames", type=int, default=40, help="frames per session of the serving workload")
+    ap.add_argument("--serving-sequences", type=int, default=6,
+                    help="distinct seeded sequences per resolution of the serving workload")
+    ap.add_argument("--serving-warmup", type=float, default=0.25, help="seconds of arrivals left out of latency")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--counters", action="store_true",
                     help="only run the level-0 residual pass and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -211,6 +375,9 @@ def main():
         run_counters(args)
         return
     g = run_gpu(args)
+    serving = None
+    if not args.no_serving:
+        serving = run_serving(args)
     cpu = None
     if not args.no_cpu_baseline and args.cpu_frames > 0:
         t = time.time()
@@ -224,7 +391,7 @@ def main():
                                "IMU 200 Hz, procedural 3-plane/4-sphere scene", "width": 640, "height": 480,
                    "levels": 3, "iters": [10, 5, 4], "jac_format": "fp32", "frames": args.steps},
         "latency_ms": g["latency_ms"], "pose_err_final_m": g["pose_err_final_m"],
-        "roofline": g["roofline"], "cpu_baseline": cpu,
+        "roofline": g["roofline"], "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -308,6 +308,14 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
                                const dslam_frame_input* frames, void* stream);
 /* Wait for the batch's last step and copy its n results, in call order. */
 dslam_status dslam_batch_results(dslam_batch* b, dslam_track_result* out);
+/* Launch the batched residual pass of `level` of the batch's last step `reps`
+ * times back to back on `stream` (same sessions, transforms and work split;
+ * only the sessions' scratch partials are written, no estimator state
+ * changes).  *pixels (nullable) receives the pixels one launch processes.  For
+ * timing the pass with events on the caller's stream.  Asynchronous once the
+ * last step has completed. */
+dslam_status dslam_batch_profile_residual(dslam_batch* b, int32_t level, int32_t reps, void* stream,
+                                          uint64_t* pixels);
 
 /* Serving loop with continuous batching.  Frames of many sessions are
  * submitted as requests; each poll retires finished batched steps and

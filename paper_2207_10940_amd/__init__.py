@@ -342,6 +342,13 @@ class Batch:
         self._keep = (keep, frames)
         self._n = n
 
+    def profile_residual(self, level, reps, stream=None) -> int:
+        """Relaunch the last step's batched residual pass; returns the pixels per launch."""
+        px = C.c_uint64()
+        _check(lib().dslam_batch_profile_residual(self.handle, int(level), int(reps), _stream_ptr(stream),
+                                                  C.byref(px)), "dslam_batch_profile_residual")
+        return px.value
+
     def results(self) -> list:
         out = (_abi.TrackResult * self._n)()
         _check(lib().dslam_batch_results(self.handle, out), "dslam_batch_results")

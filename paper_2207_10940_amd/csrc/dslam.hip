@@ -572,10 +572,18 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
       HIP_OK(launch_pyramid_batch(b->d_vis, g, l, which, st));
     }
   HIP_OK(launch_frame_init_batch(b->d_solve, n, st));
+  b->levels = s0->levels;
   for (int l = s0->levels - 1; l >= 0; --l) {
     int max_ppt = 1;
-    for (int k = 0; k < n; ++k) max_ppt = std::max(max_ppt, sessions[k]->ppt[l]);
+    uint64_t px = 0;
+    for (int k = 0; k < n; ++k) {
+      max_ppt = std::max(max_ppt, sessions[k]->ppt[l]);
+      px += (uint64_t)sessions[k]->cur[l].W * sessions[k]->cur[l].H;
+    }
     BatchGrid g = grid([&](const dslam_session* s) { return residual_blocks(s->cur[l].W * s->cur[l].H, s->ppt[l]); });
+    b->res_grid[l] = g;
+    b->max_ppt[l] = max_ppt;
+    b->pixels[l] = px;
     for (int it = 0; it < s0->tp.iters[l]; ++it) {
       HIP_OK(launch_residual_batch(b->d_vis, g, l, max_ppt, st));
       const int last = (l == last_level && it == s0->tp.iters[l] - 1) ? 1 : 0;
@@ -593,6 +601,17 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
   }
   b->n = n;
   b->pending = true;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_batch_profile_residual(dslam_batch* b, int32_t level, int32_t reps, void* stream,
+                                          uint64_t* pixels) {
+  if (!b || !b->pending || level < 0 || level >= b->levels || reps < 1 || reps > 100000) return DSLAM_ERR_INVALID;
+  HIP_OK(hipSetDevice(b->ctx->device));
+  HIP_OK(hipEventSynchronize(b->done));
+  hipStream_t st = (hipStream_t)stream;
+  for (int r = 0; r < reps; ++r) HIP_OK(launch_residual_batch(b->d_vis, b->res_grid[level], level, b->max_ppt[level], st));
+  if (pixels) *pixels = b->pixels[level];
   return DSLAM_OK;
 }
 

@@ -137,16 +137,17 @@ def frame_pair(seed: int = 1001, width: int = 160, height: int = 120, *, noisy_i
 
 
 def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: int = 480, *, fps: float = 30.0,
-             imu_rate: float = 200.0, device="cpu", low_texture_every: int = 0) -> dict:
+             imu_rate: float = 200.0, device="cpu", low_texture_every: int = 0, duration: float | None = None) -> dict:
     """Plain method, single session: a seeded smooth B-spline trajectory (peak
     1.5 m/s, 180 deg/s), IMU at 200 Hz with random-walk biases.  Frame j is
     rendered at its ground-truth pose with depth noise; the model view used to
     track frame j is the noise-free render at frame j-1's ground-truth pose."""
     rng = np.random.default_rng(seed)
     scene = make_scene(rng, seed)
-    # the trajectory and the IMU stream always span the full 10 s sequence, so a
-    # shorter sequence is a prefix of the long one
-    duration = max((n_frames + 1) / fps, SEQUENCE_SECONDS)
+    # by default the trajectory and the IMU stream span the full 10 s sequence, so
+    # a shorter sequence is a prefix of the long one; an explicit duration (the
+    # serving workload's many short sessions) trades that for generation time
+    duration = max((n_frames + 1) / fps, SEQUENCE_SECONDS if duration is None else duration)
     traj = make_spline_trajectory(rng, duration)
     cam = camera_for(width, height)
     gen = torch.Generator(device="cpu").manual_seed(seed)
