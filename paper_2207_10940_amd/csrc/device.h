@@ -42,6 +42,8 @@ struct ResidualArgs {
   const float* xf;   // device, 24 floats: Ra-I, ta, Rb-I, tb
   float* partials;   // device, [gridDim.x][64] block sums
   uint8_t* mask;     // device, optional
+  int32_t jac;       // DSLAM_JAC_*: how the per-pixel terms are reduced
+  float col_scale[2];  // precision form: power-of-two scale of the ICP / photometric row entries
 };
 
 enum { RES_THREADS = 256, PARTIAL_STRIDE = 64, SOLVE_THREADS = 256 };

@@ -52,7 +52,8 @@ bool params_ok(const dslam_camera* cam, const dslam_track_params* tp) {
   for (int l = 0; l < tp->levels; ++l)
     if (tp->iters[l] < 0 || tp->iters[l] > 1000) return false;
   if (tp->mode != DSLAM_MODE_RGBDI && tp->mode != DSLAM_MODE_RGBD) return false;
-  if (tp->jac_format != DSLAM_JAC_FP32) return false;
+  if (tp->jac_format != DSLAM_JAC_FP32 && tp->jac_format != DSLAM_JAC_FP16 && tp->jac_format != DSLAM_JAC_BF16)
+    return false;
   if (!(tp->icp_dist > 0) || !(tp->icp_cos <= 1) || !(tp->sigma_I > 0) ||
       !(tp->depth_k > 0) || !(tp->huber_k >= 0))
     return false;
@@ -102,6 +103,9 @@ ImuParamsD imu_params_d(const dslam_imu_params& ip) {
   return d;
 }
 
+// Nearest depth (metres) for which the FP16 row scales keep every entry in range.
+constexpr double kFp16MinDepth = 0.25;
+
 int default_ppt(int npix) { return npix >= 600000 ? 4 : (npix >= 150000 ? 2 : 1); }
 
 ResidualArgs residual_args(dslam_session* s, int l, const float* xf, uint8_t* mask) {
@@ -124,6 +128,21 @@ ResidualArgs residual_args(dslam_session* s, int l, const float* xf, uint8_t* ma
   a.xf = xf;
   a.partials = s->partials;
   a.mask = mask;
+  a.jac = s->tp.jac_format;
+  a.col_scale[0] = a.col_scale[1] = 1.0f;
+  if (a.jac == DSLAM_JAC_FP16) {
+    // Power-of-two scales that bring each term's largest possible row entry
+    // to about 2^14 (FP16 overflows above 65504), from bounds at the nearest
+    // depth the scales are sized for (entries beyond saturate):
+    //   ICP: sqrt(W) = 1/(k z^2), |j| <= max(1, |p|) with |p| <= 1.5 z;
+    //   photometric: sqrt(W) = 1/sigma_I, |j| <= 255 fx_l / z (gradient times
+    //   projection Jacobian; the rotational part is bounded by the same).
+    const double zmin = kFp16MinDepth;
+    const double b_icp = std::max(1.0, 1.5 * zmin) / (s->tp.depth_k * zmin * zmin);
+    const double b_rgb = 255.0 * c.fx / (s->tp.sigma_I * zmin);
+    a.col_scale[0] = (float)std::ldexp(1.0, 14 - (int)std::ceil(std::log2(b_icp)));
+    a.col_scale[1] = (float)std::ldexp(1.0, 14 - (int)std::ceil(std::log2(b_rgb)));
+  }
   return a;
 }
 
@@ -485,7 +504,8 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
   for (int i = 0; i < n; ++i) {
     const dslam_session* s = sessions[i];
     const dslam_frame_input& f = frames[i];
-    if (!s || s->ctx != b->ctx || s->levels != s0->levels) return DSLAM_ERR_INVALID;
+    if (!s || s->ctx != b->ctx || s->levels != s0->levels || s->tp.jac_format != s0->tp.jac_format)
+      return DSLAM_ERR_INVALID;
     for (int l = 0; l < s->levels; ++l)
       if (s->tp.iters[l] != s0->tp.iters[l]) return DSLAM_ERR_INVALID;
     for (int j = 0; j < i; ++j)
@@ -573,6 +593,7 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
     }
   HIP_OK(launch_frame_init_batch(b->d_solve, n, st));
   b->levels = s0->levels;
+  b->jac = s0->tp.jac_format;
   for (int l = s0->levels - 1; l >= 0; --l) {
     int max_ppt = 1;
     uint64_t px = 0;
@@ -585,7 +606,7 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
     b->max_ppt[l] = max_ppt;
     b->pixels[l] = px;
     for (int it = 0; it < s0->tp.iters[l]; ++it) {
-      HIP_OK(launch_residual_batch(b->d_vis, g, l, max_ppt, st));
+      HIP_OK(launch_residual_batch(b->d_vis, g, l, max_ppt, s0->tp.jac_format, st));
       const int last = (l == last_level && it == s0->tp.iters[l] - 1) ? 1 : 0;
       HIP_OK(launch_solve_batch(b->d_solve, n, l, last, st));
     }
@@ -610,7 +631,8 @@ dslam_status dslam_batch_profile_residual(dslam_batch* b, int32_t level, int32_t
   HIP_OK(hipSetDevice(b->ctx->device));
   HIP_OK(hipEventSynchronize(b->done));
   hipStream_t st = (hipStream_t)stream;
-  for (int r = 0; r < reps; ++r) HIP_OK(launch_residual_batch(b->d_vis, b->res_grid[level], level, b->max_ppt[level], st));
+  for (int r = 0; r < reps; ++r)
+    HIP_OK(launch_residual_batch(b->d_vis, b->res_grid[level], level, b->max_ppt[level], b->jac, st));
   if (pixels) *pixels = b->pixels[level];
   return DSLAM_OK;
 }

@@ -55,6 +55,7 @@ struct dslam_batch {
   int n;
   int order[dslam::MAX_BATCH];        // slot -> caller index
   int levels;                         // of the last step
+  int jac;
   int max_ppt[DSLAM_MAX_LEVELS];
   dslam::BatchGrid res_grid[DSLAM_MAX_LEVELS];  // residual work split of the last step
   uint64_t pixels[DSLAM_MAX_LEVELS];            // pixels per residual pass of the last step

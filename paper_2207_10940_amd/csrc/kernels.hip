@@ -155,7 +155,35 @@ __device__ __forceinline__ void accumulate(float* acc, const float* jv, float e,
 
 __device__ __forceinline__ float huber(float s, float k) { return (k > 0.0f && s > k) ? k / s : 1.0f; }
 
-__device__ __forceinline__ void pixel(const ResidualArgs& a, const float* T, int p, float* acc) {
+// Per-pixel sinks of the two residual terms: the plain form accumulates the
+// 2 x 29 sums per thread; the precision form keeps the pixel's 16-entry row
+// [sqrt(w) j_icp (6), sqrt(w) e_icp, sqrt(w) j_rgb (6), sqrt(w) e_rgb, 0, 0].
+struct SumSink {
+  float* acc;
+  __device__ __forceinline__ void icp(const float* jv, float e, float w) { accumulate(acc, jv, e, w); }
+  __device__ __forceinline__ void rgb(const float* jv, float e, float w) { accumulate(acc + 29, jv, e, w); }
+};
+
+struct RowSink {
+  float r[16];
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) r[c] = 0.0f;
+  }
+  __device__ __forceinline__ void put(int o, const float* jv, float e, float w) {
+    const float s = __builtin_sqrtf(w);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) r[o + c] = s * jv[c];
+    r[o + 6] = s * e;
+  }
+  __device__ __forceinline__ void icp(const float* jv, float e, float w) { put(0, jv, e, w); }
+  __device__ __forceinline__ void rgb(const float* jv, float e, float w) { put(7, jv, e, w); }
+};
+
+// Association, residuals and Jacobians of pixel p; returns the inlier bits
+// (1 = ICP, 2 = photometric) and hands each inlier term to the sink.
+template <class Sink>
+__device__ __forceinline__ unsigned pixel(const ResidualArgs& a, const float* T, int p, Sink& sink) {
   const float x = a.cV0[p], y = a.cV1[p], z = a.cV2[p];
   uint8_t bits = 0;
   if (z > 0.0f) {
@@ -194,7 +222,7 @@ __device__ __forceinline__ void pixel(const ResidualArgs& a, const float* T, int
           float isg = 1.0f / (a.depth_k * z * z);
           float s = fabsf(e) * isg;
           float w = isg * isg * huber(s, a.huber_k);
-          accumulate(acc, jv, e, w);
+          sink.icp(jv, e, w);
           bits |= 1;
         }
       }
@@ -224,12 +252,13 @@ __device__ __forceinline__ void pixel(const ResidualArgs& a, const float* T, int
         float jv[6] = {gfx, gfy, g2, fmaf(py, g2, -pz * gfy), fmaf(pz, gfx, -px * g2), fmaf(px, gfy, -py * gfx)};
         float s = fabsf(e) / a.sigma_I;
         float w = huber(s, a.huber_k) / (a.sigma_I * a.sigma_I);
-        accumulate(acc + 29, jv, e, w);
+        sink.rgb(jv, e, w);
         bits |= 2;
       }
     }
   }
   if (a.mask) a.mask[p] = bits;
+  return bits;
 }
 
 // ---- wavefront reduction ---------------------------------------------------
@@ -301,7 +330,8 @@ __device__ __forceinline__ void residual_block(const ResidualArgs& a, int blk, i
 #pragma unroll
   for (int k = 0; k < PMAX; ++k) {
     int p = base + k * RES_THREADS;
-    if (k < ppt && p < a.npix) pixel(a, T, p, acc);
+    SumSink sink{acc};
+    if (k < ppt && p < a.npix) pixel(a, T, p, sink);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float tot = wave_transpose_sum(acc, lane);
@@ -315,9 +345,126 @@ __device__ __forceinline__ void residual_block(const ResidualArgs& a, int blk, i
   }
 }
 
+// ---- precision form: Jacobian rows in FP16 / BF16, J^T J on MFMA ----------
+// Every pixel yields the 16-entry row q = [sqrt(w) j_icp, sqrt(w) e_icp,
+// sqrt(w) j_rgb, sqrt(w) e_rgb, 0, 0] (zero for a term that is not an inlier),
+// scaled per term by a power of two and rounded to 16 bits.  The Gram matrix
+// G = sum q q^T holds both terms' sums in its two 7x7 diagonal blocks:
+// G[a][b] = sum w j_a j_b, G[a][6] = sum w j_a e, G[6][6] = sum w e^2.
+// v_mfma_f32_16x16x32_{f16,bf16} computes D = A B + C with lane l holding
+// A[l % 16][8 (l / 16) + 0..7] and B[8 (l / 16) + 0..7][l % 16]; with
+// A = Q^T (16 x 32 pixels) and B = Q the two operands of a lane are the same
+// eight values (entry l % 16 of eight pixels), and D = Q^T Q accumulates in
+// float32, lane l holding D[4 (l / 16) + r][l % 16], r = 0..3.  Rows reach
+// the operand layout through a per-wave transpose in LDS.  Inlier counts come
+// from ballots, so they are exact.
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+enum { STAGE_PITCH = 64 + 8 };  // 16-bit entries per staged column (padding spreads LDS banks)
+
+template <int FMT>
+__device__ __forceinline__ uint16_t to16(float x) {
+  if (FMT == DSLAM_JAC_FP16) {
+    // saturate instead of overflowing to infinity (entries are scaled to stay far below)
+    x = __builtin_fminf(__builtin_fmaxf(x, -65504.0f), 65504.0f);
+    return __builtin_bit_cast(uint16_t, (_Float16)x);
+  }
+  return __builtin_bit_cast(uint16_t, (__bf16)x);
+}
+
+template <int FMT>
+__device__ __forceinline__ f32x4_t mfma_gram(uint4 v, f32x4_t c) {
+  if (FMT == DSLAM_JAC_FP16) {
+    const half8_t h = __builtin_bit_cast(half8_t, v);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(h, h, c, 0, 0, 0);
+  }
+  const bf16x8_t h = __builtin_bit_cast(bf16x8_t, v);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, h, c, 0, 0, 0);
+}
+
+template <int PMAX, int FMT>
+__device__ __forceinline__ void residual_block_mfma(const ResidualArgs& a, int blk, int ppt) {
+  __shared__ __attribute__((aligned(16))) uint16_t stage[RES_THREADS / 64][16 * STAGE_PITCH];
+  __shared__ float gram[RES_THREADS / 64][16][17];
+  __shared__ int counts[RES_THREADS / 64][2];
+  float T[24];
+#pragma unroll
+  for (int k = 0; k < 24; ++k) T[k] = a.xf[k];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint16_t* st = stage[wave];
+  const float s_icp = a.col_scale[0], s_rgb = a.col_scale[1];
+  f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  int n_icp = 0, n_rgb = 0;
+  const int base = blk * RES_THREADS * ppt + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < PMAX; ++k) {
+    if (k < ppt) {  // uniform across the workgroup
+      const int p = base + k * RES_THREADS;
+      RowSink row;
+      row.clear();
+      unsigned bits = 0;
+      if (p < a.npix) bits = pixel(a, T, p, row);
+      n_icp += __builtin_popcountll(__ballot(bits & 1));
+      n_rgb += __builtin_popcountll(__ballot(bits & 2));
+#pragma unroll
+      for (int c = 0; c < 16; ++c) st[c * STAGE_PITCH + lane] = to16<FMT>(row.r[c] * (c < 7 ? s_icp : s_rgb));
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const uint4 v = *reinterpret_cast<const uint4*>(st + (lane & 15) * STAGE_PITCH + 32 * m + 8 * (lane >> 4));
+        acc = mfma_gram<FMT>(v, acc);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) gram[wave][4 * (lane >> 4) + r][lane & 15] = acc[r];
+  if (lane == 0) {
+    counts[wave][0] = n_icp;
+    counts[wave][1] = n_rgb;
+  }
+  __syncthreads();
+  if (threadIdx.x < 58) {
+    const int term = threadIdx.x / 29, q = threadIdx.x % 29, o = 7 * term;
+    int i = o + 6, j = o + 6;  // q == 27: sum w e^2
+    if (q < 21) {              // upper triangle of the 6x6 block, row-major
+      int r = 0, rem = q;
+      while (rem >= 6 - r) {
+        rem -= 6 - r;
+        ++r;
+      }
+      i = o + r;
+      j = o + r + rem;
+    } else if (q < 27) {
+      i = o + (q - 21);
+    }
+    float v;
+    if (q == 28) {
+      int n = 0;
+#pragma unroll
+      for (int w = 0; w < RES_THREADS / 64; ++w) n += counts[w][term];
+      v = (float)n;
+    } else {
+      v = gram[0][i][j];
+#pragma unroll
+      for (int w = 1; w < RES_THREADS / 64; ++w) v += gram[w][i][j];
+      const float inv = 1.0f / (term ? s_rgb : s_icp);  // exact: powers of two
+      v = v * inv * inv;
+    }
+    a.partials[(size_t)blk * PARTIAL_STRIDE + threadIdx.x] = v;
+  }
+}
+
 template <int PPT>
 __global__ __launch_bounds__(RES_THREADS) void residual_kernel(ResidualArgs a) {
   residual_block<PPT>(a, blockIdx.x, PPT);
+}
+
+template <int PPT, int FMT>
+__global__ __launch_bounds__(RES_THREADS) void residual_mfma_kernel(ResidualArgs a) {
+  residual_block_mfma<PPT, FMT>(a, blockIdx.x, PPT);
 }
 
 // Batched: one launch runs one residual pass of every session of the batch.
@@ -328,6 +475,16 @@ __global__ __launch_bounds__(RES_THREADS) void residual_batch_kernel(const SlotV
   const SlotVis* sv = slots + slot;
   const ResidualArgs a = sv->res[level];
   residual_block<PMAX>(a, b, sv->ppt[level]);
+}
+
+template <int PMAX, int FMT>
+__global__ __launch_bounds__(RES_THREADS) void residual_batch_mfma_kernel(const SlotVis* slots, BatchGrid g,
+                                                                          int level) {
+  int slot, b;
+  batch_locate(g, blockIdx.x, &slot, &b);
+  const SlotVis* sv = slots + slot;
+  const ResidualArgs a = sv->res[level];
+  residual_block_mfma<PMAX, FMT>(a, b, sv->ppt[level]);
 }
 
 }  // namespace dslam
@@ -357,21 +514,50 @@ hipError_t launch_pyramid_batch(const SlotVis* slots, const BatchGrid& g, int le
   return hipGetLastError();
 }
 
-hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, hipStream_t st) {
-  const dim3 grid(g.first_block[g.nclass]);
+template <int FMT>
+hipError_t launch_residual_batch_fmt(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt,
+                                     hipStream_t st) {
+  const dim3 grid(g.first_block[g.nclass]), blk(RES_THREADS);
+  auto k1 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<1> : residual_batch_mfma_kernel<1, FMT>;
+  auto k2 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<2> : residual_batch_mfma_kernel<2, FMT>;
+  auto k4 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<4> : residual_batch_mfma_kernel<4, FMT>;
   switch (max_ppt) {
-    case 1: hipLaunchKernelGGL(residual_batch_kernel<1>, grid, dim3(RES_THREADS), 0, st, slots, g, level); break;
-    case 2: hipLaunchKernelGGL(residual_batch_kernel<2>, grid, dim3(RES_THREADS), 0, st, slots, g, level); break;
-    case 4: hipLaunchKernelGGL(residual_batch_kernel<4>, grid, dim3(RES_THREADS), 0, st, slots, g, level); break;
+    case 1: hipLaunchKernelGGL(k1, grid, blk, 0, st, slots, g, level); break;
+    case 2: hipLaunchKernelGGL(k2, grid, blk, 0, st, slots, g, level); break;
+    case 4: hipLaunchKernelGGL(k4, grid, blk, 0, st, slots, g, level); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, int jac,
+                                 hipStream_t st) {
+  switch (jac) {
+    case DSLAM_JAC_FP32: return launch_residual_batch_fmt<DSLAM_JAC_FP32>(slots, g, level, max_ppt, st);
+    case DSLAM_JAC_FP16: return launch_residual_batch_fmt<DSLAM_JAC_FP16>(slots, g, level, max_ppt, st);
+    case DSLAM_JAC_BF16: return launch_residual_batch_fmt<DSLAM_JAC_BF16>(slots, g, level, max_ppt, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 int residual_blocks(int npix, int ppt) { return (npix + RES_THREADS * ppt - 1) / (RES_THREADS * ppt); }
 
 hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st) {
   int nb = residual_blocks(a.npix, ppt);
+  if (a.jac == DSLAM_JAC_FP16 || a.jac == DSLAM_JAC_BF16) {
+    const bool h = a.jac == DSLAM_JAC_FP16;
+    auto k1 = h ? residual_mfma_kernel<1, DSLAM_JAC_FP16> : residual_mfma_kernel<1, DSLAM_JAC_BF16>;
+    auto k2 = h ? residual_mfma_kernel<2, DSLAM_JAC_FP16> : residual_mfma_kernel<2, DSLAM_JAC_BF16>;
+    auto k4 = h ? residual_mfma_kernel<4, DSLAM_JAC_FP16> : residual_mfma_kernel<4, DSLAM_JAC_BF16>;
+    switch (ppt) {
+      case 1: hipLaunchKernelGGL(k1, dim3(nb), dim3(RES_THREADS), 0, st, a); break;
+      case 2: hipLaunchKernelGGL(k2, dim3(nb), dim3(RES_THREADS), 0, st, a); break;
+      case 4: hipLaunchKernelGGL(k4, dim3(nb), dim3(RES_THREADS), 0, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  if (a.jac != DSLAM_JAC_FP32) return hipErrorInvalidValue;
   switch (ppt) {
     case 1: hipLaunchKernelGGL(residual_kernel<1>, dim3(nb), dim3(RES_THREADS), 0, st, a); break;
     case 2: hipLaunchKernelGGL(residual_kernel<2>, dim3(nb), dim3(RES_THREADS), 0, st, a); break;

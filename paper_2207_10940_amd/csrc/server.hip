@@ -47,7 +47,7 @@ struct StepSlot {
 };
 
 bool same_schedule(const dslam_session* a, const dslam_session* b) {
-  if (a->levels != b->levels) return false;
+  if (a->levels != b->levels || a->tp.jac_format != b->tp.jac_format) return false;
   for (int l = 0; l < a->levels; ++l)
     if (a->tp.iters[l] != b->tp.iters[l]) return false;
   return true;

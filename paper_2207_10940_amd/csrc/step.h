@@ -48,7 +48,8 @@ int residual_blocks(int npix, int ppt);
 hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st);
 // which: 0 current frame, 1 model view
 hipError_t launch_pyramid_batch(const SlotVis* slots, const BatchGrid& g, int level, int which, hipStream_t st);
-hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, hipStream_t st);
+hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, int jac,
+                                 hipStream_t st);
 
 // solve.hip
 hipError_t launch_frame_init(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, hipStream_t st);

@@ -59,8 +59,8 @@ def seq_frame(seq, j):
             "imu": imu, "t0": t0, "t1": t1}
 
 
-def open_seq_session(ctx, seq, mode, iters=(4, 3, 2)):
-    tp = P.track_params(levels=len(iters), iters=iters, mode=mode)
+def open_seq_session(ctx, seq, mode, iters=(4, 3, 2), jac="fp32"):
+    tp = P.track_params(levels=len(iters), iters=iters, mode=mode, jac=jac)
     prior = seq["prior"] if mode != "rgbd" else None
     return P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], prior)
 

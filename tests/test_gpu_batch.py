@@ -6,7 +6,7 @@ import pytest
 
 import paper_2207_10940_amd as P
 import synth
-from gpu_common import open_seq_session as _open, same_result as _same, seq_frame as _frame
+from tests.gpu_common import open_seq_session as _open, same_result as _same, seq_frame as _frame
 
 pytestmark = pytest.mark.gpu
 
@@ -18,7 +18,8 @@ SESSIONS = [(3101, 160, 120, "rgbdi"), (3102, 320, 240, "rgbdi"), (3103, 160, 12
 STEPS = [[0, 1, 2, 3, 4], [1, 3], [0, 2, 3, 4], [4, 0, 1], [2, 1, 0, 3, 4]]
 
 
-def test_batched_results_equal_alone_results():
+@pytest.mark.parametrize("jac", ["fp32", "bf16"])
+def test_batched_results_equal_alone_results(jac):
     import torch
     seqs = [synth.configs.sequence(seed=s, n_frames=8, width=w, height=h, device="cuda") for s, w, h, _ in SESSIONS]
     stream = torch.cuda.current_stream()
@@ -26,7 +27,7 @@ def test_batched_results_equal_alone_results():
     ctx = P.Context(0)
     alone = []
     for idx, (seq, (_, _, _, mode)) in enumerate(zip(seqs, SESSIONS)):
-        s = _open(ctx, seq, mode)
+        s = _open(ctx, seq, mode, jac=jac)
         res = []
         count = sum(1 for st in STEPS if idx in st)
         for j in range(1, count + 1):
@@ -37,7 +38,7 @@ def test_batched_results_equal_alone_results():
         alone.append(res)
         s.close()
     # batched: the composition changes from step to step
-    sess = [_open(ctx, seq, mode) for seq, (_, _, _, mode) in zip(seqs, SESSIONS)]
+    sess = [_open(ctx, seq, mode, jac=jac) for seq, (_, _, _, mode) in zip(seqs, SESSIONS)]
     batch = P.Batch(ctx, len(SESSIONS))
     nxt = [1] * len(SESSIONS)
     for step, members in enumerate(STEPS):

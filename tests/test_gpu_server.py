@@ -7,7 +7,7 @@ import pytest
 
 import paper_2207_10940_amd as P
 import synth
-from gpu_common import open_seq_session, same_result, seq_frame
+from tests.gpu_common import open_seq_session, same_result, seq_frame
 
 pytestmark = pytest.mark.gpu
 
