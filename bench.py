@@ -30,7 +30,10 @@ COPY_BYTES = 256 << 20  # calibration copy for the HBM byte counters
 # reading of a 256 MiB copy (fetch x1.99987, write x1.0); valid for the kernel source with this hash.
 TRAFFIC_BYTES_LEVEL0 = (8607.8 * 262144 / 131087.7 + 150.0) * 1024
 TRAFFIC_SOURCE_SHA256 = "66d802343b8670f1"
-REF_BYTES_PER_PIXEL = 52  # V1 12 + I1 4 + V0 12 + N0 12 + I0 4 + G0 8 per pixel-iteration (N1 unread: no normal gate)
+# bytes the residual pass reads per pixel-iteration: current vertex 12 + intensity 2, model-view vertex 12 +
+# normal 12 + intensity 2 + gradient 4 (16-bit fixed-point intensity and gradient; N1 unread without the
+# normal gate)
+REF_BYTES_PER_PIXEL = 44
 
 
 def log(msg):

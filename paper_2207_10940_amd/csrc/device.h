@@ -6,17 +6,23 @@
 
 namespace dslam {
 
-// One pyramid level: float32 planes of width W, height H, pitch W.
-// vertex V (x, y, z = depth), normal N (0 where invalid), intensity I and,
-// for the model view, the central-difference intensity gradient G.
+// One pyramid level: planes of width W, height H, pitch W.
+//   V: vertex (x, y, z = depth), 3 float32 planes;
+//   N: normal (3 float32 planes, 0 where invalid);
+//   I: intensity in fixed point, I * 64 as uint16 (exact: level l holds
+//      multiples of 4^-l <= 255 and l <= 3);
+//   G: model view only, the central-difference gradient * 128 as int16
+//      (exact for the same reason: multiples of 2^-(2l+1), |G| <= 127.5).
 struct LevelPtrs {
   float* V[3];
   float* N[3];
-  float* I;
-  float* G[2];
+  uint16_t* I;
+  int16_t* G[2];
   int W, H;
   float fx, fy, cx, cy;  // level intrinsics, float32
 };
+
+constexpr float kIntensityScale = 64.0f, kGradientScale = 128.0f;
 
 // Per-session estimator state resident in device memory.
 struct SessionDev {
@@ -34,8 +40,11 @@ struct SessionDev {
 
 // Arguments of one residual pass.
 struct ResidualArgs {
-  const float *cV0, *cV1, *cV2, *cN0, *cN1, *cN2, *cI;                  // current level
-  const float *mV0, *mV1, *mV2, *mN0, *mN1, *mN2, *mI, *mG0, *mG1;     // model level
+  const float *cV0, *cV1, *cV2, *cN0, *cN1, *cN2;   // current level
+  const uint16_t* cI;
+  const float *mV0, *mV1, *mV2, *mN0, *mN1, *mN2;   // model level
+  const uint16_t* mI;
+  const int16_t *mG0, *mG1;
   int W, H, npix;
   float fx, fy, cx, cy;
   float dist2, cosmin, depth_k, sigma_I, huber_k;

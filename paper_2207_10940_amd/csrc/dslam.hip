@@ -52,8 +52,7 @@ bool params_ok(const dslam_camera* cam, const dslam_track_params* tp) {
   for (int l = 0; l < tp->levels; ++l)
     if (tp->iters[l] < 0 || tp->iters[l] > 1000) return false;
   if (tp->mode != DSLAM_MODE_RGBDI && tp->mode != DSLAM_MODE_RGBD) return false;
-  if (tp->jac_format != DSLAM_JAC_FP32 && tp->jac_format != DSLAM_JAC_FP16 && tp->jac_format != DSLAM_JAC_BF16)
-    return false;
+  if (tp->jac_format < DSLAM_JAC_FP32 || tp->jac_format > DSLAM_JAC_BF16) return false;
   if (!(tp->icp_dist > 0) || !(tp->icp_cos <= 1) || !(tp->sigma_I > 0) ||
       !(tp->depth_k > 0) || !(tp->huber_k >= 0))
     return false;
@@ -82,7 +81,8 @@ Layout layout_for(const dslam_camera& c, int levels) {
   size_t planes = 0;
   for (int l = 0; l < levels; ++l) {
     size_t n = (size_t)(c.width >> l) * (c.height >> l);
-    planes += 16 * align256(n * sizeof(float));  // 7 current + 9 model planes
+    // current: V (3), N (3) float32 + I uint16; model: the same + G (2) int16
+    planes += 12 * align256(n * sizeof(float)) + 4 * align256(n * sizeof(uint16_t));
   }
   int nb = residual_blocks(c.width * c.height, 1);
   lo.planes = planes;
@@ -277,19 +277,19 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   }
   char* p = (char*)s->arena;
   for (int l = 0; l < s->levels; ++l) {
-    size_t bytes = align256((size_t)(cam->width >> l) * (cam->height >> l) * sizeof(float));
+    const size_t npx = (size_t)(cam->width >> l) * (cam->height >> l);
+    const size_t b32 = align256(npx * sizeof(float)), b16 = align256(npx * sizeof(uint16_t));
     LevelPtrs* C = &s->cur[l];
     LevelPtrs* M = &s->model[l];
     level_intrinsics(*cam, l, C);
     level_intrinsics(*cam, l, M);
-    for (int k = 0; k < 3; ++k) { C->V[k] = (float*)p; p += bytes; }
-    for (int k = 0; k < 3; ++k) { C->N[k] = (float*)p; p += bytes; }
-    C->I = (float*)p; p += bytes;
+    for (LevelPtrs* L : {C, M}) {
+      for (int k = 0; k < 3; ++k) { L->V[k] = (float*)p; p += b32; }
+      for (int k = 0; k < 3; ++k) { L->N[k] = (float*)p; p += b32; }
+      L->I = (uint16_t*)p; p += b16;
+    }
     C->G[0] = C->G[1] = nullptr;
-    for (int k = 0; k < 3; ++k) { M->V[k] = (float*)p; p += bytes; }
-    for (int k = 0; k < 3; ++k) { M->N[k] = (float*)p; p += bytes; }
-    M->I = (float*)p; p += bytes;
-    for (int k = 0; k < 2; ++k) { M->G[k] = (float*)p; p += bytes; }
+    for (int k = 0; k < 2; ++k) { M->G[k] = (int16_t*)p; p += b16; }
     s->ppt[l] = default_ppt(C->W * C->H);
   }
   s->partials = (float*)p; p += align256(lo.partial_floats * sizeof(float));
@@ -700,16 +700,24 @@ dslam_status dslam_copy_pyramid(dslam_session* s, int32_t which, int32_t level, 
   if (!s || !host_out || level < 0 || level >= s->levels) return DSLAM_ERR_INVALID;
   if (which != DSLAM_PYR_CURRENT && which != DSLAM_PYR_MODEL) return DSLAM_ERR_INVALID;
   const LevelPtrs& L = which == DSLAM_PYR_MODEL ? s->model[level] : s->cur[level];
-  const float* src = nullptr;
-  if (channel >= DSLAM_CH_VX && channel <= DSLAM_CH_VZ) src = L.V[channel - DSLAM_CH_VX];
-  else if (channel >= DSLAM_CH_NX && channel <= DSLAM_CH_NZ) src = L.N[channel - DSLAM_CH_NX];
-  else if (channel == DSLAM_CH_I) src = L.I;
-  else if ((channel == DSLAM_CH_GX || channel == DSLAM_CH_GY) && which == DSLAM_PYR_MODEL) src = L.G[channel - DSLAM_CH_GX];
-  if (!src) return DSLAM_ERR_INVALID;
+  const bool grad = channel == DSLAM_CH_GX || channel == DSLAM_CH_GY;
+  if (channel < DSLAM_CH_VX || channel > DSLAM_CH_GY || (grad && which != DSLAM_PYR_MODEL)) return DSLAM_ERR_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
   HIP_OK(hipDeviceSynchronize());
-  HIP_OK(hipMemcpy(host_out, src, (size_t)L.W * L.H * sizeof(float), hipMemcpyDeviceToHost));
+  const size_t n = (size_t)L.W * L.H;
+  if (channel >= DSLAM_CH_NX && channel <= DSLAM_CH_NZ) {
+    HIP_OK(hipMemcpy(host_out, L.N[channel - DSLAM_CH_NX], n * sizeof(float), hipMemcpyDeviceToHost));
+  } else if (channel >= DSLAM_CH_VX && channel <= DSLAM_CH_VZ) {
+    HIP_OK(hipMemcpy(host_out, L.V[channel - DSLAM_CH_VX], n * sizeof(float), hipMemcpyDeviceToHost));
+  } else {
+    std::vector<uint16_t> tmp(n);
+    const void* src = channel == DSLAM_CH_I ? (const void*)L.I : (const void*)L.G[channel - DSLAM_CH_GX];
+    HIP_OK(hipMemcpy(tmp.data(), src, n * sizeof(uint16_t), hipMemcpyDeviceToHost));
+    for (size_t q = 0; q < n; ++q)
+      host_out[q] = channel == DSLAM_CH_I ? (float)tmp[q] / kIntensityScale
+                                          : (float)(int16_t)tmp[q] / kGradientScale;
+  }
   return DSLAM_OK;
 }
 

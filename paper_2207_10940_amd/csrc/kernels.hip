@@ -33,9 +33,9 @@ struct Src0 {  // level 0 from the caller's images
   __device__ __forceinline__ float I(int i, int j) const { return (float)inten[(size_t)j * pitch + i]; }
 };
 
-struct SrcDown {  // level l+1 from level l's depth (V[2]) and intensity planes
+struct SrcDown {  // level l+1 from level l's depth and intensity planes
   const float* pd;
-  const float* pi;
+  const uint16_t* pi;
   int pw;
   __device__ __forceinline__ float D(int i, int j) const {
     const float* r0 = pd + (size_t)(2 * j) * pw + 2 * i;
@@ -51,9 +51,10 @@ struct SrcDown {  // level l+1 from level l's depth (V[2]) and intensity planes
     return n > 0.0f ? s / n : 0.0f;
   }
   __device__ __forceinline__ float I(int i, int j) const {
-    const float* r0 = pi + (size_t)(2 * j) * pw + 2 * i;
-    const float* r1 = r0 + pw;
-    return ((r0[0] + r0[1]) + (r1[0] + r1[1])) * 0.25f;
+    const uint16_t* r0 = pi + (size_t)(2 * j) * pw + 2 * i;
+    const uint16_t* r1 = r0 + pw;
+    const float s = 1.0f / kIntensityScale;
+    return (((float)r0[0] * s + (float)r0[1] * s) + ((float)r1[0] * s + (float)r1[1] * s)) * 0.25f;
   }
 };
 
@@ -69,7 +70,7 @@ __device__ __forceinline__ void pyramid_pixel(const Src& src, const LevelPtrs& L
   L.V[0][p] = vx;
   L.V[1][p] = vy;
   L.V[2][p] = d;
-  L.I[p] = inten;
+  L.I[p] = (uint16_t)(inten * kIntensityScale);
   float nx = 0.0f, ny = 0.0f, nz = 0.0f;
   if (i < L.W - 1 && j < L.H - 1) {
     float dr = src.D(i + 1, j), dd = src.D(i, j + 1);
@@ -98,8 +99,8 @@ __device__ __forceinline__ void pyramid_pixel(const Src& src, const LevelPtrs& L
       gx = (src.I(i + 1, j) - src.I(i - 1, j)) * 0.5f;
       gy = (src.I(i, j + 1) - src.I(i, j - 1)) * 0.5f;
     }
-    L.G[0][p] = gx;
-    L.G[1][p] = gy;
+    L.G[0][p] = (int16_t)(gx * kGradientScale);
+    L.G[1][p] = (int16_t)(gy * kGradientScale);
   }
 }
 
@@ -153,7 +154,11 @@ __device__ __forceinline__ void accumulate(float* acc, const float* jv, float e,
   acc[28] = acc[28] + 1.0f;
 }
 
-__device__ __forceinline__ float huber(float s, float k) { return (k > 0.0f && s > k) ? k / s : 1.0f; }
+// Value-layer reciprocal: hardware estimate (1 ulp).  No validity bit or
+// association depends on it (weights and Jacobian scalings only).
+__device__ __forceinline__ float rcp_v(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ float huber(float s, float k) { return (k > 0.0f && s > k) ? k * rcp_v(s) : 1.0f; }
 
 // Per-pixel sinks of the two residual terms: the plain form accumulates the
 // 2 x 29 sums per thread; the precision form keeps the pixel's 16-entry row
@@ -171,7 +176,7 @@ struct RowSink {
     for (int c = 0; c < 16; ++c) r[c] = 0.0f;
   }
   __device__ __forceinline__ void put(int o, const float* jv, float e, float w) {
-    const float s = __builtin_sqrtf(w);
+    const float s = __builtin_amdgcn_sqrtf(w);  // value layer: hardware square root
 #pragma unroll
     for (int c = 0; c < 6; ++c) r[o + c] = s * jv[c];
     r[o + 6] = s * e;
@@ -219,7 +224,7 @@ __device__ __forceinline__ unsigned pixel(const ResidualArgs& a, const float* T,
           float e = fmaf(n0x, ex, fmaf(n0y, ey, n0z * ez));
           float px = qx - T[9], py = qy - T[10], pz = qz - T[11];
           float jv[6] = {n0x, n0y, n0z, fmaf(py, n0z, -pz * n0y), fmaf(pz, n0x, -px * n0z), fmaf(px, n0y, -py * n0x)};
-          float isg = 1.0f / (a.depth_k * z * z);
+          float isg = rcp_v(a.depth_k * z * z);
           float s = fabsf(e) * isg;
           float w = isg * isg * huber(s, a.huber_k);
           sink.icp(jv, e, w);
@@ -242,16 +247,25 @@ __device__ __forceinline__ unsigned pixel(const ResidualArgs& a, const float* T,
         float au = u - fu, av = v - fv;
         int m = y0 * a.W + x0;
         float w00 = (1.0f - au) * (1.0f - av), w10 = au * (1.0f - av), w01 = (1.0f - au) * av, w11 = au * av;
-        float I0 = fmaf(w00, a.mI[m], fmaf(w10, a.mI[m + 1], fmaf(w01, a.mI[m + a.W], w11 * a.mI[m + a.W + 1])));
-        float gx = fmaf(w00, a.mG0[m], fmaf(w10, a.mG0[m + 1], fmaf(w01, a.mG0[m + a.W], w11 * a.mG0[m + a.W + 1])));
-        float gy = fmaf(w00, a.mG1[m], fmaf(w10, a.mG1[m + 1], fmaf(w01, a.mG1[m + a.W], w11 * a.mG1[m + a.W + 1])));
-        float e = I0 - a.cI[p];
+        // taps in fixed point; the power-of-two unscaling commutes with every
+        // rounding of the sum, so it is applied once to the interpolated values
+        auto I_ = [&](int q) { return (float)a.mI[q]; };
+        auto GX = [&](int q) { return (float)a.mG0[q]; };
+        auto GY = [&](int q) { return (float)a.mG1[q]; };
+        float I0 = fmaf(w00, I_(m), fmaf(w10, I_(m + 1), fmaf(w01, I_(m + a.W), w11 * I_(m + a.W + 1))));
+        float gx = fmaf(w00, GX(m), fmaf(w10, GX(m + 1), fmaf(w01, GX(m + a.W), w11 * GX(m + a.W + 1))));
+        float gy = fmaf(w00, GY(m), fmaf(w10, GY(m + 1), fmaf(w01, GY(m + a.W), w11 * GY(m + a.W + 1))));
+        I0 *= 1.0f / kIntensityScale;
+        gx *= 1.0f / kGradientScale;
+        gy *= 1.0f / kGradientScale;
+        float e = I0 - (float)a.cI[p] * (1.0f / kIntensityScale);
         float gfx = gx * a.fx * inv, gfy = gy * a.fy * inv;
         float g2 = -fmaf(gfx, rx, gfy * ry) * inv;
         float px = rx - T[21], py = ry - T[22], pz = rz - T[23];
         float jv[6] = {gfx, gfy, g2, fmaf(py, g2, -pz * gfy), fmaf(pz, gfx, -px * g2), fmaf(px, gfy, -py * gfx)};
-        float s = fabsf(e) / a.sigma_I;
-        float w = huber(s, a.huber_k) / (a.sigma_I * a.sigma_I);
+        const float isI = rcp_v(a.sigma_I);
+        float s = fabsf(e) * isI;
+        float w = huber(s, a.huber_k) * (isI * isI);
         sink.rgb(jv, e, w);
         bits |= 2;
       }
@@ -362,7 +376,16 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-enum { STAGE_PITCH = 64 + 8 };  // 16-bit entries per staged column (padding spreads LDS banks)
+// LDS staging of the rows, per wave one column of 64 pixels per row entry;
+// the padding spreads the transposed reads over the LDS banks.
+template <int FMT> struct Stage {
+  using T = uint16_t;
+  static constexpr int pitch = 64 + 8;
+};
+template <> struct Stage<DSLAM_JAC_FP32_MFMA> {
+  using T = float;
+  static constexpr int pitch = 64 + 4;
+};
 
 template <int FMT>
 __device__ __forceinline__ uint16_t to16(float x) {
@@ -384,16 +407,54 @@ __device__ __forceinline__ f32x4_t mfma_gram(uint4 v, f32x4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, h, c, 0, 0, 0);
 }
 
+// Contracts one wave's 64 staged rows into the Gram accumulator.
+template <int FMT>
+__device__ __forceinline__ f32x4_t gram_round(const typename Stage<FMT>::T* st, int lane, f32x4_t acc) {
+  constexpr int P = Stage<FMT>::pitch;
+  if constexpr (FMT == DSLAM_JAC_FP32_MFMA) {
+    // v_mfma_f32_16x16x4_f32: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
+    // MFMA m takes pixels m, 16 + m, 32 + m, 48 + m, so lane l needs entry l % 16
+    // of pixels 16 (l / 16) + 0..15: four 16-byte reads
+    const float* src = st + (lane & 15) * P + 16 * (lane >> 4);
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 t = *reinterpret_cast<const float4*>(src + 4 * q);
+      v[4 * q] = t.x;
+      v[4 * q + 1] = t.y;
+      v[4 * q + 2] = t.z;
+      v[4 * q + 3] = t.w;
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[m], v[m], acc, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const uint4 v = *reinterpret_cast<const uint4*>(st + (lane & 15) * P + 32 * m + 8 * (lane >> 4));
+      acc = mfma_gram<FMT>(v, acc);
+    }
+  }
+  return acc;
+}
+
+template <int FMT>
+__device__ __forceinline__ typename Stage<FMT>::T stage_entry(float x) {
+  if constexpr (FMT == DSLAM_JAC_FP32_MFMA) return x;
+  else return to16<FMT>(x);
+}
+
 template <int PMAX, int FMT>
 __device__ __forceinline__ void residual_block_mfma(const ResidualArgs& a, int blk, int ppt) {
-  __shared__ __attribute__((aligned(16))) uint16_t stage[RES_THREADS / 64][16 * STAGE_PITCH];
+  using ST = typename Stage<FMT>::T;
+  constexpr int P = Stage<FMT>::pitch;
+  __shared__ __attribute__((aligned(16))) ST stage[RES_THREADS / 64][16 * P];
   __shared__ float gram[RES_THREADS / 64][16][17];
   __shared__ int counts[RES_THREADS / 64][2];
   float T[24];
 #pragma unroll
   for (int k = 0; k < 24; ++k) T[k] = a.xf[k];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint16_t* st = stage[wave];
+  ST* st = stage[wave];
   const float s_icp = a.col_scale[0], s_rgb = a.col_scale[1];
   f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
   int n_icp = 0, n_rgb = 0;
@@ -409,13 +470,9 @@ __device__ __forceinline__ void residual_block_mfma(const ResidualArgs& a, int b
       n_icp += __builtin_popcountll(__ballot(bits & 1));
       n_rgb += __builtin_popcountll(__ballot(bits & 2));
 #pragma unroll
-      for (int c = 0; c < 16; ++c) st[c * STAGE_PITCH + lane] = to16<FMT>(row.r[c] * (c < 7 ? s_icp : s_rgb));
+      for (int c = 0; c < 16; ++c) st[c * P + lane] = stage_entry<FMT>(row.r[c] * (c < 7 ? s_icp : s_rgb));
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const uint4 v = *reinterpret_cast<const uint4*>(st + (lane & 15) * STAGE_PITCH + 32 * m + 8 * (lane >> 4));
-        acc = mfma_gram<FMT>(v, acc);
-      }
+      acc = gram_round<FMT>(st, lane, acc);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
   }
@@ -518,9 +575,10 @@ template <int FMT>
 hipError_t launch_residual_batch_fmt(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt,
                                      hipStream_t st) {
   const dim3 grid(g.first_block[g.nclass]), blk(RES_THREADS);
-  auto k1 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<1> : residual_batch_mfma_kernel<1, FMT>;
-  auto k2 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<2> : residual_batch_mfma_kernel<2, FMT>;
-  auto k4 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<4> : residual_batch_mfma_kernel<4, FMT>;
+  constexpr int M = FMT == DSLAM_JAC_FP32 ? DSLAM_JAC_FP32_MFMA : FMT;  // (the plain kernel takes no format)
+  auto k1 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<1> : residual_batch_mfma_kernel<1, M>;
+  auto k2 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<2> : residual_batch_mfma_kernel<2, M>;
+  auto k4 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<4> : residual_batch_mfma_kernel<4, M>;
   switch (max_ppt) {
     case 1: hipLaunchKernelGGL(k1, grid, blk, 0, st, slots, g, level); break;
     case 2: hipLaunchKernelGGL(k2, grid, blk, 0, st, slots, g, level); break;
@@ -534,6 +592,7 @@ hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int l
                                  hipStream_t st) {
   switch (jac) {
     case DSLAM_JAC_FP32: return launch_residual_batch_fmt<DSLAM_JAC_FP32>(slots, g, level, max_ppt, st);
+    case DSLAM_JAC_FP32_MFMA: return launch_residual_batch_fmt<DSLAM_JAC_FP32_MFMA>(slots, g, level, max_ppt, st);
     case DSLAM_JAC_FP16: return launch_residual_batch_fmt<DSLAM_JAC_FP16>(slots, g, level, max_ppt, st);
     case DSLAM_JAC_BF16: return launch_residual_batch_fmt<DSLAM_JAC_BF16>(slots, g, level, max_ppt, st);
     default: return hipErrorInvalidValue;
@@ -544,11 +603,15 @@ int residual_blocks(int npix, int ppt) { return (npix + RES_THREADS * ppt - 1) /
 
 hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st) {
   int nb = residual_blocks(a.npix, ppt);
-  if (a.jac == DSLAM_JAC_FP16 || a.jac == DSLAM_JAC_BF16) {
-    const bool h = a.jac == DSLAM_JAC_FP16;
-    auto k1 = h ? residual_mfma_kernel<1, DSLAM_JAC_FP16> : residual_mfma_kernel<1, DSLAM_JAC_BF16>;
-    auto k2 = h ? residual_mfma_kernel<2, DSLAM_JAC_FP16> : residual_mfma_kernel<2, DSLAM_JAC_BF16>;
-    auto k4 = h ? residual_mfma_kernel<4, DSLAM_JAC_FP16> : residual_mfma_kernel<4, DSLAM_JAC_BF16>;
+  if (a.jac == DSLAM_JAC_FP16 || a.jac == DSLAM_JAC_BF16 || a.jac == DSLAM_JAC_FP32_MFMA) {
+    const int f = a.jac;
+    auto pick = [f](auto k16, auto kb16, auto k32) { return f == DSLAM_JAC_FP16 ? k16 : (f == DSLAM_JAC_BF16 ? kb16 : k32); };
+    auto k1 = pick(residual_mfma_kernel<1, DSLAM_JAC_FP16>, residual_mfma_kernel<1, DSLAM_JAC_BF16>,
+                   residual_mfma_kernel<1, DSLAM_JAC_FP32_MFMA>);
+    auto k2 = pick(residual_mfma_kernel<2, DSLAM_JAC_FP16>, residual_mfma_kernel<2, DSLAM_JAC_BF16>,
+                   residual_mfma_kernel<2, DSLAM_JAC_FP32_MFMA>);
+    auto k4 = pick(residual_mfma_kernel<4, DSLAM_JAC_FP16>, residual_mfma_kernel<4, DSLAM_JAC_BF16>,
+                   residual_mfma_kernel<4, DSLAM_JAC_FP32_MFMA>);
     switch (ppt) {
       case 1: hipLaunchKernelGGL(k1, dim3(nb), dim3(RES_THREADS), 0, st, a); break;
       case 2: hipLaunchKernelGGL(k2, dim3(nb), dim3(RES_THREADS), 0, st, a); break;

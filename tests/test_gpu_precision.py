@@ -17,10 +17,11 @@ pytestmark = pytest.mark.gpu
 # relative bounds on J^T J (Frobenius), J^T r (against its normwise scale) and
 # the cost: the unit roundoff of the 16-bit format (FP16 4.9e-4, BF16 3.9e-3)
 # scaled by 0.6 -- rounding errors of many pixels average out
-BOUND = {"fp16": 3e-4, "bf16": 2.4e-3}
+BOUND = {"fp16": 3e-4, "bf16": 2.4e-3,
+         "fp32_mfma": 1e-5}  # float32 rows on v_mfma_f32_16x16x4_f32: the plain form's bar
 
 
-@pytest.mark.parametrize("jac", ["fp16", "bf16"])
+@pytest.mark.parametrize("jac", ["fp16", "bf16", "fp32_mfma"])
 @pytest.mark.parametrize("W,H,levels,seed", [(160, 120, 2, 1001), (200, 152, 3, 7), (640, 480, 3, 1002)])
 def test_precision_linearize(jac, W, H, levels, seed):
     import torch
@@ -51,10 +52,10 @@ def test_precision_linearize(jac, W, H, levels, seed):
                 ec = abs(g["cost_" + term] - vis["cost_" + term]) / vis["cost_" + term]
                 print(f"  level {l} {term}: JtJ vs oracle {eH:.2e} vs fp32 {eH32:.2e}  Jtr {eb:.2e}  cost {ec:.2e}",
                       flush=True)
-                assert eH < BOUND[jac] and eb < BOUND[jac] and ec < BOUND[jac], (l, term, eH, eb, ec)
+                assert eH < BOUND[jac] and eb < BOUND[jac] and ec < max(BOUND[jac], 1e-4), (l, term, eH, eb, ec)
 
 
-@pytest.mark.parametrize("jac", ["fp16", "bf16"])
+@pytest.mark.parametrize("jac", ["fp16", "bf16", "fp32_mfma"])
 @pytest.mark.parametrize("mode", ["rgbdi", "rgbd"])
 def test_precision_track_pair_recovers_pose(jac, mode):
     """Gauss-Newton iteration recovers what the 16-bit rows lose: the tracked
