@@ -55,7 +55,7 @@ struct ResidualArgs {
   float col_scale[2];  // precision form: power-of-two scale of the ICP / photometric row entries
 };
 
-enum { RES_THREADS = 256, PARTIAL_STRIDE = 64, SOLVE_THREADS = 256 };
+enum { RES_THREADS = 256, PARTIAL_STRIDE = 64, SOLVE_THREADS = 512 };
 
 // ---- batched steps: several sessions share every launch ---------------------
 enum { MAX_BATCH = 256, MAX_CLASSES = 16, PYR_TILE_W = 64, PYR_TILE_H = 4 };

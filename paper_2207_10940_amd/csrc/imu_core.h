@@ -365,26 +365,24 @@ struct ImuStage {
   V3 phib, dvt, dpt, ea, yr, yg, Sdv, QSdv;
 };
 
-#ifndef TASK
 // Independent serial tasks run on the first lane of different wavefronts
 // (concurrently on the device, one after the other on the host).
-#define TASK(t) if (par.lane == (((t) * 64 < par.nl) ? (t) * 64 : 0))
-#endif
+DX int task_lane(Par par, int t) { return t * 64 < par.nl ? t * 64 : 0; }
+#define TASK(t) if (par.lane == task_lane(par, (t)))
 
-// imu_common split over the first lanes of three wavefronts: the three
-// rotations and the bias-corrected preintegration first, then the residual,
-// then the Jacobian operands.  Same arithmetic as imu_common.  `side` runs on
-// a fourth wavefront during the last stage.
-template <class Side>
-DX void imu_common_par(Par par, const dslam_frame_state& x0, const dslam_frame_state& x1, const double* qIW,
-                       const dslam_preint& pre, const ImuParamsD& ip, double* e, ImuCommon* c, ImuStage* t,
-                       Side side) {
-  TASK(0) t->R0 = q2R(x0.q);
-  TASK(1) {
+// imu_common split into three stages over the first lanes of the wavefronts
+// tb, tb + 1, tb + 2 (and tb + 3 for `side`): the three rotations and the
+// bias-corrected preintegration first, then the residual, then the Jacobian
+// operands.  Same arithmetic as imu_common.  The caller separates the stages
+// by barriers (imu_common_par below, or a caller that interleaves other work).
+DX void imu_stage0(Par par, int tb, const dslam_frame_state& x0, const dslam_frame_state& x1, const double* qIW,
+                   const dslam_preint& pre, ImuStage* t) {
+  TASK(tb) t->R0 = q2R(x0.q);
+  TASK(tb + 1) {
     t->R1 = q2R(x1.q);
     t->Q = q2R(qIW);
   }
-  TASK(2) {
+  TASK(tb + 2) {
     double db[6];
     for (int i = 0; i < 3; ++i) {
       db[i] = x0.bg[i] - pre.bg[i];
@@ -408,8 +406,11 @@ DX void imu_common_par(Par par, const dslam_frame_state& x0, const dslam_frame_s
     t->Rb = Exp(t->phib);
     t->Jrb = Jr(t->phib);
   }
-  DSLAM_SYNC();
-  TASK(0) {
+}
+
+DX void imu_stage1(Par par, int tb, const dslam_frame_state& x0, const dslam_frame_state& x1,
+                   const dslam_preint& pre, const ImuParamsD& ip, double* e, ImuStage* t) {
+  TASK(tb) {
     M3 R0 = t->R0, Q = t->Q;
     M3 Rcs = load33(ip.R_CS);
     V3 tcs = load3(ip.t_CS);
@@ -444,16 +445,20 @@ DX void imu_common_par(Par par, const dslam_frame_state& x0, const dslam_frame_s
     t->Sdv = Sdv;
     t->QSdv = QSdv;
   }
-  DSLAM_SYNC();
+}
+
+template <class Side>
+DX void imu_stage2(Par par, int tb, const dslam_preint& pre, const ImuParamsD& ip, ImuCommon* c, ImuStage* t,
+                   Side side) {
   M3* m = c->mats;
-  TASK(0) {
+  TASK(tb) {
     M3 Jli = JlInv(t->ea);
     m[IC_JLI] = Jli;
     m[IC_KAL] = Jli * t->SdRt * t->Jrb;
     m[IC_JRI] = (-1.0) * tr(Jli);
     m[IC_JLI_SDRT] = Jli * t->SdRt;
   }
-  TASK(1) {
+  TASK(tb + 1) {
     M3 Rcs = load33(ip.R_CS);
     V3 wt = tr(Rcs) * load3(ip.t_CS);
     M3 hwt = hat(wt);
@@ -470,7 +475,7 @@ DX void imu_common_par(Par par, const dslam_frame_state& x0, const dslam_frame_s
     m[IC_KROT_NOISE] = t->SdRt * hwt;
     m[IC_RBT] = tr(t->Rb);
   }
-  TASK(2) {
+  TASK(tb + 2) {
     m[IC_I] = eye3();
     m[IC_NEG_I] = (-1.0) * eye3();
     for (int i = 0; i < 3; ++i)
@@ -484,7 +489,18 @@ DX void imu_common_par(Par par, const dslam_frame_state& x0, const dslam_frame_s
       }
     c->T = pre.dt;
   }
-  TASK(3) side();
+  TASK(tb + 3) side();
+}
+
+template <class Side>
+DX void imu_common_par(Par par, const dslam_frame_state& x0, const dslam_frame_state& x1, const double* qIW,
+                       const dslam_preint& pre, const ImuParamsD& ip, double* e, ImuCommon* c, ImuStage* t,
+                       Side side) {
+  imu_stage0(par, 0, x0, x1, qIW, pre, t);
+  DSLAM_SYNC();
+  imu_stage1(par, 0, x0, x1, pre, ip, e, t);
+  DSLAM_SYNC();
+  imu_stage2(par, 0, pre, ip, c, t, side);
   DSLAM_SYNC();
 }
 

@@ -82,13 +82,14 @@ DX V3 Log(const M3& R) {
   double th = acos(c);
   if (th < 1e-5) return (0.5 * (1.0 + th * th / 6.0)) * w;
   if (M_PI - th < 1e-6) {
-    int k = 0;
-    double best = R(0, 0);
-    if (R(1, 1) > best) { k = 1; best = R(1, 1); }
-    if (R(2, 2) > best) { k = 2; best = R(2, 2); }
-    double akk = 0.5 * (R(k, k) + 1.0);
-    V3 a = v3(0.5 * (R(0, k) + (k == 0 ? 1.0 : 0.0)), 0.5 * (R(1, k) + (k == 1 ? 1.0 : 0.0)),
-              0.5 * (R(2, k) + (k == 2 ? 1.0 : 0.0)));
+    // near pi: the axis from the column of R + I with the largest diagonal
+    // (columns picked by value, no run-time indexing of R)
+    const bool c1 = R(1, 1) > R(0, 0) && R(1, 1) >= R(2, 2);
+    const bool c2 = !c1 && R(2, 2) > R(0, 0);
+    V3 col = c2 ? v3(R(0, 2), R(1, 2), R(2, 2) + 1.0)
+                : (c1 ? v3(R(0, 1), R(1, 1) + 1.0, R(2, 1)) : v3(R(0, 0) + 1.0, R(1, 0), R(2, 0)));
+    V3 a = 0.5 * col;
+    const double akk = c2 ? a.z : (c1 ? a.y : a.x);
     a = (1.0 / sqrt(akk)) * a;
     return (th / norm(a)) * a;
   }

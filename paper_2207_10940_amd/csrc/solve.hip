@@ -9,10 +9,13 @@
 namespace dslam {
 
 // Fixed-order float64 sum of the block partials ([nblocks][64] floats, 58
-// used): thread t sums the float4 column group t % 16 over blocks t/16,
-// t/16 + 16, ...; the 16 partial sums of each column are then added in row
-// order.  Same order whatever the launch.  Needs SOLVE_THREADS == 256.
-__device__ void reduce_partials(const float* partials, int nblocks, double* red /*shared 16x64*/, double* out) {
+// used), in two steps separated by a barrier of the caller: reduce_rows has
+// thread t < REDUCE_THREADS sum the float4 column group t % 16 over blocks
+// t/16, t/16 + 16, ... into red (16 x 64 doubles); reduce_cols then adds the
+// 16 row sums of each column in row order.  Same order whatever the launch.
+enum { REDUCE_THREADS = 256 };
+
+__device__ __forceinline__ void reduce_rows(const float* partials, int nblocks, double* red) {
   const int g = threadIdx.x & 15, r = threadIdx.x >> 4;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   const float* base = partials + 4 * g;
@@ -40,24 +43,27 @@ __device__ void reduce_partials(const float* partials, int nblocks, double* red 
   red[r * 64 + 4 * g + 1] = s1;
   red[r * 64 + 4 * g + 2] = s2;
   red[r * 64 + 4 * g + 3] = s3;
-  __syncthreads();
+}
+
+__device__ __forceinline__ void reduce_cols(const double* red, double* out) {
   if (threadIdx.x < 58) {
     double acc = 0.0;
     for (int k = 0; k < 16; ++k) acc += red[k * 64 + threadIdx.x];
     out[threadIdx.x] = acc;
   }
-  __syncthreads();
 }
 
-__global__ __launch_bounds__(SOLVE_THREADS) void reduce_kernel(const float* partials, int nblocks, double* out) {
+__global__ __launch_bounds__(REDUCE_THREADS) void reduce_kernel(const float* partials, int nblocks, double* out) {
   __shared__ double red[16 * 64];
-  reduce_partials(partials, nblocks, red, out);
+  reduce_rows(partials, nblocks, red);
+  __syncthreads();
+  reduce_cols(red, out);
 }
 
 
 // Preintegrates the frame's IMU samples at x0's bias estimate and predicts x1
 // (Section IV-C); resets the frame's status and inlier counts.
-__device__ void frame_init_body(SessionDev* sd, const ImuBatch& batch, const FrameArgs& fa) {
+__device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& batch, const FrameArgs& fa) {
   __shared__ PreintWork pw;
   __shared__ dslam_preint pre;
   __shared__ dslam_frame_state x0;
@@ -100,7 +106,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void frame_init_batch_kernel(const S
 
 // One Gauss-Newton step of one session: reduce the block partials, solve,
 // update the states (and on the frame's last step marginalise and publish).
-__device__ void solve_body(SessionDev* sd, const float* partials, const SolveArgs& a) {
+__device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials, const SolveArgs& a) {
   __shared__ SolveWork w;
   __shared__ double raw[58];
   __shared__ dslam_frame_state x0, x1;
@@ -109,24 +115,22 @@ __device__ void solve_body(SessionDev* sd, const float* partials, const SolveArg
   __shared__ dslam_prior prior;
   __shared__ dslam_preint pre;
   __shared__ int skip;
+  __shared__ double red[16 * 64];
   Par par{(int)threadIdx.x, SOLVE_THREADS};
-  // stage the prior and the preintegrated measurement in shared memory (one
-  // coalesced pass) so the serial parts of the step never wait on global loads
+  // stage the states, the prior and the preintegrated measurement in shared
+  // memory (one coalesced pass) so the serial parts never wait on global loads
   {
-    const double* src = reinterpret_cast<const double*>(&sd->prior);
-    double* dst = reinterpret_cast<double*>(&prior);
-    for (int i = threadIdx.x; i < (int)(sizeof(dslam_prior) / 8); i += SOLVE_THREADS) dst[i] = src[i];
-    src = reinterpret_cast<const double*>(&sd->pre);
-    dst = reinterpret_cast<double*>(&pre);
-    for (int i = threadIdx.x; i < (int)(sizeof(dslam_preint) / 8); i += SOLVE_THREADS) dst[i] = src[i];
-  }
-  reduce_partials(partials, a.nblocks, w.L, raw);
-  if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
-  SERIAL {
-    skip = sd->status != DSLAM_OK;
-    x0 = sd->x0;
-    x1 = sd->x1;
-    for (int i = 0; i < 4; ++i) qIW[i] = sd->qIW[i];
+    auto copy = [](const void* from, void* to, int bytes) {
+      const double* src = reinterpret_cast<const double*>(from);
+      double* dst = reinterpret_cast<double*>(to);
+      for (int i = threadIdx.x; i < bytes / 8; i += SOLVE_THREADS) dst[i] = src[i];
+    };
+    copy(&sd->prior, &prior, sizeof(dslam_prior));
+    copy(&sd->pre, &pre, sizeof(dslam_preint));
+    copy(&sd->x0, &x0, sizeof(dslam_frame_state));
+    copy(&sd->x1, &x1, sizeof(dslam_frame_state));
+    copy(sd->qIW, qIW, sizeof(qIW));
+    SERIAL skip = sd->status != DSLAM_OK;
   }
   DSLAM_SYNC();
   if (skip) {
@@ -140,7 +144,23 @@ __device__ void solve_body(SessionDev* sd, const float* partials, const SolveArg
   }
   SolveParams sp = a.sp;
   sp.marginalise = a.last;
-  int st = solve_step(par, &w, raw, sp, &pre, &prior, &x0, &x1, qIW, &marg);
+  const bool full = sp.mode != DSLAM_MODE_RGBD;
+  // the first waves reduce the block partials while the IMU factor's operands,
+  // which depend on the states only, are computed on the first lanes of the
+  // last four waves (three stages, one barrier sequence for both)
+  constexpr int IMU_TASKS = SOLVE_THREADS / 64 - 4;
+  static_assert(SOLVE_THREADS >= REDUCE_THREADS + 256, "needs four spare waves");
+  if (threadIdx.x < REDUCE_THREADS) reduce_rows(partials, a.nblocks, red);
+  if (full) imu_stage0(par, IMU_TASKS, x0, x1, qIW, pre, &w.is);
+  DSLAM_SYNC();
+  reduce_cols(red, raw);
+  if (full) imu_stage1(par, IMU_TASKS, x0, x1, pre, sp.imu, w.e, &w.is);
+  DSLAM_SYNC();
+  if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
+  TASK(0) visual_front(&w, raw, sp, x0, x1);
+  if (full) imu_stage2(par, IMU_TASKS, pre, sp.imu, &w.ic, &w.is, [&]() { prior_delta(&w, &prior, x0, qIW); });
+  DSLAM_SYNC();
+  int st = solve_back(par, &w, sp, &pre, &prior, &x0, &x1, qIW, &marg);
   SERIAL {
     if (st != DSLAM_OK) {
       sd->status = st;
@@ -222,7 +242,7 @@ hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& 
 }
 
 hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, partials, nblocks, out);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(REDUCE_THREADS), 0, st, partials, nblocks, out);
   return hipGetLastError();
 }
 

@@ -278,31 +278,50 @@ DX int spd_solve(Par par, SolveWork* w, const double* H, const double* b, int n,
 // One Gauss-Newton step.  raw: the 58 sums of the residual pass (ICP then RGB),
 // taken at (x0, x1).  Updates x0, x1, qIW in place on success, writes the
 // marginal prior if sp.marginalise.  Returns a dslam_status.
+// The visual sums of one pass and the lift operators at the current states.
+DX void visual_front(SolveWork* w, const double* raw, const SolveParams& sp, const dslam_frame_state& x0,
+                     const dslam_frame_state& x1) {
+  unpack_term(raw, w->Hm[0], w->gm[0]);
+  unpack_term(raw + 29, w->Hm[1], w->gm[1]);
+  w->cost[0] = raw[27];
+  w->cost[1] = raw[29 + 27];
+  w->cost[2] = 0.0;
+  w->cost[3] = 0.0;
+  build_lift(sp.R_WM, x0, x1, w->Li, w->Lr);
+}
+
+// The prior's linearisation offset (x0, q_IW) [-] xbar.
+DX void prior_delta(SolveWork* w, const dslam_prior* prior, const dslam_frame_state& x0, const double* qIW) {
+  state_boxminus(x0, prior->xbar, w->prior_d);
+  V3 dg = qboxminus(qIW, prior->q_IW_bar);
+  w->prior_d[15] = dg.x;
+  w->prior_d[16] = dg.y;
+  w->prior_d[17] = dg.z;
+}
+
+// Everything of one step after the visual sums are unpacked and the IMU
+// factor's operands (imu_common) are computed: assembly, solve, update and
+// marginalisation.
+DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre, const dslam_prior* prior,
+                  dslam_frame_state* x0, dslam_frame_state* x1, double* qIW, dslam_prior* marg_out);
+
 DX int solve_step(Par par, SolveWork* w, const double* raw, const SolveParams& sp, const dslam_preint* pre,
                   const dslam_prior* prior, dslam_frame_state* x0, dslam_frame_state* x1, double* qIW,
                   dslam_prior* marg_out) {
+  // ---- independent serial set-up, spread over the first lanes of the wavefronts
+  TASK(3) visual_front(w, raw, sp, *x0, *x1);
+  if (sp.mode != DSLAM_MODE_RGBD)
+    imu_common_par(par, *x0, *x1, qIW, *pre, sp.imu, w->e, &w->ic, &w->is, [&]() { prior_delta(w, prior, *x0, qIW); });
+  else
+    DSLAM_SYNC();
+  return solve_back(par, w, sp, pre, prior, x0, x1, qIW, marg_out);
+}
+
+DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre, const dslam_prior* prior,
+                  dslam_frame_state* x0, dslam_frame_state* x1, double* qIW, dslam_prior* marg_out) {
   const bool full = sp.mode != DSLAM_MODE_RGBD;
   const int n = full ? NZ : 6;
   const bool marg = full && sp.marginalise && marg_out != nullptr;
-  // ---- independent serial set-up, spread over the first lanes of the wavefronts
-  TASK(3) {
-    unpack_term(raw, w->Hm[0], w->gm[0]);
-    unpack_term(raw + 29, w->Hm[1], w->gm[1]);
-    w->cost[0] = raw[27];
-    w->cost[1] = raw[29 + 27];
-    w->cost[2] = 0.0;
-    w->cost[3] = 0.0;
-    build_lift(sp.R_WM, *x0, *x1, w->Li, w->Lr);
-  }
-  if (full) {
-    imu_common_par(par, *x0, *x1, qIW, *pre, sp.imu, w->e, &w->ic, &w->is, [&]() {
-      state_boxminus(*x0, prior->xbar, w->prior_d);
-      V3 dg = qboxminus(qIW, prior->q_IW_bar);
-      w->prior_d[15] = dg.x;
-      w->prior_d[16] = dg.y;
-      w->prior_d[17] = dg.z;
-    });
-  }
   PFOR(i, NZ * NZ) w->H[i] = 0.0;
   PFOR(i, NZ) w->b[i] = 0.0;
   PFOR(i, 9 * NZ) w->J9[i] = 0.0;
