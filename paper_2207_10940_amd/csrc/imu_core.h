@@ -447,9 +447,11 @@ DX void imu_stage1(Par par, int tb, const dslam_frame_state& x0, const dslam_fra
   }
 }
 
+// tb2: the wavefront of the second half of the Jacobian operands (tb + 1 may
+// be given to run both halves on one wavefront).
 template <class Side>
-DX void imu_stage2(Par par, int tb, const dslam_preint& pre, const ImuParamsD& ip, ImuCommon* c, ImuStage* t,
-                   Side side) {
+DX void imu_stage2(Par par, int tb, int tb2, const dslam_preint& pre, const ImuParamsD& ip, ImuCommon* c,
+                   ImuStage* t, Side side) {
   M3* m = c->mats;
   TASK(tb) {
     M3 Jli = JlInv(t->ea);
@@ -460,19 +462,23 @@ DX void imu_stage2(Par par, int tb, const dslam_preint& pre, const ImuParamsD& i
   }
   TASK(tb + 1) {
     M3 Rcs = load33(ip.R_CS);
-    V3 wt = tr(Rcs) * load3(ip.t_CS);
-    M3 hwt = hat(wt);
     M3 Qt = tr(t->Q);
+    M3 S = t->R0 * Rcs;
     m[IC_HAT_R0YR] = (-1.0) * hat(t->R0 * t->yr);
     m[IC_QT] = pre.dt * Qt;
-    m[IC_S] = t->R0 * Rcs;
-    m[IC_KROT] = t->SdRt * hwt * t->Jrb;
+    m[IC_S] = S;
     m[IC_HAT_YG] = Qt * hat(t->yg);
     m[IC_Q] = (-1.0) * t->Q;
+    m[IC_QS] = t->Q * S;
+  }
+  TASK(tb2) {
+    M3 Rcs = load33(ip.R_CS);
+    V3 wt = tr(Rcs) * load3(ip.t_CS);
+    M3 SdRthwt = t->SdRt * hat(wt);
+    m[IC_KROT] = SdRthwt * t->Jrb;
+    m[IC_KROT_NOISE] = SdRthwt;
     m[IC_HAT_SDV] = hat(t->Sdv);
-    m[IC_QS] = t->Q * m[IC_S];
     m[IC_HAT_QSDV] = (-1.0) * hat(t->QSdv);
-    m[IC_KROT_NOISE] = t->SdRt * hwt;
     m[IC_RBT] = tr(t->Rb);
   }
   TASK(tb + 2) {
@@ -500,7 +506,7 @@ DX void imu_common_par(Par par, const dslam_frame_state& x0, const dslam_frame_s
   DSLAM_SYNC();
   imu_stage1(par, 0, x0, x1, pre, ip, e, t);
   DSLAM_SYNC();
-  imu_stage2(par, 0, pre, ip, c, t, side);
+  imu_stage2(par, 0, 1, pre, ip, c, t, side);
   DSLAM_SYNC();
 }
 

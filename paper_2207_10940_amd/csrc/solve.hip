@@ -154,11 +154,15 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   if (full) imu_stage0(par, IMU_TASKS, x0, x1, qIW, pre, &w.is);
   DSLAM_SYNC();
   reduce_cols(red, raw);
-  if (full) imu_stage1(par, IMU_TASKS, x0, x1, pre, sp.imu, w.e, &w.is);
+  if (full) {
+    imu_stage1(par, IMU_TASKS, x0, x1, pre, sp.imu, w.e, &w.is);
+    TASK(1) prior_delta_state(&w, &prior, x0);
+    TASK(2) prior_delta_gravity(&w, &prior, qIW);
+  }
   DSLAM_SYNC();
   if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
   TASK(0) visual_front(&w, raw, sp, x0, x1);
-  if (full) imu_stage2(par, IMU_TASKS, pre, sp.imu, &w.ic, &w.is, [&]() { prior_delta(&w, &prior, x0, qIW); });
+  if (full) imu_stage2(par, IMU_TASKS, 3, pre, sp.imu, &w.ic, &w.is, []() {});
   DSLAM_SYNC();
   int st = solve_back(par, &w, sp, &pre, &prior, &x0, &x1, qIW, &marg);
   SERIAL {

@@ -290,13 +290,20 @@ DX void visual_front(SolveWork* w, const double* raw, const SolveParams& sp, con
   build_lift(sp.R_WM, x0, x1, w->Li, w->Lr);
 }
 
-// The prior's linearisation offset (x0, q_IW) [-] xbar.
-DX void prior_delta(SolveWork* w, const dslam_prior* prior, const dslam_frame_state& x0, const double* qIW) {
+// The prior's linearisation offset (x0, q_IW) [-] xbar, in two independent
+// parts (the state's 15 entries, the gravity direction's 3).
+DX void prior_delta_state(SolveWork* w, const dslam_prior* prior, const dslam_frame_state& x0) {
   state_boxminus(x0, prior->xbar, w->prior_d);
+}
+DX void prior_delta_gravity(SolveWork* w, const dslam_prior* prior, const double* qIW) {
   V3 dg = qboxminus(qIW, prior->q_IW_bar);
   w->prior_d[15] = dg.x;
   w->prior_d[16] = dg.y;
   w->prior_d[17] = dg.z;
+}
+DX void prior_delta(SolveWork* w, const dslam_prior* prior, const dslam_frame_state& x0, const double* qIW) {
+  prior_delta_state(w, prior, x0);
+  prior_delta_gravity(w, prior, qIW);
 }
 
 // Everything of one step after the visual sums are unpacked and the IMU

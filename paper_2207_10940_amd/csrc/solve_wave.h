@@ -59,8 +59,22 @@ __device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* 
     inv = fma(inv, fma(-p, inv, 1.0), inv);
     const double m = (lane == k) ? 0.0 : R[k] * inv;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // the whole remaining column into registers with 16-byte broadcast reads,
+    // all in flight at once, before any update uses them
+    double cv[NSTEP];
 #pragma unroll
-    for (int j = k + 1; j < NSTEP; ++j) R[j] = fma(-m, c[j], R[j]);
+    for (int j = (k + 1) & ~1; j < NSTEP; j += 2) {
+      if (j + 1 < NSTEP) {
+        const double2 t = *reinterpret_cast<const double2*>(c + j);
+        cv[j] = t.x;
+        cv[j + 1] = t.y;
+      } else {
+        cv[j] = c[j];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = k + 1; j < NSTEP; ++j) R[j] = fma(-m, cv[j], R[j]);
 #pragma unroll
     for (int j = 0; j < NR; ++j) R[NSTEP + j] = fma(-m, rhs[j], R[NSTEP + j]);
   }
@@ -79,7 +93,7 @@ __device__ __forceinline__ double own_diag(const double (&R)[NC], int lane) {
 // block; wave 0 computes.  Returns 0, or 1 if S9 is not SPD.
 __device__ int spd_inverse9_dev(const double* S9, double* W9) {
   __shared__ int bad;
-  __shared__ double col[128];
+  __shared__ __attribute__((aligned(16))) double col[128];
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     double R[18];
@@ -120,7 +134,7 @@ __device__ __forceinline__ bool solve_rows(const double* H, const double* b, int
 // leading 15x15 block of [H | b].  Called by every thread; wave 0 computes.
 __device__ int spd_solve_dev(const double* H, const double* b, int n, double* dz, double* schur) {
   __shared__ int bad;
-  __shared__ double col[128];
+  __shared__ __attribute__((aligned(16))) double col[128];
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     bool ok = false;
