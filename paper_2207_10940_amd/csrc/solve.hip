@@ -163,6 +163,8 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
   TASK(0) visual_front(&w, raw, sp, x0, x1);
   if (full) imu_stage2(par, IMU_TASKS, 3, pre, sp.imu, &w.ic, &w.is, []() {});
+  if (threadIdx.x >= 64 && threadIdx.x < 192)  // two otherwise idle waves
+    init_system(Par{(int)threadIdx.x - 64, 128}, &w, sp, &pre, &prior);
   DSLAM_SYNC();
   int st = solve_back(par, &w, sp, &pre, &prior, &x0, &x1, qIW, &marg);
   SERIAL {

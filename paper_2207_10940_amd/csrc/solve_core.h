@@ -306,9 +306,51 @@ DX void prior_delta(SolveWork* w, const dslam_prior* prior, const dslam_frame_st
   prior_delta_gravity(w, prior, qIW);
 }
 
-// Everything of one step after the visual sums are unpacked and the IMU
-// factor's operands (imu_common) are computed: assembly, solve, update and
-// marginalisation.
+// Start values of the system: the prior on (x0, q_IW) with its first-order
+// correction, H* and b* - H* d (eqs. (6), (9)), and the IMU bias random-walk
+// rows e = b0 - b1 with J = [I at x0, -I at x1] and weight 1/(sigma_rw^2 dt)
+// (RGB-D mode: zero); the visual and IMU terms are added to them.  Also zeroes
+// the IMU Jacobian rows.  Needs the IMU residual e and the prior offset.
+DX void init_system(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre, const dslam_prior* prior) {
+  const bool full = sp.mode != DSLAM_MODE_RGBD;
+  const double T = pre->dt;
+  const double wbg = full ? 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T) : 0.0;
+  const double wba = full ? 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T) : 0.0;
+  // z index -> prior index (x0: 0..14, gravity direction: 15..17), else -1
+  auto pidx = [](int z) { return z < 15 ? z : (z >= 30 ? z - 15 : -1); };
+  // bias random-walk weight of z index (x0 or x1 bias entries), else 0
+  auto rw = [&](int z) {
+    const int q = z < 15 ? z : z - 15;
+    return (z < 30 && q >= 9) ? (q < 12 ? wbg : wba) : 0.0;
+  };
+  PFOR(idx, NZ * NZ + NZ) {
+    if (idx < NZ * NZ) {
+      const int i = idx / NZ, j = idx % NZ, pi = pidx(i), pj = pidx(j);
+      double a = (full && pi >= 0 && pj >= 0) ? prior->H[18 * pi + pj] : 0.0;
+      if (i == j) a += rw(i);
+      else if (j == i + 15 || i == j + 15) a -= rw(i);  // x0 bias <-> the same x1 bias
+      w->H[idx] = a;
+    } else {
+      const int i = idx - NZ * NZ, pi = pidx(i);
+      double a = 0.0;
+      if (full && pi >= 0) {
+        a = prior->b[pi];
+        for (int k = 0; k < 18; ++k) a -= prior->H[18 * pi + k] * w->prior_d[k];
+      }
+      if (full && rw(i) != 0.0) {
+        const double eb = w->e[i < 15 ? i : i - 15];  // b0 - b1 for this bias entry
+        a += (i < 15 ? -rw(i) : rw(i)) * eb;
+      }
+      w->b[i] = a;
+    }
+  }
+  PFOR(i, 9 * NZ) w->J9[i] = 0.0;
+  PFOR(i, 81) w->A9[i] = 0.0;
+}
+
+// Everything of one step after the visual sums are unpacked, the IMU factor's
+// operands (imu_common) are computed and the system is initialised
+// (init_system): assembly, solve, update and marginalisation.
 DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre, const dslam_prior* prior,
                   dslam_frame_state* x0, dslam_frame_state* x1, double* qIW, dslam_prior* marg_out);
 
@@ -321,6 +363,8 @@ DX int solve_step(Par par, SolveWork* w, const double* raw, const SolveParams& s
     imu_common_par(par, *x0, *x1, qIW, *pre, sp.imu, w->e, &w->ic, &w->is, [&]() { prior_delta(w, prior, *x0, qIW); });
   else
     DSLAM_SYNC();
+  init_system(par, w, sp, pre, prior);
+  DSLAM_SYNC();
   return solve_back(par, w, sp, pre, prior, x0, x1, qIW, marg_out);
 }
 
@@ -329,11 +373,6 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
   const bool full = sp.mode != DSLAM_MODE_RGBD;
   const int n = full ? NZ : 6;
   const bool marg = full && sp.marginalise && marg_out != nullptr;
-  PFOR(i, NZ * NZ) w->H[i] = 0.0;
-  PFOR(i, NZ) w->b[i] = 0.0;
-  PFOR(i, 9 * NZ) w->J9[i] = 0.0;
-  PFOR(i, 81) w->A9[i] = 0.0;
-  DSLAM_SYNC();
   // ---- LH = L Hm (12x6) per term; IMU Jacobian blocks
   PFOR(idx, 72 + IMU_BLOCKS) {
     if (idx < 72) {
@@ -357,14 +396,14 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
       int i = idx / 12, j = idx % 12;
       double a = 0.0;
       for (int k = 0; k < 6; ++k) a += w->LH[6 * i + k] * w->Lr[6 * j + k] + w->LHi[6 * i + k] * w->Li[6 * j + k];
-      if (full) w->H[(i < 6 ? i : 9 + i) * NZ + (j < 6 ? j : 9 + j)] = a;
-      else if (i >= 6 && j >= 6) w->H[(i - 6) * NZ + (j - 6)] = a;
+      if (full) w->H[(i < 6 ? i : 9 + i) * NZ + (j < 6 ? j : 9 + j)] += a;
+      else if (i >= 6 && j >= 6) w->H[(i - 6) * NZ + (j - 6)] += a;
     } else if (idx < 156) {
       int i = idx - 144;
       double a = 0.0;
       for (int k = 0; k < 6; ++k) a -= w->Lr[6 * i + k] * w->gm[1][k] + w->Li[6 * i + k] * w->gm[0][k];
-      if (full) w->b[i < 6 ? i : 9 + i] = a;
-      else if (i >= 6) w->b[i - 6] = a;
+      if (full) w->b[i < 6 ? i : 9 + i] += a;
+      else if (i >= 6) w->b[i - 6] += a;
     } else if (full) {
       int q = idx - 156, i = q / 9, j = q % 9;
       double a = 0.0;
@@ -403,7 +442,16 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
       }
     }
     DSLAM_SYNC();
-    // H += J9^T T, b -= J9^T we
+    // H += J9^T T, b -= J9^T we; the IMU cost e^T W e plus the random-walk rows
+    TASK(1) {
+      double c = 0.0;
+      for (int k = 0; k < 9; ++k) c += w->e[k] * w->y[k];
+      const double T = pre->dt;
+      const double wbg = 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T);
+      const double wba = 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T);
+      for (int i = 0; i < 3; ++i) c += wbg * w->e[9 + i] * w->e[9 + i] + wba * w->e[12 + i] * w->e[12 + i];
+      w->cost[2] = c;
+    }
     PFOR(idx, NZ * NZ + NZ) {
       if (idx < NZ * NZ) {
         int i = idx / NZ, j = idx % NZ;
@@ -415,54 +463,6 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
         double a = 0.0;
         for (int k = 0; k < 9; ++k) a += w->J9[k * NZ + i] * w->y[k];
         w->b[i] -= a;
-      }
-    }
-    DSLAM_SYNC();
-    // bias random-walk rows (e = b0 - b1, J = [I at x0, -I at x1]) and the prior
-    SERIAL {
-      double T = pre->dt;
-      double wbg = 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T);
-      double wba = 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T);
-      double c = 0.0;
-      for (int k = 0; k < 9; ++k) c += w->e[k] * w->y[k];
-      for (int i = 0; i < 3; ++i) {
-        double eg = w->e[9 + i], ea = w->e[12 + i];
-        int g0 = 9 + i, g1 = 24 + i, a0 = 12 + i, a1 = 27 + i;
-        w->H[g0 * NZ + g1] -= wbg;
-        w->H[g1 * NZ + g0] -= wbg;
-        w->H[g1 * NZ + g1] += wbg;
-        w->H[a0 * NZ + a1] -= wba;
-        w->H[a1 * NZ + a0] -= wba;
-        w->H[a1 * NZ + a1] += wba;
-        w->b[g1] += wbg * eg;
-        w->b[a1] += wba * ea;
-        c += wbg * eg * eg + wba * ea * ea;
-      }
-      w->cost[2] = c;
-    }
-    // prior on (x0, q_IW): H += H*, b += b* - H* d; the x0-bias diagonal of the
-    // random-walk rows is added here too (disjoint from the SERIAL block's entries)
-    PFOR(idx, 18 * 18 + 18) {
-      if (idx < 324) {
-        int i = idx / 18, j = idx % 18;
-        int zi = i < 15 ? i : 15 + i, zj = j < 15 ? j : 15 + j;
-        double a = prior->H[idx];
-        if (i == j && i >= 9 && i < 15) {
-          double T = pre->dt;
-          double sr = i < 12 ? sp.imu.sigma_bg_rw : sp.imu.sigma_ba_rw;
-          a += 1.0 / (sr * sr * T);
-        }
-        w->H[zi * NZ + zj] += a;
-      } else {
-        int i = idx - 324;
-        double a = prior->b[i];
-        for (int k = 0; k < 18; ++k) a -= prior->H[18 * i + k] * w->prior_d[k];
-        if (i >= 9 && i < 15) {
-          double T = pre->dt;
-          double sr = i < 12 ? sp.imu.sigma_bg_rw : sp.imu.sigma_ba_rw;
-          a -= w->e[i] / (sr * sr * T);
-        }
-        w->b[i < 15 ? i : 15 + i] += a;
       }
     }
     DSLAM_SYNC();
