@@ -191,6 +191,14 @@ typedef struct {
   double t0, t1;
 } dslam_frame_input;
 
+/* One result of the tile-shape autotuner: the residual pass of `level` of a
+ * width x height camera with `jac_format` runs fastest with `ppt` pixels per
+ * thread (us: its measured time per launch). */
+typedef struct {
+  int32_t width, height, level, jac_format, ppt;
+  float us;
+} dslam_tune_entry;
+
 /* Human-readable name of a status code (static string). */
 const char* dslam_status_string(dslam_status s);
 
@@ -204,6 +212,19 @@ dslam_status dslam_context_create(int32_t device, uint64_t hbm_budget_bytes, dsl
 dslam_status dslam_context_destroy(dslam_context* ctx);
 /* Bytes currently admitted on the context. */
 uint64_t dslam_context_used_bytes(const dslam_context* ctx);
+
+/* Tile-shape autotuner for the residual pass.  For each camera cams[0..n) and
+ * each of its `levels` pyramid levels, times the pass (jac_format's kernel)
+ * with 1, 2 and 4 pixels per thread on a synthetic slanted, textured plane
+ * and records the fastest in the context; sessions opened on the context
+ * afterwards with the same resolution and format use it (a session keeps its
+ * tile shape for life, so its results do not depend on batching).  Runs
+ * synchronously on `stream`, with temporary device memory counted against
+ * the budget while it runs.  out (nullable, capacity max_out) receives the
+ * chosen entries, *n_out their number. */
+dslam_status dslam_context_autotune(dslam_context* ctx, const dslam_camera* cams, int32_t n, int32_t levels,
+                                    int32_t jac_format, void* stream, dslam_tune_entry* out, int32_t max_out,
+                                    int32_t* n_out);
 
 /* Device bytes a session of this camera and pyramid depth holds for its lifetime. */
 uint64_t dslam_session_bytes(const dslam_camera* cam, int32_t levels);

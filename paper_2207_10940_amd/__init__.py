@@ -181,6 +181,19 @@ class Context:
     def used_bytes(self) -> int:
         return int(lib().dslam_context_used_bytes(self.handle))
 
+    def autotune(self, cams, levels=3, jac="fp32", stream=None) -> list:
+        """Tile-shape autotuner (dslam_context_autotune); returns the chosen entries as dicts."""
+        cs = [camera(c) if not isinstance(c, _abi.Camera) else c for c in cams]
+        arr = (_abi.Camera * len(cs))(*cs)
+        cap = len(cs) * _abi.MAX_LEVELS
+        out = (_abi.TuneEntry * cap)()
+        n = C.c_int32()
+        jf = JAC[jac] if isinstance(jac, str) else int(jac)
+        _check(lib().dslam_context_autotune(self.handle, arr, len(cs), int(levels), jf, _stream_ptr(stream), out, cap,
+                                            C.byref(n)), "dslam_context_autotune")
+        return [{"width": e.width, "height": e.height, "level": e.level, "jac_format": e.jac_format, "ppt": e.ppt,
+                 "us": e.us} for e in out[:n.value]]
+
     def close(self):
         if self.handle:
             _check(lib().dslam_context_destroy(self.handle), "dslam_context_destroy")

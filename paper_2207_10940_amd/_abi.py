@@ -62,6 +62,11 @@ class LinearSystem(C.Structure):
                 ("cost_rgb", C.c_double), ("n_rgb", C.c_int64), ("raw", C.c_double * 58)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("level", C.c_int32), ("jac_format", C.c_int32),
+                ("ppt", C.c_int32), ("us", C.c_float)]
+
+
 class FrameInput(C.Structure):
     _fields_ = [("depth", C.c_void_p), ("intensity", C.c_void_p), ("pitch", C.c_int32),
                 ("model_depth", C.c_void_p), ("model_intensity", C.c_void_p), ("model_pitch", C.c_int32),
@@ -110,6 +115,8 @@ SIGNATURES = {
     "dslam_profile_residual": (C.c_int, [vp, C.c_int32, C.c_int32, vp]),
     "dslam_session_get_state": (C.c_int, [vp, P(FrameState), dp, P(Prior), P(C.c_int32)]),
     "dslam_session_set_state": (C.c_int, [vp, P(FrameState), dp, P(Prior), C.c_int32]),
+    "dslam_context_autotune": (C.c_int, [vp, P(Camera), C.c_int32, C.c_int32, C.c_int32, vp, P(TuneEntry),
+                                         C.c_int32, P(C.c_int32)]),
     "dslam_batch_create": (C.c_int, [vp, C.c_int32, P(vp)]),
     "dslam_batch_destroy": (C.c_int, [vp]),
     "dslam_batch_track": (C.c_int, [vp, C.c_int32, P(vp), P(FrameInput), vp]),

@@ -158,6 +158,14 @@ SolveParams solve_params(dslam_session* s) {
   return sp;
 }
 
+// Pixels per thread the autotuner chose for this resolution, level and format (0: none).
+int tuned_ppt(dslam_context* ctx, int W, int H, int level, int jac) {
+  std::lock_guard<std::mutex> g(ctx->tune_mu);
+  for (const dslam_tune_entry& e : ctx->tuned)
+    if (e.width == W && e.height == H && e.level == level && e.jac_format == jac) return e.ppt;
+  return 0;
+}
+
 // Validates the frame's IMU samples and packs them for the device.
 dslam_status pack_imu(const dslam_session* s, const dslam_imu_sample* imu, int32_t n_imu, double t0, double t1,
                       ImuBatch* batch) {
@@ -290,7 +298,8 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
     }
     C->G[0] = C->G[1] = nullptr;
     for (int k = 0; k < 2; ++k) { M->G[k] = (int16_t*)p; p += b16; }
-    s->ppt[l] = default_ppt(C->W * C->H);
+    const int tuned = tuned_ppt(ctx, cam->width, cam->height, l, tp->jac_format);
+    s->ppt[l] = tuned ? tuned : default_ppt(C->W * C->H);
   }
   s->partials = (float*)p; p += align256(lo.partial_floats * sizeof(float));
   s->sd = (SessionDev*)p; p += align256(sizeof(SessionDev));
@@ -306,6 +315,109 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   if (hipMemcpy(s->sd, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
   if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
   *out = s;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_context_autotune(dslam_context* ctx, const dslam_camera* cams, int32_t n, int32_t levels,
+                                    int32_t jac_format, void* stream, dslam_tune_entry* out, int32_t max_out,
+                                    int32_t* n_out) {
+  if (!ctx || !cams || n < 1 || levels < 1 || levels > DSLAM_MAX_LEVELS || max_out < 0 || (max_out > 0 && !out))
+    return DSLAM_ERR_INVALID;
+  dslam_track_params tp;
+  std::memset(&tp, 0, sizeof(tp));
+  tp.levels = levels;
+  for (int l = 0; l < levels; ++l) tp.iters[l] = 1;
+  tp.icp_dist = 0.10;
+  tp.icp_cos = -2.0;
+  tp.sigma_I = 4.0;
+  tp.depth_k = 1e-3;
+  tp.huber_k = 1.345;
+  tp.jac_format = jac_format;
+  tp.mode = DSLAM_MODE_RGBD;
+  for (int c = 0; c < n; ++c)
+    if (!params_ok(&cams[c], &tp)) return DSLAM_ERR_INVALID;
+  dslam_imu_params ip;
+  std::memset(&ip, 0, sizeof(ip));
+  dslam_frame_state x0;
+  std::memset(&x0, 0, sizeof(x0));
+  x0.q[0] = 1.0;
+  const double q[4] = {1.0, 0.0, 0.0, 0.0};
+  double T[16];
+  for (int i = 0; i < 16; ++i) T[i] = (i % 5 == 0) ? 1.0 : 0.0;
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  std::vector<dslam_tune_entry> found;
+  dslam_status rc = DSLAM_OK;
+  for (int c = 0; c < n && rc == DSLAM_OK; ++c) {
+    const dslam_camera& cam = cams[c];
+    dslam_session* s = nullptr;
+    rc = dslam_session_open(ctx, &cam, &tp, &ip, &x0, q, nullptr, &s);
+    if (rc != DSLAM_OK) break;
+    void* img = nullptr;
+    const size_t npx = (size_t)cam.width * cam.height;
+    if (hipMalloc(&img, npx * 5) != hipSuccess) {
+      (void)dslam_session_close(s);
+      rc = DSLAM_ERR_NO_CAPACITY;
+      break;
+    }
+    float* depth = (float*)img;
+    uint8_t* inten = (uint8_t*)img + npx * 4;
+    auto run = [&]() -> dslam_status {
+      if (launch_tune_scene(depth, inten, cam.width, cam.height, st) != hipSuccess) return DSLAM_ERR_DEVICE;
+      dslam_status b = dslam_build_pyramid(s, DSLAM_PYR_MODEL, depth, inten, cam.width, T, st);
+      if (b == DSLAM_OK) b = dslam_build_pyramid(s, DSLAM_PYR_CURRENT, depth, inten, cam.width, nullptr, st);
+      if (b != DSLAM_OK) return b;
+      // identity transforms: every valid pixel associates with itself
+      if (hipMemsetAsync(s->sd->xf, 0, sizeof(s->sd->xf), st) != hipSuccess) return DSLAM_ERR_DEVICE;
+      for (int l = 0; l < levels; ++l) {
+        const ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
+        dslam_tune_entry best{cam.width, cam.height, l, jac_format, 0, 0.0f};
+        for (int ppt : {1, 2, 4}) {
+          const int reps = 20;
+          for (int r = 0; r < 3; ++r)
+            if (launch_residual(ra, ppt, st) != hipSuccess) return DSLAM_ERR_DEVICE;
+          if (hipEventRecord(e0, st) != hipSuccess) return DSLAM_ERR_DEVICE;
+          for (int r = 0; r < reps; ++r)
+            if (launch_residual(ra, ppt, st) != hipSuccess) return DSLAM_ERR_DEVICE;
+          if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return DSLAM_ERR_DEVICE;
+          float ms = 0.0f;
+          if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return DSLAM_ERR_DEVICE;
+          const float us = ms * 1000.0f / reps;
+          if (best.ppt == 0 || us < best.us) {
+            best.ppt = ppt;
+            best.us = us;
+          }
+        }
+        found.push_back(best);
+      }
+      return DSLAM_OK;
+    };
+    rc = run();
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(img);
+    (void)dslam_session_close(s);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != DSLAM_OK) return rc;
+  {
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    for (const dslam_tune_entry& f : found) {
+      bool replaced = false;
+      for (dslam_tune_entry& e : ctx->tuned)
+        if (e.width == f.width && e.height == f.height && e.level == f.level && e.jac_format == f.jac_format) {
+          e = f;
+          replaced = true;
+        }
+      if (!replaced) ctx->tuned.push_back(f);
+    }
+  }
+  int k = 0;
+  for (; k < (int)found.size() && k < max_out; ++k) out[k] = found[k];
+  if (n_out) *n_out = k;
   return DSLAM_OK;
 }
 

@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <mutex>
+#include <vector>
 
 #include "step.h"
 
@@ -12,6 +13,8 @@ struct dslam_context {
   int device;
   uint64_t budget;
   std::atomic<uint64_t> used{0};
+  std::mutex tune_mu;
+  std::vector<dslam_tune_entry> tuned;  // autotuned pixels per thread (dslam_context_autotune)
 };
 
 using dslam::LevelPtrs;

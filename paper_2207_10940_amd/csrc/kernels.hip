@@ -599,6 +599,22 @@ hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int l
   }
 }
 
+// Synthetic scene for the autotuner: a slanted plane 1.2-2.8 m away with a
+// smooth periodic texture, so that every pixel associates and is textured.
+__global__ void tune_scene_kernel(float* depth, uint8_t* inten, int W, int H) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (i >= W || j >= H) return;
+  const float u = (float)i / (float)W, v = (float)j / (float)H;
+  depth[(size_t)j * W + i] = 1.2f + 1.0f * u + 0.6f * v;
+  const float t = 128.0f + 60.0f * __sinf(0.21f * (float)i) + 50.0f * __cosf(0.17f * (float)j);
+  inten[(size_t)j * W + i] = (uint8_t)t;
+}
+
+hipError_t launch_tune_scene(float* depth, uint8_t* inten, int W, int H, hipStream_t st) {
+  hipLaunchKernelGGL(tune_scene_kernel, dim3((W + 255) / 256, H), dim3(256), 0, st, depth, inten, W, H);
+  return hipGetLastError();
+}
+
 int residual_blocks(int npix, int ppt) { return (npix + RES_THREADS * ppt - 1) / (RES_THREADS * ppt); }
 
 hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st) {

@@ -46,6 +46,7 @@ hipError_t launch_pyramid_level0(const float* depth, const uint8_t* inten, int p
 hipError_t launch_pyramid_down(const LevelPtrs& parent, const LevelPtrs& L, int with_grad, hipStream_t st);
 int residual_blocks(int npix, int ppt);
 hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st);
+hipError_t launch_tune_scene(float* depth, uint8_t* inten, int W, int H, hipStream_t st);
 // which: 0 current frame, 1 model view
 hipError_t launch_pyramid_batch(const SlotVis* slots, const BatchGrid& g, int level, int which, hipStream_t st);
 hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, int jac,

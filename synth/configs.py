@@ -137,11 +137,17 @@ def frame_pair(seed: int = 1001, width: int = 160, height: int = 120, *, noisy_i
 
 
 def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: int = 480, *, fps: float = 30.0,
-             imu_rate: float = 200.0, device="cpu", low_texture_every: int = 0, duration: float | None = None) -> dict:
+             imu_rate: float = 200.0, device="cpu", low_texture_every: int = 0, duration: float | None = None,
+             low_texture_frames=(), hole_frames=(), hole_fraction: float = 0.8) -> dict:
     """Plain method, single session: a seeded smooth B-spline trajectory (peak
     1.5 m/s, 180 deg/s), IMU at 200 Hz with random-walk biases.  Frame j is
     rendered at its ground-truth pose with depth noise; the model view used to
-    track frame j is the noise-free render at frame j-1's ground-truth pose."""
+    track frame j is the noise-free render at frame j-1's ground-truth pose.
+
+    Stress options: frames listed in ``low_texture_frames`` (or every
+    ``low_texture_every``-th) get the low-texture albedo (variance x 0.01);
+    frames in ``hole_frames`` lose ``hole_fraction`` of their measured depth to
+    zero-depth blobs (value noise thresholded at that quantile)."""
     rng = np.random.default_rng(seed)
     scene = make_scene(rng, seed)
     # by default the trajectory and the IMU stream span the full 10 s sequence, so
@@ -160,10 +166,14 @@ def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: in
     stamps, gyro, acc, tbg, tba = synth_imu(traj, 0.0, duration - 1.0 / fps, imu_rate, rng, noise, bg0, ba0)
     for j, t in enumerate(times):
         R_IC, p_IC = traj.pose(t)
+        lt = bool(low_texture_every and j % low_texture_every == 0) or j in set(low_texture_frames)
         z, inten = render(scene, R_IC, p_IC, cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy,
-                          device=device, low_texture=bool(low_texture_every and j % low_texture_every == 0))
+                          device=device, low_texture=lt)
         clean.append(z)
-        noisy.append((add_depth_noise(z, 1e-3, gen), inten))
+        zn = add_depth_noise(z, 1e-3, gen)
+        if j in set(hole_frames):
+            zn = apply_holes(zn, seed * 1000 + j, hole_fraction)
+        noisy.append((zn, inten))
         _, _, v = state_truth(traj, t)
         k = min(int(np.searchsorted(stamps, t, side="right")) - 1, len(stamps) - 1)
         gts.append(make_state(R_IW.T @ R_IC, R_IW.T @ p_IC, v, tbg[k], tba[k]))
@@ -180,6 +190,20 @@ def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: in
         "x0": x0, "q_IW": q_IW_init, "prior": initial_prior(x0, q_IW_init), "noise": noise,
         "gravity": GRAVITY,
     }
+
+
+def apply_holes(z: torch.Tensor, seed: int, fraction: float) -> torch.Tensor:
+    """Zero the depth where smooth value noise falls below its `fraction` quantile (blob-shaped holes)."""
+    from .scene import value_noise2
+    H, W = z.shape
+    jj, ii = torch.meshgrid(torch.arange(H, dtype=torch.float64, device=z.device),
+                            torch.arange(W, dtype=torch.float64, device=z.device), indexing="ij")
+    hv = value_noise2(ii, jj, seed, scale=1.0 / (24.0 * max(1.0, W / 640.0)))
+    flat = hv.flatten().float()
+    if flat.numel() > 4_000_000:  # quantile of a strided sample for very large images
+        flat = flat[:: (flat.numel() // 4_000_000) + 1]
+    thr = torch.quantile(flat, fraction).to(torch.float64)
+    return torch.where(hv < thr, torch.zeros_like(z), z)
 
 
 def model_view(seq: dict, j: int):
