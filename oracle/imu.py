@@ -177,14 +177,63 @@ def factor(x0, x1, q_IW, pre, params):
                         pre, params)
 
     J = _richardson(f, 33, 1e-4)
+    Sigma = residual_covariance(x0, x1, q_IW, pre, params)
+    W = np.linalg.inv(Sigma)
+    W = 0.5 * (W + W.T)
+    return e, J, W
+
+
+def residual_covariance(x0, x1, q_IW, pre, params):
+    """Covariance (15x15) of e_IMU: the preintegration noise mapped through the
+    residual (finite differences) plus the bias random walks."""
     A = _richardson(lambda d: residual(x0, x1, q_IW, pre, params, dnoise=d), 9, 1e-4)
     Sigma = A @ pre["Sigma"] @ A.T
     T = pre["dt"]
     Sigma[9:12, 9:12] += np.eye(3) * params["sigma_bg_rw"] ** 2 * T
     Sigma[12:15, 12:15] += np.eye(3) * params["sigma_ba_rw"] ** 2 * T
-    W = np.linalg.inv(Sigma)
-    W = 0.5 * (W + W.T)
-    return e, J, W
+    return Sigma
+
+
+# Gyro-only variant (the paper's comparison in which the accelerometer-related
+# residuals are ignored, Section VI): the IMU rows kept are the rotation
+# residual and the gyroscope-bias random walk.
+GYRO_ROWS = np.r_[3:6, 9:12]
+# z entries that only the dropped rows constrain: x0 and x1 velocity and
+# accelerometer bias, and the gravity direction (it cancels from the rotation
+# residual); the gyro-only system holds them fixed.
+GYRO_FIXED = np.r_[6:9, 12:15, 21:24, 27:30, 30:33]
+
+
+def factor_gyro(x0, x1, q_IW, pre, params):
+    """The gyro-only IMU factor: the kept rows of the full factor, weighted by
+    the inverse of their marginal covariance (the rows dropped are not
+    measured, so they carry no information about the kept ones)."""
+    e = residual(x0, x1, q_IW, pre, params)
+
+    def f(d):
+        return residual(state_boxplus(x0, d[0:15]), state_boxplus(x1, d[15:30]), quat_boxplus(q_IW, d[30:33]),
+                        pre, params)
+
+    J = _richardson(f, 33, 1e-4)
+    Sigma = residual_covariance(x0, x1, q_IW, pre, params)
+    Sk = Sigma[np.ix_(GYRO_ROWS, GYRO_ROWS)]
+    Wk = np.linalg.inv(0.5 * (Sk + Sk.T))
+    return e[GYRO_ROWS], J[GYRO_ROWS], 0.5 * (Wk + Wk.T)
+
+
+def predict_state_gyro(x0, pre, params):
+    """x1 initialised from x0 with the orientation rotated by the gyro-integrated
+    rotation (no accelerometer: position, velocity and biases stay at x0's):
+    R1 = R0 R_CS dR R_CS^T."""
+    from .lie import copy_state
+    R_CS = params["R_CS"]
+    dbg = x0["bg"] - pre["bg"]
+    dR = pre["dR"] @ exp_so3(pre["J"][0:3, 0:3] @ dbg)
+    R0 = quat_to_rot(x0["q"])
+    R1 = R0 @ R_CS @ dR @ R_CS.T
+    x1 = copy_state(x0)
+    x1["q"] = quat_boxplus(x0["q"], log_so3(R1 @ R0.T))
+    return x1
 
 
 def predict_state(x0, q_IW, pre, params):

@@ -10,6 +10,13 @@ Readings taken where the paper is silent:
 
 * x1 starts at the IMU prediction from x0 (RGB-D-inertial mode) or at x0's
   pose with x0 held fixed (RGB-D-only mode, the paper's baseline system);
+* gyro-only mode (the paper's variant without the accelerometer residuals):
+  only the rotation residual and the gyro-bias random walk of the IMU factor
+  remain; the entries no remaining term constrains (velocities, accelerometer
+  biases, gravity direction) are held fixed, their rows and columns of the
+  normal equations replaced by the identity with a zero right-hand side
+  (the same solution as the system without them); x1 starts at x0 rotated by
+  the gyro-integrated rotation;
 * the IMU and prior terms are added at every iteration of every level;
 * a fixed number of iterations per level, no damping, no early exit;
 * the float32 transforms that drive association are the float64 compositions
@@ -83,6 +90,8 @@ def track_frame(depth, intensity, model_depth, model_intensity, T_WM, camera, im
         x1 = copy_state(x1_init)
     elif mode == "rgbd":
         x1 = copy_state(x0)
+    elif mode == "gyro":
+        x1 = imu_mod.predict_state_gyro(x0, pre, params)
     else:
         x1 = imu_mod.predict_state(x0, q_IW, pre, params)
     log = []
@@ -109,12 +118,21 @@ def track_frame(depth, intensity, model_depth, model_intensity, T_WM, camera, im
                 idx = np.r_[0:6, 15:21]
                 H[np.ix_(idx, idx)] += vis["H_icp"] + vis["H_rgb"]
                 b[idx] += vis["b_icp"] + vis["b_rgb"]
-                e, J, W = imu_mod.factor(x0, x1, q_IW, pre, params)
+                if mode == "gyro":
+                    e, J, W = imu_mod.factor_gyro(x0, x1, q_IW, pre, params)
+                else:
+                    e, J, W = imu_mod.factor(x0, x1, q_IW, pre, params)
                 H += J.T @ W @ J
                 b += -(J.T @ W @ e)
                 Hp, bp = slv.prior_terms(x0, q_IW, prior)
                 H += Hp
                 b += bp
+                if mode == "gyro":
+                    fixed = imu_mod.GYRO_FIXED
+                    H[fixed, :] = 0.0
+                    H[:, fixed] = 0.0
+                    H[fixed, fixed] = 1.0
+                    b[fixed] = 0.0
                 if not slv.is_spd(H):
                     status = "singular"
                     break

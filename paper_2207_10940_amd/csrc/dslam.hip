@@ -51,7 +51,7 @@ bool params_ok(const dslam_camera* cam, const dslam_track_params* tp) {
   if (!(cam->fx > 0) || !(cam->fy > 0) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy)) return false;
   for (int l = 0; l < tp->levels; ++l)
     if (tp->iters[l] < 0 || tp->iters[l] > 1000) return false;
-  if (tp->mode != DSLAM_MODE_RGBDI && tp->mode != DSLAM_MODE_RGBD) return false;
+  if (tp->mode != DSLAM_MODE_RGBDI && tp->mode != DSLAM_MODE_RGBD && tp->mode != DSLAM_MODE_GYRO) return false;
   if (tp->jac_format < DSLAM_JAC_FP32 || tp->jac_format > DSLAM_JAC_BF16) return false;
   if (!(tp->icp_dist > 0) || !(tp->icp_cos <= 1) || !(tp->sigma_I > 0) ||
       !(tp->depth_k > 0) || !(tp->huber_k >= 0))
@@ -475,8 +475,9 @@ dslam_status dslam_solve_step(const double raw[58], const double T_WM[16], const
                               dslam_frame_state* x0, dslam_frame_state* x1, double q_IW[4], double dz_out[33],
                               dslam_prior* marg_out) {
   if (!raw || !T_WM || !ip || !tp || !x0 || !x1 || !q_IW) return DSLAM_ERR_INVALID;
-  if (tp->mode != DSLAM_MODE_RGBD && tp->mode != DSLAM_MODE_RGBDI) return DSLAM_ERR_INVALID;
-  if (tp->mode == DSLAM_MODE_RGBDI && (!pre || !prior)) return DSLAM_ERR_INVALID;
+  if (tp->mode != DSLAM_MODE_RGBD && tp->mode != DSLAM_MODE_RGBDI && tp->mode != DSLAM_MODE_GYRO)
+    return DSLAM_ERR_INVALID;
+  if (tp->mode != DSLAM_MODE_RGBD && (!pre || !prior)) return DSLAM_ERR_INVALID;
   if (!state_ok(x0) || !state_ok(x1) || !quat_ok(q_IW)) return DSLAM_ERR_INVALID;
   SolveWork* w = new (std::nothrow) SolveWork;
   if (!w) return DSLAM_ERR_NO_CAPACITY;

@@ -561,6 +561,24 @@ DX void imu_block(const ImuCommon& c, int b, double* J9, double* A9) {
   if (b == IMU_BLOCKS - 1) put_block(A9, 9, 6, 3, c.mats[IC_QS]);  // e_v / d(dv) = R_IW S
 }
 
+// Gyro-only prediction: x1 = x0 with the orientation rotated by the
+// gyro-integrated rotation, R1 = R0 R_CS dR R_CS^T (dR at x0's gyro bias).
+DX void imu_predict_gyro(const dslam_frame_state& x0, const dslam_preint& pre, const ImuParamsD& ip,
+                         dslam_frame_state* x1) {
+  double pb[3];
+  for (int i = 0; i < 3; ++i) {
+    double a = 0.0;
+    for (int k = 0; k < 3; ++k) a += pre.J[6 * i + k] * (x0.bg[k] - pre.bg[k]);
+    pb[i] = a;
+  }
+  const M3 Rcs = load33(ip.R_CS);
+  const M3 dR = load33(pre.dR) * Exp(load3(pb));
+  const M3 R0 = q2R(x0.q);
+  const M3 R1 = R0 * Rcs * dR * tr(Rcs);
+  *x1 = x0;
+  qboxplus(x1->q, Log(R1 * tr(R0)));
+}
+
 // IMU prediction of the current state from x0 (x1 <- x1_hat(x0)).  Serial.
 DX void imu_predict(const dslam_frame_state& x0, const double* qIW, const dslam_preint& pre, const ImuParamsD& ip,
                     dslam_frame_state* x1) {

@@ -83,7 +83,8 @@ __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& 
     dslam_frame_state x1 = x0;
     if (fa.mode != DSLAM_MODE_RGBD && st == DSLAM_OK) {
       sd->pre = pre;
-      imu_predict(x0, qIW, pre, fa.imu, &x1);
+      if (fa.mode == DSLAM_MODE_GYRO) imu_predict_gyro(x0, pre, fa.imu, &x1);
+      else imu_predict(x0, qIW, pre, fa.imu, &x1);
     }
     sd->x1 = x1;
     next_transforms(x0, x1, fa.R_WM, fa.t_WM, sd->xf);

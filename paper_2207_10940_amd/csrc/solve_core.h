@@ -278,6 +278,14 @@ DX int spd_solve(Par par, SolveWork* w, const double* H, const double* b, int n,
 // One Gauss-Newton step.  raw: the 58 sums of the residual pass (ICP then RGB),
 // taken at (x0, x1).  Updates x0, x1, qIW in place on success, writes the
 // marginal prior if sp.marginalise.  Returns a dslam_status.
+// Gyro-only mode (no accelerometer residuals): the z entries only the dropped
+// rows constrain, held fixed -- x0 and x1 velocity (6-8, 21-23) and
+// accelerometer bias (12-14, 27-29), and the gravity direction (30-32).
+DX bool gyro_fixed(int z) {
+  const int q = z < 15 ? z : z - 15;
+  return z >= 30 || (q >= 6 && q < 9) || (q >= 12 && q < 15);
+}
+
 // The visual sums of one pass and the lift operators at the current states.
 DX void visual_front(SolveWork* w, const double* raw, const SolveParams& sp, const dslam_frame_state& x0,
                      const dslam_frame_state& x1) {
@@ -315,7 +323,7 @@ DX void init_system(Par par, SolveWork* w, const SolveParams& sp, const dslam_pr
   const bool full = sp.mode != DSLAM_MODE_RGBD;
   const double T = pre->dt;
   const double wbg = full ? 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T) : 0.0;
-  const double wba = full ? 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T) : 0.0;
+  const double wba = (full && sp.mode != DSLAM_MODE_GYRO) ? 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T) : 0.0;
   // z index -> prior index (x0: 0..14, gravity direction: 15..17), else -1
   auto pidx = [](int z) { return z < 15 ? z : (z >= 30 ? z - 15 : -1); };
   // bias random-walk weight of z index (x0 or x1 bias entries), else 0
@@ -371,6 +379,7 @@ DX int solve_step(Par par, SolveWork* w, const double* raw, const SolveParams& s
 DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre, const dslam_prior* prior,
                   dslam_frame_state* x0, dslam_frame_state* x1, double* qIW, dslam_prior* marg_out) {
   const bool full = sp.mode != DSLAM_MODE_RGBD;
+  const bool gyro = sp.mode == DSLAM_MODE_GYRO;
   const int n = full ? NZ : 6;
   const bool marg = full && sp.marginalise && marg_out != nullptr;
   // ---- LH = L Hm (12x6) per term; IMU Jacobian blocks
@@ -414,11 +423,23 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
   DSLAM_SYNC();
   if (full) {
     // ---- IMU term: Sigma_e = A9 Sigma A9^T (+ random-walk rows), W = Sigma_e^-1
-    PFOR(idx, 81) {
-      int i = idx / 9, j = idx % 9;
-      double a = 0.0;
-      for (int k = 0; k < 9; ++k) a += w->Y[9 * i + k] * w->A9[9 * j + k];
-      w->S9[idx] = a;
+    PFOR(idx, 81 + 9 * NZ + 9) {
+      if (idx < 81) {
+        int i = idx / 9, j = idx % 9;
+        double a = 0.0;
+        for (int k = 0; k < 9; ++k) a += w->Y[9 * i + k] * w->A9[9 * j + k];
+        // gyro-only: the position and velocity rows (accelerometer) are dropped;
+        // decoupling them leaves the rotation rows weighted by the inverse of
+        // their marginal covariance
+        if (gyro && !(i >= 3 && i < 6 && j >= 3 && j < 6)) a = (i == j) ? 1.0 : 0.0;
+        w->S9[idx] = a;
+      } else if (gyro) {  // zero the dropped rows of the Jacobian and the residual
+        const int q = idx - 81, r = q < 9 * NZ ? q / NZ : q - 9 * NZ;
+        if (r < 3 || r >= 6) {
+          if (q < 9 * NZ) w->J9[q] = 0.0;
+          else w->e[r] = 0.0;
+        }
+      }
     }
     DSLAM_SYNC();
     if (spd_inverse9(par, w, w->S9, w->A9)) {  // W9 overwrites A9
@@ -448,7 +469,7 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
       for (int k = 0; k < 9; ++k) c += w->e[k] * w->y[k];
       const double T = pre->dt;
       const double wbg = 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T);
-      const double wba = 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T);
+      const double wba = gyro ? 0.0 : 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T);
       for (int i = 0; i < 3; ++i) c += wbg * w->e[9 + i] * w->e[9 + i] + wba * w->e[12 + i] * w->e[12 + i];
       w->cost[2] = c;
     }
@@ -457,12 +478,16 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
         int i = idx / NZ, j = idx % NZ;
         double a = 0.0;
         for (int k = 0; k < 9; ++k) a += w->J9[k * NZ + i] * w->Y[k * NZ + j];
-        w->H[idx] += a;
+        // gyro-only: the entries no remaining term constrains are held fixed
+        // (identity rows and columns, zero right-hand side)
+        if (gyro && (gyro_fixed(i) || gyro_fixed(j))) w->H[idx] = (i == j) ? 1.0 : 0.0;
+        else w->H[idx] += a;
       } else {
         int i = idx - NZ * NZ;
         double a = 0.0;
         for (int k = 0; k < 9; ++k) a += w->J9[k * NZ + i] * w->y[k];
-        w->b[i] -= a;
+        if (gyro && gyro_fixed(i)) w->b[i] = 0.0;
+        else w->b[i] -= a;
       }
     }
     DSLAM_SYNC();

@@ -11,11 +11,11 @@ from tests.gpu_common import open_seq_session as _open, same_result as _same, se
 pytestmark = pytest.mark.gpu
 
 # (seed, width, height, mode): mixed resolutions, a ragged one (200x152: tiles
-# and blocks do not divide the image) and one RGB-D-only session
+# and blocks do not divide the image), one RGB-D-only and one gyro-only session
 SESSIONS = [(3101, 160, 120, "rgbdi"), (3102, 320, 240, "rgbdi"), (3103, 160, 120, "rgbdi"),
-            (3104, 200, 152, "rgbdi"), (3105, 160, 120, "rgbd")]
+            (3104, 200, 152, "rgbdi"), (3105, 160, 120, "rgbd"), (3106, 160, 120, "gyro")]
 # batch composition per step: indices of the sessions that get their next frame
-STEPS = [[0, 1, 2, 3, 4], [1, 3], [0, 2, 3, 4], [4, 0, 1], [2, 1, 0, 3, 4]]
+STEPS = [[0, 1, 2, 3, 4, 5], [1, 3, 5], [0, 2, 3, 4], [4, 0, 1, 5], [2, 1, 0, 3, 4, 5]]
 
 
 @pytest.mark.parametrize("jac", ["fp32", "bf16"])

@@ -111,7 +111,7 @@ def _track_pair(mode, seed=1001, W=160, H=120, levels=2, iters=(4, 4)):
     return d, o, g
 
 
-@pytest.mark.parametrize("mode", ["rgbdi", "rgbd"])
+@pytest.mark.parametrize("mode", ["rgbdi", "rgbd", "gyro"])
 def test_track_frame_pair_matches_oracle(mode):
     print(f"track pair {mode}", flush=True)
     d, o, g = _track_pair(mode)
@@ -120,7 +120,7 @@ def test_track_frame_pair_matches_oracle(mode):
     assert dr < 1e-6 and da < 1e-6, (dr, da)
     last = o["log"][-1]
     assert g["n_icp"][0] == last["n_icp"] and g["n_rgb"][0] == last["n_rgb"]
-    if mode == "rgbdi":
+    if mode != "rgbd":
         dr0, da0 = pose_err(g["x0"], o["x0"])
         assert dr0 < 1e-6 and da0 < 1e-6
         assert np.linalg.norm(lie.quat_boxminus(g["q_IW"], o["q_IW"])) < 1e-6

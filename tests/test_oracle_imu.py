@@ -3,6 +3,7 @@ import numpy as np
 from scipy.integrate import solve_ivp
 
 from oracle import imu, lie
+import synth
 from synth.configs import quat_from_matrix
 
 
@@ -188,3 +189,42 @@ def test_factor_jacobian_known_blocks():
     assert np.abs(J[9:15, 24:30] + np.eye(6)).max() < 1e-8
     assert np.abs(J[3:6, 18:21] + I3).max() < 1e-6          # de_alpha / d da1 at e = 0
     assert np.allclose(W, W.T) and np.linalg.eigvalsh(W).min() > 0
+
+
+def test_gyro_only_prediction_is_the_closed_form_rotation():
+    """Constant body rate w, no noise, zero bias: the gyro-only prediction is
+    R1 = R0 R_CS Exp(w T) R_CS^T, position and velocity unchanged."""
+    from oracle import lie
+    rng = np.random.default_rng(11)
+    w = np.array([0.4, -0.9, 1.3])
+    T = 0.05
+    stamps = np.arange(0.0, T, 0.005)
+    gyro = np.tile(w, (len(stamps), 1))
+    acc = np.tile([0.3, 9.5, -1.0], (len(stamps), 1))
+    x0 = {"r": rng.normal(size=3), "q": lie.quat_exp(rng.normal(size=3)), "v": rng.normal(size=3),
+          "bg": np.zeros(3), "ba": np.zeros(3)}
+    R_CS = lie.exp_so3(np.array([0.1, 0.2, -0.3]))
+    params = {"R_CS": R_CS, "t_CS": np.zeros(3)}
+    pre = imu.preintegrate(stamps, gyro, acc, 0.0, T, x0["bg"], x0["ba"], 1.7e-4, 2e-3)
+    x1 = imu.predict_state_gyro(x0, pre, params)
+    R0 = lie.quat_to_rot(x0["q"])
+    want = R0 @ R_CS @ lie.exp_so3(w * T) @ R_CS.T
+    assert np.abs(lie.quat_to_rot(x1["q"]) - want).max() < 1e-12
+    assert np.array_equal(x1["r"], x0["r"]) and np.array_equal(x1["v"], x0["v"])
+
+
+def test_gyro_only_factor_is_the_rotation_marginal_of_the_full_factor():
+    from oracle import lie, track
+    d = synth.configs.frame_pair(seed=1001)
+    params = track.default_params(levels=2, iters=(1, 1), mode="gyro")
+    pre = imu.preintegrate(d["imu"]["t"], d["imu"]["gyro"], d["imu"]["acc"], d["t0"], d["t1"], d["x0"]["bg"],
+                           d["x0"]["ba"], params["sigma_g"], params["sigma_a"])
+    x1 = lie.state_boxplus(d["gt1"], np.r_[1e-3 * np.ones(6), np.zeros(9)])
+    e, J, W = imu.factor(d["x0"], x1, d["q_IW"], pre, params)
+    eg, Jg, Wg = imu.factor_gyro(d["x0"], x1, d["q_IW"], pre, params)
+    rows = np.r_[3:6, 9:12]
+    assert np.array_equal(eg, e[rows])
+    assert np.abs(Jg - J[rows]).max() < 1e-12
+    # weights: inverse of the kept rows' block of the full covariance W^-1
+    S = np.linalg.inv(W)[np.ix_(rows, rows)]
+    assert np.abs(np.linalg.inv(Wg) - S).max() < 1e-9 * np.abs(S).max()

@@ -15,7 +15,7 @@ def _run(mode, **kw):
 
 
 def test_frame_pair_tracks_close_to_ground_truth():
-    for mode in ("rgbd", "rgbdi"):
+    for mode in ("rgbd", "rgbdi", "gyro"):
         d, out = _run(mode)
         assert out["status"] == "ok"
         gt = d["gt1"]
@@ -46,3 +46,31 @@ def test_no_valid_depth_is_singular_in_rgbd_mode():
     out = track.track_frame(z, d["intensity"].numpy(), d["model_depth"].numpy(), d["model_intensity"].numpy(),
                             d["T_WM"], d["camera"], d["imu"], d["t0"], d["t1"], d["x0"], d["q_IW"], d["prior"], p)
     assert out["status"] == "ok"
+
+
+def test_gyro_only_holds_the_entries_only_accelerometers_observe():
+    d, out = _run("gyro")
+    assert out["status"] == "ok"
+    for k in ("v", "ba"):
+        assert np.array_equal(out["x1"][k], d["x0"][k]) and np.array_equal(out["x0"][k], d["x0"][k])
+    assert np.array_equal(out["q_IW"], d["q_IW"])
+    # the marginal prior keeps them decoupled (identity rows, zero right-hand side)
+    H, b = out["prior"]["H"], out["prior"]["b"]
+    fixed = np.r_[6:9, 12:15, 15:18]  # x1 velocity, x1 accelerometer bias, gravity direction
+    assert np.array_equal(H[np.ix_(fixed, fixed)], np.eye(9))
+    free = np.setdiff1d(np.arange(18), fixed)
+    assert not H[np.ix_(fixed, free)].any() and not b[fixed].any()
+    assert np.linalg.eigvalsh(H).min() > 0
+
+
+def test_gyro_only_fails_without_visual_input():
+    """The paper's observation for the gyro-only variant: with no visual
+    constraint the relative position is unconstrained (singular), while the
+    full IMU factor still carries the frame."""
+    d = synth.configs.frame_pair()
+    z = np.zeros_like(d["depth"].numpy())
+    for mode, want in (("gyro", "singular"), ("rgbdi", "ok")):
+        p = track.default_params(levels=2, iters=(2, 2), mode=mode)
+        out = track.track_frame(z, d["intensity"].numpy(), d["model_depth"].numpy(), d["model_intensity"].numpy(),
+                                d["T_WM"], d["camera"], d["imu"], d["t0"], d["t1"], d["x0"], d["q_IW"], d["prior"], p)
+        assert out["status"] == want, mode
