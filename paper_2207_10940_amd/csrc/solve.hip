@@ -19,25 +19,24 @@ __device__ __forceinline__ void reduce_rows(const float* partials, int nblocks, 
   const int g = threadIdx.x & 15, r = threadIdx.x >> 4;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   const float* base = partials + 4 * g;
-  int b = r;
-  for (; b + 16 * 15 < nblocks; b += 16 * 16) {  // sixteen independent loads in flight
-    float4 v[16];
+  const int n = nblocks > r ? (nblocks - r + 15) / 16 : 0;  // this thread sums blocks r + 16 u, u < n
+  constexpr int CHUNK = 40;  // loads in flight at once (one round trip for up to 640 blocks)
+  for (int u0 = 0; u0 < n; u0 += CHUNK) {
+    float4 v[CHUNK];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = *reinterpret_cast<const float4*>(base + (size_t)(b + 16 * u) * PARTIAL_STRIDE);
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      s0 += (double)v[u].x;
-      s1 += (double)v[u].y;
-      s2 += (double)v[u].z;
-      s3 += (double)v[u].w;
+    for (int u = 0; u < CHUNK; ++u) {
+      const int b = r + 16 * min(u0 + u, n - 1);  // clamped: always a valid block
+      v[u] = *reinterpret_cast<const float4*>(base + (size_t)b * PARTIAL_STRIDE);
     }
-  }
-  for (; b < nblocks; b += 16) {
-    const float4 v = *reinterpret_cast<const float4*>(base + (size_t)b * PARTIAL_STRIDE);
-    s0 += (double)v.x;
-    s1 += (double)v.y;
-    s2 += (double)v.z;
-    s3 += (double)v.w;
+#pragma unroll
+    for (int u = 0; u < CHUNK; ++u) {
+      if (u0 + u < n) {
+        s0 += (double)v[u].x;
+        s1 += (double)v[u].y;
+        s2 += (double)v[u].z;
+        s3 += (double)v[u].w;
+      }
+    }
   }
   red[r * 64 + 4 * g + 0] = s0;
   red[r * 64 + 4 * g + 1] = s1;
@@ -160,12 +159,14 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
     TASK(1) prior_delta_state(&w, &prior, x0);
     TASK(2) prior_delta_gravity(&w, &prior, qIW);
   }
+  if (threadIdx.x < 64 || (threadIdx.x >= 192 && threadIdx.x < 256))  // waves 0 and 3
+    init_system_H(Par{threadIdx.x < 64 ? (int)threadIdx.x : (int)threadIdx.x - 128, 128}, &w, sp, &pre, &prior);
   DSLAM_SYNC();
   if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
-  TASK(0) visual_front(&w, raw, sp, x0, x1);
+  if (threadIdx.x < 64) visual_front_lanes((int)threadIdx.x, 64, &w, raw, sp, x0, x1);
   if (full) imu_stage2(par, IMU_TASKS, 3, pre, sp.imu, &w.ic, &w.is, []() {});
   if (threadIdx.x >= 64 && threadIdx.x < 192)  // two otherwise idle waves
-    init_system(Par{(int)threadIdx.x - 64, 128}, &w, sp, &pre, &prior);
+    init_system_b(Par{(int)threadIdx.x - 64, 128}, &w, sp, &pre, &prior);
   DSLAM_SYNC();
   int st = solve_back(par, &w, sp, &pre, &prior, &x0, &x1, qIW, &marg);
   SERIAL {

@@ -44,6 +44,7 @@ struct SolveWork {
   double Lr[12 * 6], LH[12 * 6], Li[12 * 6], LHi[12 * 6];
   double Y[18 * 19 > 9 * NZ ? 18 * 19 : 9 * NZ];  // scratch: A9 Sigma, W9 J9, H00^-1 [H0k, b0], Schur complement
   double prior_d[18];
+  double lift_src[27];  // R_WM, R0, R0 [t_b]x for the parallel lift
   double cost[4];
   ImuCommon ic;
   ImuStage is;
@@ -298,6 +299,59 @@ DX void visual_front(SolveWork* w, const double* raw, const SolveParams& sp, con
   build_lift(sp.R_WM, x0, x1, w->Li, w->Lr);
 }
 
+// visual_front spread over the nl lanes of one wavefront (lane < nl): the
+// lanes unpack the 58 sums and fill the lift operators entry by entry.
+DX void visual_front_lanes(int lane, int nl, SolveWork* w, const double* raw, const SolveParams& sp,
+                           const dslam_frame_state& x0, const dslam_frame_state& x1) {
+  if (lane < 58) {
+    const int t = lane / 29, q = lane % 29;
+    if (q < 21) {
+      int r = 0, rem = q;
+      while (rem >= 6 - r) {
+        rem -= 6 - r;
+        ++r;
+      }
+      w->Hm[t][6 * r + r + rem] = raw[lane];
+      w->Hm[t][6 * (r + rem) + r] = raw[lane];
+    } else if (q < 27) {
+      w->gm[t][q - 21] = raw[lane];
+    } else if (q == 27) {
+      w->cost[t] = raw[lane];
+    }
+  }
+  if (lane == 0) {
+    w->cost[2] = 0.0;
+    w->cost[3] = 0.0;
+  }
+  // the three 3x3 sources go through shared memory (indexed by entry below;
+  // private arrays indexed at run time would live in scratch memory)
+  const M3 RWM = load33(sp.R_WM), R0 = q2R(x0.q);
+  const V3 tb = tr(R0) * (load3(x1.r) - load3(x0.r));
+  const M3 R0Tb = R0 * hat(tb);
+  double* src = w->lift_src;
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    if (lane == k) {
+      src[k] = RWM.m[k];
+      src[9 + k] = R0.m[k];
+      src[18 + k] = R0Tb.m[k];
+    }
+#ifdef __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#endif
+  for (int idx = lane; idx < 144; idx += nl) {
+    const int m = idx / 72, r = (idx % 72) / 6, c = idx % 6;  // m 0: Li (ICP), 1: Lr (photometric)
+    const double* R = src + 9 * m;
+    double v = 0.0;
+    if (r >= 6 && r < 9 && c < 3) v = R[3 * (r - 6) + c];
+    else if (r >= 9 && c >= 3) v = R[3 * (r - 9) + c - 3];
+    else if (m == 1 && r < 3 && c < 3) v = -src[9 + 3 * r + c];
+    else if (m == 1 && r >= 3 && r < 6 && c >= 3) v = -src[9 + 3 * (r - 3) + c - 3];
+    else if (m == 1 && r >= 3 && r < 6 && c < 3) v = -src[18 + 3 * (r - 3) + c];
+    (m == 0 ? w->Li : w->Lr)[6 * r + c] = v;
+  }
+}
+
 // The prior's linearisation offset (x0, q_IW) [-] xbar, in two independent
 // parts (the state's 15 entries, the gravity direction's 3).
 DX void prior_delta_state(SolveWork* w, const dslam_prior* prior, const dslam_frame_state& x0) {
@@ -317,43 +371,65 @@ DX void prior_delta(SolveWork* w, const dslam_prior* prior, const dslam_frame_st
 // Start values of the system: the prior on (x0, q_IW) with its first-order
 // correction, H* and b* - H* d (eqs. (6), (9)), and the IMU bias random-walk
 // rows e = b0 - b1 with J = [I at x0, -I at x1] and weight 1/(sigma_rw^2 dt)
-// (RGB-D mode: zero); the visual and IMU terms are added to them.  Also zeroes
-// the IMU Jacobian rows.  Needs the IMU residual e and the prior offset.
-DX void init_system(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre, const dslam_prior* prior) {
-  const bool full = sp.mode != DSLAM_MODE_RGBD;
-  const double T = pre->dt;
-  const double wbg = full ? 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T) : 0.0;
-  const double wba = (full && sp.mode != DSLAM_MODE_GYRO) ? 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T) : 0.0;
-  // z index -> prior index (x0: 0..14, gravity direction: 15..17), else -1
-  auto pidx = [](int z) { return z < 15 ? z : (z >= 30 ? z - 15 : -1); };
-  // bias random-walk weight of z index (x0 or x1 bias entries), else 0
-  auto rw = [&](int z) {
+// (RGB-D mode: zero); the visual and IMU terms are added to them.  In two
+// parts: init_system_H (the matrix; also zeroes the IMU Jacobian rows and the
+// noise map) needs nothing of the current step, init_system_b (the right-hand
+// side) needs the IMU residual e and the prior offset.
+struct InitWeights {
+  double wbg, wba;
+  DX int pidx(int z) const { return z < 15 ? z : (z >= 30 ? z - 15 : -1); }  // z -> prior index, or -1
+  DX double rw(int z) const {  // random-walk weight of a bias entry of x0 or x1, else 0
     const int q = z < 15 ? z : z - 15;
     return (z < 30 && q >= 9) ? (q < 12 ? wbg : wba) : 0.0;
-  };
-  PFOR(idx, NZ * NZ + NZ) {
-    if (idx < NZ * NZ) {
-      const int i = idx / NZ, j = idx % NZ, pi = pidx(i), pj = pidx(j);
-      double a = (full && pi >= 0 && pj >= 0) ? prior->H[18 * pi + pj] : 0.0;
-      if (i == j) a += rw(i);
-      else if (j == i + 15 || i == j + 15) a -= rw(i);  // x0 bias <-> the same x1 bias
-      w->H[idx] = a;
-    } else {
-      const int i = idx - NZ * NZ, pi = pidx(i);
-      double a = 0.0;
-      if (full && pi >= 0) {
-        a = prior->b[pi];
-        for (int k = 0; k < 18; ++k) a -= prior->H[18 * pi + k] * w->prior_d[k];
-      }
-      if (full && rw(i) != 0.0) {
-        const double eb = w->e[i < 15 ? i : i - 15];  // b0 - b1 for this bias entry
-        a += (i < 15 ? -rw(i) : rw(i)) * eb;
-      }
-      w->b[i] = a;
-    }
+  }
+};
+
+DX InitWeights init_weights(const SolveParams& sp, const dslam_preint* pre) {
+  const bool full = sp.mode != DSLAM_MODE_RGBD;
+  const double T = pre->dt;
+  InitWeights iw;
+  iw.wbg = full ? 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T) : 0.0;
+  iw.wba = (full && sp.mode != DSLAM_MODE_GYRO) ? 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T) : 0.0;
+  return iw;
+}
+
+DX void init_system_H(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre,
+                      const dslam_prior* prior) {
+  const bool full = sp.mode != DSLAM_MODE_RGBD;
+  const InitWeights iw = init_weights(sp, pre);
+  PFOR(idx, NZ * NZ) {
+    const int i = idx / NZ, j = idx % NZ, pi = iw.pidx(i), pj = iw.pidx(j);
+    double a = (full && pi >= 0 && pj >= 0) ? prior->H[18 * pi + pj] : 0.0;
+    if (i == j) a += iw.rw(i);
+    else if (j == i + 15 || i == j + 15) a -= iw.rw(i);  // x0 bias <-> the same x1 bias
+    w->H[idx] = a;
   }
   PFOR(i, 9 * NZ) w->J9[i] = 0.0;
   PFOR(i, 81) w->A9[i] = 0.0;
+}
+
+DX void init_system_b(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre,
+                      const dslam_prior* prior) {
+  const bool full = sp.mode != DSLAM_MODE_RGBD;
+  const InitWeights iw = init_weights(sp, pre);
+  PFOR(i, NZ) {
+    const int pi = iw.pidx(i);
+    double a = 0.0;
+    if (full && pi >= 0) {
+      a = prior->b[pi];
+      for (int k = 0; k < 18; ++k) a -= prior->H[18 * pi + k] * w->prior_d[k];
+    }
+    if (full && iw.rw(i) != 0.0) {
+      const double eb = w->e[i < 15 ? i : i - 15];  // b0 - b1 for this bias entry
+      a += (i < 15 ? -iw.rw(i) : iw.rw(i)) * eb;
+    }
+    w->b[i] = a;
+  }
+}
+
+DX void init_system(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre, const dslam_prior* prior) {
+  init_system_H(par, w, sp, pre, prior);
+  init_system_b(par, w, sp, pre, prior);
 }
 
 // Everything of one step after the visual sums are unpacked, the IMU factor's
