@@ -135,8 +135,10 @@ __global__ __launch_bounds__(256) void pyramid_batch_kernel(const SlotVis* slots
 // reduction of the per-term normal equations (Section IV-B/D).
 // ---------------------------------------------------------------------------
 
-// j = [k, a x k]; accumulates w j j^T (upper triangle, 21), w j e (6), w e^2, count.
-__device__ __forceinline__ void accumulate(float* acc, const float* jv, float e, float w) {
+// j = [k, a x k]; accumulates w j j^T (upper triangle, 21), w j e (6), w e^2
+// and the inlier count.  A term that is not an inlier arrives as j = 0, e = 0,
+// w = 0 and adds exact zeros, so the sums equal those over the inliers alone.
+__device__ __forceinline__ void accumulate(float* acc, const float* jv, float e, float w, bool inlier) {
   float wj[6];
 #pragma unroll
   for (int a = 0; a < 6; ++a) wj[a] = w * jv[a];
@@ -151,7 +153,7 @@ __device__ __forceinline__ void accumulate(float* acc, const float* jv, float e,
 #pragma unroll
   for (int a = 0; a < 6; ++a) acc[21 + a] = fmaf(wj[a], e, acc[21 + a]);
   acc[27] = fmaf(w * e, e, acc[27]);
-  acc[28] = acc[28] + 1.0f;
+  acc[28] = acc[28] + (inlier ? 1.0f : 0.0f);
 }
 
 // Value-layer reciprocal: hardware estimate (1 ulp).  No validity bit or
@@ -163,115 +165,163 @@ __device__ __forceinline__ float huber(float s, float k) { return (k > 0.0f && s
 // Per-pixel sinks of the two residual terms: the plain form accumulates the
 // 2 x 29 sums per thread; the precision form keeps the pixel's 16-entry row
 // [sqrt(w) j_icp (6), sqrt(w) e_icp, sqrt(w) j_rgb (6), sqrt(w) e_rgb, 0, 0].
+// Both receive every pixel's two terms, zeroed where the term is not an inlier.
 struct SumSink {
   float* acc;
-  __device__ __forceinline__ void icp(const float* jv, float e, float w) { accumulate(acc, jv, e, w); }
-  __device__ __forceinline__ void rgb(const float* jv, float e, float w) { accumulate(acc + 29, jv, e, w); }
+  __device__ __forceinline__ void icp(const float* jv, float e, float w, bool in) { accumulate(acc, jv, e, w, in); }
+  __device__ __forceinline__ void rgb(const float* jv, float e, float w, bool in) {
+    accumulate(acc + 29, jv, e, w, in);
+  }
 };
 
 struct RowSink {
   float r[16];
-  __device__ __forceinline__ void clear() {
-#pragma unroll
-    for (int c = 0; c < 16; ++c) r[c] = 0.0f;
-  }
   __device__ __forceinline__ void put(int o, const float* jv, float e, float w) {
     const float s = __builtin_amdgcn_sqrtf(w);  // value layer: hardware square root
 #pragma unroll
     for (int c = 0; c < 6; ++c) r[o + c] = s * jv[c];
     r[o + 6] = s * e;
   }
-  __device__ __forceinline__ void icp(const float* jv, float e, float w) { put(0, jv, e, w); }
-  __device__ __forceinline__ void rgb(const float* jv, float e, float w) { put(7, jv, e, w); }
+  __device__ __forceinline__ void icp(const float* jv, float e, float w, bool) { put(0, jv, e, w); }
+  __device__ __forceinline__ void rgb(const float* jv, float e, float w, bool) {
+    put(7, jv, e, w);
+    r[14] = 0.0f;
+    r[15] = 0.0f;
+  }
 };
 
+// Plane loads at a 32-bit byte offset from a uniform base (one address
+// operation per pixel instead of one 64-bit add per plane).  The planes are
+// device memory: the cast to the global address space lets the batched kernels,
+// which read their plane pointers from memory, use global instead of flat loads.
+template <class T>
+__device__ __forceinline__ T ld(const T* base, unsigned byte_off) {
+  typedef const __attribute__((address_space(1))) T GT;
+  typedef const __attribute__((address_space(1))) char GC;
+  return *(GT*)((GC*)base + byte_off);
+}
+
+// Keeps a term's value-layer outputs where it is an inlier and zeros them
+// elsewhere (a select, so that NaN or infinity from a pixel that failed an
+// earlier test never reaches the sums).
+__device__ __forceinline__ void keep_if(bool in, float* jv, float* e, float* w) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) jv[c] = in ? jv[c] : 0.0f;
+  *e = in ? *e : 0.0f;
+  *w = in ? *w : 0.0f;
+}
+
 // Association, residuals and Jacobians of pixel p; returns the inlier bits
-// (1 = ICP, 2 = photometric) and hands each inlier term to the sink.
+// (1 = ICP, 2 = photometric) and hands both terms to the sink.
+//
+// The code is straight-line: every test of the mask layer is evaluated on all
+// lanes (the same IEEE operations in the same order as when nested), both
+// model-view gathers are issued together once the two projections are known
+// (the ICP point and normal at the rounded pixel, the photometric taps at the
+// bilinear cell), and a lane whose projection fails a test gathers at pixel 0
+// instead and has that term zeroed before the sink.  A thread past the end of
+// the image (valid = false) evaluates pixel 0 and contributes zeros.
 template <class Sink>
-__device__ __forceinline__ unsigned pixel(const ResidualArgs& a, const float* T, int p, Sink& sink) {
-  const float x = a.cV0[p], y = a.cV1[p], z = a.cV2[p];
-  uint8_t bits = 0;
-  if (z > 0.0f) {
-    // ---- ICP: projective association in the model-view camera (mask layer)
-    // transforms arrive as D = R - I: q = p + (D p + t)
-    float qx = x + (((T[0] * x + T[1] * y) + T[2] * z) + T[9]);
-    float qy = y + (((T[3] * x + T[4] * y) + T[5] * z) + T[10]);
-    float qz = z + (((T[6] * x + T[7] * y) + T[8] * z) + T[11]);
-    if (qz > 0.0f) {
-      float inv = 1.0f / qz;
-      float u = ((a.fx * qx) * inv) + a.cx;
-      float v = ((a.fy * qy) * inv) + a.cy;
-      float ui = __builtin_rintf(u), vi = __builtin_rintf(v);
-      if (ui >= 0.0f && ui <= (float)(a.W - 1) && vi >= 0.0f && vi <= (float)(a.H - 1)) {
-        int m = (int)vi * a.W + (int)ui;
-        float v0x = a.mV0[m], v0y = a.mV1[m], v0z = a.mV2[m];
-        float n0x = a.mN0[m], n0y = a.mN1[m], n0z = a.mN2[m];
-        bool n0ok = (n0x != 0.0f) | (n0y != 0.0f) | (n0z != 0.0f);
-        float ex = qx - v0x, ey = qy - v0y, ez = qz - v0z;
-        float dist2 = (ex * ex + ey * ey) + ez * ez;
-        bool ok = v0z > 0.0f && n0ok && dist2 <= a.dist2;
-        if (a.cosmin >= -1.0f) {  // optional normal-compatibility gate
-          float n1x = a.cN0[p], n1y = a.cN1[p], n1z = a.cN2[p];
-          bool n1ok = (n1x != 0.0f) | (n1y != 0.0f) | (n1z != 0.0f);
-          float nrx = n1x + ((T[0] * n1x + T[1] * n1y) + T[2] * n1z);
-          float nry = n1y + ((T[3] * n1x + T[4] * n1y) + T[5] * n1z);
-          float nrz = n1z + ((T[6] * n1x + T[7] * n1y) + T[8] * n1z);
-          float cosang = (nrx * n0x + nry * n0y) + nrz * n0z;
-          ok = ok && n1ok && cosang >= a.cosmin;
-        }
-        if (ok) {
-          // ---- value layer (eq. (4)): e = n0 . (q - v0), j = [n0, a' x n0]
-          float e = fmaf(n0x, ex, fmaf(n0y, ey, n0z * ez));
-          float px = qx - T[9], py = qy - T[10], pz = qz - T[11];
-          float jv[6] = {n0x, n0y, n0z, fmaf(py, n0z, -pz * n0y), fmaf(pz, n0x, -px * n0z), fmaf(px, n0y, -py * n0x)};
-          float isg = rcp_v(a.depth_k * z * z);
-          float s = fabsf(e) * isg;
-          float w = isg * isg * huber(s, a.huber_k);
-          sink.icp(jv, e, w);
-          bits |= 1;
-        }
-      }
-    }
-    // ---- photometric: warp into the reference camera (mask layer)
-    float rx = x + (((T[12] * x + T[13] * y) + T[14] * z) + T[21]);
-    float ry = y + (((T[15] * x + T[16] * y) + T[17] * z) + T[22]);
-    float rz = z + (((T[18] * x + T[19] * y) + T[20] * z) + T[23]);
-    if (rz > 0.0f) {
-      float inv = 1.0f / rz;
-      float u = ((a.fx * rx) * inv) + a.cx;
-      float v = ((a.fy * ry) * inv) + a.cy;
-      if (u >= 1.0f && u < (float)(a.W - 2) && v >= 1.0f && v < (float)(a.H - 2)) {
-        // ---- value layer (eq. (3)): bilinear I0 and gradient at (u, v)
-        float fu = floorf(u), fv = floorf(v);
-        int x0 = (int)fu, y0 = (int)fv;
-        float au = u - fu, av = v - fv;
-        int m = y0 * a.W + x0;
-        float w00 = (1.0f - au) * (1.0f - av), w10 = au * (1.0f - av), w01 = (1.0f - au) * av, w11 = au * av;
-        // taps in fixed point; the power-of-two unscaling commutes with every
-        // rounding of the sum, so it is applied once to the interpolated values
-        auto I_ = [&](int q) { return (float)a.mI[q]; };
-        auto GX = [&](int q) { return (float)a.mG0[q]; };
-        auto GY = [&](int q) { return (float)a.mG1[q]; };
-        float I0 = fmaf(w00, I_(m), fmaf(w10, I_(m + 1), fmaf(w01, I_(m + a.W), w11 * I_(m + a.W + 1))));
-        float gx = fmaf(w00, GX(m), fmaf(w10, GX(m + 1), fmaf(w01, GX(m + a.W), w11 * GX(m + a.W + 1))));
-        float gy = fmaf(w00, GY(m), fmaf(w10, GY(m + 1), fmaf(w01, GY(m + a.W), w11 * GY(m + a.W + 1))));
-        I0 *= 1.0f / kIntensityScale;
-        gx *= 1.0f / kGradientScale;
-        gy *= 1.0f / kGradientScale;
-        float e = I0 - (float)a.cI[p] * (1.0f / kIntensityScale);
-        float gfx = gx * a.fx * inv, gfy = gy * a.fy * inv;
-        float g2 = -fmaf(gfx, rx, gfy * ry) * inv;
-        float px = rx - T[21], py = ry - T[22], pz = rz - T[23];
-        float jv[6] = {gfx, gfy, g2, fmaf(py, g2, -pz * gfy), fmaf(pz, gfx, -px * g2), fmaf(px, gfy, -py * gfx)};
-        const float isI = rcp_v(a.sigma_I);
-        float s = fabsf(e) * isI;
-        float w = huber(s, a.huber_k) * (isI * isI);
-        sink.rgb(jv, e, w);
-        bits |= 2;
-      }
-    }
+__device__ __forceinline__ unsigned pixel(const ResidualArgs& a, const float* T, int p, bool valid, Sink& sink) {
+  const unsigned pv = valid ? (unsigned)p : 0u;
+  const unsigned o4 = pv * 4u, o2 = pv * 2u;
+  const float x = ld(a.cV0, o4), y = ld(a.cV1, o4), z = ld(a.cV2, o4);
+  const bool zok = valid && z > 0.0f;
+  // ---- mask layer: both warps and projections
+  // transforms arrive as D = R - I: q = p + (D p + t)
+  const float qx = x + (((T[0] * x + T[1] * y) + T[2] * z) + T[9]);
+  const float qy = y + (((T[3] * x + T[4] * y) + T[5] * z) + T[10]);
+  const float qz = z + (((T[6] * x + T[7] * y) + T[8] * z) + T[11]);
+  const float inv_q = 1.0f / qz;
+  const float uq = ((a.fx * qx) * inv_q) + a.cx;
+  const float vq = ((a.fy * qy) * inv_q) + a.cy;
+  const float ui = __builtin_rintf(uq), vi = __builtin_rintf(vq);
+  const bool in_q = zok && qz > 0.0f && ui >= 0.0f && ui <= (float)(a.W - 1) && vi >= 0.0f && vi <= (float)(a.H - 1);
+  const float rx = x + (((T[12] * x + T[13] * y) + T[14] * z) + T[21]);
+  const float ry = y + (((T[15] * x + T[16] * y) + T[17] * z) + T[22]);
+  const float rz = z + (((T[18] * x + T[19] * y) + T[20] * z) + T[23]);
+  const float inv_r = 1.0f / rz;
+  const float ur = ((a.fx * rx) * inv_r) + a.cx;
+  const float vr = ((a.fy * ry) * inv_r) + a.cy;
+  const bool in_r = zok && rz > 0.0f && ur >= 1.0f && ur < (float)(a.W - 2) && vr >= 1.0f && vr < (float)(a.H - 2);
+  const float fu = floorf(ur), fv = floorf(vr);
+  // ---- gathers (a failed projection reads pixel 0)
+  const unsigned m4 = in_q ? ((unsigned)vi * (unsigned)a.W + (unsigned)ui) * 4u : 0u;
+  const unsigned m2 = in_r ? ((unsigned)fv * (unsigned)a.W + (unsigned)fu) * 2u : 0u, r2 = (unsigned)a.W * 2u;
+  const float v0x = ld(a.mV0, m4), v0y = ld(a.mV1, m4), v0z = ld(a.mV2, m4);
+  const float n0x = ld(a.mN0, m4), n0y = ld(a.mN1, m4), n0z = ld(a.mN2, m4);
+  const unsigned q[4] = {m2, m2 + 2u, m2 + r2, m2 + r2 + 2u};
+  float ti[4], tx[4], ty[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    ti[k] = (float)ld(a.mI, q[k]);
+    tx[k] = (float)ld(a.mG0, q[k]);
+    ty[k] = (float)ld(a.mG1, q[k]);
   }
-  if (a.mask) a.mask[p] = bits;
+  const float ic = (float)ld(a.cI, o2);
+  // ---- ICP term (eq. (4)): association tests, e = n0 . (q - v0), j = [n0, a' x n0]
+  bool icp_ok;
+  float ji[6], ei, wi;
+  {
+    const bool n0ok = (n0x != 0.0f) | (n0y != 0.0f) | (n0z != 0.0f);
+    const float ex = qx - v0x, ey = qy - v0y, ez = qz - v0z;
+    const float dist2 = (ex * ex + ey * ey) + ez * ez;
+    bool ok = in_q && v0z > 0.0f && n0ok && dist2 <= a.dist2;
+    if (a.cosmin >= -1.0f) {  // optional normal-compatibility gate
+      const float n1x = ld(a.cN0, o4), n1y = ld(a.cN1, o4), n1z = ld(a.cN2, o4);
+      const bool n1ok = (n1x != 0.0f) | (n1y != 0.0f) | (n1z != 0.0f);
+      const float nrx = n1x + ((T[0] * n1x + T[1] * n1y) + T[2] * n1z);
+      const float nry = n1y + ((T[3] * n1x + T[4] * n1y) + T[5] * n1z);
+      const float nrz = n1z + ((T[6] * n1x + T[7] * n1y) + T[8] * n1z);
+      const float cosang = (nrx * n0x + nry * n0y) + nrz * n0z;
+      ok = ok && n1ok && cosang >= a.cosmin;
+    }
+    ei = fmaf(n0x, ex, fmaf(n0y, ey, n0z * ez));
+    const float px = qx - T[9], py = qy - T[10], pz = qz - T[11];
+    ji[0] = n0x;
+    ji[1] = n0y;
+    ji[2] = n0z;
+    ji[3] = fmaf(py, n0z, -pz * n0y);
+    ji[4] = fmaf(pz, n0x, -px * n0z);
+    ji[5] = fmaf(px, n0y, -py * n0x);
+    const float isg = rcp_v(a.depth_k * z * z);
+    const float s = fabsf(ei) * isg;
+    wi = isg * isg * huber(s, a.huber_k);
+    keep_if(ok, ji, &ei, &wi);
+    icp_ok = ok;
+  }
+  sink.icp(ji, ei, wi, icp_ok);
+  // ---- photometric term (eq. (3)): bilinear I0 and gradient at (u, v)
+  float jr[6], er, wr;
+  {
+    const float au = ur - fu, av = vr - fv;
+    const float w00 = (1.0f - au) * (1.0f - av), w10 = au * (1.0f - av), w01 = (1.0f - au) * av, w11 = au * av;
+    // taps in fixed point; the power-of-two unscaling commutes with every
+    // rounding of the sum, so it is applied once to the interpolated values
+    float I0 = fmaf(w00, ti[0], fmaf(w10, ti[1], fmaf(w01, ti[2], w11 * ti[3])));
+    float gx = fmaf(w00, tx[0], fmaf(w10, tx[1], fmaf(w01, tx[2], w11 * tx[3])));
+    float gy = fmaf(w00, ty[0], fmaf(w10, ty[1], fmaf(w01, ty[2], w11 * ty[3])));
+    I0 *= 1.0f / kIntensityScale;
+    gx *= 1.0f / kGradientScale;
+    gy *= 1.0f / kGradientScale;
+    er = I0 - ic * (1.0f / kIntensityScale);
+    const float gfx = gx * a.fx * inv_r, gfy = gy * a.fy * inv_r;
+    const float g2 = -fmaf(gfx, rx, gfy * ry) * inv_r;
+    const float px = rx - T[21], py = ry - T[22], pz = rz - T[23];
+    jr[0] = gfx;
+    jr[1] = gfy;
+    jr[2] = g2;
+    jr[3] = fmaf(py, g2, -pz * gfy);
+    jr[4] = fmaf(pz, gfx, -px * g2);
+    jr[5] = fmaf(px, gfy, -py * gfx);
+    const float isI = rcp_v(a.sigma_I);
+    const float s = fabsf(er) * isI;
+    wr = huber(s, a.huber_k) * (isI * isI);
+    keep_if(in_r, jr, &er, &wr);
+  }
+  sink.rgb(jr, er, wr, in_r);
+  const unsigned bits = (icp_ok ? 1u : 0u) | (in_r ? 2u : 0u);
+  if (a.mask && valid) a.mask[p] = (uint8_t)bits;
   return bits;
 }
 
@@ -345,7 +395,7 @@ __device__ __forceinline__ void residual_block(const ResidualArgs& a, int blk, i
   for (int k = 0; k < PMAX; ++k) {
     int p = base + k * RES_THREADS;
     SumSink sink{acc};
-    if (k < ppt && p < a.npix) pixel(a, T, p, sink);
+    if (k < ppt) pixel(a, T, p, p < a.npix, sink);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float tot = wave_transpose_sum(acc, lane);
@@ -464,9 +514,7 @@ __device__ __forceinline__ void residual_block_mfma(const ResidualArgs& a, int b
     if (k < ppt) {  // uniform across the workgroup
       const int p = base + k * RES_THREADS;
       RowSink row;
-      row.clear();
-      unsigned bits = 0;
-      if (p < a.npix) bits = pixel(a, T, p, row);
+      const unsigned bits = pixel(a, T, p, p < a.npix, row);
       n_icp += __builtin_popcountll(__ballot(bits & 1));
       n_rgb += __builtin_popcountll(__ballot(bits & 2));
 #pragma unroll
