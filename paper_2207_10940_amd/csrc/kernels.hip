@@ -201,6 +201,17 @@ __device__ __forceinline__ T ld(const T* base, unsigned byte_off) {
   return *(GT*)((GC*)base + byte_off);
 }
 
+// The two pass transforms (24 floats, written by the previous solve) are
+// uniform: read them through the constant address space so that they arrive by
+// scalar loads into scalar registers, also where the pointer itself was read
+// from memory (batched launches).
+__device__ __forceinline__ void load_transforms(const float* xf, float* T) {
+  typedef const __attribute__((address_space(4))) float CF;
+  const CF* c = (const CF*)xf;
+#pragma unroll
+  for (int k = 0; k < 24; ++k) T[k] = c[k];
+}
+
 // Keeps a term's value-layer outputs where it is an inlier and zeros them
 // elsewhere (a select, so that NaN or infinity from a pixel that failed an
 // earlier test never reaches the sums).
@@ -211,45 +222,99 @@ __device__ __forceinline__ void keep_if(bool in, float* jv, float* e, float* w) 
   *w = in ? *w : 0.0f;
 }
 
-// Association, residuals and Jacobians of pixel p; returns the inlier bits
-// (1 = ICP, 2 = photometric) and hands both terms to the sink.
+// Association, residuals and Jacobians.
 //
 // The code is straight-line: every test of the mask layer is evaluated on all
-// lanes (the same IEEE operations in the same order as when nested), both
-// model-view gathers are issued together once the two projections are known
-// (the ICP point and normal at the rounded pixel, the photometric taps at the
-// bilinear cell), and a lane whose projection fails a test gathers at pixel 0
-// instead and has that term zeroed before the sink.  A thread past the end of
-// the image (valid = false) evaluates pixel 0 and contributes zeros.
-template <class Sink>
-__device__ __forceinline__ unsigned pixel(const ResidualArgs& a, const float* T, int p, bool valid, Sink& sink) {
+// lanes (the same IEEE operations in the same order as when nested), the
+// model-view gathers are issued once the projections are known, and a lane
+// whose projection fails a test gathers at pixel 0 instead and has that term
+// zeroed (j = 0, e = 0, w = 0) before it reaches a sink.  A thread past the end
+// of the image (valid = false) evaluates pixel 0 and contributes zeros.
+
+struct Term {
+  float j[6], e, w;
+  bool in;  // the term is an inlier of this pixel
+};
+
+// The current pixel's vertex; zok = the pixel exists and has depth.
+struct Cur {
+  float x, y, z;
+  unsigned o4, o2;  // byte offsets of the pixel in a float / 16-bit plane
+  bool valid, zok;
+};
+
+__device__ __forceinline__ Cur load_cur(const ResidualArgs& a, int p, bool valid) {
+  Cur c;
   const unsigned pv = valid ? (unsigned)p : 0u;
-  const unsigned o4 = pv * 4u, o2 = pv * 2u;
-  const float x = ld(a.cV0, o4), y = ld(a.cV1, o4), z = ld(a.cV2, o4);
-  const bool zok = valid && z > 0.0f;
-  // ---- mask layer: both warps and projections
-  // transforms arrive as D = R - I: q = p + (D p + t)
+  c.o4 = pv * 4u;
+  c.o2 = pv * 2u;
+  c.x = ld(a.cV0, c.o4);
+  c.y = ld(a.cV1, c.o4);
+  c.z = ld(a.cV2, c.o4);
+  c.valid = valid;
+  c.zok = valid && c.z > 0.0f;
+  return c;
+}
+
+// ICP term (eq. (4)): projective association in the model-view camera, the
+// distance and optional normal tests, e = n0 . (q - v0), j = [n0, a' x n0].
+// Transforms arrive as D = R - I: q = p + (D p + t).
+__device__ __forceinline__ Term icp_term(const ResidualArgs& a, const float* T, const Cur& c) {
+  const float x = c.x, y = c.y, z = c.z;
   const float qx = x + (((T[0] * x + T[1] * y) + T[2] * z) + T[9]);
   const float qy = y + (((T[3] * x + T[4] * y) + T[5] * z) + T[10]);
   const float qz = z + (((T[6] * x + T[7] * y) + T[8] * z) + T[11]);
-  const float inv_q = 1.0f / qz;
-  const float uq = ((a.fx * qx) * inv_q) + a.cx;
-  const float vq = ((a.fy * qy) * inv_q) + a.cy;
-  const float ui = __builtin_rintf(uq), vi = __builtin_rintf(vq);
-  const bool in_q = zok && qz > 0.0f && ui >= 0.0f && ui <= (float)(a.W - 1) && vi >= 0.0f && vi <= (float)(a.H - 1);
+  const float inv = 1.0f / qz;
+  const float u = ((a.fx * qx) * inv) + a.cx;
+  const float v = ((a.fy * qy) * inv) + a.cy;
+  const float ui = __builtin_rintf(u), vi = __builtin_rintf(v);
+  const bool in = c.zok && qz > 0.0f && ui >= 0.0f && ui <= (float)(a.W - 1) && vi >= 0.0f && vi <= (float)(a.H - 1);
+  const unsigned m4 = in ? ((unsigned)vi * (unsigned)a.W + (unsigned)ui) * 4u : 0u;
+  const float v0x = ld(a.mV0, m4), v0y = ld(a.mV1, m4), v0z = ld(a.mV2, m4);
+  const float n0x = ld(a.mN0, m4), n0y = ld(a.mN1, m4), n0z = ld(a.mN2, m4);
+  const bool n0ok = (n0x != 0.0f) | (n0y != 0.0f) | (n0z != 0.0f);
+  const float ex = qx - v0x, ey = qy - v0y, ez = qz - v0z;
+  const float dist2 = (ex * ex + ey * ey) + ez * ez;
+  bool ok = in && v0z > 0.0f && n0ok && dist2 <= a.dist2;
+  if (a.cosmin >= -1.0f) {  // optional normal-compatibility gate
+    const float n1x = ld(a.cN0, c.o4), n1y = ld(a.cN1, c.o4), n1z = ld(a.cN2, c.o4);
+    const bool n1ok = (n1x != 0.0f) | (n1y != 0.0f) | (n1z != 0.0f);
+    const float nrx = n1x + ((T[0] * n1x + T[1] * n1y) + T[2] * n1z);
+    const float nry = n1y + ((T[3] * n1x + T[4] * n1y) + T[5] * n1z);
+    const float nrz = n1z + ((T[6] * n1x + T[7] * n1y) + T[8] * n1z);
+    const float cosang = (nrx * n0x + nry * n0y) + nrz * n0z;
+    ok = ok && n1ok && cosang >= a.cosmin;
+  }
+  Term t;
+  t.e = fmaf(n0x, ex, fmaf(n0y, ey, n0z * ez));
+  const float px = qx - T[9], py = qy - T[10], pz = qz - T[11];
+  t.j[0] = n0x;
+  t.j[1] = n0y;
+  t.j[2] = n0z;
+  t.j[3] = fmaf(py, n0z, -pz * n0y);
+  t.j[4] = fmaf(pz, n0x, -px * n0z);
+  t.j[5] = fmaf(px, n0y, -py * n0x);
+  const float isg = rcp_v(a.depth_k * z * z);
+  const float s = fabsf(t.e) * isg;
+  t.w = isg * isg * huber(s, a.huber_k);
+  keep_if(ok, t.j, &t.e, &t.w);
+  t.in = ok;
+  return t;
+}
+
+// Photometric term (eq. (3)): warp into the reference camera, bilinear I0 and
+// gradient at (u, v) from the 16-bit fixed-point planes.
+__device__ __forceinline__ Term rgb_term(const ResidualArgs& a, const float* T, const Cur& c) {
+  const float x = c.x, y = c.y, z = c.z;
   const float rx = x + (((T[12] * x + T[13] * y) + T[14] * z) + T[21]);
   const float ry = y + (((T[15] * x + T[16] * y) + T[17] * z) + T[22]);
   const float rz = z + (((T[18] * x + T[19] * y) + T[20] * z) + T[23]);
-  const float inv_r = 1.0f / rz;
-  const float ur = ((a.fx * rx) * inv_r) + a.cx;
-  const float vr = ((a.fy * ry) * inv_r) + a.cy;
-  const bool in_r = zok && rz > 0.0f && ur >= 1.0f && ur < (float)(a.W - 2) && vr >= 1.0f && vr < (float)(a.H - 2);
-  const float fu = floorf(ur), fv = floorf(vr);
-  // ---- gathers (a failed projection reads pixel 0)
-  const unsigned m4 = in_q ? ((unsigned)vi * (unsigned)a.W + (unsigned)ui) * 4u : 0u;
-  const unsigned m2 = in_r ? ((unsigned)fv * (unsigned)a.W + (unsigned)fu) * 2u : 0u, r2 = (unsigned)a.W * 2u;
-  const float v0x = ld(a.mV0, m4), v0y = ld(a.mV1, m4), v0z = ld(a.mV2, m4);
-  const float n0x = ld(a.mN0, m4), n0y = ld(a.mN1, m4), n0z = ld(a.mN2, m4);
+  const float inv = 1.0f / rz;
+  const float u = ((a.fx * rx) * inv) + a.cx;
+  const float v = ((a.fy * ry) * inv) + a.cy;
+  const bool in = c.zok && rz > 0.0f && u >= 1.0f && u < (float)(a.W - 2) && v >= 1.0f && v < (float)(a.H - 2);
+  const float fu = floorf(u), fv = floorf(v);
+  const unsigned m2 = in ? ((unsigned)fv * (unsigned)a.W + (unsigned)fu) * 2u : 0u, r2 = (unsigned)a.W * 2u;
   const unsigned q[4] = {m2, m2 + 2u, m2 + r2, m2 + r2 + 2u};
   float ti[4], tx[4], ty[4];
 #pragma unroll
@@ -258,69 +323,46 @@ __device__ __forceinline__ unsigned pixel(const ResidualArgs& a, const float* T,
     tx[k] = (float)ld(a.mG0, q[k]);
     ty[k] = (float)ld(a.mG1, q[k]);
   }
-  const float ic = (float)ld(a.cI, o2);
-  // ---- ICP term (eq. (4)): association tests, e = n0 . (q - v0), j = [n0, a' x n0]
-  bool icp_ok;
-  float ji[6], ei, wi;
-  {
-    const bool n0ok = (n0x != 0.0f) | (n0y != 0.0f) | (n0z != 0.0f);
-    const float ex = qx - v0x, ey = qy - v0y, ez = qz - v0z;
-    const float dist2 = (ex * ex + ey * ey) + ez * ez;
-    bool ok = in_q && v0z > 0.0f && n0ok && dist2 <= a.dist2;
-    if (a.cosmin >= -1.0f) {  // optional normal-compatibility gate
-      const float n1x = ld(a.cN0, o4), n1y = ld(a.cN1, o4), n1z = ld(a.cN2, o4);
-      const bool n1ok = (n1x != 0.0f) | (n1y != 0.0f) | (n1z != 0.0f);
-      const float nrx = n1x + ((T[0] * n1x + T[1] * n1y) + T[2] * n1z);
-      const float nry = n1y + ((T[3] * n1x + T[4] * n1y) + T[5] * n1z);
-      const float nrz = n1z + ((T[6] * n1x + T[7] * n1y) + T[8] * n1z);
-      const float cosang = (nrx * n0x + nry * n0y) + nrz * n0z;
-      ok = ok && n1ok && cosang >= a.cosmin;
-    }
-    ei = fmaf(n0x, ex, fmaf(n0y, ey, n0z * ez));
-    const float px = qx - T[9], py = qy - T[10], pz = qz - T[11];
-    ji[0] = n0x;
-    ji[1] = n0y;
-    ji[2] = n0z;
-    ji[3] = fmaf(py, n0z, -pz * n0y);
-    ji[4] = fmaf(pz, n0x, -px * n0z);
-    ji[5] = fmaf(px, n0y, -py * n0x);
-    const float isg = rcp_v(a.depth_k * z * z);
-    const float s = fabsf(ei) * isg;
-    wi = isg * isg * huber(s, a.huber_k);
-    keep_if(ok, ji, &ei, &wi);
-    icp_ok = ok;
-  }
-  sink.icp(ji, ei, wi, icp_ok);
-  // ---- photometric term (eq. (3)): bilinear I0 and gradient at (u, v)
-  float jr[6], er, wr;
-  {
-    const float au = ur - fu, av = vr - fv;
-    const float w00 = (1.0f - au) * (1.0f - av), w10 = au * (1.0f - av), w01 = (1.0f - au) * av, w11 = au * av;
-    // taps in fixed point; the power-of-two unscaling commutes with every
-    // rounding of the sum, so it is applied once to the interpolated values
-    float I0 = fmaf(w00, ti[0], fmaf(w10, ti[1], fmaf(w01, ti[2], w11 * ti[3])));
-    float gx = fmaf(w00, tx[0], fmaf(w10, tx[1], fmaf(w01, tx[2], w11 * tx[3])));
-    float gy = fmaf(w00, ty[0], fmaf(w10, ty[1], fmaf(w01, ty[2], w11 * ty[3])));
-    I0 *= 1.0f / kIntensityScale;
-    gx *= 1.0f / kGradientScale;
-    gy *= 1.0f / kGradientScale;
-    er = I0 - ic * (1.0f / kIntensityScale);
-    const float gfx = gx * a.fx * inv_r, gfy = gy * a.fy * inv_r;
-    const float g2 = -fmaf(gfx, rx, gfy * ry) * inv_r;
-    const float px = rx - T[21], py = ry - T[22], pz = rz - T[23];
-    jr[0] = gfx;
-    jr[1] = gfy;
-    jr[2] = g2;
-    jr[3] = fmaf(py, g2, -pz * gfy);
-    jr[4] = fmaf(pz, gfx, -px * g2);
-    jr[5] = fmaf(px, gfy, -py * gfx);
-    const float isI = rcp_v(a.sigma_I);
-    const float s = fabsf(er) * isI;
-    wr = huber(s, a.huber_k) * (isI * isI);
-    keep_if(in_r, jr, &er, &wr);
-  }
-  sink.rgb(jr, er, wr, in_r);
-  const unsigned bits = (icp_ok ? 1u : 0u) | (in_r ? 2u : 0u);
+  const float ic = (float)ld(a.cI, c.o2);
+  const float au = u - fu, av = v - fv;
+  const float w00 = (1.0f - au) * (1.0f - av), w10 = au * (1.0f - av), w01 = (1.0f - au) * av, w11 = au * av;
+  // taps in fixed point; the power-of-two unscaling commutes with every
+  // rounding of the sum, so it is applied once to the interpolated values
+  float I0 = fmaf(w00, ti[0], fmaf(w10, ti[1], fmaf(w01, ti[2], w11 * ti[3])));
+  float gx = fmaf(w00, tx[0], fmaf(w10, tx[1], fmaf(w01, tx[2], w11 * tx[3])));
+  float gy = fmaf(w00, ty[0], fmaf(w10, ty[1], fmaf(w01, ty[2], w11 * ty[3])));
+  I0 *= 1.0f / kIntensityScale;
+  gx *= 1.0f / kGradientScale;
+  gy *= 1.0f / kGradientScale;
+  Term t;
+  t.e = I0 - ic * (1.0f / kIntensityScale);
+  const float gfx = gx * a.fx * inv, gfy = gy * a.fy * inv;
+  const float g2 = -fmaf(gfx, rx, gfy * ry) * inv;
+  const float px = rx - T[21], py = ry - T[22], pz = rz - T[23];
+  t.j[0] = gfx;
+  t.j[1] = gfy;
+  t.j[2] = g2;
+  t.j[3] = fmaf(py, g2, -pz * gfy);
+  t.j[4] = fmaf(pz, gfx, -px * g2);
+  t.j[5] = fmaf(px, gfy, -py * gfx);
+  const float isI = rcp_v(a.sigma_I);
+  const float s = fabsf(t.e) * isI;
+  t.w = huber(s, a.huber_k) * (isI * isI);
+  keep_if(in, t.j, &t.e, &t.w);
+  t.in = in;
+  return t;
+}
+
+// Both terms of pixel p into the sink; returns the inlier bits (1 = ICP,
+// 2 = photometric) and writes them to the mask when one is requested.
+template <class Sink>
+__device__ __forceinline__ unsigned pixel(const ResidualArgs& a, const float* T, int p, bool valid, Sink& sink) {
+  const Cur c = load_cur(a, p, valid);
+  const Term ti = icp_term(a, T, c);
+  const Term tr = rgb_term(a, T, c);
+  sink.icp(ti.j, ti.e, ti.w, ti.in);
+  sink.rgb(tr.j, tr.e, tr.w, tr.in);
+  const unsigned bits = (ti.in ? 1u : 0u) | (tr.in ? 2u : 0u);
   if (a.mask && valid) a.mask[p] = (uint8_t)bits;
   return bits;
 }
@@ -378,34 +420,51 @@ __device__ __forceinline__ float wave_transpose_sum(const float (&v)[N], int lan
   return y[0];
 }
 
-// Workgroup blk of a residual pass with ppt pixels per thread: thread t visits
-// pixels blk*256*ppt + t + 256 k, k = 0..ppt-1, in that order, so the sums of a
-// session do not depend on whether it runs alone or in a batch.
+// Workgroup blk of a residual pass covers pixels blk*B*ppt .. +B*ppt-1
+// (B = RES_THREADS).  The plain form splits its waves by term: the first half
+// accumulates the ICP sums, the second half the photometric sums, each thread
+// over the 2 ppt pixels blk*B*ppt + t + (B/2) k, k = 0..2ppt-1, t = thread
+// index within its half, in that order (so the sums of a session do not depend
+// on whether it runs alone or in a batch).  A thread holds 29 running sums
+// instead of 58, which keeps enough waves resident to cover the gathers'
+// latency.
 template <int PMAX>
 __device__ __forceinline__ void residual_block(const ResidualArgs& a, int blk, int ppt) {
-  __shared__ float red[RES_THREADS / 64][58];
+  constexpr int HALF = RES_THREADS / 2;
+  __shared__ float red[RES_THREADS / 64][29];
+  __shared__ uint8_t inl[2][RES_THREADS * PMAX];  // inlier bits per term (masks only)
   float T[24];
+  load_transforms(a.xf, T);
+  float acc[33];  // 29 sums and 4 zeros (the wavefront reduction takes 33..64 values)
 #pragma unroll
-  for (int k = 0; k < 24; ++k) T[k] = a.xf[k];
-  float acc[58];
-#pragma unroll
-  for (int k = 0; k < 58; ++k) acc[k] = 0.0f;
-  const int base = blk * RES_THREADS * ppt + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < PMAX; ++k) {
-    int p = base + k * RES_THREADS;
-    SumSink sink{acc};
-    if (k < ppt) pixel(a, T, p, p < a.npix, sink);
-  }
+  for (int k = 0; k < 33; ++k) acc[k] = 0.0f;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool rgb = threadIdx.x >= HALF;  // uniform per wavefront
+  const int t = threadIdx.x - (rgb ? HALF : 0);
+  const int first = blk * RES_THREADS * ppt;
+#pragma unroll
+  for (int k = 0; k < 2 * PMAX; ++k) {
+    if (k < 2 * ppt) {  // uniform across the workgroup
+      const int p = first + t + k * HALF;
+      const Cur c = load_cur(a, p, p < a.npix);
+      const Term tm = rgb ? rgb_term(a, T, c) : icp_term(a, T, c);
+      accumulate(acc, tm.j, tm.e, tm.w, tm.in);
+      if (a.mask) inl[rgb][t + k * HALF] = tm.in;
+    }
+  }
   const float tot = wave_transpose_sum(acc, lane);
-  if (lane < 58) red[wave][lane] = tot;
+  if (lane < 29) red[wave][lane] = tot;
   __syncthreads();
   if (threadIdx.x < 58) {
-    float s = red[0][threadIdx.x];
+    const int term = threadIdx.x / 29, q = threadIdx.x - 29 * term, w0 = term * (HALF / 64);
+    float s = red[w0][q];
 #pragma unroll
-    for (int w = 1; w < RES_THREADS / 64; ++w) s += red[w][threadIdx.x];
+    for (int w = 1; w < HALF / 64; ++w) s += red[w0 + w][q];
     a.partials[(size_t)blk * PARTIAL_STRIDE + threadIdx.x] = s;
+  }
+  if (a.mask) {  // uniform
+    for (int i = threadIdx.x; i < RES_THREADS * ppt; i += RES_THREADS)
+      if (first + i < a.npix) a.mask[first + i] = (uint8_t)(inl[0][i] | (inl[1][i] << 1));
   }
 }
 
@@ -501,8 +560,7 @@ __device__ __forceinline__ void residual_block_mfma(const ResidualArgs& a, int b
   __shared__ float gram[RES_THREADS / 64][16][17];
   __shared__ int counts[RES_THREADS / 64][2];
   float T[24];
-#pragma unroll
-  for (int k = 0; k < 24; ++k) T[k] = a.xf[k];
+  load_transforms(a.xf, T);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   ST* st = stage[wave];
   const float s_icp = a.col_scale[0], s_rgb = a.col_scale[1];
