@@ -145,28 +145,36 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   SolveParams sp = a.sp;
   sp.marginalise = a.last;
   const bool full = sp.mode != DSLAM_MODE_RGBD;
-  // the first waves reduce the block partials while the IMU factor's operands,
-  // which depend on the states only, are computed on the first lanes of the
-  // last four waves (three stages, one barrier sequence for both)
-  constexpr int IMU_TASKS = SOLVE_THREADS / 64 - 4;
-  static_assert(SOLVE_THREADS >= REDUCE_THREADS + 256, "needs four spare waves");
-  if (threadIdx.x < REDUCE_THREADS) reduce_rows(partials, a.nblocks, red);
-  if (full) imu_stage0(par, IMU_TASKS, x0, x1, qIW, pre, &w.is);
+  // The first four waves reduce the block partials while the operands of the
+  // IMU factor, the prior offset and the visual lift, which depend on the
+  // states only, are computed on the others (three stages, one barrier
+  // sequence for both).  Wave w runs on SIMD w % 4: each stage puts its
+  // longest serial task on a SIMD whose other wave has little to do.
+  //   stage 0: reduction (waves 0-3); IMU rotations and bias-corrected
+  //            preintegration (waves 4-6); lift sources (wave 7)
+  //   stage 1: column sums (wave 0); IMU residual (wave 7); prior offset
+  //            (waves 1, 2); system matrix start (waves 0, 4); lift (waves 5, 6)
+  //   stage 2: unpacked sums (wave 0); IMU Jacobian operands (waves 3-6);
+  //            right-hand side start (waves 1, 2)
+  static_assert(SOLVE_THREADS == 512 && REDUCE_THREADS == 256, "stage plan assumes 8 waves");
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  if (wave < 4) reduce_rows(partials, a.nblocks, red);
+  if (full) imu_stage0(par, 4, x0, x1, qIW, pre, &w.is);
+  if (wave == 7) lift_sources(lane, &w, sp, x0, x1);
   DSLAM_SYNC();
   reduce_cols(red, raw);
   if (full) {
-    imu_stage1(par, IMU_TASKS, x0, x1, pre, sp.imu, w.e, &w.is);
+    imu_stage1(par, 7, x0, x1, pre, sp.imu, w.e, &w.is);
     TASK(1) prior_delta_state(&w, &prior, x0);
     TASK(2) prior_delta_gravity(&w, &prior, qIW);
   }
-  if (threadIdx.x < 64 || (threadIdx.x >= 192 && threadIdx.x < 256))  // waves 0 and 3
-    init_system_H(Par{threadIdx.x < 64 ? (int)threadIdx.x : (int)threadIdx.x - 128, 128}, &w, sp, &pre, &prior);
+  if (wave == 0 || wave == 4) init_system_H(Par{lane + (wave == 4 ? 64 : 0), 128}, &w, sp, &pre, &prior);
+  if (wave == 5 || wave == 6) lift_fill(lane + (wave == 6 ? 64 : 0), 128, &w);
   DSLAM_SYNC();
   if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
-  if (threadIdx.x < 64) visual_front_lanes((int)threadIdx.x, 64, &w, raw, sp, x0, x1);
-  if (full) imu_stage2(par, IMU_TASKS, 3, pre, sp.imu, &w.ic, &w.is, []() {});
-  if (threadIdx.x >= 64 && threadIdx.x < 192)  // two otherwise idle waves
-    init_system_b(Par{(int)threadIdx.x - 64, 128}, &w, sp, &pre, &prior);
+  if (wave == 0) unpack_sums(lane, &w, raw);
+  if (full) imu_stage2(par, 4, 3, pre, sp.imu, &w.ic, &w.is, []() {});
+  if (wave == 1 || wave == 2) init_system_b(Par{lane + (wave == 2 ? 64 : 0), 128}, &w, sp, &pre, &prior);
   DSLAM_SYNC();
   int st = solve_back(par, &w, sp, &pre, &prior, &x0, &x1, qIW, &marg);
   SERIAL {

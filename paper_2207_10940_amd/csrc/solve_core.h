@@ -299,10 +299,45 @@ DX void visual_front(SolveWork* w, const double* raw, const SolveParams& sp, con
   build_lift(sp.R_WM, x0, x1, w->Li, w->Lr);
 }
 
-// visual_front spread over the nl lanes of one wavefront (lane < nl): the
-// lanes unpack the 58 sums and fill the lift operators entry by entry.
-DX void visual_front_lanes(int lane, int nl, SolveWork* w, const double* raw, const SolveParams& sp,
-                           const dslam_frame_state& x0, const dslam_frame_state& x1) {
+// visual_front split for the device workgroup, in three parts that run on
+// different wavefronts and stages.  The lift operators depend on the states
+// only, so they are built before the visual sums are reduced:
+//   lift_sources: lanes 0..8 write the three 3x3 sources of the lift entries
+//     (R_WM, R0 and R0 hat(R0^T (r1 - r0))) to shared memory (indexed by entry
+//     below; private arrays indexed at run time would live in scratch memory);
+//   lift_fill: lanes 0..nl-1 fill the 144 entries of Li and Lr from them;
+//   unpack_sums: lanes 0..57 unpack the 58 sums.
+DX void lift_sources(int lane, SolveWork* w, const SolveParams& sp, const dslam_frame_state& x0,
+                     const dslam_frame_state& x1) {
+  const M3 RWM = load33(sp.R_WM), R0 = q2R(x0.q);
+  const V3 tb = tr(R0) * (load3(x1.r) - load3(x0.r));
+  const M3 R0Tb = R0 * hat(tb);
+  double* src = w->lift_src;
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    if (lane == k) {
+      src[k] = RWM.m[k];
+      src[9 + k] = R0.m[k];
+      src[18 + k] = R0Tb.m[k];
+    }
+}
+
+DX void lift_fill(int lane, int nl, SolveWork* w) {
+  const double* src = w->lift_src;
+  for (int idx = lane; idx < 144; idx += nl) {
+    const int m = idx / 72, r = (idx % 72) / 6, c = idx % 6;  // m 0: Li (ICP), 1: Lr (photometric)
+    const double* R = src + 9 * m;
+    double v = 0.0;
+    if (r >= 6 && r < 9 && c < 3) v = R[3 * (r - 6) + c];
+    else if (r >= 9 && c >= 3) v = R[3 * (r - 9) + c - 3];
+    else if (m == 1 && r < 3 && c < 3) v = -src[9 + 3 * r + c];
+    else if (m == 1 && r >= 3 && r < 6 && c >= 3) v = -src[9 + 3 * (r - 3) + c - 3];
+    else if (m == 1 && r >= 3 && r < 6 && c < 3) v = -src[18 + 3 * (r - 3) + c];
+    (m == 0 ? w->Li : w->Lr)[6 * r + c] = v;
+  }
+}
+
+DX void unpack_sums(int lane, SolveWork* w, const double* raw) {
   if (lane < 58) {
     const int t = lane / 29, q = lane % 29;
     if (q < 21) {
@@ -322,33 +357,6 @@ DX void visual_front_lanes(int lane, int nl, SolveWork* w, const double* raw, co
   if (lane == 0) {
     w->cost[2] = 0.0;
     w->cost[3] = 0.0;
-  }
-  // the three 3x3 sources go through shared memory (indexed by entry below;
-  // private arrays indexed at run time would live in scratch memory)
-  const M3 RWM = load33(sp.R_WM), R0 = q2R(x0.q);
-  const V3 tb = tr(R0) * (load3(x1.r) - load3(x0.r));
-  const M3 R0Tb = R0 * hat(tb);
-  double* src = w->lift_src;
-#pragma unroll
-  for (int k = 0; k < 9; ++k)
-    if (lane == k) {
-      src[k] = RWM.m[k];
-      src[9 + k] = R0.m[k];
-      src[18 + k] = R0Tb.m[k];
-    }
-#ifdef __HIP_DEVICE_COMPILE__
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#endif
-  for (int idx = lane; idx < 144; idx += nl) {
-    const int m = idx / 72, r = (idx % 72) / 6, c = idx % 6;  // m 0: Li (ICP), 1: Lr (photometric)
-    const double* R = src + 9 * m;
-    double v = 0.0;
-    if (r >= 6 && r < 9 && c < 3) v = R[3 * (r - 6) + c];
-    else if (r >= 9 && c >= 3) v = R[3 * (r - 9) + c - 3];
-    else if (m == 1 && r < 3 && c < 3) v = -src[9 + 3 * r + c];
-    else if (m == 1 && r >= 3 && r < 6 && c >= 3) v = -src[9 + 3 * (r - 3) + c - 3];
-    else if (m == 1 && r >= 3 && r < 6 && c < 3) v = -src[18 + 3 * (r - 3) + c];
-    (m == 0 ? w->Li : w->Lr)[6 * r + c] = v;
   }
 }
 
@@ -397,12 +405,28 @@ DX void init_system_H(Par par, SolveWork* w, const SolveParams& sp, const dslam_
                       const dslam_prior* prior) {
   const bool full = sp.mode != DSLAM_MODE_RGBD;
   const InitWeights iw = init_weights(sp, pre);
-  PFOR(idx, NZ * NZ) {
-    const int i = idx / NZ, j = idx % NZ, pi = iw.pidx(i), pj = iw.pidx(j);
-    double a = (full && pi >= 0 && pj >= 0) ? prior->H[18 * pi + pj] : 0.0;
-    if (i == j) a += iw.rw(i);
-    else if (j == i + 15 || i == j + 15) a -= iw.rw(i);  // x0 bias <-> the same x1 bias
-    w->H[idx] = a;
+  // U entries per lane and round: all of a lane's prior reads are issued before
+  // its stores (one shared-memory round trip instead of one per entry)
+  constexpr int U = 9;
+  for (int base = par.lane; base < NZ * NZ; base += U * par.nl) {
+    double pv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * par.nl, i = idx / NZ, j = idx % NZ, pi = iw.pidx(i), pj = iw.pidx(j);
+      const bool in_prior = full && idx < NZ * NZ && pi >= 0 && pj >= 0;
+      const double h = prior->H[in_prior ? 18 * pi + pj : 0];
+      pv[u] = in_prior ? h : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * par.nl, i = idx / NZ, j = idx % NZ;
+      if (idx < NZ * NZ) {
+        double a = pv[u];
+        if (i == j) a += iw.rw(i);
+        else if (j == i + 15 || i == j + 15) a -= iw.rw(i);  // x0 bias <-> the same x1 bias
+        w->H[idx] = a;
+      }
+    }
   }
   PFOR(i, 9 * NZ) w->J9[i] = 0.0;
   PFOR(i, 81) w->A9[i] = 0.0;
