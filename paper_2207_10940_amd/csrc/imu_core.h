@@ -199,32 +199,29 @@ DX int preintegrate(Par par, const dslam_imu_sample* s, int n, double t0, double
   for (int m = 0; m < nsub; ++m) {
     const double* A = w->A[m];
     const double* B = w->B[m];
-    PFOR(idx, 81) {
-      int i = idx / 9, j = idx % 9;
-      double acc = 0.0;
-      for (int k = 0; k < 9; ++k) acc += A[9 * i + k] * out->Sigma[9 * k + j];
-      w->T[idx] = acc;
-    }
-    PFOR(idx, 54) {
-      int i = idx / 6, j = idx % 6;
-      double acc = 0.0;
-      for (int k = 0; k < 9; ++k) acc += A[9 * i + k] * out->J[6 * k + j];
-      w->TB[idx] = acc;
+    PFOR(idx, 81 + 54) {
+      if (idx < 81) {
+        int i = idx / 9, j = idx % 9;
+        w->T[idx] = dotN<9>(A + 9 * i, 1, out->Sigma + j, 9);
+      } else {
+        int q = idx - 81, i = q / 6, j = q % 6;
+        w->TB[q] = dotN<9>(A + 9 * i, 1, out->J + j, 6);
+      }
     }
     DSLAM_SYNC();
     double dt = w->st[m].dt;
     double vg = sigma_g * sigma_g / dt, va = sigma_a * sigma_a / dt;
-    PFOR(idx, 81) {
-      int i = idx / 9, j = idx % 9;
-      double acc = 0.0;
-      for (int k = 0; k < 9; ++k) acc += w->T[9 * i + k] * A[9 * j + k];
-      double q = 0.0;
-      for (int k = 0; k < 3; ++k) q += B[6 * i + k] * B[6 * j + k];
-      double r = 0.0;
-      for (int k = 3; k < 6; ++k) r += B[6 * i + k] * B[6 * j + k];
-      out->Sigma[idx] = acc + vg * q + va * r;
+    PFOR(idx, 81 + 54) {
+      if (idx < 81) {
+        int i = idx / 9, j = idx % 9;
+        const double acc = dotN<9>(w->T + 9 * i, 1, A + 9 * j, 1);
+        const double q = dotN<3>(B + 6 * i, 1, B + 6 * j, 1);
+        const double r = dotN<3>(B + 6 * i + 3, 1, B + 6 * j + 3, 1);
+        out->Sigma[idx] = acc + vg * q + va * r;
+      } else {
+        out->J[idx - 81] = w->TB[idx - 81] + B[idx - 81];
+      }
     }
-    PFOR(idx, 54) out->J[idx] = w->TB[idx] + B[idx];
     DSLAM_SYNC();
   }
   SERIAL {
@@ -552,13 +549,26 @@ DX ImuBlockSpec imu_block_spec(int b) {
   }
 }
 
-DX void imu_block(const ImuCommon& c, int b, double* J9, double* A9) {
+// Entry q (0 <= q < IMU_BLOCK_ENTRIES) of the block table: entry (i, j) =
+// (q % 9 / 3, q % 3) of block q / 9, with the arithmetic of the 3x3 products
+// (A1 A2)(i, j) + (A3 A4)(i, j), so nine lanes compute a block together.
+// Entries 9 IMU_BLOCKS.. copy e_v / d(dv) = R_IW S into A9.
+enum { IMU_BLOCK_ENTRIES = 9 * (IMU_BLOCKS + 1) };
+DX void imu_block_entry(const ImuCommon& c, int q, double* J9, double* A9) {
+  const int b = q / 9, i = (q % 9) / 3, j = q % 3;
+  if (b == IMU_BLOCKS) {
+    A9[9 * (6 + i) + 3 + j] = c.mats[IC_QS](i, j);
+    return;
+  }
   const ImuBlockSpec t = imu_block_spec(b);
-  M3 r = c.mats[t.a1] * c.mats[t.a2];
-  if (t.a3 != IC_COUNT) r = r + c.mats[t.a3] * c.mats[t.a4];
-  if (t.dst == 0) put_block(J9, 33, t.row, t.col, r);
-  else put_block(A9, 9, t.row, t.col, r);
-  if (b == IMU_BLOCKS - 1) put_block(A9, 9, 6, 3, c.mats[IC_QS]);  // e_v / d(dv) = R_IW S
+  const M3 &a1 = c.mats[t.a1], &a2 = c.mats[t.a2];
+  double r = a1(i, 0) * a2(0, j) + a1(i, 1) * a2(1, j) + a1(i, 2) * a2(2, j);
+  if (t.a3 != IC_COUNT) {
+    const M3 &a3 = c.mats[t.a3], &a4 = c.mats[t.a4];
+    r = r + (a3(i, 0) * a4(0, j) + a3(i, 1) * a4(1, j) + a3(i, 2) * a4(2, j));
+  }
+  if (t.dst == 0) J9[(t.row + i) * 33 + t.col + j] = r;
+  else A9[(t.row + i) * 9 + t.col + j] = r;
 }
 
 // Gyro-only prediction: x1 = x0 with the orientation rotated by the

@@ -50,6 +50,47 @@ DX M3 operator-(const M3& a, const M3& b) { M3 r; for (int i = 0; i < 9; ++i) r.
 DX M3 operator*(double s, const M3& a) { M3 r; for (int i = 0; i < 9; ++i) r.m[i] = s * a.m[i]; return r; }
 DX M3 tr(const M3& a) { M3 r; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) r(i, j) = a(j, i); return r; }
 
+// sum_{k<N} a[k sa] b[k sb], accumulated from 0 in the order k = 0..N-1 (the
+// arithmetic of the plain loop), with all 2N shared-memory reads issued before
+// the first product: left to itself the compiler waits on each read in turn.
+template <int N>
+DX double dotN(const double* a, int sa, const double* b, int sb) {
+  double x[N], y[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    x[k] = a[k * sa];
+    y[k] = b[k * sb];
+  }
+#ifdef __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) s += x[k] * y[k];
+  return s;
+}
+
+// sum_{k<N} (a[k] b[k] + c[k] d[k]) in the same way (each step adds the sum of
+// the two products).
+template <int N>
+DX double dot2N(const double* a, const double* b, const double* c, const double* d) {
+  double x[N], y[N], u[N], v[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    x[k] = a[k];
+    y[k] = b[k];
+    u[k] = c[k];
+    v[k] = d[k];
+  }
+#ifdef __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) s += x[k] * y[k] + u[k] * v[k];
+  return s;
+}
+
 // Rodrigues' formula; below 0.1 rad its coefficients come from their Taylor
 // series (exact to double precision there), which avoids sin/cos for the small
 // rotations of a Gauss-Newton step or an IMU sample.

@@ -177,15 +177,20 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   if (wave == 1 || wave == 2) init_system_b(Par{lane + (wave == 2 ? 64 : 0), 128}, &w, sp, &pre, &prior);
   DSLAM_SYNC();
   int st = solve_back(par, &w, sp, &pre, &prior, &x0, &x1, qIW, &marg);
-  SERIAL {
+  // the next pass's transforms on 24 lanes of wave 0, the states and the
+  // step's record by the first lanes of waves 1 and 2
+  if (st == DSLAM_OK && threadIdx.x < 24)
+    sd->xf[threadIdx.x] = next_transform_entry(x0, x1, sp.R_WM, sp.t_WM, (int)threadIdx.x);
+  TASK(1) {
     if (st != DSLAM_OK) {
       sd->status = st;
     } else {
       sd->x0 = x0;
       sd->x1 = x1;
       for (int i = 0; i < 4; ++i) sd->qIW[i] = qIW[i];
-      next_transforms(x0, x1, sp.R_WM, sp.t_WM, sd->xf);
     }
+  }
+  TASK(2) {
     sd->result.n_icp[a.level] = (int64_t)raw[28];
     sd->result.n_rgb[a.level] = (int64_t)raw[57];
     sd->result.cost_icp = w.cost[0];

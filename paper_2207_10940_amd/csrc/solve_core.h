@@ -26,6 +26,8 @@ namespace dslam {
 
 enum { NZ = 33 };
 
+
+
 struct SolveParams {
   double R_WM[9], t_WM[3];
   ImuParamsD imu;
@@ -141,6 +143,30 @@ DX void next_transforms(const dslam_frame_state& x0, const dslam_frame_state& x1
     xf[9 + i] = (float)ta[i];
     xf[21 + i] = (float)tb[i];
   }
+}
+
+// Entry e (0..23) of next_transforms' output, computed on its own (the same
+// operations as next_transforms performs for that entry), so 24 lanes can
+// produce the transforms together.
+DX float next_transform_entry(const dslam_frame_state& x0, const dslam_frame_state& x1, const double* R_WM,
+                              const double* t_WM, int e) {
+  const bool second = e >= 12;  // Rb, tb (reference camera) else Ra, ta (model view)
+  const int q = second ? e - 12 : e;
+  const M3 L = second ? q2R(x0.q) : load33(R_WM);  // the transform is L^T [R1 | r1 - o]
+  const M3 R1 = q2R(x1.q);
+  const V3 d = load3(x1.r) - (second ? load3(x0.r) : load3(t_WM));
+  // every entry with fixed indices, then a select (private arrays indexed at
+  // run time would live in scratch memory)
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int i = k / 3, j = k % 3;
+    const double r = L(0, i) * R1(0, j) + L(1, i) * R1(1, j) + L(2, i) * R1(2, j);
+    v = (q == k) ? r - ((i == j) ? 1.0 : 0.0) : v;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v = (q == 9 + i) ? L(0, i) * d.x + L(1, i) * d.y + L(2, i) * d.z : v;
+  return (float)v;
 }
 
 DX void state_boxplus(dslam_frame_state* x, const double* d) {
@@ -274,6 +300,33 @@ DX int spd_solve(Par par, SolveWork* w, const double* H, const double* b, int n,
   }
   return 0;
 #endif
+}
+
+// The IMU factor's weight and weighted Jacobian from Y = A9 Sigma:
+// S9 = Y A9^T (gyro-only: the rotation rows' block, identity elsewhere, which
+// decouples the dropped rows and leaves the rotation rows weighted by the
+// inverse of their marginal covariance), W9 = S9^-1 (overwrites A9),
+// T = W9 J9 (into Y) and we = W9 e (into y).  Returns 0, or 1 if S9 is not SPD.
+DX int imu_weight(Par par, SolveWork* w, bool gyro) {
+  PFOR(idx, 81) {
+    const int i = idx / 9, j = idx % 9;
+    double a = dotN<9>(w->Y + 9 * i, 1, w->A9 + 9 * j, 1);
+    if (gyro && !(i >= 3 && i < 6 && j >= 3 && j < 6)) a = (i == j) ? 1.0 : 0.0;
+    w->S9[idx] = a;
+  }
+  DSLAM_SYNC();
+  if (spd_inverse9(par, w, w->S9, w->A9)) return 1;  // W9 overwrites A9 (ends with a barrier)
+  PFOR(idx, 9 * NZ + 9) {
+    if (idx < 9 * NZ) {
+      const int i = idx / NZ, c = idx % NZ;
+      w->Y[idx] = dotN<9>(w->A9 + 9 * i, 1, w->J9 + c, NZ);
+    } else {
+      const int r = idx - 9 * NZ;
+      w->y[r] = dotN<9>(w->A9 + 9 * r, 1, w->e, 1);
+    }
+  }
+  DSLAM_SYNC();
+  return 0;
 }
 
 // One Gauss-Newton step.  raw: the 58 sums of the residual pass (ICP then RGB),
@@ -482,29 +535,25 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
   const bool gyro = sp.mode == DSLAM_MODE_GYRO;
   const int n = full ? NZ : 6;
   const bool marg = full && sp.marginalise && marg_out != nullptr;
-  // ---- LH = L Hm (12x6) per term; IMU Jacobian blocks
-  PFOR(idx, 72 + IMU_BLOCKS) {
+  // ---- LH = L Hm (12x6) per term; IMU Jacobian blocks, one entry per lane
+  PFOR(idx, 72 + IMU_BLOCK_ENTRIES) {
     if (idx < 72) {
       int i = idx / 6, j = idx % 6;
-      double a = 0.0, c = 0.0;
-      for (int k = 0; k < 6; ++k) {
-        a += w->Lr[6 * i + k] * w->Hm[1][6 * k + j];
-        c += w->Li[6 * i + k] * w->Hm[0][6 * k + j];
-      }
-      w->LH[idx] = a;
-      w->LHi[idx] = c;
+      w->LH[idx] = dotN<6>(w->Lr + 6 * i, 1, w->Hm[1] + j, 6);
+      w->LHi[idx] = dotN<6>(w->Li + 6 * i, 1, w->Hm[0] + j, 6);
     } else if (full) {
-      imu_block(w->ic, idx - 72, w->J9, w->A9);
+      imu_block_entry(w->ic, idx - 72, w->J9, w->A9);
     }
   }
   DSLAM_SYNC();
   // ---- visual 12x12 block into z indices {0..5, 15..20} (RGBD mode: only the
-  // x1 pose block); Y = A9 Sigma for the IMU covariance
-  PFOR(idx, 144 + 12 + 81) {
+  // x1 pose block); Y = A9 Sigma for the IMU covariance; gyro-only: the
+  // position and velocity rows (accelerometer) of the Jacobian and the residual
+  // are dropped (zeroed)
+  PFOR(idx, 144 + 12 + 81 + 9 * NZ + 9) {
     if (idx < 144) {
       int i = idx / 12, j = idx % 12;
-      double a = 0.0;
-      for (int k = 0; k < 6; ++k) a += w->LH[6 * i + k] * w->Lr[6 * j + k] + w->LHi[6 * i + k] * w->Li[6 * j + k];
+      const double a = dot2N<6>(w->LH + 6 * i, w->Lr + 6 * j, w->LHi + 6 * i, w->Li + 6 * j);
       if (full) w->H[(i < 6 ? i : 9 + i) * NZ + (j < 6 ? j : 9 + j)] += a;
       else if (i >= 6 && j >= 6) w->H[(i - 6) * NZ + (j - 6)] += a;
     } else if (idx < 156) {
@@ -513,56 +562,28 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
       for (int k = 0; k < 6; ++k) a -= w->Lr[6 * i + k] * w->gm[1][k] + w->Li[6 * i + k] * w->gm[0][k];
       if (full) w->b[i < 6 ? i : 9 + i] += a;
       else if (i >= 6) w->b[i - 6] += a;
-    } else if (full) {
-      int q = idx - 156, i = q / 9, j = q % 9;
-      double a = 0.0;
-      for (int k = 0; k < 9; ++k) a += w->A9[9 * i + k] * pre->Sigma[9 * k + j];
-      w->Y[q] = a;
+    } else if (idx < 237) {
+      if (full) {
+        int q = idx - 156, i = q / 9, j = q % 9;
+        w->Y[q] = dotN<9>(w->A9 + 9 * i, 1, pre->Sigma + j, 9);
+      }
+    } else if (gyro) {
+      const int q = idx - 237, r = q < 9 * NZ ? q / NZ : q - 9 * NZ;
+      if (r < 3 || r >= 6) {
+        if (q < 9 * NZ) w->J9[q] = 0.0;
+        else w->e[r] = 0.0;
+      }
     }
   }
   DSLAM_SYNC();
   if (full) {
-    // ---- IMU term: Sigma_e = A9 Sigma A9^T (+ random-walk rows), W = Sigma_e^-1
-    PFOR(idx, 81 + 9 * NZ + 9) {
-      if (idx < 81) {
-        int i = idx / 9, j = idx % 9;
-        double a = 0.0;
-        for (int k = 0; k < 9; ++k) a += w->Y[9 * i + k] * w->A9[9 * j + k];
-        // gyro-only: the position and velocity rows (accelerometer) are dropped;
-        // decoupling them leaves the rotation rows weighted by the inverse of
-        // their marginal covariance
-        if (gyro && !(i >= 3 && i < 6 && j >= 3 && j < 6)) a = (i == j) ? 1.0 : 0.0;
-        w->S9[idx] = a;
-      } else if (gyro) {  // zero the dropped rows of the Jacobian and the residual
-        const int q = idx - 81, r = q < 9 * NZ ? q / NZ : q - 9 * NZ;
-        if (r < 3 || r >= 6) {
-          if (q < 9 * NZ) w->J9[q] = 0.0;
-          else w->e[r] = 0.0;
-        }
-      }
-    }
-    DSLAM_SYNC();
-    if (spd_inverse9(par, w, w->S9, w->A9)) {  // W9 overwrites A9
+    // ---- IMU term: Sigma_e = A9 Sigma A9^T (+ random-walk rows), W = Sigma_e^-1,
+    // T = W9 J9 (9 x 33) into Y, we = W9 e9 into y
+    if (imu_weight(par, w, gyro)) {
       SERIAL w->status = DSLAM_ERR_SINGULAR;
       DSLAM_SYNC();
       return DSLAM_ERR_SINGULAR;
     }
-    DSLAM_SYNC();
-    // T = W9 J9 (9 x 33), we = W9 e9
-    PFOR(idx, 9 * NZ + 9) {
-      int i = idx / NZ, c = idx % NZ;
-      if (idx < 9 * NZ) {
-        double a = 0.0;
-        for (int k = 0; k < 9; ++k) a += w->A9[9 * i + k] * w->J9[k * NZ + c];
-        w->Y[idx] = a;
-      } else {
-        int r = idx - 9 * NZ;
-        double a = 0.0;
-        for (int k = 0; k < 9; ++k) a += w->A9[9 * r + k] * w->e[k];
-        w->y[r] = a;
-      }
-    }
-    DSLAM_SYNC();
     // H += J9^T T, b -= J9^T we; the IMU cost e^T W e plus the random-walk rows
     TASK(1) {
       double c = 0.0;
@@ -576,16 +597,14 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
     PFOR(idx, NZ * NZ + NZ) {
       if (idx < NZ * NZ) {
         int i = idx / NZ, j = idx % NZ;
-        double a = 0.0;
-        for (int k = 0; k < 9; ++k) a += w->J9[k * NZ + i] * w->Y[k * NZ + j];
+        const double a = dotN<9>(w->J9 + i, NZ, w->Y + j, NZ);
         // gyro-only: the entries no remaining term constrains are held fixed
         // (identity rows and columns, zero right-hand side)
         if (gyro && (gyro_fixed(i) || gyro_fixed(j))) w->H[idx] = (i == j) ? 1.0 : 0.0;
         else w->H[idx] += a;
       } else {
         int i = idx - NZ * NZ;
-        double a = 0.0;
-        for (int k = 0; k < 9; ++k) a += w->J9[k * NZ + i] * w->y[k];
+        const double a = dotN<9>(w->J9 + i, NZ, w->y, 1);
         if (gyro && gyro_fixed(i)) w->b[i] = 0.0;
         else w->b[i] -= a;
       }
