@@ -30,6 +30,7 @@ struct SessionDev {
   double qIW[4];
   dslam_prior prior;
   dslam_preint pre;
+  double Linv[81];     // L^-1 of pre.Sigma = L L^T (row-major, lower triangular)
   float xf[24];        // Ra-I (9) ta (3) Rb-I (9) tb (3) for the next residual pass
   double sys[58];      // reduced sums of the last residual pass
   dslam_track_result result;

@@ -251,28 +251,30 @@ struct ImuParamsD {
 
 // Quantities shared by the IMU error and its Jacobian blocks.
 struct ImuCommon {
-  // operands of the Jacobian blocks (see imu_block); mats[0] is the identity
-  M3 mats[24];
+  // operands of the Jacobian blocks (see imu_block_entry) and of the noise
+  // map's inverse; mats[0] is the identity
+  M3 mats[27];
   double T;
 };
 
 // indices into ImuCommon::mats
 enum {
   IC_I = 0, IC_NEG_I, IC_HAT_R0YR, IC_QT, IC_S, IC_JPG, IC_KROT, IC_JRG, IC_JPA, IC_JRA, IC_HAT_YG, IC_JLI, IC_KAL,
-  IC_JRI, IC_Q, IC_HAT_SDV, IC_QS, IC_JVG, IC_JVA, IC_HAT_QSDV, IC_KROT_NOISE, IC_JLI_SDRT, IC_RBT, IC_COUNT
+  IC_JRI, IC_Q, IC_HAT_SDV, IC_QS, IC_JVG, IC_JVA, IC_HAT_QSDV,
+  // the noise map's inverse (see imu_whitening)
+  IC_YI, IC_ST, IC_QST, IC_SXY, IC_COUNT
 };
 
-enum { IMU_BLOCKS = 20 };
+enum { IMU_BLOCKS = 17 };
 
-// IMU error e = x1_hat(x0) [-] x1 (eq. (5)), ordered [r, alpha, v, bg, ba],
-// and the quantities its Jacobian blocks need (c may be nullptr: residual
-// only).  The derivation uses the left perturbations of Section IV-A; with
+// IMU error e = x1_hat(x0) [-] x1 (eq. (5)), ordered [r, alpha, v, bg, ba]
+// (the staged form below also produces the Jacobian operands).  The derivation uses the left perturbations of Section IV-A; with
 // S = R0 R_CS, dR~ = dR Exp(J_R db) and y_r = t_CS + R_CS dp~ - R_CS dR~ R_CS^T t_CS:
 //   r_hat = r0 + R0 y_r + R_IW^T (v0 T + g T^2/2),
 //   R_hat = S dR~ R_CS^T,  v_hat = v0 + g T + R_IW S dv~.
 // Serial.
 DX void imu_common(const dslam_frame_state& x0, const dslam_frame_state& x1, const double* qIW,
-                   const dslam_preint& pre, const ImuParamsD& ip, double* e, ImuCommon* c) {
+                   const dslam_preint& pre, const ImuParamsD& ip, double* e) {
   M3 R0 = q2R(x0.q), R1 = q2R(x1.q), Q = q2R(qIW);
   M3 Rcs = load33(ip.R_CS);
   V3 tcs = load3(ip.t_CS);
@@ -322,38 +324,6 @@ DX void imu_common(const dslam_frame_state& x0, const dslam_frame_state& x1, con
     e[9 + i] = x0.bg[i] - x1.bg[i];
     e[12 + i] = x0.ba[i] - x1.ba[i];
   }
-  if (c == nullptr) return;
-  M3* m = c->mats;
-  M3 Jli = JlInv(ea);
-  M3 Jrb = Jr(phib);
-  M3 hwt = hat(wt);
-  m[IC_I] = eye3();
-  m[IC_NEG_I] = (-1.0) * eye3();
-  m[IC_HAT_R0YR] = (-1.0) * hat(R0 * yr);
-  m[IC_QT] = T * Qt;
-  m[IC_S] = S;
-  m[IC_KROT] = SdRt * hwt * Jrb;
-  m[IC_HAT_YG] = Qt * hat(yg);
-  m[IC_JLI] = Jli;
-  m[IC_KAL] = Jli * SdRt * Jrb;
-  m[IC_JRI] = (-1.0) * tr(Jli);
-  m[IC_Q] = (-1.0) * Q;
-  m[IC_HAT_SDV] = hat(Sdv);
-  m[IC_QS] = Q * S;
-  m[IC_HAT_QSDV] = (-1.0) * hat(QSdv);
-  m[IC_KROT_NOISE] = SdRt * hwt;
-  m[IC_JLI_SDRT] = Jli * SdRt;
-  m[IC_RBT] = tr(Rb);
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      m[IC_JRG](i, j) = pre.J[6 * i + j];
-      m[IC_JRA](i, j) = pre.J[6 * i + 3 + j];
-      m[IC_JVG](i, j) = pre.J[6 * (3 + i) + j];
-      m[IC_JVA](i, j) = pre.J[6 * (3 + i) + 3 + j];
-      m[IC_JPG](i, j) = pre.J[6 * (6 + i) + j];
-      m[IC_JPA](i, j) = pre.J[6 * (6 + i) + 3 + j];
-    }
-  c->T = T;
 }
 
 // Intermediates of imu_common_par shared between its lanes.
@@ -455,28 +425,33 @@ DX void imu_stage2(Par par, int tb, int tb2, const dslam_preint& pre, const ImuP
     m[IC_JLI] = Jli;
     m[IC_KAL] = Jli * t->SdRt * t->Jrb;
     m[IC_JRI] = (-1.0) * tr(Jli);
-    m[IC_JLI_SDRT] = Jli * t->SdRt;
   }
   TASK(tb + 1) {
     M3 Rcs = load33(ip.R_CS);
     M3 Qt = tr(t->Q);
     M3 S = t->R0 * Rcs;
+    M3 QS = t->Q * S;
     m[IC_HAT_R0YR] = (-1.0) * hat(t->R0 * t->yr);
     m[IC_QT] = pre.dt * Qt;
     m[IC_S] = S;
     m[IC_HAT_YG] = Qt * hat(t->yg);
     m[IC_Q] = (-1.0) * t->Q;
-    m[IC_QS] = t->Q * S;
+    m[IC_QS] = QS;
+    m[IC_ST] = tr(S);
+    m[IC_QST] = tr(QS);
   }
   TASK(tb2) {
     M3 Rcs = load33(ip.R_CS);
     V3 wt = tr(Rcs) * load3(ip.t_CS);
     M3 SdRthwt = t->SdRt * hat(wt);
     m[IC_KROT] = SdRthwt * t->Jrb;
-    m[IC_KROT_NOISE] = SdRthwt;
     m[IC_HAT_SDV] = hat(t->Sdv);
     m[IC_HAT_QSDV] = (-1.0) * hat(t->QSdv);
-    m[IC_RBT] = tr(t->Rb);
+    // inverse of the noise map's blocks (imu_whitening): with P = (S dR~)^T Jl(e_a),
+    // Y^-1 = Rb P and S^T X Y^-1 = S^T (S dR~ [w]x) P (Jl(a) = Jr(-a))
+    M3 P = tr(t->SdRt) * Jr((-1.0) * t->ea);
+    m[IC_YI] = t->Rb * P;
+    m[IC_SXY] = (-1.0) * (tr(t->R0 * Rcs) * (SdRthwt * P));
   }
   TASK(tb + 2) {
     m[IC_I] = eye3();
@@ -512,54 +487,45 @@ DX void put_block(double* M, int ld, int r0, int c0, const M3& B) {
     for (int j = 0; j < 3; ++j) M[(r0 + i) * ld + c0 + j] = B(i, j);
 }
 
-// Jacobian block table: block b is out[row, col] = A1 A2 + A3 A4 with the
+// Jacobian block table: block b is J9[row, col] = A1 A2 + A3 A4 with the
 // operands taken from ImuCommon::mats (the identity pads unused factors, and
-// A3 A4 = 0 when A3 is IC_COUNT).  dst 0: J9 (9x33), dst 1: A9 (9x9).
+// A3 A4 = 0 when A3 is IC_COUNT).
 struct ImuBlockSpec {
-  signed char dst, row, col, a1, a2, a3, a4;
+  signed char row, col, a1, a2, a3, a4;
 };
 
 // Block b (0 <= b < IMU_BLOCKS) of the Jacobian rows J9 (9x33 over
-// [x0 (15), x1 (15), dg (3)]) of the first nine IMU error entries and of the
-// map A9 (9x9) from the preintegration noise (dphi, dv, dp) to them.  J9 and
-// A9 must be zero-filled first; blocks write disjoint entries.  Every block
-// runs the same instructions on different operands, so lanes do not diverge.
+// [x0 (15), x1 (15), dg (3)]) of the first nine IMU error entries.  J9 must be
+// zero-filled first; blocks write disjoint entries.  Every block runs the same
+// instructions on different operands, so lanes do not diverge.
 DX ImuBlockSpec imu_block_spec(int b) {
   switch (b) {
-    case 0: return {0, 0, 0, IC_I, IC_I, IC_COUNT, 0};               // e_r / dr0 = I
-    case 1: return {0, 0, 15, IC_NEG_I, IC_I, IC_COUNT, 0};          // e_r / dr1 = -I
-    case 2: return {0, 0, 3, IC_HAT_R0YR, IC_I, IC_COUNT, 0};        // e_r / da0 = -[R0 y_r]x
-    case 3: return {0, 0, 6, IC_QT, IC_I, IC_COUNT, 0};              // e_r / dv0 = T R_IW^T
-    case 4: return {0, 0, 9, IC_S, IC_JPG, IC_KROT, IC_JRG};         // e_r / dbg0
-    case 5: return {0, 0, 12, IC_S, IC_JPA, IC_KROT, IC_JRA};        // e_r / dba0
-    case 6: return {0, 0, 30, IC_HAT_YG, IC_I, IC_COUNT, 0};         // e_r / dg = R_IW^T [y_g]x
-    case 7: return {0, 3, 3, IC_JLI, IC_I, IC_COUNT, 0};             // e_a / da0 = Jl^-1
-    case 8: return {0, 3, 9, IC_KAL, IC_JRG, IC_COUNT, 0};           // e_a / dbg0
-    case 9: return {0, 3, 12, IC_KAL, IC_JRA, IC_COUNT, 0};          // e_a / dba0
-    case 10: return {0, 3, 18, IC_JRI, IC_I, IC_COUNT, 0};           // e_a / da1 = -Jr^-1
-    case 11: return {0, 6, 6, IC_I, IC_I, IC_COUNT, 0};              // e_v / dv0 = I
-    case 12: return {0, 6, 21, IC_NEG_I, IC_I, IC_COUNT, 0};         // e_v / dv1 = -I
-    case 13: return {0, 6, 3, IC_Q, IC_HAT_SDV, IC_COUNT, 0};        // e_v / da0 = -R_IW [S dv~]x
-    case 14: return {0, 6, 9, IC_QS, IC_JVG, IC_COUNT, 0};           // e_v / dbg0
-    case 15: return {0, 6, 12, IC_QS, IC_JVA, IC_COUNT, 0};          // e_v / dba0
-    case 16: return {0, 6, 30, IC_HAT_QSDV, IC_I, IC_COUNT, 0};      // e_v / dg = -[R_IW S dv~]x
-    case 17: return {1, 0, 0, IC_KROT_NOISE, IC_RBT, IC_COUNT, 0};   // e_r / dphi
-    case 18: return {1, 3, 0, IC_JLI_SDRT, IC_RBT, IC_COUNT, 0};     // e_a / dphi
-    default: return {1, 0, 6, IC_S, IC_I, IC_COUNT, 0};              // e_r / d(dp) (e_v / d(dv) below)
+    case 0: return {0, 0, IC_I, IC_I, IC_COUNT, 0};               // e_r / dr0 = I
+    case 1: return {0, 15, IC_NEG_I, IC_I, IC_COUNT, 0};          // e_r / dr1 = -I
+    case 2: return {0, 3, IC_HAT_R0YR, IC_I, IC_COUNT, 0};        // e_r / da0 = -[R0 y_r]x
+    case 3: return {0, 6, IC_QT, IC_I, IC_COUNT, 0};              // e_r / dv0 = T R_IW^T
+    case 4: return {0, 9, IC_S, IC_JPG, IC_KROT, IC_JRG};         // e_r / dbg0
+    case 5: return {0, 12, IC_S, IC_JPA, IC_KROT, IC_JRA};        // e_r / dba0
+    case 6: return {0, 30, IC_HAT_YG, IC_I, IC_COUNT, 0};         // e_r / dg = R_IW^T [y_g]x
+    case 7: return {3, 3, IC_JLI, IC_I, IC_COUNT, 0};             // e_a / da0 = Jl^-1
+    case 8: return {3, 9, IC_KAL, IC_JRG, IC_COUNT, 0};           // e_a / dbg0
+    case 9: return {3, 12, IC_KAL, IC_JRA, IC_COUNT, 0};          // e_a / dba0
+    case 10: return {3, 18, IC_JRI, IC_I, IC_COUNT, 0};           // e_a / da1 = -Jr^-1
+    case 11: return {6, 6, IC_I, IC_I, IC_COUNT, 0};              // e_v / dv0 = I
+    case 12: return {6, 21, IC_NEG_I, IC_I, IC_COUNT, 0};         // e_v / dv1 = -I
+    case 13: return {6, 3, IC_Q, IC_HAT_SDV, IC_COUNT, 0};        // e_v / da0 = -R_IW [S dv~]x
+    case 14: return {6, 9, IC_QS, IC_JVG, IC_COUNT, 0};           // e_v / dbg0
+    case 15: return {6, 12, IC_QS, IC_JVA, IC_COUNT, 0};          // e_v / dba0
+    default: return {6, 30, IC_HAT_QSDV, IC_I, IC_COUNT, 0};      // e_v / dg = -[R_IW S dv~]x
   }
 }
 
 // Entry q (0 <= q < IMU_BLOCK_ENTRIES) of the block table: entry (i, j) =
 // (q % 9 / 3, q % 3) of block q / 9, with the arithmetic of the 3x3 products
 // (A1 A2)(i, j) + (A3 A4)(i, j), so nine lanes compute a block together.
-// Entries 9 IMU_BLOCKS.. copy e_v / d(dv) = R_IW S into A9.
-enum { IMU_BLOCK_ENTRIES = 9 * (IMU_BLOCKS + 1) };
-DX void imu_block_entry(const ImuCommon& c, int q, double* J9, double* A9) {
+enum { IMU_BLOCK_ENTRIES = 9 * IMU_BLOCKS };
+DX void imu_block_entry(const ImuCommon& c, int q, double* J9) {
   const int b = q / 9, i = (q % 9) / 3, j = q % 3;
-  if (b == IMU_BLOCKS) {
-    A9[9 * (6 + i) + 3 + j] = c.mats[IC_QS](i, j);
-    return;
-  }
   const ImuBlockSpec t = imu_block_spec(b);
   const M3 &a1 = c.mats[t.a1], &a2 = c.mats[t.a2];
   double r = a1(i, 0) * a2(0, j) + a1(i, 1) * a2(1, j) + a1(i, 2) * a2(2, j);
@@ -567,8 +533,33 @@ DX void imu_block_entry(const ImuCommon& c, int q, double* J9, double* A9) {
     const M3 &a3 = c.mats[t.a3], &a4 = c.mats[t.a4];
     r = r + (a3(i, 0) * a4(0, j) + a3(i, 1) * a4(1, j) + a3(i, 2) * a4(2, j));
   }
-  if (t.dst == 0) J9[(t.row + i) * 33 + t.col + j] = r;
-  else A9[(t.row + i) * 9 + t.col + j] = r;
+  J9[(t.row + i) * 33 + t.col + j] = r;
+}
+
+// The IMU factor's weight W = (A Sigma A^T)^-1 in factored form.  The map A
+// (9x9) from the preintegration noise (dphi, dv, dp) to the error rows
+// (r, alpha, v) has the block structure
+//   r = X dphi + S dp,  alpha = Y dphi,  v = R_IW S dv
+// with X = S dR~ [w]x Rb^T, Y = Jl^-1(e_a) S dR~ Rb^T (w = R_CS^T t_CS), so
+//   A^-1 = [[0, Y^-1, 0], [0, 0, (R_IW S)^T], [S^T, -S^T X Y^-1, 0]]
+// (rows dphi, dv, dp; columns r, alpha, v), where every factor but Jl^-1 is a
+// rotation.  With Sigma = L L^T (Cholesky, once per step) and M = L^-1 A^-1,
+// W = M^T M: the whitened rows M J and M e replace the 9x9 inverse.
+// Entry (i, c) of M from Linv = L^-1 (lower triangular, row-major) and the
+// operands IC_YI, IC_ST, IC_QST, IC_SXY.
+DX double imu_whitening(const ImuCommon& ic, const double* Linv, int i, int c) {
+  const M3* m = ic.mats;
+  const int j = c % 3;
+  double a = 0.0;
+  if (c < 3) {  // r: dp rows of A^-1
+    for (int k = 0; k < 3; ++k) a += Linv[9 * i + 6 + k] * m[IC_ST](k, j);
+  } else if (c < 6) {  // alpha: dphi and dp rows
+    for (int k = 0; k < 3; ++k) a += Linv[9 * i + k] * m[IC_YI](k, j);
+    for (int k = 0; k < 3; ++k) a += Linv[9 * i + 6 + k] * m[IC_SXY](k, j);
+  } else {  // v: dv rows
+    for (int k = 0; k < 3; ++k) a += Linv[9 * i + 3 + k] * m[IC_QST](k, j);
+  }
+  return a;
 }
 
 // Gyro-only prediction: x1 = x0 with the orientation rotated by the
@@ -593,7 +584,7 @@ DX void imu_predict_gyro(const dslam_frame_state& x0, const dslam_preint& pre, c
 DX void imu_predict(const dslam_frame_state& x0, const double* qIW, const dslam_preint& pre, const ImuParamsD& ip,
                     dslam_frame_state* x1) {
   double e[15];
-  imu_common(x0, x0, qIW, pre, ip, e, nullptr);
+  imu_common(x0, x0, qIW, pre, ip, e);
   // e = x1_hat [-] x0 with x1 := x0; recover x1_hat
   *x1 = x0;
   for (int i = 0; i < 3; ++i) {

@@ -77,6 +77,20 @@ __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& 
   int st = DSLAM_OK;
   if (fa.mode != DSLAM_MODE_RGBD)
     st = preintegrate(par, batch.s, batch.n, batch.t0, batch.t1, x0.bg, x0.ba, fa.sigma_g, fa.sigma_a, &pw, &pre);
+  if (fa.mode != DSLAM_MODE_RGBD && st == DSLAM_OK) {  // uniform
+    // L^-1 of the preintegration covariance for the IMU whitening of every
+    // step of this frame (wave 0)
+    __shared__ __attribute__((aligned(16))) double col[128];
+    __shared__ double linv[81];
+    __shared__ int lbad;
+    if (threadIdx.x < 64) {
+      const bool ok = chol_inv_lower9_wave(pre.Sigma, linv, (int)threadIdx.x, col);
+      if (threadIdx.x == 0) lbad = ok ? 0 : 1;
+    }
+    DSLAM_SYNC();
+    if (threadIdx.x < 81) sd->Linv[threadIdx.x] = linv[threadIdx.x];
+    if (lbad) st = DSLAM_ERR_SINGULAR;
+  }
   SERIAL {
     if (st != DSLAM_OK) sd->status = st;
     dslam_frame_state x1 = x0;
@@ -127,6 +141,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
     };
     copy(&sd->prior, &prior, sizeof(dslam_prior));
     copy(&sd->pre, &pre, sizeof(dslam_preint));
+    copy(sd->Linv, w.Linv, sizeof(w.Linv));
     copy(&sd->x0, &x0, sizeof(dslam_frame_state));
     copy(&sd->x1, &x1, sizeof(dslam_frame_state));
     copy(sd->qIW, qIW, sizeof(qIW));

@@ -39,12 +39,13 @@ struct SolveWork {
   double H[NZ * NZ];   // assembled system (full symmetric)
   double L[(NZ + 1) * NZ];  // Cholesky factor (lower) with the right-hand side as row NZ; Schur workspace
   double b[NZ], y[NZ], dz[NZ];
-  double J9[9 * NZ];   // IMU Jacobian rows (then whitened)
-  double A9[81], S9[81];
+  double J9[9 * NZ];   // IMU Jacobian rows
+  double Linv[81];     // L^-1 of the preintegration covariance Sigma = L L^T
+  double M9[81];       // whitening of the IMU error rows: W = M9^T M9
   double e[15];
   double Hm[2][36], gm[2][6];
   double Lr[12 * 6], LH[12 * 6], Li[12 * 6], LHi[12 * 6];
-  double Y[18 * 19 > 9 * NZ ? 18 * 19 : 9 * NZ];  // scratch: A9 Sigma, W9 J9, H00^-1 [H0k, b0], Schur complement
+  double Y[18 * 19 > 9 * NZ ? 18 * 19 : 9 * NZ];  // scratch: whitened J9 rows, H00^-1 [H0k, b0], Schur complement
   double prior_d[18];
   double lift_src[27];  // R_WM, R0, R0 [t_b]x for the parallel lift
   double cost[4];
@@ -242,27 +243,37 @@ DX void lift_visual(const double* raw, const double* R_WM, const dslam_frame_sta
 // declared here and defined by the device translation unit.
 // ---------------------------------------------------------------------------
 #ifdef __HIP_DEVICE_COMPILE__
-__device__ int spd_inverse9_dev(const double* S9, double* W9);
 __device__ int spd_solve_dev(const double* H, const double* b, int n, double* dz, double* schur);
 #endif
 
-// W9 = S9^-1 for a 9x9 SPD matrix.  Returns 0, or 1 if S9 is not SPD.
-DX int spd_inverse9(Par par, SolveWork* w, const double* S9, double* W9) {
-#ifdef __HIP_DEVICE_COMPILE__
-  (void)par;
-  (void)w;
-  return spd_inverse9_dev(S9, W9);
-#else
-  double L[81], X[81];
-  for (int i = 0; i < 81; ++i) {
-    L[i] = S9[i];
-    X[i] = (i % 10 == 0) ? 1.0 : 0.0;
-  }
-  if (cholesky(par, L, 9, 9, 0, &w->status)) return 1;
-  chol_solve_cols(par, L, 9, 9, X, 9, 9);
-  for (int i = 0; i < 81; ++i) W9[i] = X[i];
+// Linv = L^-1 for the 9x9 SPD S = L L^T (row-major; L lower triangular):
+// textbook Cholesky, then forward substitution.  Returns 0, or 1 if S is not
+// positive definite.  Host; the device computes it on a wavefront
+// (chol_inv_lower9_wave) once per frame.
+DX int chol_inv_lower9(const double* S, double* Linv) {
+  double L[81] = {0.0};
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double a = S[9 * i + j];
+      for (int k = 0; k < j; ++k) a -= L[9 * i + k] * L[9 * j + k];
+      if (i == j) {
+        if (!(a > 0.0) || !(a < 1e300)) return 1;
+        L[9 * i + i] = sqrt(a);
+      } else {
+        L[9 * i + j] = a / L[9 * j + j];
+      }
+    }
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j) {
+      double a = (i == j) ? 1.0 : 0.0;
+      if (j > i) {
+        Linv[9 * i + j] = 0.0;
+        continue;
+      }
+      for (int k = j; k < i; ++k) a -= L[9 * i + k] * Linv[9 * k + j];
+      Linv[9 * i + j] = a / L[9 * i + i];
+    }
   return 0;
-#endif
 }
 
 // dz = H^-1 b for the leading n x n block of H (leading dimension NZ).  If
@@ -300,33 +311,6 @@ DX int spd_solve(Par par, SolveWork* w, const double* H, const double* b, int n,
   }
   return 0;
 #endif
-}
-
-// The IMU factor's weight and weighted Jacobian from Y = A9 Sigma:
-// S9 = Y A9^T (gyro-only: the rotation rows' block, identity elsewhere, which
-// decouples the dropped rows and leaves the rotation rows weighted by the
-// inverse of their marginal covariance), W9 = S9^-1 (overwrites A9),
-// T = W9 J9 (into Y) and we = W9 e (into y).  Returns 0, or 1 if S9 is not SPD.
-DX int imu_weight(Par par, SolveWork* w, bool gyro) {
-  PFOR(idx, 81) {
-    const int i = idx / 9, j = idx % 9;
-    double a = dotN<9>(w->Y + 9 * i, 1, w->A9 + 9 * j, 1);
-    if (gyro && !(i >= 3 && i < 6 && j >= 3 && j < 6)) a = (i == j) ? 1.0 : 0.0;
-    w->S9[idx] = a;
-  }
-  DSLAM_SYNC();
-  if (spd_inverse9(par, w, w->S9, w->A9)) return 1;  // W9 overwrites A9 (ends with a barrier)
-  PFOR(idx, 9 * NZ + 9) {
-    if (idx < 9 * NZ) {
-      const int i = idx / NZ, c = idx % NZ;
-      w->Y[idx] = dotN<9>(w->A9 + 9 * i, 1, w->J9 + c, NZ);
-    } else {
-      const int r = idx - 9 * NZ;
-      w->y[r] = dotN<9>(w->A9 + 9 * r, 1, w->e, 1);
-    }
-  }
-  DSLAM_SYNC();
-  return 0;
 }
 
 // One Gauss-Newton step.  raw: the 58 sums of the residual pass (ICP then RGB),
@@ -433,8 +417,8 @@ DX void prior_delta(SolveWork* w, const dslam_prior* prior, const dslam_frame_st
 // correction, H* and b* - H* d (eqs. (6), (9)), and the IMU bias random-walk
 // rows e = b0 - b1 with J = [I at x0, -I at x1] and weight 1/(sigma_rw^2 dt)
 // (RGB-D mode: zero); the visual and IMU terms are added to them.  In two
-// parts: init_system_H (the matrix; also zeroes the IMU Jacobian rows and the
-// noise map) needs nothing of the current step, init_system_b (the right-hand
+// parts: init_system_H (the matrix; also zeroes the IMU Jacobian rows) needs
+// nothing of the current step, init_system_b (the right-hand
 // side) needs the IMU residual e and the prior offset.
 struct InitWeights {
   double wbg, wba;
@@ -482,7 +466,6 @@ DX void init_system_H(Par par, SolveWork* w, const SolveParams& sp, const dslam_
     }
   }
   PFOR(i, 9 * NZ) w->J9[i] = 0.0;
-  PFOR(i, 81) w->A9[i] = 0.0;
 }
 
 DX void init_system_b(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre,
@@ -519,6 +502,7 @@ DX int solve_step(Par par, SolveWork* w, const double* raw, const SolveParams& s
                   const dslam_prior* prior, dslam_frame_state* x0, dslam_frame_state* x1, double* qIW,
                   dslam_prior* marg_out) {
   // ---- independent serial set-up, spread over the first lanes of the wavefronts
+  if (sp.mode != DSLAM_MODE_RGBD && chol_inv_lower9(pre->Sigma, w->Linv)) return DSLAM_ERR_SINGULAR;
   TASK(3) visual_front(w, raw, sp, *x0, *x1);
   if (sp.mode != DSLAM_MODE_RGBD)
     imu_common_par(par, *x0, *x1, qIW, *pre, sp.imu, w->e, &w->ic, &w->is, [&]() { prior_delta(w, prior, *x0, qIW); });
@@ -542,15 +526,15 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
       w->LH[idx] = dotN<6>(w->Lr + 6 * i, 1, w->Hm[1] + j, 6);
       w->LHi[idx] = dotN<6>(w->Li + 6 * i, 1, w->Hm[0] + j, 6);
     } else if (full) {
-      imu_block_entry(w->ic, idx - 72, w->J9, w->A9);
+      imu_block_entry(w->ic, idx - 72, w->J9);
     }
   }
   DSLAM_SYNC();
   // ---- visual 12x12 block into z indices {0..5, 15..20} (RGBD mode: only the
-  // x1 pose block); Y = A9 Sigma for the IMU covariance; gyro-only: the
-  // position and velocity rows (accelerometer) of the Jacobian and the residual
-  // are dropped (zeroed)
-  PFOR(idx, 144 + 12 + 81 + 9 * NZ + 9) {
+  // x1 pose block); the IMU whitening M9 (W = M9^T M9, see imu_whitening;
+  // gyro-only: the rotation rows alone, weighted by the inverse of their
+  // marginal covariance, whose Cholesky factor is the leading 3x3 block of L)
+  PFOR(idx, 144 + 12 + 81) {
     if (idx < 144) {
       int i = idx / 12, j = idx % 12;
       const double a = dot2N<6>(w->LH + 6 * i, w->Lr + 6 * j, w->LHi + 6 * i, w->Li + 6 * j);
@@ -562,32 +546,28 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
       for (int k = 0; k < 6; ++k) a -= w->Lr[6 * i + k] * w->gm[1][k] + w->Li[6 * i + k] * w->gm[0][k];
       if (full) w->b[i < 6 ? i : 9 + i] += a;
       else if (i >= 6) w->b[i - 6] += a;
-    } else if (idx < 237) {
-      if (full) {
-        int q = idx - 156, i = q / 9, j = q % 9;
-        w->Y[q] = dotN<9>(w->A9 + 9 * i, 1, pre->Sigma + j, 9);
-      }
-    } else if (gyro) {
-      const int q = idx - 237, r = q < 9 * NZ ? q / NZ : q - 9 * NZ;
-      if (r < 3 || r >= 6) {
-        if (q < 9 * NZ) w->J9[q] = 0.0;
-        else w->e[r] = 0.0;
-      }
+    } else if (full) {
+      const int q = idx - 156, i = q / 9, c = q % 9;
+      w->M9[q] = (gyro && (i >= 3 || c < 3 || c >= 6)) ? 0.0 : imu_whitening(w->ic, w->Linv, i, c);
     }
   }
   DSLAM_SYNC();
   if (full) {
-    // ---- IMU term: Sigma_e = A9 Sigma A9^T (+ random-walk rows), W = Sigma_e^-1,
-    // T = W9 J9 (9 x 33) into Y, we = W9 e9 into y
-    if (imu_weight(par, w, gyro)) {
-      SERIAL w->status = DSLAM_ERR_SINGULAR;
-      DSLAM_SYNC();
-      return DSLAM_ERR_SINGULAR;
+    // ---- IMU term: whitened rows M9 J9 (9 x 33, into Y) and M9 e (into y)
+    PFOR(idx, 9 * NZ + 9) {
+      if (idx < 9 * NZ) {
+        const int i = idx / NZ, c = idx % NZ;
+        w->Y[idx] = dotN<9>(w->M9 + 9 * i, 1, w->J9 + c, NZ);
+      } else {
+        const int r = idx - 9 * NZ;
+        w->y[r] = dotN<9>(w->M9 + 9 * r, 1, w->e, 1);
+      }
     }
-    // H += J9^T T, b -= J9^T we; the IMU cost e^T W e plus the random-walk rows
+    DSLAM_SYNC();
+    // H += (M9 J9)^T (M9 J9), b -= (M9 J9)^T (M9 e); the IMU cost |M9 e|^2 plus
+    // the random-walk rows
     TASK(1) {
-      double c = 0.0;
-      for (int k = 0; k < 9; ++k) c += w->e[k] * w->y[k];
+      double c = dotN<9>(w->y, 1, w->y, 1);
       const double T = pre->dt;
       const double wbg = 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T);
       const double wba = gyro ? 0.0 : 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T);
@@ -597,14 +577,14 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
     PFOR(idx, NZ * NZ + NZ) {
       if (idx < NZ * NZ) {
         int i = idx / NZ, j = idx % NZ;
-        const double a = dotN<9>(w->J9 + i, NZ, w->Y + j, NZ);
+        const double a = dotN<9>(w->Y + i, NZ, w->Y + j, NZ);
         // gyro-only: the entries no remaining term constrains are held fixed
         // (identity rows and columns, zero right-hand side)
         if (gyro && (gyro_fixed(i) || gyro_fixed(j))) w->H[idx] = (i == j) ? 1.0 : 0.0;
         else w->H[idx] += a;
       } else {
         int i = idx - NZ * NZ;
-        const double a = dotN<9>(w->J9 + i, NZ, w->y, 1);
+        const double a = dotN<9>(w->Y + i, NZ, w->y, 1);
         if (gyro && gyro_fixed(i)) w->b[i] = 0.0;
         else w->b[i] -= a;
       }

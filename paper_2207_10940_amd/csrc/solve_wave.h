@@ -33,7 +33,11 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // which lane j holds: one shared-memory store per lane publishes the whole
 // pivot row, and every lane reads it back with wide broadcast loads.  The
 // pivot row's right-hand-side entries are published by lane k.
-template <int NC, int NSTEP, int CAP>
+//
+// With FWD, rows above the pivot are left alone (forward elimination only):
+// lane i then ends with row i of [U | E] where S = E^-1 U, E unit lower
+// triangular and U upper triangular with U_ii the pivots.
+template <int NC, int NSTEP, int CAP, bool FWD = false>
 __device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* col, double* cap) {
   constexpr int NR = NC - NSTEP;  // right-hand-side columns
   bool ok = true;
@@ -57,7 +61,7 @@ __device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* 
     double inv = __builtin_amdgcn_rcp(p);
     inv = fma(inv, fma(-p, inv, 1.0), inv);
     inv = fma(inv, fma(-p, inv, 1.0), inv);
-    const double m = (lane == k) ? 0.0 : R[k] * inv;
+    const double m = (FWD ? lane <= k : lane == k) ? 0.0 : R[k] * inv;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     // the whole remaining column into registers with 16-byte broadcast reads,
     // all in flight at once, before any update uses them
@@ -89,29 +93,27 @@ __device__ __forceinline__ double own_diag(const double (&R)[NC], int lane) {
   return d;
 }
 
-// W9 = S9^-1 (9x9 row-major, shared memory).  Called by every thread of the
-// block; wave 0 computes.  Returns 0, or 1 if S9 is not SPD.
-__device__ int spd_inverse9_dev(const double* S9, double* W9) {
-  __shared__ int bad;
-  __shared__ __attribute__((aligned(16))) double col[128];
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    double R[18];
+// Linv = L^-1 for the 9x9 SPD S = L L^T (row-major, shared memory) on the
+// wavefront of the calling lanes (lane < 64 of the wave): forward elimination
+// of [S | I] leaves row i of [U | E] in lane i with S = E^-1 U and U = D E^-T,
+// D = diag(U_ii), so L = E^-1 D^1/2 and row i of L^-1 is row i of E scaled by
+// U_ii^-1/2.  col: 128 doubles of shared memory.  Returns false if S is not
+// positive definite.
+__device__ __forceinline__ bool chol_inv_lower9_wave(const double* S, double* Linv, int lane, double* col) {
+  double R[18];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      R[j] = lane < 9 ? S9[9 * lane + j] : (lane == j ? 1.0 : 0.0);
-      R[9 + j] = (lane == j) ? 1.0 : 0.0;
-    }
-    bool ok = gauss_jordan<18, 9, -1>(R, lane, col, nullptr);
-    const double d = own_diag(R, lane);
-    if (lane < 9) {
-#pragma unroll
-      for (int j = 0; j < 9; ++j) W9[9 * lane + j] = R[9 + j] / d;
-    }
-    if (lane == 0) bad = ok ? 0 : 1;
+  for (int j = 0; j < 9; ++j) {
+    R[j] = lane < 9 ? S[9 * lane + j] : (lane == j ? 1.0 : 0.0);
+    R[9 + j] = (lane == j) ? 1.0 : 0.0;
   }
-  __syncthreads();
-  return bad;
+  const bool ok = gauss_jordan<18, 9, -1, true>(R, lane, col, nullptr);
+  const double d = own_diag(R, lane);
+  if (lane < 9) {
+    const double s = 1.0 / sqrt(d);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) Linv[9 * lane + j] = (j <= lane) ? R[9 + j] * s : 0.0;
+  }
+  return ok;
 }
 
 template <int N, int CAP>
