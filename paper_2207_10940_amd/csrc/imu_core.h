@@ -329,6 +329,7 @@ DX void imu_common(const dslam_frame_state& x0, const dslam_frame_state& x1, con
 // Intermediates of imu_common_par shared between its lanes.
 struct ImuStage {
   M3 R0, R1, Q, Rb, Jrb, SdRt, Jli;
+  M3 G, K, Jl;  // noise-map inverse operands: Y^-1 = G Jl, S^T X Y^-1 = -K Jl
   V3 phib, dvt, dpt, ea, yr, yg, Sdv, QSdv;
 };
 
@@ -414,6 +415,30 @@ DX void imu_stage1(Par par, int tb, const dslam_frame_state& x0, const dslam_fra
   }
 }
 
+// The rotation factors of the noise map's inverse (see imu_whitening), from
+// the stage-0 rotations only, so any idle lane can compute them during stage
+// 1: with S = R0 R_CS and dR~ = dR Rb,
+//   Y^-1 = Rb (S dR~)^T Jl(e_a) = G Jl,
+//   S^T X Y^-1 = S^T (S dR~ [w]x Rb^T) Rb (S dR~)^T Jl = dR~ [w]x (S dR~)^T Jl = -K Jl
+// (S^T S = Rb^T Rb = I).  Serial.
+DX void imu_noise_inverse_factors(const dslam_preint& pre, const ImuParamsD& ip, ImuStage* t) {
+  const M3 Rcs = load33(ip.R_CS);
+  const V3 wt = tr(Rcs) * load3(ip.t_CS);
+  const M3 dRt = load33(pre.dR) * t->Rb;
+  const M3 SdRtT = tr((t->R0 * Rcs) * dRt);
+  t->G = t->Rb * SdRtT;
+  t->K = (-1.0) * ((dRt * hat(wt)) * SdRtT);
+}
+
+// Entry q (0 <= q < 18) of Y^-1 (q < 9) and of -S^T X Y^-1 (the operands
+// IC_YI, IC_SXY of imu_whitening), one lane each, once Jl is known.
+DX void imu_noise_inverse_entry(const ImuStage& t, int q, ImuCommon* c) {
+  const int e = q % 9, i = e / 3, j = e % 3;
+  const M3& F = q < 9 ? t.G : t.K;
+  const double r = F(i, 0) * t.Jl(0, j) + F(i, 1) * t.Jl(1, j) + F(i, 2) * t.Jl(2, j);
+  c->mats[q < 9 ? IC_YI : IC_SXY](i, j) = r;
+}
+
 // tb2: the wavefront of the second half of the Jacobian operands (tb + 1 may
 // be given to run both halves on one wavefront).
 template <class Side>
@@ -447,11 +472,6 @@ DX void imu_stage2(Par par, int tb, int tb2, const dslam_preint& pre, const ImuP
     m[IC_KROT] = SdRthwt * t->Jrb;
     m[IC_HAT_SDV] = hat(t->Sdv);
     m[IC_HAT_QSDV] = (-1.0) * hat(t->QSdv);
-    // inverse of the noise map's blocks (imu_whitening): with P = (S dR~)^T Jl(e_a),
-    // Y^-1 = Rb P and S^T X Y^-1 = S^T (S dR~ [w]x) P (Jl(a) = Jr(-a))
-    M3 P = tr(t->SdRt) * Jr((-1.0) * t->ea);
-    m[IC_YI] = t->Rb * P;
-    m[IC_SXY] = (-1.0) * (tr(t->R0 * Rcs) * (SdRthwt * P));
   }
   TASK(tb + 2) {
     m[IC_I] = eye3();
@@ -467,7 +487,10 @@ DX void imu_stage2(Par par, int tb, int tb2, const dslam_preint& pre, const ImuP
       }
     c->T = pre.dt;
   }
-  TASK(tb + 3) side();
+  TASK(tb + 3) {
+    t->Jl = Jr((-1.0) * t->ea);  // Jl(a) = Jr(-a)
+    side();
+  }
 }
 
 template <class Side>
@@ -477,8 +500,11 @@ DX void imu_common_par(Par par, const dslam_frame_state& x0, const dslam_frame_s
   imu_stage0(par, 0, x0, x1, qIW, pre, t);
   DSLAM_SYNC();
   imu_stage1(par, 0, x0, x1, pre, ip, e, t);
+  TASK(1) imu_noise_inverse_factors(pre, ip, t);
   DSLAM_SYNC();
   imu_stage2(par, 0, 1, pre, ip, c, t, side);
+  DSLAM_SYNC();
+  PFOR(q, 18) imu_noise_inverse_entry(*t, q, c);
   DSLAM_SYNC();
 }
 
@@ -546,7 +572,7 @@ DX void imu_block_entry(const ImuCommon& c, int q, double* J9) {
 // rotation.  With Sigma = L L^T (Cholesky, once per step) and M = L^-1 A^-1,
 // W = M^T M: the whitened rows M J and M e replace the 9x9 inverse.
 // Entry (i, c) of M from Linv = L^-1 (lower triangular, row-major) and the
-// operands IC_YI, IC_ST, IC_QST, IC_SXY.
+// operands IC_YI, IC_ST, IC_QST, IC_SXY (the sign of the last included).
 DX double imu_whitening(const ImuCommon& ic, const double* Linv, int i, int c) {
   const M3* m = ic.mats;
   const int j = c % 3;

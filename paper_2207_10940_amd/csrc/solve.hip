@@ -168,8 +168,9 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   //   stage 0: reduction (waves 0-3); IMU rotations and bias-corrected
   //            preintegration (waves 4-6); lift sources (wave 7)
   //   stage 1: column sums (wave 0); IMU residual (wave 7); prior offset
-  //            (waves 1, 2); system matrix start (waves 0, 4); lift (waves 5, 6)
-  //   stage 2: unpacked sums (wave 0); IMU Jacobian operands (waves 3-6);
+  //            (waves 1, 2); system matrix start (waves 0, 4); lift (waves 5, 6);
+  //            rotation factors of the IMU noise map's inverse (wave 5)
+  //   stage 2: unpacked sums (wave 0); IMU Jacobian operands (waves 3-7);
   //            right-hand side start (waves 1, 2)
   static_assert(SOLVE_THREADS == 512 && REDUCE_THREADS == 256, "stage plan assumes 8 waves");
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
@@ -185,6 +186,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   }
   if (wave == 0 || wave == 4) init_system_H(Par{lane + (wave == 4 ? 64 : 0), 128}, &w, sp, &pre, &prior);
   if (wave == 5 || wave == 6) lift_fill(lane + (wave == 6 ? 64 : 0), 128, &w);
+  if (full) TASK(5) imu_noise_inverse_factors(pre, sp.imu, &w.is);
   DSLAM_SYNC();
   if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
   if (wave == 0) unpack_sums(lane, &w, raw);

@@ -519,14 +519,17 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
   const bool gyro = sp.mode == DSLAM_MODE_GYRO;
   const int n = full ? NZ : 6;
   const bool marg = full && sp.marginalise && marg_out != nullptr;
-  // ---- LH = L Hm (12x6) per term; IMU Jacobian blocks, one entry per lane
-  PFOR(idx, 72 + IMU_BLOCK_ENTRIES) {
+  // ---- LH = L Hm (12x6) per term; IMU Jacobian blocks and the noise map's
+  // inverse operands, one entry per lane
+  PFOR(idx, 72 + IMU_BLOCK_ENTRIES + 18) {
     if (idx < 72) {
       int i = idx / 6, j = idx % 6;
       w->LH[idx] = dotN<6>(w->Lr + 6 * i, 1, w->Hm[1] + j, 6);
       w->LHi[idx] = dotN<6>(w->Li + 6 * i, 1, w->Hm[0] + j, 6);
-    } else if (full) {
+    } else if (full && idx < 72 + IMU_BLOCK_ENTRIES) {
       imu_block_entry(w->ic, idx - 72, w->J9);
+    } else if (full) {
+      imu_noise_inverse_entry(w->is, idx - 72 - IMU_BLOCK_ENTRIES, &w->ic);
     }
   }
   DSLAM_SYNC();
