@@ -330,6 +330,7 @@ DX void imu_common(const dslam_frame_state& x0, const dslam_frame_state& x1, con
 struct ImuStage {
   M3 R0, R1, Q, Rb, Jrb, SdRt, Jli;
   M3 G, K, Jl;  // noise-map inverse operands: Y^-1 = G Jl, S^T X Y^-1 = -K Jl
+  M3 SdRtJrb;   // S dR~ Jr(phi_b)
   V3 phib, dvt, dpt, ea, yr, yg, Sdv, QSdv;
 };
 
@@ -344,8 +345,30 @@ DX int task_lane(Par par, int t) { return t * 64 < par.nl ? t * 64 : 0; }
 // operands.  Same arithmetic as imu_common.  The caller separates the stages
 // by barriers (imu_common_par below, or a caller that interleaves other work).
 DX void imu_stage0(Par par, int tb, const dslam_frame_state& x0, const dslam_frame_state& x1, const double* qIW,
-                   const dslam_preint& pre, ImuStage* t) {
-  TASK(tb) t->R0 = q2R(x0.q);
+                   const dslam_preint& pre, ImuCommon* c, ImuStage* t) {
+  TASK(tb) {
+    // the operands that are copies of the preintegration's bias Jacobians
+    // (read before any store, see state_boxplus)
+    double J[54];
+    for (int i = 0; i < 54; ++i) J[i] = pre.J[i];
+    const double T = pre.dt;
+    double q0[4];
+    for (int i = 0; i < 4; ++i) q0[i] = x0.q[i];
+    t->R0 = q2R(q0);
+    M3* m = c->mats;
+    m[IC_I] = eye3();
+    m[IC_NEG_I] = (-1.0) * eye3();
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        m[IC_JRG](i, j) = J[6 * i + j];
+        m[IC_JRA](i, j) = J[6 * i + 3 + j];
+        m[IC_JVG](i, j) = J[6 * (3 + i) + j];
+        m[IC_JVA](i, j) = J[6 * (3 + i) + 3 + j];
+        m[IC_JPG](i, j) = J[6 * (6 + i) + j];
+        m[IC_JPA](i, j) = J[6 * (6 + i) + 3 + j];
+      }
+    c->T = T;
+  }
   TASK(tb + 1) {
     t->R1 = q2R(x1.q);
     t->Q = q2R(qIW);
@@ -399,12 +422,17 @@ DX void imu_stage1(Par par, int tb, const dslam_frame_state& x0, const dslam_fra
     V3 ea = Log(Rh1 * tr(t->R1));
     V3 er = rh - load3(x1.r);
     V3 ev = vh - load3(x1.v);
+    double eb[6];  // read before the first store (see state_boxplus)
+    for (int i = 0; i < 3; ++i) {
+      eb[i] = x0.bg[i] - x1.bg[i];
+      eb[3 + i] = x0.ba[i] - x1.ba[i];
+    }
     for (int i = 0; i < 3; ++i) {
       e[i] = er[i];
       e[3 + i] = ea[i];
       e[6 + i] = ev[i];
-      e[9 + i] = x0.bg[i] - x1.bg[i];
-      e[12 + i] = x0.ba[i] - x1.ba[i];
+      e[9 + i] = eb[i];
+      e[12 + i] = eb[3 + i];
     }
     t->SdRt = SdRt;
     t->ea = ea;
@@ -415,19 +443,52 @@ DX void imu_stage1(Par par, int tb, const dslam_frame_state& x0, const dslam_fra
   }
 }
 
-// The rotation factors of the noise map's inverse (see imu_whitening), from
-// the stage-0 rotations only, so any idle lane can compute them during stage
-// 1: with S = R0 R_CS and dR~ = dR Rb,
+// Jacobian operands that need only the stage-0 rotations, so idle lanes can
+// compute them during stage 1, in two serial tasks.  With S = R0 R_CS and
+// dR~ = dR Rb (the same operations as the stage-1 residual task):
+// imu_rotation_operands: S, R_IW S, T R_IW^T, -R_IW and the transposes the
+// noise map's inverse uses;
+// imu_krot_operands: KROT = S dR~ [w]x Jr(phi_b) and S dR~ Jr(phi_b);
+// imu_noise_inverse_factors: the factors of the noise map's inverse (see
+// imu_whitening)
 //   Y^-1 = Rb (S dR~)^T Jl(e_a) = G Jl,
 //   S^T X Y^-1 = S^T (S dR~ [w]x Rb^T) Rb (S dR~)^T Jl = dR~ [w]x (S dR~)^T Jl = -K Jl
-// (S^T S = Rb^T Rb = I).  Serial.
+// (S^T S = Rb^T Rb = I).
+DX void imu_rotation_operands(const dslam_preint& pre, const ImuParamsD& ip, ImuCommon* c, const ImuStage* t) {
+  M3* m = c->mats;
+  const M3 Rcs = load33(ip.R_CS);
+  const M3 R0 = t->R0, Q = t->Q;
+  const double T = pre.dt;
+  const M3 S = R0 * Rcs;
+  const M3 QS = Q * S;
+  m[IC_S] = S;
+  m[IC_QS] = QS;
+  m[IC_QT] = T * tr(Q);
+  m[IC_Q] = (-1.0) * Q;
+  m[IC_ST] = tr(S);
+  m[IC_QST] = tr(QS);
+}
+
+DX void imu_krot_operands(const dslam_preint& pre, const ImuParamsD& ip, ImuCommon* c, ImuStage* t) {
+  const M3 Rcs = load33(ip.R_CS);
+  const V3 wt = tr(Rcs) * load3(ip.t_CS);
+  const M3 Rb = t->Rb, R0 = t->R0, Jrb = t->Jrb, dR = load33(pre.dR);
+  const M3 SdRt = (R0 * Rcs) * (dR * Rb);
+  const M3 KROT = (SdRt * hat(wt)) * Jrb, SJ = SdRt * Jrb;
+  c->mats[IC_KROT] = KROT;
+  t->SdRtJrb = SJ;
+}
+
 DX void imu_noise_inverse_factors(const dslam_preint& pre, const ImuParamsD& ip, ImuStage* t) {
   const M3 Rcs = load33(ip.R_CS);
   const V3 wt = tr(Rcs) * load3(ip.t_CS);
-  const M3 dRt = load33(pre.dR) * t->Rb;
-  const M3 SdRtT = tr((t->R0 * Rcs) * dRt);
-  t->G = t->Rb * SdRtT;
-  t->K = (-1.0) * ((dRt * hat(wt)) * SdRtT);
+  const M3 Rb = t->Rb, R0 = t->R0, dR = load33(pre.dR);
+  const M3 dRt = dR * Rb;
+  const M3 SdRtT = tr((R0 * Rcs) * dRt);
+  const M3 G = Rb * SdRtT;
+  const M3 K = (-1.0) * ((dRt * hat(wt)) * SdRtT);
+  t->G = G;
+  t->K = K;
 }
 
 // Entry q (0 <= q < 18) of Y^-1 (q < 9) and of -S^T X Y^-1 (the operands
@@ -439,56 +500,36 @@ DX void imu_noise_inverse_entry(const ImuStage& t, int q, ImuCommon* c) {
   c->mats[q < 9 ? IC_YI : IC_SXY](i, j) = r;
 }
 
-// tb2: the wavefront of the second half of the Jacobian operands (tb + 1 may
-// be given to run both halves on one wavefront).
+// Stage 2: the operands that need the stage-1 residual, on the first lanes of
+// wavefronts tb, tb + 1 and tj (tj also runs `side`).
 template <class Side>
-DX void imu_stage2(Par par, int tb, int tb2, const dslam_preint& pre, const ImuParamsD& ip, ImuCommon* c,
+DX void imu_stage2(Par par, int tb, int tj, const dslam_preint& pre, const ImuParamsD& ip, ImuCommon* c,
                    ImuStage* t, Side side) {
+  (void)pre;
+  (void)ip;
   M3* m = c->mats;
+  // (each task reads its operands before its first store, see state_boxplus)
   TASK(tb) {
-    M3 Jli = JlInv(t->ea);
+    const V3 ea = t->ea;
+    const M3 SdRtJrb = t->SdRtJrb;
+    const M3 Jli = JlInv(ea);
+    const M3 KAL = Jli * SdRtJrb;
     m[IC_JLI] = Jli;
-    m[IC_KAL] = Jli * t->SdRt * t->Jrb;
+    m[IC_KAL] = KAL;
     m[IC_JRI] = (-1.0) * tr(Jli);
   }
   TASK(tb + 1) {
-    M3 Rcs = load33(ip.R_CS);
-    M3 Qt = tr(t->Q);
-    M3 S = t->R0 * Rcs;
-    M3 QS = t->Q * S;
-    m[IC_HAT_R0YR] = (-1.0) * hat(t->R0 * t->yr);
-    m[IC_QT] = pre.dt * Qt;
-    m[IC_S] = S;
-    m[IC_HAT_YG] = Qt * hat(t->yg);
-    m[IC_Q] = (-1.0) * t->Q;
-    m[IC_QS] = QS;
-    m[IC_ST] = tr(S);
-    m[IC_QST] = tr(QS);
+    const M3 R0 = t->R0, Q = t->Q;
+    const V3 yr = t->yr, yg = t->yg, Sdv = t->Sdv, QSdv = t->QSdv;
+    const M3 A = (-1.0) * hat(R0 * yr), B = tr(Q) * hat(yg);
+    m[IC_HAT_R0YR] = A;
+    m[IC_HAT_YG] = B;
+    m[IC_HAT_SDV] = hat(Sdv);
+    m[IC_HAT_QSDV] = (-1.0) * hat(QSdv);
   }
-  TASK(tb2) {
-    M3 Rcs = load33(ip.R_CS);
-    V3 wt = tr(Rcs) * load3(ip.t_CS);
-    M3 SdRthwt = t->SdRt * hat(wt);
-    m[IC_KROT] = SdRthwt * t->Jrb;
-    m[IC_HAT_SDV] = hat(t->Sdv);
-    m[IC_HAT_QSDV] = (-1.0) * hat(t->QSdv);
-  }
-  TASK(tb + 2) {
-    m[IC_I] = eye3();
-    m[IC_NEG_I] = (-1.0) * eye3();
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        m[IC_JRG](i, j) = pre.J[6 * i + j];
-        m[IC_JRA](i, j) = pre.J[6 * i + 3 + j];
-        m[IC_JVG](i, j) = pre.J[6 * (3 + i) + j];
-        m[IC_JVA](i, j) = pre.J[6 * (3 + i) + 3 + j];
-        m[IC_JPG](i, j) = pre.J[6 * (6 + i) + j];
-        m[IC_JPA](i, j) = pre.J[6 * (6 + i) + 3 + j];
-      }
-    c->T = pre.dt;
-  }
-  TASK(tb + 3) {
-    t->Jl = Jr((-1.0) * t->ea);  // Jl(a) = Jr(-a)
+  TASK(tj) {
+    const V3 ea = t->ea;
+    t->Jl = Jr((-1.0) * ea);  // Jl(a) = Jr(-a)
     side();
   }
 }
@@ -497,12 +538,14 @@ template <class Side>
 DX void imu_common_par(Par par, const dslam_frame_state& x0, const dslam_frame_state& x1, const double* qIW,
                        const dslam_preint& pre, const ImuParamsD& ip, double* e, ImuCommon* c, ImuStage* t,
                        Side side) {
-  imu_stage0(par, 0, x0, x1, qIW, pre, t);
+  imu_stage0(par, 0, x0, x1, qIW, pre, c, t);
   DSLAM_SYNC();
   imu_stage1(par, 0, x0, x1, pre, ip, e, t);
-  TASK(1) imu_noise_inverse_factors(pre, ip, t);
+  TASK(1) imu_rotation_operands(pre, ip, c, t);
+  TASK(2) imu_krot_operands(pre, ip, c, t);
+  TASK(3) imu_noise_inverse_factors(pre, ip, t);
   DSLAM_SYNC();
-  imu_stage2(par, 0, 1, pre, ip, c, t, side);
+  imu_stage2(par, 0, 2, pre, ip, c, t, side);
   DSLAM_SYNC();
   PFOR(q, 18) imu_noise_inverse_entry(*t, q, c);
   DSLAM_SYNC();

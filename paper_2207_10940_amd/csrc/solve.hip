@@ -165,18 +165,23 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   // states only, are computed on the others (three stages, one barrier
   // sequence for both).  Wave w runs on SIMD w % 4: each stage puts its
   // longest serial task on a SIMD whose other wave has little to do.
-  //   stage 0: reduction (waves 0-3); IMU rotations and bias-corrected
-  //            preintegration (waves 4-6); lift sources (wave 7)
+  //   stage 0: reduction (waves 0-3); IMU rotations, operand copies and
+  //            bias-corrected preintegration (waves 4-6); the visual lift
+  //            (wave 7: sources on lanes 0-8, then all entries)
   //   stage 1: column sums (wave 0); IMU residual (wave 7); prior offset
-  //            (waves 1, 2); system matrix start (waves 0, 4); lift (waves 5, 6);
-  //            rotation factors of the IMU noise map's inverse (wave 5)
-  //   stage 2: unpacked sums (wave 0); IMU Jacobian operands (waves 3-7);
-  //            right-hand side start (waves 1, 2)
+  //            (waves 1, 2); system matrix start (waves 0, 4); IMU operands of
+  //            the stage-0 rotations (waves 2, 5, 6)
+  //   stage 2: unpacked sums (wave 0); IMU operands of the residual (waves 4,
+  //            5, 7); right-hand side start (waves 1, 2)
   static_assert(SOLVE_THREADS == 512 && REDUCE_THREADS == 256, "stage plan assumes 8 waves");
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   if (wave < 4) reduce_rows(partials, a.nblocks, red);
-  if (full) imu_stage0(par, 4, x0, x1, qIW, pre, &w.is);
-  if (wave == 7) lift_sources(lane, &w, sp, x0, x1);
+  if (full) imu_stage0(par, 4, x0, x1, qIW, pre, &w.ic, &w.is);
+  if (wave == 7) {
+    lift_sources(lane, &w, sp, x0, x1);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    lift_fill(lane, 64, &w);
+  }
   DSLAM_SYNC();
   reduce_cols(red, raw);
   if (full) {
@@ -185,12 +190,15 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
     TASK(2) prior_delta_gravity(&w, &prior, qIW);
   }
   if (wave == 0 || wave == 4) init_system_H(Par{lane + (wave == 4 ? 64 : 0), 128}, &w, sp, &pre, &prior);
-  if (wave == 5 || wave == 6) lift_fill(lane + (wave == 6 ? 64 : 0), 128, &w);
-  if (full) TASK(5) imu_noise_inverse_factors(pre, sp.imu, &w.is);
+  if (full) {
+    TASK(2) imu_rotation_operands(pre, sp.imu, &w.ic, &w.is);
+    TASK(5) imu_krot_operands(pre, sp.imu, &w.ic, &w.is);
+    TASK(6) imu_noise_inverse_factors(pre, sp.imu, &w.is);
+  }
   DSLAM_SYNC();
   if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
   if (wave == 0) unpack_sums(lane, &w, raw);
-  if (full) imu_stage2(par, 4, 3, pre, sp.imu, &w.ic, &w.is, []() {});
+  if (full) imu_stage2(par, 4, 7, pre, sp.imu, &w.ic, &w.is, []() {});
   if (wave == 1 || wave == 2) init_system_b(Par{lane + (wave == 2 ? 64 : 0), 128}, &w, sp, &pre, &prior);
   DSLAM_SYNC();
   int st = solve_back(par, &w, sp, &pre, &prior, &x0, &x1, qIW, &marg);
@@ -202,9 +210,12 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
     if (st != DSLAM_OK) {
       sd->status = st;
     } else {
-      sd->x0 = x0;
-      sd->x1 = x1;
-      for (int i = 0; i < 4; ++i) sd->qIW[i] = qIW[i];
+      const dslam_frame_state a0 = x0, a1 = x1;  // read before the first store
+      double q[4];
+      for (int i = 0; i < 4; ++i) q[i] = qIW[i];
+      sd->x0 = a0;
+      sd->x1 = a1;
+      for (int i = 0; i < 4; ++i) sd->qIW[i] = q[i];
     }
   }
   TASK(2) {

@@ -170,17 +170,25 @@ DX float next_transform_entry(const dslam_frame_state& x0, const dslam_frame_sta
   return (float)v;
 }
 
+// The serial tasks below read all their shared-memory operands into registers
+// before their first store: the compiler cannot tell that the stores do not
+// alias the later reads and would otherwise wait a round trip per statement.
 DX void state_boxplus(dslam_frame_state* x, const double* d) {
+  dslam_frame_state y = *x;
+  double dd[15];
+  for (int i = 0; i < 15; ++i) dd[i] = d[i];
   for (int i = 0; i < 3; ++i) {
-    x->r[i] += d[i];
-    x->v[i] += d[6 + i];
-    x->bg[i] += d[9 + i];
-    x->ba[i] += d[12 + i];
+    y.r[i] += dd[i];
+    y.v[i] += dd[6 + i];
+    y.bg[i] += dd[9 + i];
+    y.ba[i] += dd[12 + i];
   }
-  qboxplus(x->q, v3(d[3], d[4], d[5]));
+  qboxplus(y.q, v3(dd[3], dd[4], dd[5]));
+  *x = y;
 }
 
-DX void state_boxminus(const dslam_frame_state& x, const dslam_frame_state& y, double* d) {
+DX void state_boxminus(const dslam_frame_state& xs, const dslam_frame_state& ys, double* d) {
+  const dslam_frame_state x = xs, y = ys;  // read before the first store
   V3 a = qboxminus(x.q, y.q);
   for (int i = 0; i < 3; ++i) {
     d[i] = x.r[i] - y.r[i];
