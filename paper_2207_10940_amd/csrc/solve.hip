@@ -9,39 +9,58 @@
 namespace dslam {
 
 // Fixed-order float64 sum of the block partials ([nblocks][64] floats, 58
-// used), in two steps separated by a barrier of the caller: reduce_rows has
-// thread t < REDUCE_THREADS sum the float4 column group t % 16 over blocks
-// t/16, t/16 + 16, ... into red (16 x 64 doubles); reduce_cols then adds the
-// 16 row sums of each column in row order.  Same order whatever the launch.
+// used): thread t < REDUCE_THREADS sums the float4 column group t % 16 over
+// blocks t/16, t/16 + 16, ... (RowSums, in that order; the caller may split
+// the blocks into parts run between other work, the running sums staying in
+// registers), stores the row sums into red (16 x 64 doubles), and after a
+// barrier reduce_cols adds the 16 row sums of each column in row order.  Same
+// order whatever the launch.
 enum { REDUCE_THREADS = 256 };
 
-__device__ __forceinline__ void reduce_rows(const float* partials, int nblocks, double* red) {
-  const int g = threadIdx.x & 15, r = threadIdx.x >> 4;
+struct RowSums {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+};
+
+// Blocks of part `part` (0 or 1 of `parts`): this thread's u-range
+// [n part / parts, n (part + 1) / parts) of its n blocks r + 16 u.
+__device__ __forceinline__ void reduce_rows_part(const float* partials, int nblocks, int part, int parts,
+                                                 RowSums& rs) {
+  const int g = threadIdx.x & 15, r = threadIdx.x >> 4;
   const float* base = partials + 4 * g;
   const int n = nblocks > r ? (nblocks - r + 15) / 16 : 0;  // this thread sums blocks r + 16 u, u < n
-  constexpr int CHUNK = 40;  // loads in flight at once (one round trip for up to 640 blocks)
-  for (int u0 = 0; u0 < n; u0 += CHUNK) {
+  const int lo = n * part / parts, hi = n * (part + 1) / parts;
+  constexpr int CHUNK = 20;  // loads in flight at once (one round trip for up to 320 blocks per part)
+  for (int u0 = lo; u0 < hi; u0 += CHUNK) {
     float4 v[CHUNK];
 #pragma unroll
     for (int u = 0; u < CHUNK; ++u) {
-      const int b = r + 16 * min(u0 + u, n - 1);  // clamped: always a valid block
+      const int b = r + 16 * min(u0 + u, hi - 1);  // clamped: always a valid block
       v[u] = *reinterpret_cast<const float4*>(base + (size_t)b * PARTIAL_STRIDE);
     }
 #pragma unroll
     for (int u = 0; u < CHUNK; ++u) {
-      if (u0 + u < n) {
-        s0 += (double)v[u].x;
-        s1 += (double)v[u].y;
-        s2 += (double)v[u].z;
-        s3 += (double)v[u].w;
+      if (u0 + u < hi) {
+        rs.s0 += (double)v[u].x;
+        rs.s1 += (double)v[u].y;
+        rs.s2 += (double)v[u].z;
+        rs.s3 += (double)v[u].w;
       }
     }
   }
-  red[r * 64 + 4 * g + 0] = s0;
-  red[r * 64 + 4 * g + 1] = s1;
-  red[r * 64 + 4 * g + 2] = s2;
-  red[r * 64 + 4 * g + 3] = s3;
+}
+
+__device__ __forceinline__ void reduce_rows_store(const RowSums& rs, double* red) {
+  const int g = threadIdx.x & 15, r = threadIdx.x >> 4;
+  red[r * 64 + 4 * g + 0] = rs.s0;
+  red[r * 64 + 4 * g + 1] = rs.s1;
+  red[r * 64 + 4 * g + 2] = rs.s2;
+  red[r * 64 + 4 * g + 3] = rs.s3;
+}
+
+__device__ __forceinline__ void reduce_rows(const float* partials, int nblocks, double* red) {
+  RowSums rs;
+  reduce_rows_part(partials, nblocks, 0, 1, rs);
+  reduce_rows_store(rs, red);
 }
 
 __device__ __forceinline__ void reduce_cols(const double* red, double* out) {
@@ -160,44 +179,57 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   SolveParams sp = a.sp;
   sp.marginalise = a.last;
   const bool full = sp.mode != DSLAM_MODE_RGBD;
-  // The first four waves reduce the block partials while the operands of the
-  // IMU factor, the prior offset and the visual lift, which depend on the
-  // states only, are computed on the others (three stages, one barrier
+  // The first four waves reduce the block partials (their loads split over
+  // the first two stages, the running sums in registers) while the operands
+  // of the IMU factor, the prior offset and the visual lift, which depend on
+  // the states only, are computed on the others (three stages, one barrier
   // sequence for both).  Wave w runs on SIMD w % 4: each stage puts its
   // longest serial task on a SIMD whose other wave has little to do.
-  //   stage 0: reduction (waves 0-3); IMU rotations, operand copies and
-  //            bias-corrected preintegration (waves 4-6); the visual lift
-  //            (wave 7: sources on lanes 0-8, then all entries)
-  //   stage 1: column sums (wave 0); IMU residual (wave 7); prior offset
-  //            (waves 1, 2); system matrix start (waves 0, 4); IMU operands of
-  //            the stage-0 rotations (waves 2, 5, 6)
-  //   stage 2: unpacked sums (wave 0); IMU operands of the residual (waves 4,
-  //            5, 7); right-hand side start (waves 1, 2)
+  //   stage 0: first half of the reduction (waves 0-3); IMU rotations, operand
+  //            copies and bias-corrected preintegration (waves 4-6); system
+  //            matrix start (waves 4, 5); the visual lift (wave 7: sources on
+  //            lanes 0-8, then all entries)
+  //   stage 1: second half of the reduction (waves 0-3); IMU residual (wave
+  //            7); prior offset and the IMU operands of the stage-0 rotations
+  //            (waves 4-6)
+  //   stage 2: column sums, then the unpacked sums (wave 0); IMU operands of
+  //            the residual (waves 4, 5, 7); right-hand side start (waves 1, 2)
   static_assert(SOLVE_THREADS == 512 && REDUCE_THREADS == 256, "stage plan assumes 8 waves");
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
-  if (wave < 4) reduce_rows(partials, a.nblocks, red);
+  RowSums rs;
+  if (wave < 4) reduce_rows_part(partials, a.nblocks, 0, 2, rs);
   if (full) imu_stage0(par, 4, x0, x1, qIW, pre, &w.ic, &w.is);
+  if (wave == 4 || wave == 5) init_system_H(Par{lane + (wave == 5 ? 64 : 0), 128}, &w, sp, &pre, &prior);
   if (wave == 7) {
     lift_sources(lane, &w, sp, x0, x1);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     lift_fill(lane, 64, &w);
   }
   DSLAM_SYNC();
-  reduce_cols(red, raw);
+  if (wave < 4) {
+    reduce_rows_part(partials, a.nblocks, 1, 2, rs);
+    reduce_rows_store(rs, red);
+  }
   if (full) {
     imu_stage1(par, 7, x0, x1, pre, sp.imu, w.e, &w.is);
-    TASK(1) prior_delta_state(&w, &prior, x0);
-    TASK(2) prior_delta_gravity(&w, &prior, qIW);
-  }
-  if (wave == 0 || wave == 4) init_system_H(Par{lane + (wave == 4 ? 64 : 0), 128}, &w, sp, &pre, &prior);
-  if (full) {
-    TASK(2) imu_rotation_operands(pre, sp.imu, &w.ic, &w.is);
-    TASK(5) imu_krot_operands(pre, sp.imu, &w.ic, &w.is);
-    TASK(6) imu_noise_inverse_factors(pre, sp.imu, &w.is);
+    TASK(5) {
+      prior_delta_state(&w, &prior, x0);
+      imu_rotation_operands(pre, sp.imu, &w.ic, &w.is);
+    }
+    TASK(6) {
+      prior_delta_gravity(&w, &prior, qIW);
+      imu_noise_inverse_factors(pre, sp.imu, &w.is);
+    }
+    TASK(4) imu_krot_operands(pre, sp.imu, &w.ic, &w.is);
   }
   DSLAM_SYNC();
-  if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
-  if (wave == 0) unpack_sums(lane, &w, raw);
+  if (wave == 0) {
+    // the column sums and their unpacking: lane t < 58 writes and then reads
+    // raw[t] only, so no barrier is needed between them
+    reduce_cols(red, raw);
+    if (threadIdx.x < 58) sd->sys[threadIdx.x] = raw[threadIdx.x];
+    unpack_sums(lane, &w, raw);
+  }
   if (full) imu_stage2(par, 4, 7, pre, sp.imu, &w.ic, &w.is, []() {});
   if (wave == 1 || wave == 2) init_system_b(Par{lane + (wave == 2 ? 64 : 0), 128}, &w, sp, &pre, &prior);
   DSLAM_SYNC();
