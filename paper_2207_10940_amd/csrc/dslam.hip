@@ -154,7 +154,7 @@ SolveParams solve_params(dslam_session* s) {
   }
   sp.imu = imu_params_d(s->ip);
   sp.mode = s->tp.mode;
-  sp.marginalise = 0;
+  sp.marginalise = 1;  // the device solve marginalises on the frame's last step only
   return sp;
 }
 

@@ -224,21 +224,29 @@ DX int preintegrate(Par par, const dslam_imu_sample* s, int n, double t0, double
     }
     DSLAM_SYNC();
   }
-  SERIAL {
-    for (int i = 0; i < 9; ++i) out->dR[i] = w->dR[i];
-    for (int i = 0; i < 3; ++i) {
-      out->dv[i] = w->dv[i];
-      out->dp[i] = w->dp[i];
-      out->bg[i] = bg[i];
-      out->ba[i] = ba[i];
-    }
-    out->dt = t1 - t0;
-    for (int i = 0; i < 9; ++i)
-      for (int j = i + 1; j < 9; ++j) {
-        double a = 0.5 * (out->Sigma[9 * i + j] + out->Sigma[9 * j + i]);
-        out->Sigma[9 * i + j] = a;
-        out->Sigma[9 * j + i] = a;
+  // the measurement and the symmetrised covariance, entry by entry
+  PFOR(q, 9 + 12 + 1 + 36) {
+    if (q < 9) {
+      out->dR[q] = w->dR[q];
+    } else if (q < 21) {
+      const int i = (q - 9) % 3, k = (q - 9) / 3;
+      if (k == 0) out->dv[i] = w->dv[i];
+      else if (k == 1) out->dp[i] = w->dp[i];
+      else if (k == 2) out->bg[i] = bg[i];
+      else out->ba[i] = ba[i];
+    } else if (q == 21) {
+      out->dt = t1 - t0;
+    } else {
+      int i = 0, r = q - 22;  // pair r of the upper triangle (i < j), row by row
+      while (r >= 8 - i) {
+        r -= 8 - i;
+        ++i;
       }
+      const int j = i + 1 + r;
+      const double a = 0.5 * (out->Sigma[9 * i + j] + out->Sigma[9 * j + i]);
+      out->Sigma[9 * i + j] = a;
+      out->Sigma[9 * j + i] = a;
+    }
   }
   DSLAM_SYNC();
   return DSLAM_OK;

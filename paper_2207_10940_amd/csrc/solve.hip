@@ -84,7 +84,7 @@ __global__ __launch_bounds__(REDUCE_THREADS) void reduce_kernel(const float* par
 __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& batch, const FrameArgs& fa) {
   __shared__ PreintWork pw;
   __shared__ dslam_preint pre;
-  __shared__ dslam_frame_state x0;
+  __shared__ dslam_frame_state x0, x1;
   __shared__ double qIW[4];
   Par par{(int)threadIdx.x, SOLVE_THREADS};
   SERIAL {
@@ -110,16 +110,28 @@ __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& 
     if (threadIdx.x < 81) sd->Linv[threadIdx.x] = linv[threadIdx.x];
     if (lbad) st = DSLAM_ERR_SINGULAR;
   }
+  // the prediction of x1 on one lane while the others publish the measurement
+  if (fa.mode != DSLAM_MODE_RGBD && st == DSLAM_OK) {  // uniform
+    const double* src = reinterpret_cast<const double*>(&pre);
+    double* dst = reinterpret_cast<double*>(&sd->pre);
+    for (int i = threadIdx.x; i < (int)(sizeof(dslam_preint) / 8); i += SOLVE_THREADS) dst[i] = src[i];
+  }
   SERIAL {
     if (st != DSLAM_OK) sd->status = st;
-    dslam_frame_state x1 = x0;
+    dslam_frame_state p = x0;
     if (fa.mode != DSLAM_MODE_RGBD && st == DSLAM_OK) {
-      sd->pre = pre;
-      if (fa.mode == DSLAM_MODE_GYRO) imu_predict_gyro(x0, pre, fa.imu, &x1);
-      else imu_predict(x0, qIW, pre, fa.imu, &x1);
+      if (fa.mode == DSLAM_MODE_GYRO) imu_predict_gyro(x0, pre, fa.imu, &p);
+      else imu_predict(x0, qIW, pre, fa.imu, &p);
     }
-    sd->x1 = x1;
-    next_transforms(x0, x1, fa.R_WM, fa.t_WM, sd->xf);
+    x1 = p;
+  }
+  DSLAM_SYNC();
+  // the first pass's transforms on 24 lanes, the state and the record's reset
+  // by the first lane of wave 1
+  if (threadIdx.x < 24) sd->xf[threadIdx.x] = next_transform_entry(x0, x1, fa.R_WM, fa.t_WM, (int)threadIdx.x);
+  TASK(1) {
+    const dslam_frame_state p = x1;
+    sd->x1 = p;
     for (int l = 0; l < DSLAM_MAX_LEVELS; ++l) {
       sd->result.n_icp[l] = 0;
       sd->result.n_rgb[l] = 0;
@@ -139,7 +151,21 @@ __global__ __launch_bounds__(SOLVE_THREADS) void frame_init_batch_kernel(const S
 
 // One Gauss-Newton step of one session: reduce the block partials, solve,
 // update the states (and on the frame's last step marginalise and publish).
-__device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials, const SolveArgs& a) {
+// Word k (0..35) of the state triple (x0: 16 doubles, x1: 16, q_IW: 4).
+static_assert(sizeof(dslam_frame_state) == 16 * sizeof(double), "state of 16 doubles");
+template <class S, class D>
+__device__ __forceinline__ D& state_word(S& x0, S& x1, D* q, int k) {
+  D* a = reinterpret_cast<D*>(&x0);
+  D* b = reinterpret_cast<D*>(&x1);
+  return k < 16 ? a[k] : (k < 32 ? b[k - 16] : q[k - 32]);
+}
+
+// sp is read where it lies (the kernel argument, or the batch slot in device
+// memory): a private copy of it is not promoted to registers reliably and
+// then lives in scratch memory.  The marginalisation of the frame's last step
+// is selected by `last` (sp.marginalise is ignored here).
+__device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials, const SolveParams& sp, int level,
+                                           int last, int nblocks) {
   __shared__ SolveWork w;
   __shared__ double raw[58];
   __shared__ dslam_frame_state x0, x1;
@@ -168,7 +194,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   }
   DSLAM_SYNC();
   if (skip) {
-    if (a.last) {
+    if (last) {
       SERIAL {
         sd->result.status = sd->status;
         sd->result.frame_index = sd->frame_index;
@@ -176,8 +202,6 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
     }
     return;
   }
-  SolveParams sp = a.sp;
-  sp.marginalise = a.last;
   const bool full = sp.mode != DSLAM_MODE_RGBD;
   // The first four waves reduce the block partials (their loads split over
   // the first two stages, the running sums in registers) while the operands
@@ -197,7 +221,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   static_assert(SOLVE_THREADS == 512 && REDUCE_THREADS == 256, "stage plan assumes 8 waves");
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   RowSums rs;
-  if (wave < 4) reduce_rows_part(partials, a.nblocks, 0, 2, rs);
+  if (wave < 4) reduce_rows_part(partials, nblocks, 0, 2, rs);
   if (full) imu_stage0(par, 4, x0, x1, qIW, pre, &w.ic, &w.is);
   if (wave == 4 || wave == 5) init_system_H(Par{lane + (wave == 5 ? 64 : 0), 128}, &w, sp, &pre, &prior);
   if (wave == 7) {
@@ -207,7 +231,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   }
   DSLAM_SYNC();
   if (wave < 4) {
-    reduce_rows_part(partials, a.nblocks, 1, 2, rs);
+    reduce_rows_part(partials, nblocks, 1, 2, rs);
     reduce_rows_store(rs, red);
   }
   if (full) {
@@ -233,26 +257,20 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   if (full) imu_stage2(par, 4, 7, pre, sp.imu, &w.ic, &w.is, []() {});
   if (wave == 1 || wave == 2) init_system_b(Par{lane + (wave == 2 ? 64 : 0), 128}, &w, sp, &pre, &prior);
   DSLAM_SYNC();
-  int st = solve_back(par, &w, sp, &pre, &prior, &x0, &x1, qIW, &marg);
+  int st = solve_back(par, &w, sp, &pre, &prior, &x0, &x1, qIW, last ? &marg : nullptr);
   // the next pass's transforms on 24 lanes of wave 0, the states and the
   // step's record by the first lanes of waves 1 and 2
   if (st == DSLAM_OK && threadIdx.x < 24)
     sd->xf[threadIdx.x] = next_transform_entry(x0, x1, sp.R_WM, sp.t_WM, (int)threadIdx.x);
-  TASK(1) {
-    if (st != DSLAM_OK) {
-      sd->status = st;
-    } else {
-      const dslam_frame_state a0 = x0, a1 = x1;  // read before the first store
-      double q[4];
-      for (int i = 0; i < 4; ++i) q[i] = qIW[i];
-      sd->x0 = a0;
-      sd->x1 = a1;
-      for (int i = 0; i < 4; ++i) sd->qIW[i] = q[i];
-    }
+  // the states x0, x1, q_IW (16 + 16 + 4 doubles), one double per lane of
+  // wave 1 (a one-lane struct copy is lowered through scratch memory)
+  if (wave == 1 && lane < 36) {
+    if (st == DSLAM_OK) state_word(sd->x0, sd->x1, sd->qIW, lane) = state_word(x0, x1, qIW, lane);
+    else if (lane == 0) sd->status = st;
   }
   TASK(2) {
-    sd->result.n_icp[a.level] = (int64_t)raw[28];
-    sd->result.n_rgb[a.level] = (int64_t)raw[57];
+    sd->result.n_icp[level] = (int64_t)raw[28];
+    sd->result.n_rgb[level] = (int64_t)raw[57];
     sd->result.cost_icp = w.cost[0];
     sd->result.cost_rgb = w.cost[1];
     sd->result.cost_imu = w.cost[2];
@@ -261,7 +279,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
     for (int i = 0; i < n; ++i) nrm += w.dz[i] * w.dz[i];
     sd->result.last_step_norm = sqrt(nrm);
   }
-  if (a.last) {
+  if (last) {
     DSLAM_SYNC();
     const bool ok = st == DSLAM_OK;
     if (ok && sp.mode != DSLAM_MODE_RGBD) {  // publish the marginal prior (parallel copy)
@@ -273,34 +291,25 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
         d2[i] = src[i];
       }
     }
+    dslam_track_result& r = sd->result;
+    if (wave == 1 && lane < 36) state_word(r.x0, r.x1, r.q_IW, lane) = state_word(x0, x1, qIW, lane);
+    // the current state becomes the previous one of the next frame
+    if (ok && wave == 2 && lane < 16) reinterpret_cast<double*>(&sd->x0)[lane] = reinterpret_cast<const double*>(&x1)[lane];
     SERIAL {
-      dslam_track_result& r = sd->result;
       r.status = sd->status;
-      r.x0 = x0;
-      r.x1 = x1;
-      for (int i = 0; i < 4; ++i) r.q_IW[i] = qIW[i];
-      if (ok) {
-        // the current state becomes the previous one of the next frame
-        sd->x0 = x1;
-        sd->frame_index += 1;
-      }
+      if (ok) sd->frame_index += 1;
       r.frame_index = sd->frame_index;
     }
   }
 }
 
 __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, const float* partials, SolveArgs a) {
-  solve_body(sd, partials, a);
+  solve_body(sd, partials, a.sp, a.level, a.last, a.nblocks);
 }
 
 __global__ __launch_bounds__(SOLVE_THREADS) void solve_batch_kernel(const SlotSolve* slots, int level, int last) {
   const SlotSolve* s = slots + blockIdx.x;
-  SolveArgs a;
-  a.sp = s->sp;
-  a.level = level;
-  a.last = last;
-  a.nblocks = s->nblocks[level];
-  solve_body(s->sd, s->partials, a);
+  solve_body(s->sd, s->partials, s->sp, level, last, s->nblocks[level]);
 }
 
 // Copies each session's result record into the batch's contiguous result array.

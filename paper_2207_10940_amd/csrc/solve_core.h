@@ -153,9 +153,17 @@ DX float next_transform_entry(const dslam_frame_state& x0, const dslam_frame_sta
                               const double* t_WM, int e) {
   const bool second = e >= 12;  // Rb, tb (reference camera) else Ra, ta (model view)
   const int q = second ? e - 12 : e;
-  const M3 L = second ? q2R(x0.q) : load33(R_WM);  // the transform is L^T [R1 | r1 - o]
+  // the transform is L^T [R1 | r1 - o]; L and o chosen entry by entry (a choice
+  // between whole private objects would put them in scratch memory)
+  const M3 Lq = q2R(x0.q), Lm = load33(R_WM);
+  M3 L;
+  for (int k = 0; k < 9; ++k) L.m[k] = second ? Lq.m[k] : Lm.m[k];
   const M3 R1 = q2R(x1.q);
-  const V3 d = load3(x1.r) - (second ? load3(x0.r) : load3(t_WM));
+  V3 o;
+  o.x = second ? x0.r[0] : t_WM[0];
+  o.y = second ? x0.r[1] : t_WM[1];
+  o.z = second ? x0.r[2] : t_WM[2];
+  const V3 d = load3(x1.r) - o;
   // every entry with fixed indices, then a select (private arrays indexed at
   // run time would live in scratch memory)
   double v = 0.0;
