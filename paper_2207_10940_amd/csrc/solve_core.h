@@ -593,19 +593,54 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
       for (int i = 0; i < 3; ++i) c += wbg * w->e[9 + i] * w->e[9 + i] + wba * w->e[12 + i] * w->e[12 + i];
       w->cost[2] = c;
     }
-    PFOR(idx, NZ * NZ + NZ) {
-      if (idx < NZ * NZ) {
-        int i = idx / NZ, j = idx % NZ;
-        const double a = dotN<9>(w->Y + i, NZ, w->Y + j, NZ);
-        // gyro-only: the entries no remaining term constrains are held fixed
-        // (identity rows and columns, zero right-hand side)
-        if (gyro && (gyro_fixed(i) || gyro_fixed(j))) w->H[idx] = (i == j) ? 1.0 : 0.0;
-        else w->H[idx] += a;
-      } else {
-        int i = idx - NZ * NZ;
-        const double a = dotN<9>(w->Y + i, NZ, w->y, 1);
-        if (gyro && gyro_fixed(i)) w->b[i] = 0.0;
-        else w->b[i] -= a;
+    // (M9 J9)^T (M9 J9) is symmetric bit for bit (entry (j, i) has the same
+    // products in the same order as (i, j)), so each unordered pair is formed
+    // once and added to both entries.  Items: the 33 x 17 pairs (i, i + c mod
+    // 33), c = 0..16 (33 is odd: every pair i != j has one circular distance
+    // of at most 16 in one direction), then the 33 right-hand-side entries; a
+    // lane forms its two items' dot products together (all reads in flight)
+    // before any update.
+    constexpr int NPAIR = NZ * 17, NITEM = NPAIR + NZ;
+    for (int base = par.lane; base < NITEM; base += 2 * par.nl) {
+      int ii[2], jj[2];
+      double xa[2][9], xb[2][9];
+      for (int u = 0; u < 2; ++u) {
+        const int it = base + u * par.nl;
+        const int q = it < NITEM ? it : 0;  // a past-the-end item reads item 0 and is not applied
+        const bool pair = q < NPAIR;
+        const int i = pair ? q % NZ : q - NPAIR, c = pair ? q / NZ : 0;
+        const int j = pair ? (i + c < NZ ? i + c : i + c - NZ) : -1;
+        ii[u] = i;
+        jj[u] = j;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          xa[u][k] = w->Y[k * NZ + i];
+          xb[u][k] = pair ? w->Y[k * NZ + j] : w->y[k];
+        }
+      }
+#ifdef __HIP_DEVICE_COMPILE__
+      __builtin_amdgcn_sched_barrier(0);
+#endif
+      for (int u = 0; u < 2; ++u) {
+        if (base + u * par.nl >= NITEM) continue;
+        double a = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a += xa[u][k] * xb[u][k];
+        const int i = ii[u], j = jj[u];
+        if (j >= 0) {
+          // gyro-only: the entries no remaining term constrains are held fixed
+          // (identity rows and columns, zero right-hand side)
+          if (gyro && (gyro_fixed(i) || gyro_fixed(j))) {
+            w->H[i * NZ + j] = (i == j) ? 1.0 : 0.0;
+            w->H[j * NZ + i] = (i == j) ? 1.0 : 0.0;
+          } else {
+            w->H[i * NZ + j] += a;
+            if (j != i) w->H[j * NZ + i] += a;
+          }
+        } else {
+          if (gyro && gyro_fixed(i)) w->b[i] = 0.0;
+          else w->b[i] -= a;
+        }
       }
     }
     DSLAM_SYNC();
