@@ -518,8 +518,8 @@ def main():
                     help="only run the level-0 residual pass and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the tracking step shards by session, one process per GPU, and this "
-              "build runs and reports a single MI355X only", file=sys.stderr)
+        print("bench.py measures one GPU: the tracking step shards by session (one process per GPU), and only "
+              "the single-GPU figure is measured and reported", file=sys.stderr)
         sys.exit(2)
     if args.counters:
         run_counters(args)
