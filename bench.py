@@ -83,10 +83,10 @@ def run_gpu(args):
     x_init = sess.get_state()
     stream = torch.cuda.current_stream()
 
-    def track(k):
+    def track(k):  # both pyramids, preintegration and prediction share the frame's first launch
         md, mi, T, d, i, imu, t0, t1 = frames[k]
-        sess.set_model(md, mi, T, stream)
-        sess.track_frame(d, i, imu, t0, t1, stream)
+        sess.track_frame_input({"depth": d, "intensity": i, "model_depth": md, "model_intensity": mi, "T_WM": T,
+                                "imu": imu, "t0": t0, "t1": t1}, stream)
 
     for k in range(args.warmup):
         track(k)
@@ -285,8 +285,7 @@ def run_serving(args):
         for j in range(min(nf, 12)):
             f = frames[(w, h)][specs[i][2]][j]
             ts = time.perf_counter()
-            s.set_model(f["model_depth"], f["model_intensity"], f["T_WM"], stream)
-            s.track_frame(f["depth"], f["intensity"], f["imu"], f["t0"], f["t1"], stream)
+            s.track_frame_input(f, stream)
             s.result()
             tl.append(time.perf_counter() - ts)
         per_class[f"{w}x{h}"] = float(np.median(tl[2:]))

@@ -174,10 +174,11 @@ typedef struct dslam_batch dslam_batch;
 #define DSLAM_MAX_BATCH 256
 #define DSLAM_MAX_BATCH_RESOLUTIONS 16
 
-/* One session's inputs for a batched step: the new frame and the model view
- * predicted for it (device images, height x width, row pitch in elements),
- * the model-view pose T_WM (4x4 row-major, host) and the frame's IMU samples
- * (host, same rules as dslam_track_frame; ignored in DSLAM_MODE_RGBD). */
+/* One session's inputs for a batched step or for dslam_track_frame_input:
+ * the new frame and the model view predicted for it (device images, height x
+ * width, row pitch in elements), the model-view pose T_WM (4x4 row-major,
+ * host) and the frame's IMU samples (host, same rules as dslam_track_frame;
+ * ignored in DSLAM_MODE_RGBD). */
 typedef struct {
   const float* depth;
   const uint8_t* intensity;
@@ -279,6 +280,17 @@ dslam_status dslam_solve_step(const double raw[58], const double T_WM[16], const
 dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const uint8_t* intensity_dev,
                                int32_t pitch_elems, const dslam_imu_sample* imu, int32_t n_imu, double t0,
                                double t1, void* stream);
+
+/* Track one frame given with its model view, as one session's input of a
+ * batched step (dslam_frame_input: device images, T_WM, host IMU samples):
+ * the same as dslam_build_pyramid(MODEL) followed by dslam_track_frame, with
+ * the same results, but both pyramids are built in the launch that
+ * preintegrates and predicts, alongside it.  No earlier MODEL pyramid is
+ * needed; this one stays for later dslam_track_frame calls.  The caller owns
+ * the images until the session's stream reaches the end of the frame.  Errors
+ * as dslam_track_frame, and INVALID for a missing model view or a non-finite
+ * T_WM. */
+dslam_status dslam_track_frame_input(dslam_session* s, const dslam_frame_input* in, void* stream);
 
 /* Wait for the session's last tracked frame and copy its result to host memory. */
 dslam_status dslam_session_result(dslam_session* s, dslam_track_result* out);

@@ -254,6 +254,15 @@ class Session:
                                        int(depth.shape[1]), arr, n, float(t0), float(t1), _stream_ptr(stream)),
                "dslam_track_frame")
 
+    def track_frame_input(self, frame: dict, stream=None):
+        """Enqueue one tracking step with its model view: frame = dict(depth, intensity, model_depth,
+        model_intensity, T_WM, imu, t0, t1) as for Batch.track; both pyramids are built in the launch
+        that initialises the frame (dslam_track_frame_input)."""
+        fi, keep = frame_input(frame)
+        _check(lib().dslam_track_frame_input(self.handle, C.byref(fi), _stream_ptr(stream)),
+               "dslam_track_frame_input")
+        self._keep_input = keep
+
     def result(self) -> dict:
         r = _abi.TrackResult()
         _check(lib().dslam_session_result(self.handle, C.byref(r)), "dslam_session_result")

@@ -33,7 +33,7 @@ EXACT_FP64 = ["-ffp-contract=off"]
 
 SOURCES = {
     "kernels.hip": EXACT_FP32,
-    "solve.hip": EXACT_FP64,
+    "solve.hip": EXACT_FP32,  # the frame-init launch also builds the pyramid; float64 contracts nothing either
     "dslam.hip": EXACT_FP64,
     "server.hip": EXACT_FP64,
 }

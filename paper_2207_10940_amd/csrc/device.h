@@ -59,7 +59,7 @@ struct ResidualArgs {
 enum { RES_THREADS = 256, PARTIAL_STRIDE = 64, SOLVE_THREADS = 512 };
 
 // ---- batched steps: several sessions share every launch ---------------------
-enum { MAX_BATCH = 256, MAX_CLASSES = 16, PYR_TILE_W = 64, PYR_TILE_H = 4 };
+enum { MAX_BATCH = 256, MAX_CLASSES = 16 };
 
 // One session's visual inputs for a batched step (device copy of host staging).
 struct SlotVis {

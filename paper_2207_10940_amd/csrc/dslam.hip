@@ -432,6 +432,17 @@ dslam_status dslam_session_close(dslam_session* s) {
   return DSLAM_OK;
 }
 
+// One pyramid launch of the session's CURRENT or MODEL planes.
+static PyrArgs pyr_args(const dslam_session* s, int which, const float* depth, const uint8_t* inten, int pitch) {
+  PyrArgs a;
+  a.src = PyrSrc{depth, inten, pitch};
+  const LevelPtrs* P = which == DSLAM_PYR_MODEL ? s->model : s->cur;
+  for (int l = 0; l < DSLAM_MAX_LEVELS; ++l) a.L[l] = P[l < s->levels ? l : 0];
+  a.levels = s->levels;
+  a.with_grad = which == DSLAM_PYR_MODEL;
+  return a;
+}
+
 dslam_status dslam_build_pyramid(dslam_session* s, int32_t which, const float* depth_dev,
                                  const uint8_t* intensity_dev, int32_t pitch_elems, const double T_W_ref[16],
                                  void* stream) {
@@ -445,10 +456,7 @@ dslam_status dslam_build_pyramid(dslam_session* s, int32_t which, const float* d
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  LevelPtrs* P = which == DSLAM_PYR_MODEL ? s->model : s->cur;
-  int grad = which == DSLAM_PYR_MODEL;
-  HIP_OK(launch_pyramid_level0(depth_dev, intensity_dev, pitch_elems, P[0], grad, st));
-  for (int l = 1; l < s->levels; ++l) HIP_OK(launch_pyramid_down(P[l - 1], P[l], grad, st));
+  HIP_OK(launch_pyramid(pyr_args(s, which, depth_dev, intensity_dev, pitch_elems), st));
   if (which == DSLAM_PYR_MODEL) {
     std::memcpy(s->T_WM, T_W_ref, sizeof(s->T_WM));
     s->have_model = true;
@@ -511,23 +519,23 @@ dslam_status dslam_solve_step(const double raw[58], const double T_WM[16], const
   return (dslam_status)st;
 }
 
-dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const uint8_t* intensity_dev,
-                               int32_t pitch_elems, const dslam_imu_sample* imu, int32_t n_imu, double t0,
-                               double t1, void* stream) {
-  if (!s || !depth_dev || !intensity_dev || pitch_elems < s->cam.width) return DSLAM_ERR_INVALID;
-  ImuBatch batch;
-  dslam_status sti = pack_imu(s, imu, n_imu, t0, t1, &batch);
-  if (sti != DSLAM_OK) return sti;
-  if (last_level_of(s->tp) < 0) return DSLAM_ERR_INVALID;
-  if (!s->have_model) return DSLAM_ERR_NOT_READY;
-  dslam_status st0 = dslam_build_pyramid(s, DSLAM_PYR_CURRENT, depth_dev, intensity_dev, pitch_elems, nullptr, stream);
-  if (st0 != DSLAM_OK) return st0;
+// Enqueues one frame; with a model view (mdepth != nullptr) its pyramid is
+// built in the same launch as the current frame's and the frame's
+// initialisation.  Arguments validated by the callers.
+static dslam_status track_enqueue(dslam_session* s, const float* depth, const uint8_t* inten, int32_t pitch,
+                                  const float* mdepth, const uint8_t* minten, int32_t mpitch, const double* T_WM,
+                                  const ImuBatch& batch, hipStream_t st) {
   std::lock_guard<std::mutex> g(s->mu);
-  hipStream_t st = (hipStream_t)stream;
+  HIP_OK(hipSetDevice(s->ctx->device));
+  if (mdepth) std::memcpy(s->T_WM, T_WM, sizeof(s->T_WM));
   SolveArgs sa;
   sa.sp = solve_params(s);
   FrameArgs fa = frame_args(s, sa.sp);
-  HIP_OK(launch_frame_init(s->sd, batch, fa, st));
+  const PyrArgs cur = pyr_args(s, DSLAM_PYR_CURRENT, depth, inten, pitch);
+  PyrArgs model;
+  if (mdepth) model = pyr_args(s, DSLAM_PYR_MODEL, mdepth, minten, mpitch);
+  HIP_OK(launch_frame_init_pyramid(s->sd, batch, fa, cur, mdepth ? &model : nullptr, st));
+  if (mdepth) s->have_model = true;
   const int last_level = last_level_of(s->tp);
   for (int l = s->levels - 1; l >= 0; --l) {
     ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
@@ -542,6 +550,32 @@ dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const u
   }
   HIP_OK(hipEventRecord(s->done, st));
   return DSLAM_OK;
+}
+
+dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const uint8_t* intensity_dev,
+                               int32_t pitch_elems, const dslam_imu_sample* imu, int32_t n_imu, double t0,
+                               double t1, void* stream) {
+  if (!s || !depth_dev || !intensity_dev || pitch_elems < s->cam.width) return DSLAM_ERR_INVALID;
+  ImuBatch batch;
+  dslam_status sti = pack_imu(s, imu, n_imu, t0, t1, &batch);
+  if (sti != DSLAM_OK) return sti;
+  if (last_level_of(s->tp) < 0) return DSLAM_ERR_INVALID;
+  if (!s->have_model) return DSLAM_ERR_NOT_READY;
+  return track_enqueue(s, depth_dev, intensity_dev, pitch_elems, nullptr, nullptr, 0, nullptr, batch,
+                       (hipStream_t)stream);
+}
+
+dslam_status dslam_track_frame_input(dslam_session* s, const dslam_frame_input* f, void* stream) {
+  if (!s || !f || !f->depth || !f->intensity || f->pitch < s->cam.width) return DSLAM_ERR_INVALID;
+  if (!f->model_depth || !f->model_intensity || f->model_pitch < s->cam.width) return DSLAM_ERR_INVALID;
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(f->T_WM[i])) return DSLAM_ERR_INVALID;
+  ImuBatch batch;
+  dslam_status sti = pack_imu(s, f->imu, f->n_imu, f->t0, f->t1, &batch);
+  if (sti != DSLAM_OK) return sti;
+  if (last_level_of(s->tp) < 0) return DSLAM_ERR_INVALID;
+  return track_enqueue(s, f->depth, f->intensity, f->pitch, f->model_depth, f->model_intensity, f->model_pitch,
+                       f->T_WM, batch, (hipStream_t)stream);
 }
 
 dslam_status dslam_batch_create(dslam_context* ctx, int32_t max_sessions, dslam_batch** out) {
@@ -696,14 +730,10 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
     g.first_block[nclass] = blk;
     return g;
   };
-  for (int which = 0; which < 2; ++which)
-    for (int l = 0; l < s0->levels; ++l) {
-      BatchGrid g = grid([&](const dslam_session* s) {
-        const LevelPtrs& L = s->cur[l];
-        return ((L.W + PYR_TILE_W - 1) / PYR_TILE_W) * ((L.H + PYR_TILE_H - 1) / PYR_TILE_H);
-      });
-      HIP_OK(launch_pyramid_batch(b->d_vis, g, l, which, st));
-    }
+  {  // every level of the current and model-view pyramids: one launch
+    BatchGrid g = grid([&](const dslam_session* s) { return 2 * PyrTileStd::tiles(s->cam.width, s->cam.height); });
+    HIP_OK(launch_pyramid_batch(b->d_vis, s0->levels, g, st));
+  }
   HIP_OK(launch_frame_init_batch(b->d_solve, n, st));
   b->levels = s0->levels;
   b->jac = s0->tp.jac_format;

@@ -12,122 +12,26 @@
 
 namespace dslam {
 
-// ---------------------------------------------------------------------------
-// Pyramid (Section IV-D: three-level coarse-to-fine scheme).
-//   level 0: depth cleaned (finite and > 0, else 0), intensity = float(uint8);
-//   level l+1: depth = mean of the valid depths of the 2x2 block summed in the
-//   order (2x,2y), (2x+1,2y), (2x,2y+1), (2x+1,2y+1); intensity =
-//   ((a + b) + (c + d)) * 0.25;
-//   vertex = rho(u, d) = (((i - cx) d) / fx, ((j - cy) d) / fy, d);
-//   normal = (a x b) / |a x b| with a = V(i+1,j) - V(i,j), b = V(i,j+1) - V(i,j);
-//   gradient (model view) = central differences * 0.5, zero on the border.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ float clean_depth(float d) { return (__builtin_isfinite(d) && d > 0.0f) ? d : 0.0f; }
-
-struct Src0 {  // level 0 from the caller's images
-  const float* depth;
-  const uint8_t* inten;
-  int pitch;
-  __device__ __forceinline__ float D(int i, int j) const { return clean_depth(depth[(size_t)j * pitch + i]); }
-  __device__ __forceinline__ float I(int i, int j) const { return (float)inten[(size_t)j * pitch + i]; }
-};
-
-struct SrcDown {  // level l+1 from level l's depth and intensity planes
-  const float* pd;
-  const uint16_t* pi;
-  int pw;
-  __device__ __forceinline__ float D(int i, int j) const {
-    const float* r0 = pd + (size_t)(2 * j) * pw + 2 * i;
-    const float* r1 = r0 + pw;
-    float t[4] = {r0[0], r0[1], r1[0], r1[1]};
-    float s = 0.0f, n = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (t[k] > 0.0f) {
-        s = s + t[k];
-        n = n + 1.0f;
-      }
-    return n > 0.0f ? s / n : 0.0f;
-  }
-  __device__ __forceinline__ float I(int i, int j) const {
-    const uint16_t* r0 = pi + (size_t)(2 * j) * pw + 2 * i;
-    const uint16_t* r1 = r0 + pw;
-    const float s = 1.0f / kIntensityScale;
-    return (((float)r0[0] * s + (float)r0[1] * s) + ((float)r1[0] * s + (float)r1[1] * s)) * 0.25f;
-  }
-};
-
-template <class Src>
-__device__ __forceinline__ void pyramid_pixel(const Src& src, const LevelPtrs& L, int with_grad, int i, int j) {
-  if (i >= L.W || j >= L.H) return;
-  const size_t p = (size_t)j * L.W + i;
-  float d = src.D(i, j);
-  float inten = src.I(i, j);
-  float fi = (float)i, fj = (float)j;
-  float vx = ((fi - L.cx) * d) / L.fx;
-  float vy = ((fj - L.cy) * d) / L.fy;
-  L.V[0][p] = vx;
-  L.V[1][p] = vy;
-  L.V[2][p] = d;
-  L.I[p] = (uint16_t)(inten * kIntensityScale);
-  float nx = 0.0f, ny = 0.0f, nz = 0.0f;
-  if (i < L.W - 1 && j < L.H - 1) {
-    float dr = src.D(i + 1, j), dd = src.D(i, j + 1);
-    float ax = (((fi + 1.0f) - L.cx) * dr) / L.fx - vx;
-    float ay = ((fj - L.cy) * dr) / L.fy - vy;
-    float az = dr - d;
-    float bx = ((fi - L.cx) * dd) / L.fx - vx;
-    float by = (((fj + 1.0f) - L.cy) * dd) / L.fy - vy;
-    float bz = dd - d;
-    float cx = ay * bz - az * by;
-    float cy = az * bx - ax * bz;
-    float cz = ax * by - ay * bx;
-    float len = __builtin_sqrtf((cx * cx + cy * cy) + cz * cz);
-    if (d > 0.0f && dr > 0.0f && dd > 0.0f && len > 0.0f) {
-      nx = cx / len;
-      ny = cy / len;
-      nz = cz / len;
-    }
-  }
-  L.N[0][p] = nx;
-  L.N[1][p] = ny;
-  L.N[2][p] = nz;
-  if (with_grad) {
-    float gx = 0.0f, gy = 0.0f;
-    if (i > 0 && i < L.W - 1 && j > 0 && j < L.H - 1) {
-      gx = (src.I(i + 1, j) - src.I(i - 1, j)) * 0.5f;
-      gy = (src.I(i, j + 1) - src.I(i, j - 1)) * 0.5f;
-    }
-    L.G[0][p] = (int16_t)(gx * kGradientScale);
-    L.G[1][p] = (int16_t)(gy * kGradientScale);
-  }
+// Pyramid (Section IV-D): every level of one image in one launch, one
+// workgroup per 64 x 8 tile of level 0 (the tile code and the operations that
+// define each value are in pyramid.h).
+__global__ __launch_bounds__(256) void pyramid_kernel(PyrArgs a) {
+  __shared__ PyrTileStd::Lds s;
+  pyramid_tile<256, 64, 8>(a.src, a.L, a.levels, a.with_grad, blockIdx.x, s, threadIdx.x);
 }
 
-template <class Src>
-__global__ __launch_bounds__(256) void pyramid_level_kernel(Src src, LevelPtrs L, int with_grad) {
-  pyramid_pixel(src, L, with_grad, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y * blockDim.y + threadIdx.y);
-}
-
-// Batched: one launch builds one level of the current (which = 0) or model-view
-// (which = 1) pyramid of every session of the batch; each workgroup covers one
-// PYR_TILE_W x PYR_TILE_H tile of one session.
-__global__ __launch_bounds__(256) void pyramid_batch_kernel(const SlotVis* slots, BatchGrid g, int level, int which) {
+// Batched: both pyramids of every session of the batch in one launch, per
+// session 2 x PyrTileStd::tiles workgroups (current frame first), located
+// through g.
+__global__ __launch_bounds__(256) void pyramid_batch_kernel(const SlotVis* slots, int levels, BatchGrid g) {
   int slot, b;
   batch_locate(g, blockIdx.x, &slot, &b);
   const SlotVis* sv = slots + slot;
-  const LevelPtrs& L = which ? sv->model[level] : sv->cur[level];
-  const int tiles_x = (L.W + PYR_TILE_W - 1) / PYR_TILE_W;
-  const int ty = b / tiles_x, tx = b - ty * tiles_x;
-  const int i = tx * PYR_TILE_W + (threadIdx.x % PYR_TILE_W), j = ty * PYR_TILE_H + (threadIdx.x / PYR_TILE_W);
-  if (level == 0) {
-    Src0 src{which ? sv->mdepth : sv->depth, which ? sv->minten : sv->inten, which ? sv->mpitch : sv->pitch};
-    pyramid_pixel(src, L, which, i, j);
-  } else {
-    const LevelPtrs& P = which ? sv->model[level - 1] : sv->cur[level - 1];
-    SrcDown src{P.V[2], P.I, P.W};
-    pyramid_pixel(src, L, which, i, j);
-  }
+  const int per = PyrTileStd::tiles(sv->cur[0].W, sv->cur[0].H);
+  const int which = b >= per ? 1 : 0;
+  const PyrSrc src{which ? sv->mdepth : sv->depth, which ? sv->minten : sv->inten, which ? sv->mpitch : sv->pitch};
+  __shared__ PyrTileStd::Lds s;
+  pyramid_tile<256, 64, 8>(src, which ? sv->model : sv->cur, levels, which, b - which * per, s, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,23 +561,13 @@ __global__ __launch_bounds__(RES_THREADS) void residual_batch_mfma_kernel(const 
 // ---------------------------------------------------------------------------
 namespace dslam {
 
-hipError_t launch_pyramid_level0(const float* depth, const uint8_t* inten, int pitch, const LevelPtrs& L,
-                                 int with_grad, hipStream_t st) {
-  dim3 blk(64, 4), grd((L.W + 63) / 64, (L.H + 3) / 4);
-  Src0 s{depth, inten, pitch};
-  hipLaunchKernelGGL(pyramid_level_kernel<Src0>, grd, blk, 0, st, s, L, with_grad);
+hipError_t launch_pyramid_batch(const SlotVis* slots, int levels, const BatchGrid& g, hipStream_t st) {
+  hipLaunchKernelGGL(pyramid_batch_kernel, dim3(g.first_block[g.nclass]), dim3(256), 0, st, slots, levels, g);
   return hipGetLastError();
 }
 
-hipError_t launch_pyramid_down(const LevelPtrs& parent, const LevelPtrs& L, int with_grad, hipStream_t st) {
-  dim3 blk(64, 4), grd((L.W + 63) / 64, (L.H + 3) / 4);
-  SrcDown s{parent.V[2], parent.I, parent.W};
-  hipLaunchKernelGGL(pyramid_level_kernel<SrcDown>, grd, blk, 0, st, s, L, with_grad);
-  return hipGetLastError();
-}
-
-hipError_t launch_pyramid_batch(const SlotVis* slots, const BatchGrid& g, int level, int which, hipStream_t st) {
-  hipLaunchKernelGGL(pyramid_batch_kernel, dim3(g.first_block[g.nclass]), dim3(256), 0, st, slots, g, level, which);
+hipError_t launch_pyramid(const PyrArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(pyramid_kernel, dim3(PyrTileStd::tiles(a.L[0].W, a.L[0].H)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

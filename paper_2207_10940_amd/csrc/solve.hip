@@ -139,11 +139,32 @@ __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& 
   }
 }
 
-__global__ __launch_bounds__(SOLVE_THREADS) void frame_init_kernel(SessionDev* sd, ImuBatch batch, FrameArgs fa) {
-  frame_init_body(sd, batch, fa);
+// Workgroup 0 initialises the frame; the others build the current frame's
+// pyramid (cur) and, if model_tiles > 0, the model view's (model), one tile
+// each, while it runs (the three touch disjoint memory).
+__global__ __launch_bounds__(SOLVE_THREADS) void frame_init_pyramid_kernel(SessionDev* sd, ImuBatch batch,
+                                                                           FrameArgs fa, PyrArgs cur, PyrArgs model,
+                                                                           int cur_tiles) {
+  if (blockIdx.x == 0) {
+    frame_init_body(sd, batch, fa);
+    return;
+  }
+  const int t = (int)blockIdx.x - 1;
+  __shared__ PyrTileBig::Lds lds;
+  // (two calls rather than a select between the argument structs, which would
+  // copy them to scratch memory)
+  if (t < cur_tiles)
+    pyramid_tile<SOLVE_THREADS, 64, 16>(cur.src, cur.L, cur.levels, cur.with_grad, t, lds, (int)threadIdx.x);
+  else
+    pyramid_tile<SOLVE_THREADS, 64, 16>(model.src, model.L, model.levels, model.with_grad, t - cur_tiles, lds,
+                                        (int)threadIdx.x);
 }
+static_assert(sizeof(SessionDev*) + sizeof(ImuBatch) + sizeof(FrameArgs) + 2 * sizeof(PyrArgs) + 16 <= 4096,
+              "frame-init arguments exceed the kernel-argument segment");
 
-// one workgroup per session of the batch
+// Batched: one workgroup per session of the batch.  (The batched pyramids run
+// in a launch of their own: sharing this kernel's register and LDS allocation
+// would leave them a quarter of the occupancy they need at batch scale.)
 __global__ __launch_bounds__(SOLVE_THREADS) void frame_init_batch_kernel(const SlotSolve* slots) {
   const SlotSolve* s = slots + blockIdx.x;
   frame_init_body(s->sd, s->imu, s->fa);
@@ -321,11 +342,6 @@ __global__ __launch_bounds__(SOLVE_THREADS) void gather_results_kernel(const Slo
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_frame_init(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, hipStream_t st) {
-  hipLaunchKernelGGL(frame_init_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, sd, b, fa);
-  return hipGetLastError();
-}
-
 hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(solve_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, sd, partials, a);
   return hipGetLastError();
@@ -333,6 +349,15 @@ hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& 
 
 hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(REDUCE_THREADS), 0, st, partials, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_frame_init_pyramid(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, const PyrArgs& cur,
+                                     const PyrArgs* model, hipStream_t st) {
+  const int ct = PyrTileBig::tiles(cur.L[0].W, cur.L[0].H);
+  const int mt = model ? PyrTileBig::tiles(model->L[0].W, model->L[0].H) : 0;
+  hipLaunchKernelGGL(frame_init_pyramid_kernel, dim3(1 + ct + mt), dim3(SOLVE_THREADS), 0, st, sd, b, fa, cur,
+                     model ? *model : cur, ct);
   return hipGetLastError();
 }
 

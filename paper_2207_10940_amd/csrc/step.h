@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include "device.h"
+#include "pyramid.h"
 #include "solve_core.h"
 
 namespace dslam {
@@ -41,19 +42,21 @@ struct SlotSolve {
 };
 
 // kernels.hip
-hipError_t launch_pyramid_level0(const float* depth, const uint8_t* inten, int pitch, const LevelPtrs& L,
-                                 int with_grad, hipStream_t st);
-hipError_t launch_pyramid_down(const LevelPtrs& parent, const LevelPtrs& L, int with_grad, hipStream_t st);
+hipError_t launch_pyramid(const PyrArgs& a, hipStream_t st);
 int residual_blocks(int npix, int ppt);
 hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st);
 hipError_t launch_tune_scene(float* depth, uint8_t* inten, int W, int H, hipStream_t st);
-// which: 0 current frame, 1 model view
-hipError_t launch_pyramid_batch(const SlotVis* slots, const BatchGrid& g, int level, int which, hipStream_t st);
+// every level of every session's current and model-view pyramids; g maps the
+// workgroups (2 x PyrTileStd::tiles per session: current frame first)
+hipError_t launch_pyramid_batch(const SlotVis* slots, int levels, const BatchGrid& g, hipStream_t st);
 hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, int jac,
                                  hipStream_t st);
 
 // solve.hip
-hipError_t launch_frame_init(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, hipStream_t st);
+// the frame initialisation, the current frame's pyramid and (model != nullptr)
+// the model view's pyramid in one launch
+hipError_t launch_frame_init_pyramid(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, const PyrArgs& cur,
+                                     const PyrArgs* model, hipStream_t st);
 hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& a, hipStream_t st);
 hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st);
 hipError_t launch_frame_init_batch(const SlotSolve* slots, int n, hipStream_t st);
