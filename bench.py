@@ -27,9 +27,9 @@ METRIC = "tracked frames/s + residual-pass GB/s at 640x480; p50/p99 track latenc
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20  # calibration copy for the HBM byte counters
 # HBM bytes per level-0 residual launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by the
-# reading of a 256 MiB copy (fetch x1.99981, write x1.0); valid for the kernel source with this hash.
-TRAFFIC_BYTES_LEVEL0 = (7810.9 * 262144 / 131087.6 + 150.0) * 1024
-TRAFFIC_SOURCE_SHA256 = "80adab6fc111c0ce"
+# reading of a 256 MiB copy (fetch x1.99985, write x1.0); valid for the kernel source with this hash.
+TRAFFIC_BYTES_LEVEL0 = (7810.9 * 262144 / 131085.1 + 150.0) * 1024
+TRAFFIC_SOURCE_SHA256 = "fd49821d72aecd30"
 # bytes the residual pass reads per pixel-iteration: current vertex 12 + intensity 2, model-view vertex 12 +
 # normal 12 + intensity 2 + gradient 4 (16-bit fixed-point intensity and gradient; N1 unread without the
 # normal gate)

@@ -32,6 +32,7 @@ EXACT_FP32 = ["-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt"]
 EXACT_FP64 = ["-ffp-contract=off"]
 
 SOURCES = {
+    "pyramid.hip": EXACT_FP32,
     "kernels.hip": EXACT_FP32,
     "solve.hip": EXACT_FP32,  # the frame-init launch also builds the pyramid; float64 contracts nothing either
     "dslam.hip": EXACT_FP64,

@@ -41,14 +41,16 @@ struct SlotSolve {
   int32_t nblocks[DSLAM_MAX_LEVELS];
 };
 
-// kernels.hip
+// pyramid.hip
 hipError_t launch_pyramid(const PyrArgs& a, hipStream_t st);
-int residual_blocks(int npix, int ppt);
-hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st);
-hipError_t launch_tune_scene(float* depth, uint8_t* inten, int W, int H, hipStream_t st);
 // every level of every session's current and model-view pyramids; g maps the
 // workgroups (2 x PyrTileStd::tiles per session: current frame first)
 hipError_t launch_pyramid_batch(const SlotVis* slots, int levels, const BatchGrid& g, hipStream_t st);
+
+// kernels.hip
+int residual_blocks(int npix, int ppt);
+hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st);
+hipError_t launch_tune_scene(float* depth, uint8_t* inten, int W, int H, hipStream_t st);
 hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, int jac,
                                  hipStream_t st);
 
