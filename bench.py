@@ -474,6 +474,101 @@ def run_stress(args):
     }
 
 
+def ate_rmse(est, gt, align=True):
+    """Absolute trajectory error (RMSE of the position differences, the metric of the paper's evaluation
+    after Sturm et al.): est and gt are N x 3 positions; with align, est is first moved by the rigid
+    transform (rotation and translation, no scale) that minimises the squared error (closed form from the
+    SVD of the cross-covariance, with the reflection excluded)."""
+    est = np.asarray(est, dtype=np.float64)
+    gt = np.asarray(gt, dtype=np.float64)
+    if align and len(est) >= 3:
+        me, mg = est.mean(axis=0), gt.mean(axis=0)
+        U, _, Vt = np.linalg.svd((gt - mg).T @ (est - me))
+        D = np.diag([1.0, 1.0, np.sign(np.linalg.det(U @ Vt))])
+        R = U @ D @ Vt
+        est = (est - me) @ R.T + mg
+    return float(np.sqrt(np.mean(np.sum((est - gt) ** 2, axis=1))))
+
+
+def rot_angle_deg(Ra, Rb):
+    """Angle of Ra^T Rb in degrees."""
+    c = (np.trace(Ra.T @ Rb) - 1.0) / 2.0
+    return float(np.degrees(np.arccos(np.clip(c, -1.0, 1.0))))
+
+
+ROBUST_LOST_M, ROBUST_LOST_DEG = 0.10, 5.0
+
+
+def run_robustness(args):
+    """The paper's robustness comparison (RGB-D-inertial against RGB-D-only, plus the gyro-aided variant)
+    on synthetic stand-ins: one seeded sequence tracked at 30 Hz, with frames skipped (fast motion: the
+    same trajectory at 15 and 7.5 Hz) and with low-texture albedo.  Every frame is tracked against the
+    noise-free model view rendered at the previous frame's estimate (as a dense map would supply it), so
+    a frame that fails to converge hands its error on.  Reports per case and estimator the ATE RMSE of
+    the current-frame positions (raw and rigidly aligned), the largest orientation error and the frames
+    lost (position error above ROBUST_LOST_M or orientation error above ROBUST_LOST_DEG)."""
+    import torch
+
+    import paper_2207_10940_amd as P
+    S = synth_mod()
+    W, H, n = args.robust_width, args.robust_height, args.robust_frames
+    t = time.time()
+    seqs = {tex: S.configs.sequence(seed=5001, n_frames=n, width=W, height=H, device="cuda",
+                                    low_texture_every=1 if tex else 0) for tex in (False, True)}
+    log(f"[robust] generated 2 sequences x {n} frames {W}x{H} in {time.time() - t:.1f}s")
+    cases = [("30 Hz", False, 1), ("15 Hz", False, 2), ("7.5 Hz", False, 4), ("low texture, 30 Hz", True, 1),
+             ("low texture, 7.5 Hz", True, 4)]
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"{W}x{H} spline sequence (seed 5001, peak 1.5 m/s and 180 deg/s), {n} frames at 30 Hz, "
+                       f"every k-th frame tracked; 3 levels 10/5/4 iterations; model view rendered at the "
+                       f"previous estimate",
+           "lost_threshold": {"m": ROBUST_LOST_M, "deg": ROBUST_LOST_DEG}, "cases": {}}
+    for name, tex, skip in cases:
+        seq = seqs[tex]
+        cam = seq["camera"]
+        R_IW = S.configs._rot_from_quat(seq["q_IW_gt"])
+        res = {}
+        for mode in ("rgbdi", "rgbd", "gyro"):
+            ctx = P.Context(0)
+            tp = P.track_params(levels=3, iters=(10, 5, 4), mode=mode, jac="fp32")
+            sess = P.Session(ctx, cam, tp, P.imu_params(), seq["x0"], seq["q_IW"],
+                             seq["prior"] if mode != "rgbd" else None)
+            prev = seq["x0"]
+            est, gtp, rot_err, lost, failed = [], [], [], 0, 0
+            for j in range(skip, n, skip):
+                R_WC = S.configs._rot_from_quat(prev["q"])
+                z, inten = S.scene.render(seq["scene"], R_IW @ R_WC, R_IW @ prev["r"], W, H, cam.fx, cam.fy,
+                                          cam.cx, cam.cy, depth_noise_k=0.0, low_texture=tex, device="cuda")
+                T = np.eye(4)
+                T[:3, :3], T[:3, 3] = R_WC, prev["r"]
+                t0, t1 = seq["times"][j - skip], seq["times"][j]
+                a, b = S.configs.imu_window(seq["imu"]["t"], t0, t1)
+                imu = {k: v[a:b] for k, v in seq["imu"].items()} if mode != "rgbd" else None
+                sess.track_frame_input({"depth": seq["depth"][j].contiguous(),
+                                        "intensity": seq["intensity"][j].contiguous(),
+                                        "model_depth": z.contiguous(), "model_intensity": inten.contiguous(),
+                                        "T_WM": T, "imu": imu, "t0": t0, "t1": t1}, stream)
+                r = sess.result()
+                failed += r["status"] != 0
+                prev = r["x1"]
+                g = seq["gt"][j]
+                est.append(prev["r"])
+                gtp.append(g["r"])
+                dr = float(np.linalg.norm(prev["r"] - g["r"]))
+                da = rot_angle_deg(S.configs._rot_from_quat(g["q"]), S.configs._rot_from_quat(prev["q"]))
+                rot_err.append(da)
+                lost += (dr > ROBUST_LOST_M) or (da > ROBUST_LOST_DEG)
+            sess.close()
+            ctx.close()
+            res[mode] = {"ate_rmse_m": ate_rmse(est, gtp, align=False), "ate_rmse_aligned_m": ate_rmse(est, gtp),
+                         "max_rot_err_deg": max(rot_err), "lost_frames": int(lost), "failed_frames": int(failed),
+                         "frames": len(est)}
+        out["cases"][name] = res
+        log(f"[robust] {name}: " + "  ".join(f"{m} ATE {v['ate_rmse_m'] * 100:.2f} cm lost {v['lost_frames']}/"
+                                            f"{v['frames']}" for m, v in res.items()))
+    return out
+
+
 def cpu_baseline(seq, n_frames):
     """The oracle as it stands, single-threaded, on the first frames of the same sequence."""
     from threadpoolctl import threadpool_limits
@@ -513,6 +608,11 @@ def main():
     ap.add_argument("--stress-sequences", type=int, default=4,
                     help="distinct seeded sequences per resolution of the stress workload")
     ap.add_argument("--no-stress", action="store_true")
+    ap.add_argument("--robust-frames", type=int, default=91, help="frames of the robustness sequences")
+    ap.add_argument("--robust-width", type=int, default=320)
+    ap.add_argument("--robust-height", type=int, default=240)
+    ap.add_argument("--no-robustness", action="store_true")
+    ap.add_argument("--robustness-only", action="store_true", help="only run the robustness comparison")
     ap.add_argument("--counters", action="store_true",
                     help="only run the level-0 residual pass and a calibration copy (for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -523,6 +623,9 @@ def main():
     if args.counters:
         run_counters(args)
         return
+    if args.robustness_only:
+        print(json.dumps(run_robustness(args)), flush=True)
+        return
     g = run_gpu(args)
     serving = None
     if not args.no_serving:
@@ -530,6 +633,9 @@ def main():
     stress = None
     if not args.no_stress:
         stress = run_stress(args)
+    robust = None
+    if not args.no_robustness:
+        robust = run_robustness(args)
     cpu = None
     if not args.no_cpu_baseline and args.cpu_frames > 0:
         t = time.time()
@@ -544,6 +650,7 @@ def main():
                    "levels": 3, "iters": [10, 5, 4], "jac_format": "fp32", "frames": args.steps},
         "latency_ms": g["latency_ms"], "pose_err_final_m": g["pose_err_final_m"],
         "roofline": g["roofline"], "cpu_baseline": cpu, "serving": serving, "stress": stress,
+        "robustness": robust,
     }
     print(json.dumps(out), flush=True)
 

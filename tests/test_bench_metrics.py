@@ -1,0 +1,53 @@
+"""Host-side metrics of the benchmark's robustness comparison: the absolute
+trajectory error (RMSE of position differences after the optional rigid
+alignment) and the rotation angle between two orientations."""
+import numpy as np
+
+import bench
+
+
+def _rot(axis, deg):
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    t = np.radians(deg)
+    return np.eye(3) + np.sin(t) * K + (1 - np.cos(t)) * K @ K
+
+
+def test_ate_zero_for_identical_and_rigidly_moved_trajectories():
+    rng = np.random.default_rng(7)
+    gt = np.cumsum(rng.normal(size=(40, 3)) * 0.05, axis=0)
+    assert bench.ate_rmse(gt, gt, align=False) == 0.0
+    assert bench.ate_rmse(gt, gt) < 1e-12
+    R, t = _rot([1, 2, 3], 37.0), np.array([0.3, -1.2, 2.0])
+    moved = gt @ R.T + t
+    assert bench.ate_rmse(moved, gt) < 1e-12  # removed by the alignment
+    # without it, the error of a pure translation is its length
+    assert abs(bench.ate_rmse(gt + t, gt, align=False) - np.linalg.norm(t)) < 1e-12
+
+
+def test_ate_matches_hand_computed_residual():
+    # a fixed offset of +-d along one axis on alternate points cannot be aligned away when the
+    # points are spread along an orthogonal axis with zero mean offset: RMSE = d
+    d = 0.01
+    gt = np.stack([np.zeros(6), np.linspace(-1.0, 1.0, 6), np.zeros(6)], axis=1)
+    est = gt.copy()
+    est[:, 0] += d * np.array([1, -1, 1, -1, 1, -1])
+    raw = bench.ate_rmse(est, gt, align=False)
+    assert abs(raw - d) < 1e-15
+    assert bench.ate_rmse(est, gt) <= raw + 1e-15  # alignment can only lower it
+
+
+def test_ate_alignment_is_not_a_reflection():
+    # a mirrored planar trajectory must not be "aligned" by a reflection
+    rng = np.random.default_rng(3)
+    gt = rng.normal(size=(30, 3))
+    mirrored = gt * np.array([1.0, 1.0, -1.0])
+    assert bench.ate_rmse(mirrored, gt) > 0.1
+
+
+def test_rotation_angle():
+    R = _rot([0, 0, 1], 30.0)
+    assert abs(bench.rot_angle_deg(np.eye(3), R) - 30.0) < 1e-9
+    assert abs(bench.rot_angle_deg(R, R)) < 1e-6
+    assert abs(bench.rot_angle_deg(np.eye(3), _rot([1, 1, 0], 179.0)) - 179.0) < 1e-6
