@@ -25,16 +25,20 @@ COMMON = [
 # correctly rounded division and square root.
 EXACT_FP32 = ["-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt"]
 
-# The float64 solve and IMU code contracts nothing implicitly either: every
-# fused multiply-add it uses is written out, so the same source gives the same
-# bits in every kernel that inlines it (single-session and batched launches)
-# and on the host.
+# Host code contracts nothing implicitly.
 EXACT_FP64 = ["-ffp-contract=off"]
+
+# The device float64 solve, IMU and frame-initialisation code fuses the
+# multiply-adds within each expression (-ffp-contract=on: decided per source
+# expression, so every kernel that inlines a function gets the same bits,
+# single-session and batched alike); the float32 pyramid code it shares a
+# launch with switches contraction off in its own functions.
+DEVICE_FP64 = ["-ffp-contract=on", "-fhip-fp32-correctly-rounded-divide-sqrt"]
 
 SOURCES = {
     "pyramid.hip": EXACT_FP32,
     "kernels.hip": EXACT_FP32,
-    "solve.hip": EXACT_FP32,  # the frame-init launch also builds the pyramid; float64 contracts nothing either
+    "solve.hip": DEVICE_FP64,
     "dslam.hip": EXACT_FP64,
     "server.hip": EXACT_FP64,
 }

@@ -14,9 +14,10 @@
 // pixel for the coarsest level's normals and gradients, and at every finer
 // level the 2x2 parents of the next level's margin.  The margin is recomputed
 // by the neighbouring tiles too, with the same operations, so every value is
-// the one a level-by-level construction produces.  Include only in translation
-// units built with -ffp-contract=off and correctly rounded float32 division
-// and square root.
+// the one a level-by-level construction produces.  The functions below contract
+// no multiply-add (whatever the translation unit's setting); include only in
+// translation units built with correctly rounded float32 division and square
+// root.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -83,6 +84,7 @@ __device__ __forceinline__ void pyr_st(T* base, size_t idx, T v) {
 // region of width E in LDS (all four neighbours are inside the region).
 __device__ __forceinline__ void pyr_out(const LevelPtrs& L, const float* D, const float* In, int E, int a, int b,
                                         int i, int j, int with_grad) {
+#pragma clang fp contract(off)
   const int q = b * E + a;
   // every LDS read first
   const float d = D[q], dr = D[q + 1], dd = D[q + E];
@@ -139,6 +141,7 @@ __device__ __forceinline__ void pyr_out(const LevelPtrs& L, const float* D, cons
 template <int NT, int TW, int TH>
 __device__ __forceinline__ void pyramid_tile(const PyrSrc& src, const LevelPtrs* L, int levels, int with_grad,
                                              int tile, typename PyrTile<TW, TH>::Lds& s, int tid) {
+#pragma clang fp contract(off)
   using P = PyrTile<TW, TH>;
   const int c = levels - 1;
   const int tiles_x = (L[0].W + TW - 1) / TW;
