@@ -502,7 +502,8 @@ ROBUST_LOST_M, ROBUST_LOST_DEG = 0.10, 5.0
 def run_robustness(args):
     """The paper's robustness comparison (RGB-D-inertial against RGB-D-only, plus the gyro-aided variant)
     on synthetic stand-ins: one seeded sequence tracked at 30 Hz, with frames skipped (fast motion: the
-    same trajectory at 15 and 7.5 Hz) and with low-texture albedo.  Every frame is tracked against the
+    same trajectory at 15 and 7.5 Hz), with low-texture albedo, and low texture with the back wall alone
+    in view (little photometric and geometric variation).  Every frame is tracked against the
     noise-free model view rendered at the previous frame's estimate (as a dense map would supply it), so
     a frame that fails to converge hands its error on.  Reports per case and estimator the ATE RMSE of
     the current-frame positions (raw and rigidly aligned), the largest orientation error and the frames
@@ -513,18 +514,21 @@ def run_robustness(args):
     S = synth_mod()
     W, H, n = args.robust_width, args.robust_height, args.robust_frames
     t = time.time()
-    seqs = {tex: S.configs.sequence(seed=5001, n_frames=n, width=W, height=H, device="cuda",
-                                    low_texture_every=1 if tex else 0) for tex in (False, True)}
-    log(f"[robust] generated 2 sequences x {n} frames {W}x{H} in {time.time() - t:.1f}s")
-    cases = [("30 Hz", False, 1), ("15 Hz", False, 2), ("7.5 Hz", False, 4), ("low texture, 30 Hz", True, 1),
-             ("low texture, 7.5 Hz", True, 4)]
+    variants = [("room", False), ("room", True), ("wall", True)]
+    seqs = {v: S.configs.sequence(seed=5001, n_frames=n, width=W, height=H, device="cuda",
+                                  low_texture_every=1 if v[1] else 0, layout=v[0]) for v in variants}
+    log(f"[robust] generated {len(seqs)} sequences x {n} frames {W}x{H} in {time.time() - t:.1f}s")
+    cases = [("30 Hz", ("room", False), 1), ("15 Hz", ("room", False), 2), ("7.5 Hz", ("room", False), 4),
+             ("low texture, 30 Hz", ("room", True), 1), ("low texture, 7.5 Hz", ("room", True), 4),
+             ("flat wall, low texture, 30 Hz", ("wall", True), 1)]
     stream = torch.cuda.current_stream()
     out = {"workload": f"{W}x{H} spline sequence (seed 5001, peak 1.5 m/s and 180 deg/s), {n} frames at 30 Hz, "
                        f"every k-th frame tracked; 3 levels 10/5/4 iterations; model view rendered at the "
-                       f"previous estimate",
+                       f"previous estimate; scene: room corner with spheres, or the back wall alone",
            "lost_threshold": {"m": ROBUST_LOST_M, "deg": ROBUST_LOST_DEG}, "cases": {}}
-    for name, tex, skip in cases:
-        seq = seqs[tex]
+    for name, var, skip in cases:
+        seq = seqs[var]
+        tex = var[1]
         cam = seq["camera"]
         R_IW = S.configs._rot_from_quat(seq["q_IW_gt"])
         res = {}

@@ -138,7 +138,7 @@ def frame_pair(seed: int = 1001, width: int = 160, height: int = 120, *, noisy_i
 
 def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: int = 480, *, fps: float = 30.0,
              imu_rate: float = 200.0, device="cpu", low_texture_every: int = 0, duration: float | None = None,
-             low_texture_frames=(), hole_frames=(), hole_fraction: float = 0.8) -> dict:
+             low_texture_frames=(), hole_frames=(), hole_fraction: float = 0.8, layout: str = "room") -> dict:
     """Plain method, single session: a seeded smooth B-spline trajectory (peak
     1.5 m/s, 180 deg/s), IMU at 200 Hz with random-walk biases.  Frame j is
     rendered at its ground-truth pose with depth noise; the model view used to
@@ -147,9 +147,10 @@ def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: in
     Stress options: frames listed in ``low_texture_frames`` (or every
     ``low_texture_every``-th) get the low-texture albedo (variance x 0.01);
     frames in ``hole_frames`` lose ``hole_fraction`` of their measured depth to
-    zero-depth blobs (value noise thresholded at that quantile)."""
+    zero-depth blobs (value noise thresholded at that quantile).  ``layout``
+    "wall" renders the back wall alone (same trajectory and IMU stream)."""
     rng = np.random.default_rng(seed)
-    scene = make_scene(rng, seed)
+    scene = make_scene(rng, seed, layout)
     # by default the trajectory and the IMU stream span the full 10 s sequence, so
     # a shorter sequence is a prefix of the long one; an explicit duration (the
     # serving workload's many short sessions) trades that for generation time

@@ -29,8 +29,10 @@ class Scene:
     seed: int = 0
 
 
-def make_scene(rng: np.random.Generator, seed: int) -> Scene:
-    """Room corner (floor, back wall, left wall) with four spheres in view."""
+def make_scene(rng: np.random.Generator, seed: int, layout: str = "room") -> Scene:
+    """Room corner (floor, back wall, left wall) with four spheres in view; with
+    layout "wall", the back wall alone (a geometrically degenerate view: the
+    same random draws, so the rest of a seeded sequence is unchanged)."""
     h = rng.uniform(1.1, 1.5)
     yb = rng.uniform(3.0, 3.6)
     xs = rng.uniform(1.6, 2.2)
@@ -40,6 +42,10 @@ def make_scene(rng: np.random.Generator, seed: int) -> Scene:
         r = rng.uniform(0.2, 0.5)
         c = np.array([rng.uniform(-1.2, 1.2), rng.uniform(1.5, 2.8), rng.uniform(-h + r, 0.5)])
         spheres.append((c, r))
+    if layout == "wall":
+        return Scene(planes=[planes[1]], spheres=[], seed=int(seed))
+    if layout != "room":
+        raise ValueError(f"unknown scene layout {layout!r}")
     return Scene(planes=planes, spheres=spheres, seed=int(seed))
 
 
