@@ -114,6 +114,18 @@ def run_gpu(args):
     lat = np.array(lat[5:] if len(lat) > 10 else lat)
     log(f"[bench] latency over {len(lat)} frames: p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
 
+    # accuracy over the whole sequence, frame by frame from the initial state (outside the timed region):
+    # the analogue of the paper's velocity / bias convergence plots and its ATE RMSE
+    sess.set_state(*x_init)
+    est = []
+    for k in range(n_frames - 1):
+        track(k)
+        est.append(sess.result()["x1"])
+    accuracy = sequence_accuracy(est, seq["gt"][1:n_frames])
+    log(f"[bench] accuracy over {len(est)} frames: ATE {accuracy['ate_rmse_m'] * 100:.3f} cm, velocity error "
+        f"{accuracy['windows'][-1]['vel_err_mps']:.2e} m/s, gyro bias {accuracy['windows'][-1]['bg_err_radps']:.2e} "
+        f"rad/s, accel bias {accuracy['windows'][-1]['ba_err_mps2']:.2e} m/s^2 (last window)")
+
     # dominant kernel: the level-0 residual pass, timed back to back with events on the same stream
     reps = args.kernel_reps
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -133,6 +145,7 @@ def run_gpu(args):
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "frames": int(len(lat)), "kind": "host submit to result, one frame at a time"},
         "pose_err_final_m": pos_err,
+        "accuracy": accuracy,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "residual_kernel<2> (level 0, 640x480)", "kernel_us": k_ms * 1e3,
@@ -491,9 +504,33 @@ def ate_rmse(est, gt, align=True):
 
 
 def rot_angle_deg(Ra, Rb):
-    """Angle of Ra^T Rb in degrees."""
-    c = (np.trace(Ra.T @ Rb) - 1.0) / 2.0
-    return float(np.degrees(np.arccos(np.clip(c, -1.0, 1.0))))
+    """Angle of Ra^T Rb in degrees (from the sine and the cosine: accurate for small angles too)."""
+    R = Ra.T @ Rb
+    s = 0.5 * np.linalg.norm([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+    c = (np.trace(R) - 1.0) / 2.0
+    return float(np.degrees(np.arctan2(s, c)))
+
+
+def sequence_accuracy(est, gt, windows=((0, 30), (30, 100), (100, None))):
+    """Tracking accuracy of a sequence against ground truth: the ATE RMSE of the positions (raw and aligned),
+    the largest orientation error, and per window of frames the mean error of the velocity and of the two
+    bias estimates (the analogue of the paper's convergence plots of the IMU states)."""
+    n = len(est)
+    err = {k: np.array([np.linalg.norm(np.asarray(e[k]) - np.asarray(g[k])) for e, g in zip(est, gt)])
+           for k in ("v", "bg", "ba")}
+    R = synth_mod().configs._rot_from_quat
+    rot = [rot_angle_deg(R(g["q"]), R(e["q"])) for e, g in zip(est, gt)]
+    out = {"frames": n, "ate_rmse_m": ate_rmse([e["r"] for e in est], [g["r"] for g in gt], align=False),
+           "ate_rmse_aligned_m": ate_rmse([e["r"] for e in est], [g["r"] for g in gt]),
+           "max_rot_err_deg": float(max(rot)), "windows": []}
+    for a, b in windows:
+        b = n if b is None else min(b, n)
+        if a >= b:
+            continue
+        out["windows"].append({"frames": [a + 1, b], "vel_err_mps": float(err["v"][a:b].mean()),
+                               "bg_err_radps": float(err["bg"][a:b].mean()),
+                               "ba_err_mps2": float(err["ba"][a:b].mean())})
+    return out
 
 
 ROBUST_LOST_M, ROBUST_LOST_DEG = 0.10, 5.0
@@ -652,7 +689,7 @@ def main():
         "config": {"workload": "single-session 640x480 RGB-D-inertial sequence, 3 levels 10/5/4 GN iterations, "
                                "IMU 200 Hz, procedural 3-plane/4-sphere scene", "width": 640, "height": 480,
                    "levels": 3, "iters": [10, 5, 4], "jac_format": "fp32", "frames": args.steps},
-        "latency_ms": g["latency_ms"], "pose_err_final_m": g["pose_err_final_m"],
+        "latency_ms": g["latency_ms"], "pose_err_final_m": g["pose_err_final_m"], "accuracy": g["accuracy"],
         "roofline": g["roofline"], "cpu_baseline": cpu, "serving": serving, "stress": stress,
         "robustness": robust,
     }

@@ -51,3 +51,27 @@ def test_rotation_angle():
     assert abs(bench.rot_angle_deg(np.eye(3), R) - 30.0) < 1e-9
     assert abs(bench.rot_angle_deg(R, R)) < 1e-6
     assert abs(bench.rot_angle_deg(np.eye(3), _rot([1, 1, 0], 179.0)) - 179.0) < 1e-6
+
+
+def test_sequence_accuracy_windows():
+    rng = np.random.default_rng(11)
+    gt = []
+    for k in range(50):
+        q = rng.normal(size=4)
+        gt.append({"r": rng.normal(size=3), "q": q / np.linalg.norm(q), "v": rng.normal(size=3),
+                   "bg": rng.normal(size=3) * 1e-3, "ba": rng.normal(size=3) * 1e-2})
+    est = [dict(g) for g in gt]
+    a = bench.sequence_accuracy(est, gt, windows=((0, 10), (10, None)))
+    assert a["frames"] == 50 and a["ate_rmse_m"] == 0.0 and a["max_rot_err_deg"] < 1e-6
+    assert [w["frames"] for w in a["windows"]] == [[1, 10], [11, 50]]
+    assert all(w["vel_err_mps"] == 0.0 and w["bg_err_radps"] == 0.0 for w in a["windows"])
+    # a velocity error of 0.3 m/s on the first 10 frames only, a gyro bias error of 1e-4 on the rest
+    for k in range(50):
+        est[k] = dict(gt[k])
+        if k < 10:
+            est[k]["v"] = gt[k]["v"] + np.array([0.0, 0.3, 0.0])
+        else:
+            est[k]["bg"] = gt[k]["bg"] + np.array([1e-4, 0.0, 0.0])
+    a = bench.sequence_accuracy(est, gt, windows=((0, 10), (10, None)))
+    assert abs(a["windows"][0]["vel_err_mps"] - 0.3) < 1e-12 and a["windows"][1]["vel_err_mps"] == 0.0
+    assert a["windows"][0]["bg_err_radps"] == 0.0 and abs(a["windows"][1]["bg_err_radps"] - 1e-4) < 1e-15
