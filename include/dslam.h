@@ -292,6 +292,77 @@ dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const u
  * T_WM. */
 dslam_status dslam_track_frame_input(dslam_session* s, const dslam_frame_input* in, void* stream);
 
+/* Surfel map: the dense model the tracker aligns to (the mapping step the
+ * paper keeps from its RGB-D base system, Sections III and V).  A map holds
+ * up to `capacity` surfels (world position, unit normal, intensity, radius,
+ * confidence) for one camera; dslam_map_fuse adds a tracked frame to it and
+ * dslam_map_predict renders the model view the next frame is tracked
+ * against.  All of the map's memory is allocated at creation and counted
+ * against the context's budget (NO_CAPACITY).  Calls on one map are ordered
+ * by the caller's stream; the map's arrays are reproducible bit for bit (the
+ * float32 operations are fixed and every surfel is written by at most one
+ * thread per call). */
+typedef struct dslam_map dslam_map;
+
+typedef struct {
+  int32_t capacity;  /* surfels, >= 1 */
+  float assoc_dist;  /* metres: a frame pixel joins the surfel of its cell when their depths differ by at most this */
+  float assoc_cos;   /* ... and the cosine between their world normals is at least this, in [-1, 1] */
+  float render_band; /* metres, >= 0: surfels this far behind a pixel's nearest one still count as its front
+                        surface, of which the most central is shown */
+} dslam_map_params;
+
+/* Field indices of dslam_map_copy. */
+enum {
+  DSLAM_MAP_PX = 0, DSLAM_MAP_PY, DSLAM_MAP_PZ, DSLAM_MAP_NX, DSLAM_MAP_NY, DSLAM_MAP_NZ,
+  DSLAM_MAP_INTENSITY, DSLAM_MAP_RADIUS, DSLAM_MAP_CONFIDENCE
+};
+
+/* Create an empty map for `cam` (level-0 intrinsics; sessions that fuse into
+ * or predict from it must use the same camera and context).  Errors:
+ * INVALID (arguments), NO_CAPACITY (budget or allocation), DEVICE. */
+dslam_status dslam_map_create(dslam_context* ctx, const dslam_camera* cam, const dslam_map_params* p,
+                              dslam_map** out);
+/* Wait for the map's work and free it. */
+dslam_status dslam_map_destroy(dslam_map* m);
+/* Empty the map (asynchronous on `stream`). */
+dslam_status dslam_map_reset(dslam_map* m, void* stream);
+/* Fuse the session's current frame (level 0 of its CURRENT pyramid, i.e. the
+ * frame last tracked or built) into the map at its pose T_WC (camera to world,
+ * 4x4 row-major, host): each surfel in front of the camera marks the pixel of
+ * its projected centre (nearest, then lowest index); a valid pixel (level-0
+ * depth, and the normal of its parent pixel at level 1 of a deeper pyramid)
+ * whose cell
+ * holds a surfel within assoc_dist in depth and assoc_cos in normal updates it
+ * with confidence-weighted averages (pixel weight 1 / (1 + g^2), g the
+ * distance from the image centre relative to the centre's own distance from
+ * the corner); every other valid pixel becomes a new surfel, appended in
+ * pixel order while the capacity lasts (the rest are counted as dropped).
+ * Asynchronous on `stream`.  Errors: INVALID (arguments, camera mismatch),
+ * DEVICE. */
+dslam_status dslam_map_fuse(dslam_map* m, dslam_session* s, const double T_WC[16], void* stream);
+/* Predict the model view at T_WM (4x4 row-major, host) by splatting the
+ * surfels (each covers the pixels of its disk; of the surfels within
+ * render_band of a pixel's nearest, the one whose centre projects closest to
+ * the pixel is shown) and build the
+ * session's MODEL pyramid from it, as dslam_build_pyramid(MODEL) would from
+ * caller images, except that its level-0 normals are the shown surfels'
+ * (camera frame; zero where no surfel covers the pixel).  Asynchronous on
+ * `stream`.  Errors as dslam_map_fuse. */
+dslam_status dslam_map_predict(dslam_map* m, dslam_session* s, const double T_WM[16], void* stream);
+/* The same prediction into caller device images (height x width, pitch =
+ * width): depth in metres (0 where no surfel covers the pixel) and intensity.
+ * Asynchronous on `stream`. */
+dslam_status dslam_map_render(dslam_map* m, const double T_WM[16], float* depth_dev, uint8_t* intensity_dev,
+                              void* stream);
+/* Wait for the map's last call and read its surfel count and the number of
+ * new surfels dropped so far for lack of capacity (nullable). */
+dslam_status dslam_map_count(dslam_map* m, int32_t* count, int32_t* dropped);
+/* Wait for the map's last call and copy one field (DSLAM_MAP_*) of its
+ * surfels, in index order, to host memory (at most max_surfels floats;
+ * INVALID if the map holds more). */
+dslam_status dslam_map_copy(dslam_map* m, int32_t field, float* host_out, int32_t max_surfels);
+
 /* Wait for the session's last tracked frame and copy its result to host memory. */
 dslam_status dslam_session_result(dslam_session* s, dslam_track_result* out);
 

@@ -22,7 +22,11 @@ operations in the same order):
   its projected centre with the key (bits(q_z) << 32) | index; the smallest
   key wins (the nearest surfel, then the lowest index);
 * fusion of pixel u with a valid depth and normal: the measurement
-  p_m = camera-to-world(V(u)), n_m = rotated N(u), I_m = I(u), weight
+  p_m = camera-to-world(V(u)) from the frame's level-0 vertex, n_m = the
+  rotated normal of its parent pixel (u >> 1) at level 1 of the frame's
+  pyramid (level 0 for a one-level pyramid: forward differences of the raw
+  depth are dominated by its noise at full resolution, while the level-1
+  normal averages 2x2 depths over twice the baseline), I_m = I(u), weight
   alpha = 1 / (1 + g2) with g2 = ((i - cx)^2 + (j - cy)^2) / (cx^2 + cy^2)
   (down-weighting the image periphery), radius
   r_m = (z sqrt2) / (fx max(|N_z|, 0.5)).  It updates the surfel of its index
@@ -37,9 +41,18 @@ operations in the same order):
   rounded centre; a pixel's ray d = ((i - cx) / fx, (j - cy) / fy, 1) meets the
   surfel's plane at depth t = (n_c . q) / (n_c . d) (dot products summed as
   (x + y) + z, n_c the camera-frame normal, |n_c . d| > 1e-6); the pixel is
-  covered when t > 0 and |t d - q|^2 <= r^2, with the key
-  (bits(t) << 32) | index, smallest wins.  The rendered depth is t, the
-  intensity the surfel's, rounded half-even and clamped to [0, 255].
+  covered when t > 0 and |t d - q|^2 <= r^2.  Of the surfels covering a
+  pixel, those within `band` metres of the nearest one (t <= t_min + band)
+  form its front surface, and the one whose projected centre (u, v) is
+  closest to the pixel, d2 = (i - u)^2 + (j - v)^2, wins (then the lowest
+  index): taking the nearest depth alone would pick, of several noisy
+  observations of one surface, the one nearest the camera.  The rendered
+  depth is the winner's t, the intensity the winner's, rounded half-even and
+  clamped to [0, 255], and the normal the winner's camera-frame normal n_c
+  (zero where no surfel covers the pixel).  The model view's level-0 normals
+  are these surfel normals, averaged over the frames fused into each surfel,
+  rather than forward differences of the rendered depth, which carry the
+  depth noise of the frames the surfels came from.
 """
 from __future__ import annotations
 
@@ -50,6 +63,17 @@ EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
 HMAX = 4
 FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "inten", "radius", "conf")
 SQRT2 = F(1.41421356)
+
+
+def fusion_normals(levels: list) -> np.ndarray:
+    """(H, W, 3) normals the fusion uses: level 1's normal of each level-0 pixel's parent (u >> 1), or
+    level 0's own for a one-level pyramid (levels: the frame's pyramid, oracle.pyramid.build)."""
+    if len(levels) < 2:
+        return levels[0]["N"]
+    N1 = levels[1]["N"]
+    H, W = levels[0]["V"].shape[:2]
+    jj, ii = np.meshgrid(np.arange(H) >> 1, np.arange(W) >> 1, indexing="ij")
+    return N1[jj, ii]
 
 
 def empty_map() -> dict:
@@ -110,8 +134,9 @@ def index_map(m: dict, D_cw, t_cw, cam, W: int, H: int) -> np.ndarray:
 
 
 def fuse(m: dict, V, N, I16, T_WC, cam, W: int, H: int, capacity: int, dist=0.05, cos_min=0.8):
-    """The map after fusing one frame: V, N (H, W, 3) camera-frame vertices and normals of the frame's
-    level 0 (float32), I16 its fixed-point intensity plane (value * 64, uint16), T_WC the frame's pose,
+    """The map after fusing one frame: V (H, W, 3) camera-frame vertices of the frame's level 0, N its
+    fusion normals (fusion_normals), I16 its fixed-point intensity plane (value * 64, uint16), T_WC the
+    frame's pose,
     cam (fx, fy, cx, cy).  Returns (new map, number of new surfels dropped for lack of capacity)."""
     D_wc, t_wc, D_cw, t_cw = transforms(T_WC)
     key = index_map(m, D_cw, t_cw, cam, W, H).ravel()
@@ -161,50 +186,77 @@ def fuse(m: dict, V, N, I16, T_WC, cam, W: int, H: int, capacity: int, dist=0.05
     return out, dropped
 
 
-def render(m: dict, T_WM, cam, W: int, H: int):
-    """Predicted model view at pose T_WM: (depth float32 (H, W), intensity uint8 (H, W))."""
+def render(m: dict, T_WM, cam, W: int, H: int, band=0.03, with_normals=False):
+    """Predicted model view at pose T_WM: (depth float32 (H, W), intensity uint8 (H, W)), and with
+    with_normals the (H, W, 3) float32 camera-frame normals as a third element."""
     _, _, D_cw, t_cw = transforms(T_WM)
-    zbuf = np.full(H * W, EMPTY, dtype=np.uint64)
-    n = len(m["px"])
-    if n:
-        fx, fy, cx, cy = F(cam[0]), F(cam[1]), F(cam[2]), F(cam[3])
-        qx, qy, qz = _xform(D_cw, t_cw, m["px"], m["py"], m["pz"])
-        ncx, ncy, ncz = _rotate(D_cw, m["nx"], m["ny"], m["nz"])
-        u, v = _project(qx, qy, qz, cam)
-        with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
-            front = qz > 0
-            u0 = np.where(front, np.rint(u), F(-1e9)).astype(np.float32)
-            v0 = np.where(front, np.rint(v), F(-1e9)).astype(np.float32)
-            rp = ((m["radius"] * fx) / qz).astype(np.float32)
-            h = np.where(front, np.minimum(np.ceil(rp), F(HMAX)), F(-1)).astype(np.float32)
-        r2 = (m["radius"] * m["radius"]).astype(np.float32)
-        # centres far outside the image cover nothing: keep the integer pixel arithmetic in range
-        inb = front & (u0 >= F(-HMAX)) & (u0 <= F(W - 1 + HMAX)) & (v0 >= F(-HMAX)) & (v0 <= F(H - 1 + HMAX))
-        s_all = np.nonzero(inb)[0]
-        ui, vi, hi = u0[s_all].astype(np.int64), v0[s_all].astype(np.int64), h[s_all].astype(np.int64)
-        for dv in range(-HMAX, HMAX + 1):
-            for du in range(-HMAX, HMAX + 1):
-                sel = (np.abs(du) <= hi) & (np.abs(dv) <= hi)
-                i, j = ui[sel] + du, vi[sel] + dv
-                inimg = (i >= 0) & (i < W) & (j >= 0) & (j < H)
-                s = s_all[sel][inimg]
-                i, j = i[inimg], j[inimg]
-                dxr = ((i.astype(np.float32) - cx) / fx).astype(np.float32)
-                dyr = ((j.astype(np.float32) - cy) / fy).astype(np.float32)
-                den = ((ncx[s] * dxr + ncy[s] * dyr) + ncz[s]).astype(np.float32)
-                num = ((ncx[s] * qx[s] + ncy[s] * qy[s]) + ncz[s] * qz[s]).astype(np.float32)
-                with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
-                    t = (num / den).astype(np.float32)
-                    ex = ((t * dxr) - qx[s]).astype(np.float32)
-                    ey = ((t * dyr) - qy[s]).astype(np.float32)
-                    ez = (t - qz[s]).astype(np.float32)
-                    d2 = ((ex * ex + ey * ey) + ez * ez).astype(np.float32)
-                    hit = (np.abs(den) > F(1e-6)) & (t > 0) & (d2 <= r2[s])
-                np.minimum.at(zbuf, j[hit] * W + i[hit], _keys(t[hit], s[hit]))
-    has = zbuf != EMPTY
-    depth = np.zeros(H * W, dtype=np.float32)
-    depth[has] = (zbuf[has] >> np.uint64(32)).astype(np.uint32).view(np.float32)
-    inten = np.zeros(H * W, dtype=np.uint8)
-    si = (zbuf[has] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    npx = H * W
+    zmin = np.full(npx, np.inf, dtype=np.float32)
+    best = np.full(npx, EMPTY, dtype=np.uint64)
+    depth = np.zeros(npx, dtype=np.float32)
+    inten = np.zeros(npx, dtype=np.uint8)
+    nrm = np.zeros((npx, 3), dtype=np.float32)
+    if len(m["px"]) == 0:
+        out = (depth.reshape(H, W), inten.reshape(H, W))
+        return out + (nrm.reshape(H, W, 3),) if with_normals else out
+    cands = list(_splat_candidates(m, D_cw, t_cw, cam, W, H))
+    for pix, s, t, d2c in cands:  # pass 1: the nearest depth of each pixel
+        np.minimum.at(zmin, pix, t)
+    bandf = F(band)
+    for pix, s, t, d2c in cands:  # pass 2: the front surface's most central surfel
+        front = t <= (zmin[pix] + bandf).astype(np.float32)
+        np.minimum.at(best, pix[front], _keys(d2c[front], s[front]))
+    for pix, s, t, d2c in cands:  # the winner's own depth
+        win = best[pix] == _keys(d2c, s)
+        depth[pix[win]] = t[win]
+    has = best != EMPTY
+    si = (best[has] & np.uint64(0xFFFFFFFF)).astype(np.int64)
     inten[has] = np.clip(np.rint(m["inten"][si]), F(0), F(255)).astype(np.uint8)
-    return depth.reshape(H, W), inten.reshape(H, W)
+    if not with_normals:
+        return depth.reshape(H, W), inten.reshape(H, W)
+    ncx, ncy, ncz = _rotate(D_cw, m["nx"][si], m["ny"][si], m["nz"][si])
+    nrm[has] = np.stack([ncx, ncy, ncz], axis=1)
+    return depth.reshape(H, W), inten.reshape(H, W), nrm.reshape(H, W, 3)
+
+
+def _splat_candidates(m, D_cw, t_cw, cam, W, H):
+    """(pixel, surfel, depth t, squared centre distance) of every pixel a surfel's disk covers, in
+    batches by footprint offset."""
+    fx, fy, cx, cy = F(cam[0]), F(cam[1]), F(cam[2]), F(cam[3])
+    qx, qy, qz = _xform(D_cw, t_cw, m["px"], m["py"], m["pz"])
+    ncx, ncy, ncz = _rotate(D_cw, m["nx"], m["ny"], m["nz"])
+    u, v = _project(qx, qy, qz, cam)
+    with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+        front = qz > 0
+        u0 = np.where(front, np.rint(u), F(-1e9)).astype(np.float32)
+        v0 = np.where(front, np.rint(v), F(-1e9)).astype(np.float32)
+        rp = ((m["radius"] * fx) / qz).astype(np.float32)
+        h = np.where(front, np.minimum(np.ceil(rp), F(HMAX)), F(-1)).astype(np.float32)
+    r2 = (m["radius"] * m["radius"]).astype(np.float32)
+    # centres far outside the image cover nothing: keep the integer pixel arithmetic in range
+    inb = front & (u0 >= F(-HMAX)) & (u0 <= F(W - 1 + HMAX)) & (v0 >= F(-HMAX)) & (v0 <= F(H - 1 + HMAX))
+    s_all = np.nonzero(inb)[0]
+    ui, vi, hi = u0[s_all].astype(np.int64), v0[s_all].astype(np.int64), h[s_all].astype(np.int64)
+    for dv in range(-HMAX, HMAX + 1):
+        for du in range(-HMAX, HMAX + 1):
+            sel = (np.abs(du) <= hi) & (np.abs(dv) <= hi)
+            i, j = ui[sel] + du, vi[sel] + dv
+            inimg = (i >= 0) & (i < W) & (j >= 0) & (j < H)
+            s = s_all[sel][inimg]
+            i, j = i[inimg], j[inimg]
+            fi, fj = i.astype(np.float32), j.astype(np.float32)
+            dxr = ((fi - cx) / fx).astype(np.float32)
+            dyr = ((fj - cy) / fy).astype(np.float32)
+            den = ((ncx[s] * dxr + ncy[s] * dyr) + ncz[s]).astype(np.float32)
+            num = ((ncx[s] * qx[s] + ncy[s] * qy[s]) + ncz[s] * qz[s]).astype(np.float32)
+            with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+                t = (num / den).astype(np.float32)
+                ex = ((t * dxr) - qx[s]).astype(np.float32)
+                ey = ((t * dyr) - qy[s]).astype(np.float32)
+                ez = (t - qz[s]).astype(np.float32)
+                d2 = ((ex * ex + ey * ey) + ez * ez).astype(np.float32)
+                hit = (np.abs(den) > F(1e-6)) & (t > 0) & (d2 <= r2[s])
+            eu = (fi - u[s]).astype(np.float32)
+            ev = (fj - v[s]).astype(np.float32)
+            d2c = (eu * eu + ev * ev).astype(np.float32)
+            yield (j[hit] * W + i[hit]), s[hit], t[hit], d2c[hit]

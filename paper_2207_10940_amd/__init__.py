@@ -15,7 +15,7 @@ from . import _abi
 from ._abi import (CH_GX, CH_GY, CH_I, CH_NX, CH_NY, CH_NZ, CH_VX, CH_VY, CH_VZ, JAC_BF16, JAC_FP16, JAC_FP32,
                    JAC_FP32_MFMA, MODE_GYRO, MODE_RGBD, MODE_RGBDI, PYR_CURRENT, PYR_MODEL)
 
-__all__ = ["DslamError", "Context", "Session", "Batch", "Server", "frame_input", "preintegrate_imu", "solve_step", "track_params", "imu_params",
+__all__ = ["DslamError", "Context", "Session", "Map", "Batch", "Server", "frame_input", "preintegrate_imu", "solve_step", "track_params", "imu_params",
            "camera", "state_struct", "state_dict", "prior_struct", "prior_dict", "lib"]
 
 MODES = {"rgbdi": MODE_RGBDI, "rgbd": MODE_RGBD, "gyro": MODE_GYRO}
@@ -326,6 +326,64 @@ def frame_input(f: dict):
         fi.imu, fi.n_imu = arr, cnt
     fi.t0, fi.t1 = float(f.get("t0", 0.0)), float(f.get("t1", 0.0))
     return fi, (arr, f)
+
+
+MAP_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "inten", "radius", "conf")
+
+
+class Map:
+    """Surfel map of one camera (dslam_map_*): fusion of tracked frames and model-view prediction."""
+
+    def __init__(self, ctx: Context, cam, capacity: int, assoc_dist: float = 0.05, assoc_cos: float = 0.8,
+                 render_band: float = 0.03):
+        self.cam = camera(cam) if not isinstance(cam, _abi.Camera) else cam
+        prm = _abi.MapParams(int(capacity), float(assoc_dist), float(assoc_cos), float(render_band))
+        h = C.c_void_p()
+        _check(lib().dslam_map_create(ctx.handle, C.byref(self.cam), C.byref(prm), C.byref(h)), "dslam_map_create")
+        self.handle = h
+        self.capacity = int(capacity)
+
+    def close(self):
+        if self.handle:
+            _check(lib().dslam_map_destroy(self.handle), "dslam_map_destroy")
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self, stream=None):
+        _check(lib().dslam_map_reset(self.handle, _stream_ptr(stream)), "dslam_map_reset")
+
+    def fuse(self, session: "Session", T_WC, stream=None):
+        T, Tp = _dptr(np.asarray(T_WC).ravel())
+        _check(lib().dslam_map_fuse(self.handle, session.handle, Tp, _stream_ptr(stream)), "dslam_map_fuse")
+
+    def predict(self, session: "Session", T_WM, stream=None):
+        T, Tp = _dptr(np.asarray(T_WM).ravel())
+        _check(lib().dslam_map_predict(self.handle, session.handle, Tp, _stream_ptr(stream)), "dslam_map_predict")
+
+    def render(self, T_WM, depth, intensity, stream=None):
+        assert depth.is_cuda and intensity.is_cuda and depth.is_contiguous() and intensity.is_contiguous()
+        T, Tp = _dptr(np.asarray(T_WM).ravel())
+        _check(lib().dslam_map_render(self.handle, Tp, C.c_void_p(depth.data_ptr()), C.c_void_p(intensity.data_ptr()),
+                                      _stream_ptr(stream)), "dslam_map_render")
+
+    def count(self):
+        n, d = C.c_int32(), C.c_int32()
+        _check(lib().dslam_map_count(self.handle, C.byref(n), C.byref(d)), "dslam_map_count")
+        return int(n.value), int(d.value)
+
+    def arrays(self) -> dict:
+        n, _ = self.count()
+        out = {}
+        for k, name in enumerate(MAP_FIELDS):
+            a = np.empty(n, dtype=np.float32)
+            _check(lib().dslam_map_copy(self.handle, k, a.ctypes.data_as(C.POINTER(C.c_float)), n), "dslam_map_copy")
+            out[name] = a
+        return out
 
 
 class Batch:

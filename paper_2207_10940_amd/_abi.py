@@ -92,6 +92,11 @@ vp = C.c_void_p
 dp = P(C.c_double)
 fp = P(C.c_float)
 
+class MapParams(C.Structure):
+    _fields_ = [("capacity", C.c_int32), ("assoc_dist", C.c_float), ("assoc_cos", C.c_float),
+                ("render_band", C.c_float)]
+
+
 SIGNATURES = {
     "dslam_status_string": (C.c_char_p, [C.c_int]),
     "dslam_build_info": (C.c_char_p, []),
@@ -129,6 +134,14 @@ SIGNATURES = {
     "dslam_server_poll": (C.c_int, [vp, C.c_int32, P(RequestDone), C.c_int32, P(C.c_int32)]),
     "dslam_server_counts": (C.c_int, [vp, P(C.c_int32), P(C.c_int32)]),
     "dslam_server_clock": (C.c_double, []),
+    "dslam_map_create": (C.c_int, [vp, P(Camera), P(MapParams), P(vp)]),
+    "dslam_map_destroy": (C.c_int, [vp]),
+    "dslam_map_reset": (C.c_int, [vp, vp]),
+    "dslam_map_fuse": (C.c_int, [vp, vp, dp, vp]),
+    "dslam_map_predict": (C.c_int, [vp, vp, dp, vp]),
+    "dslam_map_render": (C.c_int, [vp, dp, vp, vp, vp]),
+    "dslam_map_count": (C.c_int, [vp, P(C.c_int32), P(C.c_int32)]),
+    "dslam_map_copy": (C.c_int, [vp, C.c_int32, fp, C.c_int32]),
 }
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdslam.so")

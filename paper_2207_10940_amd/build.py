@@ -41,6 +41,7 @@ SOURCES = {
     "solve.hip": DEVICE_FP64,
     "dslam.hip": EXACT_FP64,
     "server.hip": EXACT_FP64,
+    "map.hip": EXACT_FP32,
 }
 
 

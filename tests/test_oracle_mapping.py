@@ -15,9 +15,9 @@ CAM = (40.0, 40.0, 24.0, 18.0)  # fx, fy, cx, cy (level 0)
 def _frame(depth, inten=None):
     if inten is None:
         inten = (np.arange(W * H) % 251).reshape(H, W).astype(np.uint8)
-    lev = pyr.build(depth.astype(np.float32), inten, *CAM, 1)[0]
-    I16 = (lev["I"] * np.float32(64.0)).astype(np.uint16)
-    return lev["V"], lev["N"], I16
+    levels = pyr.build(depth.astype(np.float32), inten, *CAM, 2)
+    I16 = (levels[0]["I"] * np.float32(64.0)).astype(np.uint16)
+    return levels[0]["V"], M.fusion_normals(levels), I16
 
 
 def _plane(Z):
@@ -62,6 +62,32 @@ def test_index_map_marks_back_projected_pixels_nearest_then_lowest_index():
     assert (idx != M.EMPTY).sum() == 3
 
 
+def test_fusion_normals_are_the_level1_parents():
+    depth = (2.0 + 0.01 * np.random.default_rng(2).random((H, W))).astype(np.float32)
+    levels = pyr.build(depth, np.zeros((H, W), np.uint8), *CAM, 2)
+    Nf = M.fusion_normals(levels)
+    assert np.array_equal(Nf[7, 9], levels[1]["N"][3, 4]) and np.array_equal(Nf[6, 8], levels[1]["N"][3, 4])
+    assert np.array_equal(M.fusion_normals(levels[:1]), levels[0]["N"])
+
+
+def test_render_front_surface_prefers_the_central_surfel_within_the_band():
+    """Two surfels cover a pixel: one 1 cm nearer but off-centre, one centred.  Within a 3 cm band the
+    centred one wins; with a 5 mm band only the nearer one is in the front surface."""
+    fx, fy, cx, cy = CAM
+    m = M.empty_map()
+    # surfel 0: centred on pixel (20, 15) at 2.00 m; surfel 1: centred one pixel left at 1.99 m
+    pts = [((20 - cx) / fx * 2.0, (15 - cy) / fy * 2.0, 2.0), ((19 - cx) / fx * 1.99, (15 - cy) / fy * 1.99, 1.99)]
+    for k, f in enumerate(("px", "py", "pz")):
+        m[f] = np.array([p[k] for p in pts], dtype=np.float32)
+    for f, vals in (("nx", (0, 0)), ("ny", (0, 0)), ("nz", (1, 1)), ("inten", (10, 200)), ("radius", (0.08, 0.08)),
+                    ("conf", (1, 1))):
+        m[f] = np.array(vals, dtype=np.float32)
+    d, i = M.render(m, np.eye(4), CAM, W, H, band=0.03)
+    assert i[15, 20] == 10 and d[15, 20] == np.float32(2.0)
+    d, i = M.render(m, np.eye(4), CAM, W, H, band=0.005)
+    assert i[15, 20] == 200 and d[15, 20] == np.float32(1.99)
+
+
 def test_plane_renders_its_own_depth_and_intensity():
     V, N, I16 = _frame(_plane(2.0), np.full((H, W), 77, dtype=np.uint8))
     m, _ = M.fuse(M.empty_map(), V, N, I16, np.eye(4), CAM, W, H, capacity=10**6)
@@ -69,6 +95,14 @@ def test_plane_renders_its_own_depth_and_intensity():
     ok = _valid(V, N)
     assert np.all(depth[ok] == np.float32(2.0))
     assert np.all(inten[ok] == 77)
+    _, _, nrm = M.render(m, np.eye(4), CAM, W, H, with_normals=True)
+    assert np.all(nrm[ok] == np.array([0, 0, 1], dtype=np.float32))
+    assert np.all(nrm[depth == 0] == 0)
+    # every pixel of the plane shows its own surfel: the most central of the equally near ones
+    V2, N2, I2 = _frame(_plane(2.0))
+    m2, _ = M.fuse(M.empty_map(), V2, N2, I2, np.eye(4), CAM, W, H, capacity=10**6)
+    _, inten2 = M.render(m2, np.eye(4), CAM, W, H)
+    assert np.array_equal(inten2[ok], (I2[ok] // 64).astype(np.uint8))
     # camera moved 0.25 m towards the plane: depth 1.75 wherever covered, and the centre is covered
     T = np.eye(4)
     T[2, 3] = 0.25
