@@ -511,6 +511,73 @@ def rot_angle_deg(Ra, Rb):
     return float(np.degrees(np.arctan2(s, c)))
 
 
+def run_mapping(args, seq):
+    """Tracking against the fused surfel map on the 640x480 sequence: per frame the model view is predicted
+    from the map at the previous estimate (splat rendering, model pyramid), the frame is tracked, and it
+    is fused into the map at its new estimate.  The loop waits for each frame's pose (the next prediction
+    needs it on the host).  Reports frames/s of the whole loop, the device time of each part (HIP events on
+    the stream), the surfel count and the ATE against the ground truth."""
+    import torch
+
+    import paper_2207_10940_amd as P
+    S = synth_mod()
+    n = min(args.map_frames, seq["n_frames"] - 1)
+    W, H = seq["camera"].width, seq["camera"].height
+    ctx = P.Context(0)
+    tp = P.track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32")
+    sess = P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], seq["prior"])
+    mp = P.Map(ctx, seq["camera"], args.map_capacity)
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    R = S.configs._rot_from_quat
+
+    def pose(x):
+        T = np.eye(4)
+        T[:3, :3], T[:3, 3] = R(x["q"]), x["r"]
+        return T
+
+    sess.build_pyramid(P.PYR_CURRENT, seq["depth"][0].contiguous(), seq["intensity"][0].contiguous(), None, st)
+    prev = pose(seq["x0"])
+    mp.fuse(sess, prev, st)
+    parts = np.zeros(3)
+    est = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for j in range(1, n + 1):
+        t0, t1 = seq["times"][j - 1], seq["times"][j]
+        a, b = S.configs.imu_window(seq["imu"]["t"], t0, t1)
+        imu = {k: v[a:b] for k, v in seq["imu"].items()}
+        ev[0].record(st)
+        mp.predict(sess, prev, st)
+        ev[1].record(st)
+        sess.track_frame(seq["depth"][j].contiguous(), seq["intensity"][j].contiguous(), imu, t0, t1, st)
+        ev[2].record(st)
+        r = sess.result()
+        prev = pose(r["x1"])
+        mp.fuse(sess, prev, st)
+        ev[3].record(st)
+        ev[3].synchronize()
+        parts += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+        est.append(r["x1"])
+    elapsed = time.perf_counter() - t_start
+    count, dropped = mp.count()
+    acc = sequence_accuracy(est, seq["gt"][1:n + 1])
+    mp.close()
+    sess.close()
+    ctx.close()
+    out = {"workload": f"{W}x{H} sequence, {n} frames: predict the model view from the map at the previous "
+                       f"estimate, track (3 levels 10/5/4), fuse at the new estimate",
+           "frames_per_s": n / elapsed, "ms_per_frame": elapsed * 1e3 / n,
+           "device_ms_per_frame": {"predict": parts[0] / n, "track": parts[1] / n, "fuse": parts[2] / n},
+           "surfels": count, "dropped": dropped, "capacity": args.map_capacity,
+           "ate_rmse_m": acc["ate_rmse_m"], "ate_rmse_aligned_m": acc["ate_rmse_aligned_m"],
+           "max_rot_err_deg": acc["max_rot_err_deg"]}
+    log(f"[mapping] {n} frames in {elapsed * 1e3:.1f} ms ({out['frames_per_s']:.0f} frames/s); device ms/frame "
+        f"predict {parts[0] / n:.3f} track {parts[1] / n:.3f} fuse {parts[2] / n:.3f}; {count} surfels; "
+        f"ATE {acc['ate_rmse_m'] * 100:.2f} cm, max rotation error {acc['max_rot_err_deg']:.3f} deg")
+    return out
+
+
 def sequence_accuracy(est, gt, windows=((0, 30), (30, 100), (100, None))):
     """Tracking accuracy of a sequence against ground truth: the ATE RMSE of the positions (raw and aligned),
     the largest orientation error, and per window of frames the mean error of the velocity and of the two
@@ -653,6 +720,9 @@ def main():
     ap.add_argument("--robust-width", type=int, default=320)
     ap.add_argument("--robust-height", type=int, default=240)
     ap.add_argument("--no-robustness", action="store_true")
+    ap.add_argument("--map-frames", type=int, default=299, help="frames of the surfel-map tracking loop")
+    ap.add_argument("--map-capacity", type=int, default=8_000_000)
+    ap.add_argument("--no-mapping", action="store_true")
     ap.add_argument("--robustness-only", action="store_true", help="only run the robustness comparison")
     ap.add_argument("--counters", action="store_true",
                     help="only run the level-0 residual pass and a calibration copy (for rocprofv3 --pmc)")
@@ -677,6 +747,9 @@ def main():
     robust = None
     if not args.no_robustness:
         robust = run_robustness(args)
+    mapping = None
+    if not args.no_mapping:
+        mapping = run_mapping(args, g["seq"])
     cpu = None
     if not args.no_cpu_baseline and args.cpu_frames > 0:
         t = time.time()
@@ -691,7 +764,7 @@ def main():
                    "levels": 3, "iters": [10, 5, 4], "jac_format": "fp32", "frames": args.steps},
         "latency_ms": g["latency_ms"], "pose_err_final_m": g["pose_err_final_m"], "accuracy": g["accuracy"],
         "roofline": g["roofline"], "cpu_baseline": cpu, "serving": serving, "stress": stress,
-        "robustness": robust,
+        "robustness": robust, "mapping": mapping,
     }
     print(json.dumps(out), flush=True)
 

@@ -336,8 +336,10 @@ dslam_status dslam_map_reset(dslam_map* m, void* stream);
  * holds a surfel within assoc_dist in depth and assoc_cos in normal updates it
  * with confidence-weighted averages (pixel weight 1 / (1 + g^2), g the
  * distance from the image centre relative to the centre's own distance from
- * the corner); every other valid pixel becomes a new surfel, appended in
- * pixel order while the capacity lasts (the rest are counted as dropped).
+ * the corner); every other valid pixel becomes a new surfel unless one of its
+ * 8 neighbouring cells holds a surfel within assoc_dist of its depth,
+ * appended in pixel order while the capacity lasts (the rest are counted as
+ * dropped).
  * Asynchronous on `stream`.  Errors: INVALID (arguments, camera mismatch),
  * DEVICE. */
 dslam_status dslam_map_fuse(dslam_map* m, dslam_session* s, const double T_WC[16], void* stream);

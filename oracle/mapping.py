@@ -33,8 +33,11 @@ operations in the same order):
   map cell when |z_s - z| <= dist and n_s . n_m >= cos_min: c' = c + alpha,
   p' = ((c p) + (alpha p_m)) / c' per component, n' = the normalised
   (c n) + (alpha n_m), I' = ((c I) + (alpha I_m)) / c', r' = min(r, r_m).
-  Every surfel marks one cell, so it is updated by at most one pixel.  Other
-  valid pixels become new surfels (p_m, n_m, I_m, r_m, alpha), appended in
+  Every surfel marks one cell, so it is updated by at most one pixel.  A valid
+  pixel that updates no surfel becomes a new surfel (p_m, n_m, I_m, r_m,
+  alpha) unless one of the 8 neighbouring cells holds a surfel within dist of
+  its depth (the surface is already mapped there: a moving camera leaves
+  cells between projected surfel centres empty); new surfels are appended in
   pixel order after the existing ones while the capacity lasts;
 * prediction (splat rendering) at the model pose: each surfel in front of the
   camera covers the pixels within h = min(ceil((r fx) / q_z), HMAX) of its
@@ -176,7 +179,19 @@ def fuse(m: dict, V, N, I16, T_WC, cam, W: int, H: int, capacity: int, dist=0.05
         out[f][sa[pos]] = (nn[k][pos] / ln[pos]).astype(np.float32)
     out["radius"][sa] = np.minimum(m["radius"][sa], rm[a])
     out["conf"][sa] = c1
-    new = np.nonzero(valid & ~assoc)[0]
+    covered = np.zeros(H * W, dtype=bool)
+    zk = (key >> np.uint64(32)).astype(np.uint32).view(np.float32)
+    jj2, ii2 = jj.ravel(), ii.ravel()
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            if di == 0 and dj == 0:
+                continue
+            i2, j2 = ii2 + di, jj2 + dj
+            inimg = (i2 >= 0) & (i2 < W) & (j2 >= 0) & (j2 < H)
+            q = np.where(inimg, j2 * W + i2, 0)
+            near = inimg & (key[q] != EMPTY) & (np.abs((zk[q] - Vz).astype(np.float32)) <= F(dist))
+            covered |= near
+    new = np.nonzero(valid & ~assoc & ~covered)[0]
     room = max(0, capacity - len(m["px"]))
     dropped = max(0, len(new) - room)
     new = new[:room]

@@ -18,8 +18,12 @@
 //     normalised (c n) + (alpha n_m), I' likewise, r' = min(r, r_m),
 //     alpha = 1 / (1 + g2), g2 = ((i - cx)^2 + (j - cy)^2) / (cx^2 + cy^2),
 //     r_m = (z sqrt2) / (fx max(|N_z|, 0.5)); every other valid pixel becomes
-//     a new surfel, appended in pixel order while the capacity lasts (each
-//     surfel marks one cell, so at most one pixel updates it: no races);
+//     a new surfel unless one of its 8 neighbouring cells holds a surfel
+//     within dist of its depth (the surface is mapped there already: a moving
+//     camera leaves cells between projected centres empty), appended in pixel
+//     order while the capacity lasts (each surfel marks one cell, so at most
+//     one pixel updates it, and the neighbour test reads only the index map:
+//     no races);
 //   * prediction: each surfel covers the pixels within
 //     h = min(ceil((r fx) / q_z), 4) of its rounded centre whose ray meets
 //     its disk (depth t = (n_c . q) / (n_c . d), |t d - q|^2 <= r^2); of the
@@ -203,7 +207,19 @@ __global__ __launch_bounds__(256) void map_fuse_kernel(MapDev m, MapFrame fr, Xf
           m.f[MAP_C][s] = c1;
         }
       }
-      isnew = (a.valid && !assoc) ? 1 : 0;
+      bool covered = false;
+      if (a.valid && !assoc) {  // a mapped neighbour cell at this depth
+        const int j = p / cam.W, i = p - j * cam.W;
+        const float z = fr.L0.V[2][p];
+        for (int dj = -1; dj <= 1; ++dj)
+          for (int di = -1; di <= 1; ++di) {
+            const int i2 = i + di, j2 = j + dj;
+            if ((di == 0 && dj == 0) || i2 < 0 || i2 >= cam.W || j2 < 0 || j2 >= cam.H) continue;
+            const uint64_t k2 = keys[j2 * cam.W + i2];
+            if (k2 != MAP_EMPTY && fabsf(__uint_as_float((uint32_t)(k2 >> 32)) - z) <= dist) covered = true;
+          }
+      }
+      isnew = (a.valid && !assoc && !covered) ? 1 : 0;
       flags[p] = (uint8_t)isnew;
     }
     int t;

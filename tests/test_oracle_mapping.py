@@ -132,6 +132,21 @@ def test_repeated_and_offset_observations_average_with_their_weights():
     assert len(m4["px"]) == 2 * n1 and np.array_equal(m4["pz"][:n1], m1["pz"])
 
 
+def test_cells_next_to_mapped_ones_add_no_surfels():
+    """A plane mapped at 2.0 m and seen again from 1.9 m: the surfel centres spread out and leave empty
+    cells between them, but each has a mapped neighbour at the plane's depth, so nothing is added."""
+    V, N, I16 = _frame(_plane(2.0))
+    m1, _ = M.fuse(M.empty_map(), V, N, I16, np.eye(4), CAM, W, H, capacity=10**6)
+    T = np.eye(4)
+    T[2, 3] = 0.1
+    V2, N2, I2 = _frame(_plane(1.9))
+    _, _, D_cw, t_cw = M.transforms(T)
+    empty = M.index_map(m1, D_cw, t_cw, CAM, W, H) == M.EMPTY
+    assert empty[2:-2, 2:-2].sum() > 20  # interior cells with no surfel centre
+    m2, _ = M.fuse(m1, V2, N2, I2, T, CAM, W, H, capacity=10**6)
+    assert len(m2["px"]) == len(m1["px"])
+
+
 def test_weight_and_radius_closed_forms():
     V, N, I16 = _frame(_plane(3.0))
     m, _ = M.fuse(M.empty_map(), V, N, I16, np.eye(4), CAM, W, H, capacity=10**6)
