@@ -1,0 +1,114 @@
+"""Pins of the deformation-graph oracle (Section V, eqs. (10)-(17)): the
+analytic Jacobians against central differences, the identity as the exact
+minimiser of consistent zero-motion constraints, exact recovery of a rigid
+motion about gravity (every term vanishes), the gravity term resisting a
+tilt, influence weights, and a monotone energy decrease."""
+import numpy as np
+import pytest
+
+from oracle import deformation as D
+
+
+def _grid_nodes(n_side=3, spacing=0.5):
+    g = np.arange(n_side) * spacing
+    return np.array([[x, y, z] for x in g for y in g for z in g[:2]], dtype=np.float64)
+
+
+def _rot(axis, deg):
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    t = np.radians(deg)
+    return np.eye(3) + np.sin(t) * K + (1 - np.cos(t)) * K @ K
+
+
+def _rigid_params(prob, R, t):
+    """Node parameters of the rigid motion v -> R v + t: A_l = R, t_l = R g_l + t - g_l."""
+    x = np.zeros(12 * len(prob["nodes"]))
+    for l, g in enumerate(prob["nodes"]):
+        x[12 * l:12 * l + 9] = R.ravel()
+        x[12 * l + 9:12 * l + 12] = R @ g + t - g
+    return x
+
+
+def test_influence_weights():
+    nodes = _grid_nodes()
+    v = nodes[4] + np.array([0.01, 0.02, 0.0])
+    idx, w = D.influence(nodes, v)
+    assert len(idx) == D.K_NEAREST and abs(w.sum() - 1.0) < 1e-15 and np.all(w >= 0)
+    assert idx[0] == 4 and w[0] == w.max()       # the nearest node weighs most
+    # a point exactly on a node, with the (K+1)-th neighbour at the lattice spacing
+    idx, w = D.influence(nodes, nodes[0])
+    assert idx[0] == 0
+
+
+def test_jacobians_match_central_differences():
+    rng = np.random.default_rng(1)
+    nodes = _grid_nodes()
+    src = nodes[rng.integers(0, len(nodes), 6)] + rng.normal(size=(6, 3)) * 0.05
+    prob = D.problem(nodes, con=[(s, s + rng.normal(size=3) * 0.05) for s in src],
+                     pin=list(nodes[:3] + 0.1), rel=[(src[0], src[1])], global_=True)
+    x = D.identity_params(len(nodes)) + rng.normal(size=12 * len(nodes)) * 0.05
+    terms = D.residuals(x, prob)
+    h = 1e-6
+    for k in rng.integers(0, len(x), 25):
+        xp, xm = x.copy(), x.copy()
+        xp[k] += h
+        xm[k] -= h
+        for (w, r, J), (_, rp, _), (_, rm, _) in zip(terms, D.residuals(xp, prob), D.residuals(xm, prob)):
+            assert np.allclose((rp - rm) / (2 * h), J[:, k], atol=1e-8)
+
+
+def test_identity_is_the_minimiser_of_zero_motion():
+    nodes = _grid_nodes()
+    pts = nodes[::3] + 0.03
+    prob = D.problem(nodes, con=[(p, p) for p in pts], pin=list(nodes[1::4] - 0.02))
+    x = D.solve(prob, iters=3)
+    assert np.abs(x - D.identity_params(len(nodes))).max() < 1e-12
+    assert D.energy(x, prob) < 1e-24
+
+
+def test_rigid_motion_about_gravity_is_recovered_exactly():
+    nodes = _grid_nodes()
+    rng = np.random.default_rng(3)
+    R, t = _rot([0, 0, 1], 4.0), np.array([0.05, -0.03, 0.02])  # yaw: the gravity term allows it
+    src = nodes + rng.normal(size=nodes.shape) * 0.1
+    prob = D.problem(nodes, con=[(s, R @ s + t) for s in src])
+    x_star = _rigid_params(prob, R, t)
+    assert D.energy(x_star, prob) < 1e-20  # every term vanishes
+    x = D.solve(prob, iters=6)
+    assert np.abs(x - x_star).max() < 1e-9
+    for s in src[:5]:
+        assert np.abs(D.deform(x, prob, s) - (R @ s + t)).max() < 1e-9
+
+
+def test_gravity_term_resists_a_tilt(monkeypatch):
+    nodes = _grid_nodes()
+    rng = np.random.default_rng(4)
+    R, t = _rot([1, 0, 0], 3.0), np.zeros(3)  # a tilt: R g != g
+    src = nodes + rng.normal(size=nodes.shape) * 0.1
+    prob = D.problem(nodes, con=[(s, R @ s + t) for s in src])
+    g = prob["g_W"]
+    x = D.solve(prob, iters=6)
+    A = x.reshape(-1, 12)[:, :9].reshape(-1, 3, 3)
+    tilt = max(np.linalg.norm(a @ g - g) for a in A)
+    assert tilt < np.linalg.norm(R @ g - g)  # less tilted than the constraints ask
+    assert D.energy(x, prob) < D.energy(_rigid_params(prob, R, t), prob)
+    # without the gravity term the tilt is taken in full
+    monkeypatch.setattr(D, "W_IMU", 0.0)
+    x0 = D.solve(prob, iters=6)
+    assert np.abs(x0 - _rigid_params(prob, R, t)).max() < 1e-9
+
+
+def test_energy_decreases_over_gauss_newton_steps():
+    nodes = _grid_nodes()
+    rng = np.random.default_rng(5)
+    src = nodes[rng.integers(0, len(nodes), 10)] + rng.normal(size=(10, 3)) * 0.1
+    prob = D.problem(nodes, con=[(s, s + np.array([0.1, 0.0, 0.05]) + rng.normal(size=3) * 0.02) for s in src],
+                     pin=list(nodes[-4:]))
+    x = D.identity_params(len(nodes))
+    e = [D.energy(x, prob)]
+    for _ in range(4):
+        x = D.solve(prob, iters=1, x0=x)
+        e.append(D.energy(x, prob))
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(e, e[1:])) and e[-1] < e[0]
