@@ -365,6 +365,47 @@ dslam_status dslam_map_count(dslam_map* m, int32_t* count, int32_t* dropped);
  * INVALID if the map holds more). */
 dslam_status dslam_map_copy(dslam_map* m, int32_t field, float* host_out, int32_t max_surfels);
 
+/* Deformation graph with the gravity term (Section V, eqs. (10)-(17)): the
+ * non-rigid correction the paper applies to its map on a loop closure.
+ * Nodes l sit at positions g_l and carry a 3x3 matrix A_l and a translation
+ * t_l; a point v deforms as phi(v) = sum_k w_k (A_k (v - g_k) + g_k + t_k)
+ * over its 4 nearest nodes, w_k = (1 - |v - g_k| / d_max)^2 normalised, d_max
+ * the distance of the 5th nearest.  The cost is
+ * E = 1 E_rot + 10 E_reg + 100 (E_con + E_pin [+ E_rel]) + 100 E_imu with
+ * E_rot = sum |A^T A - I|_F^2, E_reg over each node's 4 nearest other nodes,
+ * E_con = sum |phi(source) - destination|^2, E_pin = sum |phi(d) - d|^2 over
+ * pinned points, E_rel = sum |phi(source) - phi(destination)|^2 over earlier
+ * registrations (global closures only) and E_imu = sum |A g_W - g_W|^2. */
+typedef struct dslam_deform dslam_deform;
+
+typedef struct {
+  int32_t n_nodes;     /* >= 6 */
+  const double* nodes; /* host, 3 per node */
+  int32_t n_con;
+  const double* con;   /* host, source xyz then destination xyz per constraint */
+  int32_t n_pin;
+  const double* pin;   /* host, xyz per pinned point */
+  int32_t n_rel;
+  const double* rel;   /* host, source xyz then destination xyz per earlier registration */
+  int32_t global;      /* 1: global closure (E_rel included), 0: local */
+  double g_W[3];       /* gravity in the vision-world frame */
+} dslam_deform_problem;
+
+/* Allocate a solver for up to max_nodes (6..256) nodes and max_points
+ * constraint points (con + pin + rel) on the context's device (counted
+ * against its budget).  Errors: INVALID, NO_CAPACITY. */
+dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t max_points, dslam_deform** out);
+dslam_status dslam_deform_destroy(dslam_deform* d);
+/* Minimise E by `iters` (1..63) Gauss-Newton steps from A = I, t = 0 on the
+ * device (each step: residuals and Jacobians, the normal equations, a
+ * Cholesky solve) and copy the node parameters to params_out (host, 12 per
+ * node: A row-major, then t) and, if cost_out is not NULL, the cost before
+ * each step (iters values).  Waits for the device.  Errors: INVALID
+ * (arguments, sizes, non-finite input), SINGULAR (the normal equations were
+ * not positive definite: too few constraints), DEVICE. */
+dslam_status dslam_deform_solve(dslam_deform* d, const dslam_deform_problem* p, int32_t iters, double* params_out,
+                                double* cost_out, void* stream);
+
 /* Wait for the session's last tracked frame and copy its result to host memory. */
 dslam_status dslam_session_result(dslam_session* s, dslam_track_result* out);
 

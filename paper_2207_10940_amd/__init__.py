@@ -15,7 +15,7 @@ from . import _abi
 from ._abi import (CH_GX, CH_GY, CH_I, CH_NX, CH_NY, CH_NZ, CH_VX, CH_VY, CH_VZ, JAC_BF16, JAC_FP16, JAC_FP32,
                    JAC_FP32_MFMA, MODE_GYRO, MODE_RGBD, MODE_RGBDI, PYR_CURRENT, PYR_MODEL)
 
-__all__ = ["DslamError", "Context", "Session", "Map", "Batch", "Server", "frame_input", "preintegrate_imu", "solve_step", "track_params", "imu_params",
+__all__ = ["DslamError", "Context", "Session", "Map", "Deform", "Batch", "Server", "frame_input", "preintegrate_imu", "solve_step", "track_params", "imu_params",
            "camera", "state_struct", "state_dict", "prior_struct", "prior_dict", "lib"]
 
 MODES = {"rgbdi": MODE_RGBDI, "rgbd": MODE_RGBD, "gyro": MODE_GYRO}
@@ -384,6 +384,51 @@ class Map:
             _check(lib().dslam_map_copy(self.handle, k, a.ctypes.data_as(C.POINTER(C.c_float)), n), "dslam_map_copy")
             out[name] = a
         return out
+
+
+class Deform:
+    """Deformation-graph solver with the gravity term (dslam_deform_*)."""
+
+    def __init__(self, ctx: Context, max_nodes: int, max_points: int):
+        h = C.c_void_p()
+        _check(lib().dslam_deform_create(ctx.handle, int(max_nodes), int(max_points), C.byref(h)),
+               "dslam_deform_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _check(lib().dslam_deform_destroy(self.handle), "dslam_deform_destroy")
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, nodes, con=(), pin=(), rel=(), g_W=(0.0, 0.0, -9.81), global_=False, iters=5, stream=None):
+        """Node parameters (N x 12: A row-major, t) after `iters` Gauss-Newton steps, and the cost before
+        each step.  con / rel: (source, destination) pairs; pin: points."""
+        keep = []
+
+        def arr(a, width):
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1, width))
+            keep.append(a)
+            return len(a), (a.ctypes.data_as(C.POINTER(C.c_double)) if len(a) else None)
+
+        pr = _abi.DeformProblem()
+        pr.n_nodes, pr.nodes = arr(nodes, 3)
+        pr.n_con, pr.con = arr([np.r_[s, d] for s, d in con] if len(con) else np.zeros((0, 6)), 6)
+        pr.n_pin, pr.pin = arr(pin if len(pin) else np.zeros((0, 3)), 3)
+        pr.n_rel, pr.rel = arr([np.r_[s, d] for s, d in rel] if len(rel) else np.zeros((0, 6)), 6)
+        pr.global_ = 1 if global_ else 0
+        pr.g_W[:] = [float(v) for v in g_W]
+        x = np.zeros(12 * pr.n_nodes)
+        cost = np.zeros(iters)
+        _check(lib().dslam_deform_solve(self.handle, C.byref(pr), int(iters), x.ctypes.data_as(C.POINTER(C.c_double)),
+                                        cost.ctypes.data_as(C.POINTER(C.c_double)), _stream_ptr(stream)),
+               "dslam_deform_solve")
+        return x.reshape(-1, 12), cost
 
 
 class Batch:

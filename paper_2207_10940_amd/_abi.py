@@ -97,6 +97,13 @@ class MapParams(C.Structure):
                 ("render_band", C.c_float)]
 
 
+class DeformProblem(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("nodes", C.POINTER(C.c_double)), ("n_con", C.c_int32),
+                ("con", C.POINTER(C.c_double)), ("n_pin", C.c_int32), ("pin", C.POINTER(C.c_double)),
+                ("n_rel", C.c_int32), ("rel", C.POINTER(C.c_double)), ("global_", C.c_int32),
+                ("g_W", C.c_double * 3)]
+
+
 SIGNATURES = {
     "dslam_status_string": (C.c_char_p, [C.c_int]),
     "dslam_build_info": (C.c_char_p, []),
@@ -142,6 +149,9 @@ SIGNATURES = {
     "dslam_map_render": (C.c_int, [vp, dp, vp, vp, vp]),
     "dslam_map_count": (C.c_int, [vp, P(C.c_int32), P(C.c_int32)]),
     "dslam_map_copy": (C.c_int, [vp, C.c_int32, fp, C.c_int32]),
+    "dslam_deform_create": (C.c_int, [vp, C.c_int32, C.c_int32, P(vp)]),
+    "dslam_deform_destroy": (C.c_int, [vp]),
+    "dslam_deform_solve": (C.c_int, [vp, P(DeformProblem), C.c_int32, dp, dp, vp]),
 }
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdslam.so")

@@ -42,6 +42,7 @@ SOURCES = {
     "dslam.hip": EXACT_FP64,
     "server.hip": EXACT_FP64,
     "map.hip": EXACT_FP32,
+    "deform.hip": DEVICE_FP64,
 }
 
 

@@ -1,0 +1,467 @@
+// Deformation graph with the gravity term (Section V, eqs. (10)-(17)) on the
+// GPU: Gauss-Newton over the node matrices A_l (the paper's node "rotation",
+// held orthonormal by E_rot only) and translations t_l.  Readings:
+//   * influence of the nodes on a point v: its K = 4 nearest nodes (ties by
+//     index), weights w_k = (1 - |v - g_k| / d_max)^2 with d_max the distance
+//     of the (K+1)-th nearest node, normalised (equal weights if all vanish);
+//     phi(v) = sum_k w_k (A_k (v - g_k) + g_k + t_k);
+//   * E_reg's neighbours N(l): the K nearest other nodes;
+//   * E_rot = sum_l |A_l^T A_l - I|_F^2 (all nine entries), E_reg, E_con,
+//     E_pin, E_rel (global closures only) and E_imu as written, weights
+//     w_f = 1, w_r = 10, w_c = w_i = 100;
+//   * each step forms every term's residual and Jacobian rows scaled by the
+//     square root of its weight (one thread per term, dense rows of
+//     [J | r]), the normal equations as [J r]^T [J r] (tiled, every entry
+//     summed over the rows in row order: the last column holds J^T r and the
+//     corner the cost), and solves them by Cholesky in one workgroup.
+// Everything is float64; the neighbour lists and influences are computed on
+// the host.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "host.h"
+
+namespace dslam {
+
+constexpr int DEF_K = 4;
+constexpr double DEF_W_ROT = 1.0, DEF_W_REG = 10.0, DEF_W_CON = 100.0, DEF_W_IMU = 100.0;
+constexpr int DEF_TILE = 16;
+
+struct DefDev {
+  int N, P, Pp, Pr, global;
+  int m, n, ld;       // rows of [J | r], unknowns (12 N), row length (n + 1 rounded up to the tile)
+  const double* nodes;  // N x 3
+  const int* nbr;       // N x K
+  const double* con;    // P x 6: source, destination
+  const int* con_idx;   // P x K
+  const double* con_w;
+  const double* pin;    // Pp x 3
+  const int* pin_idx;
+  const double* pin_w;
+  const double* rel;    // Pr x 6
+  const int* rel_idx;   // Pr x 2K: the source's influence, then the destination's
+  const double* rel_w;
+  double g[3];
+  double* x;   // 12 N: A_l row-major, t_l
+  double* Jr;  // m x ld
+  double* H;   // ld x ld
+  double* cost;
+  int* bad;
+};
+
+__global__ __launch_bounds__(256) void def_zero_kernel(double* p, size_t n) {
+  for (size_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0.0;
+}
+
+// phi at v with the given influence, added with sign `sg` to the three rows
+// starting at `row` (Jacobian entries and residual column).
+__device__ __forceinline__ void def_phi_rows(const DefDev& d, const int* idx, const double* w, const double* v,
+                                             double sg, double sw, int row, double* r) {
+  for (int k = 0; k < DEF_K; ++k) {
+    const int nd = idx[k];
+    const double wk = w[k];
+    const double* g = d.nodes + 3 * nd;
+    const double dv[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
+    const double* A = d.x + 12 * nd;
+    for (int a = 0; a < 3; ++a) {
+      double* J = d.Jr + (size_t)(row + a) * d.ld;
+      for (int b = 0; b < 3; ++b) J[12 * nd + 3 * a + b] += sg * sw * wk * dv[b];
+      J[12 * nd + 9 + a] += sg * sw * wk;
+      const double pa = A[3 * a] * dv[0] + A[3 * a + 1] * dv[1] + A[3 * a + 2] * dv[2] + g[a] + A[9 + a];
+      r[a] += sg * wk * pa;
+    }
+  }
+}
+
+// One thread per term: its rows of [J | r], scaled by sqrt(weight).
+__global__ __launch_bounds__(256) void def_jacobian_kernel(DefDev d) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  const int N = d.N, nrot = N, nreg = N * DEF_K, ncon = d.P, npin = d.Pp, nrel = d.global ? d.Pr : 0;
+  const int T = nrot + nreg + ncon + npin + nrel + N;
+  if (q >= T) return;
+  const int n = d.n;
+  if (q < nrot) {  // E_rot
+    const int l = q;
+    const double sw = sqrt(DEF_W_ROT);
+    const double* A = d.x + 12 * l;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double* J = d.Jr + (size_t)(9 * l + 3 * i + j) * d.ld;
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          s += A[3 * a + i] * A[3 * a + j];
+          J[12 * l + 3 * a + j] += sw * A[3 * a + i];
+          J[12 * l + 3 * a + i] += sw * A[3 * a + j];
+        }
+        J[n] = sw * (s - (i == j ? 1.0 : 0.0));
+      }
+    return;
+  }
+  int row = 9 * N;
+  int t = q - nrot;
+  if (t < nreg) {  // E_reg
+    const int l = t / DEF_K, nb = d.nbr[t];
+    const double sw = sqrt(DEF_W_REG);
+    const double* gl = d.nodes + 3 * l;
+    const double* gn = d.nodes + 3 * nb;
+    const double dv[3] = {gn[0] - gl[0], gn[1] - gl[1], gn[2] - gl[2]};
+    const double* A = d.x + 12 * l;
+    for (int a = 0; a < 3; ++a) {
+      double* J = d.Jr + (size_t)(row + 3 * t + a) * d.ld;
+      for (int b = 0; b < 3; ++b) J[12 * l + 3 * a + b] = sw * dv[b];
+      J[12 * l + 9 + a] += sw;
+      J[12 * nb + 9 + a] -= sw;
+      const double r = A[3 * a] * dv[0] + A[3 * a + 1] * dv[1] + A[3 * a + 2] * dv[2] + gl[a] + A[9 + a] -
+                       (gn[a] + d.x[12 * nb + 9 + a]);
+      J[n] = sw * r;
+    }
+    return;
+  }
+  row += 3 * nreg;
+  t -= nreg;
+  const double sw = sqrt(DEF_W_CON);
+  double r[3] = {0.0, 0.0, 0.0};
+  if (t < ncon) {  // E_con: phi(source) - destination
+    const double* c = d.con + 6 * t;
+    def_phi_rows(d, d.con_idx + DEF_K * t, d.con_w + DEF_K * t, c, 1.0, sw, row + 3 * t, r);
+    for (int a = 0; a < 3; ++a) d.Jr[(size_t)(row + 3 * t + a) * d.ld + n] = sw * (r[a] - c[3 + a]);
+    return;
+  }
+  row += 3 * ncon;
+  t -= ncon;
+  if (t < npin) {  // E_pin: phi(destination) - destination
+    const double* c = d.pin + 3 * t;
+    def_phi_rows(d, d.pin_idx + DEF_K * t, d.pin_w + DEF_K * t, c, 1.0, sw, row + 3 * t, r);
+    for (int a = 0; a < 3; ++a) d.Jr[(size_t)(row + 3 * t + a) * d.ld + n] = sw * (r[a] - c[a]);
+    return;
+  }
+  row += 3 * npin;
+  t -= npin;
+  if (t < nrel) {  // E_rel: phi(source) - phi(destination)
+    const double* c = d.rel + 6 * t;
+    def_phi_rows(d, d.rel_idx + 2 * DEF_K * t, d.rel_w + 2 * DEF_K * t, c, 1.0, sw, row + 3 * t, r);
+    def_phi_rows(d, d.rel_idx + 2 * DEF_K * t + DEF_K, d.rel_w + 2 * DEF_K * t + DEF_K, c + 3, -1.0, sw,
+                 row + 3 * t, r);
+    for (int a = 0; a < 3; ++a) d.Jr[(size_t)(row + 3 * t + a) * d.ld + n] = sw * r[a];
+    return;
+  }
+  row += 3 * nrel;
+  t -= nrel;
+  {  // E_imu: A_l g - g
+    const int l = t;
+    const double si = sqrt(DEF_W_IMU);
+    const double* A = d.x + 12 * l;
+    for (int a = 0; a < 3; ++a) {
+      double* J = d.Jr + (size_t)(row + 3 * l + a) * d.ld;
+      for (int b = 0; b < 3; ++b) J[12 * l + 3 * a + b] = si * d.g[b];
+      J[n] = si * (A[3 * a] * d.g[0] + A[3 * a + 1] * d.g[1] + A[3 * a + 2] * d.g[2] - d.g[a]);
+    }
+  }
+}
+
+// [J r]^T [J r], one 16 x 16 tile per workgroup, every entry summed over the
+// rows in row order.
+__global__ __launch_bounds__(256) void def_normal_kernel(DefDev d) {
+  __shared__ double As[DEF_TILE][DEF_TILE + 1], Bs[DEF_TILE][DEF_TILE + 1];
+  const int tx = threadIdx.x % DEF_TILE, ty = threadIdx.x / DEF_TILE;
+  const int i0 = blockIdx.y * DEF_TILE, j0 = blockIdx.x * DEF_TILE;
+  double acc = 0.0;
+  for (int r0 = 0; r0 < d.m; r0 += DEF_TILE) {
+    const int r = r0 + ty;
+    As[ty][tx] = r < d.m ? d.Jr[(size_t)r * d.ld + i0 + tx] : 0.0;
+    Bs[ty][tx] = r < d.m ? d.Jr[(size_t)r * d.ld + j0 + tx] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < DEF_TILE; ++k) acc += As[k][ty] * Bs[k][tx];
+    __syncthreads();
+  }
+  d.H[(size_t)(i0 + ty) * d.ld + j0 + tx] = acc;
+}
+
+// Cholesky of the n x n normal matrix (lower triangle, in place), then
+// L L^T dx = -J^T r by column-oriented substitution, and x += dx; cost[it]
+// receives the step's cost r^T r.  One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void def_cholesky_kernel(DefDev d, int it) {
+  __shared__ int bad;
+  __shared__ double tiny;
+  const int n = d.n, ld = d.ld, tid = threadIdx.x;
+  double* H = d.H;
+  double* rhs = H + (size_t)n * ld;  // row n of the symmetric [J r]^T [J r] is (J^T r)^T
+  if (tid == 0) {
+    bad = 0;
+    d.cost[it] = H[(size_t)n * ld + n];
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) dmax = fmax(dmax, H[(size_t)i * ld + i]);
+    tiny = 1e-12 * dmax;  // a pivot at or below this marks the system singular
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double p = H[(size_t)k * ld + k];
+      if (!(p > tiny) || !(p < 1e300)) bad = 1;
+      H[(size_t)k * ld + k] = sqrt(p > 0.0 ? p : 1.0);
+    }
+    __syncthreads();
+    if (bad) break;  // uniform
+    const double piv = H[(size_t)k * ld + k];
+    for (int i = k + 1 + tid; i < n; i += 1024) H[(size_t)i * ld + k] /= piv;
+    __syncthreads();
+    const int tx = tid & 31, ty = tid >> 5;
+    for (int i = k + 1 + ty; i < n; i += 32) {
+      const double lik = H[(size_t)i * ld + k];
+      for (int j = k + 1 + tx; j <= i; j += 32) H[(size_t)i * ld + j] -= lik * H[(size_t)j * ld + k];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) *d.bad = 1;
+    return;
+  }
+  // forward: L y = -J^T r (y in rhs)
+  for (int i = tid; i < n; i += 1024) rhs[i] = -rhs[i];
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double yj = rhs[j] / H[(size_t)j * ld + j];
+    __syncthreads();
+    if (tid == 0) rhs[j] = yj;
+    for (int i = j + 1 + tid; i < n; i += 1024) rhs[i] -= H[(size_t)i * ld + j] * yj;
+    __syncthreads();
+  }
+  // backward: L^T dx = y
+  for (int j = n - 1; j >= 0; --j) {
+    const double xj = rhs[j] / H[(size_t)j * ld + j];
+    __syncthreads();
+    if (tid == 0) rhs[j] = xj;
+    for (int i = tid; i < j; i += 1024) rhs[i] -= H[(size_t)j * ld + i] * xj;
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += 1024) d.x[i] += rhs[i];
+}
+
+}  // namespace dslam
+
+// ---------------------------------------------------------------------------
+// C ABI (include/dslam.h)
+// ---------------------------------------------------------------------------
+using namespace dslam;
+
+struct dslam_deform {
+  dslam_context* ctx;
+  int max_nodes, max_points;
+  uint64_t bytes;
+  void* arena;
+  double* nodes;
+  int* nbr;
+  double* pts;   // constraint coordinates
+  int* idx;      // influences
+  double* w;
+  double* x;
+  double* Jr;
+  double* H;
+  double* cost;
+  int* bad;
+  std::mutex mu;
+};
+
+#define DEF_HIP(expr)                                 \
+  do {                                                \
+    if ((expr) != hipSuccess) return DSLAM_ERR_DEVICE; \
+  } while (0)
+
+static size_t def_align(size_t n) { return (n + 255) & ~size_t(255); }
+static int def_round(int v) { return (v + DEF_TILE - 1) / DEF_TILE * DEF_TILE; }
+
+static void def_sizes(int N, int points, int* m, int* n, int* ld) {
+  *n = 12 * N;
+  *ld = def_round(*n + 1);
+  *m = def_round(9 * N + 3 * N * DEF_K + 3 * points + 3 * N);
+}
+
+// The K nearest nodes to v (ties by index, skipping `exclude`) and the
+// distance of the next one.
+static void def_nearest(const double* nodes, int N, const double* v, int exclude, int* idx, double* dist,
+                        double* dmax) {
+  std::vector<std::pair<double, int>> c;
+  c.reserve(N);
+  for (int k = 0; k < N; ++k) {
+    if (k == exclude) continue;
+    const double dx = v[0] - nodes[3 * k], dy = v[1] - nodes[3 * k + 1], dz = v[2] - nodes[3 * k + 2];
+    c.push_back({std::sqrt(dx * dx + dy * dy + dz * dz), k});
+  }
+  std::sort(c.begin(), c.end());
+  for (int k = 0; k < DEF_K; ++k) {
+    idx[k] = c[k].second;
+    dist[k] = c[k].first;
+  }
+  *dmax = c[DEF_K].first;
+}
+
+static void def_influence(const double* nodes, int N, const double* v, int* idx, double* w) {
+  double dist[DEF_K], dmax;
+  def_nearest(nodes, N, v, -1, idx, dist, &dmax);
+  double s = 0.0;
+  for (int k = 0; k < DEF_K; ++k) {
+    const double a = 1.0 - dist[k] / dmax;
+    w[k] = a * a;
+    s += w[k];
+  }
+  for (int k = 0; k < DEF_K; ++k) w[k] = s > 0.0 ? w[k] / s : 1.0 / DEF_K;
+}
+
+extern "C" {
+
+dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t max_points, dslam_deform** out) {
+  if (!ctx || !out || max_nodes < DEF_K + 2 || max_nodes > 256 || max_points < 0 || max_points > (1 << 20))
+    return DSLAM_ERR_INVALID;
+  int m, n, ld;
+  def_sizes(max_nodes, max_points, &m, &n, &ld);
+  const size_t N = max_nodes, Pt = max_points;
+  const uint64_t bytes = def_align(N * 3 * 8) + def_align(N * DEF_K * 4) + def_align(Pt * 6 * 8) +
+                         def_align(Pt * 2 * DEF_K * 4) + def_align(Pt * 2 * DEF_K * 8) + def_align(N * 12 * 8) +
+                         def_align((size_t)m * ld * 8) + def_align((size_t)ld * ld * 8) + def_align(64 * 8) +
+                         def_align(4);
+  const uint64_t prev = ctx->used.fetch_add(bytes);
+  if (ctx->budget && prev + bytes > ctx->budget) {
+    ctx->used.fetch_sub(bytes);
+    return DSLAM_ERR_NO_CAPACITY;
+  }
+  dslam_deform* d = new (std::nothrow) dslam_deform;
+  if (!d) {
+    ctx->used.fetch_sub(bytes);
+    return DSLAM_ERR_NO_CAPACITY;
+  }
+  d->ctx = ctx;
+  d->max_nodes = max_nodes;
+  d->max_points = max_points;
+  d->bytes = bytes;
+  if (hipSetDevice(ctx->device) != hipSuccess || hipMalloc(&d->arena, bytes) != hipSuccess) {
+    ctx->used.fetch_sub(bytes);
+    delete d;
+    return DSLAM_ERR_NO_CAPACITY;
+  }
+  char* q = (char*)d->arena;
+  d->nodes = (double*)q; q += def_align(N * 3 * 8);
+  d->nbr = (int*)q; q += def_align(N * DEF_K * 4);
+  d->pts = (double*)q; q += def_align(Pt * 6 * 8);
+  d->idx = (int*)q; q += def_align(Pt * 2 * DEF_K * 4);
+  d->w = (double*)q; q += def_align(Pt * 2 * DEF_K * 8);
+  d->x = (double*)q; q += def_align(N * 12 * 8);
+  d->Jr = (double*)q; q += def_align((size_t)m * ld * 8);
+  d->H = (double*)q; q += def_align((size_t)ld * ld * 8);
+  d->cost = (double*)q; q += def_align(64 * 8);
+  d->bad = (int*)q;
+  *out = d;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_deform_destroy(dslam_deform* d) {
+  if (!d) return DSLAM_ERR_INVALID;
+  (void)hipSetDevice(d->ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(d->arena);
+  d->ctx->used.fetch_sub(d->bytes);
+  delete d;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_deform_solve(dslam_deform* d, const dslam_deform_problem* p, int32_t iters, double* params_out,
+                                double* cost_out, void* stream) {
+  if (!d || !p || !params_out || iters < 1 || iters > 63) return DSLAM_ERR_INVALID;
+  const int N = p->n_nodes, P = p->n_con, Pp = p->n_pin, Pr = p->global ? p->n_rel : 0;
+  if (N < DEF_K + 2 || N > d->max_nodes || P < 0 || Pp < 0 || Pr < 0 || P + Pp + Pr > d->max_points) return DSLAM_ERR_INVALID;
+  if (!p->nodes || (P && !p->con) || (Pp && !p->pin) || (Pr && !p->rel)) return DSLAM_ERR_INVALID;
+  auto finite = [](const double* a, int n) {
+    for (int i = 0; i < n; ++i)
+      if (!std::isfinite(a[i])) return false;
+    return true;
+  };
+  if (!finite(p->nodes, 3 * N) || (P && !finite(p->con, 6 * P)) || (Pp && !finite(p->pin, 3 * Pp)) ||
+      (Pr && !finite(p->rel, 6 * Pr)) || !finite(p->g_W, 3))
+    return DSLAM_ERR_INVALID;
+  std::lock_guard<std::mutex> g(d->mu);
+  DEF_HIP(hipSetDevice(d->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  // host: neighbour lists and influences
+  std::vector<int> nbr(N * DEF_K);
+  for (int l = 0; l < N; ++l) {
+    double dist[DEF_K], dmax;
+    def_nearest(p->nodes, N, p->nodes + 3 * l, l, &nbr[DEF_K * l], dist, &dmax);
+  }
+  std::vector<double> pts;
+  std::vector<int> idx;
+  std::vector<double> w;
+  auto add_inf = [&](const double* v) {
+    int i4[DEF_K];
+    double w4[DEF_K];
+    def_influence(p->nodes, N, v, i4, w4);
+    idx.insert(idx.end(), i4, i4 + DEF_K);
+    w.insert(w.end(), w4, w4 + DEF_K);
+  };
+  for (int k = 0; k < P; ++k) add_inf(p->con + 6 * k);
+  for (int k = 0; k < Pp; ++k) add_inf(p->pin + 3 * k);
+  for (int k = 0; k < Pr; ++k) {
+    add_inf(p->rel + 6 * k);
+    add_inf(p->rel + 6 * k + 3);
+  }
+  pts.insert(pts.end(), p->con, p->con + 6 * P);
+  pts.insert(pts.end(), p->pin, p->pin + 3 * Pp);
+  if (Pr) pts.insert(pts.end(), p->rel, p->rel + 6 * Pr);
+  std::vector<double> x(12 * N, 0.0);
+  for (int l = 0; l < N; ++l) x[12 * l] = x[12 * l + 4] = x[12 * l + 8] = 1.0;
+  DEF_HIP(hipMemcpyAsync(d->nodes, p->nodes, sizeof(double) * 3 * N, hipMemcpyHostToDevice, st));
+  DEF_HIP(hipMemcpyAsync(d->nbr, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice, st));
+  if (!pts.empty()) DEF_HIP(hipMemcpyAsync(d->pts, pts.data(), sizeof(double) * pts.size(), hipMemcpyHostToDevice, st));
+  if (!idx.empty()) {
+    DEF_HIP(hipMemcpyAsync(d->idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, st));
+    DEF_HIP(hipMemcpyAsync(d->w, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, st));
+  }
+  DEF_HIP(hipMemcpyAsync(d->x, x.data(), sizeof(double) * x.size(), hipMemcpyHostToDevice, st));
+  int zero = 0;
+  DEF_HIP(hipMemcpyAsync(d->bad, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  DefDev dv;
+  dv.N = N; dv.P = P; dv.Pp = Pp; dv.Pr = Pr; dv.global = p->global ? 1 : 0;
+  def_sizes(N, P + Pp + Pr, &dv.m, &dv.n, &dv.ld);
+  dv.nodes = d->nodes;
+  dv.nbr = d->nbr;
+  dv.con = d->pts;
+  dv.con_idx = d->idx;
+  dv.con_w = d->w;
+  dv.pin = d->pts + 6 * P;
+  dv.pin_idx = d->idx + DEF_K * P;
+  dv.pin_w = d->w + DEF_K * P;
+  dv.rel = d->pts + 6 * P + 3 * Pp;
+  dv.rel_idx = d->idx + DEF_K * (P + Pp);
+  dv.rel_w = d->w + DEF_K * (P + Pp);
+  for (int i = 0; i < 3; ++i) dv.g[i] = p->g_W[i];
+  dv.x = d->x;
+  dv.Jr = d->Jr;
+  dv.H = d->H;
+  dv.cost = d->cost;
+  dv.bad = d->bad;
+  const int T = N + N * DEF_K + P + Pp + Pr + N;
+  const size_t jr = (size_t)dv.m * dv.ld;
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL(def_zero_kernel, dim3((unsigned)std::min<size_t>((jr + 255) / 256, 4096)), dim3(256), 0, st,
+                       d->Jr, jr);
+    hipLaunchKernelGGL(def_jacobian_kernel, dim3((T + 255) / 256), dim3(256), 0, st, dv);
+    hipLaunchKernelGGL(def_normal_kernel, dim3(dv.ld / DEF_TILE, dv.ld / DEF_TILE), dim3(256), 0, st, dv);
+    hipLaunchKernelGGL(def_cholesky_kernel, dim3(1), dim3(1024), 0, st, dv, it);
+  }
+  DEF_HIP(hipGetLastError());
+  std::vector<double> cost(iters);
+  int bad = 0;
+  DEF_HIP(hipMemcpyAsync(params_out, d->x, sizeof(double) * 12 * N, hipMemcpyDeviceToHost, st));
+  DEF_HIP(hipMemcpyAsync(cost.data(), d->cost, sizeof(double) * iters, hipMemcpyDeviceToHost, st));
+  DEF_HIP(hipMemcpyAsync(&bad, d->bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  DEF_HIP(hipStreamSynchronize(st));
+  if (cost_out)
+    for (int i = 0; i < iters; ++i) cost_out[i] = cost[i];
+  return bad ? DSLAM_ERR_SINGULAR : DSLAM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+"""GPU deformation-graph solver (dslam_deform_*) against the oracle's
+Gauss-Newton (float64): node parameters and per-step costs agree to
+rounding, a yaw-rigid motion is recovered exactly, and singular or invalid
+problems are refused."""
+import numpy as np
+import pytest
+
+import paper_2207_10940_amd as P
+from oracle import deformation as D
+
+pytestmark = pytest.mark.gpu
+
+
+def _rot(axis, deg):
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    t = np.radians(deg)
+    return np.eye(3) + np.sin(t) * K + (1 - np.cos(t)) * K @ K
+
+
+def _case(seed, n_nodes, n_con, n_pin, n_rel):
+    rng = np.random.default_rng(seed)
+    nodes = rng.uniform(-1.0, 1.0, size=(n_nodes, 3)) * np.array([2.0, 2.0, 1.0])
+    R, t = _rot(rng.normal(size=3), 3.0), rng.normal(size=3) * 0.05
+    src = nodes[rng.integers(0, n_nodes, n_con)] + rng.normal(size=(n_con, 3)) * 0.2
+    con = [(s, R @ s + t + rng.normal(size=3) * 0.01) for s in src]
+    pin = list(nodes[rng.integers(0, n_nodes, n_pin)] + rng.normal(size=(n_pin, 3)) * 0.2)
+    rsrc = nodes[rng.integers(0, n_nodes, n_rel)] + rng.normal(size=(n_rel, 3)) * 0.2
+    rel = [(s, s + rng.normal(size=3) * 0.01) for s in rsrc]
+    return nodes, con, pin, rel
+
+
+@pytest.mark.parametrize("seed,n_nodes,n_con,n_pin,n_rel,glob", [(1, 16, 40, 20, 0, False), (2, 32, 96, 64, 24, True),
+                                                                  (3, 64, 256, 128, 64, True)])
+def test_solve_matches_oracle(seed, n_nodes, n_con, n_pin, n_rel, glob):
+    print(f"deform {n_nodes} nodes {n_con}+{n_pin}+{n_rel} points global {glob}", flush=True)
+    nodes, con, pin, rel = _case(seed, n_nodes, n_con, n_pin, n_rel)
+    prob = D.problem(nodes, con=con, pin=pin, rel=rel, global_=glob)
+    iters = 4
+    ctx = P.Context(0)
+    df = P.Deform(ctx, 64, 512)
+    try:
+        x, cost = df.solve(nodes, con=con, pin=pin, rel=rel, global_=glob, iters=iters)
+    finally:
+        df.close()
+        ctx.close()
+    xo = D.identity_params(n_nodes)
+    for it in range(iters):
+        eo = D.energy(xo, prob)
+        assert abs(cost[it] - eo) <= 1e-9 * max(eo, 1e-12), (it, cost[it], eo)
+        xo = D.solve(prob, iters=1, x0=xo)
+    assert np.abs(x.ravel() - xo).max() < 1e-9
+
+
+def test_yaw_rigid_motion_recovered():
+    rng = np.random.default_rng(4)
+    nodes = rng.uniform(-1.0, 1.0, size=(24, 3))
+    R, t = _rot([0, 0, 1], 5.0), np.array([0.1, -0.05, 0.02])
+    src = nodes + rng.normal(size=nodes.shape) * 0.1
+    ctx = P.Context(0)
+    df = P.Deform(ctx, 32, 64)
+    try:
+        x, cost = df.solve(nodes, con=[(s, R @ s + t) for s in src], iters=6)
+    finally:
+        df.close()
+        ctx.close()
+    for l, g in enumerate(nodes):
+        assert np.abs(x[l, :9] - R.ravel()).max() < 1e-9
+        assert np.abs(x[l, 9:] - (R @ g + t - g)).max() < 1e-9
+    assert cost[-1] < 1e-16 * cost[0]
+
+
+def test_singular_and_invalid():
+    rng = np.random.default_rng(6)
+    nodes = rng.uniform(-1.0, 1.0, size=(12, 3))
+    ctx = P.Context(0)
+    df = P.Deform(ctx, 16, 16)
+    try:
+        with pytest.raises(P.DslamError) as ei:  # no point constraints: the global translation is free
+            df.solve(nodes, iters=2)
+        assert ei.value.code == P._abi.ERR_SINGULAR
+        with pytest.raises(P.DslamError):  # more nodes than the solver holds
+            df.solve(rng.normal(size=(20, 3)), pin=[nodes[0]], iters=1)
+        bad = nodes.copy()
+        bad[3, 1] = np.inf
+        with pytest.raises(P.DslamError):
+            df.solve(bad, pin=[nodes[0]], iters=1)
+    finally:
+        df.close()
+        ctx.close()
