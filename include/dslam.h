@@ -357,6 +357,15 @@ dslam_status dslam_map_predict(dslam_map* m, dslam_session* s, const double T_WM
  * Asynchronous on `stream`. */
 dslam_status dslam_map_render(dslam_map* m, const double T_WM[16], float* depth_dev, uint8_t* intensity_dev,
                               void* stream);
+/* Deform the map by a solved deformation graph (dslam_deform_solve): each
+ * surfel moves to phi(p) over its 4 nearest of the n_nodes (5..256) nodes
+ * (host, 3 doubles each) with the node parameters `params` (host, 12 per
+ * node: A row-major, then t), and its normal to the normalised
+ * sum_k w_k A_k n; evaluated in float64, rounded once to the map's float32.
+ * Waits for the device.  Errors: INVALID (arguments, non-finite input),
+ * DEVICE. */
+dslam_status dslam_map_deform(dslam_map* m, int32_t n_nodes, const double* nodes, const double* params,
+                              void* stream);
 /* Wait for the map's last call and read its surfel count and the number of
  * new surfels dropped so far for lack of capacity (nullable). */
 dslam_status dslam_map_count(dslam_map* m, int32_t* count, int32_t* dropped);

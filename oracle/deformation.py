@@ -155,3 +155,20 @@ def deform(x, prob, v):
     idx, w = influence(prob["nodes"], np.asarray(v, float))
     J, c = _phi_rows(prob["nodes"], idx, w, np.asarray(v, float), len(prob["nodes"]))
     return J @ x + c
+
+
+def deform_surfels(x, prob, pos, nrm):
+    """Deformed surfel positions and normals (float32 arrays N x 3 in, float32 out): p' = phi(p) and
+    n' = normalised sum_k w_k A_k n over p's influence, evaluated in float64 and rounded once."""
+    nodes, N = prob["nodes"], len(prob["nodes"])
+    A = x.reshape(N, 12)[:, :9].reshape(N, 3, 3)
+    t = x.reshape(N, 12)[:, 9:]
+    P = np.empty_like(pos)
+    Q = np.empty_like(nrm)
+    for i, (v, n) in enumerate(zip(pos.astype(np.float64), nrm.astype(np.float64))):
+        idx, w = influence(nodes, v)
+        P[i] = sum(wk * (A[k] @ (v - nodes[k]) + nodes[k] + t[k]) for k, wk in zip(idx, w))
+        m = sum(wk * (A[k] @ n) for k, wk in zip(idx, w))
+        ln = np.linalg.norm(m)
+        Q[i] = m / ln if ln > 0 else n
+    return P.astype(np.float32), Q.astype(np.float32)

@@ -371,6 +371,13 @@ class Map:
         _check(lib().dslam_map_render(self.handle, Tp, C.c_void_p(depth.data_ptr()), C.c_void_p(intensity.data_ptr()),
                                       _stream_ptr(stream)), "dslam_map_render")
 
+    def deform(self, nodes, params, stream=None):
+        """Apply a solved deformation graph (nodes N x 3, params N x 12) to every surfel."""
+        nd, ndp = _dptr(np.asarray(nodes, dtype=np.float64).ravel())
+        pr, prp = _dptr(np.asarray(params, dtype=np.float64).ravel())
+        _check(lib().dslam_map_deform(self.handle, int(len(nd) // 3), ndp, prp, _stream_ptr(stream)),
+               "dslam_map_deform")
+
     def count(self):
         n, d = C.c_int32(), C.c_int32()
         _check(lib().dslam_map_count(self.handle, C.byref(n), C.byref(d)), "dslam_map_count")

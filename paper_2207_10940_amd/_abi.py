@@ -149,6 +149,7 @@ SIGNATURES = {
     "dslam_map_render": (C.c_int, [vp, dp, vp, vp, vp]),
     "dslam_map_count": (C.c_int, [vp, P(C.c_int32), P(C.c_int32)]),
     "dslam_map_copy": (C.c_int, [vp, C.c_int32, fp, C.c_int32]),
+    "dslam_map_deform": (C.c_int, [vp, C.c_int32, dp, dp, vp]),
     "dslam_deform_create": (C.c_int, [vp, C.c_int32, C.c_int32, P(vp)]),
     "dslam_deform_destroy": (C.c_int, [vp]),
     "dslam_deform_solve": (C.c_int, [vp, P(DeformProblem), C.c_int32, dp, dp, vp]),

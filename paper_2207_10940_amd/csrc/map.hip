@@ -45,6 +45,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "host.h"
 
@@ -399,6 +400,69 @@ __global__ __launch_bounds__(256) void map_set_normals_kernel(LevelPtrs L, const
   L.N[2][p] = nz[p];
 }
 
+// Deformation of the map by a solved deformation graph: each surfel moves to
+// phi(p) = sum_k w_k (A_k (p - g_k) + g_k + t_k) over its 4 nearest nodes
+// (ties by index; w_k = (1 - d_k / d_5)^2 normalised, equal if all vanish)
+// and its normal to the normalised sum_k w_k A_k n, in float64, rounded once.
+// node: 3 positions then 12 parameters (A row-major, t) per node.
+constexpr int MAP_DEF_K = 4, MAP_DEF_MAX_NODES = 256;
+
+__global__ __launch_bounds__(256) void map_deform_kernel(MapDev m, const double* node, int N) {
+  const int n = *m.count;
+  for (int s = blockIdx.x * 256 + threadIdx.x; s < n; s += gridDim.x * 256) {
+    const double v[3] = {m.f[MAP_PX][s], m.f[MAP_PY][s], m.f[MAP_PZ][s]};
+    // the five nearest nodes by (distance, index), by insertion
+    double bd[MAP_DEF_K + 1];
+    int bi[MAP_DEF_K + 1];
+    for (int k = 0; k <= MAP_DEF_K; ++k) {
+      bd[k] = 1e300;
+      bi[k] = N;
+    }
+    for (int l = 0; l < N; ++l) {
+      const double* g = node + 15 * l;
+      const double dx = v[0] - g[0], dy = v[1] - g[1], dz = v[2] - g[2];
+      const double d = sqrt(dx * dx + dy * dy + dz * dz);
+      if (!(d < bd[MAP_DEF_K] || (d == bd[MAP_DEF_K] && l < bi[MAP_DEF_K]))) continue;
+      int k = MAP_DEF_K;
+      while (k > 0 && (d < bd[k - 1] || (d == bd[k - 1] && l < bi[k - 1]))) {
+        bd[k] = bd[k - 1];
+        bi[k] = bi[k - 1];
+        --k;
+      }
+      bd[k] = d;
+      bi[k] = l;
+    }
+    if (bi[MAP_DEF_K] >= N) continue;  // (non-finite position: left as it is)
+    double w[MAP_DEF_K], sw = 0.0;
+    for (int k = 0; k < MAP_DEF_K; ++k) {
+      const double a = 1.0 - bd[k] / bd[MAP_DEF_K];
+      w[k] = a * a;
+      sw += w[k];
+    }
+    const double nv[3] = {m.f[MAP_NX][s], m.f[MAP_NY][s], m.f[MAP_NZ][s]};
+    double P[3] = {0.0, 0.0, 0.0}, Q[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < MAP_DEF_K; ++k) {
+      const double wk = sw > 0.0 ? w[k] / sw : 1.0 / MAP_DEF_K;
+      const double* g = node + 15 * bi[k];
+      const double* A = g + 3;
+      const double dv[3] = {v[0] - g[0], v[1] - g[1], v[2] - g[2]};
+      for (int a = 0; a < 3; ++a) {
+        P[a] += wk * (A[3 * a] * dv[0] + A[3 * a + 1] * dv[1] + A[3 * a + 2] * dv[2] + g[a] + A[9 + a]);
+        Q[a] += wk * (A[3 * a] * nv[0] + A[3 * a + 1] * nv[1] + A[3 * a + 2] * nv[2]);
+      }
+    }
+    const double ln = sqrt(Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]);
+    m.f[MAP_PX][s] = (float)P[0];
+    m.f[MAP_PY][s] = (float)P[1];
+    m.f[MAP_PZ][s] = (float)P[2];
+    if (ln > 0.0) {
+      m.f[MAP_NX][s] = (float)(Q[0] / ln);
+      m.f[MAP_NY][s] = (float)(Q[1] / ln);
+      m.f[MAP_NZ][s] = (float)(Q[2] / ln);
+    }
+  }
+}
+
 }  // namespace dslam
 
 // ---------------------------------------------------------------------------
@@ -422,6 +486,7 @@ struct dslam_map {
   float* depth;          // rendered model view, W x H
   uint8_t* inten;
   float* nrm[3];         // its camera-frame normals, W x H each
+  double* def_nodes;     // deformation nodes: position and parameters, 15 doubles each
   int nb;
   hipEvent_t done;
   std::mutex mu;
@@ -473,7 +538,7 @@ dslam_status dslam_map_create(dslam_context* ctx, const dslam_camera* cam, const
   const size_t field = map_align((size_t)p->capacity * sizeof(float));
   const uint64_t bytes = MAP_FIELDS * field + map_align(3 * sizeof(int32_t)) + map_align(npx * 8) +
                          map_align(npx * 4) + map_align(npx) + 2 * map_align((size_t)nb * 4) + 4 * map_align(npx * 4) +
-                         map_align(npx);
+                         map_align(npx) + map_align(MAP_DEF_MAX_NODES * 15 * sizeof(double));
   const uint64_t prev = ctx->used.fetch_add(bytes);
   if (ctx->budget && prev + bytes > ctx->budget) {
     ctx->used.fetch_sub(bytes);
@@ -509,7 +574,8 @@ dslam_status dslam_map_create(dslam_context* ctx, const dslam_camera* cam, const
   m->block_off = (int32_t*)q; q += map_align((size_t)nb * 4);
   m->depth = (float*)q; q += map_align(npx * 4);
   for (int k = 0; k < 3; ++k) { m->nrm[k] = (float*)q; q += map_align(npx * 4); }
-  m->inten = (uint8_t*)q;
+  m->inten = (uint8_t*)q; q += map_align(npx);
+  m->def_nodes = (double*)q;
   if (hipMemset(ints, 0, 3 * sizeof(int32_t)) != hipSuccess || hipEventCreateWithFlags(&m->done, hipEventDisableTiming) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(m->arena);
@@ -604,6 +670,30 @@ dslam_status dslam_map_predict(dslam_map* m, dslam_session* s, const double T_WM
                      (const float*)m->nrm[0], (const float*)m->nrm[1], (const float*)m->nrm[2]);
   MAP_HIP(hipGetLastError());
   MAP_HIP(hipEventRecord(m->done, st));
+  return DSLAM_OK;
+}
+
+dslam_status dslam_map_deform(dslam_map* m, int32_t n_nodes, const double* nodes, const double* params,
+                              void* stream) {
+  if (!m || !nodes || !params || n_nodes < MAP_DEF_K + 1 || n_nodes > MAP_DEF_MAX_NODES) return DSLAM_ERR_INVALID;
+  for (int i = 0; i < 3 * n_nodes; ++i)
+    if (!std::isfinite(nodes[i])) return DSLAM_ERR_INVALID;
+  for (int i = 0; i < 12 * n_nodes; ++i)
+    if (!std::isfinite(params[i])) return DSLAM_ERR_INVALID;
+  std::lock_guard<std::mutex> g(m->mu);
+  MAP_HIP(hipSetDevice(m->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> buf(15 * (size_t)n_nodes);
+  for (int l = 0; l < n_nodes; ++l) {
+    for (int i = 0; i < 3; ++i) buf[15 * l + i] = nodes[3 * l + i];
+    for (int i = 0; i < 12; ++i) buf[15 * l + 3 + i] = params[12 * l + i];
+  }
+  MAP_HIP(hipMemcpyAsync(m->def_nodes, buf.data(), sizeof(double) * buf.size(), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(map_deform_kernel, dim3(map_grid(m->dev.capacity)), dim3(256), 0, st, m->dev,
+                     (const double*)m->def_nodes, n_nodes);
+  MAP_HIP(hipGetLastError());
+  MAP_HIP(hipEventRecord(m->done, st));
+  MAP_HIP(hipStreamSynchronize(st));  // the staging buffer is the caller's stack
   return DSLAM_OK;
 }
 

@@ -89,3 +89,44 @@ def test_singular_and_invalid():
     finally:
         df.close()
         ctx.close()
+
+
+def test_map_deformation_matches_oracle():
+    """A fused map deformed by a solved graph: every surfel's position and normal within float32 rounding
+    of the oracle's phi (float64, rounded once)."""
+    import synth
+    from oracle import mapping as M
+    from oracle import pyramid as pyr
+    from tests.gpu_common import cuda, session
+    seq = synth.configs.sequence(seed=3003, n_frames=1, width=160, height=120)
+    cam = seq["camera"]
+    g = seq["gt"][0]
+    T = np.eye(4)
+    T[:3, :3] = synth.configs._rot_from_quat(g["q"])
+    T[:3, 3] = g["r"]
+    rng = np.random.default_rng(9)
+    with session(160, 120, 2, [1, 1], mode="rgbd") as s:
+        mp = P.Map(s.ctx, cam, 10**5)
+        try:
+            s.build_pyramid(P.PYR_CURRENT, cuda(seq["depth"][0].numpy()), cuda(seq["intensity"][0].numpy()))
+            mp.fuse(s, T)
+            before = mp.arrays()
+            pos = np.stack([before["px"], before["py"], before["pz"]], 1)
+            nodes = pos[rng.choice(len(pos), 24, replace=False)].astype(np.float64)
+            R, t = _rot([0.3, 1, 0.2], 2.0), np.array([0.02, -0.01, 0.03])
+            src = pos[rng.choice(len(pos), 60, replace=False)].astype(np.float64)
+            prob = D.problem(nodes, con=[(p_, R @ p_ + t) for p_ in src[:40]], pin=list(src[40:]))
+            x = D.solve(prob, iters=4)
+            mp.deform(nodes, x.reshape(-1, 12))
+            after = mp.arrays()
+        finally:
+            mp.close()
+    nrm = np.stack([before["nx"], before["ny"], before["nz"]], 1)
+    Pw, Qw = D.deform_surfels(x, prob, pos, nrm)
+    got_p = np.stack([after["px"], after["py"], after["pz"]], 1)
+    got_n = np.stack([after["nx"], after["ny"], after["nz"]], 1)
+    assert np.abs(got_p - Pw).max() <= 4 * np.finfo(np.float32).eps * max(1.0, np.abs(Pw).max())
+    assert np.abs(got_n - Qw).max() <= 4 * np.finfo(np.float32).eps
+    assert np.abs(got_p - pos).max() > 1e-3  # it moved
+    for k in ("inten", "radius", "conf"):
+        assert np.array_equal(after[k], before[k])
