@@ -562,6 +562,7 @@ def run_mapping(args, seq):
     elapsed = time.perf_counter() - t_start
     count, dropped = mp.count()
     acc = sequence_accuracy(est, seq["gt"][1:n + 1])
+    deform = run_deformation(args, ctx, mp, st)
     mp.close()
     sess.close()
     ctx.close()
@@ -571,10 +572,53 @@ def run_mapping(args, seq):
            "device_ms_per_frame": {"predict": parts[0] / n, "track": parts[1] / n, "fuse": parts[2] / n},
            "surfels": count, "dropped": dropped, "capacity": args.map_capacity,
            "ate_rmse_m": acc["ate_rmse_m"], "ate_rmse_aligned_m": acc["ate_rmse_aligned_m"],
-           "max_rot_err_deg": acc["max_rot_err_deg"]}
+           "max_rot_err_deg": acc["max_rot_err_deg"], "deformation": deform}
     log(f"[mapping] {n} frames in {elapsed * 1e3:.1f} ms ({out['frames_per_s']:.0f} frames/s); device ms/frame "
         f"predict {parts[0] / n:.3f} track {parts[1] / n:.3f} fuse {parts[2] / n:.3f}; {count} surfels; "
         f"ATE {acc['ate_rmse_m'] * 100:.2f} cm, max rotation error {acc['max_rot_err_deg']:.3f} deg")
+    return out
+
+
+def run_deformation(args, ctx, mp, st):
+    """A loop-closure deformation of the fused map (the paper's map correction with the gravity term,
+    Section V): 64 nodes sampled from the surfels, 256 constraints that pull one part of the map by a
+    2 cm / 1 degree drift correction, 128 pinned points elsewhere and 64 earlier registrations (a global
+    closure); solved by 5 Gauss-Newton steps on the device and applied to every surfel."""
+    import torch
+
+    import paper_2207_10940_amd as P
+    rng = np.random.default_rng(77)
+    a = mp.arrays()
+    pos = np.stack([a["px"], a["py"], a["pz"]], 1).astype(np.float64)
+    pos = pos[np.all(np.isfinite(pos), axis=1)]
+    nodes = pos[rng.choice(len(pos), args.deform_nodes, replace=False)]
+    c = pos.mean(axis=0)
+    side = pos[:, 0] > c[0]  # the part of the map the closure moves
+    th = np.radians(1.0)
+    R = np.array([[np.cos(th), -np.sin(th), 0.0], [np.sin(th), np.cos(th), 0.0], [0.0, 0.0, 1.0]])
+    t = np.array([0.02, -0.01, 0.0])
+    src = pos[side][rng.choice(side.sum(), 256, replace=False)]
+    con = [(s, R @ (s - c) + c + t) for s in src]
+    pin = list(pos[~side][rng.choice((~side).sum(), 128, replace=False)])
+    rs = pos[rng.choice(len(pos), 64, replace=False)]
+    rel = [(s, s) for s in rs]
+    df = P.Deform(ctx, args.deform_nodes, 512)
+    df.solve(nodes, con=con, pin=pin, rel=rel, global_=True, iters=1)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, cost = df.solve(nodes, con=con, pin=pin, rel=rel, global_=True, iters=5)
+    t_solve = time.perf_counter() - t0
+    df.close()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    mp.deform(nodes, x, st)
+    e1.record(st)
+    e1.synchronize()
+    out = {"nodes": int(args.deform_nodes), "constraints": 256, "pinned": 128, "registrations": 64,
+           "gauss_newton_steps": 5, "solve_ms": t_solve * 1e3, "cost_first_step": float(cost[0]),
+           "cost_last_step": float(cost[-1]), "apply_ms": e0.elapsed_time(e1), "surfels": int(len(pos))}
+    log(f"[deform] {args.deform_nodes} nodes, 256+128+64 points: 5 steps in {t_solve * 1e3:.2f} ms (cost "
+        f"{cost[0]:.3e} -> {cost[-1]:.3e}); applied to {len(pos)} surfels in {out['apply_ms']:.3f} ms")
     return out
 
 
@@ -723,6 +767,7 @@ def main():
     ap.add_argument("--map-frames", type=int, default=299, help="frames of the surfel-map tracking loop")
     ap.add_argument("--map-capacity", type=int, default=8_000_000)
     ap.add_argument("--no-mapping", action="store_true")
+    ap.add_argument("--deform-nodes", type=int, default=64, help="nodes of the map-deformation problem")
     ap.add_argument("--robustness-only", action="store_true", help="only run the robustness comparison")
     ap.add_argument("--counters", action="store_true",
                     help="only run the level-0 residual pass and a calibration copy (for rocprofv3 --pmc)")
