@@ -13,7 +13,8 @@
 //     square root of its weight (one thread per term, dense rows of
 //     [J | r]), the normal equations as [J r]^T [J r] (tiled, every entry
 //     summed over the rows in row order: the last column holds J^T r and the
-//     corner the cost), and solves them by Cholesky in one workgroup.
+//     corner the cost), and solves them by a blocked Cholesky (panels of 16
+//     columns factored in one workgroup, trailing updates over the chip).
 // Everything is float64; the neighbour lists and influences are computed on
 // the host.
 #include <hip/hip_runtime.h>
@@ -52,6 +53,7 @@ struct DefDev {
   double* H;   // ld x ld
   double* cost;
   int* bad;
+  double* tiny;
 };
 
 __global__ __launch_bounds__(256) void def_zero_kernel(double* p, size_t n) {
@@ -183,45 +185,116 @@ __global__ __launch_bounds__(256) void def_normal_kernel(DefDev d) {
   d.H[(size_t)(i0 + ty) * d.ld + j0 + tx] = acc;
 }
 
-// Cholesky of the n x n normal matrix (lower triangle, in place), then
-// L L^T dx = -J^T r by column-oriented substitution, and x += dx; cost[it]
-// receives the step's cost r^T r.  One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void def_cholesky_kernel(DefDev d, int it) {
-  __shared__ int bad;
-  __shared__ double tiny;
+// Blocked right-looking Cholesky of the n x n normal matrix (lower triangle,
+// in place), panel by panel of DEF_PANEL columns: def_panel_kernel factors
+// the diagonal block in LDS and solves the rows below it against it (one
+// workgroup), def_update_kernel subtracts the panel's contribution from the
+// trailing lower triangle (16 x 16 tiles over the chip); def_solve_kernel
+// then solves L L^T dx = -J^T r and updates the parameters.  A pivot at or
+// below 1e-12 of the largest diagonal entry of the normal matrix marks the
+// system singular (def_prepare_kernel also records the step's cost r^T r).
+constexpr int DEF_PANEL = 16;
+
+__global__ __launch_bounds__(256) void def_prepare_kernel(DefDev d, int it) {
+  __shared__ double part[256];
+  const int n = d.n, ld = d.ld;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, d.H[(size_t)i * ld + i]);
+  part[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    d.cost[it] = d.H[(size_t)n * ld + n];
+    *d.tiny = 1e-12 * part[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void def_panel_kernel(DefDev d, int kb) {
+  __shared__ double L[DEF_PANEL][DEF_PANEL + 1];
   const int n = d.n, ld = d.ld, tid = threadIdx.x;
+  const int bs = min(DEF_PANEL, n - kb);
   double* H = d.H;
-  double* rhs = H + (size_t)n * ld;  // row n of the symmetric [J r]^T [J r] is (J^T r)^T
-  if (tid == 0) {
-    bad = 0;
-    d.cost[it] = H[(size_t)n * ld + n];
-    double dmax = 0.0;
-    for (int i = 0; i < n; ++i) dmax = fmax(dmax, H[(size_t)i * ld + i]);
-    tiny = 1e-12 * dmax;  // a pivot at or below this marks the system singular
+  for (int e = tid; e < DEF_PANEL * DEF_PANEL; e += 256) {
+    const int r = e / DEF_PANEL, c = e % DEF_PANEL;
+    L[r][c] = (r < bs && c <= r) ? H[(size_t)(kb + r) * ld + kb + c] : 0.0;
   }
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
+  const double tiny = *d.tiny;
+  for (int k = 0; k < bs; ++k) {  // unblocked Cholesky of the diagonal block
     if (tid == 0) {
-      const double p = H[(size_t)k * ld + k];
-      if (!(p > tiny) || !(p < 1e300)) bad = 1;
-      H[(size_t)k * ld + k] = sqrt(p > 0.0 ? p : 1.0);
+      const double p = L[k][k];
+      if (!(p > tiny) || !(p < 1e300)) *d.bad = 1;
+      L[k][k] = sqrt(p > 0.0 ? p : 1.0);
     }
     __syncthreads();
-    if (bad) break;  // uniform
-    const double piv = H[(size_t)k * ld + k];
-    for (int i = k + 1 + tid; i < n; i += 1024) H[(size_t)i * ld + k] /= piv;
+    const double piv = L[k][k];
+    if (tid > k && tid < bs) L[tid][k] /= piv;
     __syncthreads();
-    const int tx = tid & 31, ty = tid >> 5;
-    for (int i = k + 1 + ty; i < n; i += 32) {
-      const double lik = H[(size_t)i * ld + k];
-      for (int j = k + 1 + tx; j <= i; j += 32) H[(size_t)i * ld + j] -= lik * H[(size_t)j * ld + k];
+    for (int e = tid; e < DEF_PANEL * DEF_PANEL; e += 256) {
+      const int r = e / DEF_PANEL, c = e % DEF_PANEL;
+      if (c > k && r >= c && r < bs) L[r][c] -= L[r][k] * L[c][k];
     }
     __syncthreads();
   }
-  if (bad) {
-    if (tid == 0) *d.bad = 1;
-    return;
+  for (int e = tid; e < DEF_PANEL * DEF_PANEL; e += 256) {
+    const int r = e / DEF_PANEL, c = e % DEF_PANEL;
+    if (r < bs && c <= r) H[(size_t)(kb + r) * ld + kb + c] = L[r][c];
   }
+  // a short last block is padded with identity rows, so that the solves
+  // below run over all DEF_PANEL columns with the row in registers
+  if (tid >= bs && tid < DEF_PANEL) L[tid][tid] = 1.0;
+  __syncthreads();
+  // rows below: x L^T = h, one thread per row (forward substitution over the block's columns)
+  for (int i = kb + bs + tid; i < n; i += 256) {
+    double* row = H + (size_t)i * ld + kb;
+    double x[DEF_PANEL];
+#pragma unroll
+    for (int c = 0; c < DEF_PANEL; ++c) x[c] = c < bs ? row[c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < DEF_PANEL; ++c) {
+      double v = x[c];
+#pragma unroll
+      for (int c2 = 0; c2 < c; ++c2) v -= x[c2] * L[c][c2];
+      x[c] = v / L[c][c];
+    }
+#pragma unroll
+    for (int c = 0; c < DEF_PANEL; ++c)
+      if (c < bs) row[c] = x[c];
+  }
+}
+
+// A[i][j] -= sum_c L[i][kb + c] L[j][kb + c] for kb + bs <= j <= i < n.
+__global__ __launch_bounds__(256) void def_update_kernel(DefDev d, int kb) {
+  __shared__ double Li[DEF_TILE][DEF_PANEL + 1], Lj[DEF_TILE][DEF_PANEL + 1];
+  const int n = d.n, ld = d.ld;
+  const int bs = min(DEF_PANEL, n - kb), base = kb + bs;
+  const int ti = blockIdx.y, tj = blockIdx.x;
+  if (tj > ti) return;  // upper tiles: nothing (uniform per workgroup)
+  const int i0 = base + ti * DEF_TILE, j0 = base + tj * DEF_TILE;
+  const int tx = threadIdx.x % DEF_TILE, ty = threadIdx.x / DEF_TILE;
+  for (int e = threadIdx.x; e < DEF_TILE * DEF_PANEL; e += 256) {
+    const int r = e / DEF_PANEL, c = e % DEF_PANEL;
+    Li[r][c] = (i0 + r < n && c < bs) ? d.H[(size_t)(i0 + r) * ld + kb + c] : 0.0;
+    Lj[r][c] = (j0 + r < n && c < bs) ? d.H[(size_t)(j0 + r) * ld + kb + c] : 0.0;
+  }
+  __syncthreads();
+  const int i = i0 + ty, j = j0 + tx;
+  if (i < n && j <= i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < DEF_PANEL; ++c) acc += Li[ty][c] * Lj[tx][c];
+    d.H[(size_t)i * ld + j] -= acc;
+  }
+}
+
+__global__ __launch_bounds__(1024) void def_solve_kernel(DefDev d) {
+  const int n = d.n, ld = d.ld, tid = threadIdx.x;
+  if (*d.bad) return;  // the same value for every thread
+  double* H = d.H;
+  double* rhs = H + (size_t)n * ld;  // row n of the symmetric [J r]^T [J r] is (J^T r)^T
   // forward: L y = -J^T r (y in rhs)
   for (int i = tid; i < n; i += 1024) rhs[i] = -rhs[i];
   __syncthreads();
@@ -265,6 +338,7 @@ struct dslam_deform {
   double* H;
   double* cost;
   int* bad;
+  double* tiny;
   std::mutex mu;
 };
 
@@ -324,7 +398,7 @@ dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t 
   const uint64_t bytes = def_align(N * 3 * 8) + def_align(N * DEF_K * 4) + def_align(Pt * 6 * 8) +
                          def_align(Pt * 2 * DEF_K * 4) + def_align(Pt * 2 * DEF_K * 8) + def_align(N * 12 * 8) +
                          def_align((size_t)m * ld * 8) + def_align((size_t)ld * ld * 8) + def_align(64 * 8) +
-                         def_align(4);
+                         def_align(4) + def_align(8);
   const uint64_t prev = ctx->used.fetch_add(bytes);
   if (ctx->budget && prev + bytes > ctx->budget) {
     ctx->used.fetch_sub(bytes);
@@ -354,7 +428,8 @@ dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t 
   d->Jr = (double*)q; q += def_align((size_t)m * ld * 8);
   d->H = (double*)q; q += def_align((size_t)ld * ld * 8);
   d->cost = (double*)q; q += def_align(64 * 8);
-  d->bad = (int*)q;
+  d->bad = (int*)q; q += def_align(4);
+  d->tiny = (double*)q;
   *out = d;
   return DSLAM_OK;
 }
@@ -443,6 +518,7 @@ dslam_status dslam_deform_solve(dslam_deform* d, const dslam_deform_problem* p, 
   dv.H = d->H;
   dv.cost = d->cost;
   dv.bad = d->bad;
+  dv.tiny = d->tiny;
   const int T = N + N * DEF_K + P + Pp + Pr + N;
   const size_t jr = (size_t)dv.m * dv.ld;
   for (int it = 0; it < iters; ++it) {
@@ -450,7 +526,16 @@ dslam_status dslam_deform_solve(dslam_deform* d, const dslam_deform_problem* p, 
                        d->Jr, jr);
     hipLaunchKernelGGL(def_jacobian_kernel, dim3((T + 255) / 256), dim3(256), 0, st, dv);
     hipLaunchKernelGGL(def_normal_kernel, dim3(dv.ld / DEF_TILE, dv.ld / DEF_TILE), dim3(256), 0, st, dv);
-    hipLaunchKernelGGL(def_cholesky_kernel, dim3(1), dim3(1024), 0, st, dv, it);
+    hipLaunchKernelGGL(def_prepare_kernel, dim3(1), dim3(256), 0, st, dv, it);
+    for (int kb = 0; kb < dv.n; kb += DEF_PANEL) {
+      hipLaunchKernelGGL(def_panel_kernel, dim3(1), dim3(256), 0, st, dv, kb);
+      const int rest = dv.n - kb - DEF_PANEL;
+      if (rest > 0) {
+        const int t = (rest + DEF_TILE - 1) / DEF_TILE;
+        hipLaunchKernelGGL(def_update_kernel, dim3(t, t), dim3(256), 0, st, dv, kb);
+      }
+    }
+    hipLaunchKernelGGL(def_solve_kernel, dim3(1), dim3(1024), 0, st, dv);
   }
   DEF_HIP(hipGetLastError());
   std::vector<double> cost(iters);
