@@ -166,17 +166,23 @@ __global__ __launch_bounds__(256) void def_jacobian_kernel(DefDev d) {
   }
 }
 
-// [J r]^T [J r], one 16 x 16 tile per workgroup, every entry summed over the
-// rows in row order.
-__global__ __launch_bounds__(256) void def_normal_kernel(DefDev d) {
+// [J r]^T [J r] on its lower tiles (all that the factorisation and the solves
+// read), one 16 x 16 tile per workgroup.  A tile sums, in row order, only the
+// rows with entries in both of its column blocks: the host lists them per
+// tile (the pattern of J is the same at every Gauss-Newton step), and a row
+// left out would add exact zeros.
+__global__ __launch_bounds__(256) void def_normal_kernel(DefDev d, const int* tile_ij, const int* off,
+                                                         const int* rows) {
   __shared__ double As[DEF_TILE][DEF_TILE + 1], Bs[DEF_TILE][DEF_TILE + 1];
   const int tx = threadIdx.x % DEF_TILE, ty = threadIdx.x / DEF_TILE;
-  const int i0 = blockIdx.y * DEF_TILE, j0 = blockIdx.x * DEF_TILE;
+  const int p = blockIdx.x;
+  const int i0 = tile_ij[2 * p] * DEF_TILE, j0 = tile_ij[2 * p + 1] * DEF_TILE;
+  const int beg = off[p], end = off[p + 1];
   double acc = 0.0;
-  for (int r0 = 0; r0 < d.m; r0 += DEF_TILE) {
-    const int r = r0 + ty;
-    As[ty][tx] = r < d.m ? d.Jr[(size_t)r * d.ld + i0 + tx] : 0.0;
-    Bs[ty][tx] = r < d.m ? d.Jr[(size_t)r * d.ld + j0 + tx] : 0.0;
+  for (int k0 = beg; k0 < end; k0 += DEF_TILE) {
+    const int r = k0 + ty < end ? rows[k0 + ty] : -1;
+    As[ty][tx] = r >= 0 ? d.Jr[(size_t)r * d.ld + i0 + tx] : 0.0;
+    Bs[ty][tx] = r >= 0 ? d.Jr[(size_t)r * d.ld + j0 + tx] : 0.0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < DEF_TILE; ++k) acc += As[k][ty] * Bs[k][tx];
@@ -290,30 +296,92 @@ __global__ __launch_bounds__(256) void def_update_kernel(DefDev d, int kb) {
   }
 }
 
+// The two triangular solves, panel by panel of DEF_PANEL rows.  Wave 0 solves
+// the panel's diagonal block, lane i holding row i (forward) or column i
+// (backward) of it and the finished entries broadcast by shuffles; meanwhile
+// every thread has loaded its part of the panel's columns (forward) or rows
+// (backward), with which it then updates one remaining right-hand-side entry.
+// Each entry takes its updates in column order (forward) and in panel order,
+// columns in order within a panel (backward).  The right-hand side lives in
+// LDS (n <= 12 x 256).
+constexpr int DEF_MAX_N = 12 * 256;
+
 __global__ __launch_bounds__(1024) void def_solve_kernel(DefDev d) {
-  const int n = d.n, ld = d.ld, tid = threadIdx.x;
+  __shared__ double y[DEF_MAX_N];
+  const int n = d.n, ld = d.ld, tid = threadIdx.x, lane = tid & 63;
   if (*d.bad) return;  // the same value for every thread
-  double* H = d.H;
-  double* rhs = H + (size_t)n * ld;  // row n of the symmetric [J r]^T [J r] is (J^T r)^T
-  // forward: L y = -J^T r (y in rhs)
-  for (int i = tid; i < n; i += 1024) rhs[i] = -rhs[i];
+  const double* H = d.H;
+  const double* jtr = H + (size_t)n * ld;  // row n of the symmetric [J r]^T [J r] is (J^T r)^T
+  for (int i = tid; i < n; i += 1024) y[i] = -jtr[i];
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const double yj = rhs[j] / H[(size_t)j * ld + j];
+  // forward: L y = -J^T r
+  for (int pb = 0; pb < n; pb += DEF_PANEL) {
+    const int bs = min(DEF_PANEL, n - pb);
+    const int r0 = pb + bs + tid;
+    double seg[DEF_PANEL];
+#pragma unroll
+    for (int c = 0; c < DEF_PANEL; ++c) seg[c] = (r0 < n && c < bs) ? H[(size_t)r0 * ld + pb + c] : 0.0;
+    if (tid < 64) {
+      double Lr[DEF_PANEL];
+#pragma unroll
+      for (int c = 0; c < DEF_PANEL; ++c) Lr[c] = (lane < bs && c <= lane) ? H[(size_t)(pb + lane) * ld + pb + c] : 1.0;
+      double yi = lane < bs ? y[pb + lane] : 0.0;
+#pragma unroll
+      for (int c = 0; c < DEF_PANEL; ++c) {
+        if (lane == c) yi = yi / Lr[c];
+        const double yc = __shfl(yi, c);
+        if (lane > c) yi -= Lr[c] * yc;
+      }
+      if (lane < bs) y[pb + lane] = yi;
+    }
     __syncthreads();
-    if (tid == 0) rhs[j] = yj;
-    for (int i = j + 1 + tid; i < n; i += 1024) rhs[i] -= H[(size_t)i * ld + j] * yj;
+    if (r0 < n) {
+      double v = y[r0];
+#pragma unroll
+      for (int c = 0; c < DEF_PANEL; ++c) v -= seg[c] * y[pb + min(c, bs - 1)];
+      y[r0] = v;
+    }
+    for (int r = r0 + 1024; r < n; r += 1024) {
+      double v = y[r];
+      for (int c = 0; c < bs; ++c) v -= H[(size_t)r * ld + pb + c] * y[pb + c];
+      y[r] = v;
+    }
     __syncthreads();
   }
   // backward: L^T dx = y
-  for (int j = n - 1; j >= 0; --j) {
-    const double xj = rhs[j] / H[(size_t)j * ld + j];
+  for (int pb = ((n - 1) / DEF_PANEL) * DEF_PANEL; pb >= 0; pb -= DEF_PANEL) {
+    const int bs = min(DEF_PANEL, n - pb);
+    double seg[DEF_PANEL];
+#pragma unroll
+    for (int c = 0; c < DEF_PANEL; ++c) seg[c] = (tid < pb && c < bs) ? H[(size_t)(pb + c) * ld + tid] : 0.0;
+    if (tid < 64) {
+      double Lc[DEF_PANEL];
+#pragma unroll
+      for (int c = 0; c < DEF_PANEL; ++c) Lc[c] = (lane < bs && c < bs && c >= lane) ? H[(size_t)(pb + c) * ld + pb + lane] : 1.0;
+      double yi = lane < bs ? y[pb + lane] : 0.0;
+#pragma unroll
+      for (int c = DEF_PANEL - 1; c >= 0; --c) {
+        if (lane == c) yi = yi / Lc[c];
+        const double yc = __shfl(yi, c);
+        if (lane < c) yi -= Lc[c] * yc;
+      }
+      if (lane < bs) y[pb + lane] = yi;
+    }
     __syncthreads();
-    if (tid == 0) rhs[j] = xj;
-    for (int i = tid; i < j; i += 1024) rhs[i] -= H[(size_t)j * ld + i] * xj;
+    if (tid < pb) {
+      double v = y[tid];
+#pragma unroll
+      for (int c = 0; c < DEF_PANEL; ++c) v -= seg[c] * y[pb + min(c, bs - 1)];
+      y[tid] = v;
+    }
+    for (int r = tid + 1024; r < pb; r += 1024) {
+      double v = y[r];
+      for (int c = 0; c < bs; ++c) v -= H[(size_t)(pb + c) * ld + r] * y[pb + c];
+      y[r] = v;
+    }
     __syncthreads();
   }
-  for (int i = tid; i < n; i += 1024) d.x[i] += rhs[i];
+  for (int i = tid; i < n; i += 1024) d.x[i] += y[i];
 }
 
 }  // namespace dslam
@@ -339,6 +407,8 @@ struct dslam_deform {
   double* cost;
   int* bad;
   double* tiny;
+  int* pairs;         // per lower tile pair: its two tiles, then the list offsets, then the row lists
+  size_t pairs_cap;   // ints
   std::mutex mu;
 };
 
@@ -354,6 +424,68 @@ static void def_sizes(int N, int points, int* m, int* n, int* ld) {
   *n = 12 * N;
   *ld = def_round(*n + 1);
   *m = def_round(9 * N + 3 * N * DEF_K + 3 * points + 3 * N);
+}
+
+// A row of J has entries in at most 8 nodes (E_rel), each across at most two
+// column tiles, plus the residual column's tile: at most 17 tiles, so it
+// appears in at most 17 * 18 / 2 lower tile pairs.
+constexpr int DEF_ROW_PAIRS = 17 * 18 / 2;
+
+static size_t def_pairs_cap(int m, int ld) {
+  const size_t nt = ld / DEF_TILE;
+  return (size_t)m * DEF_ROW_PAIRS + 3 * (nt * (nt + 1) / 2) + 1;
+}
+
+// The row lists of the lower tile pairs of [J r]^T [J r] for the row layout
+// of def_jacobian_kernel: E_rot (9 rows per node), E_reg (3 per node and
+// neighbour), E_con, E_pin, E_rel (3 per point), E_imu (3 per node).  `idx`
+// holds the influences (K per con and pin point, 2K per rel pair).  Packs
+// [tile pairs (2 ints each) | offsets (pairs + 1) | rows] into `out`.
+static void def_pair_lists(int N, int P, int Pp, int Pr, int n, int ld, const int* nbr, const int* idx,
+                           std::vector<int>* out) {
+  const int nt = ld / DEF_TILE, rt = n / DEF_TILE, W = (nt + 63) / 64;
+  const int mr = 9 * N + 3 * N * DEF_K + 3 * (P + Pp + Pr) + 3 * N;
+  std::vector<uint64_t> mask((size_t)mr * W, 0);
+  auto mark = [&](int row, int node) {
+    for (int t = 12 * node / DEF_TILE; t <= (12 * node + 11) / DEF_TILE; ++t)
+      mask[(size_t)row * W + t / 64] |= 1ull << (t % 64);
+  };
+  int row = 0;
+  for (int l = 0; l < N; ++l)
+    for (int q = 0; q < 9; ++q) mark(row++, l);
+  for (int t = 0; t < N * DEF_K; ++t)
+    for (int a = 0; a < 3; ++a, ++row) {
+      mark(row, t / DEF_K);
+      mark(row, nbr[t]);
+    }
+  for (int t = 0; t < P + Pp; ++t)
+    for (int a = 0; a < 3; ++a, ++row)
+      for (int k = 0; k < DEF_K; ++k) mark(row, idx[DEF_K * t + k]);
+  for (int t = 0; t < Pr; ++t)
+    for (int a = 0; a < 3; ++a, ++row)
+      for (int k = 0; k < 2 * DEF_K; ++k) mark(row, idx[DEF_K * (P + Pp) + 2 * DEF_K * t + k]);
+  for (int l = 0; l < N; ++l)
+    for (int a = 0; a < 3; ++a) mark(row++, l);
+  std::vector<std::vector<int>> trows(nt);
+  for (int r = 0; r < mr; ++r) {
+    mask[(size_t)r * W + rt / 64] |= 1ull << (rt % 64);
+    for (int w = 0; w < W; ++w)
+      for (uint64_t b = mask[(size_t)r * W + w]; b; b &= b - 1) trows[64 * w + __builtin_ctzll(b)].push_back(r);
+  }
+  const int np = nt * (nt + 1) / 2;
+  out->assign(3 * (size_t)np + 1, 0);
+  int p = 0;
+  for (int I = 0; I < nt; ++I)
+    for (int J = 0; J <= I; ++J, ++p) {
+      (*out)[2 * p] = I;
+      (*out)[2 * p + 1] = J;
+      (*out)[2 * np + p] = (int)(out->size() - (3 * (size_t)np + 1));
+      const bool a_is_i = trows[I].size() <= trows[J].size();
+      const int o = a_is_i ? J : I;
+      for (int r : a_is_i ? trows[I] : trows[J])
+        if ((mask[(size_t)r * W + o / 64] >> (o % 64)) & 1) out->push_back(r);
+    }
+  (*out)[3 * np] = (int)(out->size() - (3 * (size_t)np + 1));
 }
 
 // The K nearest nodes to v (ties by index, skipping `exclude`) and the
@@ -395,10 +527,11 @@ dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t 
   int m, n, ld;
   def_sizes(max_nodes, max_points, &m, &n, &ld);
   const size_t N = max_nodes, Pt = max_points;
+  const size_t pairs_cap = def_pairs_cap(m, ld);
   const uint64_t bytes = def_align(N * 3 * 8) + def_align(N * DEF_K * 4) + def_align(Pt * 6 * 8) +
                          def_align(Pt * 2 * DEF_K * 4) + def_align(Pt * 2 * DEF_K * 8) + def_align(N * 12 * 8) +
                          def_align((size_t)m * ld * 8) + def_align((size_t)ld * ld * 8) + def_align(64 * 8) +
-                         def_align(4) + def_align(8);
+                         def_align(4) + def_align(8) + def_align(pairs_cap * 4);
   const uint64_t prev = ctx->used.fetch_add(bytes);
   if (ctx->budget && prev + bytes > ctx->budget) {
     ctx->used.fetch_sub(bytes);
@@ -429,7 +562,9 @@ dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t 
   d->H = (double*)q; q += def_align((size_t)ld * ld * 8);
   d->cost = (double*)q; q += def_align(64 * 8);
   d->bad = (int*)q; q += def_align(4);
-  d->tiny = (double*)q;
+  d->tiny = (double*)q; q += def_align(8);
+  d->pairs = (int*)q;
+  d->pairs_cap = pairs_cap;
   *out = d;
   return DSLAM_OK;
 }
@@ -498,6 +633,13 @@ dslam_status dslam_deform_solve(dslam_deform* d, const dslam_deform_problem* p, 
   DEF_HIP(hipMemcpyAsync(d->x, x.data(), sizeof(double) * x.size(), hipMemcpyHostToDevice, st));
   int zero = 0;
   DEF_HIP(hipMemcpyAsync(d->bad, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+  int m, n, ld;
+  def_sizes(N, P + Pp + Pr, &m, &n, &ld);
+  std::vector<int> pairs;
+  def_pair_lists(N, P, Pp, Pr, n, ld, nbr.data(), idx.data(), &pairs);
+  if (pairs.size() > d->pairs_cap) return DSLAM_ERR_DEVICE;  // cannot happen: a row is in at most DEF_ROW_PAIRS pairs
+  DEF_HIP(hipMemcpyAsync(d->pairs, pairs.data(), sizeof(int) * pairs.size(), hipMemcpyHostToDevice, st));
+  const int np = (ld / DEF_TILE) * (ld / DEF_TILE + 1) / 2;
   DefDev dv;
   dv.N = N; dv.P = P; dv.Pp = Pp; dv.Pr = Pr; dv.global = p->global ? 1 : 0;
   def_sizes(N, P + Pp + Pr, &dv.m, &dv.n, &dv.ld);
@@ -525,7 +667,8 @@ dslam_status dslam_deform_solve(dslam_deform* d, const dslam_deform_problem* p, 
     hipLaunchKernelGGL(def_zero_kernel, dim3((unsigned)std::min<size_t>((jr + 255) / 256, 4096)), dim3(256), 0, st,
                        d->Jr, jr);
     hipLaunchKernelGGL(def_jacobian_kernel, dim3((T + 255) / 256), dim3(256), 0, st, dv);
-    hipLaunchKernelGGL(def_normal_kernel, dim3(dv.ld / DEF_TILE, dv.ld / DEF_TILE), dim3(256), 0, st, dv);
+    hipLaunchKernelGGL(def_normal_kernel, dim3(np), dim3(256), 0, st, dv, d->pairs, d->pairs + 2 * np,
+                       d->pairs + 3 * np + 1);
     hipLaunchKernelGGL(def_prepare_kernel, dim3(1), dim3(256), 0, st, dv, it);
     for (int kb = 0; kb < dv.n; kb += DEF_PANEL) {
       hipLaunchKernelGGL(def_panel_kernel, dim3(1), dim3(256), 0, st, dv, kb);
