@@ -51,6 +51,7 @@ struct DefDev {
   double* x;   // 12 N: A_l row-major, t_l
   double* Jr;  // m x ld
   double* H;   // ld x ld
+  double* L;   // ld x ld: the Cholesky factor (lower triangle; off-diagonal panels also transposed above it)
   double* cost;
   int* bad;
   double* tiny;
@@ -170,7 +171,8 @@ __global__ __launch_bounds__(256) void def_jacobian_kernel(DefDev d) {
 // read), one 16 x 16 tile per workgroup.  A tile sums, in row order, only the
 // rows with entries in both of its column blocks: the host lists them per
 // tile (the pattern of J is the same at every Gauss-Newton step), and a row
-// left out would add exact zeros.
+// left out would add exact zeros.  The one exception is the corner entry
+// r^T r, left incomplete here: nothing reads it (the cost is summed apart).
 __global__ __launch_bounds__(256) void def_normal_kernel(DefDev d, const int* tile_ij, const int* off,
                                                          const int* rows) {
   __shared__ double As[DEF_TILE][DEF_TILE + 1], Bs[DEF_TILE][DEF_TILE + 1];
@@ -192,196 +194,258 @@ __global__ __launch_bounds__(256) void def_normal_kernel(DefDev d, const int* ti
 }
 
 // Blocked right-looking Cholesky of the n x n normal matrix (lower triangle,
-// in place), panel by panel of DEF_PANEL columns: def_panel_kernel factors
-// the diagonal block in LDS and solves the rows below it against it (one
-// workgroup), def_update_kernel subtracts the panel's contribution from the
-// trailing lower triangle (16 x 16 tiles over the chip); def_solve_kernel
-// then solves L L^T dx = -J^T r and updates the parameters.  A pivot at or
-// below 1e-12 of the largest diagonal entry of the normal matrix marks the
-// system singular (def_prepare_kernel also records the step's cost r^T r).
+// into L), panel by panel of DEF_PANEL columns, one launch of def_chol_kernel
+// per panel; def_solve_kernel then solves L L^T dx = -J^T r and updates the
+// parameters.  A pivot at or below 1e-12 of the largest diagonal entry of the
+// normal matrix marks the system singular (def_prepare_kernel also records
+// the step's cost r^T r, summed over the residual column of [J r]).
 constexpr int DEF_PANEL = 16;
 
 __global__ __launch_bounds__(256) void def_prepare_kernel(DefDev d, int it) {
-  __shared__ double part[256];
-  const int n = d.n, ld = d.ld;
-  double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, d.H[(size_t)i * ld + i]);
-  part[threadIdx.x] = m;
+  __shared__ double part[256], cost[256];
+  const int n = d.n, ld = d.ld, tid = threadIdx.x;
+  double m = 0.0, c = 0.0;
+  for (int i = tid; i < n; i += 256) m = fmax(m, d.H[(size_t)i * ld + i]);
+  for (int r = tid; r < d.m; r += 256) {
+    const double v = d.Jr[(size_t)r * ld + n];
+    c += v * v;
+  }
+  part[tid] = m;
+  cost[tid] = c;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + s]);
+    if (tid < s) {
+      part[tid] = fmax(part[tid], part[tid + s]);
+      cost[tid] += cost[tid + s];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    d.cost[it] = d.H[(size_t)n * ld + n];
+  if (tid == 0) {
+    d.cost[it] = cost[0];
     *d.tiny = 1e-12 * part[0];
   }
 }
 
-__global__ __launch_bounds__(256) void def_panel_kernel(DefDev d, int kb) {
-  __shared__ double L[DEF_PANEL][DEF_PANEL + 1];
+// A lane's double from lane l of the wave (l the same for every lane).
+__device__ __forceinline__ double def_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// One step of the blocked right-looking Cholesky, for the panel of DEF_PANEL
+// columns at kb, in a single launch.  The factor goes to the separate matrix
+// L, so that the panel's columns of H stay as they were for every workgroup
+// to read; the panel below the diagonal is also written transposed into L's
+// otherwise unused upper triangle, where the forward solve reads it by rows.
+// Workgroup p owns the p-th lower trailing tile (rows i0, columns j0, both
+// past the panel): it factors the panel's diagonal block in LDS, solves its
+// two row blocks of the panel against it (x L^T = h, one thread per row),
+// subtracts their product from its tile of H, and writes its row block of the
+// factor if the tile is in the first trailing column (the first tile also
+// writes the diagonal block and flags a bad pivot).  The last panel has no
+// trailing tile and runs one workgroup that only factors.
+__global__ __launch_bounds__(256) void def_chol_kernel(DefDev d, int kb) {
+  __shared__ double D[DEF_PANEL][DEF_PANEL + 1];
+  __shared__ double Li[DEF_TILE][DEF_PANEL + 1], Lj[DEF_TILE][DEF_PANEL + 1];
   const int n = d.n, ld = d.ld, tid = threadIdx.x;
-  const int bs = min(DEF_PANEL, n - kb);
+  const int bs = min(DEF_PANEL, n - kb), base = kb + bs;
+  const int p = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > p) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= p) ++ti;
+  const int tj = p - ti * (ti + 1) / 2;
+  const int i0 = base + ti * DEF_TILE, j0 = base + tj * DEF_TILE;
+  const bool first = p == 0;
   double* H = d.H;
-  for (int e = tid; e < DEF_PANEL * DEF_PANEL; e += 256) {
-    const int r = e / DEF_PANEL, c = e % DEF_PANEL;
-    L[r][c] = (r < bs && c <= r) ? H[(size_t)(kb + r) * ld + kb + c] : 0.0;
+  double* L = d.L;
+  {
+    const int r = tid / DEF_PANEL, c = tid % DEF_PANEL;
+    D[r][c] = (r < bs && c <= r) ? H[(size_t)(kb + r) * ld + kb + c] : 0.0;
   }
+  const int row = tid < DEF_TILE ? i0 + tid : j0 + tid - DEF_TILE;
+  const bool has = tid < 2 * DEF_TILE && row < n;
+  double x[DEF_PANEL];
+#pragma unroll
+  for (int c = 0; c < DEF_PANEL; ++c) x[c] = (has && c < bs) ? H[(size_t)row * ld + kb + c] : 0.0;
   __syncthreads();
   const double tiny = *d.tiny;
   for (int k = 0; k < bs; ++k) {  // unblocked Cholesky of the diagonal block
     if (tid == 0) {
-      const double p = L[k][k];
-      if (!(p > tiny) || !(p < 1e300)) *d.bad = 1;
-      L[k][k] = sqrt(p > 0.0 ? p : 1.0);
+      const double pv = D[k][k];
+      if (first && (!(pv > tiny) || !(pv < 1e300))) *d.bad = 1;
+      D[k][k] = sqrt(pv > 0.0 ? pv : 1.0);
     }
     __syncthreads();
-    const double piv = L[k][k];
-    if (tid > k && tid < bs) L[tid][k] /= piv;
+    const double piv = D[k][k];
+    if (tid > k && tid < bs) D[tid][k] /= piv;
     __syncthreads();
-    for (int e = tid; e < DEF_PANEL * DEF_PANEL; e += 256) {
-      const int r = e / DEF_PANEL, c = e % DEF_PANEL;
-      if (c > k && r >= c && r < bs) L[r][c] -= L[r][k] * L[c][k];
+    {
+      const int r = tid / DEF_PANEL, c = tid % DEF_PANEL;
+      if (c > k && r >= c && r < bs) D[r][c] -= D[r][k] * D[c][k];
     }
     __syncthreads();
   }
-  for (int e = tid; e < DEF_PANEL * DEF_PANEL; e += 256) {
-    const int r = e / DEF_PANEL, c = e % DEF_PANEL;
-    if (r < bs && c <= r) H[(size_t)(kb + r) * ld + kb + c] = L[r][c];
+  if (first) {
+    const int r = tid / DEF_PANEL, c = tid % DEF_PANEL;
+    if (r < bs && c <= r) L[(size_t)(kb + r) * ld + kb + c] = D[r][c];
   }
   // a short last block is padded with identity rows, so that the solves
   // below run over all DEF_PANEL columns with the row in registers
-  if (tid >= bs && tid < DEF_PANEL) L[tid][tid] = 1.0;
+  if (tid >= bs && tid < DEF_PANEL) D[tid][tid] = 1.0;
   __syncthreads();
-  // rows below: x L^T = h, one thread per row (forward substitution over the block's columns)
-  for (int i = kb + bs + tid; i < n; i += 256) {
-    double* row = H + (size_t)i * ld + kb;
-    double x[DEF_PANEL];
+  if (tid < 2 * DEF_TILE) {
+    if (has) {
 #pragma unroll
-    for (int c = 0; c < DEF_PANEL; ++c) x[c] = c < bs ? row[c] : 0.0;
+      for (int c = 0; c < DEF_PANEL; ++c) {
+        double v = x[c];
 #pragma unroll
-    for (int c = 0; c < DEF_PANEL; ++c) {
-      double v = x[c];
+        for (int c2 = 0; c2 < c; ++c2) v -= x[c2] * D[c][c2];
+        x[c] = v / D[c][c];
+      }
+      if (tid < DEF_TILE && tj == 0)
 #pragma unroll
-      for (int c2 = 0; c2 < c; ++c2) v -= x[c2] * L[c][c2];
-      x[c] = v / L[c][c];
+        for (int c = 0; c < DEF_PANEL; ++c)
+          if (c < bs) {
+            L[(size_t)row * ld + kb + c] = x[c];
+            L[(size_t)(kb + c) * ld + row] = x[c];
+          }
     }
+    double* dst = tid < DEF_TILE ? Li[tid] : Lj[tid - DEF_TILE];
 #pragma unroll
-    for (int c = 0; c < DEF_PANEL; ++c)
-      if (c < bs) row[c] = x[c];
-  }
-}
-
-// A[i][j] -= sum_c L[i][kb + c] L[j][kb + c] for kb + bs <= j <= i < n.
-__global__ __launch_bounds__(256) void def_update_kernel(DefDev d, int kb) {
-  __shared__ double Li[DEF_TILE][DEF_PANEL + 1], Lj[DEF_TILE][DEF_PANEL + 1];
-  const int n = d.n, ld = d.ld;
-  const int bs = min(DEF_PANEL, n - kb), base = kb + bs;
-  const int ti = blockIdx.y, tj = blockIdx.x;
-  if (tj > ti) return;  // upper tiles: nothing (uniform per workgroup)
-  const int i0 = base + ti * DEF_TILE, j0 = base + tj * DEF_TILE;
-  const int tx = threadIdx.x % DEF_TILE, ty = threadIdx.x / DEF_TILE;
-  for (int e = threadIdx.x; e < DEF_TILE * DEF_PANEL; e += 256) {
-    const int r = e / DEF_PANEL, c = e % DEF_PANEL;
-    Li[r][c] = (i0 + r < n && c < bs) ? d.H[(size_t)(i0 + r) * ld + kb + c] : 0.0;
-    Lj[r][c] = (j0 + r < n && c < bs) ? d.H[(size_t)(j0 + r) * ld + kb + c] : 0.0;
+    for (int c = 0; c < DEF_PANEL; ++c) dst[c] = (has && c < bs) ? x[c] : 0.0;
   }
   __syncthreads();
+  const int tx = tid % DEF_TILE, ty = tid / DEF_TILE;
   const int i = i0 + ty, j = j0 + tx;
   if (i < n && j <= i) {
     double acc = 0.0;
 #pragma unroll
     for (int c = 0; c < DEF_PANEL; ++c) acc += Li[ty][c] * Lj[tx][c];
-    d.H[(size_t)i * ld + j] -= acc;
+    H[(size_t)i * ld + j] -= acc;
   }
 }
 
 // The two triangular solves, panel by panel of DEF_PANEL rows.  Wave 0 solves
 // the panel's diagonal block, lane i holding row i (forward) or column i
-// (backward) of it and the finished entries broadcast by shuffles; meanwhile
-// every thread has loaded its part of the panel's columns (forward) or rows
-// (backward), with which it then updates one remaining right-hand-side entry.
-// Each entry takes its updates in column order (forward) and in panel order,
-// columns in order within a panel (backward).  The right-hand side lives in
-// LDS (n <= 12 x 256).
+// (backward) of it and the reciprocal of its diagonal entry, the finished
+// entries read across lanes; the other
+// waves then update the remaining right-hand-side entries with the panel's
+// columns (forward) or rows (backward), one entry per thread.  Both sides
+// load the next panel's part of L while they work on this one.  Each entry
+// takes its updates in column order (forward) and in panel order, columns in
+// order within a panel (backward).  The right-hand side lives in LDS
+// (n <= 12 x 256).
 constexpr int DEF_MAX_N = 12 * 256;
+constexpr int DEF_SOLVE_THREADS = 1024, DEF_UPD = DEF_SOLVE_THREADS - 64;
 
-__global__ __launch_bounds__(1024) void def_solve_kernel(DefDev d) {
+__global__ __launch_bounds__(DEF_SOLVE_THREADS) void def_solve_kernel(DefDev d) {
   __shared__ double y[DEF_MAX_N];
-  const int n = d.n, ld = d.ld, tid = threadIdx.x, lane = tid & 63;
-  if (*d.bad) return;  // the same value for every thread
-  const double* H = d.H;
-  const double* jtr = H + (size_t)n * ld;  // row n of the symmetric [J r]^T [J r] is (J^T r)^T
-  for (int i = tid; i < n; i += 1024) y[i] = -jtr[i];
-  __syncthreads();
+  const int n = d.n, ld = d.ld, tid = threadIdx.x, lane = tid & 63, ut = tid - 64;
+  const bool diag = tid < 64;  // wave 0
+  if (*d.bad) return;          // the same value for every thread
+  const double* L = d.L;
+  const double* jtr = d.H + (size_t)n * ld;  // row n of the symmetric [J r]^T [J r] is (J^T r)^T
+  for (int i = tid; i < n; i += DEF_SOLVE_THREADS) y[i] = -jtr[i];
+  const int last = ((n - 1) / DEF_PANEL) * DEF_PANEL;
   // forward: L y = -J^T r
+  double cur[DEF_PANEL], nxt[DEF_PANEL] = {}, cur_d = 1.0, nxt_d = 1.0;
+  auto fwd_load = [&](int pb, double* v, double* dg) {
+    const int bs = min(DEF_PANEL, n - pb);
+    if (diag) {
+#pragma unroll
+      for (int c = 0; c < DEF_PANEL; ++c)
+        v[c] = (lane < bs && c <= lane) ? L[(size_t)(pb + lane) * ld + pb + c] : 1.0;
+      *dg = lane < bs ? L[(size_t)(pb + lane) * ld + pb + lane] : 1.0;
+    } else {  // L[r][pb + c], from its transposed copy above the diagonal
+      const int r = pb + bs + ut;
+#pragma unroll
+      for (int c = 0; c < DEF_PANEL; ++c) v[c] = (r < n && c < bs) ? L[(size_t)(pb + c) * ld + r] : 0.0;
+    }
+  };
+  fwd_load(0, cur, &cur_d);
+  double cur_inv = 1.0 / cur_d;
+  __syncthreads();
   for (int pb = 0; pb < n; pb += DEF_PANEL) {
     const int bs = min(DEF_PANEL, n - pb);
-    const int r0 = pb + bs + tid;
-    double seg[DEF_PANEL];
-#pragma unroll
-    for (int c = 0; c < DEF_PANEL; ++c) seg[c] = (r0 < n && c < bs) ? H[(size_t)r0 * ld + pb + c] : 0.0;
-    if (tid < 64) {
-      double Lr[DEF_PANEL];
-#pragma unroll
-      for (int c = 0; c < DEF_PANEL; ++c) Lr[c] = (lane < bs && c <= lane) ? H[(size_t)(pb + lane) * ld + pb + c] : 1.0;
+    if (pb + DEF_PANEL < n) fwd_load(pb + DEF_PANEL, nxt, &nxt_d);
+    if (diag) {
       double yi = lane < bs ? y[pb + lane] : 0.0;
 #pragma unroll
       for (int c = 0; c < DEF_PANEL; ++c) {
-        if (lane == c) yi = yi / Lr[c];
-        const double yc = __shfl(yi, c);
-        if (lane > c) yi -= Lr[c] * yc;
+        if (lane == c) yi *= cur_inv;
+        const double yc = def_lane(yi, c);
+        if (lane > c) yi -= cur[c] * yc;
       }
       if (lane < bs) y[pb + lane] = yi;
     }
     __syncthreads();
-    if (r0 < n) {
-      double v = y[r0];
+    if (!diag) {
+      const int r0 = pb + bs + ut;
+      if (r0 < n) {
+        double v = y[r0];
 #pragma unroll
-      for (int c = 0; c < DEF_PANEL; ++c) v -= seg[c] * y[pb + min(c, bs - 1)];
-      y[r0] = v;
-    }
-    for (int r = r0 + 1024; r < n; r += 1024) {
-      double v = y[r];
-      for (int c = 0; c < bs; ++c) v -= H[(size_t)r * ld + pb + c] * y[pb + c];
-      y[r] = v;
+        for (int c = 0; c < DEF_PANEL; ++c) v -= cur[c] * y[pb + min(c, bs - 1)];
+        y[r0] = v;
+      }
+      for (int r = r0 + DEF_UPD; r < n; r += DEF_UPD) {
+        double v = y[r];
+        for (int c = 0; c < bs; ++c) v -= L[(size_t)(pb + c) * ld + r] * y[pb + c];
+        y[r] = v;
+      }
     }
     __syncthreads();
+#pragma unroll
+    for (int c = 0; c < DEF_PANEL; ++c) cur[c] = nxt[c];
+    cur_inv = 1.0 / nxt_d;
   }
   // backward: L^T dx = y
-  for (int pb = ((n - 1) / DEF_PANEL) * DEF_PANEL; pb >= 0; pb -= DEF_PANEL) {
+  auto bwd_load = [&](int pb, double* v, double* dg) {
     const int bs = min(DEF_PANEL, n - pb);
-    double seg[DEF_PANEL];
+    if (diag) {
 #pragma unroll
-    for (int c = 0; c < DEF_PANEL; ++c) seg[c] = (tid < pb && c < bs) ? H[(size_t)(pb + c) * ld + tid] : 0.0;
-    if (tid < 64) {
-      double Lc[DEF_PANEL];
+      for (int c = 0; c < DEF_PANEL; ++c)
+        v[c] = (lane < bs && c < bs && c >= lane) ? L[(size_t)(pb + c) * ld + pb + lane] : 1.0;
+      *dg = lane < bs ? L[(size_t)(pb + lane) * ld + pb + lane] : 1.0;
+    } else {
 #pragma unroll
-      for (int c = 0; c < DEF_PANEL; ++c) Lc[c] = (lane < bs && c < bs && c >= lane) ? H[(size_t)(pb + c) * ld + pb + lane] : 1.0;
+      for (int c = 0; c < DEF_PANEL; ++c) v[c] = (ut < pb && c < bs) ? L[(size_t)(pb + c) * ld + ut] : 0.0;
+    }
+  };
+  bwd_load(last, cur, &cur_d);
+  cur_inv = 1.0 / cur_d;
+  for (int pb = last; pb >= 0; pb -= DEF_PANEL) {
+    const int bs = min(DEF_PANEL, n - pb);
+    if (pb > 0) bwd_load(pb - DEF_PANEL, nxt, &nxt_d);
+    if (diag) {
       double yi = lane < bs ? y[pb + lane] : 0.0;
 #pragma unroll
       for (int c = DEF_PANEL - 1; c >= 0; --c) {
-        if (lane == c) yi = yi / Lc[c];
-        const double yc = __shfl(yi, c);
-        if (lane < c) yi -= Lc[c] * yc;
+        if (lane == c) yi *= cur_inv;
+        const double yc = def_lane(yi, c);
+        if (lane < c) yi -= cur[c] * yc;
       }
       if (lane < bs) y[pb + lane] = yi;
     }
     __syncthreads();
-    if (tid < pb) {
-      double v = y[tid];
+    if (!diag) {
+      if (ut < pb) {
+        double v = y[ut];
 #pragma unroll
-      for (int c = 0; c < DEF_PANEL; ++c) v -= seg[c] * y[pb + min(c, bs - 1)];
-      y[tid] = v;
-    }
-    for (int r = tid + 1024; r < pb; r += 1024) {
-      double v = y[r];
-      for (int c = 0; c < bs; ++c) v -= H[(size_t)(pb + c) * ld + r] * y[pb + c];
-      y[r] = v;
+        for (int c = 0; c < DEF_PANEL; ++c) v -= cur[c] * y[pb + min(c, bs - 1)];
+        y[ut] = v;
+      }
+      for (int r = ut + DEF_UPD; r < pb; r += DEF_UPD) {
+        double v = y[r];
+        for (int c = 0; c < bs; ++c) v -= L[(size_t)(pb + c) * ld + r] * y[pb + c];
+        y[r] = v;
+      }
     }
     __syncthreads();
+#pragma unroll
+    for (int c = 0; c < DEF_PANEL; ++c) cur[c] = nxt[c];
+    cur_inv = 1.0 / nxt_d;
   }
-  for (int i = tid; i < n; i += 1024) d.x[i] += y[i];
+  for (int i = tid; i < n; i += DEF_SOLVE_THREADS) d.x[i] += y[i];
 }
 
 }  // namespace dslam
@@ -404,6 +468,7 @@ struct dslam_deform {
   double* x;
   double* Jr;
   double* H;
+  double* L;
   double* cost;
   int* bad;
   double* tiny;
@@ -439,8 +504,10 @@ static size_t def_pairs_cap(int m, int ld) {
 // The row lists of the lower tile pairs of [J r]^T [J r] for the row layout
 // of def_jacobian_kernel: E_rot (9 rows per node), E_reg (3 per node and
 // neighbour), E_con, E_pin, E_rel (3 per point), E_imu (3 per node).  `idx`
-// holds the influences (K per con and pin point, 2K per rel pair).  Packs
-// [tile pairs (2 ints each) | offsets (pairs + 1) | rows] into `out`.
+// holds the influences (K per con and pin point, 2K per rel pair).  Every row
+// has the residual column, in the last tile; the corner pair takes only the
+// rows with node entries in that tile.  Packs [tile pairs (2 ints each) |
+// offsets (pairs + 1) | rows] into `out`.
 static void def_pair_lists(int N, int P, int Pp, int Pr, int n, int ld, const int* nbr, const int* idx,
                            std::vector<int>* out) {
   const int nt = ld / DEF_TILE, rt = n / DEF_TILE, W = (nt + 63) / 64;
@@ -466,8 +533,11 @@ static void def_pair_lists(int N, int P, int Pp, int Pr, int n, int ld, const in
       for (int k = 0; k < 2 * DEF_K; ++k) mark(row, idx[DEF_K * (P + Pp) + 2 * DEF_K * t + k]);
   for (int l = 0; l < N; ++l)
     for (int a = 0; a < 3; ++a) mark(row++, l);
+  // the corner tile pair lists only the rows with node entries in its tile
+  std::vector<int> corner;
   std::vector<std::vector<int>> trows(nt);
   for (int r = 0; r < mr; ++r) {
+    if ((mask[(size_t)r * W + rt / 64] >> (rt % 64)) & 1) corner.push_back(r);
     mask[(size_t)r * W + rt / 64] |= 1ull << (rt % 64);
     for (int w = 0; w < W; ++w)
       for (uint64_t b = mask[(size_t)r * W + w]; b; b &= b - 1) trows[64 * w + __builtin_ctzll(b)].push_back(r);
@@ -480,6 +550,10 @@ static void def_pair_lists(int N, int P, int Pp, int Pr, int n, int ld, const in
       (*out)[2 * p] = I;
       (*out)[2 * p + 1] = J;
       (*out)[2 * np + p] = (int)(out->size() - (3 * (size_t)np + 1));
+      if (I == rt && J == rt) {
+        out->insert(out->end(), corner.begin(), corner.end());
+        continue;
+      }
       const bool a_is_i = trows[I].size() <= trows[J].size();
       const int o = a_is_i ? J : I;
       for (int r : a_is_i ? trows[I] : trows[J])
@@ -530,7 +604,7 @@ dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t 
   const size_t pairs_cap = def_pairs_cap(m, ld);
   const uint64_t bytes = def_align(N * 3 * 8) + def_align(N * DEF_K * 4) + def_align(Pt * 6 * 8) +
                          def_align(Pt * 2 * DEF_K * 4) + def_align(Pt * 2 * DEF_K * 8) + def_align(N * 12 * 8) +
-                         def_align((size_t)m * ld * 8) + def_align((size_t)ld * ld * 8) + def_align(64 * 8) +
+                         def_align((size_t)m * ld * 8) + 2 * def_align((size_t)ld * ld * 8) + def_align(64 * 8) +
                          def_align(4) + def_align(8) + def_align(pairs_cap * 4);
   const uint64_t prev = ctx->used.fetch_add(bytes);
   if (ctx->budget && prev + bytes > ctx->budget) {
@@ -560,6 +634,7 @@ dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t 
   d->x = (double*)q; q += def_align(N * 12 * 8);
   d->Jr = (double*)q; q += def_align((size_t)m * ld * 8);
   d->H = (double*)q; q += def_align((size_t)ld * ld * 8);
+  d->L = (double*)q; q += def_align((size_t)ld * ld * 8);
   d->cost = (double*)q; q += def_align(64 * 8);
   d->bad = (int*)q; q += def_align(4);
   d->tiny = (double*)q; q += def_align(8);
@@ -658,6 +733,7 @@ dslam_status dslam_deform_solve(dslam_deform* d, const dslam_deform_problem* p, 
   dv.x = d->x;
   dv.Jr = d->Jr;
   dv.H = d->H;
+  dv.L = d->L;
   dv.cost = d->cost;
   dv.bad = d->bad;
   dv.tiny = d->tiny;
@@ -671,14 +747,11 @@ dslam_status dslam_deform_solve(dslam_deform* d, const dslam_deform_problem* p, 
                        d->pairs + 3 * np + 1);
     hipLaunchKernelGGL(def_prepare_kernel, dim3(1), dim3(256), 0, st, dv, it);
     for (int kb = 0; kb < dv.n; kb += DEF_PANEL) {
-      hipLaunchKernelGGL(def_panel_kernel, dim3(1), dim3(256), 0, st, dv, kb);
       const int rest = dv.n - kb - DEF_PANEL;
-      if (rest > 0) {
-        const int t = (rest + DEF_TILE - 1) / DEF_TILE;
-        hipLaunchKernelGGL(def_update_kernel, dim3(t, t), dim3(256), 0, st, dv, kb);
-      }
+      const int t = rest > 0 ? (rest + DEF_TILE - 1) / DEF_TILE : 1;
+      hipLaunchKernelGGL(def_chol_kernel, dim3(t * (t + 1) / 2), dim3(256), 0, st, dv, kb);
     }
-    hipLaunchKernelGGL(def_solve_kernel, dim3(1), dim3(1024), 0, st, dv);
+    hipLaunchKernelGGL(def_solve_kernel, dim3(1), dim3(DEF_SOLVE_THREADS), 0, st, dv);
   }
   DEF_HIP(hipGetLastError());
   std::vector<double> cost(iters);
