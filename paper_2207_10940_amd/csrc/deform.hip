@@ -566,19 +566,23 @@ static void def_pair_lists(int N, int P, int Pp, int Pr, int n, int ld, const in
 // distance of the next one.
 static void def_nearest(const double* nodes, int N, const double* v, int exclude, int* idx, double* dist,
                         double* dmax) {
-  std::vector<std::pair<double, int>> c;
-  c.reserve(N);
+  // the K + 1 smallest (distance, index) pairs, kept sorted by insertion
+  std::pair<double, int> best[DEF_K + 1];
+  int nb = 0;
   for (int k = 0; k < N; ++k) {
     if (k == exclude) continue;
     const double dx = v[0] - nodes[3 * k], dy = v[1] - nodes[3 * k + 1], dz = v[2] - nodes[3 * k + 2];
-    c.push_back({std::sqrt(dx * dx + dy * dy + dz * dz), k});
+    const std::pair<double, int> e{std::sqrt(dx * dx + dy * dy + dz * dz), k};
+    if (nb == DEF_K + 1 && !(e < best[DEF_K])) continue;
+    int j = nb < DEF_K + 1 ? nb++ : DEF_K;
+    for (; j > 0 && e < best[j - 1]; --j) best[j] = best[j - 1];
+    best[j] = e;
   }
-  std::sort(c.begin(), c.end());
   for (int k = 0; k < DEF_K; ++k) {
-    idx[k] = c[k].second;
-    dist[k] = c[k].first;
+    idx[k] = best[k].second;
+    dist[k] = best[k].first;
   }
-  *dmax = c[DEF_K].first;
+  *dmax = best[DEF_K].first;
 }
 
 static void def_influence(const double* nodes, int N, const double* v, int* idx, double* w) {
