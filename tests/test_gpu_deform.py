@@ -31,8 +31,13 @@ def _case(seed, n_nodes, n_con, n_pin, n_rel):
     return nodes, con, pin, rel
 
 
+# 6, 7, 13 and 37 nodes give 12 N unknowns that are not a multiple of the
+# 16-column panel: a short last panel, and a residual column that shares its
+# tile with node columns.
 @pytest.mark.parametrize("seed,n_nodes,n_con,n_pin,n_rel,glob", [(1, 16, 40, 20, 0, False), (2, 32, 96, 64, 24, True),
-                                                                  (3, 64, 256, 128, 64, True)])
+                                                                  (3, 64, 256, 128, 64, True), (5, 6, 12, 6, 4, True),
+                                                                  (6, 7, 20, 8, 0, False), (7, 13, 40, 16, 8, True),
+                                                                  (8, 37, 100, 40, 20, True)])
 def test_solve_matches_oracle(seed, n_nodes, n_con, n_pin, n_rel, glob):
     print(f"deform {n_nodes} nodes {n_con}+{n_pin}+{n_rel} points global {glob}", flush=True)
     nodes, con, pin, rel = _case(seed, n_nodes, n_con, n_pin, n_rel)
@@ -53,13 +58,18 @@ def test_solve_matches_oracle(seed, n_nodes, n_con, n_pin, n_rel, glob):
     assert np.abs(x.ravel() - xo).max() < 1e-9
 
 
-def test_yaw_rigid_motion_recovered():
+# 24 nodes, and the largest graphs (256 nodes: 3,072 unknowns, more
+# right-hand-side rows than the triangular solves have threads; 255 nodes:
+# the same with a short last panel), where the exact answer needs no oracle.
+@pytest.mark.parametrize("n_nodes", [24, 255, 256])
+def test_yaw_rigid_motion_recovered(n_nodes):
+    print(f"deform yaw {n_nodes} nodes", flush=True)
     rng = np.random.default_rng(4)
-    nodes = rng.uniform(-1.0, 1.0, size=(24, 3))
+    nodes = rng.uniform(-1.0, 1.0, size=(n_nodes, 3)) * (n_nodes / 24) ** (1 / 3)
     R, t = _rot([0, 0, 1], 5.0), np.array([0.1, -0.05, 0.02])
     src = nodes + rng.normal(size=nodes.shape) * 0.1
     ctx = P.Context(0)
-    df = P.Deform(ctx, 32, 64)
+    df = P.Deform(ctx, max(32, n_nodes), max(64, n_nodes))
     try:
         x, cost = df.solve(nodes, con=[(s, R @ s + t) for s in src], iters=6)
     finally:
