@@ -81,6 +81,38 @@ def test_fuse_and_render_match_oracle(W, H, levels, capacity):
         mp.close()
 
 
+def test_empty_map_and_all_hole_frames():
+    """Degenerate inputs: rendering a map with no surfels, and fusing a frame
+    whose depth is all holes, into an empty and into a filled map."""
+    W, H = 160, 120
+    seq = synth.configs.sequence(seed=3003, n_frames=2, width=W, height=H)
+    cam = seq["camera"]
+    K = (cam.fx, cam.fy, cam.cx, cam.cy)
+    holes = np.zeros((H, W), dtype=np.float32)
+    with session(W, H, 2, [1, 1], mode="rgbd") as s:
+        mp = P.Map(s.ctx, cam, 10**5)
+        om = M.empty_map()
+        T0 = _pose(seq["gt"][0])
+        dg = torch.full((H, W), 7.0, dtype=torch.float32, device="cuda")
+        ig = torch.full((H, W), 9, dtype=torch.uint8, device="cuda")
+        mp.render(T0, dg, ig)
+        torch.cuda.synchronize()
+        do, io = M.render(om, T0, K, W, H)
+        assert np.array_equal(dg.cpu().numpy().view(np.uint32), do.view(np.uint32))
+        assert np.array_equal(ig.cpu().numpy(), io)
+        assert not do.any()
+        inten = seq["intensity"][0].numpy()
+        for j, depth in enumerate((holes, seq["depth"][0].numpy(), holes)):
+            s.build_pyramid(P.PYR_CURRENT, cuda(depth), cuda(inten))
+            mp.fuse(s, T0)
+            V, N, I16 = _oracle_frame(depth, inten, cam, 2)
+            om, d = M.fuse(om, V, N, I16, T0, K, W, H, capacity=10**5)
+            assert mp.count() == (len(om["px"]), d), j
+            _assert_same_map(mp.arrays(), om)
+        assert len(om["px"]) > 0
+        mp.close()
+
+
 def test_reset_and_errors():
     seq = synth.configs.sequence(seed=3002, n_frames=1, width=160, height=120)
     cam = seq["camera"]
