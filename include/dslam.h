@@ -402,7 +402,11 @@ typedef struct {
 
 /* Allocate a solver for up to max_nodes (6..256) nodes and max_points
  * constraint points (con + pin + rel) on the context's device (counted
- * against its budget).  Errors: INVALID, NO_CAPACITY. */
+ * against its budget).  The system is held dense: with n = 12 max_nodes
+ * unknowns and m = 24 max_nodes + 3 max_points residual rows (both rounded
+ * up to 16), about 8 (m (n + 1) + 2 (n + 1)^2) + 612 m bytes ([J r], the
+ * normal matrix, its factor, the per-tile row lists): 328 MB at 256 nodes
+ * and 256 points.  Errors: INVALID, NO_CAPACITY. */
 dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t max_points, dslam_deform** out);
 dslam_status dslam_deform_destroy(dslam_deform* d);
 /* Minimise E by `iters` (1..63) Gauss-Newton steps from A = I, t = 0 on the
