@@ -126,6 +126,36 @@ def run_gpu(args):
         f"{accuracy['windows'][-1]['vel_err_mps']:.2e} m/s, gyro bias {accuracy['windows'][-1]['bg_err_radps']:.2e} "
         f"rad/s, accel bias {accuracy['windows'][-1]['ba_err_mps2']:.2e} m/s^2 (last window)")
 
+    # launch modes (outside the timed region): the frame's Gauss-Newton launches replayed from per-level HIP
+    # graphs, or issued one by one; the same frames, throughput and latency as above
+    launch_modes = {}
+    default_graphs = sess.graphs
+    for name, on in (("graphs", True), ("eager", False)):
+        sess.set_graphs(on)
+        sess.set_state(*x_init)
+        for k in range(args.warmup):
+            track(k)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(args.warmup, args.warmup + args.steps):
+            track(k)
+        torch.cuda.synchronize()
+        fps = args.steps / (time.perf_counter() - t)
+        sess.set_state(*x_init)
+        ml = []
+        for k in range(n_lat):
+            t = time.perf_counter()
+            track(k)
+            sess.result()
+            ml.append((time.perf_counter() - t) * 1e3)
+        ml = np.array(ml[5:] if len(ml) > 10 else ml)
+        launch_modes[name] = {"frames_per_s": fps, "latency_p50_ms": float(np.percentile(ml, 50)),
+                              "latency_p99_ms": float(np.percentile(ml, 99))}
+        log(f"[bench] {name}: {fps:.0f} frames/s, latency p50 {launch_modes[name]['latency_p50_ms']:.3f} ms "
+            f"p99 {launch_modes[name]['latency_p99_ms']:.3f} ms")
+    sess.set_graphs(default_graphs)
+    launch_modes["default"] = "graphs" if default_graphs else "eager"
+
     # dominant kernel: the level-0 residual pass, timed back to back with events on the same stream
     reps = args.kernel_reps
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -146,6 +176,7 @@ def run_gpu(args):
                        "frames": int(len(lat)), "kind": "host submit to result, one frame at a time"},
         "pose_err_final_m": pos_err,
         "accuracy": accuracy,
+        "launch_modes": launch_modes,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "residual_kernel<2> (level 0, 640x480)", "kernel_us": k_ms * 1e3,
@@ -808,7 +839,7 @@ def main():
                                "IMU 200 Hz, procedural 3-plane/4-sphere scene", "width": 640, "height": 480,
                    "levels": 3, "iters": [10, 5, 4], "jac_format": "fp32", "frames": args.steps},
         "latency_ms": g["latency_ms"], "pose_err_final_m": g["pose_err_final_m"], "accuracy": g["accuracy"],
-        "roofline": g["roofline"], "cpu_baseline": cpu, "serving": serving, "stress": stress,
+        "launch_modes": g["launch_modes"], "roofline": g["roofline"], "cpu_baseline": cpu, "serving": serving, "stress": stress,
         "robustness": robust, "mapping": mapping,
     }
     print(json.dumps(out), flush=True)

@@ -292,6 +292,17 @@ dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const u
  * T_WM. */
 dslam_status dslam_track_frame_input(dslam_session* s, const dslam_frame_input* in, void* stream);
 
+/* How dslam_track_frame and dslam_track_frame_input issue a frame's
+ * Gauss-Newton launches after the first.  enable = 1: each level's
+ * iterations (residual pass, step) are captured in a HIP graph at the first
+ * frame that needs them and replayed from then on, one graph launch per
+ * level; the first launch stores the frame's inputs in device memory for
+ * them.  enable = 0 (the default, faster while the host keeps ahead of the
+ * device): every launch is issued on its own.  Both give the same results bit
+ * for bit.  Errors: INVALID (enable not 0 or 1); a failed capture makes the
+ * tracking call return DEVICE. */
+dslam_status dslam_session_set_graphs(dslam_session* s, int32_t enable);
+
 /* Surfel map: the dense model the tracker aligns to (the mapping step the
  * paper keeps from its RGB-D base system, Sections III and V).  A map holds
  * up to `capacity` surfels (world position, unit normal, intensity, radius,

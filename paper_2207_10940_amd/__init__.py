@@ -254,6 +254,17 @@ class Session:
                                        int(depth.shape[1]), arr, n, float(t0), float(t1), _stream_ptr(stream)),
                "dslam_track_frame")
 
+    def set_graphs(self, enable: bool):
+        """Replay each level's Gauss-Newton launches from a captured HIP graph (True) or issue them one by
+        one (False); the results are the same (dslam_session_set_graphs)."""
+        _check(lib().dslam_session_set_graphs(self.handle, 1 if enable else 0), "dslam_session_set_graphs")
+        self._graphs = bool(enable)
+
+    @property
+    def graphs(self) -> bool:
+        """Whether the session replays captured graphs (the library's default until set_graphs)."""
+        return getattr(self, "_graphs", SESSION_GRAPHS_DEFAULT)
+
     def track_frame_input(self, frame: dict, stream=None):
         """Enqueue one tracking step with its model view: frame = dict(depth, intensity, model_depth,
         model_intensity, T_WM, imu, t0, t1) as for Batch.track; both pyramids are built in the launch
@@ -329,6 +340,8 @@ def frame_input(f: dict):
 
 
 MAP_FIELDS = ("px", "py", "pz", "nx", "ny", "nz", "inten", "radius", "conf")
+# the library's launch mode of a newly opened session (dslam_session_set_graphs)
+SESSION_GRAPHS_DEFAULT = False
 
 
 class Map:

@@ -133,6 +133,7 @@ SIGNATURES = {
     "dslam_batch_destroy": (C.c_int, [vp]),
     "dslam_batch_track": (C.c_int, [vp, C.c_int32, P(vp), P(FrameInput), vp]),
     "dslam_track_frame_input": (C.c_int, [vp, P(FrameInput), vp]),
+    "dslam_session_set_graphs": (C.c_int, [vp, C.c_int32]),
     "dslam_batch_results": (C.c_int, [vp, P(TrackResult)]),
     "dslam_batch_profile_residual": (C.c_int, [vp, C.c_int32, C.c_int32, vp, P(C.c_uint64)]),
     "dslam_server_create": (C.c_int, [vp, P(ServerParams), P(vp)]),

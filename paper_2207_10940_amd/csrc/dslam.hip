@@ -89,7 +89,7 @@ Layout layout_for(const dslam_camera& c, int levels) {
   lo.max_blocks = nb;
   lo.partial_floats = (size_t)nb * PARTIAL_STRIDE;
   lo.total = planes + align256(lo.partial_floats * sizeof(float)) + align256(sizeof(SessionDev)) +
-             align256(64 * sizeof(double)) + align256(24 * sizeof(float));
+             align256(64 * sizeof(double)) + align256(24 * sizeof(float)) + align256(sizeof(SolveParams));
   return lo;
 }
 
@@ -270,6 +270,9 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   s->bytes = lo.total;
   s->have_model = false;
   s->max_blocks = lo.max_blocks;
+  s->use_graphs = false;
+  s->capture = nullptr;
+  for (int l = 0; l < DSLAM_MAX_LEVELS; ++l) s->graph[l] = nullptr;
   for (int i = 0; i < 16; ++i) s->T_WM[i] = (i % 5 == 0) ? 1.0 : 0.0;
   auto fail = [&](dslam_status st) {
     if (s->arena) (void)hipFree(s->arena);
@@ -304,7 +307,8 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   s->partials = (float*)p; p += align256(lo.partial_floats * sizeof(float));
   s->sd = (SessionDev*)p; p += align256(sizeof(SessionDev));
   s->red_out = (double*)p; p += align256(64 * sizeof(double));
-  s->xf_scratch = (float*)p;
+  s->xf_scratch = (float*)p; p += align256(24 * sizeof(float));
+  s->sp_dev = (SolveParams*)p;
   SessionDev init;
   std::memset(&init, 0, sizeof(init));
   init.x0 = *x0;
@@ -421,10 +425,20 @@ dslam_status dslam_context_autotune(dslam_context* ctx, const dslam_camera* cams
   return DSLAM_OK;
 }
 
+static void drop_graphs(dslam_session* s) {
+  for (int l = 0; l < DSLAM_MAX_LEVELS; ++l)
+    if (s->graph[l]) {
+      (void)hipGraphExecDestroy(s->graph[l]);
+      s->graph[l] = nullptr;
+    }
+}
+
 dslam_status dslam_session_close(dslam_session* s) {
   if (!s) return DSLAM_ERR_INVALID;
   (void)hipSetDevice(s->ctx->device);
   (void)hipDeviceSynchronize();
+  drop_graphs(s);
+  if (s->capture) (void)hipStreamDestroy(s->capture);
   (void)hipEventDestroy(s->done);
   (void)hipFree(s->arena);
   s->ctx->used.fetch_sub(s->bytes);
@@ -522,6 +536,44 @@ dslam_status dslam_solve_step(const double raw[58], const double T_WM[16], const
 // Enqueues one frame; with a model view (mdepth != nullptr) its pyramid is
 // built in the same launch as the current frame's and the frame's
 // initialisation.  Arguments validated by the callers.
+// Captures, once per session, each level's Gauss-Newton iterations (residual
+// pass, then the step reading its parameters from sp_dev) into a graph on a
+// private stream.  Every argument of these launches is fixed for the session
+// (device pointers, sizes, the level's schedule), so the graphs replay
+// unchanged; the frame's own inputs reach them through device memory written
+// by the frame's first launch.
+static dslam_status capture_graphs(dslam_session* s) {
+  bool complete = true;
+  for (int l = 0; l < s->levels; ++l) complete = complete && (s->tp.iters[l] <= 0 || s->graph[l]);
+  if (complete) return DSLAM_OK;
+  if (!s->capture) HIP_OK(hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking));
+  const int last_level = last_level_of(s->tp);
+  for (int l = 0; l < s->levels; ++l) {
+    if (s->tp.iters[l] <= 0 || s->graph[l]) continue;
+    const ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
+    const int nb = residual_blocks(ra.npix, s->ppt[l]);
+    HIP_OK(hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < s->tp.iters[l] && e == hipSuccess; ++it) {
+      e = launch_residual(ra, s->ppt[l], s->capture);
+      if (e == hipSuccess)
+        e = launch_solve_graph(s->sd, s->partials, s->sp_dev, l, (l == last_level && it == s->tp.iters[l] - 1) ? 1 : 0,
+                               nb, s->capture);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(s->capture, &g);
+    if (e == hipSuccess) e = ee;
+    if (e == hipSuccess) e = hipGraphInstantiate(&s->graph[l], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      s->graph[l] = nullptr;
+      drop_graphs(s);
+      return DSLAM_ERR_DEVICE;
+    }
+  }
+  return DSLAM_OK;
+}
+
 static dslam_status track_enqueue(dslam_session* s, const float* depth, const uint8_t* inten, int32_t pitch,
                                   const float* mdepth, const uint8_t* minten, int32_t mpitch, const double* T_WM,
                                   const ImuBatch& batch, hipStream_t st) {
@@ -534,21 +586,38 @@ static dslam_status track_enqueue(dslam_session* s, const float* depth, const ui
   const PyrArgs cur = pyr_args(s, DSLAM_PYR_CURRENT, depth, inten, pitch);
   PyrArgs model;
   if (mdepth) model = pyr_args(s, DSLAM_PYR_MODEL, mdepth, minten, mpitch);
-  HIP_OK(launch_frame_init_pyramid(s->sd, batch, fa, cur, mdepth ? &model : nullptr, st));
+  if (s->use_graphs) {
+    dslam_status gs = capture_graphs(s);
+    if (gs != DSLAM_OK) return gs;
+  }
+  HIP_OK(launch_frame_init_pyramid(s->sd, batch, fa, cur, mdepth ? &model : nullptr, s->use_graphs ? s->sp_dev : nullptr,
+                                   st));
   if (mdepth) s->have_model = true;
-  const int last_level = last_level_of(s->tp);
-  for (int l = s->levels - 1; l >= 0; --l) {
-    ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
-    int nb = residual_blocks(ra.npix, s->ppt[l]);
-    for (int it = 0; it < s->tp.iters[l]; ++it) {
-      HIP_OK(launch_residual(ra, s->ppt[l], st));
-      sa.level = l;
-      sa.nblocks = nb;
-      sa.last = (l == last_level && it == s->tp.iters[l] - 1) ? 1 : 0;
-      HIP_OK(launch_solve(s->sd, s->partials, sa, st));
+  if (s->use_graphs) {
+    for (int l = s->levels - 1; l >= 0; --l)
+      if (s->graph[l]) HIP_OK(hipGraphLaunch(s->graph[l], st));
+  } else {
+    const int last_level = last_level_of(s->tp);
+    for (int l = s->levels - 1; l >= 0; --l) {
+      ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
+      int nb = residual_blocks(ra.npix, s->ppt[l]);
+      for (int it = 0; it < s->tp.iters[l]; ++it) {
+        HIP_OK(launch_residual(ra, s->ppt[l], st));
+        sa.level = l;
+        sa.nblocks = nb;
+        sa.last = (l == last_level && it == s->tp.iters[l] - 1) ? 1 : 0;
+        HIP_OK(launch_solve(s->sd, s->partials, sa, st));
+      }
     }
   }
   HIP_OK(hipEventRecord(s->done, st));
+  return DSLAM_OK;
+}
+
+dslam_status dslam_session_set_graphs(dslam_session* s, int32_t enable) {
+  if (!s || (enable != 0 && enable != 1)) return DSLAM_ERR_INVALID;
+  std::lock_guard<std::mutex> g(s->mu);
+  s->use_graphs = enable == 1;
   return DSLAM_OK;
 }
 

@@ -38,6 +38,12 @@ struct dslam_session {
   bool have_model;
   double T_WM[16];
   int ppt[DSLAM_MAX_LEVELS];
+  // a frame's Gauss-Newton launches after the first, one graph per level,
+  // captured at the first frame that uses them (null: not captured yet)
+  dslam::SolveParams* sp_dev;  // device: the frame's solve parameters
+  bool use_graphs;
+  hipStream_t capture;
+  hipGraphExec_t graph[DSLAM_MAX_LEVELS];
   std::mutex mu;
 };
 

@@ -139,14 +139,22 @@ __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& 
   }
 }
 
-// Workgroup 0 initialises the frame; the others build the current frame's
-// pyramid (cur) and, if model_tiles > 0, the model view's (model), one tile
-// each, while it runs (the three touch disjoint memory).
+// Workgroup 0 initialises the frame (and, if sp_out is not null, stores the
+// frame's solve parameters there for solve_graph_kernel); the others build the
+// current frame's pyramid (cur) and, if model_tiles > 0, the model view's
+// (model), one tile each, while it runs (the three touch disjoint memory).
 __global__ __launch_bounds__(SOLVE_THREADS) void frame_init_pyramid_kernel(SessionDev* sd, ImuBatch batch,
                                                                            FrameArgs fa, PyrArgs cur, PyrArgs model,
-                                                                           int cur_tiles) {
+                                                                           int cur_tiles, SolveParams* sp_out) {
   if (blockIdx.x == 0) {
     frame_init_body(sd, batch, fa);
+    if (sp_out && threadIdx.x == 0) {
+      for (int i = 0; i < 9; ++i) sp_out->R_WM[i] = fa.R_WM[i];
+      for (int i = 0; i < 3; ++i) sp_out->t_WM[i] = fa.t_WM[i];
+      sp_out->imu = fa.imu;
+      sp_out->mode = fa.mode;
+      sp_out->marginalise = 1;
+    }
     return;
   }
   const int t = (int)blockIdx.x - 1;
@@ -159,7 +167,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void frame_init_pyramid_kernel(Sessi
     pyramid_tile<SOLVE_THREADS, 64, 16>(model.src, model.L, model.levels, model.with_grad, t - cur_tiles, lds,
                                         (int)threadIdx.x);
 }
-static_assert(sizeof(SessionDev*) + sizeof(ImuBatch) + sizeof(FrameArgs) + 2 * sizeof(PyrArgs) + 16 <= 4096,
+static_assert(sizeof(SessionDev*) + sizeof(ImuBatch) + sizeof(FrameArgs) + 2 * sizeof(PyrArgs) + 24 <= 4096,
               "frame-init arguments exceed the kernel-argument segment");
 
 // Batched: one workgroup per session of the batch.  (The batched pyramids run
@@ -328,6 +336,15 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, co
   solve_body(sd, partials, a.sp, a.level, a.last, a.nblocks);
 }
 
+// The same step with the solve parameters in device memory (stored by the
+// frame's first launch), so that a frame's launches after the first are the
+// same at every frame and can be replayed from a captured graph.
+__global__ __launch_bounds__(SOLVE_THREADS) void solve_graph_kernel(SessionDev* sd, const float* partials,
+                                                                    const SolveParams* sp, int level, int last,
+                                                                    int nblocks) {
+  solve_body(sd, partials, *sp, level, last, nblocks);
+}
+
 __global__ __launch_bounds__(SOLVE_THREADS) void solve_batch_kernel(const SlotSolve* slots, int level, int last) {
   const SlotSolve* s = slots + blockIdx.x;
   solve_body(s->sd, s->partials, s->sp, level, last, s->nblocks[level]);
@@ -347,17 +364,23 @@ hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& 
   return hipGetLastError();
 }
 
+hipError_t launch_solve_graph(SessionDev* sd, const float* partials, const SolveParams* sp, int level, int last,
+                              int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(solve_graph_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, sd, partials, sp, level, last, nblocks);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(REDUCE_THREADS), 0, st, partials, nblocks, out);
   return hipGetLastError();
 }
 
 hipError_t launch_frame_init_pyramid(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, const PyrArgs& cur,
-                                     const PyrArgs* model, hipStream_t st) {
+                                     const PyrArgs* model, SolveParams* sp_out, hipStream_t st) {
   const int ct = PyrTileBig::tiles(cur.L[0].W, cur.L[0].H);
   const int mt = model ? PyrTileBig::tiles(model->L[0].W, model->L[0].H) : 0;
   hipLaunchKernelGGL(frame_init_pyramid_kernel, dim3(1 + ct + mt), dim3(SOLVE_THREADS), 0, st, sd, b, fa, cur,
-                     model ? *model : cur, ct);
+                     model ? *model : cur, ct, sp_out);
   return hipGetLastError();
 }
 

@@ -56,10 +56,14 @@ hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int l
 
 // solve.hip
 // the frame initialisation, the current frame's pyramid and (model != nullptr)
-// the model view's pyramid in one launch
+// the model view's pyramid in one launch; if sp_out is not null the frame's
+// solve parameters are stored there for launch_solve_graph
 hipError_t launch_frame_init_pyramid(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, const PyrArgs& cur,
-                                     const PyrArgs* model, hipStream_t st);
+                                     const PyrArgs* model, SolveParams* sp_out, hipStream_t st);
 hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& a, hipStream_t st);
+// the same step with the solve parameters read from device memory
+hipError_t launch_solve_graph(SessionDev* sd, const float* partials, const SolveParams* sp, int level, int last,
+                              int nblocks, hipStream_t st);
 hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st);
 hipError_t launch_frame_init_batch(const SlotSolve* slots, int n, hipStream_t st);
 hipError_t launch_solve_batch(const SlotSolve* slots, int n, int level, int last, hipStream_t st);
