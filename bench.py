@@ -195,7 +195,7 @@ def run_counters(args):
     W, H = 640, 480
     seq = make_sequence(4, W, H, "cuda")
     ctx = P.Context(0)
-    tp = P.track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32")
+    tp = P.track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac=args.counters_jac)
     sess = P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], seq["prior"])
     stream = torch.cuda.current_stream()
     for j in range(1, 4):
@@ -213,7 +213,8 @@ def run_counters(args):
     torch.cuda.synchronize()
     sess.close()
     ctx.close()
-    print(json.dumps({"counters_run": True, "residual_reps": args.kernel_reps, "residual_pixels": W * H,
+    print(json.dumps({"counters_run": True, "jac": args.counters_jac, "residual_reps": args.kernel_reps,
+                      "residual_pixels": W * H,
                       "copy_bytes_each_way": COPY_BYTES, "copy_reps": 3}), flush=True)
 
 
@@ -802,6 +803,8 @@ def main():
     ap.add_argument("--robustness-only", action="store_true", help="only run the robustness comparison")
     ap.add_argument("--counters", action="store_true",
                     help="only run the level-0 residual pass and a calibration copy (for rocprofv3 --pmc)")
+    ap.add_argument("--counters-jac", default="fp32", choices=("fp32", "fp32_mfma", "fp16", "bf16"),
+                    help="row format of the --counters run (the matrix-core forms for MFMA counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the tracking step shards by session (one process per GPU), and only "
