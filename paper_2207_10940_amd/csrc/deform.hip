@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void def_normal_kernel(DefDev d, const int* ti
 
 // Blocked right-looking Cholesky of the n x n normal matrix (lower triangle,
 // into L), panel by panel of DEF_PANEL columns, one launch of def_chol_kernel
-// per panel; def_solve_kernel then solves L L^T dx = -J^T r and updates the
+// per DEF_NP panels; def_solve_kernel then solves L L^T dx = -J^T r and updates the
 // parameters.  A pivot at or below 1e-12 of the largest diagonal entry of the
 // normal matrix marks the system singular (def_prepare_kernel also records
 // the step's cost r^T r, summed over the residual column of [J r]).
@@ -232,23 +232,31 @@ __device__ __forceinline__ double def_lane(double v, int l) {
                           __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// One step of the blocked right-looking Cholesky, for the panel of DEF_PANEL
-// columns at kb, in a single launch.  The factor goes to the separate matrix
-// L, so that the panel's columns of H stay as they were for every workgroup
-// to read; the panel below the diagonal is also written transposed into L's
-// otherwise unused upper triangle, where the forward solve reads it by rows.
-// Workgroup p owns the p-th lower trailing tile (rows i0, columns j0, both
-// past the panel): it factors the panel's diagonal block in LDS, solves its
-// two row blocks of the panel against it (x L^T = h, one thread per row),
-// subtracts their product from its tile of H, and writes its row block of the
-// factor if the tile is in the first trailing column (the first tile also
-// writes the diagonal block and flags a bad pivot).  The last panel has no
-// trailing tile and runs one workgroup that only factors.
+// One step of the blocked right-looking Cholesky, for the macro panel of up
+// to DEF_NP panels of DEF_PANEL columns at kb, in a single launch.  The
+// factor goes to the separate matrix L, so that the macro panel's columns of H
+// stay as they were for every workgroup to read; its part below each panel's
+// diagonal block is also written transposed into L's otherwise unused upper
+// triangle, where the forward solve reads it by rows.  Workgroup p owns the
+// p-th lower trailing tile (rows i0, columns j0, both past the macro panel).
+// Panel by panel (left-looking within the macro panel) it updates the
+// panel's diagonal block, the later panels' rows and its own two row blocks
+// with the earlier panels' columns, factors the diagonal block in LDS and
+// solves those rows against it (x L^T = h, one thread per row); it then
+// subtracts its row blocks' product from its tile of H.  A tile in the first
+// trailing column writes its row blocks of the factor (the first tile also
+// the macro panel's diagonal part and the bad-pivot flag).  The last macro
+// panel has no trailing tile and runs one workgroup that only factors.
+constexpr int DEF_NP = 2;
+
 __global__ __launch_bounds__(256) void def_chol_kernel(DefDev d, int kb) {
-  __shared__ double D[DEF_PANEL][DEF_PANEL + 1];
-  __shared__ double Li[DEF_TILE][DEF_PANEL + 1], Lj[DEF_TILE][DEF_PANEL + 1];
+  // Dd[c][a]: rows of panel c, columns of panel a (a <= c); R[s][a]: the
+  // tile's row block s (0: rows i0.., 1: rows j0..), columns of panel a
+  __shared__ double Dd[DEF_NP][DEF_NP][DEF_PANEL][DEF_PANEL + 1];
+  __shared__ double R[2][DEF_NP][DEF_TILE][DEF_PANEL + 1];
   const int n = d.n, ld = d.ld, tid = threadIdx.x;
-  const int bs = min(DEF_PANEL, n - kb), base = kb + bs;
+  const int np = min(DEF_NP, (n - kb + DEF_PANEL - 1) / DEF_PANEL);
+  const int base = min(kb + DEF_NP * DEF_PANEL, n);
   const int p = blockIdx.x;
   int ti = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
   while (ti * (ti + 1) / 2 > p) --ti;
@@ -258,43 +266,65 @@ __global__ __launch_bounds__(256) void def_chol_kernel(DefDev d, int kb) {
   const bool first = p == 0;
   double* H = d.H;
   double* L = d.L;
-  {
-    const int r = tid / DEF_PANEL, c = tid % DEF_PANEL;
-    D[r][c] = (r < bs && c <= r) ? H[(size_t)(kb + r) * ld + kb + c] : 0.0;
+  auto width = [&](int a) { return min(DEF_PANEL, n - (kb + DEF_PANEL * a)); };
+  const int r = tid / DEF_PANEL, col = tid % DEF_PANEL;
+  for (int c = 0; c < DEF_NP; ++c)
+    for (int a = 0; a < DEF_NP; ++a) {
+      const bool in = c < np && a <= c && r < width(c) && col < width(a) && (a < c || col <= r);
+      Dd[c][a][r][col] = in ? H[(size_t)(kb + DEF_PANEL * c + r) * ld + kb + DEF_PANEL * a + col] : 0.0;
+    }
+  for (int sb = 0; sb < 2; ++sb) {
+    const int row = (sb ? j0 : i0) + r;
+    for (int a = 0; a < DEF_NP; ++a)
+      R[sb][a][r][col] = (a < np && row < n && col < width(a)) ? H[(size_t)row * ld + kb + DEF_PANEL * a + col] : 0.0;
   }
-  const int row = tid < DEF_TILE ? i0 + tid : j0 + tid - DEF_TILE;
-  const bool has = tid < 2 * DEF_TILE && row < n;
-  double x[DEF_PANEL];
-#pragma unroll
-  for (int c = 0; c < DEF_PANEL; ++c) x[c] = (has && c < bs) ? H[(size_t)row * ld + kb + c] : 0.0;
   __syncthreads();
   const double tiny = *d.tiny;
-  for (int k = 0; k < bs; ++k) {  // unblocked Cholesky of the diagonal block
-    if (tid == 0) {
-      const double pv = D[k][k];
-      if (first && (!(pv > tiny) || !(pv < 1e300))) *d.bad = 1;
-      D[k][k] = sqrt(pv > 0.0 ? pv : 1.0);
+  for (int a = 0; a < np; ++a) {
+    const int bs = width(a);
+    if (a > 0) {  // the earlier panels' contribution to this panel's columns
+      const int blocks = np - a + 2;
+      for (int e = tid; e < blocks * 256; e += 256) {
+        const int blk = e / 256, rr = (e % 256) / DEF_PANEL, cc = e % DEF_PANEL;
+        const int c = a + blk;
+        if (blk < np - a && c == a && cc > rr) continue;
+        double* X = blk < np - a ? &Dd[c][a][rr][cc] : &R[blk - (np - a)][a][rr][cc];
+        double acc = 0.0;
+        for (int b2 = 0; b2 < a; ++b2) {
+          const double* xr = blk < np - a ? Dd[c][b2][rr] : R[blk - (np - a)][b2][rr];
+#pragma unroll
+          for (int k = 0; k < DEF_PANEL; ++k) acc += xr[k] * Dd[a][b2][cc][k];
+        }
+        *X -= acc;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    const double piv = D[k][k];
-    if (tid > k && tid < bs) D[tid][k] /= piv;
-    __syncthreads();
-    {
-      const int r = tid / DEF_PANEL, c = tid % DEF_PANEL;
-      if (c > k && r >= c && r < bs) D[r][c] -= D[r][k] * D[c][k];
+    double (*D)[DEF_PANEL + 1] = Dd[a][a];
+    for (int k = 0; k < bs; ++k) {  // unblocked Cholesky of the diagonal block
+      if (tid == 0) {
+        const double pv = D[k][k];
+        if (first && (!(pv > tiny) || !(pv < 1e300))) *d.bad = 1;
+        D[k][k] = sqrt(pv > 0.0 ? pv : 1.0);
+      }
+      __syncthreads();
+      const double piv = D[k][k];
+      if (tid > k && tid < bs) D[tid][k] /= piv;
+      __syncthreads();
+      if (col > k && r >= col && r < bs) D[r][col] -= D[r][k] * D[col][k];
+      __syncthreads();
     }
+    // a short last block is padded with identity rows, so that the solves
+    // below run over all DEF_PANEL columns with the row in registers
+    if (tid >= bs && tid < DEF_PANEL) D[tid][tid] = 1.0;
     __syncthreads();
-  }
-  if (first) {
-    const int r = tid / DEF_PANEL, c = tid % DEF_PANEL;
-    if (r < bs && c <= r) L[(size_t)(kb + r) * ld + kb + c] = D[r][c];
-  }
-  // a short last block is padded with identity rows, so that the solves
-  // below run over all DEF_PANEL columns with the row in registers
-  if (tid >= bs && tid < DEF_PANEL) D[tid][tid] = 1.0;
-  __syncthreads();
-  if (tid < 2 * DEF_TILE) {
-    if (has) {
+    // rows of the later panels, then the tile's two row blocks, against D
+    const int nrows = DEF_PANEL * (np - 1 - a) + 2 * DEF_TILE;
+    if (tid < nrows) {
+      const int blk = tid / DEF_PANEL, rr = tid % DEF_PANEL;
+      double* xr = blk < np - 1 - a ? Dd[a + 1 + blk][a][rr] : R[blk - (np - 1 - a)][a][rr];
+      double x[DEF_PANEL];
+#pragma unroll
+      for (int c = 0; c < DEF_PANEL; ++c) x[c] = xr[c];
 #pragma unroll
       for (int c = 0; c < DEF_PANEL; ++c) {
         double v = x[c];
@@ -302,25 +332,33 @@ __global__ __launch_bounds__(256) void def_chol_kernel(DefDev d, int kb) {
         for (int c2 = 0; c2 < c; ++c2) v -= x[c2] * D[c][c2];
         x[c] = v / D[c][c];
       }
-      if (tid < DEF_TILE && tj == 0)
 #pragma unroll
-        for (int c = 0; c < DEF_PANEL; ++c)
-          if (c < bs) {
-            L[(size_t)row * ld + kb + c] = x[c];
-            L[(size_t)(kb + c) * ld + row] = x[c];
-          }
+      for (int c = 0; c < DEF_PANEL; ++c) xr[c] = c < bs ? x[c] : 0.0;
     }
-    double* dst = tid < DEF_TILE ? Li[tid] : Lj[tid - DEF_TILE];
-#pragma unroll
-    for (int c = 0; c < DEF_PANEL; ++c) dst[c] = (has && c < bs) ? x[c] : 0.0;
+    __syncthreads();
   }
-  __syncthreads();
+  if (first)  // the macro panel's diagonal part
+    for (int c = 0; c < np; ++c)
+      for (int a = 0; a <= c; ++a)
+        if (r < width(c) && col < width(a) && (a < c || col <= r)) {
+          const int gr = kb + DEF_PANEL * c + r, gc = kb + DEF_PANEL * a + col;
+          L[(size_t)gr * ld + gc] = Dd[c][a][r][col];
+          if (a < c) L[(size_t)gc * ld + gr] = Dd[c][a][r][col];
+        }
+  if (tj == 0 && i0 + r < n)  // the first trailing column's row blocks
+    for (int a = 0; a < np; ++a)
+      if (col < width(a)) {
+        const int gr = i0 + r, gc = kb + DEF_PANEL * a + col;
+        L[(size_t)gr * ld + gc] = R[0][a][r][col];
+        L[(size_t)gc * ld + gr] = R[0][a][r][col];
+      }
   const int tx = tid % DEF_TILE, ty = tid / DEF_TILE;
   const int i = i0 + ty, j = j0 + tx;
   if (i < n && j <= i) {
     double acc = 0.0;
+    for (int a = 0; a < np; ++a)
 #pragma unroll
-    for (int c = 0; c < DEF_PANEL; ++c) acc += Li[ty][c] * Lj[tx][c];
+      for (int c = 0; c < DEF_PANEL; ++c) acc += R[0][a][ty][c] * R[1][a][tx][c];
     H[(size_t)i * ld + j] -= acc;
   }
 }
@@ -750,8 +788,8 @@ dslam_status dslam_deform_solve(dslam_deform* d, const dslam_deform_problem* p, 
     hipLaunchKernelGGL(def_normal_kernel, dim3(np), dim3(256), 0, st, dv, d->pairs, d->pairs + 2 * np,
                        d->pairs + 3 * np + 1);
     hipLaunchKernelGGL(def_prepare_kernel, dim3(1), dim3(256), 0, st, dv, it);
-    for (int kb = 0; kb < dv.n; kb += DEF_PANEL) {
-      const int rest = dv.n - kb - DEF_PANEL;
+    for (int kb = 0; kb < dv.n; kb += DEF_NP * DEF_PANEL) {
+      const int rest = dv.n - kb - DEF_NP * DEF_PANEL;
       const int t = rest > 0 ? (rest + DEF_TILE - 1) / DEF_TILE : 1;
       hipLaunchKernelGGL(def_chol_kernel, dim3(t * (t + 1) / 2), dim3(256), 0, st, dv, kb);
     }
