@@ -112,3 +112,31 @@ def test_energy_decreases_over_gauss_newton_steps():
         x = D.solve(prob, iters=1, x0=x)
         e.append(D.energy(x, prob))
     assert all(b <= a * (1 + 1e-12) for a, b in zip(e, e[1:])) and e[-1] < e[0]
+
+
+@pytest.mark.parametrize("n_side,seed", [(2, 7), (3, 8)])
+def test_gauss_newton_reaches_the_least_squares_minimiser(n_side, seed):
+    """The converged Gauss-Newton parameters equal scipy's trust-region least-squares minimiser of the same
+    weighted residuals (started from the same identity parameters).  The constraints conflict (non-zero
+    residual at the minimum), where Gauss-Newton converges linearly: 60 steps."""
+    from scipy.optimize import least_squares
+    rng = np.random.default_rng(seed)
+    g = np.arange(n_side) * 0.5
+    nodes = np.array([[x, y, z] for x in g for y in g for z in (0.0, 0.4, 0.8)], dtype=np.float64)
+    src = nodes[rng.integers(0, len(nodes), 8)] + rng.normal(size=(8, 3)) * 0.1
+    R = _rot(rng.normal(size=3), 4.0)
+    prob = D.problem(nodes, con=[(s, R @ s + np.array([0.03, -0.02, 0.01]) + rng.normal(size=3) * 0.01)
+                                 for s in src],
+                     pin=list(nodes[:2] + 0.05), rel=[(src[0], src[1] + 0.01)], global_=True)
+
+    def stacked(x):
+        return np.concatenate([np.sqrt(w) * r for w, r, _ in D.residuals(x, prob)])
+
+    def jac(x):
+        return np.vstack([np.sqrt(w) * J for w, _, J in D.residuals(x, prob)])
+
+    x0 = D.identity_params(len(nodes))
+    x_gn = D.solve(prob, iters=60)
+    ls = least_squares(stacked, x0, jac=jac, xtol=1e-15, ftol=1e-15, gtol=1e-15, max_nfev=500)
+    assert abs(D.energy(x_gn, prob) - 2 * ls.cost) <= 1e-12 * max(D.energy(x_gn, prob), 1e-30)
+    assert np.abs(x_gn - ls.x).max() < 1e-6
