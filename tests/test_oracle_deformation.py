@@ -140,3 +140,48 @@ def test_gauss_newton_reaches_the_least_squares_minimiser(n_side, seed):
     ls = least_squares(stacked, x0, jac=jac, xtol=1e-15, ftol=1e-15, gtol=1e-15, max_nfev=500)
     assert abs(D.energy(x_gn, prob) - 2 * ls.cost) <= 1e-12 * max(D.energy(x_gn, prob), 1e-30)
     assert np.abs(x_gn - ls.x).max() < 1e-6
+
+
+def test_deform_surfels_rigid_graph_rotates_normals():
+    """A graph whose nodes all carry the same rigid motion (A_l = R,
+    t_l = R g_l + t - g_l) moves every surfel rigidly: p' = R p + t and
+    n' = R n, whatever each surfel's influence weights.  Rotations come from
+    scipy's axis-angle conversion (an independent route); a transposed A, a
+    dropped weight normalisation or an affine instead of linear normal map
+    fails it."""
+    from scipy.spatial.transform import Rotation
+    nodes = _grid_nodes(n_side=4, spacing=0.4)
+    prob = D.problem(nodes, con=[(nodes[0], nodes[0])])
+    rng = np.random.default_rng(12)
+    R = Rotation.from_rotvec(np.radians(25.0) * np.array([0.3, -0.8, 0.52]) / np.linalg.norm([0.3, -0.8, 0.52]))
+    R = R.as_matrix()
+    t = np.array([0.4, -0.25, 0.1])
+    x = _rigid_params(prob, R, t)
+    pos = (rng.uniform(-0.1, 1.3, size=(200, 3))).astype(np.float32)
+    nrm = rng.normal(size=(200, 3))
+    nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
+    P, Q = D.deform_surfels(x, prob, pos, nrm)
+    want_p = pos.astype(np.float64) @ R.T + t
+    want_n = nrm.astype(np.float64) @ R.T
+    # one float32 rounding of a float64 value: within an ulp of the float32 result
+    assert np.abs(P - want_p).max() < 4 * np.finfo(np.float32).eps * np.abs(want_p).max()
+    assert np.abs(Q - want_n).max() < 4 * np.finfo(np.float32).eps
+    assert np.abs(np.linalg.norm(Q.astype(np.float64), axis=1) - 1.0).max() < 4 * np.finfo(np.float32).eps
+
+
+def test_deform_surfels_uniform_scale_keeps_normals():
+    """A_l = s I (the same uniform scaling at every node) changes no normal
+    direction: n' = n after renormalisation, while positions scale about
+    the nodes."""
+    nodes = _grid_nodes(n_side=3, spacing=0.5)
+    prob = D.problem(nodes, con=[(nodes[0], nodes[0])])
+    N = len(nodes)
+    x = np.zeros(12 * N)
+    for l in range(N):
+        x[12 * l:12 * l + 9] = (1.7 * np.eye(3)).ravel()
+    rng = np.random.default_rng(5)
+    pos = rng.uniform(0.0, 1.0, size=(50, 3)).astype(np.float32)
+    nrm = rng.normal(size=(50, 3))
+    nrm = (nrm / np.linalg.norm(nrm, axis=1, keepdims=True)).astype(np.float32)
+    _, Q = D.deform_surfels(x, prob, pos, nrm)
+    assert np.abs(Q - nrm).max() < 4 * np.finfo(np.float32).eps

@@ -228,3 +228,82 @@ def test_gyro_only_factor_is_the_rotation_marginal_of_the_full_factor():
     # weights: inverse of the kept rows' block of the full covariance W^-1
     S = np.linalg.inv(W)[np.ix_(rows, rows)]
     assert np.abs(np.linalg.inv(Wg) - S).max() < 1e-9 * np.abs(S).max()
+
+
+def _aligned_case(seed=23):
+    """Constant body rate and specific force over T = 7 sample periods of 5 ms
+    (frame times on sample stamps, so each held value spans one full period):
+    the zero-order hold is exact and the ODE gives the ground truth."""
+    rng = np.random.default_rng(seed)
+    R_CS = lie.exp_so3([0.1, -0.2, 0.05])
+    t_CS = np.array([0.03, -0.01, 0.02])
+    R_IW = lie.exp_so3([0.05, -0.08, 0.9])
+    w_S = np.array([1.2, -0.6, 0.9])
+    f_S = np.array([0.7, -0.4, 9.5])
+    bg, ba = np.array([2e-3, -1e-3, 5e-4]), np.array([3e-2, -2e-2, 1e-2])
+    dt, n = 0.005, 7
+    T = dt * n
+    R_WC0 = lie.exp_so3(rng.normal(size=3) * 0.4)
+    r0, v0 = rng.normal(size=3), rng.normal(size=3)
+    R_IS0 = R_IW @ R_WC0 @ R_CS
+    p_IS0 = R_IW @ (r0 + R_WC0 @ t_CS)
+    g = np.array([0.0, 0.0, -9.81])
+    dR, dv, dp = _ode_truth(w_S, f_S, T)
+    R_WC1 = R_IW.T @ (R_IS0 @ dR) @ R_CS.T
+    r1 = R_IW.T @ (p_IS0 + v0 * T + 0.5 * g * T * T + R_IS0 @ dp) - R_WC1 @ t_CS
+    v1 = v0 + g * T + R_IS0 @ dv
+    x0 = {"r": r0, "q": quat_from_matrix(R_WC0), "v": v0, "bg": bg, "ba": ba}
+    x1 = {"r": r1, "q": quat_from_matrix(R_WC1), "v": v1, "bg": bg.copy(), "ba": ba.copy()}
+    params = {"gravity": 9.81, "R_CS": R_CS, "t_CS": t_CS, "sigma_bg_rw": 4e-6, "sigma_ba_rw": 2e-5}
+    return {"x0": x0, "x1": x1, "q_IW": quat_from_matrix(R_IW), "stamps": np.arange(n) * dt, "T": T,
+            "gyro": np.tile(w_S + bg, (n, 1)), "acc": np.tile(f_S + ba, (n, 1)), "dt": dt, "params": params}
+
+
+def _whitened_gap(S, C):
+    """max |L^-1 C L^-T - I| with S = L L^T: how far the sample covariance C
+    is from the model covariance S, in units of the model's own spread."""
+    Li = np.linalg.inv(np.linalg.cholesky(S))
+    return np.abs(Li @ C @ Li.T - np.eye(len(S))).max()
+
+
+def test_residual_covariance_against_monte_carlo_with_bias_random_walk():
+    """W_IMU^-1 (Section IV-C, eq. (5); noise and drift densities of Table I)
+    against the sample covariance of the 15-d residual under the generative
+    model it describes: every gyro / accelerometer sample carries white noise
+    of variance sigma^2 / dt (density sigma over the sample period dt), the
+    frame-to-frame bias change is a random walk of variance sigma_rw^2 T, and
+    the residual is evaluated at the true states.  A bias random-walk variance
+    of sigma_rw^2 / T instead of sigma_rw^2 T (or a per-sample variance of
+    sigma^2 dt) moves the whitened covariance far from I."""
+    c = _aligned_case()
+    sg, sa = 1.7e-4, 2e-3
+    x0, x1, q_IW, p = c["x0"], c["x1"], c["q_IW"], c["params"]
+    stamps, T, dt = c["stamps"], c["T"], c["dt"]
+    pre = imu.preintegrate(stamps, c["gyro"], c["acc"], 0.0, T, x0["bg"], x0["ba"], sg, sa)
+    Sigma = imu.residual_covariance(x0, x1, q_IW, pre, p)
+    rng = np.random.default_rng(31)
+    N = 16000
+    E = np.empty((N, 15))
+    n = len(stamps)
+    for k in range(N):
+        gyro = c["gyro"] + rng.normal(size=(n, 3)) * (sg / np.sqrt(dt))
+        acc = c["acc"] + rng.normal(size=(n, 3)) * (sa / np.sqrt(dt))
+        dR, dv, dp = imu.integrate(stamps, gyro, acc, 0.0, T, x0["bg"], x0["ba"])
+        noisy = dict(pre, dR=dR, dv=dv, dp=dp)  # integrated at x0's biases: no bias correction applies
+        x1k = dict(x1, bg=x1["bg"] + rng.normal(size=3) * (p["sigma_bg_rw"] * np.sqrt(T)),
+                   ba=x1["ba"] + rng.normal(size=3) * (p["sigma_ba_rw"] * np.sqrt(T)))
+        E[k] = imu.residual(x0, x1k, q_IW, noisy, p)
+    C = (E.T @ E) / N  # zero mean under the model (the truth has zero residual)
+    gap = _whitened_gap(Sigma, C)
+    # sampling spread of a whitened entry ~ sqrt(2 / N) = 0.011
+    assert gap < 0.06, gap
+    chi2 = np.einsum("ni,ij,nj->n", E, np.linalg.inv(Sigma), E).mean()
+    assert abs(chi2 - 15.0) < 0.5, chi2
+    # the planted slip: random-walk variance sigma_rw^2 / T
+    slip = Sigma.copy()
+    slip[9:12, 9:12] += np.eye(3) * p["sigma_bg_rw"] ** 2 * (1.0 / T - T)
+    slip[12:15, 12:15] += np.eye(3) * p["sigma_ba_rw"] ** 2 * (1.0 / T - T)
+    assert _whitened_gap(slip, C) > 0.5
+    # and a per-sample noise variance sigma^2 dt instead of sigma^2 / dt
+    pre_slip = imu.preintegrate(stamps, c["gyro"], c["acc"], 0.0, T, x0["bg"], x0["ba"], sg * dt, sa * dt)
+    assert _whitened_gap(imu.residual_covariance(x0, x1, q_IW, pre_slip, p), C) > 0.5

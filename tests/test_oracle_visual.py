@@ -174,3 +174,48 @@ def test_huber_weight():
     s = np.array([0.0, 1.0, 1.345, 2.69, 13.45])
     assert np.allclose(res.huber_weight(s, 1.345), [1, 1, 1, 0.5, 0.1])
     assert np.all(res.huber_weight(s, 0.0) == 1)
+
+
+def test_photometric_taps_lie_where_the_gradient_is_defined():
+    """Every pixel the photometric term accepts (eq. (3)) samples I0 and its
+    central-difference gradient at four taps that all have both neighbours
+    in the image: on a linear ramp those taps carry the exact ramp slope,
+    while the border pixels, whose central difference is undefined, carry
+    the pyramid's 0.  Conversely, every pixel with valid depth in front of
+    the reference camera whose four taps are interior is accepted (the rule
+    is no stricter than the taps require).  Random warps push projections
+    across all four borders."""
+    d = tilted_plane_pair(W=48, H=36, seed=4, ramp=(0.75, 0.5, 10.0))
+    cam = Camera(d["W"], d["H"], d["f"], d["f"], d["cx"], d["cy"])
+    cur, ref = track.build_pyramids(d["z1"], d["I1"], d["z0"], d["I0"], cam, 1)
+    G = ref[0]["G"]
+    W, H = d["W"], d["H"]
+    slope = np.array([0.75, 0.5], dtype=np.float32)
+    interior = np.zeros((H, W), bool)
+    interior[1:H - 1, 1:W - 1] = True
+    assert np.all(G[interior] == slope) and np.all(G[~interior] == 0.0)
+    rng = np.random.default_rng(8)
+    x = identity_state()
+    seen_reject = 0
+    for trial in range(12):
+        x1 = lie.state_boxplus(x, np.r_[rng.normal(size=3) * 0.08, rng.normal(size=3) * 0.06, np.zeros(9)])
+        _, _, Rb, tb = track.fp32_transforms(np.eye(4), x, x1)
+        ok, u, v = assoc.rgb_validity(cur[0], ref[0], Rb, tb)
+        assert ok.sum() > 0
+        fu, fv = np.floor(u[ok]).astype(np.int64), np.floor(v[ok]).astype(np.int64)
+        for du in (0, 1):
+            for dv in (0, 1):
+                taps = G[fv + dv, fu + du]
+                assert np.all(taps == slope), trial
+        # converse: valid depth, point in front, all four taps interior
+        qz = cur[0]["V"][..., 2] + (((Rb.reshape(3, 3)[2, 0] * cur[0]["V"][..., 0]
+                                      + Rb.reshape(3, 3)[2, 1] * cur[0]["V"][..., 1])
+                                     + Rb.reshape(3, 3)[2, 2] * cur[0]["V"][..., 2]) + tb[2])
+        with np.errstate(invalid="ignore"):
+            cand = (cur[0]["D"] > 0) & (qz > 0) & np.isfinite(u) & np.isfinite(v)
+        fu_all = np.where(cand, np.floor(np.nan_to_num(u)), -10).astype(np.int64)
+        fv_all = np.where(cand, np.floor(np.nan_to_num(v)), -10).astype(np.int64)
+        taps_in = cand & (fu_all >= 1) & (fu_all + 1 <= W - 2) & (fv_all >= 1) & (fv_all + 1 <= H - 2)
+        assert np.array_equal(ok, taps_in), trial
+        seen_reject += int((cand & ~ok).sum())
+    assert seen_reject > 0  # the warps did push pixels onto the border
