@@ -113,6 +113,9 @@ typedef struct {
   double huber_k;    /* Huber threshold on the whitened residual; 0 = no robust weight */
   int32_t jac_format;
   int32_t mode;
+  /* health checks of a tracked frame (dslam_track_result.health); 0 disables each */
+  double min_inlier_frac; /* LOW_INLIERS below this fraction of 2 x (level-0 pixels) inliers of both terms */
+  double max_cost_rise;   /* COST_UP when the finest level's visual cost rises by more than this fraction */
 } dslam_track_params;
 
 typedef struct {
@@ -139,10 +142,24 @@ typedef struct {
   double q_IW_bar[4];
 } dslam_prior;
 
+/* Health flags of a tracked frame (dslam_track_result.health).  A frame
+ * with any flag set is reported as tracking lost: the estimate is returned
+ * as computed, and the caller decides whether to trust it (the paper's
+ * estimator has no failure detection of its own; these are the checks that
+ * a failed dense alignment shows, Section VI). */
+enum {
+  DSLAM_HEALTH_LOW_INLIERS = 1, /* level-0 inliers (ICP + photometric) < min_inlier_frac x 2 x pixels */
+  DSLAM_HEALTH_NONFINITE = 2,   /* a cost or an updated state entry is not finite */
+  DSLAM_HEALTH_COST_UP = 4,     /* finest level: last visual cost > (1 + max_cost_rise) x first */
+  DSLAM_HEALTH_SINGULAR = 8     /* a Gauss-Newton system was not positive definite (status SINGULAR) */
+};
+
 /* Result of one tracked frame. */
 typedef struct {
   int32_t status;       /* dslam_status of the frame */
   int32_t frame_index;  /* frames tracked by the session so far */
+  int32_t health;       /* DSLAM_HEALTH_* flags */
+  int32_t tracking_lost; /* 1 if any health flag is set, else 0 (a result flag, not an error) */
   dslam_frame_state x0; /* refined previous state */
   dslam_frame_state x1; /* current state */
   double q_IW[4];
@@ -174,11 +191,13 @@ typedef struct dslam_batch dslam_batch;
 #define DSLAM_MAX_BATCH 256
 #define DSLAM_MAX_BATCH_RESOLUTIONS 16
 
-/* One session's inputs for a batched step or for dslam_track_frame_input:
- * the new frame and the model view predicted for it (device images, height x
- * width, row pitch in elements), the model-view pose T_WM (4x4 row-major,
- * host) and the frame's IMU samples (host, same rules as dslam_track_frame;
- * ignored in DSLAM_MODE_RGBD). */
+/* One session's inputs for dslam_track_frame or a batched step: the new
+ * frame and the model view predicted for it (device images, height x width,
+ * row pitch in elements), the model-view pose T_WM (4x4 row-major, host) and
+ * the frame's IMU samples (host, sorted by time, the first stamped at or
+ * before t0; ignored in DSLAM_MODE_RGBD).  dslam_track_frame accepts
+ * model_depth = NULL (reuse the session's MODEL pyramid); a batched step
+ * needs the model view. */
 typedef struct {
   const float* depth;
   const uint8_t* intensity;
@@ -238,7 +257,10 @@ uint64_t dslam_session_bytes(const dslam_camera* cam, int32_t levels);
 dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, const dslam_track_params* tp,
                                 const dslam_imu_params* ip, const dslam_frame_state* x0, const double q_IW[4],
                                 const dslam_prior* prior, dslam_session** out);
-/* Wait for the session's work, free its memory and return its bytes to the context. */
+/* Wait for the session's last enqueued work (its own completion event, not
+ * the whole device), free its memory and return its bytes to the context.
+ * BUSY (nothing freed) while a dslam_server still holds queued or unreturned
+ * requests of the session: poll them out, or destroy the server, first. */
 dslam_status dslam_session_close(dslam_session* s);
 
 /* Build the session's CURRENT or MODEL pyramid (Section IV-D) from device
@@ -270,29 +292,37 @@ dslam_status dslam_solve_step(const double raw[58], const double T_WM[16], const
                               dslam_frame_state* x0, dslam_frame_state* x1, double q_IW[4], double dz_out[33],
                               dslam_prior* marg_out);
 
-/* Track one frame (Section IV): builds the CURRENT pyramid from the device
- * images, preintegrates the host IMU samples (n in [1, 32]) over [t0, t1) on
- * the device at the session's current bias estimates, runs the coarse-to-fine
- * Gauss-Newton iterations entirely on the device, marginalises x0 and shifts
- * the state for the next frame.  Asynchronous: returns after enqueueing on
- * `stream`; read the result with dslam_session_result.  Requires a MODEL
- * pyramid (NOT_READY otherwise). */
-dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const uint8_t* intensity_dev,
-                               int32_t pitch_elems, const dslam_imu_sample* imu, int32_t n_imu, double t0,
-                               double t1, void* stream);
+/* Track one frame (Section IV-A: at the arrival of a frame the current state
+ * x1 is estimated while the previous state x0 is refined).  `in` gives the
+ * frame (device depth and intensity, host IMU samples covering [t0, t1),
+ * n_imu in [1, 32], ignored in DSLAM_MODE_RGBD) and, optionally, the model
+ * view it is tracked against (model_depth / model_intensity device images and
+ * the pose T_WM at which the view was predicted); with model_depth NULL the
+ * MODEL pyramid of an earlier call or of dslam_build_pyramid is used
+ * (NOT_READY if there is none).  Builds the CURRENT pyramid (and the MODEL
+ * one) in the frame's first launch, beside the device preintegration of the
+ * IMU samples at the session's bias estimates and the IMU prediction of x1,
+ * then runs the coarse-to-fine Gauss-Newton iterations entirely on the device
+ * (Section IV-D), marginalises x0 into the next frame's prior (Section IV-E)
+ * and shifts the state.  Asynchronous: returns after enqueueing on `stream`.
+ * If `out` is not NULL the frame's result is copied there asynchronously; it
+ * is valid once `stream` has passed the frame (dslam_session_result also
+ * waits for it).  `out` should be pinned host memory (hipHostMalloc): with
+ * pageable memory the copy, and so this call, waits for the frame.  The
+ * caller owns the images until the stream passes the frame.  Errors (nothing
+ * is enqueued): INVALID (null or short images, IMU samples unsorted, not
+ * covering t0 or more than 32, non-finite T_WM, no iterations), NOT_READY,
+ * DEVICE. */
+dslam_status dslam_track_frame(dslam_session* s, const dslam_frame_input* in, dslam_track_result* out,
+                               void* stream);
 
-/* Track one frame given with its model view, as one session's input of a
- * batched step (dslam_frame_input: device images, T_WM, host IMU samples):
- * the same as dslam_build_pyramid(MODEL) followed by dslam_track_frame, with
- * the same results, but both pyramids are built in the launch that
- * preintegrates and predicts, alongside it.  No earlier MODEL pyramid is
- * needed; this one stays for later dslam_track_frame calls.  The caller owns
- * the images until the session's stream reaches the end of the frame.  Errors
- * as dslam_track_frame, and INVALID for a missing model view or a non-finite
- * T_WM. */
-dslam_status dslam_track_frame_input(dslam_session* s, const dslam_frame_input* in, void* stream);
+/* dslam_track_frame, then wait for the frame and copy its result to `out`
+ * (host, required).  Returns the enqueue error, or DSLAM_OK with the frame's
+ * own status (a failed solve) in out->status. */
+dslam_status dslam_track_frame_sync(dslam_session* s, const dslam_frame_input* in, dslam_track_result* out,
+                                    void* stream);
 
-/* How dslam_track_frame and dslam_track_frame_input issue a frame's
+/* How dslam_track_frame issues a frame's
  * Gauss-Newton launches after the first.  enable = 1: each level's
  * iterations (residual pass, step) are captured in a HIP graph at the first
  * frame that needs them and replayed from then on, one graph launch per
@@ -539,8 +569,26 @@ dslam_status dslam_server_counts(const dslam_server* sv, int32_t* pending, int32
 /* The server's clock (steady clock, seconds). */
 double dslam_server_clock(void);
 
-/* Checkpoint / restore the session's estimator state (x0, q_IW, prior and
- * frame counter) through host memory; the pyramids are not part of it. */
+/* Session checkpoint as an opaque, versioned byte blob in caller host memory:
+ * everything the session's later frames depend on -- the estimator state
+ * (x0, q_IW, the marginal prior of Section IV-E, the frame counter), the
+ * model-view pose and MODEL pyramid (so that frames tracked against the
+ * previous model view continue), and the camera and tracking parameters it
+ * was taken under.  dslam_session_checkpoint with buf NULL writes the size
+ * to *size; otherwise buf must hold at least dslam_session_checkpoint's size
+ * (INVALID otherwise).  Waits for the session's work.  dslam_session_restore
+ * loads a blob into a session opened with the same camera, pyramid depth and
+ * tracking parameters (INVALID for a foreign, truncated, corrupted or
+ * mismatched blob; the session is unchanged then); frames tracked after a
+ * restore give the same results, bit for bit, as frames tracked after the
+ * checkpoint by the session it was taken from.  BUSY while a server holds
+ * requests of the session. */
+dslam_status dslam_session_checkpoint(dslam_session* s, void* buf, uint64_t capacity, uint64_t* size);
+dslam_status dslam_session_restore(dslam_session* s, const void* buf, uint64_t size);
+
+/* The estimator state alone (x0, q_IW, prior, frame counter) through host
+ * memory, to start a session over from a known state; the pyramids are not
+ * part of it.  Waits for the session's work. */
 dslam_status dslam_session_get_state(dslam_session* s, dslam_frame_state* x0, double q_IW[4], dslam_prior* prior,
                                      int32_t* frame_index);
 dslam_status dslam_session_set_state(dslam_session* s, const dslam_frame_state* x0, const double q_IW[4],

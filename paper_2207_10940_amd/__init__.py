@@ -12,8 +12,9 @@ import ctypes as C
 import numpy as np
 
 from . import _abi
-from ._abi import (CH_GX, CH_GY, CH_I, CH_NX, CH_NY, CH_NZ, CH_VX, CH_VY, CH_VZ, JAC_BF16, JAC_FP16, JAC_FP32,
-                   JAC_FP32_MFMA, MODE_GYRO, MODE_RGBD, MODE_RGBDI, PYR_CURRENT, PYR_MODEL)
+from ._abi import (CH_GX, CH_GY, CH_I, CH_NX, CH_NY, CH_NZ, CH_VX, CH_VY, CH_VZ, HEALTH_COST_UP, HEALTH_LOW_INLIERS,
+                   HEALTH_NONFINITE, HEALTH_SINGULAR, JAC_BF16, JAC_FP16, JAC_FP32, JAC_FP32_MFMA, MODE_GYRO, MODE_RGBD,
+                   MODE_RGBDI, PYR_CURRENT, PYR_MODEL)
 
 __all__ = ["DslamError", "Context", "Session", "Map", "Deform", "Batch", "Server", "frame_input", "preintegrate_imu", "solve_step", "track_params", "imu_params",
            "camera", "state_struct", "state_dict", "prior_struct", "prior_dict", "lib"]
@@ -69,7 +70,8 @@ def camera(cam) -> _abi.Camera:
 
 
 def track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32", icp_dist=0.10, icp_cos=None,
-                 sigma_I=4.0, depth_k=1e-3, huber_k=1.345) -> _abi.TrackParams:
+                 sigma_I=4.0, depth_k=1e-3, huber_k=1.345, min_inlier_frac=0.05,
+                 max_cost_rise=0.5) -> _abi.TrackParams:
     p = _abi.TrackParams()
     p.levels = levels
     its = list(iters) + [0] * (_abi.MAX_LEVELS - len(iters))
@@ -81,6 +83,8 @@ def track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32", icp_dist=
     p.huber_k = huber_k
     p.jac_format = JAC[jac] if isinstance(jac, str) else int(jac)
     p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    p.min_inlier_frac = min_inlier_frac
+    p.max_cost_rise = max_cost_rise
     return p
 
 
@@ -163,7 +167,8 @@ def solve_step(raw, T_WM, pre, ip, tp, prior, x0, x1, q_IW, marginalise=False):
 
 
 def result_dict(r: _abi.TrackResult) -> dict:
-    return {"status": r.status, "frame_index": r.frame_index, "x0": state_dict(r.x0), "x1": state_dict(r.x1),
+    return {"status": r.status, "frame_index": r.frame_index, "health": r.health,
+            "tracking_lost": bool(r.tracking_lost), "x0": state_dict(r.x0), "x1": state_dict(r.x1),
             "q_IW": np.array(r.q_IW[:]), "cost_icp": r.cost_icp, "cost_rgb": r.cost_rgb, "cost_imu": r.cost_imu,
             "n_icp": list(r.n_icp), "n_rgb": list(r.n_rgb), "last_step_norm": r.last_step_norm,
             "prior": prior_dict(r.prior)}
@@ -243,16 +248,12 @@ class Session:
     def set_model(self, depth, intensity, T_WM, stream=None):
         self.build_pyramid(PYR_MODEL, depth, intensity, T_WM, stream)
 
-    def track_frame(self, depth, intensity, imu=None, t0=0.0, t1=0.0, stream=None):
-        """Enqueue one tracking step; imu = dict(t, gyro, acc) of the samples covering [t0, t1)."""
-        assert depth.is_cuda and intensity.is_cuda and depth.is_contiguous() and intensity.is_contiguous()
-        if imu is not None:
-            arr, n = imu_samples(imu["t"], imu["gyro"], imu["acc"])
-        else:
-            arr, n = None, 0
-        _check(lib().dslam_track_frame(self.handle, C.c_void_p(depth.data_ptr()), C.c_void_p(intensity.data_ptr()),
-                                       int(depth.shape[1]), arr, n, float(t0), float(t1), _stream_ptr(stream)),
-               "dslam_track_frame")
+    def track_frame(self, depth, intensity, imu=None, t0=0.0, t1=0.0, stream=None, out=None):
+        """Enqueue one tracking step against the session's MODEL pyramid; imu = dict(t, gyro, acc) of the
+        samples covering [t0, t1).  out: optional TrackResult (pinned host memory for a fully asynchronous
+        copy) that receives the result once the stream passes the frame."""
+        self.track_frame_input({"depth": depth, "intensity": intensity, "model_depth": None, "imu": imu,
+                                "t0": t0, "t1": t1}, stream, out)
 
     def set_graphs(self, enable: bool):
         """Replay each level's Gauss-Newton launches from a captured HIP graph (True) or issue them one by
@@ -265,14 +266,36 @@ class Session:
         """Whether the session replays captured graphs (the library's default until set_graphs)."""
         return getattr(self, "_graphs", SESSION_GRAPHS_DEFAULT)
 
-    def track_frame_input(self, frame: dict, stream=None):
-        """Enqueue one tracking step with its model view: frame = dict(depth, intensity, model_depth,
-        model_intensity, T_WM, imu, t0, t1) as for Batch.track; both pyramids are built in the launch
-        that initialises the frame (dslam_track_frame_input)."""
+    def track_frame_input(self, frame: dict, stream=None, out=None):
+        """Enqueue one tracking step (dslam_track_frame): frame = dict(depth, intensity, model_depth,
+        model_intensity, T_WM, imu, t0, t1) as for Batch.track; model_depth None tracks against the
+        session's MODEL pyramid, otherwise both pyramids are built in the launch that initialises the
+        frame."""
         fi, keep = frame_input(frame)
-        _check(lib().dslam_track_frame_input(self.handle, C.byref(fi), _stream_ptr(stream)),
-               "dslam_track_frame_input")
+        _check(lib().dslam_track_frame(self.handle, C.byref(fi), C.byref(out) if out is not None else None,
+                                       _stream_ptr(stream)), "dslam_track_frame")
         self._keep_input = keep
+
+    def track_frame_sync(self, frame: dict, stream=None) -> dict:
+        """dslam_track_frame_sync: enqueue the frame, wait for it and return its result."""
+        fi, keep = frame_input(frame)
+        r = _abi.TrackResult()
+        _check(lib().dslam_track_frame_sync(self.handle, C.byref(fi), C.byref(r), _stream_ptr(stream)),
+               "dslam_track_frame_sync")
+        return result_dict(r)
+
+    def checkpoint(self) -> bytes:
+        """dslam_session_checkpoint: the session's opaque, versioned state blob."""
+        n = C.c_uint64()
+        _check(lib().dslam_session_checkpoint(self.handle, None, 0, C.byref(n)), "dslam_session_checkpoint")
+        buf = C.create_string_buffer(n.value)
+        _check(lib().dslam_session_checkpoint(self.handle, buf, n.value, C.byref(n)), "dslam_session_checkpoint")
+        return buf.raw[:n.value]
+
+    def restore(self, blob: bytes):
+        """dslam_session_restore from a checkpoint blob."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(lib().dslam_session_restore(self.handle, buf, len(blob)), "dslam_session_restore")
 
     def result(self) -> dict:
         r = _abi.TrackResult()
@@ -324,13 +347,16 @@ class Session:
 def frame_input(f: dict):
     """FrameInput for dict(depth, intensity, model_depth, model_intensity, T_WM, imu, t0, t1) (device images
     contiguous); returns (struct, keep-alive) -- the IMU array must outlive the struct's use."""
-    d, im, md, mi = f["depth"], f["intensity"], f["model_depth"], f["model_intensity"]
-    for t in (d, im, md, mi):
+    d, im, md = f["depth"], f["intensity"], f.get("model_depth")
+    for t in (d, im):
         assert t.is_cuda and t.is_contiguous()
     fi = _abi.FrameInput()
     fi.depth, fi.intensity, fi.pitch = d.data_ptr(), im.data_ptr(), int(d.shape[1])
-    fi.model_depth, fi.model_intensity, fi.model_pitch = md.data_ptr(), mi.data_ptr(), int(md.shape[1])
-    fi.T_WM[:] = [float(v) for v in np.asarray(f["T_WM"], dtype=np.float64).ravel()]
+    if md is not None:  # else: track against the session's MODEL pyramid
+        mi = f["model_intensity"]
+        assert md.is_cuda and md.is_contiguous() and mi.is_cuda and mi.is_contiguous()
+        fi.model_depth, fi.model_intensity, fi.model_pitch = md.data_ptr(), mi.data_ptr(), int(md.shape[1])
+        fi.T_WM[:] = [float(v) for v in np.asarray(f["T_WM"], dtype=np.float64).ravel()]
     arr = None
     if f.get("imu") is not None:
         arr, cnt = imu_samples(f["imu"]["t"], f["imu"]["gyro"], f["imu"]["acc"])

@@ -11,6 +11,7 @@ OK, ERR_INVALID, ERR_NO_CAPACITY, ERR_SINGULAR, ERR_DEVICE, ERR_BUSY, ERR_NOT_RE
 MODE_RGBDI, MODE_RGBD, MODE_GYRO = 0, 1, 2
 JAC_FP32, JAC_FP32_MFMA, JAC_FP16, JAC_BF16 = 0, 1, 2, 3
 PYR_CURRENT, PYR_MODEL = 0, 1
+HEALTH_LOW_INLIERS, HEALTH_NONFINITE, HEALTH_COST_UP, HEALTH_SINGULAR = 1, 2, 4, 8
 CH_VX, CH_VY, CH_VZ, CH_NX, CH_NY, CH_NZ, CH_I, CH_GX, CH_GY = range(9)
 
 
@@ -33,7 +34,8 @@ class ImuParams(C.Structure):
 class TrackParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("iters", C.c_int32 * MAX_LEVELS), ("icp_dist", C.c_double),
                 ("icp_cos", C.c_double), ("sigma_I", C.c_double), ("depth_k", C.c_double), ("huber_k", C.c_double),
-                ("jac_format", C.c_int32), ("mode", C.c_int32)]
+                ("jac_format", C.c_int32), ("mode", C.c_int32), ("min_inlier_frac", C.c_double),
+                ("max_cost_rise", C.c_double)]
 
 
 class ImuSample(C.Structure):
@@ -50,7 +52,8 @@ class Prior(C.Structure):
 
 
 class TrackResult(C.Structure):
-    _fields_ = [("status", C.c_int32), ("frame_index", C.c_int32), ("x0", FrameState), ("x1", FrameState),
+    _fields_ = [("status", C.c_int32), ("frame_index", C.c_int32), ("health", C.c_int32),
+                ("tracking_lost", C.c_int32), ("x0", FrameState), ("x1", FrameState),
                 ("q_IW", C.c_double * 4), ("cost_icp", C.c_double), ("cost_rgb", C.c_double),
                 ("cost_imu", C.c_double), ("cost_prior", C.c_double), ("n_icp", C.c_int64 * MAX_LEVELS),
                 ("n_rgb", C.c_int64 * MAX_LEVELS), ("last_step_norm", C.c_double), ("prior", Prior)]
@@ -119,7 +122,10 @@ SIGNATURES = {
                                          P(Preint)]),
     "dslam_solve_step": (C.c_int, [dp, dp, P(Preint), P(ImuParams), P(TrackParams), P(Prior), P(FrameState),
                                    P(FrameState), dp, dp, P(Prior)]),
-    "dslam_track_frame": (C.c_int, [vp, vp, vp, C.c_int32, P(ImuSample), C.c_int32, C.c_double, C.c_double, vp]),
+    "dslam_track_frame": (C.c_int, [vp, P(FrameInput), P(TrackResult), vp]),
+    "dslam_track_frame_sync": (C.c_int, [vp, P(FrameInput), P(TrackResult), vp]),
+    "dslam_session_checkpoint": (C.c_int, [vp, vp, C.c_uint64, P(C.c_uint64)]),
+    "dslam_session_restore": (C.c_int, [vp, vp, C.c_uint64]),
     "dslam_session_result": (C.c_int, [vp, P(TrackResult)]),
     "dslam_linearize": (C.c_int, [vp, C.c_int32, fp, fp, fp, fp, P(FrameState), P(FrameState), vp,
                                   P(LinearSystem), vp]),
@@ -132,7 +138,6 @@ SIGNATURES = {
     "dslam_batch_create": (C.c_int, [vp, C.c_int32, P(vp)]),
     "dslam_batch_destroy": (C.c_int, [vp]),
     "dslam_batch_track": (C.c_int, [vp, C.c_int32, P(vp), P(FrameInput), vp]),
-    "dslam_track_frame_input": (C.c_int, [vp, P(FrameInput), vp]),
     "dslam_session_set_graphs": (C.c_int, [vp, C.c_int32]),
     "dslam_batch_results": (C.c_int, [vp, P(TrackResult)]),
     "dslam_batch_profile_residual": (C.c_int, [vp, C.c_int32, C.c_int32, vp, P(C.c_uint64)]),

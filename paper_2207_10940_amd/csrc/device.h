@@ -34,9 +34,9 @@ struct SessionDev {
   float xf[24];        // Ra-I (9) ta (3) Rb-I (9) tb (3) for the next residual pass
   double sys[58];      // reduced sums of the last residual pass
   dslam_track_result result;
+  double cost_first;   // visual cost at the first iteration of the frame's finest level (health check)
   int32_t status;      // first error of the current frame
   int32_t frame_index;
-  int32_t pad[2];
 };
 
 // Arguments of one residual pass.

@@ -56,6 +56,9 @@ bool params_ok(const dslam_camera* cam, const dslam_track_params* tp) {
   if (!(tp->icp_dist > 0) || !(tp->icp_cos <= 1) || !(tp->sigma_I > 0) ||
       !(tp->depth_k > 0) || !(tp->huber_k >= 0))
     return false;
+  if (!(tp->min_inlier_frac >= 0 && tp->min_inlier_frac <= 1) || !(tp->max_cost_rise >= 0) ||
+      !std::isfinite(tp->max_cost_rise))
+    return false;
   return true;
 }
 
@@ -146,6 +149,8 @@ ResidualArgs residual_args(dslam_session* s, int l, const float* xf, uint8_t* ma
   return a;
 }
 
+int last_level_of(const dslam_track_params& tp);
+
 SolveParams solve_params(dslam_session* s) {
   SolveParams sp;
   for (int r = 0; r < 3; ++r) {
@@ -155,6 +160,11 @@ SolveParams solve_params(dslam_session* s) {
   sp.imu = imu_params_d(s->ip);
   sp.mode = s->tp.mode;
   sp.marginalise = 1;  // the device solve marginalises on the frame's last step only
+  // health thresholds: inliers of both terms at the frame's finest level
+  const int fl = last_level_of(s->tp);
+  const double npix = fl >= 0 ? (double)s->cur[fl].W * (double)s->cur[fl].H : 0.0;
+  sp.min_inliers = s->tp.min_inlier_frac > 0.0 ? s->tp.min_inlier_frac * 2.0 * npix : 0.0;
+  sp.max_cost_rise = s->tp.max_cost_rise > 0.0 ? s->tp.max_cost_rise : 0.0;
   return sp;
 }
 
@@ -204,6 +214,24 @@ bool finite16(const double* T) {
   for (int i = 0; i < 16; ++i)
     if (!std::isfinite(T[i])) return false;
   return true;
+}
+
+// Orders new work of the session on `st` after its earlier work when that was
+// enqueued on another stream (the session's device state is updated in stream
+// order, so a change of stream must not let two frames overlap).
+hipError_t order_after_session(dslam_session* s, hipStream_t st) {
+  if (s->enqueued && s->last_stream != st) return hipStreamWaitEvent(st, s->done, 0);
+  return hipSuccess;
+}
+
+// Marks the end of the session's work enqueued on `st`.
+hipError_t mark_session(dslam_session* s, hipStream_t st) {
+  hipError_t e = hipEventRecord(s->done, st);
+  if (e == hipSuccess) {
+    s->last_stream = st;
+    s->enqueued = true;
+  }
+  return e;
 }
 
 }  // namespace
@@ -309,6 +337,8 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   s->red_out = (double*)p; p += align256(64 * sizeof(double));
   s->xf_scratch = (float*)p; p += align256(24 * sizeof(float));
   s->sp_dev = (SolveParams*)p;
+  s->last_stream = nullptr;
+  s->enqueued = false;
   SessionDev init;
   std::memset(&init, 0, sizeof(init));
   init.x0 = *x0;
@@ -435,8 +465,9 @@ static void drop_graphs(dslam_session* s) {
 
 dslam_status dslam_session_close(dslam_session* s) {
   if (!s) return DSLAM_ERR_INVALID;
+  if (s->server_refs.load() > 0) return DSLAM_ERR_BUSY;
   (void)hipSetDevice(s->ctx->device);
-  (void)hipDeviceSynchronize();
+  if (s->enqueued) (void)hipEventSynchronize(s->done);
   drop_graphs(s);
   if (s->capture) (void)hipStreamDestroy(s->capture);
   (void)hipEventDestroy(s->done);
@@ -470,7 +501,9 @@ dslam_status dslam_build_pyramid(dslam_session* s, int32_t which, const float* d
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
   hipStream_t st = (hipStream_t)stream;
+  HIP_OK(order_after_session(s, st));
   HIP_OK(launch_pyramid(pyr_args(s, which, depth_dev, intensity_dev, pitch_elems), st));
+  HIP_OK(mark_session(s, st));
   if (which == DSLAM_PYR_MODEL) {
     std::memcpy(s->T_WM, T_W_ref, sizeof(s->T_WM));
     s->have_model = true;
@@ -533,33 +566,53 @@ dslam_status dslam_solve_step(const double raw[58], const double T_WM[16], const
   return (dslam_status)st;
 }
 
-// Enqueues one frame; with a model view (mdepth != nullptr) its pyramid is
-// built in the same launch as the current frame's and the frame's
-// initialisation.  Arguments validated by the callers.
-// Captures, once per session, each level's Gauss-Newton iterations (residual
-// pass, then the step reading its parameters from sp_dev) into a graph on a
-// private stream.  Every argument of these launches is fixed for the session
-// (device pointers, sizes, the level's schedule), so the graphs replay
-// unchanged; the frame's own inputs reach them through device memory written
-// by the frame's first launch.
+// STEP_* flags of iteration `it` of level l.
+static int step_flags(const dslam_track_params& tp, int l, int it) {
+  const int fl = last_level_of(tp);
+  int f = 0;
+  if (l == fl && it == 0) f |= STEP_FIRST;
+  if (l == fl && it == tp.iters[l] - 1) f |= STEP_LAST;
+  return f;
+}
+
+// One level's Gauss-Newton iterations (each: the residual pass, then the
+// step).  With sp == nullptr (graph capture) the step reads the frame's solve
+// parameters from device memory, written by the frame's first launch: every
+// argument of these launches is then fixed for the session (device pointers,
+// sizes, the level's schedule), so the same launches serve every frame.
+static hipError_t enqueue_level(dslam_session* s, int l, const SolveParams* sp, hipStream_t st) {
+  const ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
+  const int nb = residual_blocks(ra.npix, s->ppt[l]);
+  for (int it = 0; it < s->tp.iters[l]; ++it) {
+    hipError_t e = launch_residual(ra, s->ppt[l], st);
+    if (e != hipSuccess) return e;
+    const int flags = step_flags(s->tp, l, it);
+    if (sp) {
+      SolveArgs sa;
+      sa.sp = *sp;
+      sa.level = l;
+      sa.flags = flags;
+      sa.nblocks = nb;
+      e = launch_solve(s->sd, s->partials, sa, st);
+    } else {
+      e = launch_solve_graph(s->sd, s->partials, s->sp_dev, l, flags, nb, st);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Captures, once per session, each level's launches into a graph on a private
+// stream (see enqueue_level).
 static dslam_status capture_graphs(dslam_session* s) {
   bool complete = true;
   for (int l = 0; l < s->levels; ++l) complete = complete && (s->tp.iters[l] <= 0 || s->graph[l]);
   if (complete) return DSLAM_OK;
   if (!s->capture) HIP_OK(hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking));
-  const int last_level = last_level_of(s->tp);
   for (int l = 0; l < s->levels; ++l) {
     if (s->tp.iters[l] <= 0 || s->graph[l]) continue;
-    const ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
-    const int nb = residual_blocks(ra.npix, s->ppt[l]);
     HIP_OK(hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int it = 0; it < s->tp.iters[l] && e == hipSuccess; ++it) {
-      e = launch_residual(ra, s->ppt[l], s->capture);
-      if (e == hipSuccess)
-        e = launch_solve_graph(s->sd, s->partials, s->sp_dev, l, (l == last_level && it == s->tp.iters[l] - 1) ? 1 : 0,
-                               nb, s->capture);
-    }
+    hipError_t e = enqueue_level(s, l, nullptr, s->capture);
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(s->capture, &g);
     if (e == hipSuccess) e = ee;
@@ -574,15 +627,17 @@ static dslam_status capture_graphs(dslam_session* s) {
   return DSLAM_OK;
 }
 
+// Enqueues one frame; with a model view (mdepth != nullptr) its pyramid is
+// built in the same launch as the current frame's and the frame's
+// initialisation.  Arguments validated by the callers.
 static dslam_status track_enqueue(dslam_session* s, const float* depth, const uint8_t* inten, int32_t pitch,
                                   const float* mdepth, const uint8_t* minten, int32_t mpitch, const double* T_WM,
-                                  const ImuBatch& batch, hipStream_t st) {
+                                  const ImuBatch& batch, dslam_track_result* out, hipStream_t st) {
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
   if (mdepth) std::memcpy(s->T_WM, T_WM, sizeof(s->T_WM));
-  SolveArgs sa;
-  sa.sp = solve_params(s);
-  FrameArgs fa = frame_args(s, sa.sp);
+  const SolveParams sp = solve_params(s);
+  const FrameArgs fa = frame_args(s, sp);
   const PyrArgs cur = pyr_args(s, DSLAM_PYR_CURRENT, depth, inten, pitch);
   PyrArgs model;
   if (mdepth) model = pyr_args(s, DSLAM_PYR_MODEL, mdepth, minten, mpitch);
@@ -590,27 +645,16 @@ static dslam_status track_enqueue(dslam_session* s, const float* depth, const ui
     dslam_status gs = capture_graphs(s);
     if (gs != DSLAM_OK) return gs;
   }
-  HIP_OK(launch_frame_init_pyramid(s->sd, batch, fa, cur, mdepth ? &model : nullptr, s->use_graphs ? s->sp_dev : nullptr,
-                                   st));
+  HIP_OK(order_after_session(s, st));
+  HIP_OK(launch_frame_init_pyramid(s->sd, batch, fa, sp, cur, mdepth ? &model : nullptr, s->sp_dev, st));
   if (mdepth) s->have_model = true;
-  if (s->use_graphs) {
-    for (int l = s->levels - 1; l >= 0; --l)
-      if (s->graph[l]) HIP_OK(hipGraphLaunch(s->graph[l], st));
-  } else {
-    const int last_level = last_level_of(s->tp);
-    for (int l = s->levels - 1; l >= 0; --l) {
-      ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
-      int nb = residual_blocks(ra.npix, s->ppt[l]);
-      for (int it = 0; it < s->tp.iters[l]; ++it) {
-        HIP_OK(launch_residual(ra, s->ppt[l], st));
-        sa.level = l;
-        sa.nblocks = nb;
-        sa.last = (l == last_level && it == s->tp.iters[l] - 1) ? 1 : 0;
-        HIP_OK(launch_solve(s->sd, s->partials, sa, st));
-      }
-    }
+  for (int l = s->levels - 1; l >= 0; --l) {
+    if (s->tp.iters[l] <= 0) continue;
+    if (s->use_graphs) HIP_OK(hipGraphLaunch(s->graph[l], st));
+    else HIP_OK(enqueue_level(s, l, &sp, st));
   }
-  HIP_OK(hipEventRecord(s->done, st));
+  if (out) HIP_OK(hipMemcpyAsync(out, &s->sd->result, sizeof(dslam_track_result), hipMemcpyDeviceToHost, st));
+  HIP_OK(mark_session(s, st));
   return DSLAM_OK;
 }
 
@@ -621,30 +665,25 @@ dslam_status dslam_session_set_graphs(dslam_session* s, int32_t enable) {
   return DSLAM_OK;
 }
 
-dslam_status dslam_track_frame(dslam_session* s, const float* depth_dev, const uint8_t* intensity_dev,
-                               int32_t pitch_elems, const dslam_imu_sample* imu, int32_t n_imu, double t0,
-                               double t1, void* stream) {
-  if (!s || !depth_dev || !intensity_dev || pitch_elems < s->cam.width) return DSLAM_ERR_INVALID;
-  ImuBatch batch;
-  dslam_status sti = pack_imu(s, imu, n_imu, t0, t1, &batch);
-  if (sti != DSLAM_OK) return sti;
-  if (last_level_of(s->tp) < 0) return DSLAM_ERR_INVALID;
-  if (!s->have_model) return DSLAM_ERR_NOT_READY;
-  return track_enqueue(s, depth_dev, intensity_dev, pitch_elems, nullptr, nullptr, 0, nullptr, batch,
-                       (hipStream_t)stream);
-}
-
-dslam_status dslam_track_frame_input(dslam_session* s, const dslam_frame_input* f, void* stream) {
+dslam_status dslam_track_frame(dslam_session* s, const dslam_frame_input* f, dslam_track_result* out, void* stream) {
   if (!s || !f || !f->depth || !f->intensity || f->pitch < s->cam.width) return DSLAM_ERR_INVALID;
-  if (!f->model_depth || !f->model_intensity || f->model_pitch < s->cam.width) return DSLAM_ERR_INVALID;
-  for (int i = 0; i < 16; ++i)
-    if (!std::isfinite(f->T_WM[i])) return DSLAM_ERR_INVALID;
+  const bool model = f->model_depth != nullptr;
+  if (model && (!f->model_intensity || f->model_pitch < s->cam.width || !finite16(f->T_WM))) return DSLAM_ERR_INVALID;
   ImuBatch batch;
   dslam_status sti = pack_imu(s, f->imu, f->n_imu, f->t0, f->t1, &batch);
   if (sti != DSLAM_OK) return sti;
   if (last_level_of(s->tp) < 0) return DSLAM_ERR_INVALID;
-  return track_enqueue(s, f->depth, f->intensity, f->pitch, f->model_depth, f->model_intensity, f->model_pitch,
-                       f->T_WM, batch, (hipStream_t)stream);
+  if (!model && !s->have_model) return DSLAM_ERR_NOT_READY;
+  return track_enqueue(s, f->depth, f->intensity, f->pitch, model ? f->model_depth : nullptr,
+                       model ? f->model_intensity : nullptr, f->model_pitch, f->T_WM, batch, out, (hipStream_t)stream);
+}
+
+dslam_status dslam_track_frame_sync(dslam_session* s, const dslam_frame_input* f, dslam_track_result* out,
+                                    void* stream) {
+  if (!out) return DSLAM_ERR_INVALID;
+  dslam_status st = dslam_track_frame(s, f, nullptr, stream);
+  if (st != DSLAM_OK) return st;
+  return dslam_session_result(s, out);
 }
 
 dslam_status dslam_batch_create(dslam_context* ctx, int32_t max_sessions, dslam_batch** out) {
@@ -729,6 +768,9 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
     if (!f.depth || !f.intensity || f.pitch < s->cam.width) return DSLAM_ERR_INVALID;
     if (!f.model_depth || !f.model_intensity || f.model_pitch < s->cam.width) return DSLAM_ERR_INVALID;
     if (!finite16(f.T_WM)) return DSLAM_ERR_INVALID;
+    ImuBatch probe;
+    const dslam_status sti = pack_imu(s, f.imu, f.n_imu, f.t0, f.t1, &probe);
+    if (sti != DSLAM_OK) return sti;
   }
   const int last_level = last_level_of(s0->tp);
   if (last_level < 0) return DSLAM_ERR_INVALID;
@@ -752,13 +794,14 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
   HIP_OK(hipSetDevice(b->ctx->device));
   if (b->pending) HIP_OK(hipEventSynchronize(b->done));  // staging memory is reused
   b->pending = false;
-  // ---- stage the slots
+  hipStream_t st = (hipStream_t)stream;
+  // ---- stage the slots (everything was validated above)
   ImuBatch imu;
   for (int k = 0; k < n; ++k) {
     dslam_session* s = sessions[order[k]];
     const dslam_frame_input& f = frames[order[k]];
-    dslam_status sti = pack_imu(s, f.imu, f.n_imu, f.t0, f.t1, &imu);
-    if (sti != DSLAM_OK) return sti;
+    (void)pack_imu(s, f.imu, f.n_imu, f.t0, f.t1, &imu);
+    HIP_OK(order_after_session(s, st));
     std::memcpy(s->T_WM, f.T_WM, sizeof(s->T_WM));
     SlotVis& v = b->h_vis[k];
     SlotSolve& o = b->h_solve[k];
@@ -781,7 +824,6 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
     o.sp = solve_params(s);
     o.fa = frame_args(s, o.sp);
   }
-  hipStream_t st = (hipStream_t)stream;
   HIP_OK(hipMemcpyAsync(b->d_vis, b->h_vis, sizeof(SlotVis) * n, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(b->d_solve, b->h_solve, sizeof(SlotSolve) * n, hipMemcpyHostToDevice, st));
   // ---- work split of each launch: one class per resolution
@@ -819,8 +861,7 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
     b->pixels[l] = px;
     for (int it = 0; it < s0->tp.iters[l]; ++it) {
       HIP_OK(launch_residual_batch(b->d_vis, g, l, max_ppt, s0->tp.jac_format, st));
-      const int last = (l == last_level && it == s0->tp.iters[l] - 1) ? 1 : 0;
-      HIP_OK(launch_solve_batch(b->d_solve, n, l, last, st));
+      HIP_OK(launch_solve_batch(b->d_solve, n, l, step_flags(s0->tp, l, it), st));
     }
   }
   HIP_OK(launch_gather_results(b->d_solve, n, b->d_res, st));
@@ -829,7 +870,7 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
   for (int k = 0; k < n; ++k) {
     dslam_session* s = sessions[order[k]];
     s->have_model = true;
-    HIP_OK(hipEventRecord(s->done, st));
+    HIP_OK(mark_session(s, st));
     b->order[k] = order[k];
   }
   b->n = n;
@@ -860,7 +901,7 @@ dslam_status dslam_batch_results(dslam_batch* b, dslam_track_result* out) {
 dslam_status dslam_session_result(dslam_session* s, dslam_track_result* out) {
   if (!s || !out) return DSLAM_ERR_INVALID;
   HIP_OK(hipSetDevice(s->ctx->device));
-  HIP_OK(hipEventSynchronize(s->done));
+  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
   HIP_OK(hipMemcpy(out, &s->sd->result, sizeof(dslam_track_result), hipMemcpyDeviceToHost));
   return DSLAM_OK;
 }
@@ -875,6 +916,7 @@ dslam_status dslam_linearize(dslam_session* s, int32_t level, const float Ra[9],
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
   hipStream_t st = (hipStream_t)stream;
+  HIP_OK(order_after_session(s, st));
   float xf[24];
   for (int i = 0; i < 9; ++i) { xf[i] = Ra[i]; xf[12 + i] = Rb[i]; }
   for (int i = 0; i < 3; ++i) { xf[9 + i] = ta[i]; xf[21 + i] = tb[i]; }
@@ -884,6 +926,7 @@ dslam_status dslam_linearize(dslam_session* s, int32_t level, const float Ra[9],
   HIP_OK(launch_reduce(s->partials, residual_blocks(ra.npix, s->ppt[level]), s->red_out, st));
   double raw[64];
   HIP_OK(hipMemcpyAsync(raw, s->red_out, 58 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_OK(mark_session(s, st));
   HIP_OK(hipStreamSynchronize(st));
   SolveParams sp = solve_params(s);
   dslam_linear_system r;
@@ -903,8 +946,10 @@ dslam_status dslam_profile_residual(dslam_session* s, int32_t level, int32_t rep
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
   hipStream_t st = (hipStream_t)stream;
+  HIP_OK(order_after_session(s, st));
   ResidualArgs ra = residual_args(s, level, s->sd->xf, nullptr);
   for (int r = 0; r < reps; ++r) HIP_OK(launch_residual(ra, s->ppt[level], st));
+  HIP_OK(mark_session(s, st));
   return DSLAM_OK;
 }
 
@@ -916,7 +961,7 @@ dslam_status dslam_copy_pyramid(dslam_session* s, int32_t which, int32_t level, 
   if (channel < DSLAM_CH_VX || channel > DSLAM_CH_GY || (grad && which != DSLAM_PYR_MODEL)) return DSLAM_ERR_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
-  HIP_OK(hipDeviceSynchronize());
+  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
   const size_t n = (size_t)L.W * L.H;
   if (channel >= DSLAM_CH_NX && channel <= DSLAM_CH_NZ) {
     HIP_OK(hipMemcpy(host_out, L.N[channel - DSLAM_CH_NX], n * sizeof(float), hipMemcpyDeviceToHost));
@@ -933,12 +978,175 @@ dslam_status dslam_copy_pyramid(dslam_session* s, int32_t which, int32_t level, 
   return DSLAM_OK;
 }
 
+// ---- checkpoint / restore ------------------------------------------------
+// Blob: CkptHeader, then the device state record (SessionDev), then each
+// level's MODEL planes in order (V x3, N x3 float32, I uint16, G x2 int16).
+namespace {
+
+constexpr char kCkptMagic[8] = {'D', 'S', 'L', 'A', 'M', 'C', 'K', 'P'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  uint64_t total_bytes, state_bytes, model_bytes;
+  uint64_t checksum;  // FNV-1a over the blob with this field zero
+  int32_t width, height, levels, mode, jac_format, have_model;
+  int32_t iters[DSLAM_MAX_LEVELS];
+  int32_t ppt[DSLAM_MAX_LEVELS];
+  double fx, fy, cx, cy;
+  double icp_dist, icp_cos, sigma_I, depth_k, huber_k, min_inlier_frac, max_cost_rise;
+  double T_WM[16];
+};
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const uint8_t* b = (const uint8_t*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+uint64_t model_plane_bytes(const dslam_session* s) {
+  uint64_t n = 0;
+  for (int l = 0; l < s->levels; ++l) n += (uint64_t)s->model[l].W * s->model[l].H * (6 * 4 + 3 * 2);
+  return n;
+}
+
+uint64_t ckpt_bytes(const dslam_session* s) { return sizeof(CkptHeader) + sizeof(SessionDev) + model_plane_bytes(s); }
+
+// Copies every MODEL plane between the session and host memory (to_host:
+// device -> p, else p -> device).
+hipError_t copy_model_planes(dslam_session* s, uint8_t* p, bool to_host) {
+  for (int l = 0; l < s->levels; ++l) {
+    const LevelPtrs& L = s->model[l];
+    const size_t n = (size_t)L.W * L.H;
+    void* planes[9] = {L.V[0], L.V[1], L.V[2], L.N[0], L.N[1], L.N[2], L.I, L.G[0], L.G[1]};
+    for (int k = 0; k < 9; ++k) {
+      const size_t bytes = n * (k < 6 ? 4 : 2);
+      hipError_t e = to_host ? hipMemcpy(p, planes[k], bytes, hipMemcpyDeviceToHost)
+                             : hipMemcpy(planes[k], p, bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return e;
+      p += bytes;
+    }
+  }
+  return hipSuccess;
+}
+
+void fill_header(const dslam_session* s, CkptHeader* h) {
+  std::memset(h, 0, sizeof(*h));
+  std::memcpy(h->magic, kCkptMagic, 8);
+  h->version = kCkptVersion;
+  h->header_bytes = sizeof(CkptHeader);
+  h->total_bytes = ckpt_bytes(s);
+  h->state_bytes = sizeof(SessionDev);
+  h->model_bytes = model_plane_bytes(s);
+  h->width = s->cam.width;
+  h->height = s->cam.height;
+  h->levels = s->levels;
+  h->mode = s->tp.mode;
+  h->jac_format = s->tp.jac_format;
+  h->have_model = s->have_model ? 1 : 0;
+  for (int l = 0; l < DSLAM_MAX_LEVELS; ++l) {
+    h->iters[l] = l < s->levels ? s->tp.iters[l] : 0;
+    h->ppt[l] = l < s->levels ? s->ppt[l] : 0;
+  }
+  h->fx = s->cam.fx;
+  h->fy = s->cam.fy;
+  h->cx = s->cam.cx;
+  h->cy = s->cam.cy;
+  h->icp_dist = s->tp.icp_dist;
+  h->icp_cos = s->tp.icp_cos;
+  h->sigma_I = s->tp.sigma_I;
+  h->depth_k = s->tp.depth_k;
+  h->huber_k = s->tp.huber_k;
+  h->min_inlier_frac = s->tp.min_inlier_frac;
+  h->max_cost_rise = s->tp.max_cost_rise;
+  std::memcpy(h->T_WM, s->T_WM, sizeof(h->T_WM));
+}
+
+bool ppt_ok(int p) { return p == 1 || p == 2 || p == 4; }
+
+}  // namespace
+
+dslam_status dslam_session_checkpoint(dslam_session* s, void* buf, uint64_t capacity, uint64_t* size) {
+  if (!s || (!buf && !size)) return DSLAM_ERR_INVALID;
+  const uint64_t need = ckpt_bytes(s);
+  if (!buf) {
+    *size = need;
+    return DSLAM_OK;
+  }
+  if (capacity < need) return DSLAM_ERR_INVALID;
+  if (s->server_refs.load() > 0) return DSLAM_ERR_BUSY;
+  std::lock_guard<std::mutex> g(s->mu);
+  HIP_OK(hipSetDevice(s->ctx->device));
+  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
+  uint8_t* p = (uint8_t*)buf;
+  CkptHeader h;
+  fill_header(s, &h);
+  HIP_OK(hipMemcpy(p + sizeof(CkptHeader), s->sd, sizeof(SessionDev), hipMemcpyDeviceToHost));
+  HIP_OK(copy_model_planes(s, p + sizeof(CkptHeader) + sizeof(SessionDev), true));
+  std::memcpy(p, &h, sizeof(h));
+  h.checksum = fnv1a(14695981039346656037ull, p, need);
+  std::memcpy(p, &h, sizeof(h));
+  if (size) *size = need;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_session_restore(dslam_session* s, const void* buf, uint64_t size) {
+  if (!s || !buf || size < sizeof(CkptHeader)) return DSLAM_ERR_INVALID;
+  CkptHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != kCkptVersion || h.header_bytes != sizeof(CkptHeader))
+    return DSLAM_ERR_INVALID;
+  if (h.state_bytes != sizeof(SessionDev) || h.model_bytes != model_plane_bytes(s) || h.total_bytes != ckpt_bytes(s) ||
+      size < h.total_bytes)
+    return DSLAM_ERR_INVALID;
+  {  // checksum over the blob with the checksum field zero
+    CkptHeader z = h;
+    z.checksum = 0;
+    uint64_t c = fnv1a(14695981039346656037ull, &z, sizeof(z));
+    c = fnv1a(c, (const uint8_t*)buf + sizeof(CkptHeader), h.total_bytes - sizeof(CkptHeader));
+    if (c != h.checksum) return DSLAM_ERR_INVALID;
+  }
+  // the session must match the one the blob was taken from (the tile shape is adopted)
+  CkptHeader mine;
+  fill_header(s, &mine);
+  bool same = h.width == mine.width && h.height == mine.height && h.levels == mine.levels && h.mode == mine.mode &&
+              h.jac_format == mine.jac_format && h.fx == mine.fx && h.fy == mine.fy && h.cx == mine.cx &&
+              h.cy == mine.cy && h.icp_dist == mine.icp_dist && h.icp_cos == mine.icp_cos &&
+              h.sigma_I == mine.sigma_I && h.depth_k == mine.depth_k && h.huber_k == mine.huber_k &&
+              h.min_inlier_frac == mine.min_inlier_frac && h.max_cost_rise == mine.max_cost_rise;
+  for (int l = 0; l < DSLAM_MAX_LEVELS; ++l) {
+    same = same && h.iters[l] == mine.iters[l];
+    if (l < s->levels) same = same && ppt_ok(h.ppt[l]);
+  }
+  if (!same || (h.have_model != 0 && h.have_model != 1)) return DSLAM_ERR_INVALID;
+  if (s->server_refs.load() > 0) return DSLAM_ERR_BUSY;
+  std::lock_guard<std::mutex> g(s->mu);
+  HIP_OK(hipSetDevice(s->ctx->device));
+  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
+  const uint8_t* p = (const uint8_t*)buf;
+  HIP_OK(hipMemcpy(s->sd, p + sizeof(CkptHeader), sizeof(SessionDev), hipMemcpyHostToDevice));
+  HIP_OK(copy_model_planes(s, const_cast<uint8_t*>(p) + sizeof(CkptHeader) + sizeof(SessionDev), false));
+  std::memcpy(s->T_WM, h.T_WM, sizeof(s->T_WM));
+  s->have_model = h.have_model == 1;
+  bool retile = false;
+  for (int l = 0; l < s->levels; ++l) {
+    retile = retile || s->ppt[l] != h.ppt[l];
+    s->ppt[l] = h.ppt[l];
+  }
+  if (retile) drop_graphs(s);  // captured with the old tile shape
+  return DSLAM_OK;
+}
+
 dslam_status dslam_session_get_state(dslam_session* s, dslam_frame_state* x0, double q_IW[4], dslam_prior* prior,
                                      int32_t* frame_index) {
   if (!s) return DSLAM_ERR_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
-  HIP_OK(hipDeviceSynchronize());
+  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
   SessionDev d;
   HIP_OK(hipMemcpy(&d, s->sd, sizeof(d), hipMemcpyDeviceToHost));
   if (x0) *x0 = d.x0;
@@ -954,7 +1162,7 @@ dslam_status dslam_session_set_state(dslam_session* s, const dslam_frame_state* 
   if (s->tp.mode != DSLAM_MODE_RGBD && !prior) return DSLAM_ERR_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
-  HIP_OK(hipDeviceSynchronize());
+  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
   SessionDev d;
   HIP_OK(hipMemcpy(&d, s->sd, sizeof(d), hipMemcpyDeviceToHost));
   d.x0 = *x0;

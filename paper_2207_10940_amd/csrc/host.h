@@ -34,7 +34,10 @@ struct dslam_session {
   int max_blocks;
   double* red_out;   // device, 64 doubles
   float* xf_scratch; // device, 24 floats (dslam_linearize)
-  hipEvent_t done;
+  hipEvent_t done;          // recorded after every enqueue of the session's work
+  hipStream_t last_stream;  // stream of the last enqueue (a later enqueue on another stream waits for done)
+  bool enqueued;            // done has been recorded at least once
+  std::atomic<int> server_refs{0};  // requests of the session held by servers (queued or not yet returned)
   bool have_model;
   double T_WM[16];
   int ppt[DSLAM_MAX_LEVELS];

@@ -354,28 +354,25 @@ DX int task_lane(Par par, int t) { return t * 64 < par.nl ? t * 64 : 0; }
 // by barriers (imu_common_par below, or a caller that interleaves other work).
 DX void imu_stage0(Par par, int tb, const dslam_frame_state& x0, const dslam_frame_state& x1, const double* qIW,
                    const dslam_preint& pre, ImuCommon* c, ImuStage* t) {
+  // the operands that are copies of the preintegration's bias Jacobians and
+  // the constant blocks, one entry per lane
+  PFOR(q, 54 + 18) {
+    M3* m = c->mats;
+    if (q < 54) {
+      const int r = q / 6, k = q % 6, blk = r / 3, i = r % 3, j = k % 3;
+      const int id = blk == 0 ? (k < 3 ? IC_JRG : IC_JRA) : (blk == 1 ? (k < 3 ? IC_JVG : IC_JVA)
+                                                                     : (k < 3 ? IC_JPG : IC_JPA));
+      m[id](i, j) = pre.J[q];
+    } else {
+      const int e = q - 54, i = (e % 9) / 3, j = e % 3;
+      m[e < 9 ? IC_I : IC_NEG_I](i, j) = e < 9 ? (i == j ? 1.0 : 0.0) : (i == j ? -1.0 : 0.0);
+    }
+  }
   TASK(tb) {
-    // the operands that are copies of the preintegration's bias Jacobians
-    // (read before any store, see state_boxplus)
-    double J[54];
-    for (int i = 0; i < 54; ++i) J[i] = pre.J[i];
-    const double T = pre.dt;
     double q0[4];
     for (int i = 0; i < 4; ++i) q0[i] = x0.q[i];
     t->R0 = q2R(q0);
-    M3* m = c->mats;
-    m[IC_I] = eye3();
-    m[IC_NEG_I] = (-1.0) * eye3();
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        m[IC_JRG](i, j) = J[6 * i + j];
-        m[IC_JRA](i, j) = J[6 * i + 3 + j];
-        m[IC_JVG](i, j) = J[6 * (3 + i) + j];
-        m[IC_JVA](i, j) = J[6 * (3 + i) + 3 + j];
-        m[IC_JPG](i, j) = J[6 * (6 + i) + j];
-        m[IC_JPA](i, j) = J[6 * (6 + i) + 3 + j];
-      }
-    c->T = T;
+    c->T = pre.dt;
   }
   TASK(tb + 1) {
     t->R1 = q2R(x1.q);
@@ -407,47 +404,74 @@ DX void imu_stage0(Par par, int tb, const dslam_frame_state& x0, const dslam_fra
   }
 }
 
+// The IMU residual in three independent parts (position, rotation,
+// velocity; the bias rows are differences), each one serial task, with the
+// operands the Jacobian blocks reuse.  imu_stage1 runs them on one lane.
+DX void imu_residual_r(const dslam_frame_state& x0, const dslam_frame_state& x1, const dslam_preint& pre,
+                       const ImuParamsD& ip, double* e, ImuStage* t) {
+  const M3 R0 = t->R0, Q = t->Q, Rb = t->Rb, dR = load33(pre.dR);
+  const V3 dpt = t->dpt, v0 = load3(x0.v), r0 = load3(x0.r), r1 = load3(x1.r);
+  const M3 Rcs = load33(ip.R_CS);
+  const V3 tcs = load3(ip.t_CS);
+  const V3 g = v3(0.0, 0.0, -ip.gravity);
+  const double T = pre.dt;
+  const M3 dRt = dR * Rb;
+  const V3 wt = tr(Rcs) * tcs;
+  const V3 yg = T * v0 + (0.5 * T * T) * g;
+  const V3 yr = tcs + Rcs * dpt - Rcs * (dRt * wt);
+  const V3 rh = r0 + R0 * yr + tr(Q) * yg;
+  const V3 er = rh - r1;
+  for (int i = 0; i < 3; ++i) e[i] = er[i];
+  t->yr = yr;
+  t->yg = yg;
+}
+
+DX void imu_residual_a(const dslam_frame_state& x1, const dslam_preint& pre, const ImuParamsD& ip, double* e,
+                       ImuStage* t) {
+  const M3 R0 = t->R0, R1 = t->R1, Rb = t->Rb, dR = load33(pre.dR);
+  const M3 Rcs = load33(ip.R_CS);
+  const M3 dRt = dR * Rb;
+  const M3 S = R0 * Rcs;
+  const M3 SdRt = S * dRt;
+  const M3 Rh1 = SdRt * tr(Rcs);
+  const V3 ea = Log(Rh1 * tr(R1));
+  for (int i = 0; i < 3; ++i) e[3 + i] = ea[i];
+  t->SdRt = SdRt;
+  t->ea = ea;
+}
+
+DX void imu_residual_v(const dslam_frame_state& x0, const dslam_frame_state& x1, const dslam_preint& pre,
+                       const ImuParamsD& ip, double* e, ImuStage* t) {
+  const M3 R0 = t->R0, Q = t->Q;
+  const V3 dvt = t->dvt, v0 = load3(x0.v), v1 = load3(x1.v);
+  const M3 Rcs = load33(ip.R_CS);
+  const V3 g = v3(0.0, 0.0, -ip.gravity);
+  const double T = pre.dt;
+  const M3 S = R0 * Rcs;
+  const V3 Sdv = S * dvt;
+  const V3 QSdv = Q * Sdv;
+  const V3 vh = v0 + T * g + QSdv;
+  const V3 ev = vh - v1;
+  double eb[6];  // read before the first store (see state_boxplus)
+  for (int i = 0; i < 3; ++i) {
+    eb[i] = x0.bg[i] - x1.bg[i];
+    eb[3 + i] = x0.ba[i] - x1.ba[i];
+  }
+  for (int i = 0; i < 3; ++i) {
+    e[6 + i] = ev[i];
+    e[9 + i] = eb[i];
+    e[12 + i] = eb[3 + i];
+  }
+  t->Sdv = Sdv;
+  t->QSdv = QSdv;
+}
+
 DX void imu_stage1(Par par, int tb, const dslam_frame_state& x0, const dslam_frame_state& x1,
                    const dslam_preint& pre, const ImuParamsD& ip, double* e, ImuStage* t) {
   TASK(tb) {
-    M3 R0 = t->R0, Q = t->Q;
-    M3 Rcs = load33(ip.R_CS);
-    V3 tcs = load3(ip.t_CS);
-    V3 g = v3(0.0, 0.0, -ip.gravity);
-    double T = pre.dt;
-    M3 dRt = load33(pre.dR) * t->Rb;
-    M3 S = R0 * Rcs;
-    M3 SdRt = S * dRt;
-    M3 Rh1 = SdRt * tr(Rcs);
-    V3 wt = tr(Rcs) * tcs;
-    V3 v0 = load3(x0.v), r0 = load3(x0.r);
-    V3 yg = T * v0 + (0.5 * T * T) * g;
-    V3 yr = tcs + Rcs * t->dpt - Rcs * (dRt * wt);
-    V3 rh = r0 + R0 * yr + tr(Q) * yg;
-    V3 Sdv = S * t->dvt;
-    V3 QSdv = Q * Sdv;
-    V3 vh = v0 + T * g + QSdv;
-    V3 ea = Log(Rh1 * tr(t->R1));
-    V3 er = rh - load3(x1.r);
-    V3 ev = vh - load3(x1.v);
-    double eb[6];  // read before the first store (see state_boxplus)
-    for (int i = 0; i < 3; ++i) {
-      eb[i] = x0.bg[i] - x1.bg[i];
-      eb[3 + i] = x0.ba[i] - x1.ba[i];
-    }
-    for (int i = 0; i < 3; ++i) {
-      e[i] = er[i];
-      e[3 + i] = ea[i];
-      e[6 + i] = ev[i];
-      e[9 + i] = eb[i];
-      e[12 + i] = eb[3 + i];
-    }
-    t->SdRt = SdRt;
-    t->ea = ea;
-    t->yr = yr;
-    t->yg = yg;
-    t->Sdv = Sdv;
-    t->QSdv = QSdv;
+    imu_residual_r(x0, x1, pre, ip, e, t);
+    imu_residual_a(x1, pre, ip, e, t);
+    imu_residual_v(x0, x1, pre, ip, e, t);
   }
 }
 

@@ -88,7 +88,10 @@ void release(dslam_server* sv) {
     if (st.t0) (void)hipEventDestroy(st.t0);
     if (st.t1) (void)hipEventDestroy(st.t1);
     if (st.stream) (void)hipStreamDestroy(st.stream);
+    for (Request& r : st.reqs) r.s->server_refs.fetch_sub(1);  // dropped with the server
   }
+  for (Request& r : sv->pending) r.s->server_refs.fetch_sub(1);
+  for (dslam_request_done& d : sv->finished) d.session->server_refs.fetch_sub(1);
   delete sv;
 }
 
@@ -244,6 +247,7 @@ dslam_status dslam_server_submit(dslam_server* sv, dslam_session* session, const
   r.in.imu = nullptr;
   r.submit_s = steady_seconds();
   sv->pending.push_back(r);
+  session->server_refs.fetch_add(1);  // the session cannot close while the server holds the request
   if (request_id) *request_id = r.id;
   return DSLAM_OK;
 }
@@ -276,6 +280,7 @@ dslam_status dslam_server_poll(dslam_server* sv, int32_t wait, dslam_request_don
   while (n < max_out && !sv->finished.empty()) {
     out[n++] = sv->finished.front();
     sv->finished.pop_front();
+    out[n - 1].session->server_refs.fetch_sub(1);
   }
   if (n_out) *n_out = n;
   return first_err;

@@ -23,13 +23,13 @@ struct RowSums {
 
 // Blocks of part `part` (0 or 1 of `parts`): this thread's u-range
 // [n part / parts, n (part + 1) / parts) of its n blocks r + 16 u.
+template <int CHUNK = 20>  // loads in flight at once (one round trip for up to 16 CHUNK blocks per part)
 __device__ __forceinline__ void reduce_rows_part(const float* partials, int nblocks, int part, int parts,
                                                  RowSums& rs) {
   const int g = threadIdx.x & 15, r = threadIdx.x >> 4;
   const float* base = partials + 4 * g;
   const int n = nblocks > r ? (nblocks - r + 15) / 16 : 0;  // this thread sums blocks r + 16 u, u < n
   const int lo = n * part / parts, hi = n * (part + 1) / parts;
-  constexpr int CHUNK = 20;  // loads in flight at once (one round trip for up to 320 blocks per part)
   for (int u0 = lo; u0 < hi; u0 += CHUNK) {
     float4 v[CHUNK];
 #pragma unroll
@@ -57,9 +57,10 @@ __device__ __forceinline__ void reduce_rows_store(const RowSums& rs, double* red
   red[r * 64 + 4 * g + 3] = rs.s3;
 }
 
+template <int CHUNK = 20>
 __device__ __forceinline__ void reduce_rows(const float* partials, int nblocks, double* red) {
   RowSums rs;
-  reduce_rows_part(partials, nblocks, 0, 1, rs);
+  reduce_rows_part<CHUNK>(partials, nblocks, 0, 1, rs);
   reduce_rows_store(rs, red);
 }
 
@@ -139,22 +140,20 @@ __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& 
   }
 }
 
-// Workgroup 0 initialises the frame (and, if sp_out is not null, stores the
-// frame's solve parameters there for solve_graph_kernel); the others build the
-// current frame's pyramid (cur) and, if model_tiles > 0, the model view's
-// (model), one tile each, while it runs (the three touch disjoint memory).
+// Workgroup 0 initialises the frame and stores the frame's solve parameters
+// at sp_out for the step kernels; the others build the current frame's
+// pyramid (cur) and, if model_tiles > 0, the model view's (model), one tile
+// each, while it runs (the three touch disjoint memory).
 __global__ __launch_bounds__(SOLVE_THREADS) void frame_init_pyramid_kernel(SessionDev* sd, ImuBatch batch,
-                                                                           FrameArgs fa, PyrArgs cur, PyrArgs model,
-                                                                           int cur_tiles, SolveParams* sp_out) {
+                                                                           FrameArgs fa, SolveParams sp, PyrArgs cur,
+                                                                           PyrArgs model, int cur_tiles,
+                                                                           SolveParams* sp_out) {
   if (blockIdx.x == 0) {
     frame_init_body(sd, batch, fa);
-    if (sp_out && threadIdx.x == 0) {
-      for (int i = 0; i < 9; ++i) sp_out->R_WM[i] = fa.R_WM[i];
-      for (int i = 0; i < 3; ++i) sp_out->t_WM[i] = fa.t_WM[i];
-      sp_out->imu = fa.imu;
-      sp_out->mode = fa.mode;
-      sp_out->marginalise = 1;
-    }
+    // one double per lane (a one-lane struct copy is lowered through scratch memory)
+    static_assert(sizeof(SolveParams) % 8 == 0, "solve parameters in whole doubles");
+    if (threadIdx.x < sizeof(SolveParams) / 8)
+      reinterpret_cast<double*>(sp_out)[threadIdx.x] = reinterpret_cast<const double*>(&sp)[threadIdx.x];
     return;
   }
   const int t = (int)blockIdx.x - 1;
@@ -167,7 +166,8 @@ __global__ __launch_bounds__(SOLVE_THREADS) void frame_init_pyramid_kernel(Sessi
     pyramid_tile<SOLVE_THREADS, 64, 16>(model.src, model.L, model.levels, model.with_grad, t - cur_tiles, lds,
                                         (int)threadIdx.x);
 }
-static_assert(sizeof(SessionDev*) + sizeof(ImuBatch) + sizeof(FrameArgs) + 2 * sizeof(PyrArgs) + 24 <= 4096,
+static_assert(sizeof(SessionDev*) + sizeof(ImuBatch) + sizeof(FrameArgs) + sizeof(SolveParams) + 2 * sizeof(PyrArgs) +
+                  24 <= 4096,
               "frame-init arguments exceed the kernel-argument segment");
 
 // Batched: one workgroup per session of the batch.  (The batched pyramids run
@@ -194,7 +194,8 @@ __device__ __forceinline__ D& state_word(S& x0, S& x1, D* q, int k) {
 // then lives in scratch memory.  The marginalisation of the frame's last step
 // is selected by `last` (sp.marginalise is ignored here).
 __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials, const SolveParams& sp, int level,
-                                           int last, int nblocks) {
+                                           int flags, int nblocks) {
+  const int last = (flags & STEP_LAST) != 0;
   __shared__ SolveWork w;
   __shared__ double raw[58];
   __shared__ dslam_frame_state x0, x1;
@@ -224,9 +225,13 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   DSLAM_SYNC();
   if (skip) {
     if (last) {
+      if (threadIdx.x < 36) state_word(sd->result.x0, sd->result.x1, sd->result.q_IW, (int)threadIdx.x) =
+          state_word(x0, x1, qIW, (int)threadIdx.x);
       SERIAL {
         sd->result.status = sd->status;
         sd->result.frame_index = sd->frame_index;
+        sd->result.health = DSLAM_HEALTH_SINGULAR;
+        sd->result.tracking_lost = 1;
       }
     }
     return;
@@ -307,6 +312,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
     int n = sp.mode != DSLAM_MODE_RGBD ? NZ : 6;
     for (int i = 0; i < n; ++i) nrm += w.dz[i] * w.dz[i];
     sd->result.last_step_norm = sqrt(nrm);
+    if (flags & STEP_FIRST) sd->cost_first = w.cost[0] + w.cost[1];
   }
   if (last) {
     DSLAM_SYNC();
@@ -325,6 +331,21 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
     // the current state becomes the previous one of the next frame
     if (ok && wave == 2 && lane < 16) reinterpret_cast<double*>(&sd->x0)[lane] = reinterpret_cast<const double*>(&x1)[lane];
     SERIAL {
+      // health of the frame (dslam_track_result.health)
+      int h = ok ? 0 : DSLAM_HEALTH_SINGULAR;
+      if (ok) {
+        const double n_in = raw[28] + raw[57];
+        if (sp.min_inliers > 0.0 && n_in < sp.min_inliers) h |= DSLAM_HEALTH_LOW_INLIERS;
+        const double cv = w.cost[0] + w.cost[1];
+        bool fin = isfinite(cv + w.cost[2]) && isfinite(qIW[0] + qIW[1] + qIW[2] + qIW[3]);
+        const double* a = reinterpret_cast<const double*>(&x0);
+        const double* b = reinterpret_cast<const double*>(&x1);
+        for (int i = 0; i < 16; ++i) fin = fin && isfinite(a[i]) && isfinite(b[i]);
+        if (!fin) h |= DSLAM_HEALTH_NONFINITE;
+        if (sp.max_cost_rise > 0.0 && cv > (1.0 + sp.max_cost_rise) * sd->cost_first) h |= DSLAM_HEALTH_COST_UP;
+      }
+      r.health = h;
+      r.tracking_lost = h != 0 ? 1 : 0;
       r.status = sd->status;
       if (ok) sd->frame_index += 1;
       r.frame_index = sd->frame_index;
@@ -333,21 +354,21 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
 }
 
 __global__ __launch_bounds__(SOLVE_THREADS) void solve_kernel(SessionDev* sd, const float* partials, SolveArgs a) {
-  solve_body(sd, partials, a.sp, a.level, a.last, a.nblocks);
+  solve_body(sd, partials, a.sp, a.level, a.flags, a.nblocks);
 }
 
 // The same step with the solve parameters in device memory (stored by the
 // frame's first launch), so that a frame's launches after the first are the
 // same at every frame and can be replayed from a captured graph.
 __global__ __launch_bounds__(SOLVE_THREADS) void solve_graph_kernel(SessionDev* sd, const float* partials,
-                                                                    const SolveParams* sp, int level, int last,
+                                                                    const SolveParams* sp, int level, int flags,
                                                                     int nblocks) {
-  solve_body(sd, partials, *sp, level, last, nblocks);
+  solve_body(sd, partials, *sp, level, flags, nblocks);
 }
 
-__global__ __launch_bounds__(SOLVE_THREADS) void solve_batch_kernel(const SlotSolve* slots, int level, int last) {
+__global__ __launch_bounds__(SOLVE_THREADS) void solve_batch_kernel(const SlotSolve* slots, int level, int flags) {
   const SlotSolve* s = slots + blockIdx.x;
-  solve_body(s->sd, s->partials, s->sp, level, last, s->nblocks[level]);
+  solve_body(s->sd, s->partials, s->sp, level, flags, s->nblocks[level]);
 }
 
 // Copies each session's result record into the batch's contiguous result array.
@@ -364,9 +385,9 @@ hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& 
   return hipGetLastError();
 }
 
-hipError_t launch_solve_graph(SessionDev* sd, const float* partials, const SolveParams* sp, int level, int last,
+hipError_t launch_solve_graph(SessionDev* sd, const float* partials, const SolveParams* sp, int level, int flags,
                               int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(solve_graph_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, sd, partials, sp, level, last, nblocks);
+  hipLaunchKernelGGL(solve_graph_kernel, dim3(1), dim3(SOLVE_THREADS), 0, st, sd, partials, sp, level, flags, nblocks);
   return hipGetLastError();
 }
 
@@ -375,11 +396,11 @@ hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_frame_init_pyramid(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, const PyrArgs& cur,
-                                     const PyrArgs* model, SolveParams* sp_out, hipStream_t st) {
+hipError_t launch_frame_init_pyramid(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, const SolveParams& sp,
+                                     const PyrArgs& cur, const PyrArgs* model, SolveParams* sp_out, hipStream_t st) {
   const int ct = PyrTileBig::tiles(cur.L[0].W, cur.L[0].H);
   const int mt = model ? PyrTileBig::tiles(model->L[0].W, model->L[0].H) : 0;
-  hipLaunchKernelGGL(frame_init_pyramid_kernel, dim3(1 + ct + mt), dim3(SOLVE_THREADS), 0, st, sd, b, fa, cur,
+  hipLaunchKernelGGL(frame_init_pyramid_kernel, dim3(1 + ct + mt), dim3(SOLVE_THREADS), 0, st, sd, b, fa, sp, cur,
                      model ? *model : cur, ct, sp_out);
   return hipGetLastError();
 }
@@ -389,8 +410,8 @@ hipError_t launch_frame_init_batch(const SlotSolve* slots, int n, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_solve_batch(const SlotSolve* slots, int n, int level, int last, hipStream_t st) {
-  hipLaunchKernelGGL(solve_batch_kernel, dim3(n), dim3(SOLVE_THREADS), 0, st, slots, level, last);
+hipError_t launch_solve_batch(const SlotSolve* slots, int n, int level, int flags, hipStream_t st) {
+  hipLaunchKernelGGL(solve_batch_kernel, dim3(n), dim3(SOLVE_THREADS), 0, st, slots, level, flags);
   return hipGetLastError();
 }
 

@@ -33,6 +33,8 @@ struct SolveParams {
   ImuParamsD imu;
   int mode;
   int marginalise;
+  double min_inliers;    // health: level-0 inliers (both terms) below this flag LOW_INLIERS (0: off)
+  double max_cost_rise;  // health: finest-level visual cost rise above this fraction flags COST_UP (0: off)
 };
 
 struct SolveWork {
@@ -491,10 +493,7 @@ DX void init_system_b(Par par, SolveWork* w, const SolveParams& sp, const dslam_
   PFOR(i, NZ) {
     const int pi = iw.pidx(i);
     double a = 0.0;
-    if (full && pi >= 0) {
-      a = prior->b[pi];
-      for (int k = 0; k < 18; ++k) a -= prior->H[18 * pi + k] * w->prior_d[k];
-    }
+    if (full && pi >= 0) a = prior->b[pi] - dotN<18>(prior->H + 18 * pi, 1, w->prior_d, 1);
     if (full && iw.rw(i) != 0.0) {
       const double eb = w->e[i < 15 ? i : i - 15];  // b0 - b1 for this bias entry
       a += (i < 15 ? -iw.rw(i) : iw.rw(i)) * eb;
@@ -527,6 +526,74 @@ DX int solve_step(Par par, SolveWork* w, const double* raw, const SolveParams& s
   init_system(par, w, sp, pre, prior);
   DSLAM_SYNC();
   return solve_back(par, w, sp, pre, prior, x0, x1, qIW, marg_out);
+}
+
+// IMU term into the system: with the whitened rows M9 J9 in Y and M9 e in y,
+// H += (M9 J9)^T (M9 J9), b -= (M9 J9)^T (M9 e), and the IMU cost |M9 e|^2
+// plus the random-walk rows into cost[2].  Gyro-only mode holds the entries
+// no remaining term constrains fixed.
+DX void imu_accumulate(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre) {
+  const bool gyro = sp.mode == DSLAM_MODE_GYRO;
+  // H += (M9 J9)^T (M9 J9), b -= (M9 J9)^T (M9 e); the IMU cost |M9 e|^2 plus
+  // the random-walk rows
+  TASK(1) {
+    double c = dotN<9>(w->y, 1, w->y, 1);
+    const double T = pre->dt;
+    const double wbg = 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T);
+    const double wba = gyro ? 0.0 : 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T);
+    for (int i = 0; i < 3; ++i) c += wbg * w->e[9 + i] * w->e[9 + i] + wba * w->e[12 + i] * w->e[12 + i];
+    w->cost[2] = c;
+  }
+  // (M9 J9)^T (M9 J9) is symmetric bit for bit (entry (j, i) has the same
+  // products in the same order as (i, j)), so each unordered pair is formed
+  // once and added to both entries.  Items: the 33 x 17 pairs (i, i + c mod
+  // 33), c = 0..16 (33 is odd: every pair i != j has one circular distance
+  // of at most 16 in one direction), then the 33 right-hand-side entries; a
+  // lane forms its two items' dot products together (all reads in flight)
+  // before any update.
+  constexpr int NPAIR = NZ * 17, NITEM = NPAIR + NZ;
+  for (int base = par.lane; base < NITEM; base += 2 * par.nl) {
+    int ii[2], jj[2];
+    double xa[2][9], xb[2][9];
+    for (int u = 0; u < 2; ++u) {
+      const int it = base + u * par.nl;
+      const int q = it < NITEM ? it : 0;  // a past-the-end item reads item 0 and is not applied
+      const bool pair = q < NPAIR;
+      const int i = pair ? q % NZ : q - NPAIR, c = pair ? q / NZ : 0;
+      const int j = pair ? (i + c < NZ ? i + c : i + c - NZ) : -1;
+      ii[u] = i;
+      jj[u] = j;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        xa[u][k] = w->Y[k * NZ + i];
+        xb[u][k] = pair ? w->Y[k * NZ + j] : w->y[k];
+      }
+    }
+#ifdef __HIP_DEVICE_COMPILE__
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+    for (int u = 0; u < 2; ++u) {
+      if (base + u * par.nl >= NITEM) continue;
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) a += xa[u][k] * xb[u][k];
+      const int i = ii[u], j = jj[u];
+      if (j >= 0) {
+        // gyro-only: the entries no remaining term constrains are held fixed
+        // (identity rows and columns, zero right-hand side)
+        if (gyro && (gyro_fixed(i) || gyro_fixed(j))) {
+          w->H[i * NZ + j] = (i == j) ? 1.0 : 0.0;
+          w->H[j * NZ + i] = (i == j) ? 1.0 : 0.0;
+        } else {
+          w->H[i * NZ + j] += a;
+          if (j != i) w->H[j * NZ + i] += a;
+        }
+      } else {
+        if (gyro && gyro_fixed(i)) w->b[i] = 0.0;
+        else w->b[i] -= a;
+      }
+    }
+  }
 }
 
 DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_preint* pre, const dslam_prior* prior,
@@ -583,66 +650,7 @@ DX int solve_back(Par par, SolveWork* w, const SolveParams& sp, const dslam_prei
       }
     }
     DSLAM_SYNC();
-    // H += (M9 J9)^T (M9 J9), b -= (M9 J9)^T (M9 e); the IMU cost |M9 e|^2 plus
-    // the random-walk rows
-    TASK(1) {
-      double c = dotN<9>(w->y, 1, w->y, 1);
-      const double T = pre->dt;
-      const double wbg = 1.0 / (sp.imu.sigma_bg_rw * sp.imu.sigma_bg_rw * T);
-      const double wba = gyro ? 0.0 : 1.0 / (sp.imu.sigma_ba_rw * sp.imu.sigma_ba_rw * T);
-      for (int i = 0; i < 3; ++i) c += wbg * w->e[9 + i] * w->e[9 + i] + wba * w->e[12 + i] * w->e[12 + i];
-      w->cost[2] = c;
-    }
-    // (M9 J9)^T (M9 J9) is symmetric bit for bit (entry (j, i) has the same
-    // products in the same order as (i, j)), so each unordered pair is formed
-    // once and added to both entries.  Items: the 33 x 17 pairs (i, i + c mod
-    // 33), c = 0..16 (33 is odd: every pair i != j has one circular distance
-    // of at most 16 in one direction), then the 33 right-hand-side entries; a
-    // lane forms its two items' dot products together (all reads in flight)
-    // before any update.
-    constexpr int NPAIR = NZ * 17, NITEM = NPAIR + NZ;
-    for (int base = par.lane; base < NITEM; base += 2 * par.nl) {
-      int ii[2], jj[2];
-      double xa[2][9], xb[2][9];
-      for (int u = 0; u < 2; ++u) {
-        const int it = base + u * par.nl;
-        const int q = it < NITEM ? it : 0;  // a past-the-end item reads item 0 and is not applied
-        const bool pair = q < NPAIR;
-        const int i = pair ? q % NZ : q - NPAIR, c = pair ? q / NZ : 0;
-        const int j = pair ? (i + c < NZ ? i + c : i + c - NZ) : -1;
-        ii[u] = i;
-        jj[u] = j;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          xa[u][k] = w->Y[k * NZ + i];
-          xb[u][k] = pair ? w->Y[k * NZ + j] : w->y[k];
-        }
-      }
-#ifdef __HIP_DEVICE_COMPILE__
-      __builtin_amdgcn_sched_barrier(0);
-#endif
-      for (int u = 0; u < 2; ++u) {
-        if (base + u * par.nl >= NITEM) continue;
-        double a = 0.0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) a += xa[u][k] * xb[u][k];
-        const int i = ii[u], j = jj[u];
-        if (j >= 0) {
-          // gyro-only: the entries no remaining term constrains are held fixed
-          // (identity rows and columns, zero right-hand side)
-          if (gyro && (gyro_fixed(i) || gyro_fixed(j))) {
-            w->H[i * NZ + j] = (i == j) ? 1.0 : 0.0;
-            w->H[j * NZ + i] = (i == j) ? 1.0 : 0.0;
-          } else {
-            w->H[i * NZ + j] += a;
-            if (j != i) w->H[j * NZ + i] += a;
-          }
-        } else {
-          if (gyro && gyro_fixed(i)) w->b[i] = 0.0;
-          else w->b[i] -= a;
-        }
-      }
-    }
+    imu_accumulate(par, w, sp, pre);
     DSLAM_SYNC();
   }
   // ---- solve H dz = b (and, on the last iteration, the Schur complement of x0)

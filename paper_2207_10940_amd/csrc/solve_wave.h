@@ -21,25 +21,29 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// Gauss-Jordan on the rows held by the lanes of one wavefront: lane i < NSTEP
-// holds R[0..NC) = row i of [A | B] with A (NSTEP x NSTEP) symmetric positive
-// definite.  After the loop every pivot column k < NSTEP is zero in every row
-// but row k, whose entries are left unscaled.  If cap != nullptr, rows
-// CAP..NSTEP-1, columns CAP..NC-1 are stored there just before step CAP
-// (row-major, NC - CAP per row).
+// Gauss-Jordan on the rows held by the lanes of one wavefront: lane i < NSYM
+// holds R[0..NC) = row i of [A | B] with A (NSYM x NSYM) symmetric and its
+// leading NSTEP x NSTEP block positive definite; the first NSTEP columns are
+// eliminated (NSYM = NSTEP: a plain solve; NSYM > NSTEP: the trailing rows
+// end as the Schur complement of the leading block).  After the loop every
+// pivot column k < NSTEP is zero in every row but row k, whose entries are
+// left unscaled.  If cap != nullptr, rows CAP..NSTEP-1, columns CAP..NC-1 are
+// stored there just before step CAP (row-major, NC - CAP per row).
 //
 // The trailing block of a symmetric matrix stays symmetric under elimination,
-// so the pivot row's entries A[k][j], j > k, equal column k's entries A[j][k],
-// which lane j holds: one shared-memory store per lane publishes the whole
-// pivot row, and every lane reads it back with wide broadcast loads.  The
-// pivot row's right-hand-side entries are published by lane k.
+// so the pivot row's entries A[k][j], k < j < NSYM, equal column k's entries
+// A[j][k], which lane j holds: one shared-memory store per lane publishes the
+// whole pivot row, and every lane reads it back with wide broadcast loads.
+// The pivot row's right-hand-side entries (columns NSYM..NC-1) are published
+// by lane k.
 //
 // With FWD, rows above the pivot are left alone (forward elimination only):
 // lane i then ends with row i of [U | E] where S = E^-1 U, E unit lower
 // triangular and U upper triangular with U_ii the pivots.
-template <int NC, int NSTEP, int CAP, bool FWD = false>
+template <int NC, int NSTEP, int CAP, bool FWD = false, int NSYM = NSTEP>
 __device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* col, double* cap) {
-  constexpr int NR = NC - NSTEP;  // right-hand-side columns
+  static_assert(NSYM >= NSTEP && NSYM <= NC && NSYM <= 64, "symmetric block");
+  constexpr int NR = NC - NSYM;  // right-hand-side columns
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < NSTEP; ++k) {
@@ -55,7 +59,7 @@ __device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* 
     const double p = readlane_d(R[k], k);
     double rhs[NR > 0 ? NR : 1];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) rhs[j] = readlane_d(R[NSTEP + j], k);
+    for (int j = 0; j < NR; ++j) rhs[j] = readlane_d(R[NSYM + j], k);
     ok = ok && (p > 0.0) && (p < 1e300);
     // reciprocal: hardware estimate refined by two Newton steps (full precision)
     double inv = __builtin_amdgcn_rcp(p);
@@ -65,10 +69,10 @@ __device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* 
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     // the whole remaining column into registers with 16-byte broadcast reads,
     // all in flight at once, before any update uses them
-    double cv[NSTEP];
+    double cv[NSYM];
 #pragma unroll
-    for (int j = (k + 1) & ~1; j < NSTEP; j += 2) {
-      if (j + 1 < NSTEP) {
+    for (int j = (k + 1) & ~1; j < NSYM; j += 2) {
+      if (j + 1 < NSYM) {
         const double2 t = *reinterpret_cast<const double2*>(c + j);
         cv[j] = t.x;
         cv[j + 1] = t.y;
@@ -78,9 +82,9 @@ __device__ __forceinline__ bool gauss_jordan(double (&R)[NC], int lane, double* 
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = k + 1; j < NSTEP; ++j) R[j] = fma(-m, cv[j], R[j]);
+    for (int j = k + 1; j < NSYM; ++j) R[j] = fma(-m, cv[j], R[j]);
 #pragma unroll
-    for (int j = 0; j < NR; ++j) R[NSTEP + j] = fma(-m, rhs[j], R[NSTEP + j]);
+    for (int j = 0; j < NR; ++j) R[NSYM + j] = fma(-m, rhs[j], R[NSYM + j]);
   }
   return ok;
 }

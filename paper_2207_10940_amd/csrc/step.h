@@ -27,7 +27,7 @@ struct FrameArgs {
 struct SolveArgs {
   SolveParams sp;
   int32_t level;
-  int32_t last;      // 1 on the last iteration of the frame: marginalise and publish
+  int32_t flags;     // STEP_* flags
   int32_t nblocks;
 };
 
@@ -40,6 +40,11 @@ struct SlotSolve {
   SolveParams sp;
   int32_t nblocks[DSLAM_MAX_LEVELS];
 };
+
+// Flags of a visual solve: the first iteration of the frame's finest level
+// (records the cost the health check compares with) and the frame's last
+// iteration (solves the 33-d system, marginalises, publishes the result).
+enum { STEP_FIRST = 1, STEP_LAST = 2 };
 
 // pyramid.hip
 hipError_t launch_pyramid(const PyrArgs& a, hipStream_t st);
@@ -56,17 +61,18 @@ hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int l
 
 // solve.hip
 // the frame initialisation, the current frame's pyramid and (model != nullptr)
-// the model view's pyramid in one launch; if sp_out is not null the frame's
-// solve parameters are stored there for launch_solve_graph
-hipError_t launch_frame_init_pyramid(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, const PyrArgs& cur,
-                                     const PyrArgs* model, SolveParams* sp_out, hipStream_t st);
+// the model view's pyramid in one launch; the frame's solve parameters are
+// stored at sp_out, where the step kernels read them
+hipError_t launch_frame_init_pyramid(SessionDev* sd, const ImuBatch& b, const FrameArgs& fa, const SolveParams& sp,
+                                     const PyrArgs& cur, const PyrArgs* model, SolveParams* sp_out, hipStream_t st);
+// one Gauss-Newton step of one session after its residual pass (STEP_* flags)
 hipError_t launch_solve(SessionDev* sd, const float* partials, const SolveArgs& a, hipStream_t st);
 // the same step with the solve parameters read from device memory
-hipError_t launch_solve_graph(SessionDev* sd, const float* partials, const SolveParams* sp, int level, int last,
+hipError_t launch_solve_graph(SessionDev* sd, const float* partials, const SolveParams* sp, int level, int flags,
                               int nblocks, hipStream_t st);
 hipError_t launch_reduce(const float* partials, int nblocks, double* out, hipStream_t st);
 hipError_t launch_frame_init_batch(const SlotSolve* slots, int n, hipStream_t st);
-hipError_t launch_solve_batch(const SlotSolve* slots, int n, int level, int last, hipStream_t st);
+hipError_t launch_solve_batch(const SlotSolve* slots, int n, int level, int flags, hipStream_t st);
 hipError_t launch_gather_results(const SlotSolve* slots, int n, dslam_track_result* out, hipStream_t st);
 
 }  // namespace dslam

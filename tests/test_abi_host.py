@@ -33,6 +33,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("dslam_build_pyramid", "dslam_preintegrate_imu", "dslam_solve_step", "dslam_track_frame",
+                     "dslam_track_frame_sync", "dslam_session_checkpoint", "dslam_session_restore",
                      "dslam_context_create", "dslam_session_open", "dslam_session_close", "dslam_status_string"):
         assert required in names
 
