@@ -509,6 +509,23 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
                                const dslam_frame_input* frames, void* stream);
 /* Wait for the batch's last step and copy its n results, in call order. */
 dslam_status dslam_batch_results(dslam_batch* b, dslam_track_result* out);
+
+/* The batched step for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same step as dslam_batch_track followed by dslam_batch_results, with the same
+ * results bit for bit, but no dslam_batch is needed and nothing is allocated.
+ * The slot records and results live in a static device array of 1.8 MiB
+ * (DSLAM_MAX_BATCH sessions' records; each GPU the library runs on holds its
+ * own copy until the process ends, its address resolved by
+ * dslam_context_create) and static host staging.  Every call on a GPU shares
+ * that GPU's array, which keeps the last call's contents (every record the
+ * step reads is written by the call first, so nothing needs clearing); calls
+ * are serialised by the library and each waits for its step, so calls that
+ * would overlap on one GPU run one after the other.  Sessions as for
+ * dslam_batch_track (all of one context); results (host, n entries) in call
+ * order.  Errors: INVALID (arguments, n > DSLAM_MAX_BATCH), DEVICE. */
+dslam_status dslam_batch_track_noalloc(int32_t n, dslam_session* const* sessions, const dslam_frame_input* frames,
+                                       dslam_track_result* results, void* stream);
 /* Launch the batched residual pass of `level` of the batch's last step `reps`
  * times back to back on `stream` (same sessions, transforms and work split;
  * only the sessions' scratch partials are written, no estimator state

@@ -526,6 +526,22 @@ class Batch:
         return [result_dict(out[i]) for i in range(self._n)]
 
 
+def batch_track_noalloc(sessions, frames, stream=None) -> list:
+    """dslam_batch_track_noalloc: one batched step with the library's static scratch (no allocation); waits
+    and returns the results in call order."""
+    n = len(sessions)
+    hs = (C.c_void_p * n)(*[s.handle for s in sessions])
+    fis, keep = [], []
+    for f in frames:
+        fi, k = frame_input(f)
+        fis.append(fi)
+        keep.append(k)
+    arr = (_abi.FrameInput * n)(*fis)
+    out = (_abi.TrackResult * n)()
+    _check(lib().dslam_batch_track_noalloc(n, hs, arr, out, _stream_ptr(stream)), "dslam_batch_track_noalloc")
+    return [result_dict(out[i]) for i in range(n)]
+
+
 class Server:
     """Serving loop with continuous batching (dslam_server_*).  One thread drives it."""
 

@@ -140,6 +140,7 @@ SIGNATURES = {
     "dslam_batch_track": (C.c_int, [vp, C.c_int32, P(vp), P(FrameInput), vp]),
     "dslam_session_set_graphs": (C.c_int, [vp, C.c_int32]),
     "dslam_batch_results": (C.c_int, [vp, P(TrackResult)]),
+    "dslam_batch_track_noalloc": (C.c_int, [C.c_int32, P(vp), P(FrameInput), P(TrackResult), vp]),
     "dslam_batch_profile_residual": (C.c_int, [vp, C.c_int32, C.c_int32, vp, P(C.c_uint64)]),
     "dslam_server_create": (C.c_int, [vp, P(ServerParams), P(vp)]),
     "dslam_server_destroy": (C.c_int, [vp]),

@@ -17,6 +17,21 @@
 
 using namespace dslam;
 
+// ---- static scratch of the allocation-free batched step ---------------------
+// One batched step's slot records and results (the memory a dslam_batch
+// allocates) for up to DSLAM_MAX_BATCH sessions, in a file-scope device array:
+// every GPU the library runs on holds its own copy until the process ends.
+// Host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device (the array's name is a host-side stand-in), resolved
+// once per device by dslam_context_create.
+static constexpr size_t al256(size_t n) { return (n + 255) & ~size_t(255); }
+static constexpr size_t kScratchVis = al256(sizeof(dslam::SlotVis) * DSLAM_MAX_BATCH);
+static constexpr size_t kScratchSolve = al256(sizeof(dslam::SlotSolve) * DSLAM_MAX_BATCH);
+static constexpr size_t kScratchRes = al256(sizeof(dslam_track_result) * DSLAM_MAX_BATCH);
+static constexpr size_t kScratchBytes = kScratchVis + kScratchSolve + kScratchRes;
+static_assert(kScratchBytes <= (4u << 20), "the static scratch stays within 4 MiB");
+static __device__ __attribute__((aligned(256))) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 const char* kStatus[] = {"ok", "invalid argument", "no capacity", "singular system", "device error", "busy",
@@ -234,6 +249,36 @@ hipError_t mark_session(dslam_session* s, hipStream_t st) {
   return e;
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// With `device` current: the device address of its scratch copy, once.
+hipError_t resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+// host staging of the same records (static, pageable: their copies complete
+// before the call returns); one host thread uses them at a time
+SlotVis g_hvis[DSLAM_MAX_BATCH];
+SlotSolve g_hsolve[DSLAM_MAX_BATCH];
+dslam_track_result g_hres[DSLAM_MAX_BATCH];
+std::mutex g_noalloc_mu;
+
 }  // namespace
 
 extern "C" {
@@ -252,6 +297,8 @@ dslam_status dslam_context_create(int32_t device, uint64_t hbm_budget_bytes, dsl
   int n = 0;
   HIP_OK(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return DSLAM_ERR_INVALID;
+  HIP_OK(hipSetDevice(device));
+  HIP_OK(resolve_scratch(device));  // the static batch scratch of this device (dslam_batch_track_noalloc)
   dslam_context* c = new (std::nothrow) dslam_context;
   if (!c) return DSLAM_ERR_NO_CAPACITY;
   c->device = device;
@@ -750,16 +797,38 @@ dslam_status dslam_batch_destroy(dslam_batch* b) {
   return DSLAM_OK;
 }
 
-dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* sessions,
-                               const dslam_frame_input* frames, void* stream) {
-  if (!b || !sessions || !frames || n < 1 || n > b->max_n) return DSLAM_ERR_INVALID;
+}  // extern "C"
+
+namespace {
+
+// Host and device memory of one batched step: staging of the slot records
+// (pinned or static host memory) and their device copies, plus the results.
+struct BatchMem {
+  SlotVis* h_vis;
+  SlotSolve* h_solve;
+  dslam_track_result* h_res;
+  SlotVis* d_vis;
+  SlotSolve* d_solve;
+  dslam_track_result* d_res;
+};
+
+// What the batched step's launches were (for dslam_batch_profile_residual).
+struct BatchInfo {
+  int levels, jac;
+  int max_ppt[DSLAM_MAX_LEVELS];
+  BatchGrid res_grid[DSLAM_MAX_LEVELS];
+  uint64_t pixels[DSLAM_MAX_LEVELS];
+};
+
+// Validates a batched step's arguments without touching any state.
+dslam_status batch_validate(const dslam_context* ctx, int32_t n, dslam_session* const* sessions,
+                            const dslam_frame_input* frames) {
   const dslam_session* s0 = sessions[0];
   if (!s0) return DSLAM_ERR_INVALID;
-  // ---- validate everything before touching any state
   for (int i = 0; i < n; ++i) {
     const dslam_session* s = sessions[i];
     const dslam_frame_input& f = frames[i];
-    if (!s || s->ctx != b->ctx || s->levels != s0->levels || s->tp.jac_format != s0->tp.jac_format)
+    if (!s || s->ctx != ctx || s->levels != s0->levels || s->tp.jac_format != s0->tp.jac_format)
       return DSLAM_ERR_INVALID;
     for (int l = 0; l < s->levels; ++l)
       if (s->tp.iters[l] != s0->tp.iters[l]) return DSLAM_ERR_INVALID;
@@ -772,10 +841,25 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
     const dslam_status sti = pack_imu(s, f.imu, f.n_imu, f.t0, f.t1, &probe);
     if (sti != DSLAM_OK) return sti;
   }
-  const int last_level = last_level_of(s0->tp);
-  if (last_level < 0) return DSLAM_ERR_INVALID;
+  if (last_level_of(s0->tp) < 0) return DSLAM_ERR_INVALID;
+  int nres = 0;
+  for (int i = 0; i < n; ++i) {
+    bool known = false;
+    for (int j = 0; j < i; ++j)
+      known = known || (sessions[j]->cam.width == sessions[i]->cam.width &&
+                        sessions[j]->cam.height == sessions[i]->cam.height);
+    nres += known ? 0 : 1;
+  }
+  return nres > MAX_CLASSES ? DSLAM_ERR_INVALID : DSLAM_OK;
+}
+
+// Stages and enqueues one validated batched step on `st` (Section IV for each
+// session, with shared launches); the results land in m.h_res (slot order)
+// once the stream has passed the step.  order[k] = caller index of slot k.
+dslam_status batch_enqueue(const BatchMem& m, int32_t n, dslam_session* const* sessions,
+                           const dslam_frame_input* frames, hipStream_t st, int* order, BatchInfo* info) {
+  const dslam_session* s0 = sessions[0];
   // ---- slot order: sessions grouped by resolution, larger images first
-  int order[MAX_BATCH];
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order, order + n, [&](int a, int c) {
     const dslam_camera& A = sessions[a]->cam;
@@ -791,11 +875,7 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
   }
   if (nclass > MAX_CLASSES) return DSLAM_ERR_INVALID;
   cls_first[nclass] = n;
-  HIP_OK(hipSetDevice(b->ctx->device));
-  if (b->pending) HIP_OK(hipEventSynchronize(b->done));  // staging memory is reused
-  b->pending = false;
-  hipStream_t st = (hipStream_t)stream;
-  // ---- stage the slots (everything was validated above)
+  // ---- stage the slots (everything was validated)
   ImuBatch imu;
   for (int k = 0; k < n; ++k) {
     dslam_session* s = sessions[order[k]];
@@ -803,8 +883,8 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
     (void)pack_imu(s, f.imu, f.n_imu, f.t0, f.t1, &imu);
     HIP_OK(order_after_session(s, st));
     std::memcpy(s->T_WM, f.T_WM, sizeof(s->T_WM));
-    SlotVis& v = b->h_vis[k];
-    SlotSolve& o = b->h_solve[k];
+    SlotVis& v = m.h_vis[k];
+    SlotSolve& o = m.h_solve[k];
     for (int l = 0; l < s->levels; ++l) {
       v.res[l] = residual_args(s, l, s->sd->xf, nullptr);
       v.cur[l] = s->cur[l];
@@ -824,8 +904,8 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
     o.sp = solve_params(s);
     o.fa = frame_args(s, o.sp);
   }
-  HIP_OK(hipMemcpyAsync(b->d_vis, b->h_vis, sizeof(SlotVis) * n, hipMemcpyHostToDevice, st));
-  HIP_OK(hipMemcpyAsync(b->d_solve, b->h_solve, sizeof(SlotSolve) * n, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(m.d_vis, m.h_vis, sizeof(SlotVis) * n, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(m.d_solve, m.h_solve, sizeof(SlotSolve) * n, hipMemcpyHostToDevice, st));
   // ---- work split of each launch: one class per resolution
   auto grid = [&](auto blocks_of) {
     BatchGrid g;
@@ -843,11 +923,11 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
   };
   {  // every level of the current and model-view pyramids: one launch
     BatchGrid g = grid([&](const dslam_session* s) { return 2 * PyrTileStd::tiles(s->cam.width, s->cam.height); });
-    HIP_OK(launch_pyramid_batch(b->d_vis, s0->levels, g, st));
+    HIP_OK(launch_pyramid_batch(m.d_vis, s0->levels, g, st));
   }
-  HIP_OK(launch_frame_init_batch(b->d_solve, n, st));
-  b->levels = s0->levels;
-  b->jac = s0->tp.jac_format;
+  HIP_OK(launch_frame_init_batch(m.d_solve, n, st));
+  info->levels = s0->levels;
+  info->jac = s0->tp.jac_format;
   for (int l = s0->levels - 1; l >= 0; --l) {
     int max_ppt = 1;
     uint64_t px = 0;
@@ -856,25 +936,75 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
       px += (uint64_t)sessions[k]->cur[l].W * sessions[k]->cur[l].H;
     }
     BatchGrid g = grid([&](const dslam_session* s) { return residual_blocks(s->cur[l].W * s->cur[l].H, s->ppt[l]); });
-    b->res_grid[l] = g;
-    b->max_ppt[l] = max_ppt;
-    b->pixels[l] = px;
+    info->res_grid[l] = g;
+    info->max_ppt[l] = max_ppt;
+    info->pixels[l] = px;
     for (int it = 0; it < s0->tp.iters[l]; ++it) {
-      HIP_OK(launch_residual_batch(b->d_vis, g, l, max_ppt, s0->tp.jac_format, st));
-      HIP_OK(launch_solve_batch(b->d_solve, n, l, step_flags(s0->tp, l, it), st));
+      HIP_OK(launch_residual_batch(m.d_vis, g, l, max_ppt, s0->tp.jac_format, st));
+      HIP_OK(launch_solve_batch(m.d_solve, n, l, step_flags(s0->tp, l, it), st));
     }
   }
-  HIP_OK(launch_gather_results(b->d_solve, n, b->d_res, st));
-  HIP_OK(hipMemcpyAsync(b->h_res, b->d_res, sizeof(dslam_track_result) * n, hipMemcpyDeviceToHost, st));
-  HIP_OK(hipEventRecord(b->done, st));
+  HIP_OK(launch_gather_results(m.d_solve, n, m.d_res, st));
+  HIP_OK(hipMemcpyAsync(m.h_res, m.d_res, sizeof(dslam_track_result) * n, hipMemcpyDeviceToHost, st));
   for (int k = 0; k < n; ++k) {
     dslam_session* s = sessions[order[k]];
     s->have_model = true;
     HIP_OK(mark_session(s, st));
-    b->order[k] = order[k];
+  }
+  return DSLAM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* sessions,
+                               const dslam_frame_input* frames, void* stream) {
+  if (!b || !sessions || !frames || n < 1 || n > b->max_n) return DSLAM_ERR_INVALID;
+  const dslam_status v = batch_validate(b->ctx, n, sessions, frames);
+  if (v != DSLAM_OK) return v;
+  HIP_OK(hipSetDevice(b->ctx->device));
+  if (b->pending) HIP_OK(hipEventSynchronize(b->done));  // staging memory is reused
+  b->pending = false;
+  hipStream_t st = (hipStream_t)stream;
+  const BatchMem m{b->h_vis, b->h_solve, b->h_res, b->d_vis, b->d_solve, b->d_res};
+  BatchInfo info;
+  const dslam_status e = batch_enqueue(m, n, sessions, frames, st, b->order, &info);
+  if (e != DSLAM_OK) return e;
+  HIP_OK(hipEventRecord(b->done, st));
+  b->levels = info.levels;
+  b->jac = info.jac;
+  for (int l = 0; l < info.levels; ++l) {
+    b->max_ppt[l] = info.max_ppt[l];
+    b->res_grid[l] = info.res_grid[l];
+    b->pixels[l] = info.pixels[l];
   }
   b->n = n;
   b->pending = true;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_batch_track_noalloc(int32_t n, dslam_session* const* sessions, const dslam_frame_input* frames,
+                                       dslam_track_result* results, void* stream) {
+  if (!sessions || !frames || !results || n < 1 || !sessions[0]) return DSLAM_ERR_INVALID;
+  if (n > DSLAM_MAX_BATCH) return DSLAM_ERR_INVALID;  // the scratch holds DSLAM_MAX_BATCH slots
+  dslam_context* ctx = sessions[0]->ctx;
+  const dslam_status v = batch_validate(ctx, n, sessions, frames);
+  if (v != DSLAM_OK) return v;
+  unsigned char* base = (unsigned char*)scratch_ptr(ctx->device);
+  if (!base) return DSLAM_ERR_DEVICE;
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  // every slot the step reads is written first: nothing in the scratch needs clearing
+  const BatchMem m{g_hvis, g_hsolve, g_hres, (SlotVis*)base, (SlotSolve*)(base + kScratchVis),
+                   (dslam_track_result*)(base + kScratchVis + kScratchSolve)};
+  int order[MAX_BATCH];
+  BatchInfo info;
+  const dslam_status e = batch_enqueue(m, n, sessions, frames, st, order, &info);
+  if (e != DSLAM_OK) return e;
+  HIP_OK(hipStreamSynchronize(st));
+  for (int k = 0; k < n; ++k) results[order[k]] = g_hres[k];
   return DSLAM_OK;
 }
 
