@@ -25,15 +25,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "tracked frames/s + residual-pass GB/s at 640x480; p50/p99 track latency"
 HBM_PEAK_GBS = 8000.0
+# vector-ALU issue peak without packed FP32 (the library is built with it off): 256 CUs x 4 SIMDs x 2.4 GHz,
+# one wave64 instruction per SIMD every 4 cycles
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
 COPY_BYTES = 256 << 20  # calibration copy for the HBM byte counters
-# HBM bytes per level-0 residual launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by the
-# reading of a 256 MiB copy (fetch x1.99985, write x1.0); valid for the kernel source with this hash.
-TRAFFIC_BYTES_LEVEL0 = (7810.9 * 262144 / 131085.1 + 150.0) * 1024
-TRAFFIC_SOURCE_SHA256 = "fd49821d72aecd30"
-# bytes the residual pass reads per pixel-iteration: current vertex 12 + intensity 2, model-view vertex 12 +
-# normal 12 + intensity 2 + gradient 4 (16-bit fixed-point intensity and gradient; N1 unread without the
-# normal gate)
-REF_BYTES_PER_PIXEL = 44
+# bytes per pixel-iteration of the residual pass under three accountings: the algorithmic floor (depth 4 +
+# intensity 1 of the current frame and of the model view; everything else can be recomputed), the reference
+# layout (all-float32 maps: V1 12 + N1 12 + I1 4 + V0 12 + N0 12 + I0 4 + G0 8) and this library's layout
+# (current vertex 12 + intensity 2, model vertex 12 + normal 12 + intensity 2 + gradient 4, 16-bit
+# fixed-point intensity and gradient; the current normal is unread without the normal gate)
+FLOOR_BYTES_PER_PIXEL = 10
+REF_LAYOUT_BYTES_PER_PIXEL = 64
+LAYOUT_BYTES_PER_PIXEL = 44
+# hardware counters of one level-0 residual launch at 640x480 (float32 rows) per launch shape ("ppt,banded")
+# and of a 256 MiB calibration copy, from rocprofv3 --pmc runs of `bench.py --counters --counters-batch`
+# (profiles/residual_kernel_640x480_counters.md); valid for the residual-pass sources with this hash
+COUNTERS = {
+    "source_sha256": "e881484d1ef392f8",
+    "copy_fetch_kib": 131086.8, "copy_write_kib": 262144.0,
+    "shapes": {  # "ppt,banded": per-dispatch means over 50 back-to-back launches
+        "1,0": {"fetch_kib": 7947.7, "write_kib": 300.0, "valu_insts": 2433026, "waves": 4800},
+        "1,1": {"fetch_kib": 5159.2, "write_kib": 300.0, "valu_insts": 2433026, "waves": 4800},
+        "2,0": {"fetch_kib": 7866.4, "write_kib": 150.0, "valu_insts": 1959026, "waves": 2400},
+        "2,1": {"fetch_kib": 5194.2, "write_kib": 150.0, "valu_insts": 1959026, "waves": 2400},
+        "4,0": {"fetch_kib": 6828.5, "write_kib": 75.0, "valu_insts": 1749626, "waves": 1200},
+        "4,1": {"fetch_kib": 5260.2, "write_kib": 75.0, "valu_insts": 1749626, "waves": 1200},
+    },
+}
+RESIDUAL_SOURCES = ("kernels.hip", "residual.h", "device.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "bench_oracle.json")
 
 
 def log(msg):
@@ -58,12 +78,82 @@ def frame_inputs(seq, j):
     return md, mi, T, seq["depth"][j], seq["intensity"][j], imu, t0, t1
 
 
-def measured_traffic():
+def residual_source_hash():
     import hashlib
-    src = os.path.join(ROOT, "paper_2207_10940_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()
-    return TRAFFIC_BYTES_LEVEL0 if h.startswith(TRAFFIC_SOURCE_SHA256) else None
+    h = hashlib.sha256()
+    for name in RESIDUAL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2207_10940_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_figures(ppt, banded):
+    """HBM bytes (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a copy of known size) and VALU
+    wave-instructions of one level-0 residual launch of the given shape, or None when the kernel sources
+    changed since the counters were taken."""
+    c = COUNTERS
+    f = c["shapes"].get(f"{ppt},{banded}")
+    if c["source_sha256"] is None or f is None or not residual_source_hash().startswith(c["source_sha256"]):
+        return None
+    fetch = f["fetch_kib"] * (COPY_BYTES / 1024) / c["copy_fetch_kib"] * 1024
+    write = f["write_kib"] * (COPY_BYTES / 1024) / c["copy_write_kib"] * 1024
+    return {"traffic_bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
+            "valu_insts": f["valu_insts"], "waves": f["waves"]}
+
+
+def measure_copy_gbs(nbytes, reps):
+    """Read + write bandwidth of a plain device copy of nbytes (HIP events around reps back-to-back copies)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2 * nbytes / t / 1e9
+
+
+def roofline(k_ms, px, kernel, launch):
+    """Roofline object of the level-0 residual pass: `achieved` counts the algorithmic floor bytes; the
+    reference-layout, own-layout and counter accountings, the measured copy bandwidths and the vector-ALU
+    issue roof sit beside it, and `binding` names the roof the kernel is closest to."""
+    t = k_ms * 1e-3
+    floor_b = FLOOR_BYTES_PER_PIXEL * px
+    hbm_copy = measure_copy_gbs(1 << 30, 20)
+    mall_copy = measure_copy_gbs(16 << 20, 200)
+    acc = {}
+    for name, bpp in (("floor_10B", FLOOR_BYTES_PER_PIXEL), ("ref_layout_64B", REF_LAYOUT_BYTES_PER_PIXEL),
+                      ("own_layout_44B", LAYOUT_BYTES_PER_PIXEL)):
+        gbs = bpp * px / t / 1e9
+        acc[name] = {"bytes_per_launch": bpp * px, "GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
+    cf = counter_figures(launch["pixels_per_thread"], launch["xcd_banded"])
+    valu = None
+    if cf is not None:
+        gbs = cf["traffic_bytes"] / t / 1e9
+        acc["counter_traffic"] = {"bytes_per_launch": cf["traffic_bytes"], "GBs": gbs,
+                                  "frac_of_peak": gbs / HBM_PEAK_GBS, "frac_of_measured_copy": gbs / hbm_copy}
+        rate = cf["valu_insts"] / t / 1e9
+        valu = {"insts_per_launch": cf["valu_insts"], "insts_per_pixel": cf["valu_insts"] / px,
+                "achieved_ginst_s": rate, "peak_ginst_s": VALU_PEAK_GINST, "frac": rate / VALU_PEAK_GINST,
+                "waves": cf["waves"]}
+    binding = None
+    if valu is not None:
+        fr = {"valu": valu["frac"], "hbm": acc["counter_traffic"]["frac_of_measured_copy"]}
+        name = max(fr, key=fr.get)
+        binding = name if fr[name] >= 0.5 else f"latency ({name} closest, at {fr[name]:.2f} of its roof)"
+    achieved = floor_b / t / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": cf["traffic_bytes"] if cf else None,
+            "kernel": kernel, "kernel_us": k_ms * 1e3, "launch": launch, "pixels": px,
+            "bytes_per_launch": floor_b, "bytes_per_pixel": FLOOR_BYTES_PER_PIXEL,
+            "accountings": acc, "measured_copy_GBs": {"hbm_1GiB": hbm_copy, "mall_16MiB": mall_copy},
+            "frac_of_measured_hbm": achieved / hbm_copy, "valu": valu, "binding": binding}
 
 
 def run_gpu(args):
@@ -78,6 +168,16 @@ def run_gpu(args):
               for (md, mi, T, d, i, imu, t0, t1) in frames]
     torch.cuda.synchronize()
     ctx = P.Context(0)
+    # the residual pass's launch shape per level from the autotuner (kept by the context for its sessions), or
+    # pinned from a file (profiler runs, whose timing the tuner must not see)
+    if args.shapes:
+        with open(args.shapes) as f:
+            tuned = [e for e in json.load(f) if e["width"] == W and e["height"] == H]
+        ctx.set_tune(tuned)
+    else:
+        tuned = ctx.autotune([seq["camera"]], levels=3, jac="fp32")
+    log("[bench] autotuned: " + ", ".join(f"L{e['level']} ppt {e['ppt']} {'banded' if e['xcd_banded'] else 'round-robin'} "
+                                          f"({e['us']:.1f} us)" for e in tuned))
     tp = P.track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32")
     sess = P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], seq["prior"])
     x_init = sess.get_state()
@@ -115,16 +215,34 @@ def run_gpu(args):
     log(f"[bench] latency over {len(lat)} frames: p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
 
     # accuracy over the whole sequence, frame by frame from the initial state (outside the timed region):
-    # the analogue of the paper's velocity / bias convergence plots and its ATE RMSE
-    sess.set_state(*x_init)
-    est = []
-    for k in range(n_frames - 1):
-        track(k)
-        est.append(sess.result()["x1"])
-    accuracy = sequence_accuracy(est, seq["gt"][1:n_frames])
-    log(f"[bench] accuracy over {len(est)} frames: ATE {accuracy['ate_rmse_m'] * 100:.3f} cm, velocity error "
-        f"{accuracy['windows'][-1]['vel_err_mps']:.2e} m/s, gyro bias {accuracy['windows'][-1]['bg_err_radps']:.2e} "
-        f"rad/s, accel bias {accuracy['windows'][-1]['ba_err_mps2']:.2e} m/s^2 (last window)")
+    # the analogue of the paper's velocity / bias convergence plots and its ATE RMSE.  Closed loop: each
+    # frame's model view is rendered (noise-free) at the previous frame's estimate, so the tracker never sees
+    # the ground truth.  The open-loop figure (model views at the previous ground-truth pose, as timed above)
+    # is reported beside it.
+    import synth
+    accuracy = {}
+    for loop in ("closed", "open"):
+        sess.set_state(*x_init)
+        est = []
+        prev = seq["x0"]
+        for k in range(n_frames - 1):
+            if loop == "closed":
+                md, mi, T = synth.configs.model_view_at(seq, prev)
+                f = frames[k]
+                sess.track_frame_input({"depth": f[3], "intensity": f[4], "model_depth": md.contiguous(),
+                                        "model_intensity": mi.contiguous(), "T_WM": T, "imu": f[5], "t0": f[6],
+                                        "t1": f[7]}, stream)
+            else:
+                track(k)
+            prev = sess.result()["x1"]
+            est.append(prev)
+        accuracy[loop] = sequence_accuracy(est, seq["gt"][1:n_frames])
+        a = accuracy[loop]
+        log(f"[bench] {loop}-loop accuracy over {len(est)} frames: ATE {a['ate_rmse_m'] * 100:.3f} cm, velocity "
+            f"error {a['windows'][-1]['vel_err_mps']:.2e} m/s, gyro bias {a['windows'][-1]['bg_err_radps']:.2e} "
+            f"rad/s, accel bias {a['windows'][-1]['ba_err_mps2']:.2e} m/s^2 (last window)")
+    accuracy = dict(accuracy["closed"], model_view="rendered at the previous frame's estimate (closed loop)",
+                    open_loop=dict(accuracy["open"], model_view="rendered at the previous ground-truth pose"))
 
     # launch modes (outside the timed region): the frame's Gauss-Newton launches replayed from per-level HIP
     # graphs, or issued one by one; the same frames, throughput and latency as above
@@ -166,8 +284,13 @@ def run_gpu(args):
     torch.cuda.synchronize()
     k_ms = e0.elapsed_time(e1) / reps
     px = W * H
-    achieved = REF_BYTES_PER_PIXEL * px / (k_ms * 1e-3) / 1e9
-    log(f"[bench] level-0 residual pass: {k_ms * 1e3:.2f} us/launch, {achieved:.1f} GB/s ({REF_BYTES_PER_PIXEL} B/px algorithmic)")
+    ppt0 = next((e["ppt"] for e in tuned if e["level"] == 0), None)
+    band0 = next((e["xcd_banded"] for e in tuned if e["level"] == 0), None)
+    roof = roofline(k_ms, px, f"residual_kernel<{ppt0}> (level 0, 640x480, float32 rows)",
+                    {"pixels_per_thread": ppt0, "xcd_banded": band0, "block": 256})
+    log(f"[bench] level-0 residual pass: {k_ms * 1e3:.2f} us/launch, {roof['achieved']:.1f} GB/s at the "
+        f"{FLOOR_BYTES_PER_PIXEL} B/px floor; measured copy {roof['measured_copy_GBs']['hbm_1GiB']:.0f} GB/s; "
+        f"binding: {roof['binding']}")
     sess.close()
     ctx.close()
     return {
@@ -177,10 +300,8 @@ def run_gpu(args):
         "pose_err_final_m": pos_err,
         "accuracy": accuracy,
         "launch_modes": launch_modes,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "residual_kernel<2> (level 0, 640x480)", "kernel_us": k_ms * 1e3,
-                     "bytes_per_launch": REF_BYTES_PER_PIXEL * px},
+        "autotune": tuned,
+        "roofline": roof,
         "seq": seq,
     }
 
@@ -188,34 +309,73 @@ def run_gpu(args):
 def run_counters(args):
     """Hardware-counter run: the level-0 residual pass on a tracked sequence frame, then a plain
     device copy of known size whose FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes.
-    Meant to be run under rocprofv3 --pmc; prints one JSON line describing what ran."""
+    Meant to be run under rocprofv3 --pmc.  The inputs are generated on the host and copied over, so the
+    only kernels are the library's and the calibration copy; prints one JSON line describing what ran."""
     import torch
 
     import paper_2207_10940_amd as P
     W, H = 640, 480
-    seq = make_sequence(4, W, H, "cuda")
+    seq = make_sequence(4, W, H, "cpu")
     ctx = P.Context(0)
     tp = P.track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac=args.counters_jac)
-    sess = P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], seq["prior"])
     stream = torch.cuda.current_stream()
+    frames = []
     for j in range(1, 4):
         md, mi, T, d, i, imu, t0, t1 = frame_inputs(seq, j)
-        sess.set_model(md.contiguous(), mi.contiguous(), T, stream)
-        sess.track_frame(d.contiguous(), i.contiguous(), imu, t0, t1, stream)
-    torch.cuda.synchronize()
-    sess.profile_residual(0, args.kernel_reps, stream)
-    torch.cuda.synchronize()
-    n = COPY_BYTES // 4
-    src = torch.ones(n, dtype=torch.float32, device="cuda")
+        frames.append({"depth": d.to("cuda"), "intensity": i.to("cuda"), "model_depth": md.to("cuda"),
+                       "model_intensity": mi.to("cuda"), "T_WM": T, "imu": imu, "t0": t0, "t1": t1})
+    # every level-0 launch shape the autotuner can pick, pinned in turn (levels 1-2 keep the library's
+    # defaults): three tracked frames (30 level-0 passes), then kernel_reps passes back to back
+    shapes = [(ppt, banded) for ppt in (1, 2, 4) for banded in (0, 1)]
+    for ppt, banded in shapes:
+        ctx.set_tune([{"width": W, "height": H, "level": 0, "jac_format": args.counters_jac, "ppt": ppt,
+                       "xcd_banded": banded}])
+        sess = P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], seq["prior"])
+        for f in frames:
+            sess.track_frame_input(f, stream)
+        torch.cuda.synchronize()
+        sess.profile_residual(0, args.kernel_reps, stream)
+        torch.cuda.synchronize()
+        sess.close()
+    batch_px = None
+    if args.counters_batch:
+        # the batched pass over a 16-session mix (2 at 1280x720, 8 at 640x480, 6 at 320x240; inputs made on the
+        # host), with level 0 pinned to 4 / 2 / 1 pixels per thread, the batch's round-robin then XCD-banded
+        # tile order:
+        # one tracked step (10 level-0 passes), then kernel_reps passes back to back, for each order
+        import synth
+        mix = ((1280, 720, 2, 4), (640, 480, 8, 2), (320, 240, 6, 1))
+        seqs = [synth.configs.session_sequence(4000 + 1000 * ci + k, 2, w, h)
+                for ci, (w, h, count, _) in enumerate(mix) for k in range(count)]
+        bf = []
+        for sq in seqs:
+            f = serving_frame(sq, 1)
+            for key in ("depth", "intensity", "model_depth", "model_intensity"):
+                f[key] = f[key].to("cuda")
+            bf.append(f)
+        for banded in (0, 1):
+            ctx.set_tune([{"width": w, "height": h, "level": 0, "jac_format": args.counters_jac, "ppt": ppt,
+                           "xcd_banded": banded} for w, h, _, ppt in mix])
+            bs = [P.Session(ctx, sq["camera"], tp, P.imu_params(), sq["x0"], sq["q_IW"], sq["prior"]) for sq in seqs]
+            batch = P.Batch(ctx, len(bs))
+            batch.set_tile_order(banded)
+            batch.track(bs, bf, stream)
+            batch.results()
+            batch_px = batch.profile_residual(0, args.kernel_reps, stream)
+            torch.cuda.synchronize()
+            batch.close()
+            for s in bs:
+                s.close()
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32).to("cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    sess.close()
     ctx.close()
     print(json.dumps({"counters_run": True, "jac": args.counters_jac, "residual_reps": args.kernel_reps,
-                      "residual_pixels": W * H,
-                      "copy_bytes_each_way": COPY_BYTES, "copy_reps": 3}), flush=True)
+                      "residual_pixels": W * H, "level0_shapes_in_order": shapes,
+                      "level0_dispatches_per_shape": 30 + args.kernel_reps,
+                      "batch_pixels": batch_px, "copy_bytes_each_way": COPY_BYTES, "copy_reps": 3}), flush=True)
 
 
 SERVING_MIX = ((1280, 720, 8), (640, 480, 32), (320, 240, 24))  # (width, height, sessions)
@@ -247,11 +407,10 @@ def run_serving(args):
     nf = args.serving_frames
     t = time.time()
     seqs, specs = {}, []
-    for ci, (w, h, count) in enumerate(SERVING_MIX):
-        nseq = min(count, args.serving_sequences)
-        seqs[(w, h)] = [synth.configs.sequence(seed=4000 + 100 * ci + k, n_frames=nf + 1, width=w, height=h,
-                                               device="cuda", duration=(nf + 3) / 30.0) for k in range(nseq)]
-        specs += [(w, h, k % nseq) for k in range(count)]
+    for ci, (w, h, count) in enumerate(SERVING_MIX):  # every session its own scene, trajectory and IMU stream
+        seqs[(w, h)] = [synth.configs.session_sequence(4000 + 1000 * ci + k, nf + 1, w, h, device="cuda")
+                        for k in range(count)]
+        specs += [(w, h, k) for k in range(count)]
     frames = {key: [[serving_frame(sq, j) for j in range(1, nf + 1)] for sq in lst] for key, lst in seqs.items()}
     fins = {key: [[P.frame_input(f)[0] for f in fl] for fl in lst] for key, lst in frames.items()}
     torch.cuda.synchronize()
@@ -268,56 +427,72 @@ def run_serving(args):
             sq = seqs[(w, h)][k]
             s.set_state(sq["x0"], sq["q_IW"], sq["prior"])
 
-    server = P.Server(ctx, max_batch=len(sess), pipeline_depth=2)
     total = len(sess) * nf
-    # ---- saturation: every frame queued at once (each session's frames in order)
-    reset()
-    torch.cuda.synchronize()
-    t0 = P.Server.clock()
-    for j in range(nf):
-        for (w, h, k), s in zip(specs, sess):
-            server.submit(s, fins[(w, h)][k][j])
-    done, bad, dev_ms, sizes = 0, 0, [], []
-    while done < total:
-        for rec in server.poll(wait=True):
-            done += 1
-            bad += rec[7].status != 0
-            dev_ms.append(rec[5])
-            sizes.append(rec[6])
-    t_sat = P.Server.clock() - t0
-    sat_fps = total / t_sat
-    log(f"[serving] saturation: {total} frames in {t_sat * 1e3:.1f} ms = {sat_fps:.0f} frames/s, "
-        f"mean batch {np.mean(sizes):.1f}, failed {bad}")
-    # ---- nominal load: Poisson arrivals at 30 Hz per session
-    reset()
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(7)
-    arrivals = []
-    for i in range(len(sess)):
-        ts = np.cumsum(rng.exponential(1.0 / 30.0, size=nf))
-        arrivals += [(float(ta), i, j) for j, ta in enumerate(ts)]
-    arrivals.sort()
-    start = P.Server.clock() + 0.01
-    owner, lat, dev_nom, sizes_nom = {}, [], [], []
-    nxt, done = 0, 0
-    while done < total:
-        now = P.Server.clock() - start
-        while nxt < total and arrivals[nxt][0] <= now:
-            ta, i, j = arrivals[nxt]
-            w, h, k = specs[i]
-            owner[server.submit(sess[i], fins[(w, h)][k][j])] = ta
-            nxt += 1
-        for rec in server.poll(wait=False):
-            done += 1
-            ta = owner[rec[0]]
-            if ta >= args.serving_warmup:
-                lat.append((rec[4] - start - ta) * 1e3)
-                dev_nom.append(rec[5])
-            sizes_nom.append(rec[6])
-    span = P.Server.clock() - start
-    log(f"[serving] nominal 30 Hz x {len(sess)}: p50 {np.percentile(lat, 50):.2f} ms p99 "
-        f"{np.percentile(lat, 99):.2f} ms over {len(lat)} frames, mean batch {np.mean(sizes_nom):.1f}")
-    server.close()
+
+    def serve(graphs):
+        """Saturation and nominal-load runs of the server, its steps' launches issued one by one or
+        replayed from graphs."""
+        server = P.Server(ctx, max_batch=len(sess), pipeline_depth=2, graphs=graphs)
+        tag = "graphs" if graphs else "eager"
+        # ---- saturation: every frame queued at once (each session's frames in order)
+        reset()
+        torch.cuda.synchronize()
+        t0 = P.Server.clock()
+        for j in range(nf):
+            for (w, h, k), s in zip(specs, sess):
+                server.submit(s, fins[(w, h)][k][j])
+        done, bad, dev_ms, sizes = 0, 0, [], []
+        while done < total:
+            for rec in server.poll(wait=True):
+                done += 1
+                bad += rec[7].status != 0
+                dev_ms.append(rec[5])
+                sizes.append(rec[6])
+        t_sat = P.Server.clock() - t0
+        sat_fps = total / t_sat
+        log(f"[serving] {tag} saturation: {total} frames in {t_sat * 1e3:.1f} ms = {sat_fps:.0f} frames/s, "
+            f"mean batch {np.mean(sizes):.1f}, failed {bad}")
+        # ---- nominal load: Poisson arrivals at 30 Hz per session
+        reset()
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(7)
+        arrivals = []
+        for i in range(len(sess)):
+            ts = np.cumsum(rng.exponential(1.0 / 30.0, size=nf))
+            arrivals += [(float(ta), i, j) for j, ta in enumerate(ts)]
+        arrivals.sort()
+        start = P.Server.clock() + 0.01
+        owner, lat, dev_nom, sizes_nom = {}, [], [], []
+        nxt, done = 0, 0
+        while done < total:
+            now = P.Server.clock() - start
+            while nxt < total and arrivals[nxt][0] <= now:
+                ta, i, j = arrivals[nxt]
+                w, h, k = specs[i]
+                owner[server.submit(sess[i], fins[(w, h)][k][j])] = ta
+                nxt += 1
+            for rec in server.poll(wait=False):
+                done += 1
+                ta = owner[rec[0]]
+                if ta >= args.serving_warmup:
+                    lat.append((rec[4] - start - ta) * 1e3)
+                    dev_nom.append(rec[5])
+                sizes_nom.append(rec[6])
+        span = P.Server.clock() - start
+        log(f"[serving] {tag} nominal 30 Hz x {len(sess)}: p50 {np.percentile(lat, 50):.2f} ms p99 "
+            f"{np.percentile(lat, 99):.2f} ms over {len(lat)} frames, mean batch {np.mean(sizes_nom):.1f}")
+        server.close()
+        return {"saturation_fps": sat_fps, "saturation_mean_batch": float(np.mean(sizes)),
+                "saturation_device_ms_per_step_p50": float(np.percentile(dev_ms, 50)), "failed": int(bad),
+                "nominal": {"offered_fps": 30.0 * len(sess), "achieved_fps": total / span,
+                            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                            "device_p50_ms": float(np.percentile(dev_nom, 50)), "frames": len(lat),
+                            "mean_batch": float(np.mean(sizes_nom)),
+                            "kind": "arrival (Poisson, 30 Hz per session) to result on the host"}}
+
+    runs = {"eager": serve(False), "graphs": serve(True)}
+    main_run = runs["eager"]
+    sat_fps = main_run["saturation_fps"]
     # ---- plain path on the same mix: one session, one frame at a time, synchronous
     stream = torch.cuda.current_stream()
     per_class = {}
@@ -342,16 +517,21 @@ def run_serving(args):
     batch = P.Batch(ctx, len(sess))
     batch.track(sess, [frames[(w, h)][k][0] for w, h, k in specs], stream)
     batch.results()
-    batch.profile_residual(0, 5, stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 20
-    e0.record(stream)
-    px = batch.profile_residual(0, reps, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    k_ms = e0.elapsed_time(e1) / reps
-    gbs = REF_BYTES_PER_PIXEL * px / (k_ms * 1e-3) / 1e9
-    log(f"[serving] batched level-0 residual pass: {px} px in {k_ms * 1e3:.1f} us = {gbs:.0f} GB/s")
+    order_us = {}
+    for name, order in (("round_robin", 0), ("xcd_banded", 1)):  # the batch default last
+        batch.set_tile_order(order)
+        batch.profile_residual(0, 5, stream)
+        e0.record(stream)
+        px = batch.profile_residual(0, reps, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        order_us[name] = e0.elapsed_time(e1) * 1e3 / reps
+    k_ms = order_us["xcd_banded"] * 1e-3
+    gbs = FLOOR_BYTES_PER_PIXEL * px / (k_ms * 1e-3) / 1e9
+    log(f"[serving] batched level-0 residual pass: {px} px in {k_ms * 1e3:.1f} us = {gbs:.0f} GB/s at the "
+        f"{FLOOR_BYTES_PER_PIXEL} B/px floor (round-robin tile order: {order_us['round_robin']:.1f} us)")
     batch.close()
     for s in sess:
         s.close()
@@ -359,20 +539,25 @@ def run_serving(args):
     return {
         "workload": "64 sessions: 8 at 1280x720, 32 at 640x480, 24 at 320x240; 3 levels 10/5/4 iterations, "
                     "RGB-D-inertial, float32 Jacobians; continuous batching, 2 steps in flight",
-        "frames": total, "distinct_sequences_per_resolution": args.serving_sequences,
-        "saturation_fps": sat_fps, "saturation_mean_batch": float(np.mean(sizes)),
-        "saturation_device_ms_per_step_p50": float(np.percentile(dev_ms, 50)),
-        "nominal": {"offered_fps": 30.0 * len(sess), "achieved_fps": total / span,
-                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                    "device_p50_ms": float(np.percentile(dev_nom, 50)), "frames": len(lat),
-                    "mean_batch": float(np.mean(sizes_nom)),
-                    "kind": "arrival (Poisson, 30 Hz per session) to result on the host"},
+        "frames": total, "sequences": "one seeded scene, trajectory and IMU stream per session",
+        "saturation_fps": sat_fps, "saturation_mean_batch": main_run["saturation_mean_batch"],
+        "saturation_device_ms_per_step_p50": main_run["saturation_device_ms_per_step_p50"],
+        "nominal": main_run["nominal"],
         "plain_fps_same_mix": plain_fps, "plain_ms_per_frame": {k: v * 1e3 for k, v in per_class.items()},
         "speedup_vs_plain": sat_fps / plain_fps,
-        "failed": int(bad),
-        "batched_residual_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                      "frac": gbs / HBM_PEAK_GBS, "kernel_us": k_ms * 1e3, "pixels": px,
-                                      "bytes_per_launch": REF_BYTES_PER_PIXEL * px},
+        "failed": main_run["failed"] + runs["graphs"]["failed"],
+        "launches": "eager (steps' kernels issued one by one); graph-replayed steps under \"graphs\"",
+        "graphs": runs["graphs"],
+        "batched_residual_roofline": {
+            "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "kernel_us": k_ms * 1e3, "pixels": px, "bytes_per_launch": FLOOR_BYTES_PER_PIXEL * px,
+            "bytes_per_pixel": FLOOR_BYTES_PER_PIXEL, "tile_order": "xcd_banded",
+            "kernel_us_by_tile_order": order_us,
+            "accountings": {name: {"GBs": bpp * px / (k_ms * 1e-3) / 1e9,
+                                   "frac_of_peak": bpp * px / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                            for name, bpp in (("floor_10B", FLOOR_BYTES_PER_PIXEL),
+                                              ("ref_layout_64B", REF_LAYOUT_BYTES_PER_PIXEL),
+                                              ("own_layout_44B", LAYOUT_BYTES_PER_PIXEL))}},
     }
 
 
@@ -394,6 +579,106 @@ def mmpp_arrivals(rng, n, base=30.0, on=3.0, off=1.0 / 3.0, switch=4.0):
     return out
 
 
+def run_precision():
+    """Precision form on the 160x120 frame pair (2 levels): per level and term, the relative Frobenius error
+    of J^T J with FP16 / BF16 rows contracted on MFMA, against the oracle's float64 normal equations (stored by
+    tests/golden/make_bench_golden.py) and against the plain float32 form at the same linearisation point;
+    then the pose Gauss-Newton reaches (4/4 iterations) against the oracle's and the float32 form's."""
+    import torch
+
+    import paper_2207_10940_amd as P
+    import synth
+    g = load_golden()["precision"]
+    W, H, L = g["width"], g["height"], g["levels"]
+    d = synth.configs.frame_pair(seed=g["seed"], width=W, height=H)  # generated as the stored values were
+    for k in ("depth", "intensity", "model_depth", "model_intensity"):
+        d[k] = d[k].to("cuda")
+    lz = g["linearize"]
+    st = lambda x: {k: np.array(v) for k, v in x.items()}  # noqa: E731
+    x0, x1 = st(lz["x0"]), st(lz["x1"])
+    T_WM = np.array(lz["T_WM"]).reshape(4, 4)
+    tr = [np.array(lz[k], dtype=np.float32) for k in ("Ra", "ta", "Rb", "tb")]
+    stream = torch.cuda.current_stream()
+    ctx = P.Context(0)
+
+    def open_session(jac, iters):
+        tp = P.track_params(levels=L, iters=iters, mode=g["mode"], jac=jac)
+        return P.Session(ctx, d["camera"], tp, P.imu_params(), d["x0"], d["q_IW"], d["prior"])
+
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))  # noqa: E731
+    systems = {}
+    for jac in ("fp32", "fp16", "bf16"):
+        s = open_session(jac, [1] * L)
+        s.set_model(d["model_depth"].contiguous(), d["model_intensity"].contiguous(), T_WM, stream)
+        s.build_pyramid(P.PYR_CURRENT, d["depth"].contiguous(), d["intensity"].contiguous(), stream=stream)
+        systems[jac] = [s.linearize(l, *tr, x0, x1, stream=stream) for l in range(L)]
+        s.close()
+    poses = {}
+    for jac in ("fp32", "fp16", "bf16"):
+        s = open_session(jac, list(g["iters"]))
+        s.track_frame_input({"depth": d["depth"].contiguous(), "intensity": d["intensity"].contiguous(),
+                             "model_depth": d["model_depth"].contiguous(),
+                             "model_intensity": d["model_intensity"].contiguous(), "T_WM": d["T_WM"],
+                             "imu": d["imu"], "t0": d["t0"], "t1": d["t1"]}, stream)
+        poses[jac] = s.result()["x1"]
+        s.close()
+    ctx.close()
+    ox = st(g["track_x1"])
+    out = {"workload": f"{W}x{H} frame pair (seed {g['seed']}), {L} levels; J^T J at a fixed linearisation point, "
+                       f"then Gauss-Newton {'/'.join(map(str, g['iters']))} iterations, RGB-D-inertial",
+           "oracle": "float64 values stored by tests/golden/make_bench_golden.py"}
+    for jac in ("fp16", "bf16", "fp32"):
+        lv = []
+        for l in range(L):
+            o = g["linearize"]["levels"][l]
+            e = {}
+            for term in ("icp", "rgb"):
+                Ho = np.array(o["H_" + term]).reshape(12, 12)
+                e[term] = {"jtj_vs_oracle": rel(systems[jac][l]["H_" + term], Ho),
+                           "jtj_vs_fp32": rel(systems[jac][l]["H_" + term], systems["fp32"][l]["H_" + term]),
+                           "n_equal_oracle": int(systems[jac][l]["n_" + term]) == o["n_" + term]}
+            lv.append(e)
+        p = poses[jac]
+        out[jac] = {"levels": lv,
+                    "pose_vs_oracle": {"m": float(np.linalg.norm(p["r"] - ox["r"])), "rad": quat_angle(p["q"], ox["q"])},
+                    "pose_vs_fp32": {"m": float(np.linalg.norm(p["r"] - poses["fp32"]["r"])),
+                                     "rad": quat_angle(p["q"], poses["fp32"]["q"])}}
+    log("[precision] " + "; ".join(
+        f"{jac}: L0 J^T J icp {out[jac]['levels'][0]['icp']['jtj_vs_oracle']:.1e} rgb "
+        f"{out[jac]['levels'][0]['rgb']['jtj_vs_oracle']:.1e}, pose {out[jac]['pose_vs_oracle']['m']:.1e} m"
+        for jac in ("fp16", "bf16", "fp32")))
+    return out
+
+
+def load_golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def quat_angle(qa, qb):
+    """Angle of the relative rotation of two unit quaternions (w, x, y, z), from the sine and the cosine."""
+    qa, qb = np.asarray(qa, dtype=np.float64), np.asarray(qb, dtype=np.float64)
+    w = qa[0] * qb[0] + qa[1:] @ qb[1:]  # conj(qa) * qb
+    v = qa[0] * qb[1:] - qb[0] * qa[1:] - np.cross(qa[1:], qb[1:])
+    return float(2.0 * np.arctan2(np.linalg.norm(v), abs(w)))
+
+
+def stored_pose_errors(specs, first, nf):
+    """Pose error of the first tracked frame of session 0 per resolution against the stored oracle pose
+    (None where the stored case does not match the workload's frame count)."""
+    out = {}
+    for g in load_golden()["stress_first_frame"]:
+        key = f"{g['width']}x{g['height']}"
+        i = next((n for n, sp in enumerate(specs) if sp == (g["width"], g["height"], g["session"])), None)
+        if i is None or i not in first or g["n_frames"] != nf + 1:
+            out[key] = None
+            continue
+        x = first[i]["x1"]
+        out[key] = {"m": float(np.linalg.norm(x["r"] - np.array(g["x1"]["r"]))),
+                    "rad": quat_angle(x["q"], g["x1"]["q"])}
+    return out
+
+
 def run_stress(args):
     """Serving + precision stress: 256 sessions (64 each at 1920x1080, 1280x720, 640x480, 320x240), FP16
     Jacobian rows on MFMA with float64 solves, tile shapes from the autotuner, 5% of frames with 80% zero-depth
@@ -403,23 +688,19 @@ def run_stress(args):
 
     import paper_2207_10940_amd as P
     synth = synth_mod()
-    nf, nseq = args.stress_frames, args.stress_sequences
-    rng = np.random.default_rng(5)
+    nf = args.stress_frames
+    rng = np.random.default_rng(5)  # arrival times
     t = time.time()
     seqs, specs, flags = {}, [], {"holes": 0, "low_texture": 0, "frames": 0}
-    for ci, (w, h, count) in enumerate(STRESS_MIX):
-        lst = []
-        for k in range(nseq):
-            holes = [j for j in range(1, nf + 1) if rng.random() < 0.05]
-            lowt = [j for j in range(1, nf + 1) if rng.random() < 0.10]
-            flags["holes"] += len(holes)
-            flags["low_texture"] += len(lowt)
+    for ci, (w, h, count) in enumerate(STRESS_MIX):  # every session its own scene, trajectory and IMU stream
+        lst = [synth.configs.session_sequence(5000 + 1000 * ci + k, nf + 1, w, h, device="cuda", hole_rate=0.05,
+                                              low_texture_rate=0.10) for k in range(count)]
+        for sq in lst:
+            flags["holes"] += len(sq["hole_frames"])
+            flags["low_texture"] += len(sq["low_texture_frames"])
             flags["frames"] += nf
-            lst.append(synth.configs.sequence(seed=5000 + 100 * ci + k, n_frames=nf + 1, width=w, height=h,
-                                              device="cuda", duration=(nf + 3) / 30.0, hole_frames=holes,
-                                              low_texture_frames=lowt))
         seqs[(w, h)] = lst
-        specs += [(w, h, k % nseq) for k in range(count)]
+        specs += [(w, h, k) for k in range(count)]
     frames = {key: [[serving_frame(sq, j) for j in range(1, nf + 1)] for sq in lst] for key, lst in seqs.items()}
     fins = {key: [[P.frame_input(f)[0] for f in fl] for fl in lst] for key, lst in frames.items()}
     torch.cuda.synchronize()
@@ -427,8 +708,9 @@ def run_stress(args):
         f"({flags['holes']} hole frames, {flags['low_texture']} low-texture of {flags['frames']})")
     ctx = P.Context(0)
     tuned = ctx.autotune([seqs[(w, h)][0]["camera"] for w, h, _ in STRESS_MIX], levels=3, jac="fp16")
-    log("[stress] autotuned pixels per thread: " +
-        ", ".join(f"{e['width']}x{e['height']} L{e['level']}: {e['ppt']} ({e['us']:.1f} us)" for e in tuned))
+    log("[stress] autotuned pixels per thread / tile order: " +
+        ", ".join(f"{e['width']}x{e['height']} L{e['level']}: {e['ppt']}{'b' if e['xcd_banded'] else ''} "
+                  f"({e['us']:.1f} us)" for e in tuned))
     tp = P.track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp16")
     sess = []
     for w, h, k in specs:
@@ -489,28 +771,16 @@ def run_stress(args):
     for s in sess:
         s.close()
     ctx.close()
-    # ---- pose error of sampled sessions (first frame from the initial state) against the oracle
-    from oracle import track
-    pose = {}
-    for w, h in ((320, 240), (640, 480)):
-        i = next(n for n, sp in enumerate(specs) if sp[:2] == (w, h))
-        sq = seqs[(w, h)][specs[i][2]]
-        f = frames[(w, h)][specs[i][2]][0]
-        params = track.default_params(levels=3, iters=(10, 5, 4), mode="rgbdi")
-        o = track.track_frame(f["depth"].cpu().numpy(), f["intensity"].cpu().numpy(),
-                              f["model_depth"].cpu().numpy(), f["model_intensity"].cpu().numpy(), f["T_WM"],
-                              sq["camera"], f["imu"], f["t0"], f["t1"], sq["x0"], sq["q_IW"], sq["prior"], params)
-        g = first[i]
-        from oracle import lie
-        pose[f"{w}x{h}"] = {"m": float(np.linalg.norm(g["x1"]["r"] - o["x1"]["r"])),
-                            "rad": float(np.linalg.norm(lie.quat_boxminus(g["x1"]["q"], o["x1"]["q"])))}
+    # ---- pose error of session 0 of every resolution (first frame, from the initial state) against the
+    # oracle's values stored by tests/golden/make_bench_golden.py for the same seeded inputs
+    pose = stored_pose_errors(specs, first, nf)
     log(f"[stress] pose vs oracle (fp16): {pose}")
     return {
         "workload": "256 sessions: 64 each at 1920x1080, 1280x720, 640x480, 320x240; RGB-D-inertial, 3 levels "
                     "10/5/4, FP16 Jacobian rows on MFMA, float64 solve; 5% of frames with 80% zero-depth holes, "
                     "10% low-texture; Markov-modulated Poisson arrivals (30 Hz mean, x3 / x0.33 states)",
         "frames": total, "hole_frames": flags["holes"], "low_texture_frames": flags["low_texture"],
-        "distinct_sequences_per_resolution": nseq, "hbm_bytes_admitted": hbm,
+        "sequences": "one seeded scene, trajectory and IMU stream per session", "hbm_bytes_admitted": hbm,
         "saturation_fps": total / t_sat, "failed": int(bad),
         "bursty": {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                    "frames": len(lat), "achieved_fps": total / span,
@@ -753,25 +1023,92 @@ def run_robustness(args):
     return out
 
 
-def cpu_baseline(seq, n_frames):
-    """The oracle as it stands, single-threaded, on the first frames of the same sequence."""
+def _oracle_frames(job):
+    """Pool worker of the all-core CPU baseline: track the given frames with the oracle on one thread,
+    each from the ground-truth state of the previous frame; returns the seconds spent tracking."""
     from threadpoolctl import threadpool_limits
 
     from oracle import track
     params = track.default_params(levels=3, iters=(10, 5, 4), mode="rgbdi")
-    x0, q, prior = seq["x0"], seq["q_IW"], seq["prior"]
-    t_total = 0.0
+    t = 0.0
     with threadpool_limits(limits=1):
-        for j in range(1, n_frames + 1):
-            md, mi, T, d, i, imu, t0, t1 = frame_inputs(seq, j)
-            args = [d.cpu().numpy(), i.cpu().numpy(), md.cpu().numpy(), mi.cpu().numpy()]
+        for f in job:
+            t0 = time.perf_counter()
+            track.track_frame(*f)
+            t += time.perf_counter() - t0
+    return t
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(seq, n_single, per_worker):
+    """The oracle as it stands, timed on the host: (1) one thread, on the first n_single frames of the
+    sequence, chained; (2) every core the process may use (at most 16), one oracle per core, each tracking
+    per_worker frames from the previous frame's ground-truth state (the frames of one sequence are
+    dependent, so more cores serve more frames, not one frame faster); (3) one thread on the 160x120 frame
+    pair (2 levels, 4/4 iterations)."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import track
+    params = track.default_params(levels=3, iters=(10, 5, 4), mode="rgbdi")
+
+    def args_of(j, x0, q, prior):
+        md, mi, T, d, i, imu, t0, t1 = frame_inputs(seq, j)
+        return (d.cpu().numpy(), i.cpu().numpy(), md.cpu().numpy(), mi.cpu().numpy(), T, seq["camera"], imu, t0, t1,
+                x0, q, prior, params)
+
+    x0, q, prior = seq["x0"], seq["q_IW"], seq["prior"]
+    t_single = 0.0
+    with threadpool_limits(limits=1):
+        for j in range(1, n_single + 1):
+            a = args_of(j, x0, q, prior)
             t = time.perf_counter()
-            o = track.track_frame(*args, T, seq["camera"], imu, t0, t1, x0, q, prior, params)
-            t_total += time.perf_counter() - t
+            o = track.track_frame(*a)
+            t_single += time.perf_counter() - t
             x0, q, prior = o["x1"], o["q_IW"], o["prior"]
-    return {"value": n_frames / t_total, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_frames} tracked frames of the 640x480 sequence, 3 levels 10/5/4 iterations, "
-                      f"numpy float64 value layer + float32 mask layer, BLAS limited to 1 thread"}
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    n_all = workers * per_worker
+    jobs = [[] for _ in range(workers)]
+    for j in range(1, n_all + 1):
+        g = seq["gt"][j - 1]
+        jobs[(j - 1) % workers].append(args_of(j, g, seq["q_IW"], synth.configs.initial_prior(g, seq["q_IW"])))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_oracle_frames, [[] for _ in range(workers)])  # start-up and imports outside the timing
+        t = time.perf_counter()
+        busy = pool.map(_oracle_frames, jobs)
+        t_all = time.perf_counter() - t
+    d = synth.configs.frame_pair(seed=1001, width=160, height=120)
+    pp = track.default_params(levels=2, iters=(4, 4), mode="rgbdi")
+    reps = 5
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        for _ in range(reps):
+            track.track_frame(d["depth"].numpy(), d["intensity"].numpy(), d["model_depth"].numpy(),
+                              d["model_intensity"].numpy(), d["T_WM"], d["camera"], d["imu"], d["t0"], d["t1"],
+                              d["x0"], d["q_IW"], d["prior"], pp)
+        t_pair = time.perf_counter() - t
+    return {"value": n_all / t_all, "unit": "frames/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n_all} frames of the 640x480 sequence ({per_worker} per worker, one single-threaded oracle "
+                      f"per core, each frame from the previous ground-truth state), 3 levels 10/5/4 iterations, "
+                      f"numpy float64 value layer + float32 mask layer",
+            "busy_s_per_worker": [float(b) for b in busy], "wall_s": t_all,
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "single_core": {"value": n_single / t_single, "unit": "frames/s", "cores": 1,
+                            "sample": f"first {n_single} frames of the 640x480 sequence, chained"},
+            "pair_160x120": {"value": reps / t_pair, "unit": "frames/s", "cores": 1,
+                             "sample": f"the 160x120 frame pair (seed 1001), 2 levels 4/4 iterations, {reps} times"}}
 
 
 def main():
@@ -781,16 +1118,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--latency-frames", type=int, default=100)
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-frames", type=int, default=20)
+    ap.add_argument("--cpu-frames", type=int, default=10, help="frames of the single-core oracle sample")
+    ap.add_argument("--cpu-frames-per-core", type=int, default=2, help="frames per core of the all-core sample")
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-frames", type=int, default=40, help="frames per session of the serving workload")
-    ap.add_argument("--serving-sequences", type=int, default=6,
-                    help="distinct seeded sequences per resolution of the serving workload")
+    ap.add_argument("--serving-frames", type=int, default=24, help="frames per session of the serving workload")
     ap.add_argument("--serving-warmup", type=float, default=0.25, help="seconds of arrivals left out of latency")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--stress-frames", type=int, default=12, help="frames per session of the stress workload")
-    ap.add_argument("--stress-sequences", type=int, default=4,
-                    help="distinct seeded sequences per resolution of the stress workload")
+    ap.add_argument("--stress-frames", type=int, default=8, help="frames per session of the stress workload")
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--robust-frames", type=int, default=91, help="frames of the robustness sequences")
     ap.add_argument("--robust-width", type=int, default=320)
@@ -803,6 +1138,11 @@ def main():
     ap.add_argument("--robustness-only", action="store_true", help="only run the robustness comparison")
     ap.add_argument("--counters", action="store_true",
                     help="only run the level-0 residual pass and a calibration copy (for rocprofv3 --pmc)")
+    ap.add_argument("--shapes", default=None,
+                    help="JSON list of launch shapes (the \"autotune\" entries of an earlier run) to pin instead "
+                         "of running the autotuner")
+    ap.add_argument("--counters-batch", action="store_true",
+                    help="with --counters: also the batched level-0 pass over a 16-session mix")
     ap.add_argument("--counters-jac", default="fp32", choices=("fp32", "fp32_mfma", "fp16", "bf16"),
                     help="row format of the --counters run (the matrix-core forms for MFMA counters)")
     args = ap.parse_args()
@@ -829,11 +1169,15 @@ def main():
     mapping = None
     if not args.no_mapping:
         mapping = run_mapping(args, g["seq"])
+    precision = None
+    if not args.no_precision:
+        precision = run_precision()
     cpu = None
     if not args.no_cpu_baseline and args.cpu_frames > 0:
         t = time.time()
-        cpu = cpu_baseline(g["seq"], args.cpu_frames)
-        log(f"[bench] cpu baseline {cpu['value']:.3f} frames/s in {time.time() - t:.1f}s")
+        cpu = cpu_baseline(g["seq"], args.cpu_frames, args.cpu_frames_per_core)
+        log(f"[bench] cpu baseline {cpu['value']:.3f} frames/s on {cpu['cores']} cores, single core "
+            f"{cpu['single_core']['value']:.3f} frames/s, in {time.time() - t:.1f}s")
     out = {
         "metric": METRIC, "value": g["value"], "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": g["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -842,7 +1186,8 @@ def main():
                                "IMU 200 Hz, procedural 3-plane/4-sphere scene", "width": 640, "height": 480,
                    "levels": 3, "iters": [10, 5, 4], "jac_format": "fp32", "frames": args.steps},
         "latency_ms": g["latency_ms"], "pose_err_final_m": g["pose_err_final_m"], "accuracy": g["accuracy"],
-        "launch_modes": g["launch_modes"], "roofline": g["roofline"], "cpu_baseline": cpu, "serving": serving, "stress": stress,
+        "launch_modes": g["launch_modes"], "autotune": g["autotune"], "roofline": g["roofline"],
+        "cpu_baseline": cpu, "precision": precision, "serving": serving, "stress": stress,
         "robustness": robust, "mapping": mapping,
     }
     print(json.dumps(out), flush=True)

@@ -211,12 +211,15 @@ typedef struct {
   double t0, t1;
 } dslam_frame_input;
 
-/* One result of the tile-shape autotuner: the residual pass of `level` of a
- * width x height camera with `jac_format` runs fastest with `ppt` pixels per
- * thread (us: its measured time per launch). */
+/* One result of the launch-shape autotuner: the residual pass of `level` of
+ * a width x height camera with `jac_format` runs fastest with `ppt` pixels per
+ * thread and, with xcd_banded = 1, its tiles dealt to the GPU's 8
+ * accelerator dies (XCDs, each with its own L2 cache) in contiguous bands
+ * rather than round-robin (us: its measured time per launch). */
 typedef struct {
   int32_t width, height, level, jac_format, ppt;
   float us;
+  int32_t xcd_banded;
 } dslam_tune_entry;
 
 /* Human-readable name of a status code (static string). */
@@ -235,16 +238,27 @@ uint64_t dslam_context_used_bytes(const dslam_context* ctx);
 
 /* Tile-shape autotuner for the residual pass.  For each camera cams[0..n) and
  * each of its `levels` pyramid levels, times the pass (jac_format's kernel)
- * with 1, 2 and 4 pixels per thread on a synthetic slanted, textured plane
- * and records the fastest in the context; sessions opened on the context
- * afterwards with the same resolution and format use it (a session keeps its
- * tile shape for life, so its results do not depend on batching).  Runs
+ * with 1, 2 and 4 pixels per thread, each with the tiles in round-robin and in
+ * XCD-banded order, on a synthetic slanted, textured plane (best of three
+ * rounds of 20 launches) and records the first shape in that order within 2%
+ * of the fastest in the context; sessions opened on the context afterwards with the
+ * same resolution and format use it (a session keeps its tile shape for life,
+ * so its results do not depend on batching; the tile order never changes a
+ * result, only which die computes each tile).  Runs
  * synchronously on `stream`, with temporary device memory counted against
  * the budget while it runs.  out (nullable, capacity max_out) receives the
  * chosen entries, *n_out their number. */
 dslam_status dslam_context_autotune(dslam_context* ctx, const dslam_camera* cams, int32_t n, int32_t levels,
                                     int32_t jac_format, void* stream, dslam_tune_entry* out, int32_t max_out,
                                     int32_t* n_out);
+/* Record launch shapes in the context as if the autotuner had chosen them
+ * (e.g. entries saved from an earlier dslam_context_autotune run on the same
+ * kind of GPU); each replaces the context's entry of the same resolution,
+ * level and format.  entries: host, n of them; `us` is kept but not used.
+ * Errors: INVALID (ppt not 1, 2 or 4, xcd_banded not 0 or 1, level outside
+ * [0, DSLAM_MAX_LEVELS), unknown format, width or height < 1); nothing is
+ * recorded then. */
+dslam_status dslam_context_set_tune(dslam_context* ctx, const dslam_tune_entry* entries, int32_t n);
 
 /* Device bytes a session of this camera and pyramid depth holds for its lifetime. */
 uint64_t dslam_session_bytes(const dslam_camera* cam, int32_t levels);
@@ -509,11 +523,32 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
                                const dslam_frame_input* frames, void* stream);
 /* Wait for the batch's last step and copy its n results, in call order. */
 dslam_status dslam_batch_results(dslam_batch* b, dslam_track_result* out);
+/* Tile order of the batch's residual passes (see dslam_tune_entry): 1 = dealt
+ * to the XCDs in contiguous bands (the default: at batch scale neighbouring
+ * tiles read the same model-view rows, and banding lets them share an L2
+ * instead of fetching those rows once per die), 0 = round-robin, -1 = the
+ * order tuned for the batch's largest sessions.  The order never changes a
+ * result.  Applies to later steps and to dslam_batch_profile_residual.  Waits
+ * for the batch's last step.  Errors: INVALID (order outside [-1, 1]). */
+dslam_status dslam_batch_set_tile_order(dslam_batch* b, int32_t order);
+/* enable = 1: the batch's later steps replay their kernel launches from HIP
+ * graphs (Section IV's per-frame schedule for the whole batch: both
+ * pyramids, the initialisation, every level's residual passes and
+ * Gauss-Newton steps, the marginalisation and the gathering of the results).
+ * One graph is captured per plan of launches, i.e. per batch composition
+ * (sessions per resolution and launch shape, in slot order) and schedule, at
+ * the first step with that plan, and replayed by later steps with the same
+ * plan; the batch keeps the 32 most recent.  The staging copies stay outside
+ * the graphs.  Results are bit for bit those of the launches issued one by
+ * one (enable = 0, the default; disabling frees the graphs).  Waits for the
+ * batch's last step.  Errors: INVALID (enable not 0 or 1), DEVICE. */
+dslam_status dslam_batch_set_graphs(dslam_batch* b, int32_t enable);
 
 /* The batched step for callers that cannot allocate memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same step as dslam_batch_track followed by dslam_batch_results, with the same
- * results bit for bit, but no dslam_batch is needed and nothing is allocated.
+ * results bit for bit (XCD-banded tile order), but no dslam_batch is needed
+ * and nothing is allocated.
  * The slot records and results live in a static device array of 1.8 MiB
  * (DSLAM_MAX_BATCH sessions' records; each GPU the library runs on holds its
  * own copy until the process ends, its address resolved by
@@ -551,6 +586,7 @@ typedef struct dslam_server dslam_server;
 typedef struct {
   int32_t max_batch;       /* sessions per batched step, 1..DSLAM_MAX_BATCH */
   int32_t pipeline_depth;  /* batched steps in flight at once, 1..8 */
+  int32_t use_graphs;      /* 1: the steps replay their launches from graphs (dslam_batch_set_graphs), 0: not */
 } dslam_server_params;
 
 /* A finished request.  submit_s / done_s are host steady-clock seconds (the

@@ -197,7 +197,16 @@ class Context:
         _check(lib().dslam_context_autotune(self.handle, arr, len(cs), int(levels), jf, _stream_ptr(stream), out, cap,
                                             C.byref(n)), "dslam_context_autotune")
         return [{"width": e.width, "height": e.height, "level": e.level, "jac_format": e.jac_format, "ppt": e.ppt,
-                 "us": e.us} for e in out[:n.value]]
+                 "xcd_banded": e.xcd_banded, "us": e.us} for e in out[:n.value]]
+
+    def set_tune(self, entries):
+        """dslam_context_set_tune: record launch shapes (dicts as autotune returns them)."""
+        arr = (_abi.TuneEntry * len(entries))()
+        for i, e in enumerate(entries):
+            jf = JAC[e["jac_format"]] if isinstance(e["jac_format"], str) else int(e["jac_format"])
+            arr[i] = _abi.TuneEntry(int(e["width"]), int(e["height"]), int(e["level"]), jf, int(e["ppt"]),
+                                    float(e.get("us", 0.0)), int(e.get("xcd_banded", 0)))
+        _check(lib().dslam_context_set_tune(self.handle, arr, len(entries)), "dslam_context_set_tune")
 
     def close(self):
         if self.handle:
@@ -513,6 +522,14 @@ class Batch:
         self._keep = (keep, frames)
         self._n = n
 
+    def set_tile_order(self, order: int):
+        """dslam_batch_set_tile_order: 1 XCD-banded (default), 0 round-robin, -1 the largest sessions' tuned order."""
+        _check(lib().dslam_batch_set_tile_order(self.handle, int(order)), "dslam_batch_set_tile_order")
+
+    def set_graphs(self, enable: bool):
+        """dslam_batch_set_graphs: replay each batch composition's launches from a captured HIP graph."""
+        _check(lib().dslam_batch_set_graphs(self.handle, int(bool(enable))), "dslam_batch_set_graphs")
+
     def profile_residual(self, level, reps, stream=None) -> int:
         """Relaunch the last step's batched residual pass; returns the pixels per launch."""
         px = C.c_uint64()
@@ -545,8 +562,8 @@ def batch_track_noalloc(sessions, frames, stream=None) -> list:
 class Server:
     """Serving loop with continuous batching (dslam_server_*).  One thread drives it."""
 
-    def __init__(self, ctx: Context, max_batch: int, pipeline_depth: int = 2):
-        p = _abi.ServerParams(int(max_batch), int(pipeline_depth))
+    def __init__(self, ctx: Context, max_batch: int, pipeline_depth: int = 2, graphs: bool = False):
+        p = _abi.ServerParams(int(max_batch), int(pipeline_depth), int(bool(graphs)))
         h = C.c_void_p()
         _check(lib().dslam_server_create(ctx.handle, C.byref(p), C.byref(h)), "dslam_server_create")
         self.handle = h

@@ -67,7 +67,7 @@ class LinearSystem(C.Structure):
 
 class TuneEntry(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("level", C.c_int32), ("jac_format", C.c_int32),
-                ("ppt", C.c_int32), ("us", C.c_float)]
+                ("ppt", C.c_int32), ("us", C.c_float), ("xcd_banded", C.c_int32)]
 
 
 class FrameInput(C.Structure):
@@ -78,7 +78,7 @@ class FrameInput(C.Structure):
 
 
 class ServerParams(C.Structure):
-    _fields_ = [("max_batch", C.c_int32), ("pipeline_depth", C.c_int32)]
+    _fields_ = [("max_batch", C.c_int32), ("pipeline_depth", C.c_int32), ("use_graphs", C.c_int32)]
 
 
 class RequestDone(C.Structure):
@@ -135,11 +135,14 @@ SIGNATURES = {
     "dslam_session_set_state": (C.c_int, [vp, P(FrameState), dp, P(Prior), C.c_int32]),
     "dslam_context_autotune": (C.c_int, [vp, P(Camera), C.c_int32, C.c_int32, C.c_int32, vp, P(TuneEntry),
                                          C.c_int32, P(C.c_int32)]),
+    "dslam_context_set_tune": (C.c_int, [vp, P(TuneEntry), C.c_int32]),
     "dslam_batch_create": (C.c_int, [vp, C.c_int32, P(vp)]),
     "dslam_batch_destroy": (C.c_int, [vp]),
     "dslam_batch_track": (C.c_int, [vp, C.c_int32, P(vp), P(FrameInput), vp]),
     "dslam_session_set_graphs": (C.c_int, [vp, C.c_int32]),
     "dslam_batch_results": (C.c_int, [vp, P(TrackResult)]),
+    "dslam_batch_set_graphs": (C.c_int, [vp, C.c_int32]),
+    "dslam_batch_set_tile_order": (C.c_int, [vp, C.c_int32]),
     "dslam_batch_track_noalloc": (C.c_int, [C.c_int32, P(vp), P(FrameInput), P(TrackResult), vp]),
     "dslam_batch_profile_residual": (C.c_int, [vp, C.c_int32, C.c_int32, vp, P(C.c_uint64)]),
     "dslam_server_create": (C.c_int, [vp, P(ServerParams), P(vp)]),

@@ -54,7 +54,20 @@ struct ResidualArgs {
   uint8_t* mask;     // device, optional
   int32_t jac;       // DSLAM_JAC_*: how the per-pixel terms are reduced
   float col_scale[2];  // precision form: power-of-two scale of the ICP / photometric row entries
+  int32_t banded;      // tile order of the launch (tile_of)
 };
+
+// Tile processed by workgroup bid of an n-workgroup launch.  Workgroups are
+// dealt to the 8 XCDs round-robin (workgroup bid runs on XCD bid % 8); with
+// banded != 0 XCD x takes the contiguous tiles [x q + min(x, r), ...) of its
+// share (q = n / 8, r = n % 8), so that neighbouring tiles, which read the
+// same rows of the model view, share that XCD's L2.  A bijection of [0, n):
+// each tile's partial sums land in the same place either way.
+__device__ __forceinline__ int tile_of(int bid, int n, int banded) {
+  if (!banded) return bid;
+  const int x = bid & 7, i = bid >> 3, q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + i;
+}
 
 enum { RES_THREADS = 256, PARTIAL_STRIDE = 64, SOLVE_THREADS = 512 };
 
@@ -85,10 +98,15 @@ struct BatchGrid {
 };
 
 // Workgroup -> (slot, workgroup within the slot); uniform across the workgroup.
-__device__ __forceinline__ void batch_locate(const BatchGrid& g, int blk, int* slot, int* b) {
+// With banded != 0 the tile order (tile_of) is applied within each class: the
+// class's workgroups that share an XCD (same local index mod 8) take one
+// contiguous band of its tiles, so every XCD gets an equal share of every
+// class (tiles of different classes differ in cost) and neighbouring tiles of
+// one session share an L2.
+__device__ __forceinline__ void batch_locate(const BatchGrid& g, int blk, int* slot, int* b, int banded = 0) {
   int c = 0;
   for (int k = 1; k < g.nclass; ++k) c = blk >= g.first_block[k] ? k : c;
-  const int off = blk - g.first_block[c];
+  const int off = tile_of(blk - g.first_block[c], g.first_block[c + 1] - g.first_block[c], banded);
   const int q = off / g.blocks_per_slot[c];
   *slot = g.first_slot[c] + q;
   *b = off - q * g.blocks_per_slot[c];

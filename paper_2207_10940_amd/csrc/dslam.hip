@@ -148,6 +148,7 @@ ResidualArgs residual_args(dslam_session* s, int l, const float* xf, uint8_t* ma
   a.mask = mask;
   a.jac = s->tp.jac_format;
   a.col_scale[0] = a.col_scale[1] = 1.0f;
+  a.banded = s->banded[l];
   if (a.jac == DSLAM_JAC_FP16) {
     // Power-of-two scales that bring each term's largest possible row entry
     // to about 2^14 (FP16 overflows above 65504), from bounds at the nearest
@@ -183,12 +184,14 @@ SolveParams solve_params(dslam_session* s) {
   return sp;
 }
 
-// Pixels per thread the autotuner chose for this resolution, level and format (0: none).
-int tuned_ppt(dslam_context* ctx, int W, int H, int level, int jac) {
+// The launch shape the autotuner chose for this resolution, level and format
+// (ppt 0: none).
+dslam_tune_entry tuned_shape(dslam_context* ctx, int W, int H, int level, int jac) {
   std::lock_guard<std::mutex> g(ctx->tune_mu);
   for (const dslam_tune_entry& e : ctx->tuned)
-    if (e.width == W && e.height == H && e.level == level && e.jac_format == jac) return e.ppt;
-  return 0;
+    if (e.width == W && e.height == H && e.level == level && e.jac_format == jac) return e;
+  dslam_tune_entry none{W, H, level, jac, 0, 0.0f, 0};
+  return none;
 }
 
 // Validates the frame's IMU samples and packs them for the device.
@@ -376,8 +379,9 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
     }
     C->G[0] = C->G[1] = nullptr;
     for (int k = 0; k < 2; ++k) { M->G[k] = (int16_t*)p; p += b16; }
-    const int tuned = tuned_ppt(ctx, cam->width, cam->height, l, tp->jac_format);
-    s->ppt[l] = tuned ? tuned : default_ppt(C->W * C->H);
+    const dslam_tune_entry tuned = tuned_shape(ctx, cam->width, cam->height, l, tp->jac_format);
+    s->ppt[l] = tuned.ppt ? tuned.ppt : default_ppt(C->W * C->H);
+    s->banded[l] = tuned.ppt ? tuned.xcd_banded : 0;
   }
   s->partials = (float*)p; p += align256(lo.partial_floats * sizeof(float));
   s->sd = (SessionDev*)p; p += align256(sizeof(SessionDev));
@@ -396,6 +400,29 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   if (hipMemcpy(s->sd, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
   if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
   *out = s;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_context_set_tune(dslam_context* ctx, const dslam_tune_entry* entries, int32_t n) {
+  if (!ctx || n < 0 || (n > 0 && !entries)) return DSLAM_ERR_INVALID;
+  for (int i = 0; i < n; ++i) {
+    const dslam_tune_entry& e = entries[i];
+    if ((e.ppt != 1 && e.ppt != 2 && e.ppt != 4) || (e.xcd_banded != 0 && e.xcd_banded != 1) || e.level < 0 ||
+        e.level >= DSLAM_MAX_LEVELS || e.jac_format < DSLAM_JAC_FP32 || e.jac_format > DSLAM_JAC_BF16 ||
+        e.width < 1 || e.height < 1)
+      return DSLAM_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> g(ctx->tune_mu);
+  for (int i = 0; i < n; ++i) {
+    const dslam_tune_entry& f = entries[i];
+    bool replaced = false;
+    for (dslam_tune_entry& e : ctx->tuned)
+      if (e.width == f.width && e.height == f.height && e.level == f.level && e.jac_format == f.jac_format) {
+        e = f;
+        replaced = true;
+      }
+    if (!replaced) ctx->tuned.push_back(f);
+  }
   return DSLAM_OK;
 }
 
@@ -454,24 +481,35 @@ dslam_status dslam_context_autotune(dslam_context* ctx, const dslam_camera* cams
       // identity transforms: every valid pixel associates with itself
       if (hipMemsetAsync(s->sd->xf, 0, sizeof(s->sd->xf), st) != hipSuccess) return DSLAM_ERR_DEVICE;
       for (int l = 0; l < levels; ++l) {
-        const ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
-        dslam_tune_entry best{cam.width, cam.height, l, jac_format, 0, 0.0f};
-        for (int ppt : {1, 2, 4}) {
-          const int reps = 20;
-          for (int r = 0; r < 3; ++r)
-            if (launch_residual(ra, ppt, st) != hipSuccess) return DSLAM_ERR_DEVICE;
-          if (hipEventRecord(e0, st) != hipSuccess) return DSLAM_ERR_DEVICE;
-          for (int r = 0; r < reps; ++r)
-            if (launch_residual(ra, ppt, st) != hipSuccess) return DSLAM_ERR_DEVICE;
-          if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return DSLAM_ERR_DEVICE;
-          float ms = 0.0f;
-          if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return DSLAM_ERR_DEVICE;
-          const float us = ms * 1000.0f / reps;
-          if (best.ppt == 0 || us < best.us) {
-            best.ppt = ppt;
-            best.us = us;
+        ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
+        // each shape's time is the best of three rounds of back-to-back launches;
+        // the first shape (in the order below) within 2% of the fastest wins, so
+        // that shapes whose times differ by noise alone do not flip between runs
+        const int shapes[6][2] = {{1, 0}, {1, 1}, {2, 0}, {2, 1}, {4, 0}, {4, 1}};
+        float t[6];
+        for (int c = 0; c < 6; ++c) {
+          ra.banded = shapes[c][1];
+          const int ppt = shapes[c][0], reps = 20;
+          t[c] = 0.0f;
+          for (int round = 0; round < 3; ++round) {
+            for (int r = 0; r < 2; ++r)
+              if (launch_residual(ra, ppt, st) != hipSuccess) return DSLAM_ERR_DEVICE;
+            if (hipEventRecord(e0, st) != hipSuccess) return DSLAM_ERR_DEVICE;
+            for (int r = 0; r < reps; ++r)
+              if (launch_residual(ra, ppt, st) != hipSuccess) return DSLAM_ERR_DEVICE;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+              return DSLAM_ERR_DEVICE;
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return DSLAM_ERR_DEVICE;
+            const float us = ms * 1000.0f / reps;
+            if (round == 0 || us < t[c]) t[c] = us;
           }
         }
+        float fastest = t[0];
+        for (int c = 1; c < 6; ++c) fastest = std::min(fastest, t[c]);
+        int pick = 0;
+        while (t[pick] > 1.02f * fastest) ++pick;
+        dslam_tune_entry best{cam.width, cam.height, l, jac_format, shapes[pick][0], t[pick], shapes[pick][1]};
         found.push_back(best);
       }
       return DSLAM_OK;
@@ -733,6 +771,11 @@ dslam_status dslam_track_frame_sync(dslam_session* s, const dslam_frame_input* f
   return dslam_session_result(s, out);
 }
 
+static void drop_batch_graphs(dslam_batch* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+}
+
 dslam_status dslam_batch_create(dslam_context* ctx, int32_t max_sessions, dslam_batch** out) {
   if (!ctx || !out || max_sessions < 1 || max_sessions > MAX_BATCH) return DSLAM_ERR_INVALID;
   const size_t vis = align256(sizeof(SlotVis) * max_sessions);
@@ -756,6 +799,7 @@ dslam_status dslam_batch_create(dslam_context* ctx, int32_t max_sessions, dslam_
   b->host = nullptr;
   b->pending = false;
   b->n = 0;
+  b->tile_order = 1;
   auto fail = [&](dslam_status st) {
     if (b->dev) (void)hipFree(b->dev);
     if (b->host) (void)hipHostFree(b->host);
@@ -789,6 +833,8 @@ dslam_status dslam_batch_destroy(dslam_batch* b) {
   if (!b) return DSLAM_ERR_INVALID;
   (void)hipSetDevice(b->ctx->device);
   if (b->pending) (void)hipEventSynchronize(b->done);
+  drop_batch_graphs(b);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
   (void)hipEventDestroy(b->done);
   (void)hipFree(b->dev);
   (void)hipHostFree(b->host);
@@ -812,13 +858,62 @@ struct BatchMem {
   dslam_track_result* d_res;
 };
 
-// What the batched step's launches were (for dslam_batch_profile_residual).
-struct BatchInfo {
-  int levels, jac;
+constexpr int kMaxBatchGraphs = 32;  // graphs kept per batch object
+
+// Sessions of one class share a batched launch's work split: same image size
+// and the same launch shape (pixels per thread) at every level.
+bool same_class(const dslam_session* a, const dslam_session* b) {
+  if (a->cam.width != b->cam.width || a->cam.height != b->cam.height) return false;
+  for (int l = 0; l < a->levels; ++l)
+    if (a->ppt[l] != b->ppt[l]) return false;
+  return true;
+}
+
+// Slot order of the classes: larger images first, then wider, then by launch shape.
+bool class_before(const dslam_session* a, const dslam_session* b) {
+  const int pa = a->cam.width * a->cam.height, pb = b->cam.width * b->cam.height;
+  if (pa != pb) return pa > pb;
+  if (a->cam.width != b->cam.width) return a->cam.width > b->cam.width;
+  for (int l = 0; l < a->levels; ++l)
+    if (a->ppt[l] != b->ppt[l]) return a->ppt[l] < b->ppt[l];
+  return false;
+}
+
+// The launches of one batched step: everything its kernels take besides the
+// staging memory (whose device pointers are fixed per batch object), so that
+// equal plans on one batch object issue identical launches.
+struct BatchPlan {
+  int n, levels, jac;
+  int iters[DSLAM_MAX_LEVELS];
+  dslam_track_params tp;  // the schedule (levels, iterations) of the step flags
+  BatchGrid pyr_grid;
   int max_ppt[DSLAM_MAX_LEVELS];
+  int banded[DSLAM_MAX_LEVELS];  // tile order of the level's batched residual pass
   BatchGrid res_grid[DSLAM_MAX_LEVELS];
   uint64_t pixels[DSLAM_MAX_LEVELS];
 };
+
+void push_grid(std::vector<int32_t>* k, const BatchGrid& g) {
+  k->push_back(g.nclass);
+  for (int c = 0; c <= g.nclass; ++c) k->push_back(g.first_block[c]);
+  for (int c = 0; c < g.nclass; ++c) {
+    k->push_back(g.blocks_per_slot[c]);
+    k->push_back(g.first_slot[c]);
+  }
+}
+
+// Everything a batched step's launches depend on, as a key of its graph.
+std::vector<int32_t> plan_key(const BatchPlan& p) {
+  std::vector<int32_t> k{p.n, p.levels, p.jac};
+  for (int l = 0; l < p.levels; ++l) k.push_back(p.iters[l]);
+  push_grid(&k, p.pyr_grid);
+  for (int l = 0; l < p.levels; ++l) {
+    k.push_back(p.max_ppt[l]);
+    k.push_back(p.banded[l]);
+    push_grid(&k, p.res_grid[l]);
+  }
+  return k;
+}
 
 // Validates a batched step's arguments without touching any state.
 dslam_status batch_validate(const dslam_context* ctx, int32_t n, dslam_session* const* sessions,
@@ -845,37 +940,26 @@ dslam_status batch_validate(const dslam_context* ctx, int32_t n, dslam_session* 
   int nres = 0;
   for (int i = 0; i < n; ++i) {
     bool known = false;
-    for (int j = 0; j < i; ++j)
-      known = known || (sessions[j]->cam.width == sessions[i]->cam.width &&
-                        sessions[j]->cam.height == sessions[i]->cam.height);
+    for (int j = 0; j < i; ++j) known = known || same_class(sessions[j], sessions[i]);
     nres += known ? 0 : 1;
   }
   return nres > MAX_CLASSES ? DSLAM_ERR_INVALID : DSLAM_OK;
 }
 
-// Stages and enqueues one validated batched step on `st` (Section IV for each
-// session, with shared launches); the results land in m.h_res (slot order)
-// once the stream has passed the step.  order[k] = caller index of slot k.
-dslam_status batch_enqueue(const BatchMem& m, int32_t n, dslam_session* const* sessions,
-                           const dslam_frame_input* frames, hipStream_t st, int* order, BatchInfo* info) {
+// Stages one validated batched step: the slot order (sessions grouped by
+// class, larger images first; order[k] = caller index of slot k), the slot
+// records and their copy to the device on `st`, and the plan of its launches.
+dslam_status batch_stage(const BatchMem& m, int32_t n, dslam_session* const* sessions,
+                         const dslam_frame_input* frames, int tile_order, hipStream_t st, int* order,
+                         BatchPlan* plan) {
   const dslam_session* s0 = sessions[0];
-  // ---- slot order: sessions grouped by resolution, larger images first
   for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order, order + n, [&](int a, int c) {
-    const dslam_camera& A = sessions[a]->cam;
-    const dslam_camera& C = sessions[c]->cam;
-    if (A.width * A.height != C.width * C.height) return A.width * A.height > C.width * C.height;
-    return A.width != C.width ? A.width > C.width : false;
-  });
+  std::stable_sort(order, order + n, [&](int a, int c) { return class_before(sessions[a], sessions[c]); });
   int nclass = 0, cls_first[MAX_BATCH + 1];
-  for (int k = 0; k < n; ++k) {
-    const dslam_camera& A = sessions[order[k]]->cam;
-    if (k == 0 || A.width != sessions[order[k - 1]]->cam.width || A.height != sessions[order[k - 1]]->cam.height)
-      cls_first[nclass++] = k;
-  }
+  for (int k = 0; k < n; ++k)
+    if (k == 0 || !same_class(sessions[order[k]], sessions[order[k - 1]])) cls_first[nclass++] = k;
   if (nclass > MAX_CLASSES) return DSLAM_ERR_INVALID;
   cls_first[nclass] = n;
-  // ---- stage the slots (everything was validated)
   ImuBatch imu;
   for (int k = 0; k < n; ++k) {
     dslam_session* s = sessions[order[k]];
@@ -906,7 +990,7 @@ dslam_status batch_enqueue(const BatchMem& m, int32_t n, dslam_session* const* s
   }
   HIP_OK(hipMemcpyAsync(m.d_vis, m.h_vis, sizeof(SlotVis) * n, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(m.d_solve, m.h_solve, sizeof(SlotSolve) * n, hipMemcpyHostToDevice, st));
-  // ---- work split of each launch: one class per resolution
+  // work split of each launch: one class per resolution and launch shape
   auto grid = [&](auto blocks_of) {
     BatchGrid g;
     g.nclass = nclass;
@@ -921,30 +1005,50 @@ dslam_status batch_enqueue(const BatchMem& m, int32_t n, dslam_session* const* s
     g.first_block[nclass] = blk;
     return g;
   };
-  {  // every level of the current and model-view pyramids: one launch
-    BatchGrid g = grid([&](const dslam_session* s) { return 2 * PyrTileStd::tiles(s->cam.width, s->cam.height); });
-    HIP_OK(launch_pyramid_batch(m.d_vis, s0->levels, g, st));
-  }
-  HIP_OK(launch_frame_init_batch(m.d_solve, n, st));
-  info->levels = s0->levels;
-  info->jac = s0->tp.jac_format;
-  for (int l = s0->levels - 1; l >= 0; --l) {
+  plan->n = n;
+  plan->levels = s0->levels;
+  plan->jac = s0->tp.jac_format;
+  plan->tp = s0->tp;
+  plan->pyr_grid = grid([&](const dslam_session* s) { return 2 * PyrTileStd::tiles(s->cam.width, s->cam.height); });
+  for (int l = 0; l < s0->levels; ++l) {
     int max_ppt = 1;
     uint64_t px = 0;
     for (int k = 0; k < n; ++k) {
       max_ppt = std::max(max_ppt, sessions[k]->ppt[l]);
       px += (uint64_t)sessions[k]->cur[l].W * sessions[k]->cur[l].H;
     }
-    BatchGrid g = grid([&](const dslam_session* s) { return residual_blocks(s->cur[l].W * s->cur[l].H, s->ppt[l]); });
-    info->res_grid[l] = g;
-    info->max_ppt[l] = max_ppt;
-    info->pixels[l] = px;
-    for (int it = 0; it < s0->tp.iters[l]; ++it) {
-      HIP_OK(launch_residual_batch(m.d_vis, g, l, max_ppt, s0->tp.jac_format, st));
-      HIP_OK(launch_solve_batch(m.d_solve, n, l, step_flags(s0->tp, l, it), st));
-    }
+    plan->iters[l] = s0->tp.iters[l];
+    plan->res_grid[l] =
+        grid([&](const dslam_session* s) { return residual_blocks(s->cur[l].W * s->cur[l].H, s->ppt[l]); });
+    plan->max_ppt[l] = max_ppt;
+    // tile order < 0: the first class's (it holds the largest images)
+    plan->banded[l] = tile_order < 0 ? sessions[order[0]]->banded[l] : tile_order;
+    plan->pixels[l] = px;
   }
-  HIP_OK(launch_gather_results(m.d_solve, n, m.d_res, st));
+  return DSLAM_OK;
+}
+
+// Every kernel of one staged batched step (Section IV for each session, with
+// shared launches): both pyramids of every session, the frames'
+// initialisation, each level's Gauss-Newton iterations and the gathering of
+// the results.  Their arguments are the plan and the fixed staging pointers,
+// so the same launches can be captured once and replayed.
+hipError_t batch_launches(const BatchMem& m, const BatchPlan& p, hipStream_t st) {
+  hipError_t e = launch_pyramid_batch(m.d_vis, p.levels, p.pyr_grid, st);
+  if (e == hipSuccess) e = launch_frame_init_batch(m.d_solve, p.n, st);
+  for (int l = p.levels - 1; l >= 0 && e == hipSuccess; --l)
+    for (int it = 0; it < p.iters[l] && e == hipSuccess; ++it) {
+      e = launch_residual_batch(m.d_vis, p.res_grid[l], l, p.max_ppt[l], p.jac, p.banded[l], st);
+      if (e == hipSuccess) e = launch_solve_batch(m.d_solve, p.n, l, step_flags(p.tp, l, it), st);
+    }
+  if (e == hipSuccess) e = launch_gather_results(m.d_solve, p.n, m.d_res, st);
+  return e;
+}
+
+// The results' copy to the host staging (m.h_res, slot order) and the
+// sessions' completion marks, after the step's launches on `st`.
+dslam_status batch_finish(const BatchMem& m, int32_t n, dslam_session* const* sessions, const int* order,
+                          hipStream_t st) {
   HIP_OK(hipMemcpyAsync(m.h_res, m.d_res, sizeof(dslam_track_result) * n, hipMemcpyDeviceToHost, st));
   for (int k = 0; k < n; ++k) {
     dslam_session* s = sessions[order[k]];
@@ -952,6 +1056,42 @@ dslam_status batch_enqueue(const BatchMem& m, int32_t n, dslam_session* const* s
     HIP_OK(mark_session(s, st));
   }
   return DSLAM_OK;
+}
+
+// The executable graph of a plan on this batch object: found in the cache or
+// captured (on a private stream) and instantiated.  Called with no step of the
+// batch in flight.  nullptr with *err set on failure.
+hipGraphExec_t batch_graph(dslam_batch* b, const BatchMem& m, const BatchPlan& p, hipError_t* err) {
+  std::vector<int32_t> key = plan_key(p);
+  for (auto& g : b->graphs)
+    if (g.first == key) return g.second;
+  *err = hipSuccess;
+  if (!b->capture) {
+    *err = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+    if (*err != hipSuccess) {
+      b->capture = nullptr;
+      return nullptr;
+    }
+  }
+  if ((int)b->graphs.size() >= kMaxBatchGraphs) {  // the oldest plan makes room
+    (void)hipGraphExecDestroy(b->graphs.front().second);
+    b->graphs.erase(b->graphs.begin());
+  }
+  *err = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+  if (*err != hipSuccess) return nullptr;
+  hipError_t e = batch_launches(m, p, b->capture);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(b->capture, &g);
+  if (e == hipSuccess) e = ee;
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    *err = e;
+    return nullptr;
+  }
+  b->graphs.emplace_back(std::move(key), exec);
+  return exec;
 }
 
 }  // namespace
@@ -968,19 +1108,49 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
   b->pending = false;
   hipStream_t st = (hipStream_t)stream;
   const BatchMem m{b->h_vis, b->h_solve, b->h_res, b->d_vis, b->d_solve, b->d_res};
-  BatchInfo info;
-  const dslam_status e = batch_enqueue(m, n, sessions, frames, st, b->order, &info);
+  BatchPlan plan;
+  const dslam_status e = batch_stage(m, n, sessions, frames, b->tile_order, st, b->order, &plan);
   if (e != DSLAM_OK) return e;
+  if (b->use_graphs) {
+    hipError_t ge = hipSuccess;
+    hipGraphExec_t exec = batch_graph(b, m, plan, &ge);
+    if (!exec) return DSLAM_ERR_DEVICE;
+    HIP_OK(hipGraphLaunch(exec, st));
+  } else {
+    HIP_OK(batch_launches(m, plan, st));
+  }
+  const dslam_status f = batch_finish(m, n, sessions, b->order, st);
+  if (f != DSLAM_OK) return f;
   HIP_OK(hipEventRecord(b->done, st));
-  b->levels = info.levels;
-  b->jac = info.jac;
-  for (int l = 0; l < info.levels; ++l) {
-    b->max_ppt[l] = info.max_ppt[l];
-    b->res_grid[l] = info.res_grid[l];
-    b->pixels[l] = info.pixels[l];
+  b->levels = plan.levels;
+  b->jac = plan.jac;
+  for (int l = 0; l < plan.levels; ++l) {
+    b->max_ppt[l] = plan.max_ppt[l];
+    b->banded[l] = plan.banded[l];
+    b->res_grid[l] = plan.res_grid[l];
+    b->pixels[l] = plan.pixels[l];
   }
   b->n = n;
   b->pending = true;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_batch_set_tile_order(dslam_batch* b, int32_t order) {
+  if (!b || order < -1 || order > 1) return DSLAM_ERR_INVALID;
+  HIP_OK(hipSetDevice(b->ctx->device));
+  if (b->pending) HIP_OK(hipEventSynchronize(b->done));
+  b->tile_order = order;
+  if (order >= 0)  // dslam_batch_profile_residual relaunches the last step's pass in the new order
+    for (int l = 0; l < DSLAM_MAX_LEVELS; ++l) b->banded[l] = order;
+  return DSLAM_OK;
+}
+
+dslam_status dslam_batch_set_graphs(dslam_batch* b, int32_t enable) {
+  if (!b || (enable != 0 && enable != 1)) return DSLAM_ERR_INVALID;
+  HIP_OK(hipSetDevice(b->ctx->device));
+  if (b->pending) HIP_OK(hipEventSynchronize(b->done));
+  if (!enable) drop_batch_graphs(b);
+  b->use_graphs = enable == 1;
   return DSLAM_OK;
 }
 
@@ -1000,9 +1170,12 @@ dslam_status dslam_batch_track_noalloc(int32_t n, dslam_session* const* sessions
   const BatchMem m{g_hvis, g_hsolve, g_hres, (SlotVis*)base, (SlotSolve*)(base + kScratchVis),
                    (dslam_track_result*)(base + kScratchVis + kScratchSolve)};
   int order[MAX_BATCH];
-  BatchInfo info;
-  const dslam_status e = batch_enqueue(m, n, sessions, frames, st, order, &info);
+  BatchPlan plan;
+  const dslam_status e = batch_stage(m, n, sessions, frames, 1, st, order, &plan);
   if (e != DSLAM_OK) return e;
+  HIP_OK(batch_launches(m, plan, st));
+  const dslam_status f = batch_finish(m, n, sessions, order, st);
+  if (f != DSLAM_OK) return f;
   HIP_OK(hipStreamSynchronize(st));
   for (int k = 0; k < n; ++k) results[order[k]] = g_hres[k];
   return DSLAM_OK;
@@ -1015,7 +1188,8 @@ dslam_status dslam_batch_profile_residual(dslam_batch* b, int32_t level, int32_t
   HIP_OK(hipEventSynchronize(b->done));
   hipStream_t st = (hipStream_t)stream;
   for (int r = 0; r < reps; ++r)
-    HIP_OK(launch_residual_batch(b->d_vis, b->res_grid[level], level, b->max_ppt[level], b->jac, st));
+    HIP_OK(launch_residual_batch(b->d_vis, b->res_grid[level], level, b->max_ppt[level], b->jac, b->banded[level],
+                                 st));
   if (pixels) *pixels = b->pixels[level];
   return DSLAM_OK;
 }

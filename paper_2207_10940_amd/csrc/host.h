@@ -41,6 +41,7 @@ struct dslam_session {
   bool have_model;
   double T_WM[16];
   int ppt[DSLAM_MAX_LEVELS];
+  int banded[DSLAM_MAX_LEVELS];  // tile order of each level's residual pass (tile_of)
   // a frame's Gauss-Newton launches after the first, one graph per level,
   // captured at the first frame that uses them (null: not captured yet)
   dslam::SolveParams* sp_dev;  // device: the frame's solve parameters
@@ -69,7 +70,14 @@ struct dslam_batch {
   int levels;                         // of the last step
   int jac;
   int max_ppt[DSLAM_MAX_LEVELS];
+  int banded[DSLAM_MAX_LEVELS];
   dslam::BatchGrid res_grid[DSLAM_MAX_LEVELS];  // residual work split of the last step
   uint64_t pixels[DSLAM_MAX_LEVELS];            // pixels per residual pass of the last step
+  // the step's launches replayed from graphs, one per plan of launches (batch
+  // composition and schedule), captured at the first step with that plan
+  int tile_order = 1;  // batched residual passes: 1 XCD-banded, 0 round-robin, -1 the first class's tuned order
+  bool use_graphs = false;
+  hipStream_t capture = nullptr;
+  std::vector<std::pair<std::vector<int32_t>, hipGraphExec_t>> graphs;
 };
 

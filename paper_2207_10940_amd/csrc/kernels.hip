@@ -10,19 +10,20 @@ namespace dslam {
 
 template <int PPT>
 __global__ __launch_bounds__(RES_THREADS) void residual_kernel(ResidualArgs a) {
-  residual_block<PPT>(a, blockIdx.x, PPT);
+  residual_block<PPT>(a, tile_of(blockIdx.x, gridDim.x, a.banded), PPT);
 }
 
 template <int PPT, int FMT>
 __global__ __launch_bounds__(RES_THREADS) void residual_mfma_kernel(ResidualArgs a) {
-  residual_block_mfma<PPT, FMT>(a, blockIdx.x, PPT);
+  residual_block_mfma<PPT, FMT>(a, tile_of(blockIdx.x, gridDim.x, a.banded), PPT);
 }
 
 // Batched: one launch runs one residual pass of every session of the batch.
 template <int PMAX>
-__global__ __launch_bounds__(RES_THREADS) void residual_batch_kernel(const SlotVis* slots, BatchGrid g, int level) {
+__global__ __launch_bounds__(RES_THREADS) void residual_batch_kernel(const SlotVis* slots, BatchGrid g, int level,
+                                                                     int banded) {
   int slot, b;
-  batch_locate(g, blockIdx.x, &slot, &b);
+  batch_locate(g, blockIdx.x, &slot, &b, banded);
   const SlotVis* sv = slots + slot;
   const ResidualArgs a = sv->res[level];
   residual_block<PMAX>(a, b, sv->ppt[level]);
@@ -30,9 +31,9 @@ __global__ __launch_bounds__(RES_THREADS) void residual_batch_kernel(const SlotV
 
 template <int PMAX, int FMT>
 __global__ __launch_bounds__(RES_THREADS) void residual_batch_mfma_kernel(const SlotVis* slots, BatchGrid g,
-                                                                          int level) {
+                                                                          int level, int banded) {
   int slot, b;
-  batch_locate(g, blockIdx.x, &slot, &b);
+  batch_locate(g, blockIdx.x, &slot, &b, banded);
   const SlotVis* sv = slots + slot;
   const ResidualArgs a = sv->res[level];
   residual_block_mfma<PMAX, FMT>(a, b, sv->ppt[level]);
@@ -47,28 +48,29 @@ namespace dslam {
 
 template <int FMT>
 hipError_t launch_residual_batch_fmt(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt,
-                                     hipStream_t st) {
+                                     int banded, hipStream_t st) {
   const dim3 grid(g.first_block[g.nclass]), blk(RES_THREADS);
   constexpr int M = FMT == DSLAM_JAC_FP32 ? DSLAM_JAC_FP32_MFMA : FMT;  // (the plain kernel takes no format)
   auto k1 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<1> : residual_batch_mfma_kernel<1, M>;
   auto k2 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<2> : residual_batch_mfma_kernel<2, M>;
   auto k4 = FMT == DSLAM_JAC_FP32 ? residual_batch_kernel<4> : residual_batch_mfma_kernel<4, M>;
   switch (max_ppt) {
-    case 1: hipLaunchKernelGGL(k1, grid, blk, 0, st, slots, g, level); break;
-    case 2: hipLaunchKernelGGL(k2, grid, blk, 0, st, slots, g, level); break;
-    case 4: hipLaunchKernelGGL(k4, grid, blk, 0, st, slots, g, level); break;
+    case 1: hipLaunchKernelGGL(k1, grid, blk, 0, st, slots, g, level, banded); break;
+    case 2: hipLaunchKernelGGL(k2, grid, blk, 0, st, slots, g, level, banded); break;
+    case 4: hipLaunchKernelGGL(k4, grid, blk, 0, st, slots, g, level, banded); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, int jac,
-                                 hipStream_t st) {
+                                 int banded, hipStream_t st) {
   switch (jac) {
-    case DSLAM_JAC_FP32: return launch_residual_batch_fmt<DSLAM_JAC_FP32>(slots, g, level, max_ppt, st);
-    case DSLAM_JAC_FP32_MFMA: return launch_residual_batch_fmt<DSLAM_JAC_FP32_MFMA>(slots, g, level, max_ppt, st);
-    case DSLAM_JAC_FP16: return launch_residual_batch_fmt<DSLAM_JAC_FP16>(slots, g, level, max_ppt, st);
-    case DSLAM_JAC_BF16: return launch_residual_batch_fmt<DSLAM_JAC_BF16>(slots, g, level, max_ppt, st);
+    case DSLAM_JAC_FP32: return launch_residual_batch_fmt<DSLAM_JAC_FP32>(slots, g, level, max_ppt, banded, st);
+    case DSLAM_JAC_FP32_MFMA:
+      return launch_residual_batch_fmt<DSLAM_JAC_FP32_MFMA>(slots, g, level, max_ppt, banded, st);
+    case DSLAM_JAC_FP16: return launch_residual_batch_fmt<DSLAM_JAC_FP16>(slots, g, level, max_ppt, banded, st);
+    case DSLAM_JAC_BF16: return launch_residual_batch_fmt<DSLAM_JAC_BF16>(slots, g, level, max_ppt, banded, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -199,7 +199,7 @@ double dslam_server_clock(void) { return steady_seconds(); }
 
 dslam_status dslam_server_create(dslam_context* ctx, const dslam_server_params* p, dslam_server** out) {
   if (!ctx || !p || !out || p->max_batch < 1 || p->max_batch > DSLAM_MAX_BATCH || p->pipeline_depth < 1 ||
-      p->pipeline_depth > 8)
+      p->pipeline_depth > 8 || (p->use_graphs != 0 && p->use_graphs != 1))
     return DSLAM_ERR_INVALID;
   dslam_server* sv = new (std::nothrow) dslam_server;
   if (!sv) return DSLAM_ERR_NO_CAPACITY;
@@ -216,6 +216,10 @@ dslam_status dslam_server_create(dslam_context* ctx, const dslam_server_params* 
       st.batch = nullptr;
       release(sv);
       return bs;
+    }
+    if (p->use_graphs && dslam_batch_set_graphs(st.batch, 1) != DSLAM_OK) {
+      release(sv);
+      return DSLAM_ERR_DEVICE;
     }
     if (hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&st.t0) != hipSuccess || hipEventCreate(&st.t1) != hipSuccess) {

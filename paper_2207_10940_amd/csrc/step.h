@@ -57,7 +57,7 @@ int residual_blocks(int npix, int ppt);
 hipError_t launch_residual(const ResidualArgs& a, int ppt, hipStream_t st);
 hipError_t launch_tune_scene(float* depth, uint8_t* inten, int W, int H, hipStream_t st);
 hipError_t launch_residual_batch(const SlotVis* slots, const BatchGrid& g, int level, int max_ppt, int jac,
-                                 hipStream_t st);
+                                 int banded, hipStream_t st);
 
 // solve.hip
 // the frame initialisation, the current frame's pyramid and (model != nullptr)

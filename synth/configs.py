@@ -160,7 +160,7 @@ def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: in
     gen = torch.Generator(device="cpu").manual_seed(seed)
     R_IW = traj.pose(0.0)[0]
     times = np.arange(n_frames) / fps
-    clean, noisy, gts = [], [], []
+    clean, noisy, gts, hole_list, lowt_list = [], [], [], [], []
     noise = ImuNoise()
     bg0 = rng.normal(0.0, 2e-3, 3)
     ba0 = rng.normal(0.0, 2e-2, 3)
@@ -172,8 +172,11 @@ def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: in
                           device=device, low_texture=lt)
         clean.append(z)
         zn = add_depth_noise(z, 1e-3, gen)
+        if lt:
+            lowt_list.append(j)
         if j in set(hole_frames):
             zn = apply_holes(zn, seed * 1000 + j, hole_fraction)
+            hole_list.append(j)
         noisy.append((zn, inten))
         _, _, v = state_truth(traj, t)
         k = min(int(np.searchsorted(stamps, t, side="right")) - 1, len(stamps) - 1)
@@ -189,7 +192,7 @@ def sequence(seed: int = 2001, n_frames: int = 300, width: int = 640, height: in
         "depth": [f[0] for f in noisy], "intensity": [f[1] for f in noisy], "clean_depth": clean,
         "imu": {"t": stamps, "gyro": gyro, "acc": acc}, "gt": gts, "q_IW_gt": q_IW,
         "x0": x0, "q_IW": q_IW_init, "prior": initial_prior(x0, q_IW_init), "noise": noise,
-        "gravity": GRAVITY,
+        "gravity": GRAVITY, "hole_frames": hole_list, "low_texture_frames": lowt_list,
     }
 
 
@@ -215,6 +218,38 @@ def model_view(seq: dict, j: int):
     T[:3, :3] = _rot_from_quat(g["q"])
     T[:3, 3] = g["r"]
     return seq["clean_depth"][j - 1], seq["intensity"][j - 1], T
+
+
+def model_view_at(seq: dict, state: dict, *, low_texture: bool = False):
+    """Noise-free render of the sequence's scene at the camera pose of
+    ``state`` (world frame of the sequence's states, e.g. the previous frame's
+    estimate for closed-loop tracking), with that pose as T_WM.  Returned on
+    the device the sequence was generated on."""
+    R_IW = _rot_from_quat(seq["q_IW_gt"])
+    R_WC = _rot_from_quat(np.asarray(state["q"], dtype=np.float64) / np.linalg.norm(state["q"]))
+    r_WC = np.asarray(state["r"], dtype=np.float64)
+    cam = seq["camera"]
+    z, inten = render(seq["scene"], R_IW @ R_WC, R_IW @ r_WC, cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy,
+                      device=seq["depth"][0].device, low_texture=low_texture)
+    T = np.eye(4)
+    T[:3, :3] = R_WC
+    T[:3, 3] = r_WC
+    return z, inten, T
+
+
+def session_sequence(seed: int, n_frames: int, width: int, height: int, *, device="cpu", hole_rate: float = 0.0,
+                     low_texture_rate: float = 0.0) -> dict:
+    """One serving session's own short sequence: scene, trajectory and IMU
+    stream from ``seed``, the trajectory spanning the frames alone.  Each of
+    frames 1..n_frames-1 independently gets 80% zero-depth holes with
+    probability ``hole_rate`` and the low-texture albedo with probability
+    ``low_texture_rate`` (draws from a generator seeded by (seed, 7), so the
+    frame flags of one session do not depend on the other sessions)."""
+    draws = np.random.default_rng([seed, 7]).random((n_frames, 2))
+    holes = [j for j in range(1, n_frames) if draws[j, 0] < hole_rate]
+    lowt = [j for j in range(1, n_frames) if draws[j, 1] < low_texture_rate]
+    return sequence(seed=seed, n_frames=n_frames, width=width, height=height, device=device,
+                    duration=(n_frames + 2) / 30.0, hole_frames=holes, low_texture_frames=lowt)
 
 
 def _rot_from_quat(q):

@@ -75,3 +75,60 @@ def test_sequence_accuracy_windows():
     a = bench.sequence_accuracy(est, gt, windows=((0, 10), (10, None)))
     assert abs(a["windows"][0]["vel_err_mps"] - 0.3) < 1e-12 and a["windows"][1]["vel_err_mps"] == 0.0
     assert a["windows"][0]["bg_err_radps"] == 0.0 and abs(a["windows"][1]["bg_err_radps"] - 1e-4) < 1e-15
+
+
+def test_quaternion_angle_matches_rotation_matrices():
+    import synth
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        qa, qb = rng.normal(size=4), rng.normal(size=4)
+        qa, qb = qa / np.linalg.norm(qa), qb / np.linalg.norm(qb)
+        R = synth.configs._rot_from_quat
+        ref = np.radians(bench.rot_angle_deg(R(qa), R(qb)))
+        assert abs(bench.quat_angle(qa, qb) - ref) < 1e-9
+        assert abs(bench.quat_angle(qa, -qb) - ref) < 1e-9  # q and -q are one rotation
+    h = np.sqrt(0.5)
+    assert abs(bench.quat_angle([1, 0, 0, 0], [h, h, 0, 0]) - np.pi / 2) < 1e-15
+
+
+def test_counter_scaling(monkeypatch):
+    """Counter readings in KiB become bytes through the calibration copy: a copy of COPY_BYTES each way
+    reads c_f KiB and writes c_w KiB, so a kernel reading f KiB moved f / c_f * COPY_BYTES bytes."""
+    c = dict(bench.COUNTERS, source_sha256=bench.residual_source_hash()[:16],
+             copy_fetch_kib=2.0 * bench.COPY_BYTES / 1024, copy_write_kib=bench.COPY_BYTES / 1024,
+             shapes={"2,1": {"fetch_kib": 1000.0, "write_kib": 10.0, "valu_insts": 123.0, "waves": 7}})
+    monkeypatch.setattr(bench, "COUNTERS", c)
+    f = bench.counter_figures(2, 1)
+    assert f["fetch_bytes"] == 1000.0 * 1024 / 2.0 and f["write_bytes"] == 10.0 * 1024
+    assert f["traffic_bytes"] == f["fetch_bytes"] + f["write_bytes"] and f["valu_insts"] == 123.0
+    assert bench.counter_figures(2, 0) is None and bench.counter_figures(4, 1) is None  # other launch shapes
+    monkeypatch.setattr(bench, "COUNTERS", dict(c, source_sha256="0" * 16))
+    assert bench.counter_figures(2, 1) is None  # taken for other kernel sources
+
+
+def test_model_view_at_reproduces_the_sequence_render():
+    """The closed-loop model view rendered at a state's pose equals the sequence's own noise-free render
+    at that frame's ground-truth pose (same scene; the pose only goes through the world frame and back)."""
+    import synth
+    seq = synth.configs.session_sequence(77, 3, 64, 48)
+    for j in range(3):
+        z, inten, T = synth.configs.model_view_at(seq, seq["gt"][j])
+        ref = seq["clean_depth"][j].numpy()
+        zz = z.numpy()
+        assert np.array_equal(zz > 0, ref > 0) or np.mean((zz > 0) != (ref > 0)) < 1e-3
+        both = (zz > 0) & (ref > 0)
+        assert np.max(np.abs(zz[both] - ref[both])) < 1e-5
+        assert np.mean(inten.numpy() != seq["intensity"][j].numpy()) < 1e-3
+        assert np.allclose(T[:3, 3], seq["gt"][j]["r"])
+
+
+def test_session_sequence_flags_depend_on_the_seed_alone():
+    import synth
+    a = synth.configs.session_sequence(5011, 12, 32, 24, hole_rate=0.3, low_texture_rate=0.3)
+    b = synth.configs.session_sequence(5011, 12, 32, 24, hole_rate=0.3, low_texture_rate=0.3)
+    assert a["hole_frames"] == b["hole_frames"] and a["low_texture_frames"] == b["low_texture_frames"]
+    assert a["hole_frames"] and a["low_texture_frames"] and 0 not in a["hole_frames"]
+    for j in a["hole_frames"]:
+        assert (a["depth"][j] == 0).float().mean() > 0.7
+    c = synth.configs.session_sequence(5012, 12, 32, 24, hole_rate=0.3, low_texture_rate=0.3)
+    assert not np.array_equal(a["depth"][1].numpy(), c["depth"][1].numpy())

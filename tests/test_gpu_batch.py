@@ -60,6 +60,64 @@ def test_batched_results_equal_alone_results(jac):
     ctx.close()
 
 
+# compositions repeat, so later steps replay graphs captured by earlier ones
+GRAPH_STEPS = [[0, 1, 2, 3, 4, 5], [1, 3, 5], [5, 4, 3, 2, 1, 0], [0, 2, 3, 4], [0, 1, 2, 3, 4, 5], [3, 1, 5],
+               [2, 0, 4, 3], [1, 0, 2, 3, 4, 5]]
+
+
+def test_batch_graph_replays_equal_alone_results():
+    """With the batch's launches replayed from graphs (one per composition), every step equals the
+    sessions tracked alone, bit for bit, also when eager work of the program (another session's
+    frames, library and torch kernels, synchronisations) runs between the replays."""
+    import torch
+    seqs = [synth.configs.sequence(seed=s, n_frames=10, width=w, height=h, device="cuda") for s, w, h, _ in SESSIONS]
+    stream = torch.cuda.current_stream()
+    ctx = P.Context(0)
+    alone = []
+    for idx, (seq, (_, _, _, mode)) in enumerate(zip(seqs, SESSIONS)):
+        s = _open(ctx, seq, mode)
+        res = []
+        for j in range(1, sum(1 for st in GRAPH_STEPS if idx in st) + 1):
+            f = _frame(seq, j)
+            if mode == "rgbd":
+                f["imu"] = None
+            res.append(s.track_frame_sync(f, stream))
+        alone.append(res)
+        s.close()
+    sess = [_open(ctx, seq, mode) for seq, (_, _, _, mode) in zip(seqs, SESSIONS)]
+    other = _open(ctx, seqs[0], "rgbdi")
+    batch = P.Batch(ctx, len(SESSIONS))
+    batch.set_graphs(True)
+    nxt = [1] * len(SESSIONS)
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for step, members in enumerate(GRAPH_STEPS):
+        frames = [_frame(seqs[i], nxt[i]) for i in members]
+        for i, f in zip(members, frames):
+            if SESSIONS[i][3] == "rgbd":
+                f["imu"] = None
+        batch.track([sess[i] for i in members], frames, stream)
+        out = batch.results()
+        for i, r in zip(members, out):
+            _same(r, alone[i][nxt[i] - 1], f"graph step {step} session {i} frame {nxt[i]}")
+            nxt[i] += 1
+        print(f"graph step {step}: sessions {members} equal to alone", flush=True)
+        # the program's own eager work between replays
+        other.track_frame_sync(_frame(seqs[0], 1 + step % 8), stream)
+        scratch.mul_(0.5).add_(float(step))
+        torch.cuda.synchronize()
+    batch.set_graphs(False)  # frees the graphs; the eager launches continue the same sessions
+    members = [0, 1, 2, 3, 4, 5]
+    frames = [_frame(seqs[i], nxt[i]) for i in members]
+    frames[4]["imu"] = None
+    batch.track([sess[i] for i in members], frames, stream)
+    assert all(r["status"] == 0 for r in batch.results())
+    batch.close()
+    other.close()
+    for s in sess:
+        s.close()
+    ctx.close()
+
+
 def test_batch_rejects_inconsistent_sessions():
     import torch
     seq = synth.configs.sequence(seed=3201, n_frames=3, width=160, height=120, device="cuda")

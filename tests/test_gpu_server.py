@@ -28,7 +28,8 @@ def _alone(ctx, seq, mode, stream):
     return out
 
 
-def test_server_results_equal_alone_results():
+@pytest.mark.parametrize("graphs", [False, True])
+def test_server_results_equal_alone_results(graphs):
     import torch
     stream = torch.cuda.current_stream()
     seqs = [synth.configs.sequence(seed=sd, n_frames=FRAMES + 2, width=w, height=h, device="cuda")
@@ -37,7 +38,7 @@ def test_server_results_equal_alone_results():
     alone = [_alone(ctx, seq, mode, stream) for seq, (_, _, _, mode) in zip(seqs, SESSIONS)]
     torch.cuda.synchronize()
     sess = [open_seq_session(ctx, seq, mode) for seq, (_, _, _, mode) in zip(seqs, SESSIONS)]
-    server = P.Server(ctx, max_batch=3, pipeline_depth=2)
+    server = P.Server(ctx, max_batch=3, pipeline_depth=2, graphs=graphs)
     inputs, owner = [], {}
     # frames interleaved across sessions (each session's in order); the last two sessions start late
     order = sorted(((i, j) for j in range(1, FRAMES + 1) for i in range(len(SESSIONS))),
