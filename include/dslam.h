@@ -215,7 +215,8 @@ typedef struct {
  * a width x height camera with `jac_format` runs fastest with `ppt` pixels per
  * thread and, with xcd_banded = 1, its tiles dealt to the GPU's 8
  * accelerator dies (XCDs, each with its own L2 cache) in contiguous bands
- * rather than round-robin (us: its measured time per launch). */
+ * rather than round-robin (us: its measured time per pass and reduction of
+ * its partials). */
 typedef struct {
   int32_t width, height, level, jac_format, ppt;
   float us;
@@ -238,9 +239,10 @@ uint64_t dslam_context_used_bytes(const dslam_context* ctx);
 
 /* Tile-shape autotuner for the residual pass.  For each camera cams[0..n) and
  * each of its `levels` pyramid levels, times the pass (jac_format's kernel)
- * with 1, 2 and 4 pixels per thread, each with the tiles in round-robin and in
+ * followed by the reduction of its block partials (as the Gauss-Newton step
+ * starts with it) with 1, 2 and 4 pixels per thread, each with the tiles in round-robin and in
  * XCD-banded order, on a synthetic slanted, textured plane (best of three
- * rounds of 20 launches) and records the first shape in that order within 2%
+ * rounds of 20 launch pairs) and records the first shape in that order within 2%
  * of the fastest in the context; sessions opened on the context afterwards with the
  * same resolution and format use it (a session keeps its tile shape for life,
  * so its results do not depend on batching; the tile order never changes a

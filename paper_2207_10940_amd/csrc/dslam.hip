@@ -482,9 +482,12 @@ dslam_status dslam_context_autotune(dslam_context* ctx, const dslam_camera* cams
       if (hipMemsetAsync(s->sd->xf, 0, sizeof(s->sd->xf), st) != hipSuccess) return DSLAM_ERR_DEVICE;
       for (int l = 0; l < levels; ++l) {
         ResidualArgs ra = residual_args(s, l, s->sd->xf, nullptr);
-        // each shape's time is the best of three rounds of back-to-back launches;
-        // the first shape (in the order below) within 2% of the fastest wins, so
-        // that shapes whose times differ by noise alone do not flip between runs
+        // a shape is timed as the pass plus the fixed-order reduction of its block
+        // partials that the Gauss-Newton step starts with (fewer pixels per
+        // thread make a faster pass but more partials to add); each shape's time
+        // is the best of three rounds of back-to-back launches, and the first
+        // shape (in the order below) within 2% of the fastest wins, so that
+        // shapes whose times differ by noise alone do not flip between runs
         const int shapes[6][2] = {{1, 0}, {1, 1}, {2, 0}, {2, 1}, {4, 0}, {4, 1}};
         float t[6];
         for (int c = 0; c < 6; ++c) {
@@ -492,11 +495,16 @@ dslam_status dslam_context_autotune(dslam_context* ctx, const dslam_camera* cams
           const int ppt = shapes[c][0], reps = 20;
           t[c] = 0.0f;
           for (int round = 0; round < 3; ++round) {
+            const int nb = residual_blocks(ra.npix, ppt);
+            auto pass = [&]() {
+              return launch_residual(ra, ppt, st) == hipSuccess &&
+                     launch_reduce(s->partials, nb, s->red_out, st) == hipSuccess;
+            };
             for (int r = 0; r < 2; ++r)
-              if (launch_residual(ra, ppt, st) != hipSuccess) return DSLAM_ERR_DEVICE;
+              if (!pass()) return DSLAM_ERR_DEVICE;
             if (hipEventRecord(e0, st) != hipSuccess) return DSLAM_ERR_DEVICE;
             for (int r = 0; r < reps; ++r)
-              if (launch_residual(ra, ppt, st) != hipSuccess) return DSLAM_ERR_DEVICE;
+              if (!pass()) return DSLAM_ERR_DEVICE;
             if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
               return DSLAM_ERR_DEVICE;
             float ms = 0.0f;
