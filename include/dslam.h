@@ -116,6 +116,14 @@ typedef struct {
   /* health checks of a tracked frame (dslam_track_result.health); 0 disables each */
   double min_inlier_frac; /* LOW_INLIERS below this fraction of 2 x (level-0 pixels) inliers of both terms */
   double max_cost_rise;   /* COST_UP when the finest level's visual cost rises by more than this fraction */
+  /* 1 (RGB-D-inertial mode only): a frame that ends with tracking lost
+   * (LOW_INLIERS, NONFINITE or COST_UP) is re-estimated without its visual
+   * terms: one Gauss-Newton step of the prior and the IMU factor alone
+   * (Sections IV-C, IV-E) from the frame's start state and its IMU
+   * prediction, marginalised at the result; health gains IMU_ONLY.  0: the
+   * joint estimate stands, flagged.  Costs one extra launch per frame, which
+   * returns at once unless the frame was lost. */
+  int32_t imu_fallback;
 } dslam_track_params;
 
 typedef struct {
@@ -151,7 +159,8 @@ enum {
   DSLAM_HEALTH_LOW_INLIERS = 1, /* level-0 inliers (ICP + photometric) < min_inlier_frac x 2 x pixels */
   DSLAM_HEALTH_NONFINITE = 2,   /* a cost or an updated state entry is not finite */
   DSLAM_HEALTH_COST_UP = 4,     /* finest level: last visual cost > (1 + max_cost_rise) x first */
-  DSLAM_HEALTH_SINGULAR = 8     /* a Gauss-Newton system was not positive definite (status SINGULAR) */
+  DSLAM_HEALTH_SINGULAR = 8,    /* a Gauss-Newton system was not positive definite (status SINGULAR) */
+  DSLAM_HEALTH_IMU_ONLY = 16    /* the estimate is the inertial-only fallback (dslam_track_params.imu_fallback) */
 };
 
 /* Result of one tracked frame. */

@@ -21,7 +21,15 @@ Readings taken where the paper is silent:
 * a fixed number of iterations per level, no damping, no early exit;
 * the float32 transforms that drive association are the float64 compositions
   T_WM^-1 T_WC1 (ICP) and T_WC0^-1 T_WC1 (photometric), their rotations kept
-  as R - I, rounded once to float32.
+  as R - I, rounded once to float32;
+* health of the frame (not in the paper): tracking is lost when the finest
+  level's last pass has fewer inliers of both terms than min_inlier_frac of
+  twice its pixels, when its visual cost exceeds (1 + max_cost_rise) times
+  its first pass's, or when a cost or state is not finite;
+* with imu_fallback (RGB-D-inertial mode), a lost frame is re-estimated
+  without its visual terms: one Gauss-Newton step of the prior and the IMU
+  factor (Sections IV-C, IV-E) from the frame's start state x0, the IMU
+  prediction of x1 and the start q_IW, marginalised at the result.
 """
 from __future__ import annotations
 
@@ -37,6 +45,7 @@ from .lie import copy_state, quat_to_rot, state_boxplus
 def default_params(levels=3, iters=(10, 5, 4), mode="rgbdi"):
     return {
         "levels": levels, "iters": list(iters), "mode": mode,
+        "min_inlier_frac": 0.05, "max_cost_rise": 0.5, "imu_fallback": False,
         "depth_k": 1e-3, "sigma_I": 4.0, "huber_k": 1.345, "icp_dist": 0.10, "icp_cos": None,
         "sigma_g": 1.7e-4, "sigma_a": 2.0e-3, "sigma_bg_rw": 4.0e-6, "sigma_ba_rw": 2.0e-5,
         "gravity": 9.81, "R_CS": np.eye(3), "t_CS": np.zeros(3),
@@ -94,6 +103,10 @@ def track_frame(depth, intensity, model_depth, model_intensity, T_WM, camera, im
         x1 = imu_mod.predict_state_gyro(x0, pre, params)
     else:
         x1 = imu_mod.predict_state(x0, q_IW, pre, params)
+    start = (copy_state(x0), copy_state(x1), q_IW.copy())  # the frame's start and the prediction of x1
+    finest = min(l for l in range(levels) if params["iters"][l] > 0)
+    cost_first = cost_last = None
+    n_last = 0
     log = []
     H = b = dz = None
     status = "ok"
@@ -101,6 +114,10 @@ def track_frame(depth, intensity, model_depth, model_intensity, T_WM, camera, im
         for it in range(params["iters"][lvl]):
             Ra, ta, Rb, tb = fp32_transforms(T_WM, x0, x1)
             vis = linearise_visual(cur[lvl], ref[lvl], T_WM, x0, x1, Ra, ta, Rb, tb, params)
+            if lvl == finest:
+                cost_last = vis["cost_icp"] + vis["cost_rgb"]
+                cost_first = cost_last if it == 0 else cost_first
+                n_last = vis["n_icp"] + vis["n_rgb"]
             if mode == "rgbd":
                 Hv = vis["H_icp"] + vis["H_rgb"]
                 bv = vis["b_icp"] + vis["b_rgb"]
@@ -149,4 +166,31 @@ def track_frame(depth, intensity, model_depth, model_intensity, T_WM, camera, im
     new_prior = None
     if status == "ok" and mode != "rgbd":
         new_prior = slv.marginalise(H, b, dz, x1, q_IW)
-    return {"x0": x0, "x1": x1, "q_IW": q_IW, "prior": new_prior, "status": status, "preint": pre, "log": log}
+    health = []
+    if status == "ok":
+        npix = cur[finest]["D"].size
+        if params.get("min_inlier_frac", 0.0) > 0.0 and n_last < params["min_inlier_frac"] * 2.0 * npix:
+            health.append("low_inliers")
+        states = np.concatenate([np.concatenate([np.ravel(x[k]) for k in ("r", "q", "v", "bg", "ba")])
+                                 for x in (x0, x1)] + [np.ravel(q_IW)])
+        if not (np.all(np.isfinite(states)) and np.isfinite(cost_last)):
+            health.append("nonfinite")
+        if params.get("max_cost_rise", 0.0) > 0.0 and cost_last > (1.0 + params["max_cost_rise"]) * cost_first:
+            health.append("cost_up")
+    if health and mode == "rgbdi" and params.get("imu_fallback"):
+        x0f, x1f, qf = copy_state(start[0]), copy_state(start[1]), start[2].copy()
+        e, J, W = imu_mod.factor(x0f, x1f, qf, pre, params)
+        Hf = J.T @ W @ J
+        bf = -(J.T @ W @ e)
+        Hp, bp = slv.prior_terms(x0f, qf, prior)
+        Hf = Hf + Hp
+        bf = bf + bp
+        if slv.is_spd(Hf):
+            dzf = slv.gn_step(Hf, bf)
+            x0, x1, q_IW = slv.apply_update(x0f, x1f, qf, dzf)
+            new_prior = slv.marginalise(Hf, bf, dzf, x1, q_IW)
+            health.append("imu_only")
+        else:
+            health.append("singular")
+    return {"x0": x0, "x1": x1, "q_IW": q_IW, "prior": new_prior, "status": status, "preint": pre, "log": log,
+            "health": health}

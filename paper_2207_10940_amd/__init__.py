@@ -13,7 +13,7 @@ import numpy as np
 
 from . import _abi
 from ._abi import (CH_GX, CH_GY, CH_I, CH_NX, CH_NY, CH_NZ, CH_VX, CH_VY, CH_VZ, HEALTH_COST_UP, HEALTH_LOW_INLIERS,
-                   HEALTH_NONFINITE, HEALTH_SINGULAR, JAC_BF16, JAC_FP16, JAC_FP32, JAC_FP32_MFMA, MODE_GYRO, MODE_RGBD,
+                   HEALTH_IMU_ONLY, HEALTH_NONFINITE, HEALTH_SINGULAR, JAC_BF16, JAC_FP16, JAC_FP32, JAC_FP32_MFMA, MODE_GYRO, MODE_RGBD,
                    MODE_RGBDI, PYR_CURRENT, PYR_MODEL)
 
 __all__ = ["DslamError", "Context", "Session", "Map", "Deform", "Batch", "Server", "frame_input", "preintegrate_imu", "solve_step", "track_params", "imu_params",
@@ -71,7 +71,7 @@ def camera(cam) -> _abi.Camera:
 
 def track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32", icp_dist=0.10, icp_cos=None,
                  sigma_I=4.0, depth_k=1e-3, huber_k=1.345, min_inlier_frac=0.05,
-                 max_cost_rise=0.5) -> _abi.TrackParams:
+                 max_cost_rise=0.5, imu_fallback=False) -> _abi.TrackParams:
     p = _abi.TrackParams()
     p.levels = levels
     its = list(iters) + [0] * (_abi.MAX_LEVELS - len(iters))
@@ -85,6 +85,7 @@ def track_params(levels=3, iters=(10, 5, 4), mode="rgbdi", jac="fp32", icp_dist=
     p.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     p.min_inlier_frac = min_inlier_frac
     p.max_cost_rise = max_cost_rise
+    p.imu_fallback = int(bool(imu_fallback))
     return p
 
 

@@ -11,7 +11,7 @@ OK, ERR_INVALID, ERR_NO_CAPACITY, ERR_SINGULAR, ERR_DEVICE, ERR_BUSY, ERR_NOT_RE
 MODE_RGBDI, MODE_RGBD, MODE_GYRO = 0, 1, 2
 JAC_FP32, JAC_FP32_MFMA, JAC_FP16, JAC_BF16 = 0, 1, 2, 3
 PYR_CURRENT, PYR_MODEL = 0, 1
-HEALTH_LOW_INLIERS, HEALTH_NONFINITE, HEALTH_COST_UP, HEALTH_SINGULAR = 1, 2, 4, 8
+HEALTH_LOW_INLIERS, HEALTH_NONFINITE, HEALTH_COST_UP, HEALTH_SINGULAR, HEALTH_IMU_ONLY = 1, 2, 4, 8, 16
 CH_VX, CH_VY, CH_VZ, CH_NX, CH_NY, CH_NZ, CH_I, CH_GX, CH_GY = range(9)
 
 
@@ -35,7 +35,7 @@ class TrackParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("iters", C.c_int32 * MAX_LEVELS), ("icp_dist", C.c_double),
                 ("icp_cos", C.c_double), ("sigma_I", C.c_double), ("depth_k", C.c_double), ("huber_k", C.c_double),
                 ("jac_format", C.c_int32), ("mode", C.c_int32), ("min_inlier_frac", C.c_double),
-                ("max_cost_rise", C.c_double)]
+                ("max_cost_rise", C.c_double), ("imu_fallback", C.c_int32)]
 
 
 class ImuSample(C.Structure):

@@ -35,6 +35,10 @@ struct SessionDev {
   double sys[58];      // reduced sums of the last residual pass
   dslam_track_result result;
   double cost_first;   // visual cost at the first iteration of the frame's finest level (health check)
+  // the frame's start (inertial-only fallback): x0, the IMU prediction of x1, q_IW and the prior
+  dslam_frame_state x0_frame, x1_pred;
+  double qIW_frame[4];
+  dslam_prior prior_frame;
   int32_t status;      // first error of the current frame
   int32_t frame_index;
 };

@@ -72,7 +72,7 @@ bool params_ok(const dslam_camera* cam, const dslam_track_params* tp) {
       !(tp->depth_k > 0) || !(tp->huber_k >= 0))
     return false;
   if (!(tp->min_inlier_frac >= 0 && tp->min_inlier_frac <= 1) || !(tp->max_cost_rise >= 0) ||
-      !std::isfinite(tp->max_cost_rise))
+      !std::isfinite(tp->max_cost_rise) || (tp->imu_fallback != 0 && tp->imu_fallback != 1))
     return false;
   return true;
 }
@@ -181,6 +181,7 @@ SolveParams solve_params(dslam_session* s) {
   const double npix = fl >= 0 ? (double)s->cur[fl].W * (double)s->cur[fl].H : 0.0;
   sp.min_inliers = s->tp.min_inlier_frac > 0.0 ? s->tp.min_inlier_frac * 2.0 * npix : 0.0;
   sp.max_cost_rise = s->tp.max_cost_rise > 0.0 ? s->tp.max_cost_rise : 0.0;
+  sp.imu_fallback = s->tp.imu_fallback == 1 && s->tp.mode == DSLAM_MODE_RGBDI ? 1 : 0;
   return sp;
 }
 
@@ -218,6 +219,7 @@ FrameArgs frame_args(dslam_session* s, const SolveParams& sp) {
   for (int i = 0; i < 9; ++i) fa.R_WM[i] = sp.R_WM[i];
   for (int i = 0; i < 3; ++i) fa.t_WM[i] = sp.t_WM[i];
   fa.mode = s->tp.mode;
+  fa.imu_fallback = sp.imu_fallback;
   return fa;
 }
 
@@ -746,6 +748,19 @@ static dslam_status track_enqueue(dslam_session* s, const float* depth, const ui
     if (s->use_graphs) HIP_OK(hipGraphLaunch(s->graph[l], st));
     else HIP_OK(enqueue_level(s, l, &sp, st));
   }
+  if (sp.imu_fallback) {  // the inertial-only re-estimate of a lost frame (returns at once otherwise)
+    const int fl = last_level_of(s->tp);
+    if (s->use_graphs) {
+      HIP_OK(launch_solve_graph(s->sd, s->partials, s->sp_dev, fl, STEP_LAST | STEP_INERTIAL, 0, st));
+    } else {
+      SolveArgs sa;
+      sa.sp = sp;
+      sa.level = fl;
+      sa.flags = STEP_LAST | STEP_INERTIAL;
+      sa.nblocks = 0;
+      HIP_OK(launch_solve(s->sd, s->partials, sa, st));
+    }
+  }
   if (out) HIP_OK(hipMemcpyAsync(out, &s->sd->result, sizeof(dslam_track_result), hipMemcpyDeviceToHost, st));
   HIP_OK(mark_session(s, st));
   return DSLAM_OK;
@@ -895,6 +910,7 @@ struct BatchPlan {
   int iters[DSLAM_MAX_LEVELS];
   dslam_track_params tp;  // the schedule (levels, iterations) of the step flags
   BatchGrid pyr_grid;
+  int fallback;  // some session re-estimates a lost frame without its visual terms
   int max_ppt[DSLAM_MAX_LEVELS];
   int banded[DSLAM_MAX_LEVELS];  // tile order of the level's batched residual pass
   BatchGrid res_grid[DSLAM_MAX_LEVELS];
@@ -912,7 +928,7 @@ void push_grid(std::vector<int32_t>* k, const BatchGrid& g) {
 
 // Everything a batched step's launches depend on, as a key of its graph.
 std::vector<int32_t> plan_key(const BatchPlan& p) {
-  std::vector<int32_t> k{p.n, p.levels, p.jac};
+  std::vector<int32_t> k{p.n, p.levels, p.jac, p.fallback};
   for (int l = 0; l < p.levels; ++l) k.push_back(p.iters[l]);
   push_grid(&k, p.pyr_grid);
   for (int l = 0; l < p.levels; ++l) {
@@ -1017,6 +1033,8 @@ dslam_status batch_stage(const BatchMem& m, int32_t n, dslam_session* const* ses
   plan->levels = s0->levels;
   plan->jac = s0->tp.jac_format;
   plan->tp = s0->tp;
+  plan->fallback = 0;
+  for (int k = 0; k < n; ++k) plan->fallback |= m.h_solve[k].sp.imu_fallback;
   plan->pyr_grid = grid([&](const dslam_session* s) { return 2 * PyrTileStd::tiles(s->cam.width, s->cam.height); });
   for (int l = 0; l < s0->levels; ++l) {
     int max_ppt = 1;
@@ -1049,6 +1067,8 @@ hipError_t batch_launches(const BatchMem& m, const BatchPlan& p, hipStream_t st)
       e = launch_residual_batch(m.d_vis, p.res_grid[l], l, p.max_ppt[l], p.jac, p.banded[l], st);
       if (e == hipSuccess) e = launch_solve_batch(m.d_solve, p.n, l, step_flags(p.tp, l, it), st);
     }
+  if (e == hipSuccess && p.fallback)
+    e = launch_solve_batch(m.d_solve, p.n, last_level_of(p.tp), STEP_LAST | STEP_INERTIAL, st);
   if (e == hipSuccess) e = launch_gather_results(m.d_solve, p.n, m.d_res, st);
   return e;
 }

@@ -138,6 +138,15 @@ __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& 
       sd->result.n_rgb[l] = 0;
     }
   }
+  if (fa.imu_fallback) {  // uniform: the frame's start for the inertial-only fallback, one double per lane
+    const int t = (int)threadIdx.x;
+    if (t < 16) reinterpret_cast<double*>(&sd->x0_frame)[t] = reinterpret_cast<const double*>(&x0)[t];
+    else if (t < 32) reinterpret_cast<double*>(&sd->x1_pred)[t - 16] = reinterpret_cast<const double*>(&x1)[t - 16];
+    else if (t < 36) sd->qIW_frame[t - 32] = qIW[t - 32];
+    const double* src = reinterpret_cast<const double*>(&sd->prior);
+    double* dst = reinterpret_cast<double*>(&sd->prior_frame);
+    for (int i = t; i < (int)(sizeof(dslam_prior) / 8); i += SOLVE_THREADS) dst[i] = src[i];
+  }
 }
 
 // Workgroup 0 initialises the frame and stores the frame's solve parameters
@@ -192,10 +201,16 @@ __device__ __forceinline__ D& state_word(S& x0, S& x1, D* q, int k) {
 // sp is read where it lies (the kernel argument, or the batch slot in device
 // memory): a private copy of it is not promoted to registers reliably and
 // then lives in scratch memory.  The marginalisation of the frame's last step
-// is selected by `last` (sp.marginalise is ignored here).
+// is selected by `last` (sp.marginalise is ignored here).  With STEP_INERTIAL
+// (after the frame's last step, with STEP_LAST) the step re-estimates a lost
+// frame without its visual terms: from the frame's start state, its IMU
+// prediction and the frame's prior, with zero visual sums; it returns at once
+// unless the frame ended with tracking lost and the fallback is enabled.
 __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials, const SolveParams& sp, int level,
                                            int flags, int nblocks) {
   const int last = (flags & STEP_LAST) != 0;
+  const bool inertial = (flags & STEP_INERTIAL) != 0;
+  if (inertial) nblocks = 0;  // no visual sums
   __shared__ SolveWork w;
   __shared__ double raw[58];
   __shared__ dslam_frame_state x0, x1;
@@ -214,15 +229,21 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
       double* dst = reinterpret_cast<double*>(to);
       for (int i = threadIdx.x; i < bytes / 8; i += SOLVE_THREADS) dst[i] = src[i];
     };
-    copy(&sd->prior, &prior, sizeof(dslam_prior));
+    copy(inertial ? &sd->prior_frame : &sd->prior, &prior, sizeof(dslam_prior));
     copy(&sd->pre, &pre, sizeof(dslam_preint));
     copy(sd->Linv, w.Linv, sizeof(w.Linv));
-    copy(&sd->x0, &x0, sizeof(dslam_frame_state));
-    copy(&sd->x1, &x1, sizeof(dslam_frame_state));
-    copy(sd->qIW, qIW, sizeof(qIW));
-    SERIAL skip = sd->status != DSLAM_OK;
+    copy(inertial ? &sd->x0_frame : &sd->x0, &x0, sizeof(dslam_frame_state));
+    copy(inertial ? &sd->x1_pred : &sd->x1, &x1, sizeof(dslam_frame_state));
+    copy(inertial ? sd->qIW_frame : sd->qIW, qIW, sizeof(qIW));
+    SERIAL {
+      skip = sd->status != DSLAM_OK;
+      if (inertial)  // 2: nothing to do (the frame was tracked, or the fallback is off)
+        skip = (!skip && sp.imu_fallback && sp.mode == DSLAM_MODE_RGBDI && sd->result.tracking_lost &&
+                !(sd->result.health & DSLAM_HEALTH_SINGULAR)) ? 0 : 2;
+    }
   }
   DSLAM_SYNC();
+  if (skip == 2) return;
   if (skip) {
     if (last) {
       if (threadIdx.x < 36) state_word(sd->result.x0, sd->result.x1, sd->result.q_IW, (int)threadIdx.x) =
@@ -303,16 +324,18 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
     else if (lane == 0) sd->status = st;
   }
   TASK(2) {
-    sd->result.n_icp[level] = (int64_t)raw[28];
-    sd->result.n_rgb[level] = (int64_t)raw[57];
-    sd->result.cost_icp = w.cost[0];
-    sd->result.cost_rgb = w.cost[1];
+    if (!inertial) {  // the inertial re-estimate keeps the frame's visual figures
+      sd->result.n_icp[level] = (int64_t)raw[28];
+      sd->result.n_rgb[level] = (int64_t)raw[57];
+      sd->result.cost_icp = w.cost[0];
+      sd->result.cost_rgb = w.cost[1];
+    }
     sd->result.cost_imu = w.cost[2];
     double nrm = 0.0;
     int n = sp.mode != DSLAM_MODE_RGBD ? NZ : 6;
     for (int i = 0; i < n; ++i) nrm += w.dz[i] * w.dz[i];
     sd->result.last_step_norm = sqrt(nrm);
-    if (flags & STEP_FIRST) sd->cost_first = w.cost[0] + w.cost[1];
+    if ((flags & STEP_FIRST) && !inertial) sd->cost_first = w.cost[0] + w.cost[1];
   }
   if (last) {
     DSLAM_SYNC();
@@ -327,9 +350,19 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
       }
     }
     dslam_track_result& r = sd->result;
-    if (wave == 1 && lane < 36) state_word(r.x0, r.x1, r.q_IW, lane) = state_word(x0, x1, qIW, lane);
+    // (a failed inertial re-estimate leaves the frame's joint estimate published)
+    if (wave == 1 && lane < 36 && (ok || !inertial))
+      state_word(r.x0, r.x1, r.q_IW, lane) = state_word(x0, x1, qIW, lane);
     // the current state becomes the previous one of the next frame
     if (ok && wave == 2 && lane < 16) reinterpret_cast<double*>(&sd->x0)[lane] = reinterpret_cast<const double*>(&x1)[lane];
+    if (inertial) {
+      SERIAL {
+        r.health |= ok ? DSLAM_HEALTH_IMU_ONLY : DSLAM_HEALTH_SINGULAR;
+        r.tracking_lost = 1;
+        if (!ok) sd->status = DSLAM_OK;  // the joint estimate stands; the next frame starts normally
+      }
+      return;
+    }
     SERIAL {
       // health of the frame (dslam_track_result.health)
       int h = ok ? 0 : DSLAM_HEALTH_SINGULAR;

@@ -33,6 +33,7 @@ struct SolveParams {
   ImuParamsD imu;
   int mode;
   int marginalise;
+  int imu_fallback;      // 1: a lost RGB-D-inertial frame is re-estimated without its visual terms
   double min_inliers;    // health: level-0 inliers (both terms) below this flag LOW_INLIERS (0: off)
   double max_cost_rise;  // health: finest-level visual cost rise above this fraction flags COST_UP (0: off)
 };

@@ -22,6 +22,7 @@ struct FrameArgs {
   double sigma_g, sigma_a;
   double R_WM[9], t_WM[3];
   int32_t mode;
+  int32_t imu_fallback;  // keep the frame's start for the inertial-only fallback
 };
 
 struct SolveArgs {
@@ -44,7 +45,9 @@ struct SlotSolve {
 // Flags of a visual solve: the first iteration of the frame's finest level
 // (records the cost the health check compares with) and the frame's last
 // iteration (solves the 33-d system, marginalises, publishes the result).
-enum { STEP_FIRST = 1, STEP_LAST = 2 };
+// STEP_INERTIAL: the inertial-only re-estimate of a lost frame (runs after the
+// frame's last step; returns at once unless the frame was lost).
+enum { STEP_FIRST = 1, STEP_LAST = 2, STEP_INERTIAL = 4 };
 
 // pyramid.hip
 hipError_t launch_pyramid(const PyrArgs& a, hipStream_t st);

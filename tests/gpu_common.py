@@ -72,6 +72,7 @@ def same_result(a, b, what):
         for f in ("r", "q", "v", "bg", "ba"):
             assert np.array_equal(a[k][f], b[k][f]), (what, k, f, a[k][f] - b[k][f])
     assert np.array_equal(a["q_IW"], b["q_IW"]), what
+    assert a["health"] == b["health"] and a["tracking_lost"] == b["tracking_lost"], what
     assert a["n_icp"] == b["n_icp"] and a["n_rgb"] == b["n_rgb"], what
     for f in ("cost_icp", "cost_rgb", "cost_imu", "last_step_norm"):
         assert a[f] == b[f], (what, f)

@@ -157,3 +157,89 @@ def test_frames_on_different_streams_are_ordered():
         b.close()
     finally:
         ctx.close()
+
+
+def _lost_pair(seed, patch):
+    d = synth.configs.frame_pair(seed=seed, width=160, height=120)
+    z = d["depth"].numpy().copy()
+    keep = np.zeros_like(z, dtype=bool)
+    keep[patch[0]:patch[0] + 6, patch[1]:patch[1] + 6] = True
+    z[~keep] = 0.0
+    return d, z
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_inertial_fallback_matches_oracle(graphs):
+    """A frame with too few valid pixels to track (LOW_INLIERS) in RGB-D-inertial mode: with imu_fallback
+    the result is the oracle's inertial-only re-estimate (one Gauss-Newton step of the prior and the IMU
+    factor from the frame's start and its IMU prediction, marginalised there) and carries IMU_ONLY;
+    without it, the oracle's joint estimate.  A frame that tracks is unaffected by the option."""
+    from oracle import lie, track
+    d, z = _lost_pair(1001, (60, 80))
+    print(f"inertial fallback, graphs {graphs}", flush=True)
+    for fallback in (True, False):
+        p = track.default_params(levels=2, iters=(4, 4), mode="rgbdi")
+        p["imu_fallback"] = fallback
+        o = track.track_frame(z, d["intensity"].numpy(), d["model_depth"].numpy(), d["model_intensity"].numpy(),
+                              d["T_WM"], d["camera"], d["imu"], d["t0"], d["t1"], d["x0"], d["q_IW"], d["prior"], p)
+        with session(160, 120, 2, [4, 4], x0=d["x0"], q_IW=d["q_IW"], prior=d["prior"],
+                     imu_fallback=fallback) as s:
+            s.set_graphs(graphs)
+            f = _pair_frame(d)
+            f["depth"] = cuda(z)
+            g = s.track_frame_sync(f)
+            st = s.get_state()
+        assert g["status"] == 0 and g["tracking_lost"] and g["health"] & P.HEALTH_LOW_INLIERS
+        assert bool(g["health"] & P.HEALTH_IMU_ONLY) == fallback == ("imu_only" in o["health"])
+        dr = np.linalg.norm(g["x1"]["r"] - o["x1"]["r"])
+        da = np.linalg.norm(lie.quat_boxminus(g["x1"]["q"], o["x1"]["q"]))
+        dv = np.linalg.norm(g["x1"]["v"] - o["x1"]["v"])
+        eH = np.linalg.norm(g["prior"]["H"] - o["prior"]["H"]) / np.linalg.norm(o["prior"]["H"])
+        print(f"  fallback {fallback}: |dr| {dr:.2e} |da| {da:.2e} |dv| {dv:.2e} prior H {eH:.2e}", flush=True)
+        assert dr < 1e-6 and da < 1e-6 and dv < 1e-6 and eH < 1e-4
+        # the next frame starts from the published estimate
+        for k in ("r", "q", "v", "bg", "ba"):
+            assert np.array_equal(st[0][k], g["x1"][k]), k
+    # a frame that tracks: the option changes nothing, bit for bit
+    d = synth.configs.frame_pair(seed=1001, width=160, height=120)
+    res = []
+    for fallback in (False, True):
+        with session(160, 120, 2, [4, 4], x0=d["x0"], q_IW=d["q_IW"], prior=d["prior"],
+                     imu_fallback=fallback) as s:
+            s.set_graphs(graphs)
+            res.append(s.track_frame_sync(_pair_frame(d)))
+    same_result(res[1], res[0], "clean frame with and without the fallback")
+    assert res[1]["health"] == 0
+
+
+def test_inertial_fallback_batched_equals_alone():
+    import torch
+    stream = torch.cuda.current_stream()
+    d, z = _lost_pair(1001, (60, 80))
+    e = synth.configs.frame_pair(seed=1002, width=160, height=120)
+    print("inertial fallback batched", flush=True)
+    lost = _pair_frame(d)
+    lost["depth"] = cuda(z)
+    clean = _pair_frame(e)
+    ctx = P.Context(0)
+    cam = synth.configs.camera_for(160, 120)
+    tp = P.track_params(levels=2, iters=(4, 4), mode="rgbdi", imu_fallback=True)
+
+    def open_(x):
+        return P.Session(ctx, cam, tp, P.imu_params(), x["x0"], x["q_IW"], x["prior"])
+    alone = []
+    for x, f in ((d, lost), (e, clean)):
+        s = open_(x)
+        alone.append(s.track_frame_sync(f, stream))
+        s.close()
+    ss = [open_(d), open_(e)]
+    batch = P.Batch(ctx, 2)
+    batch.track(ss, [lost, clean], stream)
+    out = batch.results()
+    same_result(out[0], alone[0], "lost session batched")
+    same_result(out[1], alone[1], "clean session batched")
+    assert out[0]["health"] & P.HEALTH_IMU_ONLY and out[1]["health"] == 0
+    batch.close()
+    for s in ss:
+        s.close()
+    ctx.close()

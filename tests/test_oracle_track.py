@@ -74,3 +74,60 @@ def test_gyro_only_fails_without_visual_input():
         out = track.track_frame(z, d["intensity"].numpy(), d["model_depth"].numpy(), d["model_intensity"].numpy(),
                                 d["T_WM"], d["camera"], d["imu"], d["t0"], d["t1"], d["x0"], d["q_IW"], d["prior"], p)
         assert out["status"] == want, mode
+
+
+def _lost_pair(seed, patch):
+    """The 160x120 frame pair with the current depth zeroed outside a small patch: too few inliers (the
+    patch's pixels) to track, so the frame is lost (LOW_INLIERS)."""
+    d = synth.configs.frame_pair(seed=seed, width=160, height=120)
+    z = d["depth"].numpy().copy()
+    keep = np.zeros_like(z, dtype=bool)
+    r, c = patch
+    keep[r:r + 6, c:c + 6] = True
+    z[~keep] = 0.0
+    return d, z
+
+
+def _track(d, z, fallback, iters=(4, 4)):
+    p = track.default_params(levels=2, iters=iters, mode="rgbdi")
+    p["imu_fallback"] = fallback
+    return track.track_frame(z, d["intensity"].numpy(), d["model_depth"].numpy(), d["model_intensity"].numpy(),
+                             d["T_WM"], d["camera"], d["imu"], d["t0"], d["t1"], d["x0"], d["q_IW"], d["prior"], p)
+
+
+def test_health_flags_clean_and_lost_frames():
+    d = synth.configs.frame_pair(seed=1001, width=160, height=120)
+    assert _track(d, d["depth"].numpy(), True)["health"] == []
+    d, z = _lost_pair(1001, (60, 80))
+    o = _track(d, z, False)
+    assert "low_inliers" in o["health"] and "imu_only" not in o["health"]
+
+
+def test_inertial_fallback_is_the_imu_prediction_under_a_consistent_prior():
+    """Without visual terms, from the IMU prediction and under a prior centred on x0 with zero gradient,
+    every residual of the prior and the IMU factor is zero: the Gauss-Newton step vanishes and the
+    fallback returns the prediction itself (Section IV-C), with x0 unchanged."""
+    d, z = _lost_pair(1001, (60, 80))
+    o = _track(d, z, True)
+    assert "low_inliers" in o["health"] and "imu_only" in o["health"]
+    pre = o["preint"]
+    p = track.default_params(levels=2, iters=(4, 4), mode="rgbdi")
+    pred = track.imu_mod.predict_state(d["x0"], d["q_IW"], pre, p)
+    for k in ("r", "q", "v", "bg", "ba"):
+        assert np.max(np.abs(o["x1"][k] - pred[k])) < 1e-10, k
+        assert np.max(np.abs(o["x0"][k] - d["x0"][k])) < 1e-10, k
+    assert np.max(np.abs(o["q_IW"] - d["q_IW"])) < 1e-12
+    assert np.all(np.linalg.eigvalsh(0.5 * (o["prior"]["H"] + o["prior"]["H"].T)) > 0)
+
+
+def test_inertial_fallback_ignores_the_frames_visual_data():
+    """The fallback drops the lost frame's visual terms: two lost frames that differ only in their few
+    valid pixels give the same re-estimate, while their joint estimates differ."""
+    d, za = _lost_pair(1001, (60, 80))
+    _, zb = _lost_pair(1001, (20, 30))
+    a, b = _track(d, za, True), _track(d, zb, True)
+    ja, jb = _track(d, za, False), _track(d, zb, False)
+    for k in ("r", "q", "v", "bg", "ba"):
+        assert np.array_equal(a["x1"][k], b["x1"][k]), k
+    assert np.array_equal(a["prior"]["H"], b["prior"]["H"]) and np.array_equal(a["prior"]["b"], b["prior"]["b"])
+    assert max(np.max(np.abs(ja["x1"][k] - jb["x1"][k])) for k in ("r", "q", "v")) > 0.0
