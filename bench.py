@@ -41,8 +41,8 @@ LAYOUT_BYTES_PER_PIXEL = 44
 # and of a 256 MiB calibration copy, from rocprofv3 --pmc runs of `bench.py --counters --counters-batch`
 # (profiles/residual_kernel_640x480_counters.md); valid for the residual-pass sources with this hash
 COUNTERS = {
-    "source_sha256": "e881484d1ef392f8",
-    "copy_fetch_kib": 131086.8, "copy_write_kib": 262144.0,
+    "source_sha256": "593a22782dfad708",
+    "copy_fetch_kib": 131086.5, "copy_write_kib": 262144.0,
     "shapes": {  # "ppt,banded": per-dispatch means over 50 back-to-back launches
         "1,0": {"fetch_kib": 7947.7, "write_kib": 300.0, "valu_insts": 2433026, "waves": 4800},
         "1,1": {"fetch_kib": 5159.2, "write_kib": 300.0, "valu_insts": 2433026, "waves": 4800},
