@@ -512,6 +512,8 @@ struct dslam_deform {
   double* tiny;
   int* pairs;         // per lower tile pair: its two tiles, then the list offsets, then the row lists
   size_t pairs_cap;   // ints
+  hipEvent_t done;    // recorded after every solve's work (dslam_deform_destroy waits on it)
+  bool recorded;
   std::mutex mu;
 };
 
@@ -682,6 +684,13 @@ dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t 
   d->tiny = (double*)q; q += def_align(8);
   d->pairs = (int*)q;
   d->pairs_cap = pairs_cap;
+  d->recorded = false;
+  if (hipEventCreateWithFlags(&d->done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipFree(d->arena);
+    ctx->used.fetch_sub(bytes);
+    delete d;
+    return DSLAM_ERR_DEVICE;
+  }
   *out = d;
   return DSLAM_OK;
 }
@@ -689,7 +698,8 @@ dslam_status dslam_deform_create(dslam_context* ctx, int32_t max_nodes, int32_t 
 dslam_status dslam_deform_destroy(dslam_deform* d) {
   if (!d) return DSLAM_ERR_INVALID;
   (void)hipSetDevice(d->ctx->device);
-  (void)hipDeviceSynchronize();
+  if (d->recorded) (void)hipEventSynchronize(d->done);  // the last solve's work (not the whole device)
+  (void)hipEventDestroy(d->done);
   (void)hipFree(d->arena);
   d->ctx->used.fetch_sub(d->bytes);
   delete d;
@@ -713,6 +723,12 @@ dslam_status dslam_deform_solve(dslam_deform* d, const dslam_deform_problem* p, 
   std::lock_guard<std::mutex> g(d->mu);
   DEF_HIP(hipSetDevice(d->ctx->device));
   hipStream_t st = (hipStream_t)stream;
+  // whatever path returns from here, the work enqueued so far is marked for dslam_deform_destroy
+  struct MarkDone {
+    dslam_deform* d;
+    hipStream_t st;
+    ~MarkDone() { d->recorded = hipEventRecord(d->done, st) == hipSuccess || d->recorded; }
+  } mark{d, st};
   // host: neighbour lists and influences
   std::vector<int> nbr(N * DEF_K);
   for (int l = 0; l < N; ++l) {

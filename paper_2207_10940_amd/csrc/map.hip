@@ -576,8 +576,8 @@ dslam_status dslam_map_create(dslam_context* ctx, const dslam_camera* cam, const
   for (int k = 0; k < 3; ++k) { m->nrm[k] = (float*)q; q += map_align(npx * 4); }
   m->inten = (uint8_t*)q; q += map_align(npx);
   m->def_nodes = (double*)q;
-  if (hipMemset(ints, 0, 3 * sizeof(int32_t)) != hipSuccess || hipEventCreateWithFlags(&m->done, hipEventDisableTiming) != hipSuccess ||
-      hipDeviceSynchronize() != hipSuccess) {
+  if (hipMemsetAsync(ints, 0, 3 * sizeof(int32_t), nullptr) != hipSuccess ||
+      hipEventCreateWithFlags(&m->done, hipEventDisableTiming) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
     (void)hipFree(m->arena);
     ctx->used.fetch_sub(bytes);
     delete m;
@@ -590,7 +590,7 @@ dslam_status dslam_map_create(dslam_context* ctx, const dslam_camera* cam, const
 dslam_status dslam_map_destroy(dslam_map* m) {
   if (!m) return DSLAM_ERR_INVALID;
   (void)hipSetDevice(m->ctx->device);
-  (void)hipDeviceSynchronize();
+  (void)hipEventSynchronize(m->done);  // the map's last enqueued work (not the whole device)
   (void)hipEventDestroy(m->done);
   (void)hipFree(m->arena);
   m->ctx->used.fetch_sub(m->bytes);
