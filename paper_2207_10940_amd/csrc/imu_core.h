@@ -127,24 +127,33 @@ DX int preintegrate(Par par, const dslam_imu_sample* s, int n, double t0, double
   DSLAM_SYNC();
   const int nsub = w->nsub;
   if (nsub < 0) return DSLAM_ERR_INVALID;
-  // per-step quantities, independent across steps
-  PFOR(m, nsub) {
-    const dslam_imu_sample& smp = s[w->ksub[m]];
-    double dt = w->dtsub[m];
-    V3 wv = v3(smp.gyro[0] - bg[0], smp.gyro[1] - bg[1], smp.gyro[2] - bg[2]);
-    V3 av = v3(smp.acc[0] - ba[0], smp.acc[1] - ba[1], smp.acc[2] - ba[2]);
-    V3 phi = dt * wv;
-    double c[3], d[3];
-    gamma_coeffs(norm(phi), c, d);
-    PreintStep& P = w->st[m];
-    gamma_apply(phi, av, 1.0, c[0], c[1], d[0], d[1], &P.g1a, &P.D1);
-    gamma_apply(phi, av, 0.5, c[1], c[2], d[1], d[2], &P.g2a, &P.D2);
-    M3 K = hat(phi);
-    P.G1 = eye3() + c[0] * K + c[1] * (K * K);
-    P.G2 = 0.5 * eye3() + c[1] * K + c[2] * (K * K);
-    P.E = Exp(phi);
-    P.Jr = Jr(phi);
-    P.dt = dt;
+  // per-step quantities, independent across steps, in three independent
+  // parts (the Gamma terms, Exp, the right Jacobian): index 64 part + m, so
+  // that on the device each part runs on a wavefront of its own (nsub <= 33)
+  PFOR(i, 3 * 64) {
+    const int part = i >> 6, m = i & 63;
+    if (m < nsub) {
+      const dslam_imu_sample& smp = s[w->ksub[m]];
+      const double dt = w->dtsub[m];
+      const V3 wv = v3(smp.gyro[0] - bg[0], smp.gyro[1] - bg[1], smp.gyro[2] - bg[2]);
+      const V3 phi = dt * wv;
+      PreintStep& P = w->st[m];
+      if (part == 0) {
+        const V3 av = v3(smp.acc[0] - ba[0], smp.acc[1] - ba[1], smp.acc[2] - ba[2]);
+        double c[3], d[3];
+        gamma_coeffs(norm(phi), c, d);
+        gamma_apply(phi, av, 1.0, c[0], c[1], d[0], d[1], &P.g1a, &P.D1);
+        gamma_apply(phi, av, 0.5, c[1], c[2], d[1], d[2], &P.g2a, &P.D2);
+        M3 K = hat(phi);
+        P.G1 = eye3() + c[0] * K + c[1] * (K * K);
+        P.G2 = 0.5 * eye3() + c[1] * K + c[2] * (K * K);
+        P.dt = dt;
+      } else if (part == 1) {
+        P.E = Exp(phi);
+      } else {
+        P.Jr = Jr(phi);
+      }
+    }
   }
   DSLAM_SYNC();
   // the rotation chain and the integrated velocity and position (cheap, serial)
@@ -164,33 +173,48 @@ DX int preintegrate(Par par, const dslam_imu_sample* s, int n, double t0, double
     store3(w->dp, dp);
   }
   DSLAM_SYNC();
-  // step Jacobians A (error state [dphi, dv, dp]) and B (biases [bg, ba])
-  PFOR(m, nsub) {
-    const PreintStep& P = w->st[m];
-    double dt = P.dt;
-    double* A = w->A[m];
-    double* B = w->B[m];
-    for (int i = 0; i < 81; ++i) A[i] = (i % 10 == 0) ? 1.0 : 0.0;
-    M3 Et = tr(P.E);
-    M3 Av_phi = (-dt) * (P.dR * hat(P.g1a));
-    M3 Ap_phi = (-dt * dt) * (P.dR * hat(P.g2a));
-    M3 Bphi_g = (-dt) * P.Jr;
-    M3 Bv_g = (-dt * dt) * (P.dR * P.D1);
-    M3 Bp_g = (-dt * dt * dt) * (P.dR * P.D2);
-    M3 Bv_a = (-dt) * (P.dR * P.G1);
-    M3 Bp_a = (-dt * dt) * (P.dR * P.G2);
-    for (int i = 0; i < 3; ++i) {
-      A[9 * (6 + i) + 3 + i] = dt;
-      for (int j = 0; j < 3; ++j) {
-        A[9 * i + j] = Et(i, j);
-        A[9 * (3 + i) + j] = Av_phi(i, j);
-        A[9 * (6 + i) + j] = Ap_phi(i, j);
-        B[6 * i + j] = Bphi_g(i, j);
-        B[6 * i + 3 + j] = 0.0;
-        B[6 * (3 + i) + j] = Bv_g(i, j);
-        B[6 * (3 + i) + 3 + j] = Bv_a(i, j);
-        B[6 * (6 + i) + j] = Bp_g(i, j);
-        B[6 * (6 + i) + 3 + j] = Bp_a(i, j);
+  // step Jacobians A (error state [dphi, dv, dp]) and B (biases [bg, ba]), in
+  // three parts writing disjoint entries (A; B's gyro columns; B's
+  // accelerometer columns), each part on a wavefront of its own as above
+  PFOR(i, 3 * 64) {
+    const int part = i >> 6, m = i & 63;
+    if (m < nsub) {
+      const PreintStep& P = w->st[m];
+      const double dt = P.dt;
+      double* A = w->A[m];
+      double* B = w->B[m];
+      if (part == 0) {
+        for (int k = 0; k < 81; ++k) A[k] = (k % 10 == 0) ? 1.0 : 0.0;
+        const M3 Et = tr(P.E);
+        const M3 Av_phi = (-dt) * (P.dR * hat(P.g1a));
+        const M3 Ap_phi = (-dt * dt) * (P.dR * hat(P.g2a));
+        for (int r = 0; r < 3; ++r) {
+          A[9 * (6 + r) + 3 + r] = dt;
+          for (int j = 0; j < 3; ++j) {
+            A[9 * r + j] = Et(r, j);
+            A[9 * (3 + r) + j] = Av_phi(r, j);
+            A[9 * (6 + r) + j] = Ap_phi(r, j);
+          }
+        }
+      } else if (part == 1) {
+        const M3 Bphi_g = (-dt) * P.Jr;
+        const M3 Bv_g = (-dt * dt) * (P.dR * P.D1);
+        const M3 Bp_g = (-dt * dt * dt) * (P.dR * P.D2);
+        for (int r = 0; r < 3; ++r)
+          for (int j = 0; j < 3; ++j) {
+            B[6 * r + j] = Bphi_g(r, j);
+            B[6 * (3 + r) + j] = Bv_g(r, j);
+            B[6 * (6 + r) + j] = Bp_g(r, j);
+          }
+      } else {
+        const M3 Bv_a = (-dt) * (P.dR * P.G1);
+        const M3 Bp_a = (-dt * dt) * (P.dR * P.G2);
+        for (int r = 0; r < 3; ++r)
+          for (int j = 0; j < 3; ++j) {
+            B[6 * r + 3 + j] = 0.0;
+            B[6 * (3 + r) + 3 + j] = Bv_a(r, j);
+            B[6 * (6 + r) + 3 + j] = Bp_a(r, j);
+          }
       }
     }
   }

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(REDUCE_THREADS) void reduce_kernel(const float* par
 __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& batch, const FrameArgs& fa) {
   __shared__ PreintWork pw;
   __shared__ dslam_preint pre;
-  __shared__ dslam_frame_state x0, x1;
+  __shared__ dslam_frame_state x0, x1, xp;
   __shared__ double qIW[4];
   Par par{(int)threadIdx.x, SOLVE_THREADS};
   SERIAL {
@@ -99,19 +99,26 @@ __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& 
     st = preintegrate(par, batch.s, batch.n, batch.t0, batch.t1, x0.bg, x0.ba, fa.sigma_g, fa.sigma_a, &pw, &pre);
   if (fa.mode != DSLAM_MODE_RGBD && st == DSLAM_OK) {  // uniform
     // L^-1 of the preintegration covariance for the IMU whitening of every
-    // step of this frame (wave 0)
+    // step of this frame (wave 0), and meanwhile the prediction of x1 from
+    // the measurement (first lane of wave 1; kept only if the factorisation
+    // succeeds)
     __shared__ __attribute__((aligned(16))) double col[128];
     __shared__ double linv[81];
     __shared__ int lbad;
     if (threadIdx.x < 64) {
       const bool ok = chol_inv_lower9_wave(pre.Sigma, linv, (int)threadIdx.x, col);
       if (threadIdx.x == 0) lbad = ok ? 0 : 1;
+    } else if (threadIdx.x == 64) {
+      dslam_frame_state p = x0;
+      if (fa.mode == DSLAM_MODE_GYRO) imu_predict_gyro(x0, pre, fa.imu, &p);
+      else imu_predict(x0, qIW, pre, fa.imu, &p);
+      xp = p;
     }
     DSLAM_SYNC();
     if (threadIdx.x < 81) sd->Linv[threadIdx.x] = linv[threadIdx.x];
     if (lbad) st = DSLAM_ERR_SINGULAR;
   }
-  // the prediction of x1 on one lane while the others publish the measurement
+  // all lanes publish the measurement
   if (fa.mode != DSLAM_MODE_RGBD && st == DSLAM_OK) {  // uniform
     const double* src = reinterpret_cast<const double*>(&pre);
     double* dst = reinterpret_cast<double*>(&sd->pre);
@@ -119,12 +126,7 @@ __device__ __forceinline__ void frame_init_body(SessionDev* sd, const ImuBatch& 
   }
   SERIAL {
     if (st != DSLAM_OK) sd->status = st;
-    dslam_frame_state p = x0;
-    if (fa.mode != DSLAM_MODE_RGBD && st == DSLAM_OK) {
-      if (fa.mode == DSLAM_MODE_GYRO) imu_predict_gyro(x0, pre, fa.imu, &p);
-      else imu_predict(x0, qIW, pre, fa.imu, &p);
-    }
-    x1 = p;
+    x1 = (fa.mode != DSLAM_MODE_RGBD && st == DSLAM_OK) ? xp : x0;
   }
   DSLAM_SYNC();
   // the first pass's transforms on 24 lanes, the state and the record's reset
