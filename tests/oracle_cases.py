@@ -42,3 +42,45 @@ def tilted_plane_pair(W=160, H=120, seed=0, ramp=(0.75, 0.5, 10.0)):
 
 def identity_state():
     return {"r": np.zeros(3), "q": np.array([1.0, 0, 0, 0]), "v": np.zeros(3), "bg": np.zeros(3), "ba": np.zeros(3)}
+
+
+def imu_plane_pair(W=160, H=120, seed=11):
+    """A frame pair whose every residual of the joint cost vanishes at one known state: the IMU reads a
+    constant body rate (2 deg over 15 ms) and specific force (about hover), for which the zero-order hold
+    is exact, so the oracle's IMU prediction is the true x1; frame 1 is the tilted-plane, linear-ramp scene
+    rendered at that pose (ICP and photometric residuals vanish there); the prior is centred on x0."""
+    from oracle import imu as imu_mod
+    from oracle import lie
+    from oracle import track
+    from synth.configs import Camera, initial_prior, quat_from_matrix
+    f = 130.0 * W / 160.0
+    cx, cy = W / 2.0, H / 2.0
+    rng = np.random.default_rng(seed)
+    p = track.default_params(levels=2, iters=(6, 6), mode="rgbdi")
+    x0 = {"r": np.zeros(3), "q": np.array([1.0, 0.0, 0.0, 0.0]), "v": np.array([0.9, -0.4, 0.6]),
+          "bg": np.zeros(3), "ba": np.zeros(3)}
+    q_IW = quat_from_matrix(lie.exp_so3(np.array([0.3, -0.2, 0.0])))
+    w = rng.normal(size=3)
+    w *= np.deg2rad(2.0) / 0.015 / np.linalg.norm(w)
+    R_IW = lie.quat_to_rot(q_IW)
+    fsp = R_IW.T @ np.array([0.0, 0.0, p["gravity"]]) + rng.normal(size=3) * 0.5
+    imu = {"t": np.array([0.0, 0.005, 0.010]), "gyro": np.tile(w, (3, 1)), "acc": np.tile(fsp, (3, 1))}
+    pre = imu_mod.preintegrate(imu["t"], imu["gyro"], imu["acc"], 0.0, 0.015, x0["bg"], x0["ba"],
+                               p["sigma_g"], p["sigma_a"])
+    x1 = imu_mod.predict_state(x0, q_IW, pre, p)
+    R1 = lie.quat_to_rot(x1["q"])
+    n = np.array([0.3, -0.4, -1.0])
+    n /= np.linalg.norm(n)
+    sc = Scene(planes=[(n, -2.0)], spheres=[], seed=0)
+    z0, _ = render(sc, np.eye(3), np.zeros(3), W, H, f, f, cx, cy)
+    z1, _ = render(sc, R1, x1["r"], W, H, f, f, cx, cy)
+    z0, z1 = z0.numpy(), z1.numpy()
+    jj, ii = np.mgrid[0:H, 0:W].astype(np.float64)
+    a, b, c = 0.75, 0.5, 10.0
+    I0 = (a * ii + b * jj + c).astype(np.float32)
+    z = z1.astype(np.float64)
+    P = np.stack([(ii - cx) * z / f, (jj - cy) * z / f, z], -1)
+    Q = P @ R1.T + x1["r"]
+    I1 = (a * (f * Q[..., 0] / Q[..., 2] + cx) + b * (f * Q[..., 1] / Q[..., 2] + cy) + c).astype(np.float32)
+    return {"z0": z0, "I0": I0, "z1": z1, "I1": I1, "camera": Camera(W, H, f, f, cx, cy), "imu": imu,
+            "x0": x0, "x1": x1, "q_IW": q_IW, "prior": initial_prior(x0, q_IW), "params": p}

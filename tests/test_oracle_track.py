@@ -140,47 +140,13 @@ def test_joint_mode_converges_to_the_common_zero_of_all_residuals():
     the prior is centred on x0 with zero gradient (Section IV-E).  All residuals of eq. (6) vanish at one
     state, so the joint Gauss-Newton started 1 cm / 1 degree away (x1) must return to it: a sign or
     assembly error in any term of the joint system moves the fixed point or stops the convergence."""
-    from oracle import imu as imu_mod
-    from synth.configs import Camera, initial_prior, quat_from_matrix
-    from synth.scene import Scene, render
-    W, H = 160, 120
-    f = 130.0
-    cx, cy = W / 2.0, H / 2.0
-    rng = np.random.default_rng(11)
-    p = track.default_params(levels=2, iters=(6, 6), mode="rgbdi")
-    x0 = {"r": np.zeros(3), "q": np.array([1.0, 0.0, 0.0, 0.0]), "v": np.array([0.9, -0.4, 0.6]),
-          "bg": np.zeros(3), "ba": np.zeros(3)}
-    q_IW = quat_from_matrix(lie.exp_so3(np.array([0.3, -0.2, 0.0])))
-    # constant body rate and specific force over 15 ms, sampled at 200 Hz
-    w = rng.normal(size=3)
-    w *= np.deg2rad(2.0) / 0.015 / np.linalg.norm(w)
-    R_IW = lie.quat_to_rot(q_IW)
-    fsp = R_IW.T @ np.array([0.0, 0.0, p["gravity"]]) + rng.normal(size=3) * 0.5  # about hover, world -> body
-    stamps = np.array([0.0, 0.005, 0.010])
-    imu = {"t": stamps, "gyro": np.tile(w, (3, 1)), "acc": np.tile(fsp, (3, 1))}
-    pre = imu_mod.preintegrate(imu["t"], imu["gyro"], imu["acc"], 0.0, 0.015, x0["bg"], x0["ba"],
-                               p["sigma_g"], p["sigma_a"])
-    x1 = imu_mod.predict_state(x0, q_IW, pre, p)
-    R1 = lie.quat_to_rot(x1["q"])
-    # plane + ramp scene (reference at x0 = identity, current frame at the predicted x1)
-    n = np.array([0.3, -0.4, -1.0])
-    n /= np.linalg.norm(n)
-    sc = Scene(planes=[(n, -2.0)], spheres=[], seed=0)
-    z0, _ = render(sc, np.eye(3), np.zeros(3), W, H, f, f, cx, cy)
-    z1, _ = render(sc, R1, x1["r"], W, H, f, f, cx, cy)
-    z0, z1 = z0.numpy(), z1.numpy()
-    jj, ii = np.mgrid[0:H, 0:W].astype(np.float64)
-    a, b, c = 0.75, 0.5, 10.0
-    I0 = (a * ii + b * jj + c).astype(np.float32)
-    z = z1.astype(np.float64)
-    P = np.stack([(ii - cx) * z / f, (jj - cy) * z / f, z], -1)
-    Q = P @ R1.T + x1["r"]
-    I1 = (a * (f * Q[..., 0] / Q[..., 2] + cx) + b * (f * Q[..., 1] / Q[..., 2] + cy) + c).astype(np.float32)
-    cam = Camera(W, H, f, f, cx, cy)
+    from tests.oracle_cases import imu_plane_pair
+    d = imu_plane_pair()
+    x0, x1, q_IW, p = d["x0"], d["x1"], d["q_IW"], d["params"]
     start = lie.state_boxplus(x1, np.r_[0.01 * np.array([0.6, -0.8, 0.0]), np.deg2rad(1.0) * np.array([0.0, 0.6, 0.8]),
                                         np.zeros(9)])
-    out = track.track_frame(z1, I1, z0, I0, np.eye(4), cam, imu, 0.0, 0.015, x0, q_IW, initial_prior(x0, q_IW), p,
-                            x1_init=start)
+    out = track.track_frame(d["z1"], d["I1"], d["z0"], d["I0"], np.eye(4), d["camera"], d["imu"], 0.0, 0.015, x0,
+                            q_IW, d["prior"], p, x1_init=start)
     assert out["status"] == "ok" and out["health"] == []
     assert np.linalg.norm(out["x1"]["r"] - x1["r"]) < 1e-7
     assert np.linalg.norm(lie.quat_boxminus(out["x1"]["q"], x1["q"])) < 1e-7
