@@ -16,7 +16,7 @@ from ._abi import (CH_GX, CH_GY, CH_I, CH_NX, CH_NY, CH_NZ, CH_VX, CH_VY, CH_VZ,
                    HEALTH_IMU_ONLY, HEALTH_NONFINITE, HEALTH_SINGULAR, JAC_BF16, JAC_FP16, JAC_FP32, JAC_FP32_MFMA, MODE_GYRO, MODE_RGBD,
                    MODE_RGBDI, PYR_CURRENT, PYR_MODEL)
 
-__all__ = ["DslamError", "Context", "Session", "Map", "Deform", "Batch", "Server", "frame_input", "preintegrate_imu", "solve_step", "track_params", "imu_params",
+__all__ = ["DslamError", "Context", "Session", "Map", "Deform", "Batch", "Server", "check_images", "frame_input", "preintegrate_imu", "solve_step", "track_params", "imu_params",
            "camera", "state_struct", "state_dict", "prior_struct", "prior_dict", "lib"]
 
 MODES = {"rgbdi": MODE_RGBDI, "rgbd": MODE_RGBD, "gyro": MODE_GYRO}
@@ -111,6 +111,30 @@ def imu_samples(stamps, gyro, acc):
 def _dptr(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def check_images(depth, intensity, size=None, what="frame"):
+    """Device images as the C ABI takes them: depth float32 (metres) and intensity uint8 (grey levels), both
+    H x W, C-contiguous CUDA tensors whose row pitch is their width; size = (width, height) when the camera
+    is known.  The library gets plain pointers and cannot check a buffer's type or extent, so a mismatch
+    raises ValueError here, before anything is enqueued."""
+    import torch
+    for name, t, dt in (("depth", depth, torch.float32), ("intensity", intensity, torch.uint8)):
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{what} {name}: expected a torch tensor, got {type(t).__name__}")
+        if t.dtype != dt:
+            raise ValueError(f"{what} {name}: dtype {t.dtype}, expected {dt}")
+        if t.dim() != 2:
+            raise ValueError(f"{what} {name}: {t.dim()}-d tensor, expected H x W")
+        if size is not None and tuple(t.shape) != (int(size[1]), int(size[0])):
+            raise ValueError(f"{what} {name}: shape {tuple(t.shape)}, expected {(int(size[1]), int(size[0]))}")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} {name}: not contiguous")
+    if tuple(depth.shape) != tuple(intensity.shape):
+        raise ValueError(f"{what}: depth {tuple(depth.shape)} and intensity {tuple(intensity.shape)} differ")
+    for name, t in (("depth", depth), ("intensity", intensity)):
+        if not t.is_cuda:
+            raise ValueError(f"{what} {name}: not a CUDA (device) tensor")
 
 
 def _stream_ptr(stream):
@@ -247,7 +271,7 @@ class Session:
             pass
 
     def build_pyramid(self, which, depth, intensity, T_W_ref=None, stream=None):
-        assert depth.is_cuda and intensity.is_cuda and depth.is_contiguous() and intensity.is_contiguous()
+        check_images(depth, intensity, (self.cam.width, self.cam.height), "pyramid")
         T = None
         if T_W_ref is not None:
             T, Tp = _dptr(np.asarray(T_W_ref).ravel())
@@ -281,14 +305,14 @@ class Session:
         model_intensity, T_WM, imu, t0, t1) as for Batch.track; model_depth None tracks against the
         session's MODEL pyramid, otherwise both pyramids are built in the launch that initialises the
         frame."""
-        fi, keep = frame_input(frame)
+        fi, keep = frame_input(frame, (self.cam.width, self.cam.height))
         _check(lib().dslam_track_frame(self.handle, C.byref(fi), C.byref(out) if out is not None else None,
                                        _stream_ptr(stream)), "dslam_track_frame")
         self._keep_input = keep
 
     def track_frame_sync(self, frame: dict, stream=None) -> dict:
         """dslam_track_frame_sync: enqueue the frame, wait for it and return its result."""
-        fi, keep = frame_input(frame)
+        fi, keep = frame_input(frame, (self.cam.width, self.cam.height))
         r = _abi.TrackResult()
         _check(lib().dslam_track_frame_sync(self.handle, C.byref(fi), C.byref(r), _stream_ptr(stream)),
                "dslam_track_frame_sync")
@@ -354,17 +378,17 @@ class Session:
                                              int(frame_index)), "dslam_session_set_state")
 
 
-def frame_input(f: dict):
+def frame_input(f: dict, size=None):
     """FrameInput for dict(depth, intensity, model_depth, model_intensity, T_WM, imu, t0, t1) (device images
-    contiguous); returns (struct, keep-alive) -- the IMU array must outlive the struct's use."""
+    as check_images takes them, of the session's camera size (width, height) when given); returns (struct,
+    keep-alive) -- the IMU array must outlive the struct's use."""
     d, im, md = f["depth"], f["intensity"], f.get("model_depth")
-    for t in (d, im):
-        assert t.is_cuda and t.is_contiguous()
+    check_images(d, im, size, "frame")
     fi = _abi.FrameInput()
     fi.depth, fi.intensity, fi.pitch = d.data_ptr(), im.data_ptr(), int(d.shape[1])
     if md is not None:  # else: track against the session's MODEL pyramid
         mi = f["model_intensity"]
-        assert md.is_cuda and md.is_contiguous() and mi.is_cuda and mi.is_contiguous()
+        check_images(md, mi, size, "model view")
         fi.model_depth, fi.model_intensity, fi.model_pitch = md.data_ptr(), mi.data_ptr(), int(md.shape[1])
         fi.T_WM[:] = [float(v) for v in np.asarray(f["T_WM"], dtype=np.float64).ravel()]
     arr = None
@@ -415,7 +439,7 @@ class Map:
         _check(lib().dslam_map_predict(self.handle, session.handle, Tp, _stream_ptr(stream)), "dslam_map_predict")
 
     def render(self, T_WM, depth, intensity, stream=None):
-        assert depth.is_cuda and intensity.is_cuda and depth.is_contiguous() and intensity.is_contiguous()
+        check_images(depth, intensity, (self.cam.width, self.cam.height), "render target")
         T, Tp = _dptr(np.asarray(T_WM).ravel())
         _check(lib().dslam_map_render(self.handle, Tp, C.c_void_p(depth.data_ptr()), C.c_void_p(intensity.data_ptr()),
                                       _stream_ptr(stream)), "dslam_map_render")
@@ -516,8 +540,10 @@ class Batch:
         handles = (C.c_void_p * n)(*[s.handle for s in sessions])
         inputs = (_abi.FrameInput * n)()
         keep = []
+        if len(frames) != n:
+            raise ValueError(f"{n} sessions but {len(frames)} frames")
         for i, f in enumerate(frames):
-            inputs[i], k = frame_input(f)
+            inputs[i], k = frame_input(f, (sessions[i].cam.width, sessions[i].cam.height))
             keep.append(k)
         _check(lib().dslam_batch_track(self.handle, n, handles, inputs, _stream_ptr(stream)), "dslam_batch_track")
         self._keep = (keep, frames)
@@ -550,8 +576,10 @@ def batch_track_noalloc(sessions, frames, stream=None) -> list:
     n = len(sessions)
     hs = (C.c_void_p * n)(*[s.handle for s in sessions])
     fis, keep = [], []
-    for f in frames:
-        fi, k = frame_input(f)
+    if len(frames) != n:
+        raise ValueError(f"{n} sessions but {len(frames)} frames")
+    for s, f in zip(sessions, frames):
+        fi, k = frame_input(f, (s.cam.width, s.cam.height))
         fis.append(fi)
         keep.append(k)
     arr = (_abi.FrameInput * n)(*fis)

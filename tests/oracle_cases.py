@@ -48,7 +48,10 @@ def imu_plane_pair(W=160, H=120, seed=11):
     """A frame pair whose every residual of the joint cost vanishes at one known state: the IMU reads a
     constant body rate (2 deg over 15 ms) and specific force (about hover), for which the zero-order hold
     is exact, so the oracle's IMU prediction is the true x1; frame 1 is the tilted-plane, linear-ramp scene
-    rendered at that pose (ICP and photometric residuals vanish there); the prior is centred on x0."""
+    rendered at that pose (ICP and photometric residuals vanish there); the prior is centred on x0.  The
+    intensities are float32; I0_u8 / I1_u8 are them rounded to the grey levels the device boundary takes
+    (exact no longer: the rounding moves the solution by about 3e-5 m in x1's position and 2e-4 rad in the
+    gravity direction)."""
     from oracle import imu as imu_mod
     from oracle import lie
     from oracle import track
@@ -82,5 +85,7 @@ def imu_plane_pair(W=160, H=120, seed=11):
     P = np.stack([(ii - cx) * z / f, (jj - cy) * z / f, z], -1)
     Q = P @ R1.T + x1["r"]
     I1 = (a * (f * Q[..., 0] / Q[..., 2] + cx) + b * (f * Q[..., 1] / Q[..., 2] + cy) + c).astype(np.float32)
-    return {"z0": z0, "I0": I0, "z1": z1, "I1": I1, "camera": Camera(W, H, f, f, cx, cy), "imu": imu,
+    u8 = lambda a: np.clip(np.rint(a), 0, 255).astype(np.uint8)  # noqa: E731
+    return {"z0": z0, "I0": I0, "z1": z1, "I1": I1, "I0_u8": u8(I0), "I1_u8": u8(I1),
+            "camera": Camera(W, H, f, f, cx, cy), "imu": imu,
             "x0": x0, "x1": x1, "q_IW": q_IW, "prior": initial_prior(x0, q_IW), "params": p}

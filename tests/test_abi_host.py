@@ -143,3 +143,22 @@ def test_host_solve_step_singular_without_information():
     with pytest.raises(P.DslamError) as ei:
         P.solve_step(np.zeros(58), np.eye(4), None, P.imu_params(), tp, None, x, x, np.array([1.0, 0, 0, 0]))
     assert ei.value.code == 3
+
+
+def test_binding_rejects_images_the_library_would_misread():
+    """The C ABI takes plain device pointers (depth float32 metres, intensity uint8 grey levels, H x W with
+    pitch = width); the binding refuses any other tensor before it reaches the library."""
+    import torch
+    z = torch.zeros((120, 160), dtype=torch.float32)
+    i = torch.zeros((120, 160), dtype=torch.uint8)
+    cases = [((z, i.float()), "dtype"), ((z.double(), i), "dtype"), ((z[:, :80], i), "contiguous"),
+             ((z, i[:60]), "differ"), ((z.reshape(1, 120, 160), i), "H x W"), ((z.numpy(), i), "torch tensor")]
+    for (a, b), what in cases:
+        with pytest.raises(ValueError, match=what):
+            P.check_images(a, b)
+    with pytest.raises(ValueError, match="shape"):
+        P.check_images(z, i, (200, 152))
+    with pytest.raises(ValueError, match="CUDA"):  # right type and shape, host memory
+        P.check_images(z, i, (160, 120))
+    with pytest.raises(ValueError, match="dtype"):
+        P.frame_input({"depth": z, "intensity": i.float(), "imu": None}, (160, 120))

@@ -180,34 +180,39 @@ def test_track_frame_pair_matches_oracle(mode):
         assert rel_fro(Hg, Ho) < 1e-4
 
 
-def test_track_joint_mode_reaches_the_exact_solution():
+def test_track_joint_mode_reaches_the_common_zero():
     """The frame pair of the oracle's joint-mode pin, whose visual, IMU and prior residuals all vanish at
     one known state (constant IMU readings, a plane + ramp scene rendered at the predicted pose, a prior
-    centred on the frame start).  Both sides start from a frame start 1 cm / 1 degree off that state; both
-    must reach it, and agree with each other to the parity bar."""
+    centred on the frame start), with its intensities rounded to grey levels (which moves the solution by
+    about 3e-5 m and 2e-4 rad of gravity direction).  Both sides start from a frame start 1 cm / 1 degree
+    off the prior's centre; both must reach the state to within that rounding, and agree with each other
+    to the parity bar."""
     from tests.oracle_cases import imu_plane_pair
-    print("joint mode exact solution", flush=True)
+    print("joint mode common zero", flush=True)
     d = imu_plane_pair()
     x0, x1, q_IW, p = d["x0"], d["x1"], d["q_IW"], d["params"]
     start = lie.state_boxplus(x0, np.r_[0.01 * np.array([0.6, -0.8, 0.0]),
                                         np.deg2rad(1.0) * np.array([0.0, 0.6, 0.8]), np.zeros(9)])
-    o = track.track_frame(d["z1"], d["I1"], d["z0"], d["I0"], np.eye(4), d["camera"], d["imu"], 0.0, 0.015, start,
-                          q_IW, d["prior"], p)
+    o = track.track_frame(d["z1"], d["I1_u8"], d["z0"], d["I0_u8"], np.eye(4), d["camera"], d["imu"], 0.0, 0.015,
+                          start, q_IW, d["prior"], p)
     with session(160, 120, 2, [6, 6], x0=start, q_IW=q_IW, prior=d["prior"]) as s:
-        s.set_model(cuda(d["z0"]), cuda(d["I0"]), np.eye(4))
-        s.track_frame(cuda(d["z1"]), cuda(d["I1"]), d["imu"], 0.0, 0.015)
+        s.set_model(cuda(d["z0"]), cuda(d["I0_u8"]), np.eye(4))
+        s.track_frame(cuda(d["z1"]), cuda(d["I1_u8"]), d["imu"], 0.0, 0.015)
         g = s.result()
     assert g["status"] == 0 and o["status"] == "ok" and g["health"] == 0
     for name, r in (("oracle", o), ("hip", g)):
         dr, da = pose_err(r["x1"], x1)
         dr0, da0 = pose_err(r["x0"], x0)
         dq = np.linalg.norm(lie.quat_boxminus(r["q_IW"], q_IW))
-        print(f"  {name}: x1 |dr| {dr:.2e} |da| {da:.2e}  x0 |dr| {dr0:.2e} |da| {da0:.2e}  q_IW {dq:.2e}",
-              flush=True)
-        assert dr < 1e-6 and da < 1e-6 and dr0 < 1e-6 and da0 < 1e-6 and dq < 1e-6, name
-        assert np.abs(r["x1"]["v"] - x1["v"]).max() < 1e-5, name
+        dv = np.abs(r["x1"]["v"] - x1["v"]).max()
+        print(f"  {name}: x1 |dr| {dr:.2e} |da| {da:.2e} |dv| {dv:.2e}  x0 |dr| {dr0:.2e} |da| {da0:.2e}  "
+              f"q_IW {dq:.2e}", flush=True)
+        assert dr < 1e-4 and da < 1e-5 and dr0 < 1e-6 and da0 < 1e-6 and dq < 5e-4 and dv < 5e-3, name
     dr, da = pose_err(g["x1"], o["x1"])
-    assert dr < 1e-6 and da < 1e-6, (dr, da)
+    dr0, da0 = pose_err(g["x0"], o["x0"])
+    assert dr < 1e-6 and da < 1e-6 and dr0 < 1e-6 and da0 < 1e-6, (dr, da, dr0, da0)
+    assert np.linalg.norm(lie.quat_boxminus(g["q_IW"], o["q_IW"])) < 1e-6
+    assert np.abs(g["x1"]["v"] - o["x1"]["v"]).max() < 1e-5
 
 
 def test_track_sequence_full_resolution():
