@@ -220,30 +220,61 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   __shared__ dslam_prior marg;
   __shared__ dslam_prior prior;
   __shared__ dslam_preint pre;
-  __shared__ int skip;
   __shared__ double red[16 * 64];
   Par par{(int)threadIdx.x, SOLVE_THREADS};
-  // stage the states, the prior and the preintegrated measurement in shared
-  // memory (one coalesced pass) so the serial parts never wait on global loads
+  // the session's status words, read by every thread (uniform)
+  const int status0 = sd->status, lost0 = sd->result.tracking_lost, health0 = sd->result.health;
+  // stage the prior, the preintegrated measurement, L^-1 and the states in
+  // shared memory so the serial parts never wait on global loads: one flat
+  // index over the six regions (636 doubles, at most two per thread), every
+  // load issued before the first store, so the whole copy is one memory
+  // round trip for every wave
   {
-    auto copy = [](const void* from, void* to, int bytes) {
-      const double* src = reinterpret_cast<const double*>(from);
-      double* dst = reinterpret_cast<double*>(to);
-      for (int i = threadIdx.x; i < bytes / 8; i += SOLVE_THREADS) dst[i] = src[i];
+    constexpr int NP = sizeof(dslam_prior) / 8, NQ = sizeof(dslam_preint) / 8, NL = 81, NS = 16, NG = 4;
+    constexpr int NT = NP + NQ + NL + 2 * NS + NG;
+    static_assert(NT <= 2 * SOLVE_THREADS, "two staged doubles per thread");
+    const double* s0 = reinterpret_cast<const double*>(inertial ? &sd->prior_frame : &sd->prior);
+    const double* s1 = reinterpret_cast<const double*>(&sd->pre);
+    const double* s2 = sd->Linv;
+    const double* s3 = reinterpret_cast<const double*>(inertial ? &sd->x0_frame : &sd->x0);
+    const double* s4 = reinterpret_cast<const double*>(inertial ? &sd->x1_pred : &sd->x1);
+    const double* s5 = inertial ? sd->qIW_frame : sd->qIW;
+    double* d0 = reinterpret_cast<double*>(&prior);
+    double* d1 = reinterpret_cast<double*>(&pre);
+    double* d2 = w.Linv;
+    double* d3 = reinterpret_cast<double*>(&x0);
+    double* d4 = reinterpret_cast<double*>(&x1);
+    double* d5 = qIW;
+    auto locate = [&](int i, const double*& src, double*& dst) {
+      if (i < NP) { src = s0 + i; dst = d0 + i; return; }
+      i -= NP;
+      if (i < NQ) { src = s1 + i; dst = d1 + i; return; }
+      i -= NQ;
+      if (i < NL) { src = s2 + i; dst = d2 + i; return; }
+      i -= NL;
+      if (i < NS) { src = s3 + i; dst = d3 + i; return; }
+      i -= NS;
+      if (i < NS) { src = s4 + i; dst = d4 + i; return; }
+      i -= NS;
+      src = s5 + i;
+      dst = d5 + i;
     };
-    copy(inertial ? &sd->prior_frame : &sd->prior, &prior, sizeof(dslam_prior));
-    copy(&sd->pre, &pre, sizeof(dslam_preint));
-    copy(sd->Linv, w.Linv, sizeof(w.Linv));
-    copy(inertial ? &sd->x0_frame : &sd->x0, &x0, sizeof(dslam_frame_state));
-    copy(inertial ? &sd->x1_pred : &sd->x1, &x1, sizeof(dslam_frame_state));
-    copy(inertial ? sd->qIW_frame : sd->qIW, qIW, sizeof(qIW));
-    SERIAL {
-      skip = sd->status != DSLAM_OK;
-      if (inertial)  // 2: nothing to do (the frame was tracked, or the fallback is off)
-        skip = (!skip && sp.imu_fallback && sp.mode == DSLAM_MODE_RGBDI && sd->result.tracking_lost &&
-                !(sd->result.health & DSLAM_HEALTH_SINGULAR)) ? 0 : 2;
-    }
+    const int i0 = (int)threadIdx.x, i1 = i0 + SOLVE_THREADS;
+    const double *a0, *a1 = nullptr;
+    double *b0, *b1 = nullptr;
+    locate(i0, a0, b0);
+    if (i1 < NT) locate(i1, a1, b1);
+    const double v0 = *a0;
+    const double v1 = i1 < NT ? *a1 : 0.0;
+    *b0 = v0;
+    if (i1 < NT) *b1 = v1;
   }
+  // 2: nothing to do (an inertial re-estimate of a frame that was tracked, or
+  // with the fallback off)
+  int skip = status0 != DSLAM_OK;
+  if (inertial)
+    skip = (!skip && sp.imu_fallback && sp.mode == DSLAM_MODE_RGBDI && lost0 &&
+            !(health0 & DSLAM_HEALTH_SINGULAR)) ? 0 : 2;
   DSLAM_SYNC();
   if (skip == 2) return;
   if (skip) {
