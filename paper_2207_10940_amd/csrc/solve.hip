@@ -300,7 +300,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   //   stage 0: first half of the reduction (waves 0-3); IMU rotations, operand
   //            copies and bias-corrected preintegration (waves 4-6); system
   //            matrix start (waves 4, 5); the visual lift (wave 7: sources on
-  //            lanes 0-8, then all entries)
+  //            lane 0, then all entries)
   //   stage 1: second half of the reduction (waves 0-3); IMU residual (wave
   //            7); prior offset and the IMU operands of the stage-0 rotations
   //            (waves 4-6)
@@ -313,7 +313,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   if (full) imu_stage0(par, 4, x0, x1, qIW, pre, &w.ic, &w.is);
   if (wave == 4 || wave == 5) init_system_H(Par{lane + (wave == 5 ? 64 : 0), 128}, &w, sp, &pre, &prior);
   if (wave == 7) {
-    lift_sources(lane, &w, sp, x0, x1);
+    lift_sources(lane, &w, sp, q2R(x0.q), x0, x1);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     lift_fill(lane, 64, &w);
   }

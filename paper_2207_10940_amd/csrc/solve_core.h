@@ -358,38 +358,65 @@ DX void visual_front(SolveWork* w, const double* raw, const SolveParams& sp, con
 // visual_front split for the device workgroup, in three parts that run on
 // different wavefronts and stages.  The lift operators depend on the states
 // only, so they are built before the visual sums are reduced:
-//   lift_sources: lanes 0..8 write the three 3x3 sources of the lift entries
-//     (R_WM, R0 and R0 hat(R0^T (r1 - r0))) to shared memory (indexed by entry
-//     below; private arrays indexed at run time would live in scratch memory);
+//   lift_sources: lane 0 writes the three 3x3 sources of the lift entries
+//     (R_WM, R0 and R0 hat(R0^T (r1 - r0)), R0 = x0's rotation, passed in)
+//     to shared memory (indexed by entry below; private arrays indexed at run
+//     time would live in scratch memory);
 //   lift_fill: lanes 0..nl-1 fill the 144 entries of Li and Lr from them;
 //   unpack_sums: lanes 0..57 unpack the 58 sums.
-DX void lift_sources(int lane, SolveWork* w, const SolveParams& sp, const dslam_frame_state& x0,
+DX void lift_sources(int lane, SolveWork* w, const SolveParams& sp, const M3& R0, const dslam_frame_state& x0,
                      const dslam_frame_state& x1) {
-  const M3 RWM = load33(sp.R_WM), R0 = q2R(x0.q);
+  const M3 RWM = load33(sp.R_WM);
   const V3 tb = tr(R0) * (load3(x1.r) - load3(x0.r));
   const M3 R0Tb = R0 * hat(tb);
+  // one lane stores all 27 (constant offsets; a store per lane would make
+  // the lanes take nine divergent branches in turn)
   double* src = w->lift_src;
+  if (lane == 0) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k)
-    if (lane == k) {
+    for (int k = 0; k < 9; ++k) {
       src[k] = RWM.m[k];
       src[9 + k] = R0.m[k];
       src[18 + k] = R0Tb.m[k];
     }
+  }
 }
 
+// Every entry of Li and Lr is zero, a source entry or its negation; a lane
+// first finds its entries' source index and sign (selects, no branches), then
+// issues all of its reads, then writes.
 DX void lift_fill(int lane, int nl, SolveWork* w) {
   const double* src = w->lift_src;
-  for (int idx = lane; idx < 144; idx += nl) {
-    const int m = idx / 72, r = (idx % 72) / 6, c = idx % 6;  // m 0: Li (ICP), 1: Lr (photometric)
-    const double* R = src + 9 * m;
-    double v = 0.0;
-    if (r >= 6 && r < 9 && c < 3) v = R[3 * (r - 6) + c];
-    else if (r >= 9 && c >= 3) v = R[3 * (r - 9) + c - 3];
-    else if (m == 1 && r < 3 && c < 3) v = -src[9 + 3 * r + c];
-    else if (m == 1 && r >= 3 && r < 6 && c >= 3) v = -src[9 + 3 * (r - 3) + c - 3];
-    else if (m == 1 && r >= 3 && r < 6 && c < 3) v = -src[18 + 3 * (r - 3) + c];
-    (m == 0 ? w->Li : w->Lr)[6 * r + c] = v;
+  constexpr int NE = 144, U = 3;
+  for (int base = lane; base < NE; base += U * nl) {
+    int at[U];
+    bool neg[U];
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * nl;
+      const int m = (idx % NE) / 72, r = (idx % 72) / 6, c = idx % 6;  // m 0: Li (ICP), 1: Lr (photometric)
+      int k = -1;
+      k = (r >= 6 && r < 9 && c < 3) ? 9 * m + 3 * (r - 6) + c : k;
+      k = (r >= 9 && c >= 3) ? 9 * m + 3 * (r - 9) + c - 3 : k;
+      const bool n1 = m == 1 && r < 3 && c < 3, n2 = m == 1 && r >= 3 && r < 6 && c >= 3,
+                 n3 = m == 1 && r >= 3 && r < 6 && c < 3;
+      k = n1 ? 9 + 3 * r + c : k;
+      k = n2 ? 9 + 3 * (r - 3) + c - 3 : k;
+      k = n3 ? 18 + 3 * (r - 3) + c : k;
+      at[u] = k;
+      neg[u] = n1 || n2 || n3;
+      x[u] = src[k >= 0 ? k : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * nl;
+      if (idx < NE) {
+        const int m = idx / 72, r = (idx % 72) / 6, c = idx % 6;
+        const double v = at[u] < 0 ? 0.0 : (neg[u] ? -x[u] : x[u]);
+        (m == 0 ? w->Li : w->Lr)[6 * r + c] = v;
+      }
+    }
   }
 }
 
