@@ -80,3 +80,44 @@ def test_precision_track_pair_recovers_pose(jac, mode):
     print(f"track pair {mode} {jac}: vs oracle {dr:.2e} m {da:.2e} rad; vs fp32 {dr32:.2e} m {da32:.2e} rad",
           flush=True)
     assert dr < 1e-4 and da < 1e-4, (dr, da)
+
+
+@pytest.mark.parametrize("nearest,within_bound", [(0.27, True), (0.06, False)])
+def test_fp16_rows_near_range(nearest, within_bound):
+    """FP16 rows are scaled for depths of at least 0.25 m.  The frame pair's scene and poses shrunk so
+    that the nearest depth is 0.27 m stays within the FP16 bound of the oracle; shrunk to 0.06 m, the
+    nearest pixels' entries saturate at the FP16 maximum instead of overflowing: the sums stay finite
+    (the error is then the saturation's, not bounded) and the masks and counts stay exact."""
+    import torch
+    W, H, levels = 160, 120, 2
+    d, x0, x1, T_WM = _linearize_case(W, H, 1001)
+    z = d["depth"].numpy()
+    scale = nearest / float(z[z > 0].min())
+    depth, mdepth = z * scale, d["model_depth"].numpy() * scale
+    x0 = dict(x0, r=x0["r"] * scale)
+    x1 = dict(x1, r=x1["r"] * scale)
+    T_WM = T_WM.copy()
+    T_WM[:3, 3] *= scale
+    valid = depth[depth > 0]
+    print(f"fp16 near range: nearest depth {valid.min():.3f} m", flush=True)
+    cam = d["camera"]
+    params = track.default_params(levels=levels, iters=[1] * levels, mode="rgbdi")
+    cur, ref = track.build_pyramids(depth, d["intensity"].numpy(), mdepth, d["model_intensity"].numpy(), cam,
+                                    levels)
+    Ra, ta, Rb, tb = track.fp32_transforms(T_WM, x0, x1)
+    with session(W, H, levels, [1] * levels, jac="fp16") as s:
+        s.set_model(cuda(mdepth.astype(np.float32)), cuda(d["model_intensity"].numpy()), T_WM)
+        s.build_pyramid(P.PYR_CURRENT, cuda(depth.astype(np.float32)), cuda(d["intensity"].numpy()))
+        for l in range(levels):
+            vis = track.linearise_visual(cur[l], ref[l], T_WM, x0, x1, Ra, ta, Rb, tb, params)
+            mask = torch.zeros((H >> l, W >> l), dtype=torch.uint8, device="cuda")
+            g = s.linearize(l, Ra, ta, Rb, tb, x0, x1, mask=mask)
+            m = mask.cpu().numpy()
+            assert np.array_equal((m & 1) != 0, vis["mask_icp"]) and np.array_equal((m & 2) != 0, vis["mask_rgb"])
+            assert g["n_icp"] == vis["n_icp"] and g["n_rgb"] == vis["n_rgb"]
+            for term in ("icp", "rgb"):
+                assert np.all(np.isfinite(g["H_" + term])) and np.all(np.isfinite(g["b_" + term]))
+                eH = rel_fro(g["H_" + term], vis["H_" + term])
+                print(f"  level {l} {term}: JtJ vs oracle {eH:.2e}", flush=True)
+                if within_bound:
+                    assert eH < BOUND["fp16"], (l, term, eH)
