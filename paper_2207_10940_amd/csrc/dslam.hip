@@ -1035,7 +1035,7 @@ dslam_status batch_stage(const BatchMem& m, int32_t n, dslam_session* const* ses
   plan->tp = s0->tp;
   plan->fallback = 0;
   for (int k = 0; k < n; ++k) plan->fallback |= m.h_solve[k].sp.imu_fallback;
-  plan->pyr_grid = grid([&](const dslam_session* s) { return 2 * PyrTileStd::tiles(s->cam.width, s->cam.height); });
+  plan->pyr_grid = grid([&](const dslam_session* s) { return 2 * PyrTileBatch::tiles(s->cam.width, s->cam.height); });
   for (int l = 0; l < s0->levels; ++l) {
     int max_ppt = 1;
     uint64_t px = 0;

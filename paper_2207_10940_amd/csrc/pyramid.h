@@ -25,14 +25,16 @@
 
 namespace dslam {
 
-// Tile shapes: the standalone and batched pyramid launches use 64 x 8 tiles
-// (two level-0 pixels per thread of 256); the launch shared with the frame
-// initialisation uses 64 x 16 tiles (its workgroups are few and large).  Rows
-// of 64 pixels keep the 16-bit planes' stores in whole 128-byte lines.
+// Tile shapes: the standalone pyramid launch uses 64 x 8 tiles (two level-0
+// pixels per thread of 256); the launch shared with the frame initialisation
+// and the batched launch use 64 x 16 tiles with 512 threads (less margin
+// recomputed per tile).  Rows of 64 pixels keep the 16-bit planes' stores in
+// whole 128-byte lines.
 template <int TW, int TH>
 struct PyrTile {
   static_assert((TW >> (DSLAM_MAX_LEVELS - 1)) >= 1 && (TH >> (DSLAM_MAX_LEVELS - 1)) >= 1,
                 "tile too small for the deepest pyramid");
+  static constexpr int W = TW, H = TH;
   // sides of level l's region in LDS when the coarsest level is c
   __host__ __device__ static constexpr int ew(int l, int c) { return (TW >> l) + 2 * (1 << (c - l)); }
   __host__ __device__ static constexpr int eh(int l, int c) { return (TH >> l) + 2 * (1 << (c - l)); }
@@ -50,6 +52,9 @@ struct PyrTile {
 };
 using PyrTileStd = PyrTile<64, 8>;
 using PyrTileBig = PyrTile<64, 16>;
+// the batched pyramids' tile and workgroup
+using PyrTileBatch = PyrTileBig;
+enum { PYR_BATCH_THREADS = 512 };
 
 // The level-0 images of one pyramid (device, row pitch in elements).
 struct PyrSrc {

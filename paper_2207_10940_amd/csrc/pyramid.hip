@@ -18,22 +18,25 @@ __global__ __launch_bounds__(256) void pyramid_kernel(PyrArgs a) {
 }
 
 // Batched: both pyramids of every session of the batch in one launch, per
-// session 2 x PyrTileStd::tiles workgroups (current frame first), located
+// session 2 x PyrTileBatch::tiles workgroups (current frame first), located
 // through g.
-__global__ __launch_bounds__(256) void pyramid_batch_kernel(const SlotVis* slots, int levels, BatchGrid g) {
+__global__ __launch_bounds__(PYR_BATCH_THREADS) void pyramid_batch_kernel(const SlotVis* slots, int levels,
+                                                                          BatchGrid g) {
   int slot, b;
   batch_locate(g, blockIdx.x, &slot, &b);
   const SlotVis* sv = slots + slot;
-  const int per = PyrTileStd::tiles(sv->cur[0].W, sv->cur[0].H);
+  const int per = PyrTileBatch::tiles(sv->cur[0].W, sv->cur[0].H);
   const int which = b >= per ? 1 : 0;
   const PyrSrc src{which ? sv->mdepth : sv->depth, which ? sv->minten : sv->inten, which ? sv->mpitch : sv->pitch};
-  __shared__ PyrTileStd::Lds s;
-  pyramid_tile<256, 64, 8>(src, which ? sv->model : sv->cur, levels, which, b - which * per, s, threadIdx.x);
+  __shared__ PyrTileBatch::Lds s;
+  pyramid_tile<PYR_BATCH_THREADS, PyrTileBatch::W, PyrTileBatch::H>(src, which ? sv->model : sv->cur, levels, which,
+                                                                    b - which * per, s, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 hipError_t launch_pyramid_batch(const SlotVis* slots, int levels, const BatchGrid& g, hipStream_t st) {
-  hipLaunchKernelGGL(pyramid_batch_kernel, dim3(g.first_block[g.nclass]), dim3(256), 0, st, slots, levels, g);
+  hipLaunchKernelGGL(pyramid_batch_kernel, dim3(g.first_block[g.nclass]), dim3(PYR_BATCH_THREADS), 0, st, slots,
+                     levels, g);
   return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ enum { STEP_FIRST = 1, STEP_LAST = 2, STEP_INERTIAL = 4 };
 // pyramid.hip
 hipError_t launch_pyramid(const PyrArgs& a, hipStream_t st);
 // every level of every session's current and model-view pyramids; g maps the
-// workgroups (2 x PyrTileStd::tiles per session: current frame first)
+// workgroups (2 x PyrTileBatch::tiles per session: current frame first)
 hipError_t launch_pyramid_batch(const SlotVis* slots, int levels, const BatchGrid& g, hipStream_t st);
 
 // kernels.hip
