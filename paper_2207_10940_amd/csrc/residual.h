@@ -49,7 +49,7 @@ __device__ __forceinline__ void accumulate(float* acc, const float* jv, float e,
 // association depends on it (weights and Jacobian scalings only).
 __device__ __forceinline__ float rcp_v(float x) { return __builtin_amdgcn_rcpf(x); }
 
-__device__ __forceinline__ float huber(float s, float k) { return (k > 0.0f && s > k) ? k * rcp_v(s) : 1.0f; }
+__device__ __forceinline__ float huber(float s, float k) { return ((k > 0.0f) & (s > k)) ? k * rcp_v(s) : 1.0f; }
 
 // Per-pixel sinks of the two residual terms: the plain form accumulates the
 // 2 x 29 sums per thread; the precision form keeps the pixel's 16-entry row
@@ -115,7 +115,9 @@ __device__ __forceinline__ void keep_if(bool in, float* jv, float* e, float* w) 
 // Association, residuals and Jacobians.
 //
 // The code is straight-line: every test of the mask layer is evaluated on all
-// lanes (the same IEEE operations in the same order as when nested), the
+// lanes (the same IEEE operations in the same order as when nested) and the
+// tests are combined with non-short-circuit '&' (so the compiler neither
+// branches on them nor widens a gather offset that a branch produced), the
 // model-view gathers are issued once the projections are known, and a lane
 // whose projection fails a test gathers at pixel 0 instead and has that term
 // zeroed (j = 0, e = 0, w = 0) before it reaches a sink.  A thread past the end
@@ -142,7 +144,7 @@ __device__ __forceinline__ Cur load_cur(const ResidualArgs& a, int p, bool valid
   c.y = ld(a.cV1, c.o4);
   c.z = ld(a.cV2, c.o4);
   c.valid = valid;
-  c.zok = valid && c.z > 0.0f;
+  c.zok = valid & (c.z > 0.0f);
   return c;
 }
 
@@ -159,14 +161,17 @@ __device__ __forceinline__ Term icp_term(const ResidualArgs& a, const float* T, 
   const float u = ((a.fx * qx) * inv) + a.cx;
   const float v = ((a.fy * qy) * inv) + a.cy;
   const float ui = __builtin_rintf(u), vi = __builtin_rintf(v);
-  const bool in = c.zok && qz > 0.0f && ui >= 0.0f && ui <= (float)(a.W - 1) && vi >= 0.0f && vi <= (float)(a.H - 1);
-  const unsigned m4 = in ? ((unsigned)vi * (unsigned)a.W + (unsigned)ui) * 4u : 0u;
+  const bool in = c.zok & (qz > 0.0f) & (ui >= 0.0f) & (ui <= (float)(a.W - 1)) & (vi >= 0.0f) & (vi <= (float)(a.H - 1));
+  // pixel 0 where the projection failed, selected on the rounded coordinates so
+  // that the offset is one unconditional 32-bit expression
+  const float us = in ? ui : 0.0f, vs = in ? vi : 0.0f;
+  const unsigned m4 = ((unsigned)vs * (unsigned)a.W + (unsigned)us) * 4u;
   const float v0x = ld(a.mV0, m4), v0y = ld(a.mV1, m4), v0z = ld(a.mV2, m4);
   const float n0x = ld(a.mN0, m4), n0y = ld(a.mN1, m4), n0z = ld(a.mN2, m4);
   const bool n0ok = (n0x != 0.0f) | (n0y != 0.0f) | (n0z != 0.0f);
   const float ex = qx - v0x, ey = qy - v0y, ez = qz - v0z;
   const float dist2 = (ex * ex + ey * ey) + ez * ez;
-  bool ok = in && v0z > 0.0f && n0ok && dist2 <= a.dist2;
+  bool ok = in & (v0z > 0.0f) & n0ok & (dist2 <= a.dist2);
   if (a.cosmin >= -1.0f) {  // optional normal-compatibility gate
     const float n1x = ld(a.cN0, c.o4), n1y = ld(a.cN1, c.o4), n1z = ld(a.cN2, c.o4);
     const bool n1ok = (n1x != 0.0f) | (n1y != 0.0f) | (n1z != 0.0f);
@@ -174,7 +179,7 @@ __device__ __forceinline__ Term icp_term(const ResidualArgs& a, const float* T, 
     const float nry = n1y + ((T[3] * n1x + T[4] * n1y) + T[5] * n1z);
     const float nrz = n1z + ((T[6] * n1x + T[7] * n1y) + T[8] * n1z);
     const float cosang = (nrx * n0x + nry * n0y) + nrz * n0z;
-    ok = ok && n1ok && cosang >= a.cosmin;
+    ok = ok & n1ok & (cosang >= a.cosmin);
   }
   Term t;
   t.e = fmaf(n0x, ex, fmaf(n0y, ey, n0z * ez));
@@ -204,7 +209,7 @@ __device__ __forceinline__ Term rgb_term(const ResidualArgs& a, const float* T, 
   const float inv = 1.0f / rz;
   const float u = ((a.fx * rx) * inv) + a.cx;
   const float v = ((a.fy * ry) * inv) + a.cy;
-  const bool in = c.zok && rz > 0.0f && u >= 1.0f && u < (float)(a.W - 2) && v >= 1.0f && v < (float)(a.H - 2);
+  const bool in = c.zok & (rz > 0.0f) & (u >= 1.0f) & (u < (float)(a.W - 2)) & (v >= 1.0f) & (v < (float)(a.H - 2));
   const float fu = floorf(u), fv = floorf(v);
   const unsigned m2 = in ? ((unsigned)fv * (unsigned)a.W + (unsigned)fu) * 2u : 0u, r2 = (unsigned)a.W * 2u;
   const unsigned q[4] = {m2, m2 + 2u, m2 + r2, m2 + r2 + 2u};
@@ -260,17 +265,20 @@ __device__ __forceinline__ unsigned pixel(const ResidualArgs& a, const float* T,
 }
 
 // ---- wavefront reduction ---------------------------------------------------
-// Sums N <= 64 per-lane values over the 64 lanes of a wavefront and returns
-// them transposed: lane l receives the total of value l (0 for l >= N).  Six
-// exchange stages each pair up the live values and halve their number:
-//   stage 1: lanes l, l^32 through v_permlane32_swap (value i, i+32 -> one register)
-//   stage 2: lanes l, l^16 through v_permlane16_swap
-//   stages 3-6: DPP row_mirror, row_half_mirror, quad_perm [3,2,1,0] and
-//   [1,0,3,2]; each partner differs from the lane in bit 3, 2, 1, 0 (and
-//   lower bits), and the lane keeps the value that its own bit selects.
+// Sums N <= 32 per-lane values over the 64 lanes of a wavefront and returns
+// them transposed: lanes 2q and 2q + 1 both receive the total of value q (0 for
+// q >= N).  Five exchange stages each pair up the live values and halve their
+// number, a sixth adds the last pair of neighbours:
+//   stage 1: v_permlane32_swap of values i and i + 16 (lanes 0-31 keep value i
+//            summed over l, l^32; lanes 32-63 value i + 16)
+//   stage 2: v_permlane16_swap of values i and i + 8 (partner l^16)
+//   stages 3-5: DPP row_mirror, row_half_mirror and quad_perm [3,2,1,0]; each
+//            partner differs from the lane in bit 3, 2 or 1 (and lower bits),
+//            and the lane keeps the value that its own bit selects
+//   stage 6: quad_perm [1,0,3,2] adds lanes l and l^1 (both keep the total).
 // After stage k a register holds, in lane l, the value whose index agrees with
-// l in the bits already exchanged; the pairing masks {32, 16, 15, 7, 3, 1}
-// span all 64 lanes, so every total covers each lane once.  About 140 VALU
+// l >> 1 in the bits already exchanged; the pairing masks {32, 16, 15, 7, 3,
+// 1} span all 64 lanes, so every total covers each lane once.  About 70 VALU
 // instructions with no LDS round trip; the summation order is fixed.
 __device__ __forceinline__ float f_of(unsigned u) { return __builtin_bit_cast(float, u); }
 __device__ __forceinline__ unsigned u_of(float f) { return __builtin_bit_cast(unsigned, f); }
@@ -292,24 +300,23 @@ __device__ __forceinline__ void in_row_stage(const float* in, float* out, bool h
 
 template <int N>
 __device__ __forceinline__ float wave_transpose_sum(const float (&v)[N], int lane) {
-  static_assert(N > 32 && N <= 64, "needs 33..64 values");
-  float s[32], t[16], u[8], w[4], x[2], y[1];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    const float b = (i + 32 < N) ? v[i + 32] : 0.0f;
-    const auto r = __builtin_amdgcn_permlane32_swap(u_of(v[i]), u_of(b), false, false);
-    s[i] = f_of(r[0]) + f_of(r[1]);  // lanes 0-31: value i, lanes 32-63: value i+32
-  }
+  static_assert(N > 16 && N <= 32, "needs 17..32 values");
+  float s[16], t[8], u[4], w[2], x[1];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const auto r = __builtin_amdgcn_permlane16_swap(u_of(s[i]), u_of(s[i + 16]), false, false);
-    t[i] = f_of(r[0]) + f_of(r[1]);  // value i + 16 * (lane / 16)
+    const float b = (i + 16 < N) ? v[i + 16] : 0.0f;
+    const auto r = __builtin_amdgcn_permlane32_swap(u_of(v[i]), u_of(b), false, false);
+    s[i] = f_of(r[0]) + f_of(r[1]);  // lanes 0-31: value i, lanes 32-63: value i+16
   }
-  in_row_stage<8, 0x140>(t, u, lane & 8);  // row_mirror
-  in_row_stage<4, 0x141>(u, w, lane & 4);  // row_half_mirror
-  in_row_stage<2, 0x1B>(w, x, lane & 2);   // quad_perm [3,2,1,0]
-  in_row_stage<1, 0xB1>(x, y, lane & 1);   // quad_perm [1,0,3,2]
-  return y[0];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(u_of(s[i]), u_of(s[i + 8]), false, false);
+    t[i] = f_of(r[0]) + f_of(r[1]);  // value i + 8 * (lane / 16)
+  }
+  in_row_stage<4, 0x140>(t, u, lane & 8);  // row_mirror
+  in_row_stage<2, 0x141>(u, w, lane & 4);  // row_half_mirror
+  in_row_stage<1, 0x1B>(w, x, lane & 2);   // quad_perm [3,2,1,0]
+  return x[0] + dpp<0xB1>(x[0]);           // quad_perm [1,0,3,2]
 }
 
 // Workgroup blk of a residual pass covers pixels blk*B*ppt .. +B*ppt-1
@@ -327,9 +334,9 @@ __device__ __forceinline__ void residual_block(const ResidualArgs& a, int blk, i
   __shared__ uint8_t inl[2][RES_THREADS * PMAX];  // inlier bits per term (masks only)
   float T[24];
   load_transforms(a.xf, T);
-  float acc[33];  // 29 sums and 4 zeros (the wavefront reduction takes 33..64 values)
+  float acc[29];
 #pragma unroll
-  for (int k = 0; k < 33; ++k) acc[k] = 0.0f;
+  for (int k = 0; k < 29; ++k) acc[k] = 0.0f;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool rgb = threadIdx.x >= HALF;  // uniform per wavefront
   const int t = threadIdx.x - (rgb ? HALF : 0);
@@ -345,7 +352,7 @@ __device__ __forceinline__ void residual_block(const ResidualArgs& a, int blk, i
     }
   }
   const float tot = wave_transpose_sum(acc, lane);
-  if (lane < 29) red[wave][lane] = tot;
+  if ((lane & 1) == 0 && lane < 58) red[wave][lane >> 1] = tot;
   __syncthreads();
   if (threadIdx.x < 58) {
     const int term = threadIdx.x / 29, q = threadIdx.x - 29 * term, w0 = term * (HALF / 64);
