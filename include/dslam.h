@@ -584,11 +584,12 @@ dslam_status dslam_batch_profile_residual(dslam_batch* b, int32_t level, int32_t
 /* Serving loop with continuous batching.  Frames of many sessions are
  * submitted as requests; each poll retires finished batched steps and
  * launches new ones from the pending requests: every session with a pending
- * frame and no frame in flight joins the next step (oldest request first, up
- * to max_batch sessions with the same pyramid schedule), and up to
- * pipeline_depth steps run at once on the server's own streams, so requests
- * that arrive while others are on the GPU are admitted as soon as a step slot
- * frees up.  Sessions are admitted by the context's HBM budget at
+ * frame joins the next step with its oldest one (up to max_batch sessions
+ * with the same pyramid schedule), and up to pipeline_depth steps are in
+ * flight at once on the server's own streams, so requests that arrive while
+ * others are on the GPU are admitted as soon as a step slot frees up.  A
+ * session's next frame may join a step while its previous frame is still
+ * running; the device orders the two.  Sessions are admitted by the context's HBM budget at
  * dslam_session_open (NO_CAPACITY when it is exhausted).  A session's frames
  * are tracked in submission order.  Not thread-safe: one thread drives a
  * server. */
@@ -602,7 +603,8 @@ typedef struct {
 
 /* A finished request.  submit_s / done_s are host steady-clock seconds (the
  * same clock as dslam_server_clock) at submission and at the poll that
- * retired it; device_ms is the GPU time of the batched step that ran it. */
+ * retired it; device_ms is the GPU time of the batched step that ran it
+ * (from the end of its sessions' earlier work to its own end). */
 typedef struct {
   uint64_t request_id;
   dslam_session* session;

@@ -236,24 +236,6 @@ bool finite16(const double* T) {
   return true;
 }
 
-// Orders new work of the session on `st` after its earlier work when that was
-// enqueued on another stream (the session's device state is updated in stream
-// order, so a change of stream must not let two frames overlap).
-hipError_t order_after_session(dslam_session* s, hipStream_t st) {
-  if (s->enqueued && s->last_stream != st) return hipStreamWaitEvent(st, s->done, 0);
-  return hipSuccess;
-}
-
-// Marks the end of the session's work enqueued on `st`.
-hipError_t mark_session(dslam_session* s, hipStream_t st) {
-  hipError_t e = hipEventRecord(s->done, st);
-  if (e == hipSuccess) {
-    s->last_stream = st;
-    s->enqueued = true;
-  }
-  return e;
-}
-
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices] = {};
@@ -400,7 +382,9 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   if (prior) init.prior = *prior;
   if (hipMemset(s->arena, 0, lo.total) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
   if (hipMemcpy(s->sd, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
-  if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
+  s->own_done = std::make_shared<DoneEvent>();
+  if (hipEventCreateWithFlags(&s->own_done->ev, hipEventDisableTiming) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
+  s->done = s->own_done;
   *out = s;
   return DSLAM_OK;
 }
@@ -562,10 +546,9 @@ dslam_status dslam_session_close(dslam_session* s) {
   if (!s) return DSLAM_ERR_INVALID;
   if (s->server_refs.load() > 0) return DSLAM_ERR_BUSY;
   (void)hipSetDevice(s->ctx->device);
-  if (s->enqueued) (void)hipEventSynchronize(s->done);
+  if (s->enqueued) (void)hipEventSynchronize(session_done(s));
   drop_graphs(s);
   if (s->capture) (void)hipStreamDestroy(s->capture);
-  (void)hipEventDestroy(s->done);
   (void)hipFree(s->arena);
   s->ctx->used.fetch_sub(s->bytes);
   delete s;
@@ -975,7 +958,7 @@ dslam_status batch_validate(const dslam_context* ctx, int32_t n, dslam_session* 
 // records and their copy to the device on `st`, and the plan of its launches.
 dslam_status batch_stage(const BatchMem& m, int32_t n, dslam_session* const* sessions,
                          const dslam_frame_input* frames, int tile_order, hipStream_t st, int* order,
-                         BatchPlan* plan) {
+                         BatchPlan* plan, hipEvent_t start = nullptr) {
   const dslam_session* s0 = sessions[0];
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order, order + n, [&](int a, int c) { return class_before(sessions[a], sessions[c]); });
@@ -989,7 +972,6 @@ dslam_status batch_stage(const BatchMem& m, int32_t n, dslam_session* const* ses
     dslam_session* s = sessions[order[k]];
     const dslam_frame_input& f = frames[order[k]];
     (void)pack_imu(s, f.imu, f.n_imu, f.t0, f.t1, &imu);
-    HIP_OK(order_after_session(s, st));
     std::memcpy(s->T_WM, f.T_WM, sizeof(s->T_WM));
     SlotVis& v = m.h_vis[k];
     SlotSolve& o = m.h_solve[k];
@@ -1012,8 +994,25 @@ dslam_status batch_stage(const BatchMem& m, int32_t n, dslam_session* const* ses
     o.sp = solve_params(s);
     o.fa = frame_args(s, o.sp);
   }
+  // the staging copies write only this step's staging memory: they go ahead of
+  // the waits for the sessions' earlier work (which may still be running on
+  // another stream), and the step's launches follow the waits
   HIP_OK(hipMemcpyAsync(m.d_vis, m.h_vis, sizeof(SlotVis) * n, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(m.d_solve, m.h_solve, sizeof(SlotSolve) * n, hipMemcpyHostToDevice, st));
+  // one wait per distinct completion event: the sessions of an earlier batched
+  // step share that step's event
+  const DoneEvent* waited[MAX_BATCH];
+  int nw = 0;
+  for (int k = 0; k < n; ++k) {
+    dslam_session* s = sessions[k];
+    if (!s->enqueued || s->last_stream == st) continue;
+    bool dup = false;
+    for (int w = 0; w < nw; ++w) dup = dup || waited[w] == s->done.get();
+    if (dup) continue;
+    HIP_OK(hipStreamWaitEvent(st, s->done->ev, 0));
+    waited[nw++] = s->done.get();
+  }
+  if (start) HIP_OK(hipEventRecord(start, st));
   // work split of each launch: one class per resolution and launch shape
   auto grid = [&](auto blocks_of) {
     BatchGrid g;
@@ -1074,16 +1073,32 @@ hipError_t batch_launches(const BatchMem& m, const BatchPlan& p, hipStream_t st)
 }
 
 // The results' copy to the host staging (m.h_res, slot order) and the
-// sessions' completion marks, after the step's launches on `st`.
+// sessions' completion marks, after the step's launches on `st`: one record of
+// `shared` for all of them, or (null) a record of each session's own event.
 dslam_status batch_finish(const BatchMem& m, int32_t n, dslam_session* const* sessions, const int* order,
-                          hipStream_t st) {
+                          hipStream_t st, const DoneRef* shared) {
   HIP_OK(hipMemcpyAsync(m.h_res, m.d_res, sizeof(dslam_track_result) * n, hipMemcpyDeviceToHost, st));
+  if (shared) HIP_OK(hipEventRecord((*shared)->ev, st));
   for (int k = 0; k < n; ++k) {
     dslam_session* s = sessions[order[k]];
     s->have_model = true;
-    HIP_OK(mark_session(s, st));
+    if (shared) mark_session_shared(s, st, *shared);
+    else HIP_OK(mark_session(s, st));
   }
   return DSLAM_OK;
+}
+
+// A completion event for the batch's next step: one that no session holds any
+// more (its earlier records are no longer waited for), or a new one.
+DoneRef step_done_event(dslam_batch* b, hipError_t* err) {
+  *err = hipSuccess;
+  for (const DoneRef& d : b->step_done)
+    if (d.use_count() == 1) return d;
+  DoneRef d = std::make_shared<DoneEvent>();
+  *err = hipEventCreateWithFlags(&d->ev, hipEventDisableTiming);
+  if (*err != hipSuccess) return nullptr;
+  b->step_done.push_back(d);
+  return d;
 }
 
 // The executable graph of a plan on this batch object: found in the cache or
@@ -1128,16 +1143,22 @@ extern "C" {
 
 dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* sessions,
                                const dslam_frame_input* frames, void* stream) {
+  return batch_track_timed(b, n, sessions, frames, (hipStream_t)stream, nullptr);
+}
+
+}  // extern "C"
+
+dslam_status batch_track_timed(dslam_batch* b, int32_t n, dslam_session* const* sessions,
+                               const dslam_frame_input* frames, hipStream_t st, hipEvent_t start) {
   if (!b || !sessions || !frames || n < 1 || n > b->max_n) return DSLAM_ERR_INVALID;
   const dslam_status v = batch_validate(b->ctx, n, sessions, frames);
   if (v != DSLAM_OK) return v;
   HIP_OK(hipSetDevice(b->ctx->device));
   if (b->pending) HIP_OK(hipEventSynchronize(b->done));  // staging memory is reused
   b->pending = false;
-  hipStream_t st = (hipStream_t)stream;
   const BatchMem m{b->h_vis, b->h_solve, b->h_res, b->d_vis, b->d_solve, b->d_res};
   BatchPlan plan;
-  const dslam_status e = batch_stage(m, n, sessions, frames, b->tile_order, st, b->order, &plan);
+  const dslam_status e = batch_stage(m, n, sessions, frames, b->tile_order, st, b->order, &plan, start);
   if (e != DSLAM_OK) return e;
   if (b->use_graphs) {
     hipError_t ge = hipSuccess;
@@ -1147,7 +1168,10 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
   } else {
     HIP_OK(batch_launches(m, plan, st));
   }
-  const dslam_status f = batch_finish(m, n, sessions, b->order, st);
+  hipError_t de = hipSuccess;
+  const DoneRef sd = step_done_event(b, &de);
+  HIP_OK(de);
+  const dslam_status f = batch_finish(m, n, sessions, b->order, st, &sd);
   if (f != DSLAM_OK) return f;
   HIP_OK(hipEventRecord(b->done, st));
   b->levels = plan.levels;
@@ -1162,6 +1186,8 @@ dslam_status dslam_batch_track(dslam_batch* b, int32_t n, dslam_session* const* 
   b->pending = true;
   return DSLAM_OK;
 }
+
+extern "C" {
 
 dslam_status dslam_batch_set_tile_order(dslam_batch* b, int32_t order) {
   if (!b || order < -1 || order > 1) return DSLAM_ERR_INVALID;
@@ -1202,7 +1228,7 @@ dslam_status dslam_batch_track_noalloc(int32_t n, dslam_session* const* sessions
   const dslam_status e = batch_stage(m, n, sessions, frames, 1, st, order, &plan);
   if (e != DSLAM_OK) return e;
   HIP_OK(batch_launches(m, plan, st));
-  const dslam_status f = batch_finish(m, n, sessions, order, st);
+  const dslam_status f = batch_finish(m, n, sessions, order, st, nullptr);
   if (f != DSLAM_OK) return f;
   HIP_OK(hipStreamSynchronize(st));
   for (int k = 0; k < n; ++k) results[order[k]] = g_hres[k];
@@ -1233,7 +1259,7 @@ dslam_status dslam_batch_results(dslam_batch* b, dslam_track_result* out) {
 dslam_status dslam_session_result(dslam_session* s, dslam_track_result* out) {
   if (!s || !out) return DSLAM_ERR_INVALID;
   HIP_OK(hipSetDevice(s->ctx->device));
-  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
+  if (s->enqueued) HIP_OK(hipEventSynchronize(session_done(s)));
   HIP_OK(hipMemcpy(out, &s->sd->result, sizeof(dslam_track_result), hipMemcpyDeviceToHost));
   return DSLAM_OK;
 }
@@ -1293,7 +1319,7 @@ dslam_status dslam_copy_pyramid(dslam_session* s, int32_t which, int32_t level, 
   if (channel < DSLAM_CH_VX || channel > DSLAM_CH_GY || (grad && which != DSLAM_PYR_MODEL)) return DSLAM_ERR_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
-  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
+  if (s->enqueued) HIP_OK(hipEventSynchronize(session_done(s)));
   const size_t n = (size_t)L.W * L.H;
   if (channel >= DSLAM_CH_NX && channel <= DSLAM_CH_NZ) {
     HIP_OK(hipMemcpy(host_out, L.N[channel - DSLAM_CH_NX], n * sizeof(float), hipMemcpyDeviceToHost));
@@ -1413,7 +1439,7 @@ dslam_status dslam_session_checkpoint(dslam_session* s, void* buf, uint64_t capa
   if (s->server_refs.load() > 0) return DSLAM_ERR_BUSY;
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
-  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
+  if (s->enqueued) HIP_OK(hipEventSynchronize(session_done(s)));
   uint8_t* p = (uint8_t*)buf;
   CkptHeader h;
   fill_header(s, &h);
@@ -1458,7 +1484,7 @@ dslam_status dslam_session_restore(dslam_session* s, const void* buf, uint64_t s
   if (s->server_refs.load() > 0) return DSLAM_ERR_BUSY;
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
-  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
+  if (s->enqueued) HIP_OK(hipEventSynchronize(session_done(s)));
   const uint8_t* p = (const uint8_t*)buf;
   HIP_OK(hipMemcpy(s->sd, p + sizeof(CkptHeader), sizeof(SessionDev), hipMemcpyHostToDevice));
   HIP_OK(copy_model_planes(s, const_cast<uint8_t*>(p) + sizeof(CkptHeader) + sizeof(SessionDev), false));
@@ -1478,7 +1504,7 @@ dslam_status dslam_session_get_state(dslam_session* s, dslam_frame_state* x0, do
   if (!s) return DSLAM_ERR_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
-  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
+  if (s->enqueued) HIP_OK(hipEventSynchronize(session_done(s)));
   SessionDev d;
   HIP_OK(hipMemcpy(&d, s->sd, sizeof(d), hipMemcpyDeviceToHost));
   if (x0) *x0 = d.x0;
@@ -1494,7 +1520,7 @@ dslam_status dslam_session_set_state(dslam_session* s, const dslam_frame_state* 
   if (s->tp.mode != DSLAM_MODE_RGBD && !prior) return DSLAM_ERR_INVALID;
   std::lock_guard<std::mutex> g(s->mu);
   HIP_OK(hipSetDevice(s->ctx->device));
-  if (s->enqueued) HIP_OK(hipEventSynchronize(s->done));
+  if (s->enqueued) HIP_OK(hipEventSynchronize(session_done(s)));
   SessionDev d;
   HIP_OK(hipMemcpy(&d, s->sd, sizeof(d), hipMemcpyDeviceToHost));
   d.x0 = *x0;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -20,6 +21,18 @@ struct dslam_context {
 using dslam::LevelPtrs;
 using dslam::SessionDev;
 
+// A completion event that several sessions can share: one record at the end of
+// a batched step marks that step's end for every session in it (one record
+// and, for the next step on another stream, one wait instead of one per
+// session).  Destroyed with its last holder.
+struct DoneEvent {
+  hipEvent_t ev = nullptr;
+  ~DoneEvent() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+using DoneRef = std::shared_ptr<DoneEvent>;
+
 struct dslam_session {
   dslam_context* ctx;
   dslam_camera cam;
@@ -34,7 +47,8 @@ struct dslam_session {
   int max_blocks;
   double* red_out;   // device, 64 doubles
   float* xf_scratch; // device, 24 floats (dslam_linearize)
-  hipEvent_t done;          // recorded after every enqueue of the session's work
+  DoneRef own_done;         // the session's own completion event
+  DoneRef done;             // the event recorded after the last enqueue of its work (own, or a batched step's)
   hipStream_t last_stream;  // stream of the last enqueue (a later enqueue on another stream waits for done)
   bool enqueued;            // done has been recorded at least once
   std::atomic<int> server_refs{0};  // requests of the session held by servers (queued or not yet returned)
@@ -51,6 +65,36 @@ struct dslam_session {
   std::mutex mu;
 };
 
+// Orders new work of the session on `st` after its earlier work when that was
+// enqueued on another stream (the session's device state is updated in stream
+// order, so a change of stream must not let two frames overlap).
+inline hipError_t order_after_session(dslam_session* s, hipStream_t st) {
+  if (s->enqueued && s->last_stream != st) return hipStreamWaitEvent(st, s->done->ev, 0);
+  return hipSuccess;
+}
+
+// Marks the end of the session's work enqueued on `st` with its own event.
+inline hipError_t mark_session(dslam_session* s, hipStream_t st) {
+  hipError_t e = hipEventRecord(s->own_done->ev, st);
+  if (e == hipSuccess) {
+    s->done = s->own_done;
+    s->last_stream = st;
+    s->enqueued = true;
+  }
+  return e;
+}
+
+// Marks the end of the session's work enqueued on `st` with `d`, already
+// recorded on `st` after that work.
+inline void mark_session_shared(dslam_session* s, hipStream_t st, const DoneRef& d) {
+  s->done = d;
+  s->last_stream = st;
+  s->enqueued = true;
+}
+
+// The session's completion event (valid once enqueued).
+inline hipEvent_t session_done(const dslam_session* s) { return s->done->ev; }
+
 struct dslam_batch {
   dslam_context* ctx;
   int max_n;
@@ -64,6 +108,7 @@ struct dslam_batch {
   dslam::SlotSolve* h_solve;
   dslam_track_result* h_res;
   hipEvent_t done;
+  std::vector<DoneRef> step_done;  // shared completion events of its steps (reused once no session holds one)
   bool pending;
   int n;
   int order[dslam::MAX_BATCH];        // slot -> caller index
@@ -81,3 +126,8 @@ struct dslam_batch {
   std::vector<std::pair<std::vector<int32_t>, hipGraphExec_t>> graphs;
 };
 
+// dslam_batch_track with `start` (nullable) recorded on `st` once the step's
+// staging is enqueued and its sessions' earlier work is waited for, i.e. where
+// the step's own device time begins.
+dslam_status batch_track_timed(dslam_batch* b, int32_t n, dslam_session* const* sessions,
+                               const dslam_frame_input* frames, hipStream_t st, hipEvent_t start);

@@ -3,14 +3,18 @@
 // Requests (one frame of one session each) wait in one queue in submission
 // order.  A poll first retires the batched steps whose completion event has
 // fired, then fills every free step slot with a new batch: it scans the queue
-// from the front and takes the first request of every session that has no
-// frame in flight and none taken yet, as long as the session shares the
-// pyramid schedule of the batch's first request and the batch stays within
-// the batched step's limits (sessions, distinct resolutions).  Later frames of
-// a session wait for the earlier ones, so each session's frames are tracked in
-// order; sessions that arrive while steps are running join the next free slot.
-// Each slot owns a batch's staging memory, a stream and a pair of timing
-// events, so up to pipeline_depth steps overlap on the device.
+// from the front and takes the first request of every session not taken yet,
+// as long as the session shares the pyramid schedule of the batch's first
+// request and the batch stays within the batched step's limits (sessions,
+// distinct resolutions).  Later frames of a session wait for the earlier ones,
+// so each session's frames are tracked in order.  A session's next frame may
+// join a step while its previous one is still running: the new step is staged
+// and launched at once, and on the device its launches wait for the sessions'
+// earlier work (an event per session), so when every session is in every step
+// (saturation) the next step starts as soon as the previous one ends, with no
+// host round trip in between.  Each slot owns a batch's staging memory, a
+// stream and a pair of timing events, so up to pipeline_depth steps are in
+// flight.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -73,7 +77,6 @@ struct dslam_server {
   dslam_server_params p;
   std::vector<StepSlot> slots;
   std::deque<Request> pending;
-  std::unordered_set<const dslam_session*> in_flight;
   std::deque<dslam_request_done> finished;
   uint64_t next_id = 1;
   int launched = 0;  // requests launched and not yet returned
@@ -115,7 +118,6 @@ dslam_status retire(dslam_server* sv, StepSlot& st) {
     if (rs == DSLAM_OK) d.result = res[i];
     else d.result.status = rs;
     sv->finished.push_back(d);
-    sv->in_flight.erase(st.reqs[i].s);
   }
   sv->launched -= (int)st.reqs.size();
   st.reqs.clear();
@@ -130,7 +132,7 @@ void take_batch(dslam_server* sv, std::vector<Request>* out) {
   std::vector<std::pair<int, int>> res;  // distinct resolutions in the batch
   const dslam_session* first = nullptr;
   for (Request& r : sv->pending) {
-    bool take = (int)out->size() < sv->p.max_batch && !sv->in_flight.count(r.s) && !seen.count(r.s);
+    bool take = (int)out->size() < sv->p.max_batch && !seen.count(r.s);
     if (take && first && !same_schedule(first, r.s)) take = false;
     if (take) {
       std::pair<int, int> wh{r.s->cam.width, r.s->cam.height};
@@ -164,8 +166,9 @@ dslam_status launch(dslam_server* sv, StepSlot& st) {
   }
   st.launch_s = steady_seconds();
   dslam_status rc = DSLAM_OK;
-  if (hipEventRecord(st.t0, st.stream) != hipSuccess) rc = DSLAM_ERR_DEVICE;
-  if (rc == DSLAM_OK) rc = dslam_batch_track(st.batch, n, ss.data(), fs.data(), st.stream);
+  // t0 is recorded once the step's earlier work is waited for: device_ms is the
+  // step's own time, not its wait behind the previous step
+  rc = batch_track_timed(st.batch, n, ss.data(), fs.data(), st.stream, st.t0);
   if (rc == DSLAM_OK && hipEventRecord(st.t1, st.stream) != hipSuccess) rc = DSLAM_ERR_DEVICE;
   if (rc != DSLAM_OK) {  // the step never ran: return its requests with the error
     const double t = steady_seconds();
@@ -185,7 +188,6 @@ dslam_status launch(dslam_server* sv, StepSlot& st) {
     st.reqs.clear();
     return rc;
   }
-  for (Request& r : st.reqs) sv->in_flight.insert(r.s);
   sv->launched += n;
   st.busy = true;
   return DSLAM_OK;

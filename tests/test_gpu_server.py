@@ -73,6 +73,52 @@ def test_server_results_equal_alone_results(graphs):
     ctx.close()
 
 
+def test_server_pipelines_a_sessions_frames_across_steps():
+    """Every session in every step (a saturated mix): the next step is staged and
+    launched while the previous one runs, and the device orders each session's
+    frames across the two step streams.  Results equal tracking alone."""
+    import torch
+    stream = torch.cuda.current_stream()
+    specs = [(3601, 320, 240, "rgbdi"), (3602, 160, 120, "rgbdi"), (3603, 200, 152, "rgbd")]
+    seqs = [synth.configs.sequence(seed=sd, n_frames=FRAMES + 2, width=w, height=h, device="cuda")
+            for sd, w, h, _ in specs]
+    ctx = P.Context(0)
+    alone = [_alone(ctx, seq, mode, stream) for seq, (_, _, _, mode) in zip(seqs, specs)]
+    torch.cuda.synchronize()
+    sess = [open_seq_session(ctx, seq, mode) for seq, (_, _, _, mode) in zip(seqs, specs)]
+    server = P.Server(ctx, max_batch=len(specs), pipeline_depth=2)
+    inputs, owner = [], {}
+    for j in range(1, FRAMES + 1):
+        for i in range(len(specs)):
+            f = seq_frame(seqs[i], j)
+            if specs[i][3] == "rgbd":
+                f["imu"] = None
+            fi, keep = P.frame_input(f)
+            inputs.append((fi, keep))
+            owner[server.submit(sess[i], fi)] = (i, j)
+    got = {i: {} for i in range(len(specs))}
+    while sum(len(v) for v in got.values()) < len(specs) * FRAMES:
+        for rid, _h, t_sub, t_launch, t_done, dev_ms, bsize, res in server.poll(wait=True):
+            i, j = owner[rid]
+            got[i][j] = (t_launch, t_done, bsize, P.result_dict(res))
+            assert dev_ms > 0
+    assert server.counts() == (0, 0)
+    overlapped = 0
+    for i in range(len(specs)):
+        assert sorted(got[i]) == list(range(1, FRAMES + 1)), i
+        for j in range(1, FRAMES + 1):
+            assert got[i][j][2] == len(specs)
+            same_result(got[i][j][3], alone[i][j - 1], f"session {i} frame {j}")
+            if j > 1 and got[i][j][0] < got[i][j - 1][1]:
+                overlapped += 1  # launched before the previous frame was returned
+    assert overlapped > 0
+    print(f"frames launched before their predecessor returned: {overlapped}", flush=True)
+    server.close()
+    for s in sess:
+        s.close()
+    ctx.close()
+
+
 def test_server_rejects_bad_requests():
     seq = synth.configs.sequence(seed=3401, n_frames=3, width=160, height=120, device="cuda")
     ctx = P.Context(0)
