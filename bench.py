@@ -41,15 +41,15 @@ LAYOUT_BYTES_PER_PIXEL = 44
 # and of a 256 MiB calibration copy, from rocprofv3 --pmc runs of `bench.py --counters --counters-batch`
 # (profiles/residual_kernel_640x480_counters.md); valid for the residual-pass sources with this hash
 COUNTERS = {
-    "source_sha256": "593a22782dfad708",
-    "copy_fetch_kib": 131086.5, "copy_write_kib": 262144.0,
+    "source_sha256": "0812d43df8fce201",
+    "copy_fetch_kib": 131086.7, "copy_write_kib": 262144.0,
     "shapes": {  # "ppt,banded": per-dispatch means over 50 back-to-back launches
-        "1,0": {"fetch_kib": 7947.7, "write_kib": 300.0, "valu_insts": 2433026, "waves": 4800},
-        "1,1": {"fetch_kib": 5159.2, "write_kib": 300.0, "valu_insts": 2433026, "waves": 4800},
-        "2,0": {"fetch_kib": 7866.4, "write_kib": 150.0, "valu_insts": 1959026, "waves": 2400},
-        "2,1": {"fetch_kib": 5194.2, "write_kib": 150.0, "valu_insts": 1959026, "waves": 2400},
-        "4,0": {"fetch_kib": 6828.5, "write_kib": 75.0, "valu_insts": 1749626, "waves": 1200},
-        "4,1": {"fetch_kib": 5260.2, "write_kib": 75.0, "valu_insts": 1749626, "waves": 1200},
+        "1,0": {"fetch_kib": 7939.7, "write_kib": 300.0, "valu_insts": 1993316, "waves": 4800},
+        "1,1": {"fetch_kib": 5151.2, "write_kib": 300.0, "valu_insts": 1993316, "waves": 4800},
+        "2,0": {"fetch_kib": 7861.9, "write_kib": 150.0, "valu_insts": 1747316, "waves": 2400},
+        "2,1": {"fetch_kib": 5189.7, "write_kib": 150.0, "valu_insts": 1747316, "waves": 2400},
+        "4,0": {"fetch_kib": 6821.0, "write_kib": 75.0, "valu_insts": 1624316, "waves": 1200},
+        "4,1": {"fetch_kib": 5252.8, "write_kib": 75.0, "valu_insts": 1624316, "waves": 1200},
     },
 }
 RESIDUAL_SOURCES = ("kernels.hip", "residual.h", "device.h")
