@@ -88,6 +88,7 @@ struct SlotVis {
   const uint8_t* minten;
   int32_t pitch, mpitch;
   int32_t ppt[DSLAM_MAX_LEVELS];       // pixels per thread of each level's residual pass
+  int32_t cur_normals;                 // 1: the step writes the current pyramid's normal planes
 };
 
 // Work split of one batched launch.  The slots are ordered so that slots with

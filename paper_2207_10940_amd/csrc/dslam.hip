@@ -331,6 +331,7 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   s->levels = tp->levels;
   s->bytes = lo.total;
   s->have_model = false;
+  s->cur_normals_ok = true;
   s->max_blocks = lo.max_blocks;
   s->use_graphs = false;
   s->capture = nullptr;
@@ -582,6 +583,7 @@ dslam_status dslam_build_pyramid(dslam_session* s, int32_t which, const float* d
   HIP_OK(order_after_session(s, st));
   HIP_OK(launch_pyramid(pyr_args(s, which, depth_dev, intensity_dev, pitch_elems), st));
   HIP_OK(mark_session(s, st));
+  if (which == DSLAM_PYR_CURRENT) s->cur_normals_ok = true;
   if (which == DSLAM_PYR_MODEL) {
     std::memcpy(s->T_WM, T_W_ref, sizeof(s->T_WM));
     s->have_model = true;
@@ -717,6 +719,7 @@ static dslam_status track_enqueue(dslam_session* s, const float* depth, const ui
   const SolveParams sp = solve_params(s);
   const FrameArgs fa = frame_args(s, sp);
   const PyrArgs cur = pyr_args(s, DSLAM_PYR_CURRENT, depth, inten, pitch);
+  s->cur_normals_ok = true;  // the frame's first launch builds the current pyramid with its normals
   PyrArgs model;
   if (mdepth) model = pyr_args(s, DSLAM_PYR_MODEL, mdepth, minten, mpitch);
   if (s->use_graphs) {
@@ -988,6 +991,10 @@ dslam_status batch_stage(const BatchMem& m, int32_t n, dslam_session* const* ses
     v.mdepth = f.model_depth;
     v.minten = f.model_intensity;
     v.mpitch = f.model_pitch;
+    // the current frame's normals are read only through the normal gate;
+    // otherwise the step leaves them out (ensure_cur_normals fills them on demand)
+    v.cur_normals = s->tp.icp_cos >= -1.0 ? 1 : 0;
+    s->cur_normals_ok = v.cur_normals != 0;
     o.sd = s->sd;
     o.partials = s->partials;
     o.imu = imu;
@@ -1321,6 +1328,10 @@ dslam_status dslam_copy_pyramid(dslam_session* s, int32_t which, int32_t level, 
   HIP_OK(hipSetDevice(s->ctx->device));
   if (s->enqueued) HIP_OK(hipEventSynchronize(session_done(s)));
   const size_t n = (size_t)L.W * L.H;
+  if (which == DSLAM_PYR_CURRENT && channel >= DSLAM_CH_NX && channel <= DSLAM_CH_NZ && !s->cur_normals_ok) {
+    HIP_OK(ensure_cur_normals(s, nullptr));  // the null stream: the copy below waits for it
+    HIP_OK(mark_session(s, nullptr));
+  }
   if (channel >= DSLAM_CH_NX && channel <= DSLAM_CH_NZ) {
     HIP_OK(hipMemcpy(host_out, L.N[channel - DSLAM_CH_NX], n * sizeof(float), hipMemcpyDeviceToHost));
   } else if (channel >= DSLAM_CH_VX && channel <= DSLAM_CH_VZ) {

@@ -53,6 +53,8 @@ struct dslam_session {
   bool enqueued;            // done has been recorded at least once
   std::atomic<int> server_refs{0};  // requests of the session held by servers (queued or not yet returned)
   bool have_model;
+  bool cur_normals_ok;  // the current pyramid's normal planes belong to its vertex planes (a batched step
+                        // without the normal gate leaves them out; ensure_cur_normals fills them)
   double T_WM[16];
   int ppt[DSLAM_MAX_LEVELS];
   int banded[DSLAM_MAX_LEVELS];  // tile order of each level's residual pass (tile_of)
@@ -90,6 +92,18 @@ inline void mark_session_shared(dslam_session* s, hipStream_t st, const DoneRef&
   s->done = d;
   s->last_stream = st;
   s->enqueued = true;
+}
+
+// Fills the current pyramid's normal planes on `st` where a batched step left
+// them out (the caller orders `st` after the session's work).
+inline hipError_t ensure_cur_normals(dslam_session* s, hipStream_t st) {
+  if (s->cur_normals_ok) return hipSuccess;
+  for (int l = 0; l < s->levels; ++l) {
+    const hipError_t e = dslam::launch_normals(s->cur[l], st);
+    if (e != hipSuccess) return e;
+  }
+  s->cur_normals_ok = true;
+  return hipSuccess;
 }
 
 // The session's completion event (valid once enqueued).

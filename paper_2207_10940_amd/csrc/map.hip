@@ -611,6 +611,11 @@ dslam_status dslam_map_fuse(dslam_map* m, dslam_session* s, const double T_WC[16
   XformF wc, cw;
   map_transforms(T_WC, &wc, &cw);
   const int npx = m->mc.W * m->mc.H;
+  if (!s->cur_normals_ok) {  // a batched step left the frame's normals out
+    MAP_HIP(order_after_session(s, st));
+    MAP_HIP(ensure_cur_normals(s, st));
+    MAP_HIP(mark_session(s, st));
+  }
   MapFrame fr;
   fr.L0 = s->cur[0];
   fr.Ln = s->levels > 1 ? s->cur[1] : s->cur[0];

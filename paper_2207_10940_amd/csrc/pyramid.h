@@ -85,26 +85,14 @@ __device__ __forceinline__ void pyr_st(T* base, size_t idx, T v) {
   ((GT*)base)[idx] = v;
 }
 
-// Level outputs of pixel (i, j), whose depth and intensity sit at (a, b) of a
-// region of width E in LDS (all four neighbours are inside the region).
-__device__ __forceinline__ void pyr_out(const LevelPtrs& L, const float* D, const float* In, int E, int a, int b,
-                                        int i, int j, int with_grad) {
+// Normal of pixel (i, j) of a level from its depth d, its right and lower
+// neighbours' depths dr and dd, and its vertex (vx, vy, d): the normalised
+// cross product of the forward differences, zero on the last row and column
+// and where a depth is missing.
+__device__ __forceinline__ void pyr_normal(const LevelPtrs& L, int i, int j, float d, float dr, float dd, float vx,
+                                           float vy, float* n) {
 #pragma clang fp contract(off)
-  const int q = b * E + a;
-  // every LDS read first
-  const float d = D[q], dr = D[q + 1], dd = D[q + E];
-  const float ic = In[q];
-  float il = 0.0f, ir = 0.0f, iu = 0.0f, idn = 0.0f;
-  if (with_grad) {
-    il = In[q - 1];
-    ir = In[q + 1];
-    iu = In[q - E];
-    idn = In[q + E];
-  }
-  const size_t p = (size_t)j * L.W + i;
   const float fi = (float)i, fj = (float)j;
-  const float vx = ((fi - L.cx) * d) / L.fx;
-  const float vy = ((fj - L.cy) * d) / L.fy;
   float nx = 0.0f, ny = 0.0f, nz = 0.0f;
   if (i < L.W - 1 && j < L.H - 1) {
     const float ax = (((fi + 1.0f) - L.cx) * dr) / L.fx - vx;
@@ -123,13 +111,44 @@ __device__ __forceinline__ void pyr_out(const LevelPtrs& L, const float* D, cons
       nz = cz / len;
     }
   }
+  n[0] = nx;
+  n[1] = ny;
+  n[2] = nz;
+}
+
+// Level outputs of pixel (i, j), whose depth and intensity sit at (a, b) of a
+// region of width E in LDS (all four neighbours are inside the region).
+// Without with_normals the normal planes are left unwritten (pyr_normals_at
+// fills them later from the stored depths, with the same operations).
+__device__ __forceinline__ void pyr_out(const LevelPtrs& L, const float* D, const float* In, int E, int a, int b,
+                                        int i, int j, int with_grad, int with_normals) {
+#pragma clang fp contract(off)
+  const int q = b * E + a;
+  // every LDS read first
+  const float d = D[q], dr = D[q + 1], dd = D[q + E];
+  const float ic = In[q];
+  float il = 0.0f, ir = 0.0f, iu = 0.0f, idn = 0.0f;
+  if (with_grad) {
+    il = In[q - 1];
+    ir = In[q + 1];
+    iu = In[q - E];
+    idn = In[q + E];
+  }
+  const size_t p = (size_t)j * L.W + i;
+  const float fi = (float)i, fj = (float)j;
+  const float vx = ((fi - L.cx) * d) / L.fx;
+  const float vy = ((fj - L.cy) * d) / L.fy;
   pyr_st(L.V[0], p, vx);
   pyr_st(L.V[1], p, vy);
   pyr_st(L.V[2], p, d);
   pyr_st(L.I, p, (uint16_t)(ic * kIntensityScale));
-  pyr_st(L.N[0], p, nx);
-  pyr_st(L.N[1], p, ny);
-  pyr_st(L.N[2], p, nz);
+  if (with_normals) {
+    float n[3];
+    pyr_normal(L, i, j, d, dr, dd, vx, vy, n);
+    pyr_st(L.N[0], p, n[0]);
+    pyr_st(L.N[1], p, n[1]);
+    pyr_st(L.N[2], p, n[2]);
+  }
   if (with_grad) {
     float gx = 0.0f, gy = 0.0f;
     if (i > 0 && i < L.W - 1 && j > 0 && j < L.H - 1) {
@@ -145,7 +164,8 @@ __device__ __forceinline__ void pyr_out(const LevelPtrs& L, const float* D, cons
 // threads; tid is the thread's index in the workgroup.  L[l] for l < levels.
 template <int NT, int TW, int TH>
 __device__ __forceinline__ void pyramid_tile(const PyrSrc& src, const LevelPtrs* L, int levels, int with_grad,
-                                             int tile, typename PyrTile<TW, TH>::Lds& s, int tid) {
+                                             int tile, typename PyrTile<TW, TH>::Lds& s, int tid,
+                                             int with_normals = 1) {
 #pragma clang fp contract(off)
   using P = PyrTile<TW, TH>;
   const int c = levels - 1;
@@ -188,7 +208,7 @@ __device__ __forceinline__ void pyramid_tile(const PyrSrc& src, const LevelPtrs*
     for (int k = tid; k < Tw * Th; k += NT) {
       const int b = k / Tw, a = k - b * Tw;
       const int i = tx * Tw + a, j = ty * Th + b;
-      if (i < Ll.W && j < Ll.H) pyr_out(Ll, D, In, Ew, a + m, b + m, i, j, with_grad);
+      if (i < Ll.W && j < Ll.H) pyr_out(Ll, D, In, Ew, a + m, b + m, i, j, with_grad, with_normals);
     }
     if (l + 1 < levels) {  // the next level's region from this one
       const int m1 = m >> 1, E1w = (Tw >> 1) + 2 * m1, E1h = (Th >> 1) + 2 * m1;
@@ -226,6 +246,24 @@ __device__ __forceinline__ void pyramid_tile(const PyrSrc& src, const LevelPtrs*
     }
     __syncthreads();
   }
+}
+
+// The normal planes of pixel (i, j) of a level whose vertex planes are written
+// (a pyramid built without normals): the same operations on the stored depths
+// as pyr_out, so the values are those a pyramid with normals holds.
+__device__ __forceinline__ void pyr_normals_at(const LevelPtrs& L, int i, int j) {
+#pragma clang fp contract(off)
+  const size_t p = (size_t)j * L.W + i;
+  const float d = pyr_ld(L.V[2], p);
+  const float dr = i < L.W - 1 ? pyr_ld(L.V[2], p + 1) : 0.0f;
+  const float dd = j < L.H - 1 ? pyr_ld(L.V[2], p + L.W) : 0.0f;
+  const float vx = ((((float)i) - L.cx) * d) / L.fx;
+  const float vy = ((((float)j) - L.cy) * d) / L.fy;
+  float n[3];
+  pyr_normal(L, i, j, d, dr, dd, vx, vy, n);
+  pyr_st(L.N[0], p, n[0]);
+  pyr_st(L.N[1], p, n[1]);
+  pyr_st(L.N[2], p, n[2]);
 }
 
 }  // namespace dslam

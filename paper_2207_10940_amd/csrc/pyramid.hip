@@ -30,13 +30,28 @@ __global__ __launch_bounds__(PYR_BATCH_THREADS) void pyramid_batch_kernel(const 
   const PyrSrc src{which ? sv->mdepth : sv->depth, which ? sv->minten : sv->inten, which ? sv->mpitch : sv->pitch};
   __shared__ PyrTileBatch::Lds s;
   pyramid_tile<PYR_BATCH_THREADS, PyrTileBatch::W, PyrTileBatch::H>(src, which ? sv->model : sv->cur, levels, which,
-                                                                    b - which * per, s, threadIdx.x);
+                                                                    b - which * per, s, threadIdx.x,
+                                                                    which ? 1 : sv->cur_normals);
+}
+
+// The normal planes of one level built without them (pyr_normals_at), one
+// thread per pixel.
+__global__ __launch_bounds__(256) void normals_kernel(LevelPtrs L) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= L.W * L.H) return;
+  const int j = p / L.W, i = p - j * L.W;
+  pyr_normals_at(L, i, j);
 }
 
 // ---------------------------------------------------------------------------
 hipError_t launch_pyramid_batch(const SlotVis* slots, int levels, const BatchGrid& g, hipStream_t st) {
   hipLaunchKernelGGL(pyramid_batch_kernel, dim3(g.first_block[g.nclass]), dim3(PYR_BATCH_THREADS), 0, st, slots,
                      levels, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_normals(const LevelPtrs& L, hipStream_t st) {
+  hipLaunchKernelGGL(normals_kernel, dim3((L.W * L.H + 255) / 256), dim3(256), 0, st, L);
   return hipGetLastError();
 }
 

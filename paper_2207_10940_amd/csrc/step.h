@@ -54,6 +54,7 @@ hipError_t launch_pyramid(const PyrArgs& a, hipStream_t st);
 // every level of every session's current and model-view pyramids; g maps the
 // workgroups (2 x PyrTileBatch::tiles per session: current frame first)
 hipError_t launch_pyramid_batch(const SlotVis* slots, int levels, const BatchGrid& g, hipStream_t st);
+hipError_t launch_normals(const LevelPtrs& L, hipStream_t st);
 
 // kernels.hip
 int residual_blocks(int npix, int ppt);

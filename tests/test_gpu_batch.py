@@ -144,3 +144,67 @@ def test_batch_rejects_inconsistent_sessions():
     a.close()
     b.close()
     ctx.close()
+
+
+def test_batched_step_leaves_current_normals_to_demand():
+    """Without the normal gate a batched step does not write the current
+    pyramid's normals; reading them (dslam_copy_pyramid) or fusing the frame
+    into a map fills them first, with the values a single-session frame
+    writes, bit for bit.  A session with the gate keeps them in the step."""
+    import math
+    import torch
+    stream = torch.cuda.current_stream()
+    specs = [(3121, 160, 120, None), (3122, 200, 152, None), (3123, 160, 120, math.cos(math.radians(20.0)))]
+    seqs = [synth.configs.sequence(seed=sd, n_frames=4, width=w, height=h, device="cuda") for sd, w, h, _ in specs]
+    ctx = P.Context(0)
+
+    def open_session(seq, gate):
+        tp = P.track_params(levels=3, iters=(4, 3, 2), mode="rgbdi", icp_cos=gate)
+        return P.Session(ctx, seq["camera"], tp, P.imu_params(), seq["x0"], seq["q_IW"], seq["prior"])
+
+    def planes(s):
+        return [[s.copy_pyramid(P.PYR_CURRENT, l, ch) for ch in range(P.CH_VX, P.CH_NZ + 1)] for l in range(3)]
+
+    def fused(s, seq, f):
+        m = P.Map(ctx, seq["camera"], capacity=40000)
+        m.fuse(s, f["T_WM"], stream)
+        torch.cuda.synchronize()
+        out = m.arrays()
+        m.close()
+        return out
+
+    alone = []
+    for seq, (_, _, _, gate) in zip(seqs, specs):
+        s = open_session(seq, gate)
+        for j in (1, 2):
+            f = _frame(seq, j)
+            s.set_model(f["model_depth"], f["model_intensity"], f["T_WM"], stream)
+            s.track_frame(f["depth"], f["intensity"], f["imu"], f["t0"], f["t1"], stream)
+        alone.append((s.result(), planes(s), fused(s, seq, f)))
+        s.close()
+    sess = [open_session(seq, gate) for seq, (_, _, _, gate) in zip(seqs, specs)]
+    batch = P.Batch(ctx, len(sess))
+    for j in (1, 2):
+        frames = [_frame(seq, j) for seq in seqs]
+        batch.track(sess, frames, stream)
+        out = batch.results()
+    for i, (s, seq) in enumerate(zip(sess, seqs)):
+        r, pl, mp = alone[i]
+        _same(out[i], r, f"session {i}")
+        if i == 0:  # normals filled from the stored depths by the map fusion, then read back
+            got_map = fused(s, seq, frames[i])
+            got = planes(s)
+        else:  # filled by the read (session 1); written by the gated session's step (session 2)
+            got = planes(s)
+            got_map = fused(s, seq, frames[i])
+        for l in range(3):
+            for ch in range(len(pl[l])):
+                assert np.array_equal(got[l][ch], pl[l][ch]), (i, l, ch)
+        assert mp.keys() == got_map.keys()
+        for k in mp:
+            assert np.array_equal(mp[k], got_map[k]), (i, k)
+        print(f"session {i}: current planes and fused map equal to alone ({len(mp['px'])} surfels)", flush=True)
+    batch.close()
+    for s in sess:
+        s.close()
+    ctx.close()
