@@ -41,7 +41,7 @@ LAYOUT_BYTES_PER_PIXEL = 44
 # and of a 256 MiB calibration copy, from rocprofv3 --pmc runs of `bench.py --counters --counters-batch`
 # (profiles/residual_kernel_640x480_counters.md); valid for the residual-pass sources with this hash
 COUNTERS = {
-    "source_sha256": "0812d43df8fce201",
+    "source_sha256": "49860b2aed08462e",
     "copy_fetch_kib": 131086.7, "copy_write_kib": 262144.0,
     "shapes": {  # "ppt,banded": per-dispatch means over 50 back-to-back launches
         "1,0": {"fetch_kib": 7939.7, "write_kib": 300.0, "valu_insts": 1993316, "waves": 4800},
