@@ -49,6 +49,16 @@ __device__ __forceinline__ void reduce_rows_part(const float* partials, int nblo
   }
 }
 
+// One of the two halves of the step's reduction with every load of a thread
+// in flight at once up to 16 x 2 x 32 blocks: 20 loads per round trip when
+// that covers the half (up to 640 blocks; fewer clamped duplicate loads), 32
+// for larger images (a 1280x720 level 0 at 4 pixels per thread has 900
+// blocks, which took two round trips per half at 20).
+__device__ __forceinline__ void reduce_rows_half(const float* partials, int nblocks, int part, RowSums& rs) {
+  if (nblocks <= 16 * 2 * 20) reduce_rows_part<20>(partials, nblocks, part, 2, rs);
+  else reduce_rows_part<32>(partials, nblocks, part, 2, rs);
+}
+
 __device__ __forceinline__ void reduce_rows_store(const RowSums& rs, double* red) {
   const int g = threadIdx.x & 15, r = threadIdx.x >> 4;
   red[r * 64 + 4 * g + 0] = rs.s0;
@@ -309,7 +319,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   static_assert(SOLVE_THREADS == 512 && REDUCE_THREADS == 256, "stage plan assumes 8 waves");
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   RowSums rs;
-  if (wave < 4) reduce_rows_part(partials, nblocks, 0, 2, rs);
+  if (wave < 4) reduce_rows_half(partials, nblocks, 0, rs);
   if (full) imu_stage0(par, 4, x0, x1, qIW, pre, &w.ic, &w.is);
   if (wave == 4 || wave == 5) init_system_H(Par{lane + (wave == 5 ? 64 : 0), 128}, &w, sp, &pre, &prior);
   if (wave == 7) {
@@ -319,7 +329,7 @@ __device__ __forceinline__ void solve_body(SessionDev* sd, const float* partials
   }
   DSLAM_SYNC();
   if (wave < 4) {
-    reduce_rows_part(partials, nblocks, 1, 2, rs);
+    reduce_rows_half(partials, nblocks, 1, rs);
     reduce_rows_store(rs, red);
   }
   if (full) {
