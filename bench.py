@@ -139,14 +139,16 @@ def roofline(k_ms, px, kernel, launch):
         acc["counter_traffic"] = {"bytes_per_launch": cf["traffic_bytes"], "GBs": gbs,
                                   "frac_of_peak": gbs / HBM_PEAK_GBS, "frac_of_measured_copy": gbs / hbm_copy}
         rate = cf["valu_insts"] / t / 1e9
-        valu = {"insts_per_launch": cf["valu_insts"], "insts_per_pixel": cf["valu_insts"] / px,
+        valu = {"insts_per_launch": cf["valu_insts"], "wave_insts_per_pixel": cf["valu_insts"] / px,
+                "lane_insts_per_pixel": 64.0 * cf["valu_insts"] / px,
                 "achieved_ginst_s": rate, "peak_ginst_s": VALU_PEAK_GINST, "frac": rate / VALU_PEAK_GINST,
                 "waves": cf["waves"]}
     binding = None
     if valu is not None:
         fr = {"valu": valu["frac"], "hbm": acc["counter_traffic"]["frac_of_measured_copy"]}
         name = max(fr, key=fr.get)
-        binding = name if fr[name] >= 0.5 else f"latency ({name} closest, at {fr[name]:.2f} of its roof)"
+        # a roof binds when the launch reaches 0.6 of it; below that on both, latency does
+        binding = name if fr[name] >= 0.6 else f"latency ({name} closest, at {fr[name]:.2f} of its roof)"
     achieved = floor_b / t / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": cf["traffic_bytes"] if cf else None,
