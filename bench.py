@@ -51,6 +51,8 @@ COUNTERS = {
         "4,0": {"fetch_kib": 6821.0, "write_kib": 75.0, "valu_insts": 1624316, "waves": 1200},
         "4,1": {"fetch_kib": 5252.8, "write_kib": 75.0, "valu_insts": 1624316, "waves": 1200},
     },
+    # the batched level-0 pass over a 16-session mix (2 at 1280x720, 8 at 640x480, 6 at 320x240), banded tiles
+    "batch_banded": {"pixels": 4761600, "fetch_kib": 96006.7, "write_kib": 2100.0, "valu_insts": 26489876},
 }
 RESIDUAL_SOURCES = ("kernels.hip", "residual.h", "device.h")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "bench_oracle.json")
@@ -99,6 +101,18 @@ def counter_figures(ppt, banded):
     write = f["write_kib"] * (COPY_BYTES / 1024) / c["copy_write_kib"] * 1024
     return {"traffic_bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write,
             "valu_insts": f["valu_insts"], "waves": f["waves"]}
+
+
+def batch_counter_figures():
+    """HBM bytes and VALU wave-instructions per pixel of the banded batched level-0 pass (16-session mix
+    counters, scaled like counter_figures), or None when the kernel sources changed since."""
+    c = COUNTERS
+    if c["source_sha256"] is None or not residual_source_hash().startswith(c["source_sha256"]):
+        return None
+    b = c["batch_banded"]
+    fetch = b["fetch_kib"] * (COPY_BYTES / 1024) / c["copy_fetch_kib"] * 1024
+    write = b["write_kib"] * (COPY_BYTES / 1024) / c["copy_write_kib"] * 1024
+    return {"bytes_per_pixel": (fetch + write) / b["pixels"], "valu_insts_per_pixel": b["valu_insts"] / b["pixels"]}
 
 
 def measure_copy_gbs(nbytes, reps):
@@ -532,6 +546,20 @@ def run_serving(args):
         order_us[name] = e0.elapsed_time(e1) * 1e3 / reps
     k_ms = order_us["xcd_banded"] * 1e-3
     gbs = FLOOR_BYTES_PER_PIXEL * px / (k_ms * 1e-3) / 1e9
+    hbm_copy = measure_copy_gbs(1 << 30, 20)
+    accountings = {}
+    for name, bpp in (("floor_10B", FLOOR_BYTES_PER_PIXEL), ("ref_layout_64B", REF_LAYOUT_BYTES_PER_PIXEL),
+                      ("own_layout_44B", LAYOUT_BYTES_PER_PIXEL)):
+        g = bpp * px / (k_ms * 1e-3) / 1e9
+        accountings[name] = {"GBs": g, "frac_of_peak": g / HBM_PEAK_GBS, "frac_of_measured_copy": g / hbm_copy}
+    bc = batch_counter_figures()
+    if bc is not None:  # bytes and instructions per pixel from the 16-session mix's counters
+        g = bc["bytes_per_pixel"] * px / (k_ms * 1e-3) / 1e9
+        rate = bc["valu_insts_per_pixel"] * px / (k_ms * 1e-3) / 1e9
+        accountings["counter_traffic_16_session_mix"] = {
+            "bytes_per_pixel": bc["bytes_per_pixel"], "GBs": g, "frac_of_peak": g / HBM_PEAK_GBS,
+            "frac_of_measured_copy": g / hbm_copy, "valu_lane_insts_per_pixel": 64.0 * bc["valu_insts_per_pixel"],
+            "valu_frac": rate / VALU_PEAK_GINST}
     log(f"[serving] batched level-0 residual pass: {px} px in {k_ms * 1e3:.1f} us = {gbs:.0f} GB/s at the "
         f"{FLOOR_BYTES_PER_PIXEL} B/px floor (round-robin tile order: {order_us['round_robin']:.1f} us)")
     batch.close()
@@ -554,12 +582,7 @@ def run_serving(args):
             "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
             "kernel_us": k_ms * 1e3, "pixels": px, "bytes_per_launch": FLOOR_BYTES_PER_PIXEL * px,
             "bytes_per_pixel": FLOOR_BYTES_PER_PIXEL, "tile_order": "xcd_banded",
-            "kernel_us_by_tile_order": order_us,
-            "accountings": {name: {"GBs": bpp * px / (k_ms * 1e-3) / 1e9,
-                                   "frac_of_peak": bpp * px / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-                            for name, bpp in (("floor_10B", FLOOR_BYTES_PER_PIXEL),
-                                              ("ref_layout_64B", REF_LAYOUT_BYTES_PER_PIXEL),
-                                              ("own_layout_44B", LAYOUT_BYTES_PER_PIXEL))}},
+            "kernel_us_by_tile_order": order_us, "measured_copy_GBs": hbm_copy, "accountings": accountings},
     }
 
 
