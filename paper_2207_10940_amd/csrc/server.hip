@@ -10,7 +10,8 @@
 // so each session's frames are tracked in order.  A session's next frame may
 // join a step while its previous one is still running: the new step is staged
 // and launched at once, and on the device its launches wait for the sessions'
-// earlier work (an event per session), so when every session is in every step
+// earlier work (one wait per earlier step: the sessions of a step share its
+// completion event), so when every session is in every step
 // (saturation) the next step starts as soon as the previous one ends, with no
 // host round trip in between.  Each slot owns a batch's staging memory, a
 // stream and a pair of timing events, so up to pipeline_depth steps are in
