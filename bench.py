@@ -223,9 +223,10 @@ def run_gpu(args):
     lat = []
     n_lat = min(args.latency_frames, n_frames - 1)
     for k in range(n_lat):
+        md, mi, T, d, i, imu, t0, t1 = frames[k]
         t = time.perf_counter()
-        track(k)
-        sess.result()
+        sess.track_frame_sync({"depth": d, "intensity": i, "model_depth": md, "model_intensity": mi, "T_WM": T,
+                               "imu": imu, "t0": t0, "t1": t1}, stream)
         lat.append((time.perf_counter() - t) * 1e3)
     lat = np.array(lat[5:] if len(lat) > 10 else lat)
     log(f"[bench] latency over {len(lat)} frames: p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
@@ -312,7 +313,7 @@ def run_gpu(args):
     return {
         "value": args.steps / elapsed, "ms_per_step": elapsed * 1e3 / args.steps,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "frames": int(len(lat)), "kind": "host submit to result, one frame at a time"},
+                       "frames": int(len(lat)), "kind": "host submit to result, one frame at a time (dslam_track_frame_sync)"},
         "pose_err_final_m": pos_err,
         "accuracy": accuracy,
         "launch_modes": launch_modes,

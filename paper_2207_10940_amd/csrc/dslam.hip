@@ -339,11 +339,13 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   for (int i = 0; i < 16; ++i) s->T_WM[i] = (i % 5 == 0) ? 1.0 : 0.0;
   auto fail = [&](dslam_status st) {
     if (s->arena) (void)hipFree(s->arena);
+    if (s->h_result) (void)hipHostFree(s->h_result);
     ctx->used.fetch_sub(lo.total);
     delete s;
     return st;
   };
   s->arena = nullptr;
+  s->h_result = nullptr;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
   if (hipMalloc(&s->arena, lo.total) != hipSuccess) {
     s->arena = nullptr;
@@ -382,6 +384,10 @@ dslam_status dslam_session_open(dslam_context* ctx, const dslam_camera* cam, con
   for (int i = 0; i < 4; ++i) init.qIW[i] = q_IW[i];
   if (prior) init.prior = *prior;
   if (hipMemset(s->arena, 0, lo.total) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
+  if (hipHostMalloc((void**)&s->h_result, sizeof(dslam_track_result), hipHostMallocDefault) != hipSuccess) {
+    s->h_result = nullptr;
+    return fail(DSLAM_ERR_NO_CAPACITY);
+  }
   if (hipMemcpy(s->sd, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
   s->own_done = std::make_shared<DoneEvent>();
   if (hipEventCreateWithFlags(&s->own_done->ev, hipEventDisableTiming) != hipSuccess) return fail(DSLAM_ERR_DEVICE);
@@ -551,6 +557,7 @@ dslam_status dslam_session_close(dslam_session* s) {
   drop_graphs(s);
   if (s->capture) (void)hipStreamDestroy(s->capture);
   (void)hipFree(s->arena);
+  (void)hipHostFree(s->h_result);
   s->ctx->used.fetch_sub(s->bytes);
   delete s;
   return DSLAM_OK;
@@ -775,9 +782,17 @@ dslam_status dslam_track_frame(dslam_session* s, const dslam_frame_input* f, dsl
 dslam_status dslam_track_frame_sync(dslam_session* s, const dslam_frame_input* f, dslam_track_result* out,
                                     void* stream) {
   if (!out) return DSLAM_ERR_INVALID;
-  dslam_status st = dslam_track_frame(s, f, nullptr, stream);
+  // the result is copied in stream order into the session's pinned mirror, and
+  // the frame's end is polled, so nothing is left to do between the frame's
+  // end on the device and the return (no sleep, no separate copy)
+  dslam_status st = dslam_track_frame(s, f, s ? s->h_result : nullptr, stream);
   if (st != DSLAM_OK) return st;
-  return dslam_session_result(s, out);
+  hipError_t e;
+  while ((e = hipEventQuery(session_done(s))) == hipErrorNotReady) {
+  }
+  if (e != hipSuccess) return DSLAM_ERR_DEVICE;
+  *out = *s->h_result;
+  return DSLAM_OK;
 }
 
 static void drop_batch_graphs(dslam_batch* b) {

@@ -47,6 +47,7 @@ struct dslam_session {
   int max_blocks;
   double* red_out;   // device, 64 doubles
   float* xf_scratch; // device, 24 floats (dslam_linearize)
+  dslam_track_result* h_result;  // pinned host mirror of the result record (dslam_track_frame_sync)
   DoneRef own_done;         // the session's own completion event
   DoneRef done;             // the event recorded after the last enqueue of its work (own, or a batched step's)
   hipStream_t last_stream;  // stream of the last enqueue (a later enqueue on another stream waits for done)
