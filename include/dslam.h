@@ -342,8 +342,10 @@ dslam_status dslam_track_frame(dslam_session* s, const dslam_frame_input* in, ds
                                void* stream);
 
 /* dslam_track_frame, then wait for the frame and copy its result to `out`
- * (host, required).  Returns the enqueue error, or DSLAM_OK with the frame's
- * own status (a failed solve) in out->status. */
+ * (host, required).  The result is copied in stream order to pinned memory
+ * the session owns, and the wait polls the frame's completion (the calling
+ * thread stays busy until the frame ends).  Returns the enqueue error, or
+ * DSLAM_OK with the frame's own status (a failed solve) in out->status. */
 dslam_status dslam_track_frame_sync(dslam_session* s, const dslam_frame_input* in, dslam_track_result* out,
                                     void* stream);
 
