@@ -106,6 +106,18 @@ def test_counter_scaling(monkeypatch):
     assert bench.counter_figures(2, 1) is None  # taken for other kernel sources
 
 
+def test_batch_counter_scaling(monkeypatch):
+    """The batched pass's per-pixel figures: scaled bytes and wave instructions over the mix's pixels."""
+    c = dict(bench.COUNTERS, source_sha256=bench.residual_source_hash()[:16],
+             copy_fetch_kib=2.0 * bench.COPY_BYTES / 1024, copy_write_kib=bench.COPY_BYTES / 1024,
+             batch_banded={"pixels": 1000, "fetch_kib": 20.0, "write_kib": 1.0, "valu_insts": 5000})
+    monkeypatch.setattr(bench, "COUNTERS", c)
+    f = bench.batch_counter_figures()
+    assert f["bytes_per_pixel"] == (20.0 * 1024 / 2.0 + 1.0 * 1024) / 1000 and f["valu_insts_per_pixel"] == 5.0
+    monkeypatch.setattr(bench, "COUNTERS", dict(c, source_sha256="0" * 16))
+    assert bench.batch_counter_figures() is None
+
+
 def test_model_view_at_reproduces_the_sequence_render():
     """The closed-loop model view rendered at a state's pose equals the sequence's own noise-free render
     at that frame's ground-truth pose (same scene; the pose only goes through the world frame and back)."""
