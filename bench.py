@@ -752,7 +752,8 @@ def run_stress(args):
             sq = seqs[(w, h)][k]
             s.set_state(sq["x0"], sq["q_IW"], sq["prior"])
 
-    server = P.Server(ctx, max_batch=len(sess), pipeline_depth=2)
+    server = P.Server(ctx, max_batch=min(args.stress_batch, len(sess)), pipeline_depth=args.stress_depth,
+                      graphs=args.stress_launch == "graphs")
     total = len(sess) * nf
     # ---- saturation
     reset()
@@ -1161,6 +1162,10 @@ def main():
     ap.add_argument("--serving-warmup", type=float, default=0.25, help="seconds of arrivals left out of latency")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--stress-frames", type=int, default=8, help="frames per session of the stress workload")
+    ap.add_argument("--stress-batch", type=int, default=256, help="server max_batch of the stress workload")
+    ap.add_argument("--stress-depth", type=int, default=2, help="server pipeline_depth of the stress workload")
+    ap.add_argument("--stress-launch", choices=("eager", "graphs"), default="eager",
+                    help="launch mode of the stress workload's steps")
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--robust-frames", type=int, default=91, help="frames of the robustness sequences")
     ap.add_argument("--robust-width", type=int, default=320)
